@@ -1,0 +1,706 @@
+"""FP64 NumPy oracle for the fine-stage per-ray training step of DVGO.
+
+TEST INFRASTRUCTURE ONLY: imported by tests, the smoke check and the
+benchmark's CPU-baseline leg; never by the product path.
+
+Every function cites the part of the paper it follows.  Two kinds of
+arithmetic appear:
+
+* Discrete decisions (ray validity, per-ray sample counts, which samples the
+  coarse mask keeps, Morton keys, the proposal's segment mask) are taken in
+  an explicit float32 recipe - every operation rounded to float32 in the
+  order written, no fused multiply-add - because those decisions must match
+  a float32 GPU implementation bit for bit.
+* Everything continuous (interpolation, activations, compositing, the MLP,
+  the loss, the adjoint, Adam) is float64, evaluated from the float32 input
+  values.
+
+Parity status: every public function is pinned by tests in
+``tests/test_oracle_*.py`` against closed forms, worked numbers printed in
+the paper, library routines, autograd, finite differences or brute force.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+F32 = np.float32
+NSEG = 32                     # proposal segments per ray
+MORTON_BITS = 5               # Morton quantisation bits per axis
+MORTON_INVALID = 1 << (3 * MORTON_BITS)
+
+
+# ===========================================================================
+# 1. Discrete sampler, float32 recipe
+# ===========================================================================
+def ray_box_clip(o, d, box_min, box_max):
+    """Ray-box clipping of the fine-stage sampler (Sec. 4.2, "Fine-stage
+    points sampling"): the near and far bounds become the two ends of the
+    ray-box intersection, the near bound is not moved when the origin is
+    already inside the box (t_near = max(t_enter, 0)), and rays that miss the
+    box are dropped (valid = 0).
+
+    Slab test in float32: per axis inv = 1/d, t0 = (min - o)*inv,
+    t1 = (max - o)*inv; t_enter = max_i fmin(t0,t1), t_exit = min_i
+    fmax(t0,t1).  An axis with d = 0 imposes no bound when min <= o <= max and
+    misses otherwise.  valid iff t_near < t_far (strict).  Invalid rays get
+    t_near = t_far = 0.
+    """
+    o = np.asarray(o, F32)
+    d = np.asarray(d, F32)
+    B = o.shape[0]
+    t_enter = np.full(B, -np.inf, F32)
+    t_exit = np.full(B, np.inf, F32)
+    miss = np.zeros(B, bool)
+    with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+        for i in range(3):
+            di, oi = d[:, i], o[:, i]
+            lo_b, hi_b = F32(box_min[i]), F32(box_max[i])
+            zero = di == 0
+            inv = F32(1.0) / np.where(zero, F32(1.0), di)
+            t0 = (lo_b - oi) * inv
+            t1 = (hi_b - oi) * inv
+            lo = np.where(zero, F32(-np.inf), np.fmin(t0, t1))
+            hi = np.where(zero, F32(np.inf), np.fmax(t0, t1))
+            miss |= zero & ((oi < lo_b) | (oi > hi_b))
+            t_enter = np.fmax(t_enter, lo)
+            t_exit = np.fmin(t_exit, hi)
+    t_near = np.fmax(t_enter, F32(0.0))
+    t_far = t_exit
+    valid = (~miss) & (t_near < t_far)
+    t_near = np.where(valid, t_near, F32(0.0)).astype(F32)
+    t_far = np.where(valid, t_far, F32(0.0)).astype(F32)
+    return t_near, t_far, valid
+
+
+def sample_t(t_near, jitter, k, step):
+    """Distance of uniform sample k (Eq. coarse_sample with the training
+    jitter of the supplementary implementation details): with a unit
+    direction, t_k = t_near + (k + p) * delta, three float32 roundings in that
+    order (k + p, then * delta, then t_near +)."""
+    k = np.asarray(k)
+    kp = k.astype(F32) + np.asarray(jitter, F32)
+    return (np.asarray(t_near, F32) + (kp * F32(step)).astype(F32)).astype(F32)
+
+
+def uniform_count(t_near, t_far, valid, jitter, step, max_samples):
+    """Number of uniform samples per ray (Eq. coarse_sample, index range
+    clipped to the box): N_r = #{k >= 0 : t_k < t_far, k < max_samples},
+    counted by brute-force enumeration of every k.  Invalid rays have 0."""
+    B = t_near.shape[0]
+    p = np.zeros(B, F32) if jitter is None else np.asarray(jitter, F32)
+    k = np.arange(max_samples, dtype=np.int64)[None, :]
+    t = sample_t(t_near[:, None], p[:, None], k, step)
+    inside = t < t_far[:, None]
+    # t_k is non-decreasing in k, so the kept k form a prefix; count it
+    n = inside.sum(axis=1).astype(np.int32)
+    return np.where(valid, n, 0).astype(np.int32)
+
+
+def sample_x(o, d, t):
+    """Sample position x = o + t * d per component (multiply, then add),
+    float32."""
+    return (np.asarray(o, F32) + (np.asarray(t, F32)[..., None] * np.asarray(d, F32))
+            .astype(F32)).astype(F32)
+
+
+def coarse_raw_threshold(tau, step, act_shift=0.0):
+    """Free-space test of Sec. 4.2 ("Known free space and unknown space"):
+    a point is known-free when alpha(softplus(raw + b), delta) < tau.  Both
+    activations increase with raw, so alpha >= tau  <=>  raw >= thr with
+    thr = softplus^{-1}(-log(1 - tau)/delta) - b = log(expm1(-log1p(-tau)/delta)) - b.
+    Returned as the largest float32 not above the float64 threshold, so the
+    float32 comparison never drops a point the exact test keeps."""
+    sig = -math.log1p(-tau) / step
+    thr = math.log(math.expm1(sig)) - act_shift
+    t32 = F32(thr)
+    if float(t32) > thr:
+        t32 = np.nextafter(t32, F32(-np.inf))
+    return F32(t32)
+
+
+def coarse_cell_bits(raw, raw_thr):
+    """Per-cell keep bits of the frozen coarse density grid (Sec. 4.2,
+    "Free space skipping", first rule).  A cell is kept when the largest of
+    its 8 corner raw values reaches ``raw_thr``: trilinear interpolation is a
+    convex combination of the corners and the activations are increasing, so
+    every point whose own post-activated coarse alpha reaches tau lies in a
+    kept cell.  Bit c of word c>>5 (c = (ix*(ny-1)+iy)*(nz-1)+iz) is cell c."""
+    raw = np.asarray(raw, F32)
+    m = raw[:-1, :-1, :-1]
+    for dx in (0, 1):
+        for dy in (0, 1):
+            for dz in (0, 1):
+                m = np.maximum(m, raw[dx:raw.shape[0] - 1 + dx, dy:raw.shape[1] - 1 + dy,
+                                      dz:raw.shape[2] - 1 + dz])
+    keep = (m >= F32(raw_thr)).ravel()
+    nwords = (keep.size + 31) // 32
+    bits = np.zeros(nwords * 32, np.uint64)
+    bits[:keep.size] = keep
+    words = (bits.reshape(nwords, 32) << np.arange(32, dtype=np.uint64)).sum(axis=1)
+    return words.astype(np.uint32)
+
+
+def coarse_cell_index(x, cmin, cmax, cn):
+    """Cell containing a float32 point: clamp(floor((x - min) * s), 0, n-2)
+    per axis with s = (n-1)/(max-min) rounded once to float32."""
+    x = np.asarray(x, F32)
+    idx = []
+    for i in range(3):
+        s = F32(F32(cn[i] - 1) / F32(F32(cmax[i]) - F32(cmin[i])))
+        u = ((x[..., i] - F32(cmin[i])).astype(F32) * s).astype(F32)
+        fi = np.floor(u).astype(np.int64)
+        idx.append(np.clip(fi, 0, cn[i] - 2))
+    return idx
+
+
+def coarse_keep(x, cmin, cmax, cn, bits):
+    """Look up the coarse keep bit of the cell holding each point."""
+    ix, iy, iz = coarse_cell_index(x, cmin, cmax, cn)
+    c = (ix * (cn[1] - 1) + iy) * (cn[2] - 1) + iz
+    return ((bits[c >> 5] >> (c & 31).astype(np.uint32)) & 1).astype(bool)
+
+
+def segment_of(k, n_uniform):
+    """Equal-count proposal segment of sample k on a ray with N_r uniform
+    samples: floor(32 k / N_r), integer arithmetic."""
+    return (NSEG * np.asarray(k, np.int64)) // np.maximum(np.asarray(n_uniform, np.int64), 1)
+
+
+def morton_keys(o, d, t_near, t_far, valid, box_min, box_max):
+    """Spatial sort key of a ray: the 5-bit-per-axis Morton code of its
+    in-box segment midpoint.  float32 recipe: tm = (t_near + t_far) * 0.5,
+    m = o + tm * d, q = clamp(floor((m - min) * (32/(max-min))), 0, 31);
+    bits interleaved x (most significant), y, z.  Invalid rays get the key
+    2^15, after every valid key."""
+    tm = ((np.asarray(t_near, F32) + np.asarray(t_far, F32)).astype(F32) * F32(0.5)).astype(F32)
+    m = sample_x(o, d, tm)
+    q = []
+    for i in range(3):
+        s = F32(F32(1 << MORTON_BITS) / F32(F32(box_max[i]) - F32(box_min[i])))
+        u = ((m[:, i] - F32(box_min[i])).astype(F32) * s).astype(F32)
+        q.append(np.clip(np.floor(u).astype(np.int64), 0, (1 << MORTON_BITS) - 1))
+    key = np.zeros(o.shape[0], np.int64)
+    for b in range(MORTON_BITS):
+        key |= ((q[0] >> b) & 1) << (3 * b + 2)
+        key |= ((q[1] >> b) & 1) << (3 * b + 1)
+        key |= ((q[2] >> b) & 1) << (3 * b)
+    key = np.where(valid, key, MORTON_INVALID)
+    return key.astype(np.uint32)
+
+
+def sample_rays(o, d, jitter, box_min, box_max, step, max_samples, coarse=None,
+                seg_mask=None, morton=False):
+    """The fine-stage sampler (Sec. 4.2 "Fine-stage points sampling" and
+    "Free space skipping", rule one; Eq. coarse_sample): clip, count the
+    uniform samples, keep those whose coarse cell bit (and, when given, whose
+    proposal segment bit) is set, and list them per ray in ascending k.
+
+    ``coarse`` is (bits, cmin, cmax, cn) or None.  The ray order of the
+    compact list is the identity, or ascending (Morton key, ray id) when
+    ``morton``.  Returns a dict of numpy arrays.
+    """
+    o = np.asarray(o, F32)
+    d = np.asarray(d, F32)
+    B = o.shape[0]
+    p = np.zeros(B, F32) if jitter is None else np.asarray(jitter, F32)
+    t_near, t_far, valid = ray_box_clip(o, d, box_min, box_max)
+    n_uni = uniform_count(t_near, t_far, valid, p, step, max_samples)
+    if morton:
+        keys = morton_keys(o, d, t_near, t_far, valid, box_min, box_max)
+        perm = np.lexsort((np.arange(B), keys)).astype(np.int32)
+    else:
+        keys = None
+        perm = np.arange(B, dtype=np.int32)
+    counts = np.zeros(B, np.int64)
+    ks_per_ray = []
+    for slot in range(B):
+        r = perm[slot]
+        k = np.arange(n_uni[r], dtype=np.int64)
+        keep = np.ones(k.size, bool)
+        if k.size and coarse is not None:
+            bits, cmin, cmax, cn = coarse
+            x = sample_x(o[r][None, :], d[r][None, :], sample_t(t_near[r], p[r], k, step))
+            keep &= coarse_keep(x, cmin, cmax, cn, bits)
+        if k.size and seg_mask is not None:
+            seg = segment_of(k, n_uni[r])
+            keep &= ((np.uint64(seg_mask[r]) >> seg.astype(np.uint64)) & np.uint64(1)).astype(bool)
+        ks_per_ray.append(k[keep])
+        counts[slot] = keep.sum()
+    ray_offset = np.zeros(B + 1, np.int64)
+    ray_offset[1:] = np.cumsum(counts)
+    sample_k = np.concatenate(ks_per_ray) if B else np.zeros(0, np.int64)
+    sample_ray = np.repeat(perm.astype(np.int64), counts)
+    return dict(t_near=t_near, t_far=t_far, valid=valid, n_uniform=n_uni, perm=perm,
+                keys=keys, ray_offset=ray_offset.astype(np.int32),
+                sample_ray=sample_ray.astype(np.int32), sample_k=sample_k.astype(np.int32))
+
+
+# ===========================================================================
+# 2. Continuous part, float64
+# ===========================================================================
+def trilinear_corners(x, box_min, box_max, n):
+    """Trilinear interpolation weights on a vertex grid of n[i] points per
+    axis spanning the box (Eq. interp, trilinear by default).
+    u = (x - min)/(max - min)*(n-1), i0 = clamp(floor(u), 0, n-2),
+    f = clamp(u - i0, 0, 1).  Returns (i0 [S,3] int, weights [S,8],
+    corner offsets [8,3]) with corner c = (c>>2 &1, c>>1 &1, c &1)."""
+    x = np.asarray(x, np.float64)
+    bmin = np.asarray(box_min, np.float64)
+    bmax = np.asarray(box_max, np.float64)
+    nn = np.asarray(n, np.float64)
+    u = (x - bmin) / (bmax - bmin) * (nn - 1)
+    i0 = np.clip(np.floor(u), 0, nn - 2).astype(np.int64)
+    f = np.clip(u - i0, 0.0, 1.0)
+    offs = np.array([[(c >> 2) & 1, (c >> 1) & 1, c & 1] for c in range(8)], np.int64)
+    w = np.ones((x.shape[0], 8))
+    for c in range(8):
+        for a in range(3):
+            w[:, c] *= f[:, a] if offs[c, a] else (1.0 - f[:, a])
+    return i0, w, offs
+
+
+def interp(grid, x, box_min, box_max):
+    """interp(x, V) of Eq. interp for a channel-last grid [nx,ny,nz,C] (or
+    [nx,ny,nz]); float64 result [S,C] (or [S])."""
+    g = np.asarray(grid, np.float64)
+    squeeze = g.ndim == 3
+    if squeeze:
+        g = g[..., None]
+    i0, w, offs = trilinear_corners(x, box_min, box_max, g.shape[:3])
+    out = np.zeros((w.shape[0], g.shape[3]))
+    for c in range(8):
+        ii = i0 + offs[c]
+        out += w[:, c:c + 1] * g[ii[:, 0], ii[:, 1], ii[:, 2]]
+    return out[:, 0] if squeeze else out
+
+
+def interp_scatter(shape, x, box_min, box_max, g):
+    """Adjoint of ``interp``: scatter-add g [S,C] (or [S]) into a zero grid
+    of ``shape`` with the trilinear weights."""
+    out = np.zeros(shape, np.float64)
+    o3 = out if out.ndim == 4 else out[..., None]
+    gg = np.asarray(g, np.float64)
+    gg = gg if gg.ndim == 2 else gg[:, None]
+    i0, w, offs = trilinear_corners(x, box_min, box_max, shape[:3])
+    for c in range(8):
+        ii = i0 + offs[c]
+        np.add.at(o3, (ii[:, 0], ii[:, 1], ii[:, 2]), w[:, c:c + 1] * gg)
+    return out
+
+
+def softplus(x):
+    """log(1 + exp(x)), evaluated stably (Eq. density_activation)."""
+    x = np.asarray(x, np.float64)
+    return np.maximum(x, 0.0) + np.log1p(np.exp(-np.abs(x)))
+
+
+def sigmoid(x):
+    x = np.asarray(x, np.float64)
+    return 0.5 * (1.0 + np.tanh(0.5 * x))
+
+
+def density_to_alpha(sigma, delta):
+    """alpha = 1 - exp(-sigma * delta) (Eq. density_2_alpha)."""
+    return 1.0 - np.exp(-np.asarray(sigma, np.float64) * delta)
+
+
+def post_activated_alpha(raw, act_shift, delta):
+    """Post-activation (Eq. post_activation): alpha(softplus(interp + b))."""
+    return density_to_alpha(softplus(np.asarray(raw, np.float64) + act_shift), delta)
+
+
+def low_density_bias(alpha_init, voxel):
+    """Shift b of the low-density initialisation (Eq. low_density_init):
+    b = log((1 - alpha_init)^(-1/s) - 1)."""
+    return math.log((1.0 - alpha_init) ** (-1.0 / voxel) - 1.0)
+
+
+def positional_encoding(d, n_freq=4):
+    """Positional embedding of the view direction (Sec. 3, NeRF's encoding;
+    k_d = 4 in the supplementary details): [d, sin(2^0 d), cos(2^0 d), ...,
+    sin(2^{k-1} d), cos(2^{k-1} d)], 3 + 6k values, no pi factor."""
+    d = np.asarray(d, np.float64)
+    parts = [d]
+    for k in range(n_freq):
+        parts.append(np.sin(d * (2.0 ** k)))
+        parts.append(np.cos(d * (2.0 ** k)))
+    return np.concatenate(parts, axis=-1)
+
+
+def mlp_forward(Ws, bs, x):
+    """The shallow colour MLP of Eq. fine_queries: two ReLU hidden layers of
+    128, sigmoid output (Sec. 3 output activation).  Ws[l] is [out][in]."""
+    W1, W2, W3 = [np.asarray(w, np.float64) for w in Ws]
+    b1, b2, b3 = [np.asarray(b, np.float64) for b in bs]
+    z1 = x @ W1.T + b1
+    h1 = np.maximum(z1, 0.0)
+    z2 = h1 @ W2.T + b2
+    h2 = np.maximum(z2, 0.0)
+    z3 = h2 @ W3.T + b3
+    c = sigmoid(z3)
+    return c, dict(x=x, z1=z1, h1=h1, z2=z2, h2=h2, c=c)
+
+
+def mlp_backward(Ws, cache, dc):
+    """Reverse-mode derivative of ``mlp_forward`` for output gradient dc.
+    ReLU'(0) is taken as 0.  Returns (dx, [dW1,dW2,dW3], [db1,db2,db3])."""
+    W1, W2, W3 = [np.asarray(w, np.float64) for w in Ws]
+    c = cache["c"]
+    dz3 = dc * c * (1.0 - c)
+    dW3 = dz3.T @ cache["h2"]
+    db3 = dz3.sum(0)
+    dz2 = (dz3 @ W3) * (cache["z2"] > 0)
+    dW2 = dz2.T @ cache["h1"]
+    db2 = dz2.sum(0)
+    dz1 = (dz2 @ W2) * (cache["z1"] > 0)
+    dW1 = dz1.T @ cache["x"]
+    db1 = dz1.sum(0)
+    dx = dz1 @ W1
+    return dx, [dW1, dW2, dW3], [db1, db2, db3]
+
+
+def _sample_geometry(o, d, jitter, t_near, sample_ray, sample_k, step):
+    """float32 t and x of every listed sample, upcast to float64."""
+    B = o.shape[0]
+    p = np.zeros(B, F32) if jitter is None else np.asarray(jitter, F32)
+    r = np.asarray(sample_ray, np.int64)
+    t32 = sample_t(t_near[r], p[r], sample_k, step)
+    x = np.asarray(o, F32)[r].astype(np.float64) + t32.astype(np.float64)[:, None] * \
+        np.asarray(d, F32)[r].astype(np.float64)
+    return t32.astype(np.float64), x
+
+
+def _padded(ray_offset, n):
+    """Row/column of each compact sample in a [B, Kmax] per-ray layout."""
+    ro = np.asarray(ray_offset, np.int64)
+    counts = np.diff(ro)
+    kmax = int(counts.max()) if counts.size and counts.max() > 0 else 1
+    slot = np.repeat(np.arange(counts.size), counts)
+    col = np.arange(n) - np.repeat(ro[:-1], counts)
+    return slot, col, kmax
+
+
+class Params:
+    """Fine-stage scene representation: density grid, feature grid, MLP
+    (Eq. fine_queries), the softplus shift b and the AABB."""
+
+    def __init__(self, density, feat, Ws, bs, box_min, box_max, act_shift):
+        self.density = np.asarray(density)
+        self.feat = np.asarray(feat)
+        self.Ws = [np.asarray(w) for w in Ws]
+        self.bs = [np.asarray(b) for b in bs]
+        self.box_min = np.asarray(box_min, F32)
+        self.box_max = np.asarray(box_max, F32)
+        self.act_shift = float(act_shift)
+
+
+def render_forward(P: Params, o, d, jitter, samp, step, bg, with_color=True):
+    """Forward volume rendering of every ray (Eq. volume_rendering with
+    Eq. fine_queries and the post-activated density of Eq. post_activation).
+
+    For each ray, over its kept samples in ascending k:
+      raw_k = interp(x_k, V_density), sigma_k = softplus(raw_k + b),
+      alpha_k = 1 - exp(-sigma_k delta),  T_k = prod_{j<k} (1 - alpha_j),
+      c_k = MLP([interp(x_k, V_feat), PE(d)]),
+      C = sum_k T_k alpha_k c_k + T_{K+1} c_bg.
+    Also depth = sum w_k t_k, acc = sum w_k, log T_{K+1} = -delta sum sigma_k
+    (equal to log prod (1 - alpha_k)), per-segment weight sums and the
+    per-sample weights w_k = T_k alpha_k.  ``samp`` is a ``sample_rays`` dict.
+    """
+    o = np.asarray(o, F32)
+    d = np.asarray(d, F32)
+    B = o.shape[0]
+    ro, sr, sk = samp["ray_offset"], samp["sample_ray"], samp["sample_k"]
+    n = sr.size
+    t, x = _sample_geometry(o, d, jitter, samp["t_near"], sr, sk, step)
+    raw = interp(P.density, x, P.box_min, P.box_max)
+    sigma = softplus(raw + P.act_shift)
+    alpha = density_to_alpha(sigma, step)
+    slot, col, kmax = _padded(ro, n)
+    perm = np.asarray(samp["perm"], np.int64)
+    A = np.zeros((B, kmax))
+    A[slot, col] = alpha
+    T_incl = np.cumprod(1.0 - A, axis=1)
+    T_excl = np.concatenate([np.ones((B, 1)), T_incl[:, :-1]], axis=1)
+    T_end_slot = T_incl[:, -1]
+    w = T_excl[slot, col] * alpha
+    cache = dict(t=t, x=x, raw=raw, sigma=sigma, alpha=alpha, w=w, slot=slot, col=col,
+                 kmax=kmax, T_excl=T_excl)
+    sig_sum = np.zeros(B)
+    np.add.at(sig_sum, slot, sigma)
+    out_slot = dict(acc=np.zeros(B), depth=np.zeros(B))
+    np.add.at(out_slot["acc"], slot, w)
+    np.add.at(out_slot["depth"], slot, w * t)
+    seg = segment_of(sk, samp["n_uniform"][sr])
+    seg_w = np.zeros((B, NSEG))
+    np.add.at(seg_w, (slot, seg), w)
+    res = {}
+    if with_color:
+        f = interp(P.feat, x, P.box_min, P.box_max)
+        pe = positional_encoding(d.astype(np.float64))[sr]
+        xin = np.concatenate([f, pe], axis=1)
+        c, mcache = mlp_forward(P.Ws, P.bs, xin)
+        rgb = np.zeros((B, 3))
+        np.add.at(rgb, slot, w[:, None] * c)
+        rgb += T_end_slot[:, None] * np.asarray(bg, np.float64)[None, :]
+        cache.update(f=f, c=c, mcache=mcache)
+        res["rgb"] = np.empty((B, 3))
+        res["rgb"][perm] = rgb
+    for key in ("acc", "depth"):
+        res[key] = np.empty(B)
+        res[key][perm] = out_slot[key]
+    res["log_t_end"] = np.empty(B)
+    res["log_t_end"][perm] = -step * sig_sum
+    res["t_end"] = np.empty(B)
+    res["t_end"][perm] = T_end_slot
+    res["seg_w"] = np.empty((B, NSEG))
+    res["seg_w"][perm] = seg_w
+    res["sample_w"] = w
+    res["cache"] = cache
+    return res
+
+
+def render_backward(P: Params, o, d, jitter, samp, step, bg, fwd, grad_rgb,
+                    grad_depth=None, grad_acc=None):
+    """Hand-written adjoint of ``render_forward`` walked from each ray's end.
+
+    With per-sample channel vectors v_k = (c_k, t_k, 1), background
+    v_bg = (c_bg, 0, 0) and output gradient g = (dL/dC, dL/ddepth, dL/dacc):
+      S_{K+1} = T_{K+1} v_bg,  S_k = S_{k+1} + w_k v_k   (suffix sums),
+      dL/dsigma_k = delta * g . (T_{k+1} v_k - S_{k+1}),
+      dL/draw_k   = dL/dsigma_k * sigmoid(raw_k + b),
+      dL/dc_k     = w_k dL/dC, then back through the MLP to the features,
+    followed by the transpose of the trilinear interpolation into both grids.
+    Returns dict(density, feat, Ws, bs) of float64 gradients.
+    """
+    cache = fwd["cache"]
+    B = np.asarray(o).shape[0]
+    perm = np.asarray(samp["perm"], np.int64)
+    slot, col, kmax = cache["slot"], cache["col"], cache["kmax"]
+    n = slot.size
+    bgv = np.asarray(bg, np.float64)
+    g = np.zeros((B, 5))
+    g[:, :3] = np.asarray(grad_rgb, np.float64)[perm]
+    if grad_depth is not None:
+        g[:, 3] = np.asarray(grad_depth, np.float64)[perm]
+    if grad_acc is not None:
+        g[:, 4] = np.asarray(grad_acc, np.float64)[perm]
+    v = np.zeros((n, 5))
+    v[:, :3] = cache["c"] if "c" in cache else 0.0
+    v[:, 3] = cache["t"]
+    v[:, 4] = 1.0
+    Wv = np.zeros((B, kmax, 5))
+    Wv[slot, col] = cache["w"][:, None] * v
+    t_end = fwd["t_end"][perm]
+    v_bg = np.zeros(5)
+    v_bg[:3] = bgv
+    # S_after[k] = sum_{m>k} w_m v_m + T_end v_bg
+    rev = np.cumsum(Wv[:, ::-1, :], axis=1)[:, ::-1, :]
+    S_after = np.concatenate([rev[:, 1:, :], np.zeros((B, 1, 5))], axis=1) + \
+        t_end[:, None, None] * v_bg[None, None, :]
+    T_next = cache["T_excl"][slot, col] * (1.0 - cache["alpha"])
+    gs = g[slot]
+    dsigma = step * np.sum(gs * (T_next[:, None] * v - S_after[slot, col]), axis=1)
+    draw = dsigma * sigmoid(cache["raw"] + P.act_shift)
+    grads = dict(density=interp_scatter(P.density.shape, cache["x"], P.box_min, P.box_max, draw))
+    if "c" in cache:
+        dc = cache["w"][:, None] * gs[:, :3]
+        dx, dWs, dbs = mlp_backward(P.Ws, cache["mcache"], dc)
+        df = dx[:, :P.feat.shape[-1]]
+        grads["feat"] = interp_scatter(P.feat.shape, cache["x"], P.box_min, P.box_max, df)
+        grads["Ws"], grads["bs"] = dWs, dbs
+    grads["sample_draw"] = draw
+    return grads
+
+
+def photo_loss(rgb, target):
+    """Photometric MSE of Eq. photo_loss: (1/|R|) sum_r ||C_r - C*_r||^2
+    (sum over the three channels, mean over rays) and its gradient
+    2 (C - C*) / |R|."""
+    rgb = np.asarray(rgb, np.float64)
+    tgt = np.asarray(target, np.float64)
+    B = rgb.shape[0]
+    diff = rgb - tgt
+    return float(np.sum(diff * diff) / B), 2.0 * diff / B
+
+
+def adam_step(p, g, m, v, lr, beta1, beta2, eps, t):
+    """One Adam update (the optimiser of Sec. 5.2, Kingma & Ba): m <- b1 m +
+    (1-b1) g; v <- b2 v + (1-b2) g^2; p <- p - lr * mhat / (sqrt(vhat) + eps)
+    with mhat = m/(1-b1^t), vhat = v/(1-b2^t).  float64, returns new arrays."""
+    p = np.asarray(p, np.float64)
+    g = np.asarray(g, np.float64)
+    m = beta1 * np.asarray(m, np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, np.float64) + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** t)
+    vhat = v / (1.0 - beta2 ** t)
+    return p - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+def lr_at(base_lr, it, decay_steps=20000, decay=0.1):
+    """Exponential learning-rate decay reaching 0.1x at 20k iterations
+    (supplementary implementation details)."""
+    return base_lr * decay ** (it / decay_steps)
+
+
+def psnr(mse):
+    return -10.0 * math.log10(mse)
+
+
+# ===========================================================================
+# 3. Post-activation cell fits of the supplementary derivation
+# ===========================================================================
+def cell_fit_1d(c, delta, eps, Delta):
+    """Grid values (a, b) at the two ends of a unit 1D cell whose
+    post-activated alpha S(x) = 1 - (1 + exp(a(1-x) + bx))^-delta approximates
+    a step at x = c within eps outside |x - c| < Delta, with S(c) = 1/2
+    (supplementary Sec. "Derivation for a 1D grid cell": the upper bound on a
+    for delta < 1 or delta >= 1, then b from the S(c) = 1/2 relation)."""
+    L2 = math.log(2.0 ** (1.0 / delta) - 1.0)
+    Le = math.log(1.0 / eps ** (1.0 / delta) - 1.0)
+    L1 = math.log(1.0 / (1.0 - eps) ** (1.0 / delta) - 1.0)
+    if delta < 1.0:
+        a = L2 * (c + Delta) / Delta - Le * c / Delta
+    else:
+        a = L1 * c / Delta - L2 * (c - Delta) / Delta
+    b = a * (c - 1.0) / c + L2 / c
+    return a, b
+
+
+def cell_fit_2d(c0, c1, delta, eps, Delta):
+    """Corner values (V_tl, V_tr, V_bl, V_br) of a 2D cell whose boundary
+    crosses the top edge at c0 and the bottom edge at c1 (supplementary
+    Sec. "Derivation for a 2D grid cell"): each horizontal edge is a 1D fit."""
+    a0, b0 = cell_fit_1d(c0, delta, eps, Delta)
+    a1, b1 = cell_fit_1d(c1, delta, eps, Delta)
+    return a0, b0, a1, b1
+
+
+# ===========================================================================
+# 4. Learned proposal (segment weights predicted per ray)
+# ===========================================================================
+def proposal_encoding(o, d, t_near, box_min, box_max, n_freq=4):
+    """Proposal input: positional encoding of the box-entry point in box
+    coordinates [-1,1]^3 followed by that of the direction (54 values)."""
+    o = np.asarray(o, np.float64)
+    d = np.asarray(d, np.float64)
+    x0 = o + np.asarray(t_near, np.float64)[:, None] * d
+    bmin = np.asarray(box_min, np.float64)
+    bmax = np.asarray(box_max, np.float64)
+    u = (x0 - 0.5 * (bmin + bmax)) / (0.5 * (bmax - bmin))
+    return np.concatenate([positional_encoding(u, n_freq), positional_encoding(d, n_freq)], axis=1)
+
+
+def proposal_forward(Ws, bs, enc):
+    """Proposal MLP enc -> 64 ReLU -> 64 ReLU -> 32 logits."""
+    W1, W2, W3 = [np.asarray(w, np.float64) for w in Ws]
+    b1, b2, b3 = [np.asarray(b, np.float64) for b in bs]
+    z1 = enc @ W1.T + b1
+    h1 = np.maximum(z1, 0.0)
+    z2 = h1 @ W2.T + b2
+    h2 = np.maximum(z2, 0.0)
+    z = h2 @ W3.T + b3
+    return z, dict(x=enc, z1=z1, h1=h1, z2=z2, h2=h2)
+
+
+def proposal_probs(z):
+    """33-way softmax of the 32 segment logits and an implicit transmitted
+    logit fixed at 0; returns (q [B,33], predicted mass sum_{s<32} q_s)."""
+    z = np.asarray(z, np.float64)
+    zz = np.concatenate([z, np.zeros((z.shape[0], 1))], axis=1)
+    m = zz.max(axis=1, keepdims=True)
+    e = np.exp(zz - m)
+    q = e / e.sum(axis=1, keepdims=True)
+    return q, q[:, :NSEG].sum(axis=1)
+
+
+def proposal_select(z, cum_frac=0.99, min_mass=0.9):
+    """Segment mask per ray: the smallest set of segments, taken by
+    descending probability (ties to the lower index), whose probability
+    reaches cum_frac of the predicted mass; all 32 segments when the mass is
+    below min_mass (uniform fallback).  Returns uint32 masks."""
+    q, mass = proposal_probs(z)
+    B = q.shape[0]
+    out = np.zeros(B, np.uint32)
+    for r in range(B):
+        if not mass[r] >= min_mass:
+            out[r] = np.uint32(0xFFFFFFFF)
+            continue
+        order = sorted(range(NSEG), key=lambda s: (-q[r, s], s))
+        acc = 0.0
+        bits = 0
+        for s in order:
+            bits |= 1 << s
+            acc += q[r, s]
+            if acc >= cum_frac * mass[r]:
+                break
+        out[r] = np.uint32(bits)
+    return out
+
+
+def proposal_targets(seg_w, t_end):
+    """KL target per ray: the 32 segment weight sums of the plain renderer
+    and its final transmittance (they sum to one)."""
+    return np.concatenate([np.asarray(seg_w, np.float64),
+                           np.asarray(t_end, np.float64)[:, None]], axis=1)
+
+
+def proposal_loss_grad(z, p):
+    """Mean over rays of KL(p || q) with q the 33-way softmax; gradient with
+    respect to the 32 logits is (q_s - p_s)/B."""
+    q, _ = proposal_probs(z)
+    B = q.shape[0]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        kl = np.where(p > 0, p * (np.log(np.where(p > 0, p, 1.0)) - np.log(q)), 0.0)
+    return float(kl.sum() / B), (q[:, :NSEG] - p[:, :NSEG]) / B
+
+
+def proposal_backward(Ws, cache, dz):
+    """Reverse-mode derivative of ``proposal_forward``."""
+    W1, W2, W3 = [np.asarray(w, np.float64) for w in Ws]
+    dW3 = dz.T @ cache["h2"]
+    db3 = dz.sum(0)
+    dz2 = (dz @ W3) * (cache["z2"] > 0)
+    dW2 = dz2.T @ cache["h1"]
+    db2 = dz2.sum(0)
+    dz1 = (dz2 @ W2) * (cache["z1"] > 0)
+    dW1 = dz1.T @ cache["x"]
+    db1 = dz1.sum(0)
+    return [dW1, dW2, dW3], [db1, db2, db3]
+
+
+# ===========================================================================
+# 5. Ground-truth targets of the analytic scene
+# ===========================================================================
+def scene_render(o, d, centers, radii, rho, rgb, box_min, box_max, step, bg, edge=0.01):
+    """Reference image of the analytic sphere scene by the same quadrature
+    (Eq. volume_rendering) at midpoint samples t_k = t_near + (k + 1/2) step
+    while t_k < t_far, density sum_i rho_i sigmoid((r_i - |x - c_i|)/edge),
+    colour the density-weighted mean.  float64, one ray at a time (use on
+    small spot-check sets)."""
+    o = np.asarray(o, np.float64)
+    d = np.asarray(d, np.float64)
+    t_near, t_far, valid = ray_box_clip(np.asarray(o, F32), np.asarray(d, F32), box_min, box_max)
+    out = np.tile(np.asarray(bg, np.float64), (o.shape[0], 1))
+    for r in range(o.shape[0]):
+        if not valid[r]:
+            continue
+        nk = int(math.ceil((float(t_far[r]) - float(t_near[r])) / step - 0.5))
+        nk = max(nk, 0)
+        while nk > 0 and float(t_near[r]) + (nk - 0.5) * step >= float(t_far[r]):
+            nk -= 1
+        while float(t_near[r]) + (nk + 0.5) * step < float(t_far[r]):
+            nk += 1
+        t = float(t_near[r]) + (np.arange(nk) + 0.5) * step
+        x = o[r][None, :] + t[:, None] * d[r][None, :]
+        dist = np.linalg.norm(x[:, None, :] - np.asarray(centers)[None], axis=-1)
+        si = np.asarray(rho)[None, :] * sigmoid((np.asarray(radii)[None, :] - dist) / edge)
+        s = si.sum(1)
+        col = np.where(s[:, None] > 0, (si @ np.asarray(rgb)) / np.maximum(s[:, None], 1e-300), 0)
+        a = 1.0 - np.exp(-s * step)
+        T = np.concatenate([[1.0], np.cumprod(1.0 - a)])
+        out[r] = (T[:-1, None] * a[:, None] * col).sum(0) + T[-1] * np.asarray(bg, np.float64)
+    return out
