@@ -1,0 +1,264 @@
+"""Benchmark of the fine-stage per-ray training step on one MI355X.
+
+Workload (default): the full plain configuration - synthetic scene of 64
+soft spheres, 160^3 float32 density and 12-channel feature grids initialised
+as in the paper's fine stage (zero grids, low-density shift with
+alpha_init 1e-2), frozen 100^3 coarse density rasterised from the scene
+with the alpha-mask threshold 1e-4, 8192 rays per iteration drawn with
+replacement from 100 cameras of 800x800 pixels, step half a voxel, the
+39-128-128-3 colour network.  One step = sample + forward + loss + adjoint +
+Adam over all 53.2M grid values and the network, inputs resident in HBM.
+
+Metric: ray-samples/s = (sum over the timed iterations of the uniform
+in-box samples of each batch, before coarse skipping) / wall time of the
+timed iterations (HIP-synchronised on both sides).
+
+Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Algorithmic work per evaluated sample of the kernels the roofline can name.
+FLOP_MLP_FWD = 2 * (12 * 128 + 128 * 128 + 3 * 128)
+FLOP_MLP_BWD = FLOP_MLP_FWD + 2 * (3 * 128 + 128 * 128 + 12 * 128) + 2 * (3 * 128 + 128 * 128 + 128 * 40)
+BYTES_SCATTER = 8 * (1 + 12) * 4 * 2 + (4 + 48) + 8
+BYTES_GATHER_F32 = 8 * 4 + 8 * 48 + (4 + 48) + 8
+BYTES_GATHER_BF16 = 8 * 4 + 8 * 24 + (4 + 48) + 8
+PEAK = {"hbm": 8000.0, "f32": 157.3, "bf16": 2500.0}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--form", choices=["plain", "bf16"], default="plain")
+    ap.add_argument("--batches", type=int, default=8)
+    ap.add_argument("--rays", type=int, default=8192)
+    ap.add_argument("--profile-kernel", default="auto")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rays", type=int, default=256)
+    ap.add_argument("--morton", type=int, default=0)
+    return ap.parse_args()
+
+
+def setup(args):
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2111_11215_amd import api, train
+    from paper_2111_11215_amd._lib import DVGO_BF16, DVGO_F32
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    sp, cams, held, raw = synth.full_scene(0)
+    n = synth.FULL_N
+    voxel = 2.0 / (n - 1)
+    step = 0.5 * voxel
+    max_samples = int(math.ceil(2.0 * math.sqrt(3.0) / step)) + 1
+    b = api.low_density_bias(synth.FULL_ALPHA_INIT, voxel)
+    bmin, bmax = tuple(synth.BOX_MIN), tuple(synth.BOX_MAX)
+    thr = api.coarse_raw_threshold(synth.FULL_TAU, step)
+    raw_t = torch.as_tensor(raw).to(dev)
+    bits = api.coarse_mask_build(raw_t, bmin, bmax, thr)
+    coarse = (bits, bmin, bmax, raw.shape)
+    spheres = torch.as_tensor(sp.as_f32_table()).to(dev)
+    batches = []
+    for i in range(args.batches):
+        rng = np.random.default_rng(1000 + i)
+        o, d, *_ = synth.draw_pixels_with_replacement(rng, cams, 800, 800, 1000.0, args.rays)
+        jit = rng.random(args.rays).astype(np.float32)
+        ot, dt, jt = (torch.as_tensor(a).to(dev) for a in (o, d, jit))
+        tgt = api.scene_render(ot, dt, spheres, bmin, bmax, step / 4)
+        batches.append(dict(o=ot, d=dt, j=jt, target=tgt, o_np=o, d_np=d, j_np=jit))
+    rng_w = np.random.default_rng(7)
+    Ws, bs = synth.xavier_uniform_mlp(rng_w, (39, 128, 128, 3))
+    flat = api.flat_from([Ws[0], bs[0], Ws[1], bs[1], Ws[2], bs[2]], api.MLP_SHAPES, dev)
+    bf16 = args.form == "bf16"
+    cfg = train.FineConfig(step=step, max_samples=max_samples, precision=DVGO_BF16 if bf16 else DVGO_F32,
+                           bf16_feat=bf16, morton=bool(args.morton))
+    model = train.FineModel(torch.zeros((n, n, n), device=dev), torch.zeros((n, n, n, 12), device=dev), flat,
+                            bmin, bmax, b, cfg, coarse=coarse)
+    # numerators: uniform in-box samples and evaluated samples of each batch
+    for bt in batches:
+        s = model.sample(bt["o"], bt["d"], bt["j"])
+        bt["n_uniform"] = int(s.n_uniform.sum().item())
+        bt["n_kept"] = int(s.n_kept.item())
+    return dict(model=model, batches=batches, step=step, max_samples=max_samples, b=b, raw=raw, bits=bits,
+                coarse=coarse, spheres=sp, bmin=bmin, bmax=bmax, n=n)
+
+
+def run_steps(model, batches, k0, k):
+    for i in range(k):
+        bt = batches[(k0 + i) % len(batches)]
+        model.train_step(bt["o"], bt["d"], bt["target"], bt["j"])
+
+
+def cpu_baseline(ctx, rays):
+    """The oracle as it stands, one thread, on a bounded sample: the full
+    step (sample, forward, loss, adjoint) for the first `rays` rays of batch 0
+    scaled to the 8192-ray batch, plus one oracle Adam step over every
+    parameter of the configuration."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import oracle as O
+    import synth
+
+    bt = ctx["batches"][0]
+    B = bt["o_np"].shape[0]
+    o, d, j = bt["o_np"][:rays], bt["d_np"][:rays], bt["j_np"][:rays]
+    n = ctx["n"]
+    tgt = bt["target"][:rays].cpu().numpy()
+    rng_w = np.random.default_rng(7)
+    Ws, bs = synth.xavier_uniform_mlp(rng_w, (39, 128, 128, 3))
+    thr = O.coarse_raw_threshold(synth.FULL_TAU, ctx["step"])
+    bits = O.coarse_cell_bits(ctx["raw"], thr)
+    dens = np.zeros((n, n, n), np.float32)
+    feat = np.zeros((n, n, n, 12), np.float32)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        samp = O.sample_rays(o, d, j, ctx["bmin"], ctx["bmax"], ctx["step"], ctx["max_samples"],
+                             coarse=(bits, ctx["bmin"], ctx["bmax"], ctx["raw"].shape))
+        prm = O.Params(dens, feat, Ws, bs, ctx["bmin"], ctx["bmax"], ctx["b"])
+        fwd = O.render_forward(prm, o, d, j, samp, ctx["step"], (1.0, 1.0, 1.0))
+        _, g = O.photo_loss(fwd["rgb"], tgt)
+        gr = O.render_backward(prm, o, d, j, samp, ctx["step"], (1.0, 1.0, 1.0), fwd, g)
+        t_rays = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for p_, g_ in ((dens, gr["density"]), (feat, gr["feat"])):
+            O.adam_step(p_, g_, np.zeros(p_.shape), np.zeros(p_.shape), 0.1, 0.9, 0.999, 1e-8, 1)
+        for w_, gw in zip(Ws + bs, gr["Ws"] + gr["bs"]):
+            O.adam_step(w_, gw, np.zeros(w_.shape), np.zeros(w_.shape), 1e-3, 0.9, 0.999, 1e-8, 1)
+        t_adam = time.perf_counter() - t0
+    per_iter = t_rays * (B / rays) + t_adam
+    return {"value": bt["n_uniform"] / per_iter, "unit": "ray-samples/s", "cores": 1, "kind": "oracle",
+            "sample": (f"first {rays} of the {B} rays of batch 0 (sample, forward, loss, adjoint: "
+                       f"{t_rays:.2f} s, scaled x{B / rays:.0f}) + one Adam step over all parameters "
+                       f"({t_adam:.2f} s); 1 thread")}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build measures one GPU only: the training step is data-parallel over "
+                                   "rays but no multi-GPU path is built; run with --gpus 1"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2111_11215_amd import _lib
+    lib = _lib.load()
+    log("bench: setup")
+    ctx = setup(args)
+    model, batches = ctx["model"], ctx["batches"]
+    log(f"bench: warmup {args.warmup}")
+    run_steps(model, batches, 0, args.warmup)
+    torch.cuda.synchronize()
+    log(f"bench: timed {args.steps}")
+    t0 = time.perf_counter()
+    run_steps(model, batches, args.warmup, args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    used = [batches[(args.warmup + i) % len(batches)] for i in range(args.steps)]
+    total_uniform = sum(b["n_uniform"] for b in used)
+    total_kept = sum(b["n_kept"] for b in used)
+    value = total_uniform / elapsed
+    ms = 1e3 * elapsed / args.steps
+    log(f"bench: {value:.4e} ray-samples/s, {ms:.3f} ms/step, kept {total_kept / args.steps:.0f}/step")
+
+    # dominant-kernel timing: events around that kernel, on its own stream
+    bf16 = args.form == "bf16"
+    kname = args.profile_kernel if args.profile_kernel != "auto" else "mlp_bwd"
+    per_kernel = {}
+    for name in ("gather", "mlp_fwd", "compose_fwd", "compose_bwd", "mlp_bwd", "scatter", "adam", "fill_kept",
+                 "count_kept", "ray_setup", "reduce"):
+        _lib.check("dvgo_profile_enable", lib.dvgo_profile_enable(_lib.KERNEL_IDS[name]))
+        run_steps(model, batches, args.warmup, min(args.steps, 10))
+        tot = ctypes_double()
+        cnt = ctypes_int64()
+        _lib.check("dvgo_profile_read", lib.dvgo_profile_read(tot, cnt))
+        per_kernel[name] = {"ms_total": tot.value, "launches": cnt.value,
+                            "ms_avg": tot.value / max(cnt.value, 1)}
+    lib.dvgo_profile_enable(-1)
+    n_prof = min(args.steps, 10)
+    kept_prof = sum(batches[(args.warmup + i) % len(batches)]["n_kept"] for i in range(n_prof)) / n_prof
+    k = per_kernel[kname]
+    # launches per step of the named kernel
+    lps = k["launches"] / n_prof
+    if kname in ("mlp_bwd", "mlp_fwd"):
+        flop = (FLOP_MLP_BWD if kname == "mlp_bwd" else FLOP_MLP_FWD) * kept_prof / lps
+        achieved = flop / (k["ms_avg"] * 1e-3) / 1e12
+        peak = PEAK["bf16" if bf16 else "f32"]
+        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": None}
+    else:
+        per = {"scatter": BYTES_SCATTER, "gather": BYTES_GATHER_BF16 if bf16 else BYTES_GATHER_F32}.get(kname)
+        if kname == "adam":
+            nparam = model.st_density.p.numel() + model.st_feat.p.numel() + model.st_mlp.p.numel()
+            bytes_ = (32 * nparam + (2 * model.st_feat.p.numel() if bf16 else 0)) / lps
+        else:
+            bytes_ = per * kept_prof / lps
+        achieved = bytes_ / (k["ms_avg"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm"], "unit": "GB/s",
+                "frac": achieved / PEAK["hbm"], "traffic": None}
+    roof["kernel"] = kname
+    out = {
+        "metric": "fwd+bwd ray-samples/s per train iter",
+        "value": value,
+        "unit": "ray-samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16" if bf16 else "f32",
+        "data": "synthetic",
+        "config": {"workload": ("full plain configuration: 64-sphere synthetic scene, 160^3 fp32 density + "
+                                "12-ch feature grids, 100^3 coarse alpha mask (tau 1e-4), 8192 rays/iter from "
+                                "100 cameras 800x800, step 0.5 voxel, 39-128-128-3 MLP, Adam")
+                   + (" [BF16 features + BF16 MLP]" if bf16 else ""),
+                   "rays_per_iter": args.rays, "grid": 160, "coarse": 100, "max_samples": ctx["max_samples"],
+                   "morton": bool(args.morton)},
+        "evaluated_samples_per_step": total_kept / args.steps,
+        "uniform_samples_per_step": total_uniform / args.steps,
+        "rays_per_s": args.rays * args.steps / elapsed,
+        "kernels_ms_per_step": {n_: v["ms_total"] / n_prof for n_, v in per_kernel.items()},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log("bench: cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(ctx, args.cpu_rays)
+    print(json.dumps(out), flush=True)
+
+
+def ctypes_double():
+    import ctypes
+    return ctypes.c_double()
+
+
+def ctypes_int64():
+    import ctypes
+    return ctypes.c_int64()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,280 @@
+/*
+ * dvgo.h - C ABI of the MI355X (gfx950) library for the fine-stage per-ray
+ * training step of direct voxel-grid radiance-field optimisation
+ * (Sun, Sun and Chen, "Direct Voxel Grid Optimization", arXiv 2111.11215).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Pointers: unless marked "host", every pointer is a device pointer to a
+ *   caller-owned buffer (for example a torch tensor's data_ptr()).  The
+ *   library allocates nothing: scratch memory is passed in as a workspace
+ *   whose size the matching *_workspace_bytes query returns.
+ * Streams: `stream` is a hipStream_t passed as void*; NULL is the default
+ *   stream.  Every call is asynchronous with respect to the host and orders
+ *   its kernels on that stream only.
+ * Errors: every entry point returns a dvgo_status.  Arguments are validated
+ *   on the host before anything is enqueued; on a non-zero status nothing has
+ *   been enqueued.  DVGO_E_HIP means a launch failed; dvgo_last_error() then
+ *   holds the HIP error text.  Conditions only the device can see (sample
+ *   capacity overflow) are reported through device-side counters documented
+ *   per call.
+ * Layouts: rays [B][3] float32 with unit-norm directions; vertex grids
+ *   spanning the box inclusively ("align-corners"), density [nx][ny][nz] and
+ *   features channel-last [nx][ny][nz][C]; network weights row-major
+ *   [out][in] float32.
+ * Numerics: discrete decisions (ray validity, sample counts, kept samples,
+ *   Morton order, proposal masks) follow an explicit float32 recipe with no
+ *   contraction, documented per call, so they are reproducible bit for bit.
+ */
+#ifndef DVGO_H
+#define DVGO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum dvgo_status {
+    DVGO_OK = 0,
+    DVGO_E_ARG = -1,          /* null pointer, negative size, bad value      */
+    DVGO_E_SHAPE = -2,        /* inconsistent sizes                          */
+    DVGO_E_DTYPE = -3,        /* unsupported element type / precision code   */
+    DVGO_E_CAPACITY = -4,     /* a caller buffer or workspace is too small   */
+    DVGO_E_HIP = -5,          /* a HIP launch failed (see dvgo_last_error)   */
+    DVGO_E_UNSUPPORTED = -6   /* valid but not implemented (e.g. size limit) */
+} dvgo_status;
+
+enum { DVGO_F32 = 0, DVGO_BF16 = 1 };
+
+/* Axis-aligned box with n[i] grid vertices per axis spanning it inclusively. */
+typedef struct dvgo_box {
+    float xyz_min[3];
+    float xyz_max[3];
+    int32_t n[3];
+} dvgo_box;
+
+/* Fine scene representation of the paper's Sec. 4.2 (Eq. fine_queries):
+ * the density grid with post-activation (Eq. post_activation, shift b of
+ * Eq. density_activation) and the feature grid.  `feat` is float32 or a
+ * bfloat16 shadow (feat_dtype), channel-last; `channels` must be 12. */
+typedef struct dvgo_field {
+    const float* density;
+    const void* feat;
+    int32_t feat_dtype;
+    int32_t channels;
+    dvgo_box box;
+    float act_shift;
+} dvgo_field;
+
+/* The shallow colour network of Eq. fine_queries: input [feat(C), PE(d)(27)],
+ * two ReLU layers of `hidden` (must be 128) and a sigmoid RGB output.
+ * Weights are float32 masters [out][in]; `precision` selects the arithmetic
+ * of its matrix products: DVGO_F32 (float32 matrix cores) or DVGO_BF16
+ * (bfloat16 inputs, float32 accumulation). */
+typedef struct dvgo_mlp {
+    const float* w1; const float* b1;   /* [hidden][C+27], [hidden] */
+    const float* w2; const float* b2;   /* [hidden][hidden], [hidden] */
+    const float* w3; const float* b3;   /* [3][hidden], [3] */
+    int32_t hidden;
+    int32_t precision;
+} dvgo_mlp;
+
+/* Flat gradient layout of dvgo_mlp: w1, b1, w2, b2, w3, b3 concatenated. */
+int64_t dvgo_mlp_param_count(int32_t channels, int32_t hidden);
+
+/* Proposal network (not in the paper: a learned predictor of which of 32
+ * equal-count ray segments carry the compositing weight): input 54 values
+ * (positional encodings, 4 frequencies, of the box-entry point in box
+ * coordinates and of the direction), two ReLU layers of 64, 32 logits.
+ * float32 masters [out][in]; evaluated with bfloat16 matrix products. */
+typedef struct dvgo_prop {
+    const float* w1; const float* b1;   /* [64][54], [64] */
+    const float* w2; const float* b2;   /* [64][64], [64] */
+    const float* w3; const float* b3;   /* [32][64], [32] */
+} dvgo_prop;
+int64_t dvgo_prop_param_count(void);
+
+/* ------------------------------------------------------------------------ */
+/* Coarse alpha mask (paper Sec. 4.2, "Known free space and unknown space"
+ * and "Free space skipping", first rule).  One bit per cell of the frozen
+ * coarse density grid raw [nx][ny][nz] (box cbox): bit c of word c>>5, with
+ * c = (ix*(ny-1)+iy)*(nz-1)+iz, is set when the largest of the cell's 8
+ * corner raw values is >= raw_threshold.  With raw_threshold =
+ * softplus^{-1}(-log(1-tau)/delta) - b (rounded down to float32) every point
+ * whose post-activated coarse alpha reaches tau lies in a kept cell.
+ * bits: ceil((nx-1)(ny-1)(nz-1)/32) words, fully overwritten. */
+int32_t dvgo_coarse_mask_build(const float* raw, const dvgo_box* cbox /*host*/,
+                               float raw_threshold, uint32_t* bits, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Ray sampling of the fine stage (paper Eq. coarse_sample with the training
+ * jitter of the supplementary details, Sec. 4.2 "Fine-stage points
+ * sampling" and "Free space skipping" rule one).
+ *
+ * Per ray (float32 recipe, every operation rounded, no FMA):
+ *   slab clip: per axis inv = 1/d, t0 = (min-o)*inv, t1 = (max-o)*inv
+ *     (d = 0: unbounded if min <= o <= max, else a miss); t_enter = max fmin,
+ *     t_exit = min fmax; t_near = max(t_enter, 0), t_far = t_exit;
+ *     valid = t_near < t_far (invalid rays get t_near = t_far = 0);
+ *   uniform samples t_k = t_near + ((float)k + p)*step, k >= 0, while
+ *     t_k < t_far and k < max_samples: n_uniform = their count;
+ *   kept samples: x_k = o + t_k*d; kept when the coarse bit of its cell
+ *     (cell = clamp(floor((x-min)*((n-1)/(max-min))), 0, n-2)) is set
+ *     (coarse_bits NULL: all kept) and, with seg_mask, when bit
+ *     floor(32k/n_uniform) of seg_mask[r] is set.
+ * Ray order of the compact list: slot i holds ray perm[i]; perm is the
+ *   identity, or with `morton` != 0 the rays sorted by (key, ray id) where key
+ *   is the 15-bit Morton code (x most significant) of the segment midpoint
+ *   o + ((t_near+t_far)*0.5)*d quantised to 32 cells per axis of `box`,
+ *   invalid rays last (key 2^15).  morton requires B <= 32768.
+ * Outputs: t_near, t_far [B]; valid [B] (0/1); n_uniform [B];
+ *   perm [B]; ray_offset [B+1] (ray perm[i] owns samples ray_offset[i] ..
+ *   ray_offset[i+1]-1, ascending k); sample_ray, sample_k [capacity];
+ *   n_kept: device int64, the total kept.  When n_kept > capacity the list
+ *   is truncated (samples at index >= capacity are not written) and the
+ *   caller must retry with a larger capacity; capacity = B*max_samples never
+ *   overflows.
+ * jitter: [B] per-ray p in [0,1), or NULL for p = 0.
+ * workspace: dvgo_sample_workspace_bytes(B) bytes. */
+size_t dvgo_sample_workspace_bytes(int32_t B);
+int32_t dvgo_sample_rays(const float* rays_o, const float* rays_d, const float* jitter,
+                         int32_t B, const dvgo_box* box /*host*/, float step,
+                         int32_t max_samples, const uint32_t* coarse_bits,
+                         const dvgo_box* coarse_box /*host, or NULL*/,
+                         const uint32_t* seg_mask, int32_t morton,
+                         float* t_near, float* t_far, uint8_t* valid, int32_t* n_uniform,
+                         int32_t* perm, int32_t* ray_offset, int32_t* sample_ray,
+                         int32_t* sample_k, int64_t capacity, int64_t* n_kept,
+                         void* workspace, size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Forward volume rendering (paper Eq. volume_rendering, Eq. fine_queries,
+ * Eq. post_activation) of the samples listed by dvgo_sample_rays, per ray in
+ * ascending k:
+ *   raw_k = interp(x_k, density), sigma_k = softplus(raw_k + act_shift),
+ *   alpha_k = 1 - exp(-sigma_k*step), T_k = exp(-step*sum_{j<k} sigma_j),
+ *   w_k = T_k alpha_k, c_k = MLP([interp(x_k, feat), PE(d)]),
+ *   rgb = sum w_k c_k + T_end*bg, depth = sum w_k t_k, acc = sum w_k,
+ *   log_t_end = -step*sum sigma_k, seg_w[r][s] = sum of w_k over segment
+ *   s = floor(32k/n_uniform).
+ * Trilinear interpolation: u = (x-min)*((n-1)/(max-min)), i0 =
+ *   clamp(floor(u), 0, n-2), f = clamp(u-i0, 0, 1).  PE(d) = [d, sin(2^j d),
+ *   cos(2^j d)] for j = 0..3.
+ * m == NULL renders density only (rgb must then be NULL; the other outputs
+ *   are produced): the proposal's target pass.
+ * Outputs indexed by ray id: rgb [B][3], depth, acc, log_t_end [B] (each
+ *   NULL to skip except log_t_end, which the backward pass needs),
+ *   seg_w [B][32] or NULL; sample_w [capacity] or NULL (w_k in compact-list
+ *   order).  All are overwritten.
+ * n_kept: the device count written by dvgo_sample_rays; samples beyond
+ *   min(n_kept, capacity) are ignored.
+ * bg: host float[3].
+ * workspace: dvgo_render_workspace_bytes(B, capacity, channels) bytes. */
+size_t dvgo_render_workspace_bytes(int32_t B, int64_t capacity, int32_t channels);
+int32_t dvgo_render_fwd(const dvgo_field* field /*host*/, const dvgo_mlp* mlp /*host or NULL*/,
+                        const float* rays_o, const float* rays_d, const float* jitter,
+                        const float* t_near, const int32_t* n_uniform, const int32_t* perm,
+                        const int32_t* ray_offset, const int32_t* sample_ray,
+                        const int32_t* sample_k, const int64_t* n_kept, int64_t capacity,
+                        int32_t B, float step, const float* bg /*host[3]*/,
+                        float* rgb, float* depth, float* acc, float* log_t_end, float* seg_w,
+                        float* sample_w, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Backward pass of dvgo_render_fwd: the adjoint recomputes every per-sample
+ * quantity and walks each ray from its end, starting from the forward's
+ * log_t_end (no per-sample state is kept between the calls):
+ *   S_{K+1} = T_end*(bg, 0, 0),  S_k = S_{k+1} + w_k*(c_k, t_k, 1),
+ *   dL/dsigma_k = step * g.(T_{k+1}*(c_k, t_k, 1) - S_{k+1}),
+ *   dL/draw_k = dL/dsigma_k * sigmoid(raw_k + act_shift),
+ *   dL/dc_k = w_k * grad_rgb, then through the network to the features,
+ * where g = (grad_rgb, grad_depth, grad_acc) (the latter two may be NULL).
+ * Gradients are ACCUMULATED (+=) into grad_density [nx][ny][nz],
+ * grad_feat [nx][ny][nz][C] (float32 whatever feat_dtype is) and grad_mlp
+ * (flat, dvgo_mlp_param_count values; may be NULL with mlp == NULL).
+ * Grid gradients use float atomics: their summation order, and so their
+ * last bits, vary from run to run.  Same workspace as dvgo_render_fwd. */
+int32_t dvgo_render_bwd(const dvgo_field* field /*host*/, const dvgo_mlp* mlp /*host or NULL*/,
+                        const float* rays_o, const float* rays_d, const float* jitter,
+                        const float* t_near, const int32_t* n_uniform, const int32_t* perm,
+                        const int32_t* ray_offset, const int32_t* sample_ray,
+                        const int32_t* sample_k, const int64_t* n_kept, int64_t capacity,
+                        int32_t B, float step, const float* bg /*host[3]*/,
+                        const float* log_t_end, const float* grad_rgb, const float* grad_depth,
+                        const float* grad_acc, float* grad_density, float* grad_feat,
+                        float* grad_mlp, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Photometric loss of paper Eq. photo_loss: loss = (1/B) sum_r
+ * ||rgb_r - target_r||^2 and grad_rgb = 2 (rgb - target)/B.  grad_rgb [B][3]
+ * is overwritten; loss (device float, or NULL) is overwritten. */
+int32_t dvgo_photo_loss(const float* rgb, const float* target, int32_t B, float* grad_rgb,
+                        float* loss, void* stream);
+
+/* One Adam step (the paper's optimiser, Sec. 5.2) over n float32 values:
+ *   m = beta1*m + (1-beta1)*g;  v = beta2*v + (1-beta2)*g^2;
+ *   p -= lr * (m/(1-beta1^t)) / (sqrt(v/(1-beta2^t)) + eps);  g = 0;
+ * and, when shadow_bf16 is not NULL, shadow = bf16(p) (round to nearest
+ * even), the storage the bfloat16 feature gathers read.  t >= 1. */
+int32_t dvgo_adam_step(float* p, float* g, float* m, float* v, uint16_t* shadow_bf16,
+                       int64_t n, float lr, float beta1, float beta2, float eps, int32_t t,
+                       void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Learned proposal (not in the paper).  Forward: logits z [B][32] of the
+ * proposal network on each ray's encoding; q = softmax([z, 0]) over 33
+ * entries (the last is the transmitted share), pred_mass = sum_{s<32} q_s;
+ * seg_mask[r] = the smallest set of segments, by descending q (ties to the
+ * lower index), whose q sum reaches cum_frac * pred_mass, or all ones when
+ * pred_mass < min_mass or the ray is invalid.  The selection runs in float64
+ * from the float32 logits.  valid/t_near come from dvgo_sample_rays. */
+int32_t dvgo_proposal_fwd(const float* rays_o, const float* rays_d, const float* t_near,
+                          const uint8_t* valid, int32_t B, const dvgo_box* box /*host*/,
+                          const dvgo_prop* prop /*host*/, float cum_frac, float min_mass,
+                          float* logits, float* pred_mass, uint32_t* seg_mask, void* stream);
+
+/* Proposal backward: KL(p || q) averaged over the valid rays, with target
+ * p = (seg_w[r][0..31], exp(log_t_end[r])) from a density-only render;
+ * dL/dz_s = (q_s - p_s)/n_valid.  grad_prop (flat, dvgo_prop_param_count) is
+ * ACCUMULATED; loss (device float or NULL) is overwritten. */
+int32_t dvgo_proposal_bwd(const float* rays_o, const float* rays_d, const float* t_near,
+                          const uint8_t* valid, int32_t B, const dvgo_box* box /*host*/,
+                          const dvgo_prop* prop /*host*/, const float* seg_w,
+                          const float* log_t_end, float* grad_prop, float* loss,
+                          void* workspace, size_t workspace_bytes, void* stream);
+size_t dvgo_proposal_workspace_bytes(int32_t B);
+
+/* ------------------------------------------------------------------------ */
+/* Data generation (not part of the training step): colour of each ray
+ * through an analytic scene of soft spheres, rows (cx,cy,cz,r,rho,R,G,B):
+ * density sum_i rho_i*sigmoid((r_i - |x-c_i|)/edge), colour the density-
+ * weighted mean, composited by the same quadrature at midpoints
+ * t_near + (k+1/2)*step inside the box, background bg (host float[3]). */
+int32_t dvgo_scene_render(const float* rays_o, const float* rays_d, int32_t B,
+                          const dvgo_box* box /*host*/, const float* spheres, int32_t n_spheres,
+                          float edge, float step, const float* bg /*host[3]*/, float* rgb,
+                          void* stream);
+
+/* Human-readable text of a status; dvgo_last_error() is the last HIP error
+ * text recorded by this thread (empty if none).  Static strings. */
+const char* dvgo_status_string(int32_t status);
+const char* dvgo_last_error(void);
+int32_t dvgo_version(void);
+
+/* Optional timing of one kernel (host-side, not thread-safe): with
+ * kernel_id >= 0, every later launch of that kernel is bracketed by a pair of
+ * HIP events recorded on the launch's own stream; dvgo_profile_read waits for
+ * them and returns the summed elapsed milliseconds and the launch count since
+ * the last dvgo_profile_enable.  kernel_id -1 turns timing off.  Ids:
+ *   0 ray setup, 1 Morton sort, 2 count kept, 3 scan, 4 fill kept,
+ *   5 coarse mask, 6 weight pack, 7 per-ray encoding, 8 gather, 9 MLP forward,
+ *   10 compose forward, 11 compose backward, 12 MLP backward, 13 scatter,
+ *   14 partial reduce, 15 photo loss, 16 Adam, 17 proposal forward,
+ *   18 proposal backward, 19 proposal reduce, 20 scene render. */
+int32_t dvgo_profile_enable(int32_t kernel_id);
+int32_t dvgo_profile_read(double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DVGO_H */

@@ -330,35 +330,74 @@ def positional_encoding(d, n_freq=4):
     return np.concatenate(parts, axis=-1)
 
 
-def mlp_forward(Ws, bs, x):
+def bf16_round(x):
+    """Round float32 values to bfloat16 (round to nearest, ties to even) and
+    return them as float64: keep the top 16 bits of the float32 pattern after
+    adding 0x7FFF plus the lowest kept bit."""
+    a = np.ascontiguousarray(np.asarray(x, np.float32))
+    u = a.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    out = r.astype(np.uint32).view(np.float32).astype(np.float64)
+    return np.where(np.isfinite(a), out, a.astype(np.float64))
+
+
+def mlp_forward(Ws, bs, x, bf16=False, n_feat=12):
     """The shallow colour MLP of Eq. fine_queries: two ReLU hidden layers of
-    128, sigmoid output (Sec. 3 output activation).  Ws[l] is [out][in]."""
+    128, sigmoid output (Sec. 3 output activation).  Ws[l] is [out][in].
+
+    bf16=True evaluates the bfloat16 form: the inputs of every product
+    (feature part of the first-layer input, hidden activations, weights) are
+    rounded to bfloat16 and the products summed exactly; the view-encoding
+    part of the first layer and the biases stay unrounded."""
     W1, W2, W3 = [np.asarray(w, np.float64) for w in Ws]
     b1, b2, b3 = [np.asarray(b, np.float64) for b in bs]
-    z1 = x @ W1.T + b1
+    if bf16:
+        z1 = bf16_round(x[:, :n_feat]) @ bf16_round(W1[:, :n_feat]).T + (x[:, n_feat:] @ W1[:, n_feat:].T + b1)
+    else:
+        z1 = x @ W1.T + b1
     h1 = np.maximum(z1, 0.0)
-    z2 = h1 @ W2.T + b2
+    z2 = (bf16_round(h1) @ bf16_round(W2).T if bf16 else h1 @ W2.T) + b2
     h2 = np.maximum(z2, 0.0)
-    z3 = h2 @ W3.T + b3
+    z3 = (bf16_round(h2) @ bf16_round(W3).T if bf16 else h2 @ W3.T) + b3
     c = sigmoid(z3)
-    return c, dict(x=x, z1=z1, h1=h1, z2=z2, h2=h2, c=c)
+    return c, dict(x=x, z1=z1, h1=h1, z2=z2, h2=h2, c=c, bf16=bf16, n_feat=n_feat)
 
 
 def mlp_backward(Ws, cache, dc):
     """Reverse-mode derivative of ``mlp_forward`` for output gradient dc.
-    ReLU'(0) is taken as 0.  Returns (dx, [dW1,dW2,dW3], [db1,db2,db3])."""
+    ReLU'(0) is taken as 0.  Returns (dx, [dW1,dW2,dW3], [db1,db2,db3]); dx
+    holds only the feature part in the bfloat16 form.
+
+    bfloat16 form: the backward products take bfloat16-rounded weights and
+    bfloat16-rounded propagated gradients where a product consumes them as a
+    matrix operand (dz2 into W2^T, and both factors of every weight
+    gradient); the first-layer input's gradient uses bfloat16 W1 with the
+    unrounded dz1; bias gradients sum the rounded dz (dz3 unrounded)."""
     W1, W2, W3 = [np.asarray(w, np.float64) for w in Ws]
     c = cache["c"]
     dz3 = dc * c * (1.0 - c)
-    dW3 = dz3.T @ cache["h2"]
+    if not cache.get("bf16"):
+        dW3 = dz3.T @ cache["h2"]
+        db3 = dz3.sum(0)
+        dz2 = (dz3 @ W3) * (cache["z2"] > 0)
+        dW2 = dz2.T @ cache["h1"]
+        db2 = dz2.sum(0)
+        dz1 = (dz2 @ W2) * (cache["z1"] > 0)
+        dW1 = dz1.T @ cache["x"]
+        db1 = dz1.sum(0)
+        dx = dz1 @ W1
+        return dx, [dW1, dW2, dW3], [db1, db2, db3]
+    nf = cache["n_feat"]
+    bf = bf16_round
+    dW3 = bf(dz3).T @ bf(cache["h2"])
     db3 = dz3.sum(0)
-    dz2 = (dz3 @ W3) * (cache["z2"] > 0)
-    dW2 = dz2.T @ cache["h1"]
-    db2 = dz2.sum(0)
-    dz1 = (dz2 @ W2) * (cache["z1"] > 0)
-    dW1 = dz1.T @ cache["x"]
-    db1 = dz1.sum(0)
-    dx = dz1 @ W1
+    dz2 = (dz3 @ bf(W3)) * (cache["z2"] > 0)
+    dW2 = bf(dz2).T @ bf(cache["h1"])
+    db2 = bf(dz2).sum(0)
+    dz1 = (bf(dz2) @ bf(W2)) * (cache["z1"] > 0)
+    dW1 = bf(dz1).T @ bf(cache["x"])
+    db1 = bf(dz1).sum(0)
+    dx = dz1 @ bf(W1[:, :nf])
     return dx, [dW1, dW2, dW3], [db1, db2, db3]
 
 
@@ -387,7 +426,8 @@ class Params:
     """Fine-stage scene representation: density grid, feature grid, MLP
     (Eq. fine_queries), the softplus shift b and the AABB."""
 
-    def __init__(self, density, feat, Ws, bs, box_min, box_max, act_shift):
+    def __init__(self, density, feat, Ws, bs, box_min, box_max, act_shift, mlp_bf16=False):
+        self.mlp_bf16 = bool(mlp_bf16)
         self.density = np.asarray(density)
         self.feat = np.asarray(feat)
         self.Ws = [np.asarray(w) for w in Ws]
@@ -442,7 +482,7 @@ def render_forward(P: Params, o, d, jitter, samp, step, bg, with_color=True):
         f = interp(P.feat, x, P.box_min, P.box_max)
         pe = positional_encoding(d.astype(np.float64))[sr]
         xin = np.concatenate([f, pe], axis=1)
-        c, mcache = mlp_forward(P.Ws, P.bs, xin)
+        c, mcache = mlp_forward(P.Ws, P.bs, xin, bf16=P.mlp_bf16, n_feat=P.feat.shape[-1])
         rgb = np.zeros((B, 3))
         np.add.at(rgb, slot, w[:, None] * c)
         rgb += T_end_slot[:, None] * np.asarray(bg, np.float64)[None, :]
@@ -460,6 +500,7 @@ def render_forward(P: Params, o, d, jitter, samp, step, bg, with_color=True):
     res["seg_w"][perm] = seg_w
     res["sample_w"] = w
     res["cache"] = cache
+    res["_sample_ray"] = np.asarray(sr, np.int64)
     return res
 
 
@@ -608,13 +649,23 @@ def proposal_forward(Ws, bs, enc):
 
 def proposal_probs(z):
     """33-way softmax of the 32 segment logits and an implicit transmitted
-    logit fixed at 0; returns (q [B,33], predicted mass sum_{s<32} q_s)."""
+    logit fixed at 0; returns (q [B,33], predicted mass sum_{s<32} q_s).
+    Sums run sequentially in index order (the transmitted entry last), the
+    reading under which the selection is reproducible in float64."""
     z = np.asarray(z, np.float64)
     zz = np.concatenate([z, np.zeros((z.shape[0], 1))], axis=1)
-    m = zz.max(axis=1, keepdims=True)
-    e = np.exp(zz - m)
-    q = e / e.sum(axis=1, keepdims=True)
-    return q, q[:, :NSEG].sum(axis=1)
+    m = np.zeros(z.shape[0])
+    for s in range(NSEG):
+        m = np.maximum(m, zz[:, s])
+    e = np.exp(zz - m[:, None])
+    tot = np.zeros(z.shape[0])
+    for s in range(NSEG + 1):
+        tot = tot + e[:, s]
+    q = e / tot[:, None]
+    mass = np.zeros(z.shape[0])
+    for s in range(NSEG):
+        mass = mass + q[:, s]
+    return q, mass
 
 
 def proposal_select(z, cum_frac=0.99, min_mass=0.9):

@@ -1,0 +1,330 @@
+"""Thin torch-facing wrappers of the C ABI (argument marshalling only).
+
+Every function takes and returns device tensors, allocates its outputs with
+torch (device memory is torch's), passes raw pointers and the current HIP
+stream to ``libdvgo.so`` and raises ``DvgoError`` on a non-zero status.  No
+arithmetic of the method happens here.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+from . import _lib
+from ._lib import DVGO_BF16, DVGO_F32, Box, Field, Mlp, Prop, check, load, make_box
+
+NSEG = 32
+HIDDEN = 128
+CHANNELS = 12
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "expected a contiguous device tensor"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device=None) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+_WS: dict = {}
+
+
+def workspace(nbytes: int, device) -> torch.Tensor:
+    """A cached uint8 device buffer of at least ``nbytes`` per (device,
+    stream); calls on one stream are ordered, so reuse is safe."""
+    key = (torch.device(device).index, torch.cuda.current_stream(device).cuda_stream)
+    buf = _WS.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+        _WS[key] = buf
+    return buf
+
+
+# ---------------------------------------------------------------------------
+# host-side scalar hyperparameters
+# ---------------------------------------------------------------------------
+def low_density_bias(alpha_init: float, voxel: float) -> float:
+    """Softplus shift of the low-density initialisation (paper
+    Eq. low_density_init): b = log((1 - alpha_init)^(-1/s) - 1)."""
+    return math.log(math.pow(1.0 - alpha_init, -1.0 / voxel) - 1.0)
+
+
+def coarse_raw_threshold(tau: float, step: float, act_shift: float = 0.0) -> float:
+    """Raw-density threshold equivalent to post-activated alpha >= tau at
+    sample spacing ``step`` (both activations increase with the raw value):
+    softplus^{-1}(-log(1-tau)/step) - b, rounded down to float32."""
+    import numpy as np
+    sig = -math.log1p(-tau) / step
+    thr = math.log(math.expm1(sig)) - act_shift
+    t32 = np.float32(thr)
+    if float(t32) > thr:
+        t32 = np.nextafter(t32, np.float32(-np.inf))
+    return float(t32)
+
+
+# ---------------------------------------------------------------------------
+# parameters
+# ---------------------------------------------------------------------------
+@dataclass
+class Grid:
+    """Fine scene grids on the device: density [n,n,n] and channel-last
+    features [n,n,n,12] float32, an optional bfloat16 feature shadow, the box
+    and the softplus shift."""
+    density: torch.Tensor
+    feat: torch.Tensor
+    box_min: tuple
+    box_max: tuple
+    act_shift: float
+    feat_shadow: Optional[torch.Tensor] = None   # int16 storage of bf16 values
+
+    @property
+    def n(self):
+        return tuple(self.density.shape)
+
+    def field(self, use_shadow: bool = False) -> Field:
+        f = Field()
+        f.density = self.density.data_ptr()
+        if use_shadow:
+            assert self.feat_shadow is not None
+            f.feat = self.feat_shadow.data_ptr()
+            f.feat_dtype = DVGO_BF16
+        else:
+            f.feat = self.feat.data_ptr()
+            f.feat_dtype = DVGO_F32
+        f.channels = self.feat.shape[-1]
+        f.box = make_box(self.box_min, self.box_max, self.n)
+        f.act_shift = float(self.act_shift)
+        return f
+
+
+MLP_SHAPES = [("w1", (HIDDEN, CHANNELS + 27)), ("b1", (HIDDEN,)), ("w2", (HIDDEN, HIDDEN)), ("b2", (HIDDEN,)),
+              ("w3", (3, HIDDEN)), ("b3", (3,))]
+PROP_SHAPES = [("w1", (64, 54)), ("b1", (64,)), ("w2", (64, 64)), ("b2", (64,)), ("w3", (NSEG, 64)),
+               ("b3", (NSEG,))]
+
+
+def split_flat(flat: torch.Tensor, shapes):
+    out, off = {}, 0
+    for name, shp in shapes:
+        n = math.prod(shp)
+        out[name] = flat[off:off + n].view(shp)
+        off += n
+    assert off == flat.numel()
+    return out
+
+
+def flat_from(arrays, shapes, device) -> torch.Tensor:
+    parts = [torch.as_tensor(a, dtype=torch.float32).reshape(-1) for a in arrays]
+    flat = torch.cat(parts).to(device)
+    assert flat.numel() == sum(math.prod(s) for _, s in shapes)
+    return flat
+
+
+def mlp_struct(flat: torch.Tensor, precision: int = DVGO_F32) -> Mlp:
+    v = split_flat(flat, MLP_SHAPES)
+    m = Mlp()
+    for name in ("w1", "b1", "w2", "b2", "w3", "b3"):
+        setattr(m, name, v[name].data_ptr())
+    m.hidden = HIDDEN
+    m.precision = precision
+    return m
+
+
+def prop_struct(flat: torch.Tensor) -> Prop:
+    v = split_flat(flat, PROP_SHAPES)
+    p = Prop()
+    for name in ("w1", "b1", "w2", "b2", "w3", "b3"):
+        setattr(p, name, v[name].data_ptr())
+    return p
+
+
+# ---------------------------------------------------------------------------
+# entry points
+# ---------------------------------------------------------------------------
+@dataclass
+class Samples:
+    """Output of ``sample_rays`` plus the per-ray inputs later calls need."""
+    rays_o: torch.Tensor
+    rays_d: torch.Tensor
+    jitter: Optional[torch.Tensor]
+    step: float
+    t_near: torch.Tensor
+    t_far: torch.Tensor
+    valid: torch.Tensor
+    n_uniform: torch.Tensor
+    perm: torch.Tensor
+    ray_offset: torch.Tensor
+    sample_ray: torch.Tensor
+    sample_k: torch.Tensor
+    n_kept: torch.Tensor
+    capacity: int
+
+    @property
+    def B(self) -> int:
+        return self.rays_o.shape[0]
+
+
+def coarse_mask_build(raw: torch.Tensor, cmin, cmax, raw_threshold: float) -> torch.Tensor:
+    lib = load()
+    n = tuple(raw.shape)
+    ncell = (n[0] - 1) * (n[1] - 1) * (n[2] - 1)
+    bits = torch.empty((ncell + 31) // 32, dtype=torch.int32, device=raw.device)
+    box = make_box(cmin, cmax, n)
+    check("dvgo_coarse_mask_build",
+          lib.dvgo_coarse_mask_build(_ptr(raw), ctypes.byref(box), raw_threshold, _ptr(bits), _stream(raw.device)))
+    return bits
+
+
+def sample_rays(rays_o, rays_d, jitter, box_min, box_max, step, max_samples, coarse=None, seg_mask=None,
+                morton=False, capacity=None) -> Samples:
+    """``coarse`` = (bits, cmin, cmax, cn) or None; seg_mask int32 [B] or None."""
+    lib = load()
+    dev = rays_o.device
+    B = rays_o.shape[0]
+    if capacity is None:
+        capacity = B * int(max_samples)
+    t_near = torch.empty(B, dtype=torch.float32, device=dev)
+    t_far = torch.empty_like(t_near)
+    valid = torch.empty(B, dtype=torch.uint8, device=dev)
+    n_uniform = torch.empty(B, dtype=torch.int32, device=dev)
+    perm = torch.empty(B, dtype=torch.int32, device=dev)
+    ray_offset = torch.empty(B + 1, dtype=torch.int32, device=dev)
+    sample_ray = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+    sample_k = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+    n_kept = torch.empty(1, dtype=torch.int64, device=dev)
+    box = make_box(box_min, box_max)
+    cbits, cbox = None, None
+    if coarse is not None:
+        cbits = coarse[0]
+        cbox = make_box(coarse[1], coarse[2], coarse[3])
+    nws = lib.dvgo_sample_workspace_bytes(B)
+    ws = workspace(nws, dev)
+    check("dvgo_sample_rays", lib.dvgo_sample_rays(
+        _ptr(rays_o), _ptr(rays_d), _ptr(jitter), B, ctypes.byref(box), float(step), int(max_samples),
+        _ptr(cbits), ctypes.byref(cbox) if cbox is not None else None, _ptr(seg_mask), int(bool(morton)),
+        _ptr(t_near), _ptr(t_far), _ptr(valid), _ptr(n_uniform), _ptr(perm), _ptr(ray_offset), _ptr(sample_ray),
+        _ptr(sample_k), int(capacity), _ptr(n_kept), _ptr(ws), nws, _stream(dev)))
+    return Samples(rays_o, rays_d, jitter, float(step), t_near, t_far, valid, n_uniform, perm, ray_offset,
+                   sample_ray, sample_k, n_kept, int(capacity))
+
+
+def _bg(bg):
+    arr = (ctypes.c_float * 3)(*[float(x) for x in bg])
+    return arr
+
+
+def render_fwd(grid: Grid, mlp_flat: Optional[torch.Tensor], s: Samples, bg=(1.0, 1.0, 1.0),
+               precision: int = DVGO_F32, use_shadow: bool = False, want_seg_w: bool = False,
+               want_sample_w: bool = False, want_depth_acc: bool = True) -> dict:
+    lib = load()
+    dev = s.rays_o.device
+    B = s.B
+    field = grid.field(use_shadow)
+    mlp = mlp_struct(mlp_flat, precision) if mlp_flat is not None else None
+    out = {
+        "rgb": torch.empty((B, 3), dtype=torch.float32, device=dev) if mlp is not None else None,
+        "depth": torch.empty(B, dtype=torch.float32, device=dev) if want_depth_acc else None,
+        "acc": torch.empty(B, dtype=torch.float32, device=dev) if want_depth_acc else None,
+        "log_t_end": torch.empty(B, dtype=torch.float32, device=dev),
+        "seg_w": torch.empty((B, NSEG), dtype=torch.float32, device=dev) if want_seg_w else None,
+        "sample_w": torch.empty(max(s.capacity, 1), dtype=torch.float32, device=dev) if want_sample_w else None,
+    }
+    nws = lib.dvgo_render_workspace_bytes(B, s.capacity, CHANNELS)
+    ws = workspace(nws, dev)
+    check("dvgo_render_fwd", lib.dvgo_render_fwd(
+        ctypes.byref(field), ctypes.byref(mlp) if mlp is not None else None, _ptr(s.rays_o), _ptr(s.rays_d),
+        _ptr(s.jitter), _ptr(s.t_near), _ptr(s.n_uniform), _ptr(s.perm), _ptr(s.ray_offset), _ptr(s.sample_ray),
+        _ptr(s.sample_k), _ptr(s.n_kept), s.capacity, B, s.step, _bg(bg), _ptr(out["rgb"]), _ptr(out["depth"]),
+        _ptr(out["acc"]), _ptr(out["log_t_end"]), _ptr(out["seg_w"]), _ptr(out["sample_w"]), _ptr(ws), nws,
+        _stream(dev)))
+    return out
+
+
+def render_bwd(grid: Grid, mlp_flat: Optional[torch.Tensor], s: Samples, log_t_end: torch.Tensor,
+               grad_rgb: Optional[torch.Tensor], grad_density: torch.Tensor, grad_feat: Optional[torch.Tensor],
+               grad_mlp: Optional[torch.Tensor], bg=(1.0, 1.0, 1.0), precision: int = DVGO_F32,
+               use_shadow: bool = False, grad_depth=None, grad_acc=None) -> None:
+    """Accumulates (+=) into grad_density, grad_feat and grad_mlp."""
+    lib = load()
+    dev = s.rays_o.device
+    field = grid.field(use_shadow)
+    mlp = mlp_struct(mlp_flat, precision) if mlp_flat is not None else None
+    nws = lib.dvgo_render_workspace_bytes(s.B, s.capacity, CHANNELS)
+    ws = workspace(nws, dev)
+    check("dvgo_render_bwd", lib.dvgo_render_bwd(
+        ctypes.byref(field), ctypes.byref(mlp) if mlp is not None else None, _ptr(s.rays_o), _ptr(s.rays_d),
+        _ptr(s.jitter), _ptr(s.t_near), _ptr(s.n_uniform), _ptr(s.perm), _ptr(s.ray_offset), _ptr(s.sample_ray),
+        _ptr(s.sample_k), _ptr(s.n_kept), s.capacity, s.B, s.step, _bg(bg), _ptr(log_t_end), _ptr(grad_rgb),
+        _ptr(grad_depth), _ptr(grad_acc), _ptr(grad_density), _ptr(grad_feat), _ptr(grad_mlp), _ptr(ws), nws,
+        _stream(dev)))
+
+
+def photo_loss(rgb: torch.Tensor, target: torch.Tensor):
+    lib = load()
+    grad = torch.empty_like(rgb)
+    loss = torch.empty(1, dtype=torch.float32, device=rgb.device)
+    check("dvgo_photo_loss", lib.dvgo_photo_loss(_ptr(rgb), _ptr(target), rgb.shape[0], _ptr(grad), _ptr(loss),
+                                                 _stream(rgb.device)))
+    return loss, grad
+
+
+def adam_step(p, g, m, v, lr, t, betas=(0.9, 0.999), eps=1e-8, shadow=None) -> None:
+    lib = load()
+    check("dvgo_adam_step", lib.dvgo_adam_step(_ptr(p), _ptr(g), _ptr(m), _ptr(v), _ptr(shadow), p.numel(),
+                                               float(lr), float(betas[0]), float(betas[1]), float(eps), int(t),
+                                               _stream(p.device)))
+
+
+def proposal_fwd(s: Samples, box_min, box_max, prop_flat: Optional[torch.Tensor], cum_frac=0.99, min_mass=0.9,
+                 logits: Optional[torch.Tensor] = None):
+    """With prop_flat None, ``logits`` is an input and only the selection runs."""
+    lib = load()
+    dev = s.rays_o.device
+    B = s.B
+    if logits is None:
+        logits = torch.empty((B, NSEG), dtype=torch.float32, device=dev)
+    mass = torch.empty(B, dtype=torch.float32, device=dev)
+    mask = torch.empty(B, dtype=torch.int32, device=dev)
+    box = make_box(box_min, box_max)
+    prop = prop_struct(prop_flat) if prop_flat is not None else None
+    check("dvgo_proposal_fwd", lib.dvgo_proposal_fwd(
+        _ptr(s.rays_o), _ptr(s.rays_d), _ptr(s.t_near), _ptr(s.valid), B, ctypes.byref(box),
+        ctypes.byref(prop) if prop is not None else None, float(cum_frac), float(min_mass), _ptr(logits),
+        _ptr(mass), _ptr(mask), _stream(dev)))
+    return logits, mass, mask
+
+
+def proposal_bwd(s: Samples, box_min, box_max, prop_flat: torch.Tensor, seg_w: torch.Tensor,
+                 log_t_end: torch.Tensor, grad_prop: torch.Tensor):
+    lib = load()
+    dev = s.rays_o.device
+    box = make_box(box_min, box_max)
+    prop = prop_struct(prop_flat)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    nws = lib.dvgo_proposal_workspace_bytes(s.B)
+    ws = torch.empty(max(nws, 256), dtype=torch.uint8, device=dev)
+    check("dvgo_proposal_bwd", lib.dvgo_proposal_bwd(
+        _ptr(s.rays_o), _ptr(s.rays_d), _ptr(s.t_near), _ptr(s.valid), s.B, ctypes.byref(box), ctypes.byref(prop),
+        _ptr(seg_w), _ptr(log_t_end), _ptr(grad_prop), _ptr(loss), _ptr(ws), nws, _stream(dev)))
+    return loss
+
+
+def scene_render(rays_o, rays_d, spheres_f32: torch.Tensor, box_min, box_max, step, bg=(1.0, 1.0, 1.0),
+                 edge=0.01) -> torch.Tensor:
+    lib = load()
+    dev = rays_o.device
+    B = rays_o.shape[0]
+    rgb = torch.empty((B, 3), dtype=torch.float32, device=dev)
+    box = make_box(box_min, box_max)
+    check("dvgo_scene_render", lib.dvgo_scene_render(_ptr(rays_o), _ptr(rays_d), B, ctypes.byref(box),
+                                                     _ptr(spheres_f32), spheres_f32.shape[0], float(edge),
+                                                     float(step), _bg(bg), _ptr(rgb), _stream(dev)))
+    return rgb

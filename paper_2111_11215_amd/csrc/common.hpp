@@ -1,0 +1,122 @@
+// Internal helpers shared by the HIP translation units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+
+#include "dvgo.h"
+
+namespace dvgo {
+
+// Records the last HIP error text for dvgo_last_error().
+void record_hip_error(hipError_t e);
+
+// Checks the launch just enqueued; returns DVGO_OK or DVGO_E_HIP.
+inline int32_t launch_status() {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        record_hip_error(e);
+        return DVGO_E_HIP;
+    }
+    return DVGO_OK;
+}
+
+// Number of compute units of the current device (cached per device).
+int device_cu_count();
+
+// Kernel identifiers of the optional per-kernel event timing.
+enum KernelId {
+    K_RAY_SETUP = 0, K_MORTON_SORT, K_COUNT_KEPT, K_SCAN, K_FILL_KEPT, K_COARSE_MASK,
+    K_PACK, K_RAY_BASE, K_GATHER, K_MLP_FWD, K_COMPOSE_FWD, K_COMPOSE_BWD, K_MLP_BWD, K_SCATTER,
+    K_REDUCE, K_PHOTO_LOSS, K_ADAM, K_PROP_FWD, K_PROP_BWD, K_PROP_REDUCE, K_SCENE, K_NUM_KERNELS
+};
+// Bracket one launch with events when timing of `id` is enabled.
+void prof_begin(int id, hipStream_t s);
+void prof_end(int id, hipStream_t s);
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// hipLaunchKernelGGL bracketed by the optional timing events of kernel `id`.
+#define DVGO_LAUNCH(id, kernel, grid, block, shmem, stream, ...)                  \
+    do {                                                                       \
+        ::dvgo::prof_begin(::dvgo::id, (stream));                              \
+        hipLaunchKernelGGL(kernel, grid, block, shmem, (stream), __VA_ARGS__); \
+        ::dvgo::prof_end(::dvgo::id, (stream));                                \
+    } while (0)
+
+inline bool box_ok(const dvgo_box* b, int min_n) {
+    if (!b) return false;
+    for (int i = 0; i < 3; ++i) {
+        if (!(b->xyz_max[i] > b->xyz_min[i])) return false;
+        if (b->n[i] < min_n) return false;
+    }
+    return true;
+}
+
+// Grid description passed by value to kernels.  `scale` is (n-1)/(max-min)
+// rounded once to float32 on the host.
+struct GridArgs {
+    float mn[3];
+    float scale[3];
+    int n[3];
+};
+
+inline GridArgs make_grid(const dvgo_box& b) {
+    GridArgs g;
+    for (int i = 0; i < 3; ++i) {
+        g.mn[i] = b.xyz_min[i];
+        volatile float span = b.xyz_max[i] - b.xyz_min[i];
+        volatile float nm1 = static_cast<float>(b.n[i] - 1);
+        g.scale[i] = nm1 / span;
+        g.n[i] = b.n[i];
+    }
+    return g;
+}
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace dvgo
+
+// ---------------------------------------------------------------------------
+// Device-side float32 recipe of the discrete sampler (no contraction).
+// ---------------------------------------------------------------------------
+namespace dvgo_dev {
+
+// t_k = t_near + ((float)k + p) * step, three roundings in this order.
+__device__ __forceinline__ float recipe_tk(float tn, float p, int k, float step) {
+#pragma clang fp contract(off)
+    float kp = static_cast<float>(k) + p;
+    float m = kp * step;
+    return tn + m;
+}
+
+// x = o + t * d per component (multiply, then add).
+__device__ __forceinline__ void recipe_x(const float o[3], const float d[3], float t, float x[3]) {
+#pragma clang fp contract(off)
+    for (int i = 0; i < 3; ++i) {
+        float m = t * d[i];
+        x[i] = o[i] + m;
+    }
+}
+
+// Cell of the coarse grid holding x: clamp(floor((x-min)*scale), 0, n-2).
+__device__ __forceinline__ int recipe_cell(const dvgo::GridArgs& g, const float x[3]) {
+#pragma clang fp contract(off)
+    int idx[3];
+    for (int i = 0; i < 3; ++i) {
+        float u = (x[i] - g.mn[i]) * g.scale[i];
+        float fl = floorf(u);
+        fl = fminf(fmaxf(fl, 0.0f), static_cast<float>(g.n[i] - 2));
+        idx[i] = static_cast<int>(fl);
+    }
+    return (idx[0] * (g.n[1] - 1) + idx[1]) * (g.n[2] - 1) + idx[2];
+}
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
+}
+
+}  // namespace dvgo_dev

@@ -1,0 +1,820 @@
+// Colour network of the fine stage (paper Eq. fine_queries: two ReLU layers
+// of 128 and a sigmoid RGB head) on CDNA4 matrix cores.
+//
+// Layout.  A 32x32 accumulator tile of v_mfma_f32_32x32x{2f32,16bf16} holds,
+// in lane l and register r, row 8*(r/4) + 4*(l/32) + (r%4) and column l%32.
+// Activations are kept transposed ("feature rows, sample columns"): a wave
+// owns 32 samples (one per lane column) and each lane holds 16 features per
+// 32-feature tile.  The next layer consumes those registers directly as its
+// B operand; the K order this implies is folded into the packed weights
+// (phi() below), so a layer chain never leaves registers.  Weight gradients
+// need the sample index as the contraction dimension, so the activations of
+// the four waves of a workgroup are staged through LDS once per 128 samples
+// and each wave accumulates its own 32-row slice of dW in registers across
+// the whole persistent loop; per-workgroup partials are summed afterwards.
+#pragma once
+
+#include "common.hpp"
+
+namespace {
+
+constexpr int kH = 128;                 // hidden width
+constexpr int kC = 12;                  // feature channels
+constexpr int kPE = 27;                 // PE(d) with 4 frequencies
+constexpr int kIn = kC + kPE;           // first-layer input width
+// Flat gradient layout of the colour network: w1, b1, w2, b2, w3, b3.
+constexpr int kOffW1 = 0;
+constexpr int kOffB1 = kOffW1 + kH * kIn;
+constexpr int kOffW2 = kOffB1 + kH;
+constexpr int kOffB2 = kOffW2 + kH * kH;
+constexpr int kOffW3 = kOffB2 + kH;
+constexpr int kOffB3 = kOffW3 + 3 * kH;
+constexpr int kMlpParams = kOffB3 + 3;
+constexpr int kPStride = (kMlpParams + 63) / 64 * 64;
+constexpr int kW1PackF32 = 4 * 2 * 64 * 4;
+constexpr int kW2PackF32 = 4 * 16 * 64 * 4;
+constexpr int kW1PackBF16 = 4 * 64 * 8;
+constexpr int kW2PackBF16 = 4 * 8 * 64 * 8;
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short i16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f32x16 mma_f32(float a, float b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x16 mma_bf16(bf16x8 a, bf16x8 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// Hides a uniform pointer's value from the optimiser.  Used once per
+// persistent-loop iteration so weight loads are issued where they are
+// consumed instead of being hoisted out of the loop into hundreds of
+// registers.
+template <typename T>
+__device__ __forceinline__ T* opaque(T* p) {
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+// Row within a 32-row accumulator tile of register r in lane half h.
+__host__ __device__ __forceinline__ int acc_row(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
+// Feature consumed at float32 chain step st (0..63) by lane half h.
+__host__ __device__ __forceinline__ int phi32(int st, int h) { return 32 * (st >> 4) + acc_row(st & 15, h); }
+// Feature consumed at bfloat16 chain step st (0..7), element i (0..7), half h.
+__host__ __device__ __forceinline__ int phi16(int st, int i, int h) {
+    return 32 * (st >> 1) + acc_row(8 * (st & 1) + i, h);
+}
+
+__device__ __forceinline__ uint16_t f2bf(float f) {   // round to nearest even
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u) return static_cast<uint16_t>((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return static_cast<uint16_t>(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(static_cast<uint32_t>(b) << 16); }
+
+struct PackArgs {
+    const float* w1;
+    const float* w2;
+    float* w1p;
+    float* w2p;
+    float* w2tp;
+    uint16_t* w1pb;
+    uint16_t* w2pb;
+    uint16_t* w2tpb;
+    int bf16;
+};
+
+// Pack W1 (feature columns) and W2 / W2^T into matrix-core operand order.
+__global__ void pack_weights_kernel(PackArgs a) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid < kW2PackF32) {
+        // float32: index ((mt*16 + q)*64 + lane)*4 + u, step st = 4q + u
+        const int u = gid & 3, lane = (gid >> 2) & 63, q = (gid >> 8) & 15, mt = gid >> 12;
+        const int st = 4 * q + u, m = lane & 31, h = lane >> 5;
+        const int row = 32 * mt + m, kk = phi32(st, h);
+        a.w2p[gid] = a.w2[row * kH + kk];
+        a.w2tp[gid] = a.w2[kk * kH + row];
+        if (a.bf16) {
+            // bfloat16: index ((mt*8 + st)*64 + lane)*8 + i
+            const int i = gid & 7, lane2 = (gid >> 3) & 63, st2 = (gid >> 9) & 7, mt2 = gid >> 12;
+            const int m2 = lane2 & 31, h2 = lane2 >> 5;
+            const int row2 = 32 * mt2 + m2, k2 = phi16(st2, i, h2);
+            a.w2pb[gid] = f2bf(a.w2[row2 * kH + k2]);
+            a.w2tpb[gid] = f2bf(a.w2[k2 * kH + row2]);
+        }
+    }
+    if (gid < kW1PackF32) {
+        // float32 layer 1: index ((mt*2 + q)*64 + lane)*4 + u, st = 4q+u, k = 2st + h (< 12)
+        const int u = gid & 3, lane = (gid >> 2) & 63, q = (gid >> 8) & 1, mt = gid >> 9;
+        const int st = 4 * q + u, m = lane & 31, h = lane >> 5;
+        const int kk = 2 * st + h;
+        a.w1p[gid] = kk < kC ? a.w1[(32 * mt + m) * kIn + kk] : 0.0f;
+    }
+    if (a.bf16 && gid < kW1PackBF16) {
+        // bfloat16 layer 1: index (mt*64 + lane)*8 + i, k = 8h + i (< 12)
+        const int i = gid & 7, lane = (gid >> 3) & 63, mt = gid >> 9;
+        const int m = lane & 31, h = lane >> 5;
+        const int kk = 8 * h + i;
+        a.w1pb[gid] = kk < kC ? f2bf(a.w1[(32 * mt + m) * kIn + kk]) : static_cast<uint16_t>(0);
+    }
+}
+
+inline void launch_pack(const PackArgs& a, hipStream_t s) {
+    DVGO_LAUNCH(K_PACK, pack_weights_kernel, dim3(kW2PackF32 / 256), dim3(256), 0, s, a);
+}
+
+struct MlpArgs {
+    const int* sample_ray;
+    const int64_t* n_kept;
+    int64_t cap;
+    const float* w1;      // [128][39] raw, for dL/dfeat
+    const float* b2;
+    const float* w3;      // [3][128]
+    const float* b3;
+    const float* base;    // [B][128] per-ray first-layer part incl. b1
+    const float* pe;      // [B][32]
+    const float* w1p;
+    const float* w2p;
+    const float* w2tp;
+    const uint16_t* w1pb;
+    const uint16_t* w2pb;
+    const uint16_t* w2tpb;
+    float* feat;          // [cap][12]: features in; dL/dfeat out (backward)
+    float* col;           // [cap][4]: colour out (forward) / dL/dc in (backward)
+    float* partial;       // [blocks][kPStride] weight-gradient partials
+    int bf16;
+};
+
+__device__ __forceinline__ MlpArgs refresh(const MlpArgs& a) {
+    MlpArgs l = a;
+    l.w1 = opaque(a.w1);
+    l.b2 = opaque(a.b2);
+    l.w3 = opaque(a.w3);
+    l.b3 = opaque(a.b3);
+    l.w1p = opaque(a.w1p);
+    l.w2p = opaque(a.w2p);
+    l.w2tp = opaque(a.w2tp);
+    l.w1pb = opaque(a.w1pb);
+    l.w2pb = opaque(a.w2pb);
+    l.w2tpb = opaque(a.w2tpb);
+    return l;
+}
+
+// ---------------------------------------------------------------------------
+// forward chain for the 32 samples of one wave (float32 matrix cores)
+// ---------------------------------------------------------------------------
+struct ChainF32 {
+    f32x16 h1[4];   // relu(layer-1) per 32-feature tile
+    f32x16 z2[4];   // layer-2 pre-activation
+};
+
+__device__ __forceinline__ void load_base(const float* base, int r, int h, f32x16 acc[4]) {
+    const float* br = base + static_cast<int64_t>(r) * kH;
+    #pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+        #pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 v = *reinterpret_cast<const float4*>(br + 32 * mt + 8 * q + 4 * h);
+            acc[mt][4 * q + 0] = v.x;
+            acc[mt][4 * q + 1] = v.y;
+            acc[mt][4 * q + 2] = v.z;
+            acc[mt][4 * q + 3] = v.w;
+        }
+}
+
+// One chained 128x128 layer: out[mt] += W * in, one output tile at a time
+// (dependent matrix-core ops accumulate back to back).  Packed operands are
+// read from `w2op` (LDS or global memory), one float4 per 4 steps.
+template <typename P>
+__device__ __forceinline__ f32x16 chain_tile_f32(const P* w2op, int lane, int mt, const f32x16 in[4], f32x16 acc) {
+    #pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const float4 a4 = w2op[(mt * 16 + q) * 64 + lane];
+        #pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int st = 4 * q + u;
+            acc = mma_f32(a4[u], in[st >> 4][st & 15], acc);
+        }
+    }
+    return acc;
+}
+
+template <typename P>
+__device__ __forceinline__ void forward_chain_f32(const MlpArgs& a, const P* w2op, int r, const float f[12], int lane,
+                                                  ChainF32& c) {
+    const int h = lane >> 5;
+    load_base(a.base, r, h, c.h1);
+    const float4* w1p = reinterpret_cast<const float4*>(a.w1p);
+    #pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        float4 a4[4];
+        #pragma unroll
+        for (int mt = 0; mt < 4; ++mt) a4[mt] = w1p[(mt * 2 + q) * 64 + lane];
+        #pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int st = 4 * q + u;
+            const int kk = 2 * st + h;
+            const float b = kk < 12 ? f[kk] : 0.0f;
+            #pragma unroll
+            for (int mt = 0; mt < 4; ++mt) c.h1[mt] = mma_f32(a4[mt][u], b, c.h1[mt]);
+        }
+    }
+    #pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+        #pragma unroll
+        for (int rr = 0; rr < 16; ++rr) {
+            c.h1[mt][rr] = fmaxf(c.h1[mt][rr], 0.0f);
+            c.z2[mt][rr] = a.b2[32 * mt + acc_row(rr, h)];
+        }
+    #pragma unroll
+    for (int mt = 0; mt < 4; ++mt) c.z2[mt] = chain_tile_f32(w2op, lane, mt, c.h1, c.z2[mt]);
+}
+
+// Layer 3 and the sigmoid: both lane halves end with the sample's colour.
+__device__ __forceinline__ void head(const MlpArgs& a, const f32x16 z2[4], int h, float c[3]) {
+    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
+    #pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+        #pragma unroll
+        for (int rr = 0; rr < 16; ++rr) {
+            const int j = 32 * mt + acc_row(rr, h);
+            const float hv = fmaxf(z2[mt][rr], 0.0f);
+            s0 += a.w3[j] * hv;
+            s1 += a.w3[kH + j] * hv;
+            s2 += a.w3[2 * kH + j] * hv;
+        }
+    s0 += __shfl_xor(s0, 32, 64);
+    s1 += __shfl_xor(s1, 32, 64);
+    s2 += __shfl_xor(s2, 32, 64);
+    c[0] = 1.0f / (1.0f + expf(-(s0 + a.b3[0])));
+    c[1] = 1.0f / (1.0f + expf(-(s1 + a.b3[1])));
+    c[2] = 1.0f / (1.0f + expf(-(s2 + a.b3[2])));
+}
+
+__device__ __forceinline__ void load_feat(const float* feat, int64_t s, float f[12]) {
+    const float4* p = reinterpret_cast<const float4*>(feat + s * 12);
+    const float4 q0 = p[0], q1 = p[1], q2 = p[2];
+    f[0] = q0.x; f[1] = q0.y; f[2] = q0.z; f[3] = q0.w;
+    f[4] = q1.x; f[5] = q1.y; f[6] = q1.z; f[7] = q1.w;
+    f[8] = q2.x; f[9] = q2.y; f[10] = q2.z; f[11] = q2.w;
+}
+
+// Forward: colour of every listed sample.  LDS holds the packed W2.
+__global__ __launch_bounds__(256, 2) void mlp_fwd_f32_kernel(MlpArgs a0) {
+    const MlpArgs& a = a0;
+    __shared__ float4 sW2[kW2PackF32 / 4];
+    for (int i = threadIdx.x; i < kW2PackF32 / 4; i += blockDim.x)
+        sW2[i] = reinterpret_cast<const float4*>(a.w2p)[i];
+    __syncthreads();
+    const int64_t n = *a.n_kept < a.cap ? *a.n_kept : a.cap;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 31, h = lane >> 5;
+    for (int64_t tile = static_cast<int64_t>(blockIdx.x) * 4 + wave; tile * 32 < n;
+         tile += static_cast<int64_t>(gridDim.x) * 4) {
+        const MlpArgs a = refresh(a0);
+        const int64_t s = tile * 32 + m;
+        const bool ok = s < n;
+        const int64_t sc = ok ? s : n - 1;
+        const int r = a.sample_ray[sc];
+        float f[12];
+        load_feat(a.feat, sc, f);
+        ChainF32 c;
+        forward_chain_f32(a, sW2, r, f, lane, c);
+        float col[3];
+        head(a, c.z2, h, col);
+        if (ok && h == 0) reinterpret_cast<float4*>(a.col)[s] = make_float4(col[0], col[1], col[2], 0.0f);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// backward (float32): recompute, adjoint chain, weight gradients
+// ---------------------------------------------------------------------------
+constexpr int kSRow = 132;      // LDS row pitch (floats) of a staged sample row
+
+__global__ __launch_bounds__(256, 1) void mlp_bwd_f32_kernel(MlpArgs a0) {
+    __shared__ float sA[128 * kSRow];   // h1 rows, then dL/dz1 rows
+    __shared__ float sB[128 * kSRow];   // h2 / dL/dz2 rows, then x' = [f, PE, 1, 0..] rows
+    const int64_t n = *a0.n_kept < a0.cap ? *a0.n_kept : a0.cap;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 31, h = lane >> 5;
+    f32x16 dW2[4], dW1[2];
+    #pragma unroll
+    for (int t = 0; t < 4; ++t)
+        #pragma unroll
+        for (int rr = 0; rr < 16; ++rr) dW2[t][rr] = 0.0f;
+    #pragma unroll
+    for (int t = 0; t < 2; ++t)
+        #pragma unroll
+        for (int rr = 0; rr < 16; ++rr) dW1[t][rr] = 0.0f;
+    float dW3a[3] = {0, 0, 0}, dW3b[3] = {0, 0, 0}, db2a = 0.0f, db2b = 0.0f, db3[3] = {0, 0, 0};
+    float* myA = sA + wave * 32 * kSRow;
+    float* myB = sB + wave * 32 * kSRow;
+    for (int64_t blk = blockIdx.x; blk * 128 < n; blk += gridDim.x) {
+        const MlpArgs a = refresh(a0);
+        const float4* w2p = reinterpret_cast<const float4*>(a.w2p);
+        const float4* w2tp = reinterpret_cast<const float4*>(a.w2tp);
+        const int64_t s = blk * 128 + wave * 32 + m;
+        const bool ok = s < n;
+        const int64_t sc = ok ? s : n - 1;
+        const int r = a.sample_ray[sc];
+        float f[12];
+        load_feat(a.feat, sc, f);
+        ChainF32 c;
+        forward_chain_f32(a, w2p, r, f, lane, c);
+        float col[3];
+        head(a, c.z2, h, col);
+        float dz3[3] = {0, 0, 0};
+        if (ok) {
+            const float4 dc = reinterpret_cast<const float4*>(a.col)[s];
+            dz3[0] = dc.x * col[0] * (1.0f - col[0]);
+            dz3[1] = dc.y * col[1] * (1.0f - col[1]);
+            dz3[2] = dc.z * col[2] * (1.0f - col[2]);
+        }
+        // ---- dW3, db3 from h2 rows and dz3 staged in LDS
+        #pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+            #pragma unroll
+            for (int q = 0; q < 4; ++q)
+                *reinterpret_cast<float4*>(myA + m * kSRow + 32 * mt + 8 * q + 4 * h) =
+                    make_float4(fmaxf(c.z2[mt][4 * q], 0.0f), fmaxf(c.z2[mt][4 * q + 1], 0.0f),
+                                fmaxf(c.z2[mt][4 * q + 2], 0.0f), fmaxf(c.z2[mt][4 * q + 3], 0.0f));
+        if (h == 0) {
+            myB[m * kSRow + 0] = dz3[0];
+            myB[m * kSRow + 1] = dz3[1];
+            myB[m * kSRow + 2] = dz3[2];
+            db3[0] += dz3[0];
+            db3[1] += dz3[1];
+            db3[2] += dz3[2];
+        }
+        __syncthreads();
+        #pragma unroll 4
+        for (int ss = 0; ss < 32; ++ss) {
+            const float ha = myA[ss * kSRow + lane], hb = myA[ss * kSRow + lane + 64];
+            const float d0 = myB[ss * kSRow], d1 = myB[ss * kSRow + 1], d2 = myB[ss * kSRow + 2];
+            dW3a[0] += d0 * ha; dW3a[1] += d1 * ha; dW3a[2] += d2 * ha;
+            dW3b[0] += d0 * hb; dW3b[1] += d1 * hb; dW3b[2] += d2 * hb;
+        }
+        __syncthreads();
+        // ---- dz2 = (W3^T dz3) * relu'(z2), in place of z2
+        #pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+            #pragma unroll
+            for (int rr = 0; rr < 16; ++rr) {
+                const int j = 32 * mt + acc_row(rr, h);
+                const float dh = a.w3[j] * dz3[0] + a.w3[kH + j] * dz3[1] + a.w3[2 * kH + j] * dz3[2];
+                c.z2[mt][rr] = c.z2[mt][rr] > 0.0f ? dh : 0.0f;
+            }
+        // ---- stage h1 rows (sA) and dz2 rows (sB) of all four waves
+        #pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+            #pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                *reinterpret_cast<float4*>(myA + m * kSRow + 32 * mt + 8 * q + 4 * h) =
+                    make_float4(c.h1[mt][4 * q], c.h1[mt][4 * q + 1], c.h1[mt][4 * q + 2], c.h1[mt][4 * q + 3]);
+                *reinterpret_cast<float4*>(myB + m * kSRow + 32 * mt + 8 * q + 4 * h) =
+                    make_float4(c.z2[mt][4 * q], c.z2[mt][4 * q + 1], c.z2[mt][4 * q + 2], c.z2[mt][4 * q + 3]);
+            }
+        __syncthreads();
+        #pragma unroll 4
+        for (int ss = 0; ss < 32; ++ss) {
+            db2a += myB[ss * kSRow + lane];
+            db2b += myB[ss * kSRow + lane + 64];
+        }
+        // dW2[j in tile `wave`][i] += sum over the 128 staged samples
+        #pragma unroll 1
+        for (int src = 0; src < 4; ++src)
+            #pragma unroll 4
+            for (int st = 0; st < 16; ++st) {
+                const int row = src * 32 + 2 * st + h;
+                const float av = sB[row * kSRow + 32 * wave + m];
+                #pragma unroll
+                for (int nt = 0; nt < 4; ++nt) dW2[nt] = mma_f32(av, sA[row * kSRow + 32 * nt + m], dW2[nt]);
+            }
+        // ---- dh1 = W2^T dz2 (chained), dz1 = dh1 * relu'(h1), in place of h1
+        #pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            f32x16 dh1;
+            #pragma unroll
+            for (int rr = 0; rr < 16; ++rr) dh1[rr] = 0.0f;
+            dh1 = chain_tile_f32(w2tp, lane, mt, c.z2, dh1);
+            #pragma unroll
+            for (int rr = 0; rr < 16; ++rr) c.h1[mt][rr] = c.h1[mt][rr] > 0.0f ? dh1[rr] : 0.0f;
+        }
+        // ---- dL/dfeat = W1[:, :12]^T dz1
+        float df[12];
+        #pragma unroll
+        for (int cc = 0; cc < 12; ++cc) df[cc] = 0.0f;
+        #pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+            #pragma unroll
+            for (int rr = 0; rr < 16; ++rr) {
+                const int i = 32 * mt + acc_row(rr, h);
+                const float d = c.h1[mt][rr];
+                #pragma unroll
+                for (int cc = 0; cc < 12; ++cc) df[cc] += a.w1[i * kIn + cc] * d;
+            }
+        #pragma unroll
+        for (int cc = 0; cc < 12; ++cc) df[cc] += __shfl_xor(df[cc], 32, 64);
+        __syncthreads();
+        // ---- stage dz1 rows (sA) and x' rows (sB)
+        #pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+            #pragma unroll
+            for (int q = 0; q < 4; ++q)
+                *reinterpret_cast<float4*>(myA + m * kSRow + 32 * mt + 8 * q + 4 * h) =
+                    make_float4(c.h1[mt][4 * q], c.h1[mt][4 * q + 1], c.h1[mt][4 * q + 2], c.h1[mt][4 * q + 3]);
+        {
+            const float* per = a.pe + static_cast<int64_t>(r) * 32;
+            float* row = myB + m * kSRow + 32 * h;
+            #pragma unroll
+            for (int cc = 0; cc < 32; ++cc) {
+                const int col = 32 * h + cc;
+                float v;
+                if (col < kC) v = f[col];
+                else if (col < kIn) v = per[col - kC];
+                else if (col == kIn) v = 1.0f;
+                else v = 0.0f;
+                row[cc] = v;
+            }
+        }
+        if (ok && h == 0) {
+            float4* out = reinterpret_cast<float4*>(a.feat + s * 12);
+            out[0] = make_float4(df[0], df[1], df[2], df[3]);
+            out[1] = make_float4(df[4], df[5], df[6], df[7]);
+            out[2] = make_float4(df[8], df[9], df[10], df[11]);
+        }
+        __syncthreads();
+        // dW1[i in tile `wave`][col] (col 39 = bias) over the 128 staged samples
+        #pragma unroll 1
+        for (int src = 0; src < 4; ++src)
+            #pragma unroll 4
+            for (int st = 0; st < 16; ++st) {
+                const int row = src * 32 + 2 * st + h;
+                const float av = sA[row * kSRow + 32 * wave + m];
+                dW1[0] = mma_f32(av, sB[row * kSRow + m], dW1[0]);
+                dW1[1] = mma_f32(av, sB[row * kSRow + 32 + m], dW1[1]);
+            }
+        __syncthreads();
+    }
+    // ---- epilogue: this workgroup's partial of the flat gradient
+    float* out = a0.partial + static_cast<int64_t>(blockIdx.x) * kPStride;
+    #pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+        #pragma unroll
+        for (int rr = 0; rr < 16; ++rr) {
+            const int j = 32 * wave + acc_row(rr, h);
+            out[kOffW2 + j * kH + 32 * nt + m] = dW2[nt][rr];
+        }
+    #pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+        #pragma unroll
+        for (int rr = 0; rr < 16; ++rr) {
+            const int i = 32 * wave + acc_row(rr, h);
+            const int col = 32 * nt + m;
+            if (col < kIn) out[kOffW1 + i * kIn + col] = dW1[nt][rr];
+            else if (col == kIn) out[kOffB1 + i] = dW1[nt][rr];
+        }
+    #pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        db3[t] += __shfl_xor(db3[t], 32, 64);
+        #pragma unroll
+        for (int off = 16; off > 0; off >>= 1) db3[t] += __shfl_xor(db3[t], off, 64);
+    }
+    float* red = sA;   // [4 waves][512]
+    #pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        red[wave * 512 + t * kH + lane] = dW3a[t];
+        red[wave * 512 + t * kH + lane + 64] = dW3b[t];
+    }
+    red[wave * 512 + 384 + lane] = db2a;
+    red[wave * 512 + 384 + lane + 64] = db2b;
+    if (lane == 0)
+        #pragma unroll
+        for (int t = 0; t < 3; ++t) sB[wave * 4 + t] = db3[t];
+    __syncthreads();
+    for (int i = threadIdx.x; i < 512; i += blockDim.x) {
+        const float v = red[i] + red[512 + i] + red[1024 + i] + red[1536 + i];
+        if (i < 384) out[kOffW3 + i] = v;
+        else out[kOffB2 + (i - 384)] = v;
+    }
+    if (threadIdx.x < 3) out[kOffB3 + threadIdx.x] = sB[threadIdx.x] + sB[4 + threadIdx.x] + sB[8 + threadIdx.x] +
+                                                   sB[12 + threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------
+// bfloat16 matrix cores (v_mfma_f32_32x32x16_bf16): same dataflow, K = 16
+// per step, 8 consecutive K values per lane half; float32 accumulation.
+// Weight-gradient operands are staged as [feature][sample] bfloat16 so that
+// a lane's 8 consecutive samples are one 16-byte LDS read.
+// ---------------------------------------------------------------------------
+constexpr int kBP = 136;   // LDS pitch (bf16 elements) of a staged feature row
+
+__device__ __forceinline__ bf16x8 pack8(const f32x16& v, int g) {
+    bf16x8 r;
+    #pragma unroll
+    for (int e = 0; e < 8; ++e) r[e] = static_cast<__bf16>(v[8 * g + e]);
+    return r;
+}
+
+__device__ __forceinline__ float bf16r(float x) { return static_cast<float>(static_cast<__bf16>(x)); }
+
+__device__ __forceinline__ f32x16 chain_tile_bf16(const bf16x8* w, int lane, int mt, const bf16x8 in[8],
+                                                  f32x16 acc) {
+    #pragma unroll
+    for (int st = 0; st < 8; ++st) acc = mma_bf16(w[(mt * 8 + st) * 64 + lane], in[st], acc);
+    return acc;
+}
+
+__device__ __forceinline__ void forward_chain_bf16(const MlpArgs& a, const bf16x8* sW1, const bf16x8* sW2, int r,
+                                                   const float f[12], int lane, ChainF32& c) {
+    const int h = lane >> 5;
+    load_base(a.base, r, h, c.h1);
+    bf16x8 fb;
+    #pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int k = 8 * h + e;
+        fb[e] = static_cast<__bf16>(k < kC ? f[k < kC ? k : 0] : 0.0f);
+    }
+    #pragma unroll
+    for (int mt = 0; mt < 4; ++mt) c.h1[mt] = mma_bf16(sW1[mt * 64 + lane], fb, c.h1[mt]);
+    #pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+        #pragma unroll
+        for (int rr = 0; rr < 16; ++rr) {
+            c.h1[mt][rr] = fmaxf(c.h1[mt][rr], 0.0f);
+            c.z2[mt][rr] = a.b2[32 * mt + acc_row(rr, h)];
+        }
+    bf16x8 hb[8];
+    #pragma unroll
+    for (int st = 0; st < 8; ++st) hb[st] = pack8(c.h1[st >> 1], st & 1);
+    #pragma unroll
+    for (int mt = 0; mt < 4; ++mt) c.z2[mt] = chain_tile_bf16(sW2, lane, mt, hb, c.z2[mt]);
+}
+
+// Layer 3 with bfloat16-rounded inputs and weights (float32 products).
+__device__ __forceinline__ void head_bf16(const MlpArgs& a, const f32x16 z2[4], int h, float c[3]) {
+    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
+    #pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+        #pragma unroll
+        for (int rr = 0; rr < 16; ++rr) {
+            const int j = 32 * mt + acc_row(rr, h);
+            const float hv = bf16r(fmaxf(z2[mt][rr], 0.0f));
+            s0 += bf16r(a.w3[j]) * hv;
+            s1 += bf16r(a.w3[kH + j]) * hv;
+            s2 += bf16r(a.w3[2 * kH + j]) * hv;
+        }
+    s0 += __shfl_xor(s0, 32, 64);
+    s1 += __shfl_xor(s1, 32, 64);
+    s2 += __shfl_xor(s2, 32, 64);
+    c[0] = 1.0f / (1.0f + expf(-(s0 + a.b3[0])));
+    c[1] = 1.0f / (1.0f + expf(-(s1 + a.b3[1])));
+    c[2] = 1.0f / (1.0f + expf(-(s2 + a.b3[2])));
+}
+
+__device__ __forceinline__ void load_packed_bf16(const MlpArgs& a, bf16x8* sW1, bf16x8* sW2, bf16x8* sW2T) {
+    const bf16x8* g1 = reinterpret_cast<const bf16x8*>(a.w1pb);
+    const bf16x8* g2 = reinterpret_cast<const bf16x8*>(a.w2pb);
+    const bf16x8* g2t = reinterpret_cast<const bf16x8*>(a.w2tpb);
+    for (int i = threadIdx.x; i < kW2PackBF16 / 8; i += blockDim.x) {
+        sW2[i] = g2[i];
+        if (sW2T) sW2T[i] = g2t[i];
+    }
+    for (int i = threadIdx.x; i < kW1PackBF16 / 8; i += blockDim.x) sW1[i] = g1[i];
+}
+
+__global__ __launch_bounds__(256, 2) void mlp_fwd_bf16_kernel(MlpArgs a0) {
+    __shared__ bf16x8 sW2[kW2PackBF16 / 8];
+    __shared__ bf16x8 sW1[kW1PackBF16 / 8];
+    load_packed_bf16(a0, sW1, sW2, nullptr);
+    __syncthreads();
+    const int64_t n = *a0.n_kept < a0.cap ? *a0.n_kept : a0.cap;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 31, h = lane >> 5;
+    for (int64_t tile = static_cast<int64_t>(blockIdx.x) * 4 + wave; tile * 32 < n;
+         tile += static_cast<int64_t>(gridDim.x) * 4) {
+        const MlpArgs a = refresh(a0);
+        const int64_t s = tile * 32 + m;
+        const bool ok = s < n;
+        const int64_t sc = ok ? s : n - 1;
+        const int r = a.sample_ray[sc];
+        float f[12];
+        load_feat(a.feat, sc, f);
+        ChainF32 c;
+        forward_chain_bf16(a, sW1, sW2, r, f, lane, c);
+        float col[3];
+        head_bf16(a, c.z2, h, col);
+        if (ok && h == 0) reinterpret_cast<float4*>(a.col)[s] = make_float4(col[0], col[1], col[2], 0.0f);
+    }
+}
+
+__global__ __launch_bounds__(256, 1) void mlp_bwd_bf16_kernel(MlpArgs a0) {
+    __shared__ bf16x8 sW2[kW2PackBF16 / 8];
+    __shared__ bf16x8 sW2T[kW2PackBF16 / 8];
+    __shared__ bf16x8 sW1[kW1PackBF16 / 8];
+    __shared__ __attribute__((aligned(16))) __bf16 sA[128 * kBP];   // h1 then dL/dz1, [feature][sample]
+    __shared__ __attribute__((aligned(16))) __bf16 sB[128 * kBP];   // h2, then dL/dz2, then x'
+    __shared__ __attribute__((aligned(16))) __bf16 sC[32 * kBP];    // dL/dz3 in rows 0..2, zero rows 3..31
+    __shared__ float sRed[4 * 4];
+    load_packed_bf16(a0, sW1, sW2, sW2T);
+    for (int i = threadIdx.x; i < 32 * kBP; i += blockDim.x) sC[i] = static_cast<__bf16>(0.0f);
+    __syncthreads();
+    const int64_t n = *a0.n_kept < a0.cap ? *a0.n_kept : a0.cap;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 31, h = lane >> 5;
+    const int col_s = wave * 32 + m;     // this lane's sample column in the staged block
+    f32x16 dW2[4], dB2, dW1[2], dW3;
+    #pragma unroll
+    for (int t = 0; t < 4; ++t)
+        #pragma unroll
+        for (int rr = 0; rr < 16; ++rr) dW2[t][rr] = 0.0f;
+    #pragma unroll
+    for (int rr = 0; rr < 16; ++rr) {
+        dB2[rr] = 0.0f;
+        dW1[0][rr] = 0.0f;
+        dW1[1][rr] = 0.0f;
+        dW3[rr] = 0.0f;
+    }
+    float db3[3] = {0, 0, 0};
+    bf16x8 ones;
+    #pragma unroll
+    for (int e = 0; e < 8; ++e) ones[e] = static_cast<__bf16>(m == 0 ? 1.0f : 0.0f);
+    for (int64_t blk = blockIdx.x; blk * 128 < n; blk += gridDim.x) {
+        const MlpArgs a = refresh(a0);
+        const int64_t s = blk * 128 + col_s;
+        const bool ok = s < n;
+        const int64_t sc = ok ? s : n - 1;
+        const int r = a.sample_ray[sc];
+        float f[12];
+        load_feat(a.feat, sc, f);
+        ChainF32 c;
+        forward_chain_bf16(a, sW1, sW2, r, f, lane, c);
+        float col[3];
+        head_bf16(a, c.z2, h, col);
+        float dz3[3] = {0, 0, 0};
+        if (ok) {
+            const float4 dc = reinterpret_cast<const float4*>(a.col)[s];
+            dz3[0] = dc.x * col[0] * (1.0f - col[0]);
+            dz3[1] = dc.y * col[1] * (1.0f - col[1]);
+            dz3[2] = dc.z * col[2] * (1.0f - col[2]);
+        }
+        // stage h1 -> sA, h2 -> sB, dz3 -> sC
+        #pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+            #pragma unroll
+            for (int rr = 0; rr < 16; ++rr) {
+                const int j = 32 * mt + acc_row(rr, h);
+                sA[j * kBP + col_s] = static_cast<__bf16>(c.h1[mt][rr]);
+                sB[j * kBP + col_s] = static_cast<__bf16>(fmaxf(c.z2[mt][rr], 0.0f));
+            }
+        if (h == 0) {
+            #pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                sC[t * kBP + col_s] = static_cast<__bf16>(dz3[t]);
+                db3[t] += dz3[t];
+            }
+        }
+        // dz2 = (W3^T dz3) * relu'(z2), in place of z2 (bf16-rounded W3)
+        #pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+            #pragma unroll
+            for (int rr = 0; rr < 16; ++rr) {
+                const int j = 32 * mt + acc_row(rr, h);
+                const float dh = bf16r(a.w3[j]) * dz3[0] + bf16r(a.w3[kH + j]) * dz3[1] +
+                                 bf16r(a.w3[2 * kH + j]) * dz3[2];
+                c.z2[mt][rr] = c.z2[mt][rr] > 0.0f ? dh : 0.0f;
+            }
+        __syncthreads();
+        // dW3^T[j in tile `wave`][c] over the 128 staged samples
+        #pragma unroll
+        for (int st = 0; st < 8; ++st) {
+            const bf16x8 av = *reinterpret_cast<const bf16x8*>(sB + (32 * wave + m) * kBP + 16 * st + 8 * h);
+            const bf16x8 bv = *reinterpret_cast<const bf16x8*>(sC + m * kBP + 16 * st + 8 * h);
+            dW3 = mma_bf16(av, bv, dW3);
+        }
+        __syncthreads();
+        #pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+            #pragma unroll
+            for (int rr = 0; rr < 16; ++rr)
+                sB[(32 * mt + acc_row(rr, h)) * kBP + col_s] = static_cast<__bf16>(c.z2[mt][rr]);
+        __syncthreads();
+        // dW2[j in tile `wave`][i], and db2 through a constant ones column
+        #pragma unroll 2
+        for (int st = 0; st < 8; ++st) {
+            const bf16x8 av = *reinterpret_cast<const bf16x8*>(sB + (32 * wave + m) * kBP + 16 * st + 8 * h);
+            #pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const bf16x8 bv = *reinterpret_cast<const bf16x8*>(sA + (32 * nt + m) * kBP + 16 * st + 8 * h);
+                dW2[nt] = mma_bf16(av, bv, dW2[nt]);
+            }
+            dB2 = mma_bf16(av, ones, dB2);
+        }
+        // dh1 = W2^T dz2 (chained), dz1 = dh1 * relu'(h1) in place of h1
+        {
+            bf16x8 zb[8];
+            #pragma unroll
+            for (int st = 0; st < 8; ++st) zb[st] = pack8(c.z2[st >> 1], st & 1);
+            #pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                f32x16 dh1;
+                #pragma unroll
+                for (int rr = 0; rr < 16; ++rr) dh1[rr] = 0.0f;
+                dh1 = chain_tile_bf16(sW2T, lane, mt, zb, dh1);
+                #pragma unroll
+                for (int rr = 0; rr < 16; ++rr) c.h1[mt][rr] = c.h1[mt][rr] > 0.0f ? dh1[rr] : 0.0f;
+            }
+        }
+        // dL/dfeat = bf16(W1[:, :12])^T dz1
+        float df[12];
+        #pragma unroll
+        for (int cc = 0; cc < 12; ++cc) df[cc] = 0.0f;
+        #pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+            #pragma unroll
+            for (int rr = 0; rr < 16; ++rr) {
+                const int i = 32 * mt + acc_row(rr, h);
+                const float d = c.h1[mt][rr];
+                #pragma unroll
+                for (int cc = 0; cc < 12; ++cc) df[cc] += bf16r(a.w1[i * kIn + cc]) * d;
+            }
+        #pragma unroll
+        for (int cc = 0; cc < 12; ++cc) df[cc] += __shfl_xor(df[cc], 32, 64);
+        __syncthreads();
+        // stage dz1 -> sA, x' = [f, PE, 1, 0...] -> sB (64 columns)
+        #pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+            #pragma unroll
+            for (int rr = 0; rr < 16; ++rr)
+                sA[(32 * mt + acc_row(rr, h)) * kBP + col_s] = static_cast<__bf16>(c.h1[mt][rr]);
+        {
+            const float* per = a.pe + static_cast<int64_t>(r) * 32;
+            #pragma unroll 4
+            for (int cc = 0; cc < 32; ++cc) {
+                const int cidx = 32 * h + cc;
+                float v;
+                if (cidx < kC) v = f[cidx < kC ? cidx : 0];
+                else if (cidx < kIn) v = per[cidx - kC];
+                else if (cidx == kIn) v = 1.0f;
+                else v = 0.0f;
+                sB[cidx * kBP + col_s] = static_cast<__bf16>(v);
+            }
+        }
+        if (ok && h == 0) {
+            float4* out = reinterpret_cast<float4*>(a.feat + s * 12);
+            out[0] = make_float4(df[0], df[1], df[2], df[3]);
+            out[1] = make_float4(df[4], df[5], df[6], df[7]);
+            out[2] = make_float4(df[8], df[9], df[10], df[11]);
+        }
+        __syncthreads();
+        #pragma unroll
+        for (int st = 0; st < 8; ++st) {
+            const bf16x8 av = *reinterpret_cast<const bf16x8*>(sA + (32 * wave + m) * kBP + 16 * st + 8 * h);
+            const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(sB + m * kBP + 16 * st + 8 * h);
+            const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(sB + (32 + m) * kBP + 16 * st + 8 * h);
+            dW1[0] = mma_bf16(av, b0, dW1[0]);
+            dW1[1] = mma_bf16(av, b1, dW1[1]);
+        }
+        __syncthreads();
+    }
+    // ---- epilogue: this workgroup's partial of the flat gradient
+    float* out = a0.partial + static_cast<int64_t>(blockIdx.x) * kPStride;
+    #pragma unroll
+    for (int rr = 0; rr < 16; ++rr) {
+        const int row = 32 * wave + acc_row(rr, h);
+        #pragma unroll
+        for (int nt = 0; nt < 4; ++nt) out[kOffW2 + row * kH + 32 * nt + m] = dW2[nt][rr];
+        if (m == 0) out[kOffB2 + row] = dB2[rr];
+        #pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            const int cidx = 32 * nt + m;
+            if (cidx < kIn) out[kOffW1 + row * kIn + cidx] = dW1[nt][rr];
+            else if (cidx == kIn) out[kOffB1 + row] = dW1[nt][rr];
+        }
+        if (m < 3) out[kOffW3 + m * kH + row] = dW3[rr];
+    }
+    #pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        db3[t] += __shfl_xor(db3[t], 32, 64);
+        for (int off = 16; off > 0; off >>= 1) db3[t] += __shfl_xor(db3[t], off, 64);
+    }
+    if (lane == 0)
+        for (int t = 0; t < 3; ++t) sRed[wave * 4 + t] = db3[t];
+    __syncthreads();
+    if (threadIdx.x < 3)
+        out[kOffB3 + threadIdx.x] = sRed[threadIdx.x] + sRed[4 + threadIdx.x] + sRed[8 + threadIdx.x] +
+                                    sRed[12 + threadIdx.x];
+}
+
+inline void launch_mlp_fwd(const MlpArgs& a, int cus, hipStream_t s) {
+    if (a.bf16) DVGO_LAUNCH(K_MLP_FWD, mlp_fwd_bf16_kernel, dim3(cus * 2), dim3(256), 0, s, a);
+    else DVGO_LAUNCH(K_MLP_FWD, mlp_fwd_f32_kernel, dim3(cus * 2), dim3(256), 0, s, a);
+}
+inline void launch_mlp_bwd(const MlpArgs& a, int blocks, hipStream_t s) {
+    if (a.bf16) DVGO_LAUNCH(K_MLP_BWD, mlp_bwd_bf16_kernel, dim3(blocks), dim3(256), 0, s, a);
+    else DVGO_LAUNCH(K_MLP_BWD, mlp_bwd_f32_kernel, dim3(blocks), dim3(256), 0, s, a);
+}
+
+}  // namespace

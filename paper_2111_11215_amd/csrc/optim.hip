@@ -1,0 +1,151 @@
+// Photometric loss (paper Eq. photo_loss) and the fused Adam step (the
+// paper's optimiser, Sec. 5.2; update rule of Kingma and Ba with bias
+// correction).  Both are streaming kernels bound by HBM bandwidth.
+#include "common.hpp"
+
+namespace {
+
+__device__ __forceinline__ uint16_t to_bf16(float f) {   // round to nearest even
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u) return static_cast<uint16_t>((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return static_cast<uint16_t>(u >> 16);
+}
+
+struct AdamArgs {
+    float* p;
+    float* g;
+    float* m;
+    float* v;
+    uint16_t* shadow;
+    int64_t n;
+    float lr, b1, b2, eps, inv_bc1, inv_bc2;
+};
+
+__device__ __forceinline__ void adam_one(const AdamArgs& a, float& p, float g, float& m, float& v) {
+    m = a.b1 * m + (1.0f - a.b1) * g;
+    v = a.b2 * v + (1.0f - a.b2) * g * g;
+    const float mh = m * a.inv_bc1;
+    const float vh = v * a.inv_bc2;
+    p -= a.lr * mh / (sqrtf(vh) + a.eps);
+}
+
+// 16-byte vectors: every pointer 16-byte aligned, n4 = n/4 vectors.
+__global__ __launch_bounds__(256) void adam_vec_kernel(AdamArgs a) {
+    const int64_t n4 = a.n >> 2;
+    float4* P = reinterpret_cast<float4*>(a.p);
+    float4* G = reinterpret_cast<float4*>(a.g);
+    float4* M = reinterpret_cast<float4*>(a.m);
+    float4* V = reinterpret_cast<float4*>(a.v);
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n4;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        float4 p = P[i], g = G[i], m = M[i], v = V[i];
+        adam_one(a, p.x, g.x, m.x, v.x);
+        adam_one(a, p.y, g.y, m.y, v.y);
+        adam_one(a, p.z, g.z, m.z, v.z);
+        adam_one(a, p.w, g.w, m.w, v.w);
+        P[i] = p;
+        M[i] = m;
+        V[i] = v;
+        G[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (a.shadow) {
+            uint2 sh;
+            sh.x = static_cast<uint32_t>(to_bf16(p.x)) | (static_cast<uint32_t>(to_bf16(p.y)) << 16);
+            sh.y = static_cast<uint32_t>(to_bf16(p.z)) | (static_cast<uint32_t>(to_bf16(p.w)) << 16);
+            reinterpret_cast<uint2*>(a.shadow)[i] = sh;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void adam_scalar_kernel(AdamArgs a, int64_t start) {
+    for (int64_t i = start + static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < a.n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        float p = a.p[i], m = a.m[i], v = a.v[i];
+        adam_one(a, p, a.g[i], m, v);
+        a.p[i] = p;
+        a.m[i] = m;
+        a.v[i] = v;
+        a.g[i] = 0.0f;
+        if (a.shadow) a.shadow[i] = to_bf16(p);
+    }
+}
+
+// Single workgroup: grad = 2 (rgb - target)/B, loss = sum ||.||^2 / B.
+__global__ __launch_bounds__(1024) void photo_loss_kernel(const float* __restrict__ rgb,
+                                                         const float* __restrict__ target, int B,
+                                                         float* __restrict__ grad, float* __restrict__ loss) {
+    __shared__ float red[16];
+    const float invB = 1.0f / static_cast<float>(B);
+    float acc = 0.0f;
+    for (int64_t i = threadIdx.x; i < 3LL * B; i += blockDim.x) {
+        const float d = rgb[i] - target[i];
+        acc += d * d;
+        grad[i] = 2.0f * d * invB;
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0 && loss) {
+        float s = 0.0f;
+        for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) s += red[w];
+        *loss = s * invB;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t dvgo_photo_loss(const float* rgb, const float* target, int32_t B, float* grad_rgb, float* loss,
+                        void* stream) {
+    if (B < 0) return DVGO_E_ARG;
+    if (B > 0 && (!rgb || !target || !grad_rgb)) return DVGO_E_ARG;
+    if (B == 0) return DVGO_OK;
+    DVGO_LAUNCH(K_PHOTO_LOSS, photo_loss_kernel, dim3(1), dim3(1024), 0, dvgo::as_stream(stream), rgb, target, B,
+                       grad_rgb, loss);
+    return dvgo::launch_status();
+}
+
+int32_t dvgo_adam_step(float* p, float* g, float* m, float* v, uint16_t* shadow_bf16, int64_t n, float lr,
+                       float beta1, float beta2, float eps, int32_t t, void* stream) {
+    if (n < 0 || t < 1) return DVGO_E_ARG;
+    if (n > 0 && (!p || !g || !m || !v)) return DVGO_E_ARG;
+    if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f) || !(eps >= 0.0f)) return DVGO_E_ARG;
+    if (n == 0) return DVGO_OK;
+    AdamArgs a;
+    a.p = p;
+    a.g = g;
+    a.m = m;
+    a.v = v;
+    a.shadow = shadow_bf16;
+    a.n = n;
+    a.lr = lr;
+    a.b1 = beta1;
+    a.b2 = beta2;
+    a.eps = eps;
+    a.inv_bc1 = static_cast<float>(1.0 / (1.0 - std::pow(static_cast<double>(beta1), t)));
+    a.inv_bc2 = static_cast<float>(1.0 / (1.0 - std::pow(static_cast<double>(beta2), t)));
+    hipStream_t s = dvgo::as_stream(stream);
+    auto al16 = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
+    const bool vec = al16(p) && al16(g) && al16(m) && al16(v) &&
+                     (!shadow_bf16 || (reinterpret_cast<uintptr_t>(shadow_bf16) & 7u) == 0);
+    const int cus = dvgo::device_cu_count();
+    int64_t done = 0;
+    if (vec && n >= 4) {
+        const int64_t n4 = n >> 2;
+        int64_t blocks = (n4 + 255) / 256;
+        if (blocks > static_cast<int64_t>(cus) * 8) blocks = static_cast<int64_t>(cus) * 8;
+        DVGO_LAUNCH(K_ADAM, adam_vec_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, a);
+        if (int32_t st = dvgo::launch_status()) return st;
+        done = n4 * 4;
+    }
+    if (done < n) {
+        int64_t blocks = (n - done + 255) / 256;
+        if (blocks > static_cast<int64_t>(cus) * 8) blocks = static_cast<int64_t>(cus) * 8;
+        DVGO_LAUNCH(K_ADAM, adam_scalar_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, a, done);
+        if (int32_t st = dvgo::launch_status()) return st;
+    }
+    return DVGO_OK;
+}
+
+}  // extern "C"

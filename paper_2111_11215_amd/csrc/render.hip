@@ -1,0 +1,697 @@
+// Forward volume rendering of the fine stage and its adjoint (paper
+// Eq. volume_rendering, Eq. fine_queries, Eq. post_activation,
+// Eq. density_activation, Eq. photo_loss).
+//
+// One render call runs a short pipeline of kernels over the compact sample
+// list written by dvgo_sample_rays; per-sample intermediates live in the
+// caller's workspace:
+//   prep     pack the network weights into matrix-core operand order;
+//            per-ray view encoding PE(d) and the first layer's per-ray part
+//   gather   trilinear density and feature interpolation per sample
+//   mlp      colour network on float32 (or bfloat16) matrix cores
+//   compose  per-ray front-to-back compositing with wavefront prefix scans
+// and the backward pass adds
+//   compose' walk each ray from its end (suffix scans from log_t_end)
+//   mlp'     network adjoint, per-block weight-gradient partials
+//   scatter  transpose of the trilinear interpolation, float atomics
+//   reduce   deterministic sum of the per-block weight-gradient partials
+#include "common.hpp"
+#include "mlp_mfma.hpp"
+
+using dvgo::GridArgs;
+using namespace dvgo_dev;
+
+namespace {
+
+constexpr int kMaxBwdBlocks = 256;
+
+struct WsLayout {
+    size_t base, pe, w1p, w2p, w2tp, w1pb, w2pb, w2tpb, raw, feat, col, partial, total;
+};
+
+WsLayout ws_layout(int64_t B, int64_t cap) {
+    WsLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = dvgo::align_up(off + bytes, 256);
+        return o;
+    };
+    L.base = take(static_cast<size_t>(B) * kH * 4);
+    L.pe = take(static_cast<size_t>(B) * 32 * 4);
+    L.w1p = take(kW1PackF32 * 4);
+    L.w2p = take(kW2PackF32 * 4);
+    L.w2tp = take(kW2PackF32 * 4);
+    L.w1pb = take(kW1PackBF16 * 2);
+    L.w2pb = take(kW2PackBF16 * 2);
+    L.w2tpb = take(kW2PackBF16 * 2);
+    L.raw = take(static_cast<size_t>(cap) * 4);
+    L.feat = take(static_cast<size_t>(cap) * kC * 4);
+    L.col = take(static_cast<size_t>(cap) * 4 * 4);
+    L.partial = take(static_cast<size_t>(kMaxBwdBlocks) * kPStride * 4);
+    L.total = off;
+    return L;
+}
+
+// ---------------------------------------------------------------------------
+// per-sample geometry (float32 recipe for t and x) and trilinear weights
+// ---------------------------------------------------------------------------
+struct SampleArgs {
+    const float* rays_o;
+    const float* rays_d;
+    const float* jitter;
+    const float* t_near;
+    const int* sample_ray;
+    const int* sample_k;
+    float step;
+};
+
+__device__ __forceinline__ void sample_point(const SampleArgs& a, int r, int k, float x[3], float* t_out) {
+    float o[3], d[3];
+    for (int i = 0; i < 3; ++i) {
+        o[i] = a.rays_o[3 * r + i];
+        d[i] = a.rays_d[3 * r + i];
+    }
+    const float p = a.jitter ? a.jitter[r] : 0.0f;
+    const float t = recipe_tk(a.t_near[r], p, k, a.step);
+    recipe_x(o, d, t, x);
+    if (t_out) *t_out = t;
+}
+
+struct Tri {
+    int64_t base;   // linear vertex index of corner (0,0,0)
+    int sx, sy;     // vertex strides of x and y (z stride 1)
+    float w[8];     // corner c = (c>>2 &1, c>>1 &1, c &1)
+};
+
+__device__ __forceinline__ Tri trilinear(const GridArgs& g, const float x[3]) {
+    int i0[3];
+    float f[3];
+    for (int i = 0; i < 3; ++i) {
+        const float u = (x[i] - g.mn[i]) * g.scale[i];
+        const float fl = fminf(fmaxf(floorf(u), 0.0f), static_cast<float>(g.n[i] - 2));
+        i0[i] = static_cast<int>(fl);
+        f[i] = fminf(fmaxf(u - fl, 0.0f), 1.0f);
+    }
+    Tri t;
+    t.sy = g.n[2];
+    t.sx = g.n[1] * g.n[2];
+    t.base = (static_cast<int64_t>(i0[0]) * g.n[1] + i0[1]) * g.n[2] + i0[2];
+    const float gx[2] = {1.0f - f[0], f[0]}, gy[2] = {1.0f - f[1], f[1]}, gz[2] = {1.0f - f[2], f[2]};
+    for (int c = 0; c < 8; ++c) t.w[c] = gx[(c >> 2) & 1] * gy[(c >> 1) & 1] * gz[c & 1];
+    return t;
+}
+
+__device__ __forceinline__ int64_t corner(const Tri& t, int c) {
+    return t.base + ((c >> 2) & 1) * static_cast<int64_t>(t.sx) + ((c >> 1) & 1) * t.sy + (c & 1);
+}
+
+__device__ __forceinline__ float softplus_f(float x) {
+    return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x)));
+}
+__device__ __forceinline__ float sigmoid_f(float x) { return 1.0f / (1.0f + expf(-x)); }
+
+__device__ __forceinline__ int64_t live_count(const int64_t* n_kept, int64_t cap) {
+    const int64_t n = *n_kept;
+    return n < cap ? n : cap;
+}
+
+// ---------------------------------------------------------------------------
+// prep: per-ray encodings and first-layer per-ray part
+// ---------------------------------------------------------------------------
+// base[r][i] = b1[i] + sum_q W1[i][C+q] * PE(d_r)[q];  pe[r][0..31] (27 used)
+__global__ void ray_base_kernel(const float* __restrict__ rays_d, int B, const float* __restrict__ w1,
+                                const float* __restrict__ b1, float* __restrict__ base, float* __restrict__ pe) {
+    const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (gid >= static_cast<int64_t>(B) * kH) return;
+    const int r = static_cast<int>(gid / kH);
+    const int i = static_cast<int>(gid % kH);
+    float d[3] = {rays_d[3 * r], rays_d[3 * r + 1], rays_d[3 * r + 2]};
+    float e[kPE];
+    for (int c = 0; c < 3; ++c) e[c] = d[c];
+    for (int fq = 0; fq < 4; ++fq) {
+        const float sc = static_cast<float>(1 << fq);
+        for (int c = 0; c < 3; ++c) {
+            float sv, cv;
+            sincosf(d[c] * sc, &sv, &cv);
+            e[3 + 6 * fq + c] = sv;
+            e[6 + 6 * fq + c] = cv;
+        }
+    }
+    if (w1) {
+        float acc = b1[i];
+        for (int q = 0; q < kPE; ++q) acc += w1[i * kIn + kC + q] * e[q];
+        base[static_cast<int64_t>(r) * kH + i] = acc;
+    }
+    if (i < 32) pe[static_cast<int64_t>(r) * 32 + i] = i < kPE ? e[i] : 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// gather: raw density and interpolated features per sample
+// ---------------------------------------------------------------------------
+struct GatherArgs {
+    SampleArgs sa;
+    GridArgs g;
+    const float* density;
+    const void* feat;
+    int feat_bf16;
+    int with_feat;
+    const int64_t* n_kept;
+    int64_t cap;
+    float* raw_out;
+    float* feat_out;
+};
+
+__device__ __forceinline__ float bf16_to_f(uint16_t b) { return __uint_as_float(static_cast<uint32_t>(b) << 16); }
+
+__global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
+    const int64_t n = live_count(a.n_kept, a.cap);
+    for (int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; s < n;
+         s += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int r = a.sa.sample_ray[s];
+        const int k = a.sa.sample_k[s];
+        float x[3];
+        sample_point(a.sa, r, k, x, nullptr);
+        const Tri t = trilinear(a.g, x);
+        float raw = 0.0f;
+        for (int c = 0; c < 8; ++c) raw += t.w[c] * a.density[corner(t, c)];
+        a.raw_out[s] = raw;
+        if (!a.with_feat) continue;
+        float f[kC];
+        for (int ch = 0; ch < kC; ++ch) f[ch] = 0.0f;
+        if (!a.feat_bf16) {
+            const float4* F = static_cast<const float4*>(a.feat);
+            for (int c = 0; c < 8; ++c) {
+                const int64_t v = corner(t, c) * 3;
+                const float4 q0 = F[v], q1 = F[v + 1], q2 = F[v + 2];
+                const float w = t.w[c];
+                f[0] += w * q0.x; f[1] += w * q0.y; f[2] += w * q0.z; f[3] += w * q0.w;
+                f[4] += w * q1.x; f[5] += w * q1.y; f[6] += w * q1.z; f[7] += w * q1.w;
+                f[8] += w * q2.x; f[9] += w * q2.y; f[10] += w * q2.z; f[11] += w * q2.w;
+            }
+        } else {
+            const uint2* F = static_cast<const uint2*>(a.feat);
+            for (int c = 0; c < 8; ++c) {
+                const int64_t v = corner(t, c) * 3;
+                const float w = t.w[c];
+                for (int q = 0; q < 3; ++q) {
+                    const uint2 u = F[v + q];
+                    f[4 * q + 0] += w * __uint_as_float(u.x << 16);
+                    f[4 * q + 1] += w * __uint_as_float(u.x & 0xFFFF0000u);
+                    f[4 * q + 2] += w * __uint_as_float(u.y << 16);
+                    f[4 * q + 3] += w * __uint_as_float(u.y & 0xFFFF0000u);
+                }
+            }
+        }
+        float4* out = reinterpret_cast<float4*>(a.feat_out + s * kC);
+        out[0] = make_float4(f[0], f[1], f[2], f[3]);
+        out[1] = make_float4(f[4], f[5], f[6], f[7]);
+        out[2] = make_float4(f[8], f[9], f[10], f[11]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// compose: one wavefront per ray slot, 64 samples per step, prefix scans
+// ---------------------------------------------------------------------------
+struct ComposeArgs {
+    SampleArgs sa;
+    const int* perm;
+    const int* ray_offset;
+    const int* n_uniform;
+    const int64_t* n_kept;
+    int64_t cap;
+    int B;
+    float act_shift;
+    float bg[3];
+    float* raw;        // in: raw density; out (backward): dL/draw
+    float* col;        // in: colour [cap][4]; out (backward): dL/dc
+    int with_color;
+    // forward outputs
+    float* rgb;
+    float* depth;
+    float* acc;
+    float* log_t_end;
+    float* seg_w;
+    float* sample_w;
+    // backward inputs
+    const float* log_t_end_in;
+    const float* grad_rgb;
+    const float* grad_depth;
+    const float* grad_acc;
+};
+
+__device__ __forceinline__ float wave_incl_scan(float v, int lane) {
+    for (int off = 1; off < 64; off <<= 1) {
+        const float y = __shfl_up(v, off, 64);
+        if (lane >= off) v += y;
+    }
+    return v;
+}
+// inclusive suffix sum: sum over lanes >= lane
+__device__ __forceinline__ float wave_incl_suffix(float v, int lane) {
+    for (int off = 1; off < 64; off <<= 1) {
+        const float y = __shfl_down(v, off, 64);
+        if (lane + off < 64) v += y;
+    }
+    return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(256) void compose_fwd_kernel(ComposeArgs a) {
+    __shared__ float segs[4][32];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int slot = blockIdx.x * 4 + wave;
+    if (slot >= a.B) return;
+    const int64_t n = live_count(a.n_kept, a.cap);
+    const int r = a.perm[slot];
+    int64_t s0 = a.ray_offset[slot], s1 = a.ray_offset[slot + 1];
+    s0 = s0 < n ? s0 : n;
+    s1 = s1 < n ? s1 : n;
+    const int nu = a.n_uniform[r];
+    const float tn = a.sa.t_near[r];
+    const float p = a.sa.jitter ? a.sa.jitter[r] : 0.0f;
+    const float step = a.sa.step;
+    if (lane < 32) segs[wave][lane] = 0.0f;
+    __builtin_amdgcn_wave_barrier();
+    float logT = 0.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f, dep = 0.0f, accw = 0.0f;
+    for (int64_t base = s0; base < s1; base += 64) {
+        const int64_t s = base + lane;
+        const bool ok = s < s1;
+        float sd = 0.0f, alpha = 0.0f, tk = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+        int k = 0;
+        if (ok) {
+            const float sig = softplus_f(a.raw[s] + a.act_shift);
+            sd = sig * step;
+            alpha = -expm1f(-sd);
+            k = a.sa.sample_k[s];
+            tk = recipe_tk(tn, p, k, step);
+            if (a.with_color) {
+                const float4 c = reinterpret_cast<const float4*>(a.col)[s];
+                c0 = c.x; c1 = c.y; c2 = c.z;
+            }
+        }
+        const float incl = wave_incl_scan(sd, lane);
+        float excl = __shfl_up(incl, 1, 64);
+        if (lane == 0) excl = 0.0f;
+        const float w = ok ? expf(logT - excl) * alpha : 0.0f;
+        cr += w * c0; cg += w * c1; cb += w * c2;
+        dep += w * tk;
+        accw += w;
+        if (ok && a.seg_w) atomicAdd(&segs[wave][(32LL * k) / nu], w);
+        if (ok && a.sample_w) a.sample_w[s] = w;
+        logT -= __shfl(incl, 63, 64);
+    }
+    cr = wave_sum(cr); cg = wave_sum(cg); cb = wave_sum(cb);
+    dep = wave_sum(dep);
+    accw = wave_sum(accw);
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) {
+        const float T = expf(logT);
+        if (a.rgb) {
+            a.rgb[3 * r + 0] = cr + T * a.bg[0];
+            a.rgb[3 * r + 1] = cg + T * a.bg[1];
+            a.rgb[3 * r + 2] = cb + T * a.bg[2];
+        }
+        if (a.depth) a.depth[r] = dep;
+        if (a.acc) a.acc[r] = accw;
+        a.log_t_end[r] = logT;
+    }
+    if (a.seg_w && lane < 32) a.seg_w[static_cast<int64_t>(r) * 32 + lane] = segs[wave][lane];
+}
+
+// Backward of compose: walk each ray from its end in 64-sample steps.
+__global__ __launch_bounds__(256) void compose_bwd_kernel(ComposeArgs a) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int slot = blockIdx.x * 4 + wave;
+    if (slot >= a.B) return;
+    const int64_t n = live_count(a.n_kept, a.cap);
+    const int r = a.perm[slot];
+    int64_t s0 = a.ray_offset[slot], s1 = a.ray_offset[slot + 1];
+    s0 = s0 < n ? s0 : n;
+    s1 = s1 < n ? s1 : n;
+    if (s1 <= s0) return;
+    const float tn = a.sa.t_near[r];
+    const float p = a.sa.jitter ? a.sa.jitter[r] : 0.0f;
+    const float step = a.sa.step;
+    float g[5];
+    g[0] = a.grad_rgb ? a.grad_rgb[3 * r + 0] : 0.0f;
+    g[1] = a.grad_rgb ? a.grad_rgb[3 * r + 1] : 0.0f;
+    g[2] = a.grad_rgb ? a.grad_rgb[3 * r + 2] : 0.0f;
+    g[3] = a.grad_depth ? a.grad_depth[r] : 0.0f;
+    g[4] = a.grad_acc ? a.grad_acc[r] : 0.0f;
+    float logTa = a.log_t_end_in[r];          // log T after the walked suffix
+    const float Tend = expf(logTa);
+    float S[5] = {Tend * a.bg[0], Tend * a.bg[1], Tend * a.bg[2], 0.0f, 0.0f};
+    const int64_t nsteps = (s1 - s0 + 63) / 64;
+    for (int64_t it = nsteps - 1; it >= 0; --it) {
+        const int64_t s = s0 + it * 64 + lane;
+        const bool ok = s < s1;
+        float sd = 0.0f, raw = 0.0f, tk = 0.0f, v[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        if (ok) {
+            raw = a.raw[s];
+            sd = softplus_f(raw + a.act_shift) * step;
+            tk = recipe_tk(tn, p, a.sa.sample_k[s], step);
+            if (a.with_color) {
+                const float4 c = reinterpret_cast<const float4*>(a.col)[s];
+                v[0] = c.x; v[1] = c.y; v[2] = c.z;
+            }
+            v[3] = tk;
+            v[4] = 1.0f;
+        }
+        // log T_{k+1} = logTa + sum of sd over later samples of this step
+        const float suf = wave_incl_suffix(sd, lane);
+        float suf_ex = __shfl_down(suf, 1, 64);
+        if (lane == 63) suf_ex = 0.0f;
+        const float Tafter = expf(logTa + suf_ex);
+        const float w = ok ? Tafter * expm1f(sd) : 0.0f;
+        float dsig = 0.0f;
+        float tot[5];
+        for (int ch = 0; ch < 5; ++ch) {
+            const float wv = w * v[ch];
+            const float sfx = wave_incl_suffix(wv, lane);
+            float sfx_ex = __shfl_down(sfx, 1, 64);
+            if (lane == 63) sfx_ex = 0.0f;
+            dsig += g[ch] * (Tafter * v[ch] - (S[ch] + sfx_ex));
+            tot[ch] = __shfl(sfx, 0, 64);
+        }
+        if (ok) {
+            const float draw = step * dsig * sigmoid_f(raw + a.act_shift);
+            a.raw[s] = draw;
+            if (a.with_color) {
+                reinterpret_cast<float4*>(a.col)[s] = make_float4(w * g[0], w * g[1], w * g[2], 0.0f);
+            }
+        }
+        logTa += __shfl(suf, 0, 64);
+        for (int ch = 0; ch < 5; ++ch) S[ch] += tot[ch];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// scatter: transpose of the trilinear gathers into the float32 gradients
+// ---------------------------------------------------------------------------
+struct ScatterArgs {
+    SampleArgs sa;
+    GridArgs g;
+    const int64_t* n_kept;
+    int64_t cap;
+    const float* draw;
+    const float* dfeat;
+    float* grad_density;
+    float* grad_feat;
+};
+
+__global__ __launch_bounds__(256) void scatter_kernel(ScatterArgs a) {
+    const int64_t n = live_count(a.n_kept, a.cap);
+    for (int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; s < n;
+         s += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int r = a.sa.sample_ray[s];
+        const int k = a.sa.sample_k[s];
+        float x[3];
+        sample_point(a.sa, r, k, x, nullptr);
+        const Tri t = trilinear(a.g, x);
+        const float dr = a.draw[s];
+        if (dr != 0.0f)
+            for (int c = 0; c < 8; ++c) unsafeAtomicAdd(a.grad_density + corner(t, c), t.w[c] * dr);
+        if (!a.dfeat) continue;
+        float f[kC];
+        const float4* in = reinterpret_cast<const float4*>(a.dfeat + s * kC);
+        const float4 q0 = in[0], q1 = in[1], q2 = in[2];
+        f[0] = q0.x; f[1] = q0.y; f[2] = q0.z; f[3] = q0.w;
+        f[4] = q1.x; f[5] = q1.y; f[6] = q1.z; f[7] = q1.w;
+        f[8] = q2.x; f[9] = q2.y; f[10] = q2.z; f[11] = q2.w;
+        for (int c = 0; c < 8; ++c) {
+            float* dst = a.grad_feat + corner(t, c) * kC;
+            const float w = t.w[c];
+            for (int ch = 0; ch < kC; ++ch) unsafeAtomicAdd(dst + ch, w * f[ch]);
+        }
+    }
+}
+
+// Deterministic sum of the per-block weight-gradient partials (+= into out).
+__global__ void reduce_partials_kernel(const float* __restrict__ partial, int nblk, float* __restrict__ out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kMlpParams) return;
+    float s = 0.0f;
+    for (int b = 0; b < nblk; ++b) s += partial[static_cast<int64_t>(b) * kPStride + p];
+    out[p] += s;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct Common {
+    SampleArgs sa;
+    GridArgs g;
+    WsLayout L;
+    char* ws;
+    int64_t cap;
+    int B;
+};
+
+int32_t validate(const dvgo_field* field, const dvgo_mlp* mlp, const float* rays_o, const float* rays_d,
+                 const float* t_near, const int32_t* n_uniform, const int32_t* perm, const int32_t* ray_offset,
+                 const int32_t* sample_ray, const int32_t* sample_k, const int64_t* n_kept, int64_t capacity,
+                 int32_t B, float step, const float* bg, void* workspace, size_t workspace_bytes) {
+    if (!field || !bg || B < 0 || capacity < 0 || !(step > 0.0f)) return DVGO_E_ARG;
+    if (!dvgo::box_ok(&field->box, 2) || !field->density) return DVGO_E_ARG;
+    if (mlp) {
+        if (field->channels != kC) return DVGO_E_SHAPE;
+        if (!field->feat) return DVGO_E_ARG;
+        if (field->feat_dtype != DVGO_F32 && field->feat_dtype != DVGO_BF16) return DVGO_E_DTYPE;
+        if (mlp->hidden != kH) return DVGO_E_SHAPE;
+        if (mlp->precision != DVGO_F32 && mlp->precision != DVGO_BF16) return DVGO_E_DTYPE;
+        if (!mlp->w1 || !mlp->b1 || !mlp->w2 || !mlp->b2 || !mlp->w3 || !mlp->b3) return DVGO_E_ARG;
+    }
+    if (B > 0 && (!rays_o || !rays_d || !t_near || !n_uniform || !perm || !ray_offset)) return DVGO_E_ARG;
+    if (!n_kept) return DVGO_E_ARG;
+    if (capacity > 0 && (!sample_ray || !sample_k)) return DVGO_E_ARG;
+    if (workspace_bytes < dvgo_render_workspace_bytes(B, capacity, kC) || (!workspace && workspace_bytes))
+        return DVGO_E_CAPACITY;
+    return DVGO_OK;
+}
+
+int grid_for(int64_t work, int per_block, int max_blocks) {
+    int64_t b = (work + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    if (b > max_blocks) b = max_blocks;
+    return static_cast<int>(b);
+}
+
+int32_t run_prep(const Common& cm, const dvgo_mlp* mlp, hipStream_t s) {
+    float* base = reinterpret_cast<float*>(cm.ws + cm.L.base);
+    float* pe = reinterpret_cast<float*>(cm.ws + cm.L.pe);
+    if (mlp) {
+        PackArgs pk;
+        pk.w1 = mlp->w1;
+        pk.w2 = mlp->w2;
+        pk.w1p = reinterpret_cast<float*>(cm.ws + cm.L.w1p);
+        pk.w2p = reinterpret_cast<float*>(cm.ws + cm.L.w2p);
+        pk.w2tp = reinterpret_cast<float*>(cm.ws + cm.L.w2tp);
+        pk.w1pb = reinterpret_cast<uint16_t*>(cm.ws + cm.L.w1pb);
+        pk.w2pb = reinterpret_cast<uint16_t*>(cm.ws + cm.L.w2pb);
+        pk.w2tpb = reinterpret_cast<uint16_t*>(cm.ws + cm.L.w2tpb);
+        pk.bf16 = mlp->precision == DVGO_BF16;
+        launch_pack(pk, s);
+        if (int32_t st = dvgo::launch_status()) return st;
+    }
+    if (cm.B > 0 && mlp) {
+        const int64_t work = static_cast<int64_t>(cm.B) * kH;
+        DVGO_LAUNCH(K_RAY_BASE, ray_base_kernel, dim3(static_cast<unsigned>((work + 255) / 256)), dim3(256), 0, s,
+                           cm.sa.rays_d, cm.B, mlp->w1, mlp->b1, base, pe);
+        if (int32_t st = dvgo::launch_status()) return st;
+    }
+    return DVGO_OK;
+}
+
+int32_t run_gather(const Common& cm, const dvgo_field* field, bool with_feat, const int64_t* n_kept,
+                   hipStream_t s) {
+    if (cm.cap == 0) return DVGO_OK;
+    GatherArgs ga;
+    ga.sa = cm.sa;
+    ga.g = cm.g;
+    ga.density = field->density;
+    ga.feat = field->feat;
+    ga.feat_bf16 = field->feat_dtype == DVGO_BF16;
+    ga.with_feat = with_feat;
+    ga.n_kept = n_kept;
+    ga.cap = cm.cap;
+    ga.raw_out = reinterpret_cast<float*>(cm.ws + cm.L.raw);
+    ga.feat_out = reinterpret_cast<float*>(cm.ws + cm.L.feat);
+    const int blocks = grid_for(cm.cap, 256, dvgo::device_cu_count() * 16);
+    DVGO_LAUNCH(K_GATHER, gather_kernel, dim3(blocks), dim3(256), 0, s, ga);
+    return dvgo::launch_status();
+}
+
+MlpArgs make_mlp_args(const Common& cm, const dvgo_mlp* mlp, const int64_t* n_kept) {
+    MlpArgs ma;
+    ma.sample_ray = cm.sa.sample_ray;
+    ma.n_kept = n_kept;
+    ma.cap = cm.cap;
+    ma.w1 = mlp->w1;
+    ma.b2 = mlp->b2;
+    ma.w3 = mlp->w3;
+    ma.b3 = mlp->b3;
+    ma.base = reinterpret_cast<const float*>(cm.ws + cm.L.base);
+    ma.pe = reinterpret_cast<const float*>(cm.ws + cm.L.pe);
+    ma.w1p = reinterpret_cast<const float*>(cm.ws + cm.L.w1p);
+    ma.w2p = reinterpret_cast<const float*>(cm.ws + cm.L.w2p);
+    ma.w2tp = reinterpret_cast<const float*>(cm.ws + cm.L.w2tp);
+    ma.w1pb = reinterpret_cast<const uint16_t*>(cm.ws + cm.L.w1pb);
+    ma.w2pb = reinterpret_cast<const uint16_t*>(cm.ws + cm.L.w2pb);
+    ma.w2tpb = reinterpret_cast<const uint16_t*>(cm.ws + cm.L.w2tpb);
+    ma.feat = reinterpret_cast<float*>(cm.ws + cm.L.feat);
+    ma.col = reinterpret_cast<float*>(cm.ws + cm.L.col);
+    ma.partial = reinterpret_cast<float*>(cm.ws + cm.L.partial);
+    ma.bf16 = mlp->precision == DVGO_BF16;
+    return ma;
+}
+
+ComposeArgs make_compose(const Common& cm, const int32_t* perm, const int32_t* ray_offset, const int32_t* n_uniform,
+                         const int64_t* n_kept, float act_shift, const float* bg, bool with_color) {
+    ComposeArgs ca;
+    std::memset(&ca, 0, sizeof(ca));
+    ca.sa = cm.sa;
+    ca.perm = perm;
+    ca.ray_offset = ray_offset;
+    ca.n_uniform = n_uniform;
+    ca.n_kept = n_kept;
+    ca.cap = cm.cap;
+    ca.B = cm.B;
+    ca.act_shift = act_shift;
+    for (int i = 0; i < 3; ++i) ca.bg[i] = bg[i];
+    ca.raw = reinterpret_cast<float*>(cm.ws + cm.L.raw);
+    ca.col = reinterpret_cast<float*>(cm.ws + cm.L.col);
+    ca.with_color = with_color;
+    return ca;
+}
+
+Common make_common(const dvgo_field* field, const float* rays_o, const float* rays_d, const float* jitter,
+                   const float* t_near, const int32_t* sample_ray, const int32_t* sample_k, int64_t capacity,
+                   int32_t B, float step, void* workspace) {
+    Common cm;
+    cm.sa.rays_o = rays_o;
+    cm.sa.rays_d = rays_d;
+    cm.sa.jitter = jitter;
+    cm.sa.t_near = t_near;
+    cm.sa.sample_ray = sample_ray;
+    cm.sa.sample_k = sample_k;
+    cm.sa.step = step;
+    cm.g = dvgo::make_grid(field->box);
+    cm.L = ws_layout(B, capacity);
+    cm.ws = static_cast<char*>(workspace);
+    cm.cap = capacity;
+    cm.B = B;
+    return cm;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t dvgo_mlp_param_count(int32_t channels, int32_t hidden) {
+    if (channels < 0 || hidden < 0) return 0;
+    const int64_t in = channels + kPE;
+    return hidden * in + hidden + static_cast<int64_t>(hidden) * hidden + hidden + 3LL * hidden + 3;
+}
+
+size_t dvgo_render_workspace_bytes(int32_t B, int64_t capacity, int32_t channels) {
+    if (B < 0 || capacity < 0 || channels != kC) return 0;
+    return ws_layout(B, capacity).total;
+}
+
+int32_t dvgo_render_fwd(const dvgo_field* field, const dvgo_mlp* mlp, const float* rays_o, const float* rays_d,
+                        const float* jitter, const float* t_near, const int32_t* n_uniform, const int32_t* perm,
+                        const int32_t* ray_offset, const int32_t* sample_ray, const int32_t* sample_k,
+                        const int64_t* n_kept, int64_t capacity, int32_t B, float step, const float* bg, float* rgb,
+                        float* depth, float* acc, float* log_t_end, float* seg_w, float* sample_w, void* workspace,
+                        size_t workspace_bytes, void* stream) {
+    if (int32_t st = validate(field, mlp, rays_o, rays_d, t_near, n_uniform, perm, ray_offset, sample_ray, sample_k,
+                              n_kept, capacity, B, step, bg, workspace, workspace_bytes))
+        return st;
+    if (!log_t_end && B > 0) return DVGO_E_ARG;
+    if (!mlp && rgb) return DVGO_E_ARG;
+    hipStream_t s = dvgo::as_stream(stream);
+    if (B == 0) return DVGO_OK;
+    Common cm = make_common(field, rays_o, rays_d, jitter, t_near, sample_ray, sample_k, capacity, B, step,
+                            workspace);
+    if (int32_t st = run_prep(cm, mlp, s)) return st;
+    if (int32_t st = run_gather(cm, field, mlp != nullptr, n_kept, s)) return st;
+    if (mlp && capacity > 0) {
+        MlpArgs ma = make_mlp_args(cm, mlp, n_kept);
+        launch_mlp_fwd(ma, dvgo::device_cu_count(), s);
+        if (int32_t st = dvgo::launch_status()) return st;
+    }
+    ComposeArgs ca = make_compose(cm, perm, ray_offset, n_uniform, n_kept, field->act_shift, bg, mlp != nullptr);
+    ca.rgb = rgb;
+    ca.depth = depth;
+    ca.acc = acc;
+    ca.log_t_end = log_t_end;
+    ca.seg_w = seg_w;
+    ca.sample_w = sample_w;
+    DVGO_LAUNCH(K_COMPOSE_FWD, compose_fwd_kernel, dim3((B + 3) / 4), dim3(256), 0, s, ca);
+    return dvgo::launch_status();
+}
+
+int32_t dvgo_render_bwd(const dvgo_field* field, const dvgo_mlp* mlp, const float* rays_o, const float* rays_d,
+                        const float* jitter, const float* t_near, const int32_t* n_uniform, const int32_t* perm,
+                        const int32_t* ray_offset, const int32_t* sample_ray, const int32_t* sample_k,
+                        const int64_t* n_kept, int64_t capacity, int32_t B, float step, const float* bg,
+                        const float* log_t_end, const float* grad_rgb, const float* grad_depth,
+                        const float* grad_acc, float* grad_density, float* grad_feat, float* grad_mlp,
+                        void* workspace, size_t workspace_bytes, void* stream) {
+    if (int32_t st = validate(field, mlp, rays_o, rays_d, t_near, n_uniform, perm, ray_offset, sample_ray, sample_k,
+                              n_kept, capacity, B, step, bg, workspace, workspace_bytes))
+        return st;
+    if (B > 0 && (!log_t_end || !grad_density)) return DVGO_E_ARG;
+    if (mlp && (!grad_feat || !grad_mlp)) return DVGO_E_ARG;
+    if (!mlp && grad_rgb) return DVGO_E_ARG;
+    hipStream_t s = dvgo::as_stream(stream);
+    if (B == 0 || capacity == 0) return DVGO_OK;
+    Common cm = make_common(field, rays_o, rays_d, jitter, t_near, sample_ray, sample_k, capacity, B, step,
+                            workspace);
+    if (int32_t st = run_prep(cm, mlp, s)) return st;
+    if (int32_t st = run_gather(cm, field, mlp != nullptr, n_kept, s)) return st;
+    MlpArgs ma;
+    if (mlp) {
+        ma = make_mlp_args(cm, mlp, n_kept);
+        launch_mlp_fwd(ma, dvgo::device_cu_count(), s);
+        if (int32_t st = dvgo::launch_status()) return st;
+    }
+    ComposeArgs ca = make_compose(cm, perm, ray_offset, n_uniform, n_kept, field->act_shift, bg, mlp != nullptr);
+    ca.log_t_end_in = log_t_end;
+    ca.grad_rgb = grad_rgb;
+    ca.grad_depth = grad_depth;
+    ca.grad_acc = grad_acc;
+    DVGO_LAUNCH(K_COMPOSE_BWD, compose_bwd_kernel, dim3((B + 3) / 4), dim3(256), 0, s, ca);
+    if (int32_t st = dvgo::launch_status()) return st;
+    int nblk = 0;
+    if (mlp) {
+        nblk = dvgo::device_cu_count();
+        if (nblk > kMaxBwdBlocks) nblk = kMaxBwdBlocks;
+        launch_mlp_bwd(ma, nblk, s);
+        if (int32_t st = dvgo::launch_status()) return st;
+    }
+    ScatterArgs sc;
+    sc.sa = cm.sa;
+    sc.g = cm.g;
+    sc.n_kept = n_kept;
+    sc.cap = capacity;
+    sc.draw = reinterpret_cast<const float*>(cm.ws + cm.L.raw);
+    sc.dfeat = mlp ? reinterpret_cast<const float*>(cm.ws + cm.L.feat) : nullptr;
+    sc.grad_density = grad_density;
+    sc.grad_feat = grad_feat;
+    const int blocks = grid_for(capacity, 256, dvgo::device_cu_count() * 16);
+    DVGO_LAUNCH(K_SCATTER, scatter_kernel, dim3(blocks), dim3(256), 0, s, sc);
+    if (int32_t st = dvgo::launch_status()) return st;
+    if (mlp) {
+        DVGO_LAUNCH(K_REDUCE, reduce_partials_kernel, dim3((kMlpParams + 255) / 256), dim3(256), 0, s,
+                           reinterpret_cast<const float*>(cm.ws + cm.L.partial), nblk, grad_mlp);
+        if (int32_t st = dvgo::launch_status()) return st;
+    }
+    return DVGO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,362 @@
+// Fine-stage ray sampler: ray-box clip, uniform sample counts, coarse
+// alpha-mask skipping, optional Morton ray order, compaction into a per-ray
+// sample list (paper Sec. 4.2 "Fine-stage points sampling" and "Free space
+// skipping" rule one, Eq. coarse_sample, training jitter of the supplementary
+// implementation details).
+#include "common.hpp"
+
+using dvgo::GridArgs;
+using namespace dvgo_dev;
+
+namespace {
+
+constexpr int kMortonBits = 5;
+constexpr uint32_t kMortonInvalid = 1u << (3 * kMortonBits);
+constexpr int kMaxMortonRays = 32768;     // 15-bit ray id packed beside the key
+constexpr int kScanThreads = 1024;
+
+struct BoxF {
+    float mn[3];
+    float mx[3];
+    float mscale[3];   // 32/(max-min), float32
+};
+
+// One thread per ray: clip, uniform count, Morton key or identity order.
+__global__ void ray_setup_kernel(const float* __restrict__ rays_o, const float* __restrict__ rays_d,
+                                 const float* __restrict__ jitter, int B, BoxF box, float step,
+                                 int max_samples, int morton, float* __restrict__ t_near,
+                                 float* __restrict__ t_far, uint8_t* __restrict__ valid,
+                                 int* __restrict__ n_uniform, uint32_t* __restrict__ keys,
+                                 int* __restrict__ perm) {
+#pragma clang fp contract(off)
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= B) return;
+    float o[3], d[3];
+    for (int i = 0; i < 3; ++i) {
+        o[i] = rays_o[3 * r + i];
+        d[i] = rays_d[3 * r + i];
+    }
+    float te = -INFINITY, tx = INFINITY;
+    bool miss = false;
+    for (int i = 0; i < 3; ++i) {
+        if (d[i] == 0.0f) {
+            if (o[i] < box.mn[i] || o[i] > box.mx[i]) miss = true;
+        } else {
+            const float inv = 1.0f / d[i];
+            const float t0 = (box.mn[i] - o[i]) * inv;
+            const float t1 = (box.mx[i] - o[i]) * inv;
+            te = fmaxf(te, fminf(t0, t1));
+            tx = fminf(tx, fmaxf(t0, t1));
+        }
+    }
+    const float tn = fmaxf(te, 0.0f);
+    const bool v = !miss && (tn < tx);
+    int n = 0;
+    if (v) {
+        const float p = jitter ? jitter[r] : 0.0f;
+        // estimate, then settle on the exact prefix length (t_k is monotone in k)
+        const float est = (tx - tn) / step - p;
+        int k = static_cast<int>(fminf(fmaxf(floorf(est) - 2.0f, 0.0f), static_cast<float>(max_samples)));
+        while (k > 0 && !(recipe_tk(tn, p, k - 1, step) < tx)) --k;
+        while (k < max_samples && recipe_tk(tn, p, k, step) < tx) ++k;
+        n = k;
+    }
+    t_near[r] = v ? tn : 0.0f;
+    t_far[r] = v ? tx : 0.0f;
+    valid[r] = v ? 1 : 0;
+    n_uniform[r] = n;
+    if (morton) {
+        uint32_t key = kMortonInvalid;
+        if (v) {
+            const float tm = (tn + tx) * 0.5f;
+            float m[3];
+            recipe_x(o, d, tm, m);
+            uint32_t q[3];
+            for (int i = 0; i < 3; ++i) {
+                float u = (m[i] - box.mn[i]) * box.mscale[i];
+                float fl = fminf(fmaxf(floorf(u), 0.0f), static_cast<float>((1 << kMortonBits) - 1));
+                q[i] = static_cast<uint32_t>(fl);
+            }
+            key = 0;
+            for (int b = 0; b < kMortonBits; ++b) {
+                key |= ((q[0] >> b) & 1u) << (3 * b + 2);
+                key |= ((q[1] >> b) & 1u) << (3 * b + 1);
+                key |= ((q[2] >> b) & 1u) << (3 * b);
+            }
+        }
+        keys[r] = (key << 15) | static_cast<uint32_t>(r);
+    } else {
+        perm[r] = r;
+    }
+}
+
+// Single-workgroup bitonic sort of the packed (key, ray) words in LDS.
+__global__ __launch_bounds__(1024) void morton_sort_kernel(const uint32_t* __restrict__ keys, int B,
+                                                           int npow2, int* __restrict__ perm) {
+    __shared__ uint32_t s[kMaxMortonRays];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < npow2; i += blockDim.x) s[i] = i < B ? keys[i] : 0xFFFFFFFFu;
+    __syncthreads();
+    for (int k = 2; k <= npow2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < npow2; i += blockDim.x) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const uint32_t a = s[i], b = s[ixj];
+                    const bool up = (i & k) == 0;
+                    if ((a > b) == up) {
+                        s[i] = b;
+                        s[ixj] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = tid; i < B; i += blockDim.x) perm[i] = static_cast<int>(s[i] & 0x7FFFu);
+}
+
+struct KeepArgs {
+    const float* rays_o;
+    const float* rays_d;
+    const float* jitter;
+    const float* t_near;
+    const int* n_uniform;
+    const int* perm;
+    const uint32_t* coarse_bits;
+    const uint32_t* seg_mask;
+    GridArgs cg;
+    float step;
+    int B;
+};
+
+struct RayView {
+    float o[3], d[3], tn, p;
+    int r, n;
+    uint32_t seg;
+};
+
+__device__ __forceinline__ RayView load_ray(const KeepArgs& a, int slot) {
+    RayView v;
+    v.r = a.perm[slot];
+    v.n = a.n_uniform[v.r];
+    for (int i = 0; i < 3; ++i) {
+        v.o[i] = a.rays_o[3 * v.r + i];
+        v.d[i] = a.rays_d[3 * v.r + i];
+    }
+    v.tn = a.t_near[v.r];
+    v.p = a.jitter ? a.jitter[v.r] : 0.0f;
+    v.seg = a.seg_mask ? a.seg_mask[v.r] : 0xFFFFFFFFu;
+    return v;
+}
+
+__device__ __forceinline__ bool keep_sample(const KeepArgs& a, const RayView& v, int k) {
+    if (k >= v.n) return false;
+    if (a.seg_mask) {
+        const int seg = static_cast<int>((32LL * k) / v.n);
+        if (!((v.seg >> seg) & 1u)) return false;
+    }
+    if (a.coarse_bits) {
+        float x[3];
+        recipe_x(v.o, v.d, recipe_tk(v.tn, v.p, k, a.step), x);
+        const int c = recipe_cell(a.cg, x);
+        if (!((a.coarse_bits[c >> 5] >> (c & 31)) & 1u)) return false;
+    }
+    return true;
+}
+
+// One wavefront per ray slot: number of kept samples.
+__global__ __launch_bounds__(256) void count_kept_kernel(KeepArgs a, int* __restrict__ counts) {
+    const int slot = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (slot >= a.B) return;
+    const RayView v = load_ray(a, slot);
+    int cnt = 0;
+    for (int base = 0; base < v.n; base += 64) {
+        const bool keep = keep_sample(a, v, base + lane);
+        cnt += __popcll(__ballot(keep));
+    }
+    if (lane == 0) counts[slot] = cnt;
+}
+
+// Single-workgroup exclusive scan: ray_offset[i] = sum_{j<i} counts[j].
+__global__ __launch_bounds__(kScanThreads) void scan_offsets_kernel(const int* __restrict__ counts, int B,
+                                                                   int* __restrict__ ray_offset,
+                                                                   int64_t* __restrict__ n_kept) {
+    __shared__ long long wsum[kScanThreads / 64];
+    __shared__ long long carry_s;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) carry_s = 0;
+    __syncthreads();
+    constexpr int kPer = 4;
+    for (int base = 0; base < B; base += kScanThreads * kPer) {
+        long long v[kPer];
+        long long local = 0;
+        for (int u = 0; u < kPer; ++u) {
+            const int i = base + tid * kPer + u;
+            v[u] = i < B ? counts[i] : 0;
+            local += v[u];
+        }
+        // inclusive wave scan of `local`
+        long long incl = local;
+        for (int off = 1; off < 64; off <<= 1) {
+            const long long y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        long long wave_off = 0;
+        for (int w = 0; w < wave; ++w) wave_off += wsum[w];
+        long long run = carry_s + wave_off + incl - local;
+        for (int u = 0; u < kPer; ++u) {
+            const int i = base + tid * kPer + u;
+            if (i < B) ray_offset[i] = static_cast<int>(run);
+            run += v[u];
+        }
+        __syncthreads();
+        if (tid == kScanThreads - 1) carry_s = run;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        ray_offset[B] = static_cast<int>(carry_s);
+        *n_kept = carry_s;
+    }
+}
+
+// One wavefront per ray slot: write the kept (ray, k) pairs in ascending k.
+__global__ __launch_bounds__(256) void fill_kept_kernel(KeepArgs a, const int* __restrict__ ray_offset,
+                                                        int64_t capacity, int* __restrict__ sample_ray,
+                                                        int* __restrict__ sample_k) {
+    const int slot = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (slot >= a.B) return;
+    const RayView v = load_ray(a, slot);
+    int64_t pos0 = ray_offset[slot];
+    for (int base = 0; base < v.n; base += 64) {
+        const int k = base + lane;
+        const bool keep = keep_sample(a, v, k);
+        const uint64_t mask = __ballot(keep);
+        const int64_t pos = pos0 + lanes_below(mask);
+        if (keep && pos < capacity) {
+            sample_ray[pos] = v.r;
+            sample_k[pos] = k;
+        }
+        pos0 += __popcll(mask);
+    }
+}
+
+// One thread per 32-cell word of the coarse keep mask.
+__global__ void coarse_mask_kernel(const float* __restrict__ raw, int nx, int ny, int nz, float thr,
+                                   uint32_t* __restrict__ bits, int64_t ncells) {
+    const int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t nwords = (ncells + 31) / 32;
+    if (w >= nwords) return;
+    const int cy = ny - 1, cz = nz - 1;
+    uint32_t word = 0;
+    for (int b = 0; b < 32; ++b) {
+        const int64_t c = w * 32 + b;
+        if (c >= ncells) break;
+        const int iz = static_cast<int>(c % cz);
+        const int iy = static_cast<int>((c / cz) % cy);
+        const int ix = static_cast<int>(c / (static_cast<int64_t>(cz) * cy));
+        float m = -INFINITY;
+        for (int dx = 0; dx < 2; ++dx)
+            for (int dy = 0; dy < 2; ++dy)
+                for (int dz = 0; dz < 2; ++dz)
+                    m = fmaxf(m, raw[(static_cast<int64_t>(ix + dx) * ny + (iy + dy)) * nz + (iz + dz)]);
+        if (m >= thr) word |= 1u << b;
+    }
+    bits[w] = word;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t dvgo_coarse_mask_build(const float* raw, const dvgo_box* cbox, float raw_threshold, uint32_t* bits,
+                               void* stream) {
+    if (!raw || !bits || !dvgo::box_ok(cbox, 2)) return DVGO_E_ARG;
+    const int64_t ncells = static_cast<int64_t>(cbox->n[0] - 1) * (cbox->n[1] - 1) * (cbox->n[2] - 1);
+    const int64_t nwords = (ncells + 31) / 32;
+    const int threads = 256;
+    const unsigned blocks = static_cast<unsigned>((nwords + threads - 1) / threads);
+    DVGO_LAUNCH(K_COARSE_MASK, coarse_mask_kernel, dim3(blocks), dim3(threads), 0, dvgo::as_stream(stream), raw,
+                       cbox->n[0], cbox->n[1], cbox->n[2], raw_threshold, bits, ncells);
+    return dvgo::launch_status();
+}
+
+size_t dvgo_sample_workspace_bytes(int32_t B) {
+    if (B < 0) return 0;
+    return dvgo::align_up(static_cast<size_t>(B) * 4, 256) * 2 + 256;
+}
+
+int32_t dvgo_sample_rays(const float* rays_o, const float* rays_d, const float* jitter, int32_t B,
+                         const dvgo_box* box, float step, int32_t max_samples, const uint32_t* coarse_bits,
+                         const dvgo_box* coarse_box, const uint32_t* seg_mask, int32_t morton, float* t_near,
+                         float* t_far, uint8_t* valid, int32_t* n_uniform, int32_t* perm, int32_t* ray_offset,
+                         int32_t* sample_ray, int32_t* sample_k, int64_t capacity, int64_t* n_kept,
+                         void* workspace, size_t workspace_bytes, void* stream) {
+    if (B < 0 || !box) return DVGO_E_ARG;
+    if (!(step > 0.0f) || max_samples < 0 || capacity < 0) return DVGO_E_ARG;
+    for (int i = 0; i < 3; ++i)
+        if (!(box->xyz_max[i] > box->xyz_min[i])) return DVGO_E_ARG;
+    if (coarse_bits && !dvgo::box_ok(coarse_box, 2)) return DVGO_E_ARG;
+    if (!n_kept || !ray_offset) return DVGO_E_ARG;
+    if (B > 0 && (!rays_o || !rays_d || !t_near || !t_far || !valid || !n_uniform || !perm)) return DVGO_E_ARG;
+    if (capacity > 0 && (!sample_ray || !sample_k)) return DVGO_E_ARG;
+    if (morton && B > kMaxMortonRays) return DVGO_E_UNSUPPORTED;
+    if (static_cast<int64_t>(B) * max_samples >= (1LL << 31)) return DVGO_E_UNSUPPORTED;
+    if (workspace_bytes < dvgo_sample_workspace_bytes(B) || (B > 0 && !workspace)) return DVGO_E_CAPACITY;
+
+    hipStream_t s = dvgo::as_stream(stream);
+    if (B == 0) {
+        DVGO_LAUNCH(K_SCAN, scan_offsets_kernel, dim3(1), dim3(kScanThreads), 0, s,
+                           static_cast<const int*>(nullptr), 0, ray_offset, n_kept);
+        return dvgo::launch_status();
+    }
+    char* ws = static_cast<char*>(workspace);
+    int* counts = reinterpret_cast<int*>(ws);
+    uint32_t* keys = reinterpret_cast<uint32_t*>(ws + dvgo::align_up(static_cast<size_t>(B) * 4, 256));
+
+    BoxF bf;
+    for (int i = 0; i < 3; ++i) {
+        bf.mn[i] = box->xyz_min[i];
+        bf.mx[i] = box->xyz_max[i];
+        volatile float span = box->xyz_max[i] - box->xyz_min[i];
+        volatile float q = static_cast<float>(1 << kMortonBits);
+        bf.mscale[i] = q / span;
+    }
+    const int t1 = 256;
+    DVGO_LAUNCH(K_RAY_SETUP, ray_setup_kernel, dim3((B + t1 - 1) / t1), dim3(t1), 0, s, rays_o, rays_d, jitter, B, bf,
+                       step, max_samples, morton, t_near, t_far, valid, n_uniform, keys, perm);
+    if (int32_t st = dvgo::launch_status()) return st;
+    if (morton) {
+        int np2 = 2;
+        while (np2 < B) np2 <<= 1;
+        DVGO_LAUNCH(K_MORTON_SORT, morton_sort_kernel, dim3(1), dim3(1024), 0, s, keys, B, np2, perm);
+        if (int32_t st = dvgo::launch_status()) return st;
+    }
+    KeepArgs ka;
+    ka.rays_o = rays_o;
+    ka.rays_d = rays_d;
+    ka.jitter = jitter;
+    ka.t_near = t_near;
+    ka.n_uniform = n_uniform;
+    ka.perm = perm;
+    ka.coarse_bits = coarse_bits;
+    ka.seg_mask = seg_mask;
+    ka.cg = coarse_bits ? dvgo::make_grid(*coarse_box) : GridArgs{};
+    ka.step = step;
+    ka.B = B;
+    const unsigned wblocks = static_cast<unsigned>((B + 3) / 4);
+    DVGO_LAUNCH(K_COUNT_KEPT, count_kept_kernel, dim3(wblocks), dim3(256), 0, s, ka, counts);
+    if (int32_t st = dvgo::launch_status()) return st;
+    DVGO_LAUNCH(K_SCAN, scan_offsets_kernel, dim3(1), dim3(kScanThreads), 0, s, counts, B, ray_offset, n_kept);
+    if (int32_t st = dvgo::launch_status()) return st;
+    DVGO_LAUNCH(K_FILL_KEPT, fill_kept_kernel, dim3(wblocks), dim3(256), 0, s, ka, ray_offset, capacity, sample_ray,
+                       sample_k);
+    return dvgo::launch_status();
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+"""Training-step driver of the fine stage: sample, render, loss, adjoint,
+Adam - every step a call into ``libdvgo.so`` on the current stream.
+
+Hyperparameters follow the paper's implementation details: Adam with batch
+8192, learning rates 0.1 for the grids and 1e-3 for the MLP, decayed
+exponentially to 0.1x at 20k iterations.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional
+
+import torch
+
+from . import api
+from ._lib import DVGO_BF16, DVGO_F32
+
+
+@dataclass
+class AdamState:
+    p: torch.Tensor
+    g: torch.Tensor
+    m: torch.Tensor
+    v: torch.Tensor
+    shadow: Optional[torch.Tensor] = None
+
+    @staticmethod
+    def of(p: torch.Tensor, shadow: bool = False) -> "AdamState":
+        st = AdamState(p, torch.zeros_like(p), torch.zeros_like(p), torch.zeros_like(p))
+        if shadow:
+            st.shadow = torch.empty(p.shape, dtype=torch.int16, device=p.device)
+            # the first forward reads the shadow: a zero-rate Adam step with
+            # zero moments leaves p, m, v unchanged and writes bf16(p)
+            api.adam_step(st.p, st.g, st.m, st.v, 0.0, 1, shadow=st.shadow)
+        return st
+
+
+@dataclass
+class FineConfig:
+    step: float
+    max_samples: int
+    bg: tuple = (1.0, 1.0, 1.0)
+    lr_grid: float = 0.1
+    lr_mlp: float = 1e-3
+    decay_steps: int = 20000
+    betas: tuple = (0.9, 0.999)
+    eps: float = 1e-8
+    precision: int = DVGO_F32        # matrix-core arithmetic of the MLP
+    bf16_feat: bool = False          # gather features from a bfloat16 shadow
+    morton: bool = False
+    capacity: Optional[int] = None
+
+
+class FineModel:
+    """Fine-stage parameters (density grid, feature grid, colour MLP) with
+    their Adam state, plus the frozen coarse keep-mask."""
+
+    def __init__(self, density, feat, mlp_flat, box_min, box_max, act_shift, cfg: FineConfig, coarse=None):
+        self.cfg = cfg
+        self.grid = api.Grid(density, feat, tuple(box_min), tuple(box_max), float(act_shift))
+        self.mlp = mlp_flat
+        self.coarse = coarse
+        self.st_density = AdamState.of(density)
+        self.st_feat = AdamState.of(feat, shadow=cfg.bf16_feat)
+        self.st_mlp = AdamState.of(mlp_flat)
+        self.grid.feat_shadow = self.st_feat.shadow
+        self.t = 0
+
+    def lr(self, base: float) -> float:
+        return base * 0.1 ** (self.t / self.cfg.decay_steps)
+
+    def sample(self, rays_o, rays_d, jitter, seg_mask=None) -> api.Samples:
+        c = self.cfg
+        return api.sample_rays(rays_o, rays_d, jitter, self.grid.box_min, self.grid.box_max, c.step, c.max_samples,
+                               coarse=self.coarse, seg_mask=seg_mask, morton=c.morton, capacity=c.capacity)
+
+    def render(self, s: api.Samples, **kw) -> dict:
+        c = self.cfg
+        return api.render_fwd(self.grid, self.mlp, s, c.bg, precision=c.precision, use_shadow=c.bf16_feat, **kw)
+
+    def backward(self, s: api.Samples, out: dict, grad_rgb: torch.Tensor) -> None:
+        c = self.cfg
+        api.render_bwd(self.grid, self.mlp, s, out["log_t_end"], grad_rgb, self.st_density.g, self.st_feat.g,
+                       self.st_mlp.g, c.bg, precision=c.precision, use_shadow=c.bf16_feat)
+
+    def adam(self) -> None:
+        c = self.cfg
+        self.t += 1
+        lg, lm = self.lr(c.lr_grid), self.lr(c.lr_mlp)
+        for st, lr in ((self.st_density, lg), (self.st_feat, lg), (self.st_mlp, lm)):
+            api.adam_step(st.p, st.g, st.m, st.v, lr, self.t, c.betas, c.eps, shadow=st.shadow)
+
+    def train_step(self, rays_o, rays_d, target, jitter=None, seg_mask=None) -> dict:
+        """One full iteration: sample, render, photometric loss, adjoint,
+        Adam.  Returns the loss (device tensor) and the sample list."""
+        s = self.sample(rays_o, rays_d, jitter, seg_mask)
+        out = self.render(s, want_depth_acc=False)
+        loss, grad = api.photo_loss(out["rgb"], target)
+        self.backward(s, out, grad)
+        self.adam()
+        return {"loss": loss, "samples": s, "rgb": out["rgb"]}

@@ -1,0 +1,103 @@
+"""The C ABI library loads, exports every symbol the header declares, and
+rejects bad arguments on the host before any launch (no GPU needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dvgo.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(dvgo_[a-z0-9_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2111_11215_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libdvgo.so not built: run __graft_entry__.build()")
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2111_11215_amd import _lib
+    names = _declared()
+    assert len(names) >= 17
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in _lib.SIGNATURES, f"binding lacks a signature for {n}"
+
+
+def test_status_strings(lib):
+    assert lib.dvgo_status_string(0) == b"ok"
+    for s in range(-6, 0):
+        assert lib.dvgo_status_string(s) != b"unknown status"
+    assert lib.dvgo_version() >= 1
+
+
+def test_param_counts(lib):
+    assert lib.dvgo_mlp_param_count(12, 128) == 128 * 39 + 128 + 128 * 128 + 128 + 3 * 128 + 3 == 22019
+    assert lib.dvgo_prop_param_count() == 64 * 54 + 64 + 64 * 64 + 64 + 32 * 64 + 32
+
+
+def test_workspace_queries(lib):
+    assert lib.dvgo_sample_workspace_bytes(8192) >= 8192 * 8
+    assert lib.dvgo_render_workspace_bytes(8192, 8192 * 552, 12) >= 8192 * 552 * 64
+    assert lib.dvgo_render_workspace_bytes(8192, 100, 11) == 0
+    assert lib.dvgo_proposal_workspace_bytes(1024) > 0
+
+
+def test_host_validation_rejects_before_launch(lib):
+    from paper_2111_11215_amd import _lib
+    box = _lib.make_box((-1, -1, -1), (1, 1, 1), (2, 2, 2))
+    bad_box = _lib.make_box((1, -1, -1), (-1, 1, 1), (2, 2, 2))
+    nul = None
+    # negative batch
+    assert lib.dvgo_sample_rays(nul, nul, nul, -1, ctypes.byref(box), 0.1, 10, nul, nul, nul, 0, nul, nul, nul,
+                                nul, nul, nul, nul, nul, 0, nul, nul, 0, nul) == -1
+    # inverted box
+    assert lib.dvgo_sample_rays(nul, nul, nul, 0, ctypes.byref(bad_box), 0.1, 10, nul, nul, nul, 0, nul, nul, nul,
+                                nul, nul, nul, nul, nul, 0, nul, nul, 0, nul) == -1
+    # zero step
+    assert lib.dvgo_sample_rays(nul, nul, nul, 0, ctypes.byref(box), 0.0, 10, nul, nul, nul, 0, nul, nul, nul,
+                                nul, nul, nul, nul, nul, 0, nul, nul, 0, nul) == -1
+    # Morton order beyond the packed-id limit
+    fake = ctypes.c_void_p(16)
+    assert lib.dvgo_sample_rays(fake, fake, nul, 40000, ctypes.byref(box), 0.1, 10, nul, nul, nul, 1, fake, fake,
+                                fake, fake, fake, fake, fake, fake, 1, fake, fake, 1 << 20, nul) == -6
+    # workspace too small
+    assert lib.dvgo_sample_rays(fake, fake, nul, 100, ctypes.byref(box), 0.1, 10, nul, nul, nul, 0, fake, fake,
+                                fake, fake, fake, fake, fake, fake, 1, fake, fake, 8, nul) == -4
+    # adam: t = 0 and bad beta
+    assert lib.dvgo_adam_step(fake, fake, fake, fake, nul, 10, 0.1, 0.9, 0.999, 1e-8, 0, nul) == -1
+    assert lib.dvgo_adam_step(fake, fake, fake, fake, nul, 10, 0.1, 1.0, 0.999, 1e-8, 1, nul) == -1
+    # render: wrong channel count / hidden width / precision code
+    f = _lib.Field()
+    f.density = 16
+    f.feat = 16
+    f.channels = 11
+    f.box = _lib.make_box((-1, -1, -1), (1, 1, 1), (4, 4, 4))
+    m = _lib.Mlp()
+    for nm in ("w1", "b1", "w2", "b2", "w3", "b3"):
+        setattr(m, nm, 16)
+    m.hidden = 128
+    bg = (ctypes.c_float * 3)(1, 1, 1)
+    args = [fake] * 8 + [fake, fake, 10, 4, 0.1, bg, nul, nul, nul, fake, nul, nul, fake, 1 << 30, nul]
+    assert lib.dvgo_render_fwd(ctypes.byref(f), ctypes.byref(m), fake, fake, nul, *args[3:]) == -2
+    f.channels = 12
+    m.hidden = 64
+    assert lib.dvgo_render_fwd(ctypes.byref(f), ctypes.byref(m), fake, fake, nul, *args[3:]) == -2
+    m.hidden = 128
+    m.precision = 7
+    assert lib.dvgo_render_fwd(ctypes.byref(f), ctypes.byref(m), fake, fake, nul, *args[3:]) == -3
+    # scene: too many spheres
+    assert lib.dvgo_scene_render(fake, fake, 1, ctypes.byref(box), fake, 100000, 0.01, 0.01, bg, fake, nul) == -1
+    # proposal: bad selection fraction
+    assert lib.dvgo_proposal_fwd(fake, fake, fake, nul, 1, ctypes.byref(box), nul, 1.5, 0.9, fake, nul, nul,
+                                 nul) == -1

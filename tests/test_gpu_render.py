@@ -1,0 +1,218 @@
+"""GPU parity of forward rendering and its adjoint against the FP64 oracle.
+
+Tolerances.  float32 form: per-output normwise relative error
+||gpu - ref||_2 / ||ref||_2 <= 1e-5 for rgb, depth, acc, log T, segment and
+sample weights and for the density gradient.  The feature and network
+gradients pass through ReLU derivatives: a hidden unit whose pre-activation
+lies within the float32 error bound of zero (|z| <= 1e-4 x the sum of the
+absolute terms of its dot product) may take either branch, so entries and
+tensors reached by such samples are checked against a proven error budget
+(tests/helpers.kink_budget) and every other entry at 1e-5.
+
+bfloat16 form: compared with the oracle's bfloat16 form (same values rounded
+to bfloat16, exact arithmetic otherwise) at 1e-4 (float32 accumulation
+order and bfloat16 rounding-boundary cases), with the same kink budget; the
+form's own approximation error against the exact network is reported and
+held to 2e-3 for rgb, depth and opacity.  Actual errors are printed."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from tests.helpers import (check_grid_grad, check_weight_grads, kink_budget, mlp_flat_np, np_of, report,
+                           to_dev)
+
+pytestmark = pytest.mark.gpu
+F32 = np.float32
+TOL32 = 1e-5
+TOLBF = 1e-4
+ZETA = 1e-4
+
+
+def _problem(seed=0, jitter=True, n_rays=4096, bias=0.0):
+    P = synth.tiny_config(seed, jitter=jitter, n_rays=n_rays)
+    P.act_shift = bias
+    rng = np.random.default_rng(seed + 100)
+    P.bs = [(rng.normal(size=b.shape) * 0.1).astype(F32) for b in P.bs]
+    return P
+
+
+def _gpu(P, coarse=None, morton=True, bf16=False):
+    import torch
+    from paper_2111_11215_amd import api
+    grid = api.Grid(to_dev(P.density), to_dev(P.feat), tuple(P.box_min), tuple(P.box_max), P.act_shift)
+    if bf16:
+        grid.feat_shadow = grid.feat.to(torch.bfloat16).view(torch.int16).contiguous()
+    flat = to_dev(mlp_flat_np(P.Ws, P.bs))
+    s = api.sample_rays(to_dev(P.rays.o), to_dev(P.rays.d),
+                        to_dev(P.rays.jitter) if P.rays.jitter is not None else None, P.box_min, P.box_max,
+                        P.step, P.max_samples, coarse=coarse, morton=morton)
+    return grid, flat, s
+
+
+def _oracle(P, morton=True, coarse=None, bf16=False, rays=None):
+    o, d, j = P.rays.o, P.rays.d, P.rays.jitter
+    if rays is not None:
+        o, d, j = o[rays], d[rays], (j[rays] if j is not None else None)
+    samp = O.sample_rays(o, d, j, P.box_min, P.box_max, P.step, P.max_samples, coarse=coarse, morton=morton)
+    feat = O.bf16_round(P.feat) if bf16 else P.feat
+    prm = O.Params(P.density, feat, P.Ws, P.bs, P.box_min, P.box_max, P.act_shift, mlp_bf16=bf16)
+    ref = O.render_forward(prm, o, d, j, samp, P.step, P.bg)
+    return samp, prm, ref, (o, d, j)
+
+
+def _grads(api, grid, flat, s, out, g, P, bf16=False, gD=None, gA=None):
+    import torch
+    from paper_2111_11215_amd._lib import DVGO_BF16, DVGO_F32
+    gd = torch.zeros_like(grid.density)
+    gf = torch.zeros_like(grid.feat)
+    gm = torch.zeros_like(flat)
+    api.render_bwd(grid, flat, s, out["log_t_end"], to_dev(np.asarray(g, F32)), gd, gf, gm, P.bg,
+                   precision=DVGO_BF16 if bf16 else DVGO_F32, use_shadow=bf16,
+                   grad_depth=None if gD is None else to_dev(np.asarray(gD, F32)),
+                   grad_acc=None if gA is None else to_dev(np.asarray(gA, F32)))
+    return np_of(gd), np_of(gf), np_of(gm)
+
+
+def _check_backward(P, prm, ref, ro, gd, gf, gm, g_oracle, tol, gD=None, gA=None):
+    o, d, j = ro
+    gr = O.render_backward(prm, o, d, j, ref["_samp"], P.step, P.bg, ref, g_oracle, gD, gA)
+    assert report("grad_density", gd, gr["density"])[0] <= tol
+    budget, wb, frac = kink_budget(prm, ref, g_oracle, ZETA, P.feat.shape, P.box_min, P.box_max)
+    print(f"  samples with an ambiguous ReLU unit: {frac:.2e}", flush=True)
+    check_grid_grad("grad_feat", gf, gr["feat"], budget, tol)
+    check_weight_grads(gm, gr["Ws"], gr["bs"], wb, tol)
+
+
+def _fwd_keys(out, ref, keys, tol, sel=None):
+    for key in keys:
+        got = np_of(out[key]) if sel is None else np_of(out[key])[sel]
+        nw, _ = report(key, got, ref[key])
+        assert nw <= tol, key
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_render_forward_parity_tiny(gpu_lib, bf16):
+    from paper_2111_11215_amd import api
+    from paper_2111_11215_amd._lib import DVGO_BF16, DVGO_F32
+    P = _problem(0, bias=0.4)
+    grid, flat, s = _gpu(P, bf16=bf16)
+    out = api.render_fwd(grid, flat, s, P.bg, precision=DVGO_BF16 if bf16 else DVGO_F32, use_shadow=bf16,
+                         want_seg_w=True, want_sample_w=True)
+    samp, prm, ref, _ = _oracle(P, bf16=bf16)
+    n = int(samp["ray_offset"][-1])
+    print(f"  rays {P.rays.o.shape[0]} samples {n}", flush=True)
+    tol = TOLBF if bf16 else TOL32
+    _fwd_keys(out, ref, ("rgb", "depth", "acc", "log_t_end", "seg_w"), tol)
+    assert report("sample_w", np_of(out["sample_w"])[:n], ref["sample_w"])[0] <= tol
+    if bf16:
+        _, _, exact, _ = _oracle(P, bf16=False)
+        print("  bf16 form vs exact network:", flush=True)
+        _fwd_keys(out, exact, ("rgb", "depth", "acc"), 2e-3)
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_render_backward_parity_tiny(gpu_lib, bf16):
+    from paper_2111_11215_amd import api
+    from paper_2111_11215_amd._lib import DVGO_BF16, DVGO_F32
+    P = _problem(1, bias=-0.3)
+    grid, flat, s = _gpu(P, bf16=bf16)
+    out = api.render_fwd(grid, flat, s, P.bg, precision=DVGO_BF16 if bf16 else DVGO_F32, use_shadow=bf16)
+    samp, prm, ref, ro = _oracle(P, bf16=bf16)
+    ref["_samp"] = samp
+    _, g = O.photo_loss(ref["rgb"], P.rays.target)
+    gd, gf, gm = _grads(api, grid, flat, s, out, g, P, bf16)
+    _check_backward(P, prm, ref, ro, gd, gf, gm, g, TOLBF if bf16 else TOL32)
+
+
+def test_render_backward_depth_acc_channels(gpu_lib):
+    from paper_2111_11215_amd import api
+    P = _problem(2, n_rays=1024)
+    grid, flat, s = _gpu(P, morton=False)
+    out = api.render_fwd(grid, flat, s, P.bg)
+    samp, prm, ref, ro = _oracle(P, morton=False)
+    ref["_samp"] = samp
+    rng = np.random.default_rng(3)
+    gR, gD, gA = rng.normal(size=(1024, 3)), rng.normal(size=1024), rng.normal(size=1024)
+    gd, gf, gm = _grads(api, grid, flat, s, out, gR, P, gD=gD, gA=gA)
+    _check_backward(P, prm, ref, ro, gd, gf, gm, gR, TOL32, gD, gA)
+
+
+def test_render_density_only_mode(gpu_lib):
+    """No network: weights, depth, opacity, log T and segment sums only (the
+    proposal's target pass)."""
+    from paper_2111_11215_amd import api
+    P = _problem(3, n_rays=2048)
+    grid, flat, s = _gpu(P)
+    out = api.render_fwd(grid, None, s, P.bg, want_seg_w=True)
+    samp = O.sample_rays(P.rays.o, P.rays.d, P.rays.jitter, P.box_min, P.box_max, P.step, P.max_samples,
+                         morton=True)
+    prm = O.Params(P.density, P.feat, P.Ws, P.bs, P.box_min, P.box_max, P.act_shift)
+    ref = O.render_forward(prm, P.rays.o, P.rays.d, P.rays.jitter, samp, P.step, P.bg, with_color=False)
+    _fwd_keys(out, ref, ("depth", "acc", "log_t_end", "seg_w"), TOL32)
+
+
+def test_render_with_coarse_mask_and_large_values(gpu_lib):
+    """Coarse skipping on, large raw densities (alpha near 1, tiny T) and a
+    shift: forward and backward still at float32 tolerance."""
+    from paper_2111_11215_amd import api
+    P = _problem(4, n_rays=2048, bias=1.5)
+    P.density = (P.density * 6).astype(F32)
+    raw = np.random.default_rng(8).normal(-5, 3, (11, 11, 11)).astype(F32)
+    thr = O.coarse_raw_threshold(1e-3, P.step)
+    bits_ref = O.coarse_cell_bits(raw, thr)
+    bits = api.coarse_mask_build(to_dev(raw), P.box_min, P.box_max, float(thr))
+    grid, flat, s = _gpu(P, coarse=(bits, P.box_min, P.box_max, raw.shape))
+    out = api.render_fwd(grid, flat, s, P.bg)
+    samp, prm, ref, ro = _oracle(P, coarse=(bits_ref, P.box_min, P.box_max, raw.shape))
+    ref["_samp"] = samp
+    _fwd_keys(out, ref, ("rgb", "depth", "acc"), TOL32)
+    _, g = O.photo_loss(ref["rgb"], P.rays.target)
+    gd, gf, gm = _grads(api, grid, flat, s, out, g, P)
+    _check_backward(P, prm, ref, ro, gd, gf, gm, g, TOL32)
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_render_full_size_sampled_rays(gpu_lib, bf16):
+    """Full configuration (160^3 grids with random values, 8192 rays, coarse
+    mask of the sphere scene, launch configuration of the benchmark): the
+    outputs of 256 sampled rays against the oracle on those rays, and the
+    gradients with the loss gradient restricted to those rays, which the
+    oracle then computes exactly."""
+    from paper_2111_11215_amd import api
+    from paper_2111_11215_amd._lib import DVGO_BF16, DVGO_F32
+    P = synth.full_config(0)
+    rng = np.random.default_rng(1)
+    P.density = rng.uniform(-1, 1, P.density.shape).astype(F32)
+    P.feat = rng.uniform(-1, 1, P.feat.shape).astype(F32)
+    P.act_shift = O.low_density_bias(synth.FULL_ALPHA_INIT, 2.0 / 159)
+    raw = P.coarse_raw
+    thr = O.coarse_raw_threshold(synth.FULL_TAU, P.step)
+    bits = api.coarse_mask_build(to_dev(raw), P.box_min, P.box_max, float(thr))
+    bits_ref = O.coarse_cell_bits(raw, thr)
+    grid, flat, s = _gpu(P, coarse=(bits, P.box_min, P.box_max, raw.shape), bf16=bf16)
+    prec = DVGO_BF16 if bf16 else DVGO_F32
+    out = api.render_fwd(grid, flat, s, P.bg, precision=prec, use_shadow=bf16)
+    B = P.rays.o.shape[0]
+    sel = rng.choice(B, 256, replace=False)
+    samp, prm, ref, ro = _oracle(P, coarse=(bits_ref, P.box_min, P.box_max, raw.shape), bf16=bf16, rays=sel,
+                                 morton=False)
+    ref["_samp"] = samp
+    tol = TOLBF if bf16 else TOL32
+    _fwd_keys(out, ref, ("rgb", "depth", "acc", "log_t_end"), tol, sel=sel)
+    g_sub = rng.normal(size=(256, 3)) * 1e-3
+    g = np.zeros((B, 3))
+    g[sel] = g_sub
+    gd, gf, gm = _grads(api, grid, flat, s, out, g, P, bf16)
+    _check_backward(P, prm, ref, ro, gd, gf, gm, g_sub, tol)
+
+
+def test_photo_loss_parity(gpu_lib):
+    from paper_2111_11215_amd import api
+    rng = np.random.default_rng(0)
+    c, t = rng.random((8192, 3)).astype(F32), rng.random((8192, 3)).astype(F32)
+    loss, grad = api.photo_loss(to_dev(c), to_dev(t))
+    L, g = O.photo_loss(c, t)
+    assert abs(float(np_of(loss)[0]) - L) <= 1e-5 * L
+    assert report("grad", np_of(grad), g)[0] <= 1e-6

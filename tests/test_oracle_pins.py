@@ -496,3 +496,50 @@ def test_scene_render_single_sphere_closed_form():
     out = O.scene_render(o, d, c, r, rho, col, [-1] * 3, [1] * 3, 1e-4, np.ones(3), edge=1e-4)
     T = math.exp(-3.0 * 1.0)
     assert np.allclose(out[0], (1 - T) * col[0] + T, atol=2e-4)
+
+
+# ---------------------------------------------------------------------------
+# bfloat16 form of the network
+# ---------------------------------------------------------------------------
+def test_bf16_round_matches_torch():
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.normal(size=10000) * 10 ** rng.uniform(-30, 30, 10000),
+                        np.array([1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -1.0 - 2 ** -8, 0.0, -0.0, 3e38])]).astype(F32)
+    ref = torch.tensor(x).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(O.bf16_round(x), ref)
+
+
+def test_bf16_mlp_equals_exact_on_representable_inputs():
+    """With weights and inputs already bfloat16 values (and ReLU outputs
+    that stay representable because every hidden weight is a power of two
+    times a small integer), the bfloat16 form is the exact network."""
+    rng = np.random.default_rng(1)
+    Ws = [O.bf16_round(rng.normal(size=(128, 39)) * 0.1), O.bf16_round(np.eye(128) * 0.5),
+          O.bf16_round(rng.normal(size=(3, 128)) * 0.1)]
+    bs = [np.zeros(128), np.zeros(128), np.zeros(3)]
+    x = np.concatenate([O.bf16_round(rng.normal(size=(20, 12))), rng.normal(size=(20, 27))], 1)
+    # make layer-1 outputs representable: only one nonzero feature, power-of-two weights there
+    Ws[0][:, 1:] = 0.0
+    Ws[0][:, 0] = 2.0 ** rng.integers(-3, 3, 128)
+    c1, _ = O.mlp_forward(Ws, bs, x, bf16=True)
+    c0, _ = O.mlp_forward(Ws, bs, x, bf16=False)
+    assert np.allclose(c1, c0, rtol=0, atol=1e-15)
+
+
+def test_bf16_backward_close_to_exact():
+    """With the same ReLU masks and activations, the bfloat16 form's
+    gradients differ from the exact network's only by bfloat16 operand
+    rounding (catches dropped terms and transposes)."""
+    rng = np.random.default_rng(2)
+    Ws, bs = synth.xavier_uniform_mlp(rng, (39, 128, 128, 3))
+    x = rng.normal(size=(400, 39))
+    dc = rng.normal(size=(400, 3))
+    c1, m1 = O.mlp_forward(Ws, bs, x, bf16=True)
+    c0, _ = O.mlp_forward(Ws, bs, x, bf16=False)
+    assert np.abs(c1 - c0).max() < 1e-2
+    exact_same_masks = dict(m1, bf16=False)
+    d1, W1g, b1g = O.mlp_backward(Ws, m1, dc)
+    d0, W0g, b0g = O.mlp_backward(Ws, exact_same_masks, dc)
+    assert np.linalg.norm(d1[:, :12] - d0[:, :12]) / np.linalg.norm(d0[:, :12]) < 2e-2
+    for a, b in zip(W1g + b1g, W0g + b0g):
+        assert np.linalg.norm(a - b) / np.linalg.norm(b) < 2e-2
