@@ -54,6 +54,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=256)
     ap.add_argument("--morton", type=int, default=0)
+    ap.add_argument("--profile-steps", type=int, default=10,
+                    help="steps per kernel of the event-timed pass (0: skip it)")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -154,8 +158,52 @@ def cpu_baseline(ctx, rays):
                        f"({t_adam:.2f} s); 1 thread")}
 
 
+def calibrate_copy(mib):
+    """A plain device-to-device copy of known size, to scale the HBM
+    traffic counters (FETCH_SIZE, WRITE_SIZE) of a profiled run."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_mib": mib, "launches": 3}))
+
+
+def roofline(args, model, batches, per_kernel, kname, n_prof, bf16):
+    """Achieved rate of the named kernel: algorithmic work per launch over
+    its event-timed average launch duration."""
+    kept_prof = sum(batches[(args.warmup + i) % len(batches)]["n_kept"] for i in range(n_prof)) / n_prof
+    k = per_kernel[kname]
+    # launches per step of the named kernel
+    lps = k["launches"] / n_prof
+    if kname in ("mlp_bwd", "mlp_fwd"):
+        flop = (FLOP_MLP_BWD if kname == "mlp_bwd" else FLOP_MLP_FWD) * kept_prof / lps
+        achieved = flop / (k["ms_avg"] * 1e-3) / 1e12
+        peak = PEAK["bf16" if bf16 else "f32"]
+        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": None}
+    else:
+        per = {"scatter": BYTES_SCATTER, "gather": BYTES_GATHER_BF16 if bf16 else BYTES_GATHER_F32}.get(kname)
+        if kname == "adam":
+            nparam = model.st_density.p.numel() + model.st_feat.p.numel() + model.st_mlp.p.numel()
+            bytes_ = (32 * nparam + (2 * model.st_feat.p.numel() if bf16 else 0)) / lps
+        else:
+            bytes_ = per * kept_prof / lps
+        achieved = bytes_ / (k["ms_avg"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm"], "unit": "GB/s",
+                "frac": achieved / PEAK["hbm"], "traffic": None}
+    roof["kernel"] = kname
+    roof["launch_ms"] = k["ms_avg"]
+    return roof
+
+
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build measures one GPU only: the training step is data-parallel over "
@@ -187,38 +235,23 @@ def main():
     bf16 = args.form == "bf16"
     kname = args.profile_kernel if args.profile_kernel != "auto" else "mlp_bwd"
     per_kernel = {}
-    for name in ("gather", "mlp_fwd", "compose_fwd", "compose_bwd", "mlp_bwd", "scatter", "adam", "fill_kept",
-                 "count_kept", "ray_setup", "reduce"):
+    names = ("gather", "mlp_fwd", "compose_fwd", "compose_bwd", "mlp_bwd", "scatter", "bin_count", "cell_scan",
+             "bin_place", "adam", "fill_kept", "count_kept", "ray_setup", "scan", "reduce", "pack", "ray_base",
+             "photo_loss")
+    n_prof = min(args.steps, args.profile_steps)
+    for name in names if n_prof > 0 else ():
         _lib.check("dvgo_profile_enable", lib.dvgo_profile_enable(_lib.KERNEL_IDS[name]))
-        run_steps(model, batches, args.warmup, min(args.steps, 10))
+        run_steps(model, batches, args.warmup, n_prof)
         tot = ctypes_double()
         cnt = ctypes_int64()
         _lib.check("dvgo_profile_read", lib.dvgo_profile_read(tot, cnt))
         per_kernel[name] = {"ms_total": tot.value, "launches": cnt.value,
                             "ms_avg": tot.value / max(cnt.value, 1)}
     lib.dvgo_profile_enable(-1)
-    n_prof = min(args.steps, 10)
-    kept_prof = sum(batches[(args.warmup + i) % len(batches)]["n_kept"] for i in range(n_prof)) / n_prof
-    k = per_kernel[kname]
-    # launches per step of the named kernel
-    lps = k["launches"] / n_prof
-    if kname in ("mlp_bwd", "mlp_fwd"):
-        flop = (FLOP_MLP_BWD if kname == "mlp_bwd" else FLOP_MLP_FWD) * kept_prof / lps
-        achieved = flop / (k["ms_avg"] * 1e-3) / 1e12
-        peak = PEAK["bf16" if bf16 else "f32"]
-        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": None}
-    else:
-        per = {"scatter": BYTES_SCATTER, "gather": BYTES_GATHER_BF16 if bf16 else BYTES_GATHER_F32}.get(kname)
-        if kname == "adam":
-            nparam = model.st_density.p.numel() + model.st_feat.p.numel() + model.st_mlp.p.numel()
-            bytes_ = (32 * nparam + (2 * model.st_feat.p.numel() if bf16 else 0)) / lps
-        else:
-            bytes_ = per * kept_prof / lps
-        achieved = bytes_ / (k["ms_avg"] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm"], "unit": "GB/s",
-                "frac": achieved / PEAK["hbm"], "traffic": None}
-    roof["kernel"] = kname
+    out_extra = {}
+    if n_prof > 0:
+        out_extra["roofline"] = roofline(args, model, batches, per_kernel, kname, n_prof, bf16)
+        out_extra["kernels_ms_per_step"] = {n_: v["ms_total"] / n_prof for n_, v in per_kernel.items()}
     out = {
         "metric": "fwd+bwd ray-samples/s per train iter",
         "value": value,
@@ -241,9 +274,8 @@ def main():
         "evaluated_samples_per_step": total_kept / args.steps,
         "uniform_samples_per_step": total_uniform / args.steps,
         "rays_per_s": args.rays * args.steps / elapsed,
-        "kernels_ms_per_step": {n_: v["ms_total"] / n_prof for n_, v in per_kernel.items()},
-        "roofline": roof,
     }
+    out.update(out_extra)
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(ctx, args.cpu_rays)

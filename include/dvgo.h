@@ -171,8 +171,10 @@ int32_t dvgo_sample_rays(const float* rays_o, const float* rays_d, const float* 
  * n_kept: the device count written by dvgo_sample_rays; samples beyond
  *   min(n_kept, capacity) are ignored.
  * bg: host float[3].
- * workspace: dvgo_render_workspace_bytes(B, capacity, channels) bytes. */
-size_t dvgo_render_workspace_bytes(int32_t B, int64_t capacity, int32_t channels);
+ * workspace: dvgo_render_workspace_bytes(B, capacity, channels, &field.box)
+ *   bytes (0 for an unsupported channel count or an invalid box). */
+size_t dvgo_render_workspace_bytes(int32_t B, int64_t capacity, int32_t channels,
+                                   const dvgo_box* grid /*host*/);
 int32_t dvgo_render_fwd(const dvgo_field* field /*host*/, const dvgo_mlp* mlp /*host or NULL*/,
                         const float* rays_o, const float* rays_d, const float* jitter,
                         const float* t_near, const int32_t* n_uniform, const int32_t* perm,
@@ -193,8 +195,10 @@ int32_t dvgo_render_fwd(const dvgo_field* field /*host*/, const dvgo_mlp* mlp /*
  * Gradients are ACCUMULATED (+=) into grad_density [nx][ny][nz],
  * grad_feat [nx][ny][nz][C] (float32 whatever feat_dtype is) and grad_mlp
  * (flat, dvgo_mlp_param_count values; may be NULL with mlp == NULL).
- * Grid gradients use float atomics: their summation order, and so their
- * last bits, vary from run to run.  Same workspace as dvgo_render_fwd. */
+ * Grid gradients: samples are binned by fine cell and each grid vertex sums
+ * its neighbouring samples' contributions (no float atomics); the order of
+ * samples within a cell, and so the last bits of a sum, may vary from run to
+ * run.  Same workspace as dvgo_render_fwd. */
 int32_t dvgo_render_bwd(const dvgo_field* field /*host*/, const dvgo_mlp* mlp /*host or NULL*/,
                         const float* rays_o, const float* rays_d, const float* jitter,
                         const float* t_near, const int32_t* n_uniform, const int32_t* perm,
@@ -268,9 +272,10 @@ int32_t dvgo_version(void);
  * the last dvgo_profile_enable.  kernel_id -1 turns timing off.  Ids:
  *   0 ray setup, 1 Morton sort, 2 count kept, 3 scan, 4 fill kept,
  *   5 coarse mask, 6 weight pack, 7 per-ray encoding, 8 gather, 9 MLP forward,
- *   10 compose forward, 11 compose backward, 12 MLP backward, 13 scatter,
- *   14 partial reduce, 15 photo loss, 16 Adam, 17 proposal forward,
- *   18 proposal backward, 19 proposal reduce, 20 scene render. */
+ *   10 compose forward, 11 compose backward, 12 MLP backward, 13 vertex
+ *   gather (gradient scatter), 14 partial reduce, 15 photo loss, 16 Adam,
+ *   17 proposal forward, 18 proposal backward, 19 proposal reduce, 20 scene
+ *   render, 21 cell binning count, 22 cell scan, 23 cell binning place. */
 int32_t dvgo_profile_enable(int32_t kernel_id);
 int32_t dvgo_profile_read(double* total_ms, int64_t* launches);
 

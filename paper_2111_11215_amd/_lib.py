@@ -53,7 +53,7 @@ SIGNATURES = {
     "dvgo_sample_workspace_bytes": (c_size_t, [c_int32]),
     "dvgo_sample_rays": (c_int32, [P, P, P, c_int32, POINTER(Box), c_float, c_int32, P, POINTER(Box), P, c_int32,
                                    P, P, P, P, P, P, P, P, c_int64, P, P, c_size_t, P]),
-    "dvgo_render_workspace_bytes": (c_size_t, [c_int32, c_int64, c_int32]),
+    "dvgo_render_workspace_bytes": (c_size_t, [c_int32, c_int64, c_int32, POINTER(Box)]),
     "dvgo_render_fwd": (c_int32, [POINTER(Field), POINTER(Mlp), P, P, P, P, P, P, P, P, P, P, c_int64, c_int32,
                                   c_float, POINTER(c_float), P, P, P, P, P, P, P, c_size_t, P]),
     "dvgo_render_bwd": (c_int32, [POINTER(Field), POINTER(Mlp), P, P, P, P, P, P, P, P, P, P, c_int64, c_int32,
@@ -75,7 +75,7 @@ SIGNATURES = {
 KERNEL_IDS = {name: i for i, name in enumerate([
     "ray_setup", "morton_sort", "count_kept", "scan", "fill_kept", "coarse_mask", "pack", "ray_base", "gather",
     "mlp_fwd", "compose_fwd", "compose_bwd", "mlp_bwd", "scatter", "reduce", "photo_loss", "adam", "prop_fwd",
-    "prop_bwd", "prop_reduce", "scene"])}
+    "prop_bwd", "prop_reduce", "scene", "bin_count", "cell_scan", "bin_place"])}
 
 _lib = None
 

@@ -237,7 +237,7 @@ def render_fwd(grid: Grid, mlp_flat: Optional[torch.Tensor], s: Samples, bg=(1.0
         "seg_w": torch.empty((B, NSEG), dtype=torch.float32, device=dev) if want_seg_w else None,
         "sample_w": torch.empty(max(s.capacity, 1), dtype=torch.float32, device=dev) if want_sample_w else None,
     }
-    nws = lib.dvgo_render_workspace_bytes(B, s.capacity, CHANNELS)
+    nws = lib.dvgo_render_workspace_bytes(B, s.capacity, CHANNELS, ctypes.byref(field.box))
     ws = workspace(nws, dev)
     check("dvgo_render_fwd", lib.dvgo_render_fwd(
         ctypes.byref(field), ctypes.byref(mlp) if mlp is not None else None, _ptr(s.rays_o), _ptr(s.rays_d),
@@ -257,7 +257,7 @@ def render_bwd(grid: Grid, mlp_flat: Optional[torch.Tensor], s: Samples, log_t_e
     dev = s.rays_o.device
     field = grid.field(use_shadow)
     mlp = mlp_struct(mlp_flat, precision) if mlp_flat is not None else None
-    nws = lib.dvgo_render_workspace_bytes(s.B, s.capacity, CHANNELS)
+    nws = lib.dvgo_render_workspace_bytes(s.B, s.capacity, CHANNELS, ctypes.byref(field.box))
     ws = workspace(nws, dev)
     check("dvgo_render_bwd", lib.dvgo_render_bwd(
         ctypes.byref(field), ctypes.byref(mlp) if mlp is not None else None, _ptr(s.rays_o), _ptr(s.rays_d),

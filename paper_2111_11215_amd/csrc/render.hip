@@ -26,10 +26,13 @@ namespace {
 constexpr int kMaxBwdBlocks = 256;
 
 struct WsLayout {
-    size_t base, pe, w1p, w2p, w2tp, w1pb, w2pb, w2tpb, raw, feat, col, partial, total;
+    size_t base, pe, w1p, w2p, w2tp, w1pb, w2pb, w2tpb, raw, feat, col, partial, cell_count, cell_start, scan_tmp,
+        cell_rank, rec, total;
 };
 
-WsLayout ws_layout(int64_t B, int64_t cap) {
+constexpr int kScanPer = 8192;   // elements per block of the device-wide scan
+
+WsLayout ws_layout(int64_t B, int64_t cap, int64_t ncell) {
     WsLayout L;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -49,6 +52,11 @@ WsLayout ws_layout(int64_t B, int64_t cap) {
     L.feat = take(static_cast<size_t>(cap) * kC * 4);
     L.col = take(static_cast<size_t>(cap) * 4 * 4);
     L.partial = take(static_cast<size_t>(kMaxBwdBlocks) * kPStride * 4);
+    L.cell_count = take(static_cast<size_t>(ncell + 1) * 4);
+    L.cell_start = take(static_cast<size_t>(ncell + 1) * 4);
+    L.scan_tmp = take(static_cast<size_t>((ncell + 1 + kScanPer - 1) / kScanPer + 1) * 8);
+    L.cell_rank = take(static_cast<size_t>(cap) * 8);
+    L.rec = take(static_cast<size_t>(cap) * 64);
     L.total = off;
     return L;
 }
@@ -390,53 +398,229 @@ __global__ __launch_bounds__(256) void compose_bwd_kernel(ComposeArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// scatter: transpose of the trilinear gathers into the float32 gradients
+// scatter: transpose of the trilinear gathers, without float atomics.
+// Samples are counting-sorted by fine cell (one integer atomic per run of
+// equal cells in a wavefront), then one thread per grid vertex sums the
+// contributions of the samples in its 8 neighbouring cells and adds them to
+// the gradient with a plain read-modify-write.
 // ---------------------------------------------------------------------------
-struct ScatterArgs {
+struct BinArgs {
     SampleArgs sa;
     GridArgs g;
     const int64_t* n_kept;
     int64_t cap;
-    const float* draw;
-    const float* dfeat;
+    int* cell_count;       // [ncell + 1]
+    const int* cell_start; // [ncell + 1]
+    int2* cell_rank;       // [cap] (cell, rank within cell)
+    const float* draw;     // [cap]
+    const float* dfeat;    // [cap][12] or null
+    float4* rec;           // [cap][4]: (fx, fy, fz, draw), df[0..11]
     float* grad_density;
     float* grad_feat;
+    int64_t ncell;
 };
 
-__global__ __launch_bounds__(256) void scatter_kernel(ScatterArgs a) {
+__device__ __forceinline__ int cell_of(const GridArgs& g, const float x[3], float f[3]) {
+    int i0[3];
+    for (int i = 0; i < 3; ++i) {
+        const float u = (x[i] - g.mn[i]) * g.scale[i];
+        const float fl = fminf(fmaxf(floorf(u), 0.0f), static_cast<float>(g.n[i] - 2));
+        i0[i] = static_cast<int>(fl);
+        f[i] = fminf(fmaxf(u - fl, 0.0f), 1.0f);
+    }
+    return (i0[0] * (g.n[1] - 1) + i0[1]) * (g.n[2] - 1) + i0[2];
+}
+
+__global__ __launch_bounds__(256) void fill_int_kernel(int* __restrict__ p, int64_t n, int v) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        p[i] = v;
+}
+
+// Per sample: its cell and its rank among the cell's samples.  Lanes hold
+// consecutive samples, so equal cells form runs; each run's first lane adds
+// the run length with one atomic and the run shares the returned base.
+__global__ __launch_bounds__(256) void bin_count_kernel(BinArgs a) {
+    const int64_t n = live_count(a.n_kept, a.cap);
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t base = static_cast<int64_t>(blockIdx.x) * blockDim.x + (threadIdx.x & ~63); base < n;
+         base += stride) {
+        const int64_t s = base + lane;
+        const bool ok = s < n;
+        int cell = -1;
+        if (ok) {
+            float x[3], f[3];
+            sample_point(a.sa, a.sa.sample_ray[s], a.sa.sample_k[s], x, nullptr);
+            cell = cell_of(a.g, x, f);
+        }
+        const int prev = __shfl_up(cell, 1, 64);
+        const bool head = !ok || lane == 0 || prev != cell;
+        const uint64_t heads = __ballot(head);
+        const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1);
+        const uint64_t le = heads & upto;
+        const int leader = 63 - __clzll(static_cast<long long>(le));
+        const uint64_t gt = heads & ~upto;
+        const int next = gt ? __ffsll(static_cast<long long>(gt)) - 1 : 64;
+        int rbase = 0;
+        if (ok && lane == leader) rbase = atomicAdd(a.cell_count + cell, next - lane);
+        rbase = __shfl(rbase, leader, 64);
+        if (ok) a.cell_rank[s] = make_int2(cell, rbase + lane - leader);
+    }
+}
+
+__global__ __launch_bounds__(256) void bin_place_kernel(BinArgs a) {
     const int64_t n = live_count(a.n_kept, a.cap);
     for (int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; s < n;
          s += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const int r = a.sa.sample_ray[s];
-        const int k = a.sa.sample_k[s];
-        float x[3];
-        sample_point(a.sa, r, k, x, nullptr);
-        const Tri t = trilinear(a.g, x);
-        const float dr = a.draw[s];
-        if (dr != 0.0f)
-            for (int c = 0; c < 8; ++c) unsafeAtomicAdd(a.grad_density + corner(t, c), t.w[c] * dr);
-        if (!a.dfeat) continue;
-        float f[kC];
-        const float4* in = reinterpret_cast<const float4*>(a.dfeat + s * kC);
-        const float4 q0 = in[0], q1 = in[1], q2 = in[2];
-        f[0] = q0.x; f[1] = q0.y; f[2] = q0.z; f[3] = q0.w;
-        f[4] = q1.x; f[5] = q1.y; f[6] = q1.z; f[7] = q1.w;
-        f[8] = q2.x; f[9] = q2.y; f[10] = q2.z; f[11] = q2.w;
-        for (int c = 0; c < 8; ++c) {
-            float* dst = a.grad_feat + corner(t, c) * kC;
-            const float w = t.w[c];
-            for (int ch = 0; ch < kC; ++ch) unsafeAtomicAdd(dst + ch, w * f[ch]);
+        float x[3], f[3];
+        sample_point(a.sa, a.sa.sample_ray[s], a.sa.sample_k[s], x, nullptr);
+        cell_of(a.g, x, f);
+        const int2 cr = a.cell_rank[s];
+        const int64_t pos = static_cast<int64_t>(a.cell_start[cr.x]) + cr.y;
+        float4* r = a.rec + pos * 4;
+        r[0] = make_float4(f[0], f[1], f[2], a.draw[s]);
+        if (a.dfeat) {
+            const float4* df = reinterpret_cast<const float4*>(a.dfeat + s * kC);
+            r[1] = df[0];
+            r[2] = df[1];
+            r[3] = df[2];
         }
     }
 }
 
-// Deterministic sum of the per-block weight-gradient partials (+= into out).
-__global__ void reduce_partials_kernel(const float* __restrict__ partial, int nblk, float* __restrict__ out) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= kMlpParams) return;
+// One thread per vertex (i,j,k): corner (dx,dy,dz) of cell (i-dx, j-dy, k-dz).
+__global__ __launch_bounds__(256) void vertex_gather_kernel(BinArgs a) {
+    const int nx = a.g.n[0], ny = a.g.n[1], nz = a.g.n[2];
+    const int64_t nv = static_cast<int64_t>(nx) * ny * nz;
+    const int cy = ny - 1, cz = nz - 1;
+    const bool feat = a.dfeat != nullptr;
+    for (int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; v < nv;
+         v += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int k = static_cast<int>(v % nz);
+        const int j = static_cast<int>((v / nz) % ny);
+        const int i = static_cast<int>(v / (static_cast<int64_t>(nz) * ny));
+        float acc[13];
+        #pragma unroll
+        for (int q = 0; q < 13; ++q) acc[q] = 0.0f;
+        bool any = false;
+        #pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int dx = (c >> 2) & 1, dy = (c >> 1) & 1, dz = c & 1;
+            const int ci = i - dx, cj = j - dy, ck = k - dz;
+            if (ci < 0 || cj < 0 || ck < 0 || ci >= nx - 1 || cj >= cy || ck >= cz) continue;
+            const int cell = (ci * cy + cj) * cz + ck;
+            const int p0 = a.cell_start[cell], p1 = a.cell_start[cell + 1];
+            for (int p = p0; p < p1; ++p) {
+                const float4* r = a.rec + static_cast<int64_t>(p) * 4;
+                const float4 h = r[0];
+                const float w = (dx ? h.x : 1.0f - h.x) * (dy ? h.y : 1.0f - h.y) * (dz ? h.z : 1.0f - h.z);
+                acc[0] += w * h.w;
+                if (feat) {
+                    const float4 q0 = r[1], q1 = r[2], q2 = r[3];
+                    acc[1] += w * q0.x; acc[2] += w * q0.y; acc[3] += w * q0.z; acc[4] += w * q0.w;
+                    acc[5] += w * q1.x; acc[6] += w * q1.y; acc[7] += w * q1.z; acc[8] += w * q1.w;
+                    acc[9] += w * q2.x; acc[10] += w * q2.y; acc[11] += w * q2.z; acc[12] += w * q2.w;
+                }
+                any = true;
+            }
+        }
+        if (!any) continue;
+        a.grad_density[v] += acc[0];
+        if (feat) {
+            float4* gf = reinterpret_cast<float4*>(a.grad_feat + v * kC);
+            float4 g0 = gf[0], g1 = gf[1], g2 = gf[2];
+            g0.x += acc[1]; g0.y += acc[2]; g0.z += acc[3]; g0.w += acc[4];
+            g1.x += acc[5]; g1.y += acc[6]; g1.z += acc[7]; g1.w += acc[8];
+            g2.x += acc[9]; g2.y += acc[10]; g2.z += acc[11]; g2.w += acc[12];
+            gf[0] = g0;
+            gf[1] = g1;
+            gf[2] = g2;
+        }
+    }
+}
+
+// Device-wide exclusive scan of int32 counts in three passes.
+__device__ __forceinline__ int block_excl_scan_1024(int v, int* sh, int* total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int incl = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) sh[wave] = incl;
+    __syncthreads();
+    int woff = 0, tot = 0;
+    for (int w = 0; w < 16; ++w) {
+        if (w < wave) woff += sh[w];
+        tot += sh[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return woff + incl - v;
+}
+
+__global__ __launch_bounds__(1024) void scan_block_sums_kernel(const int* __restrict__ in, int64_t n,
+                                                               long long* __restrict__ bsum) {
+    __shared__ int sh[16];
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanPer + threadIdx.x * 8;
+    int v = 0;
+    for (int u = 0; u < 8; ++u)
+        if (base + u < n) v += in[base + u];
+    int tot;
+    block_excl_scan_1024(v, sh, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void scan_bsum_kernel(long long* __restrict__ bsum, int nb) {
+    __shared__ long long carry;
+    __shared__ int sh[16];
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int b0 = 0; b0 < nb; b0 += 1024) {
+        const int b = b0 + threadIdx.x;
+        const int v = b < nb ? static_cast<int>(bsum[b]) : 0;
+        int tot;
+        const int ex = block_excl_scan_1024(v, sh, &tot);
+        if (b < nb) bsum[b] = carry + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += tot;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(1024) void scan_apply_kernel(const int* __restrict__ in, int64_t n,
+                                                          const long long* __restrict__ bsum, int* __restrict__ out) {
+    __shared__ int sh[16];
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanPer + threadIdx.x * 8;
+    int v[8];
+    int loc = 0;
+    for (int u = 0; u < 8; ++u) {
+        v[u] = base + u < n ? in[base + u] : 0;
+        loc += v[u];
+    }
+    int tot;
+    int run = static_cast<int>(bsum[blockIdx.x]) + block_excl_scan_1024(loc, sh, &tot);
+    for (int u = 0; u < 8; ++u) {
+        if (base + u < n) out[base + u] = run;
+        run += v[u];
+    }
+}
+
+// Deterministic sum of the per-block weight-gradient partials (+= into out):
+// 64 parameters per workgroup, each of the 4 waves sums every 4th partial,
+// then the 4 wave sums are added in a fixed order.
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const float* __restrict__ partial, int nblk,
+                                                              float* __restrict__ out) {
+    __shared__ float sh[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int p = blockIdx.x * 64 + lane;
     float s = 0.0f;
-    for (int b = 0; b < nblk; ++b) s += partial[static_cast<int64_t>(b) * kPStride + p];
-    out[p] += s;
+    if (p < kMlpParams)
+        for (int b = wave; b < nblk; b += 4) s += partial[static_cast<int64_t>(b) * kPStride + p];
+    sh[wave][lane] = s;
+    __syncthreads();
+    if (wave == 0 && p < kMlpParams) out[p] += (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
 }
 
 // ---------------------------------------------------------------------------
@@ -468,7 +652,8 @@ int32_t validate(const dvgo_field* field, const dvgo_mlp* mlp, const float* rays
     if (B > 0 && (!rays_o || !rays_d || !t_near || !n_uniform || !perm || !ray_offset)) return DVGO_E_ARG;
     if (!n_kept) return DVGO_E_ARG;
     if (capacity > 0 && (!sample_ray || !sample_k)) return DVGO_E_ARG;
-    if (workspace_bytes < dvgo_render_workspace_bytes(B, capacity, kC) || (!workspace && workspace_bytes))
+    if (workspace_bytes < dvgo_render_workspace_bytes(B, capacity, kC, &field->box) ||
+        (!workspace && workspace_bytes))
         return DVGO_E_CAPACITY;
     return DVGO_OK;
 }
@@ -568,6 +753,10 @@ ComposeArgs make_compose(const Common& cm, const int32_t* perm, const int32_t* r
     return ca;
 }
 
+int64_t cell_count_of(const dvgo_box& b) {
+    return static_cast<int64_t>(b.n[0] - 1) * (b.n[1] - 1) * (b.n[2] - 1);
+}
+
 Common make_common(const dvgo_field* field, const float* rays_o, const float* rays_d, const float* jitter,
                    const float* t_near, const int32_t* sample_ray, const int32_t* sample_k, int64_t capacity,
                    int32_t B, float step, void* workspace) {
@@ -580,11 +769,48 @@ Common make_common(const dvgo_field* field, const float* rays_o, const float* ra
     cm.sa.sample_k = sample_k;
     cm.sa.step = step;
     cm.g = dvgo::make_grid(field->box);
-    cm.L = ws_layout(B, capacity);
+    cm.L = ws_layout(B, capacity, cell_count_of(field->box));
     cm.ws = static_cast<char*>(workspace);
     cm.cap = capacity;
     cm.B = B;
     return cm;
+}
+
+int32_t run_scatter(const Common& cm, const dvgo_field* field, bool with_feat, const int64_t* n_kept,
+                    float* grad_density, float* grad_feat, hipStream_t s) {
+    BinArgs ba;
+    ba.sa = cm.sa;
+    ba.g = cm.g;
+    ba.n_kept = n_kept;
+    ba.cap = cm.cap;
+    ba.ncell = cell_count_of(field->box);
+    ba.cell_count = reinterpret_cast<int*>(cm.ws + cm.L.cell_count);
+    ba.cell_start = reinterpret_cast<const int*>(cm.ws + cm.L.cell_start);
+    ba.cell_rank = reinterpret_cast<int2*>(cm.ws + cm.L.cell_rank);
+    ba.draw = reinterpret_cast<const float*>(cm.ws + cm.L.raw);
+    ba.dfeat = with_feat ? reinterpret_cast<const float*>(cm.ws + cm.L.feat) : nullptr;
+    ba.rec = reinterpret_cast<float4*>(cm.ws + cm.L.rec);
+    ba.grad_density = grad_density;
+    ba.grad_feat = grad_feat;
+    const int cus = dvgo::device_cu_count();
+    const int64_t nc1 = ba.ncell + 1;
+    DVGO_LAUNCH(K_CELL_SCAN, fill_int_kernel, dim3(grid_for(nc1, 256, cus * 8)), dim3(256), 0, s, ba.cell_count, nc1,
+                0);
+    if (int32_t st = dvgo::launch_status()) return st;
+    DVGO_LAUNCH(K_BIN_COUNT, bin_count_kernel, dim3(grid_for(cm.cap, 256, cus * 16)), dim3(256), 0, s, ba);
+    if (int32_t st = dvgo::launch_status()) return st;
+    const int nb = static_cast<int>((nc1 + kScanPer - 1) / kScanPer);
+    long long* bsum = reinterpret_cast<long long*>(cm.ws + cm.L.scan_tmp);
+    DVGO_LAUNCH(K_CELL_SCAN, scan_block_sums_kernel, dim3(nb), dim3(1024), 0, s, ba.cell_count, nc1, bsum);
+    DVGO_LAUNCH(K_CELL_SCAN, scan_bsum_kernel, dim3(1), dim3(1024), 0, s, bsum, nb);
+    DVGO_LAUNCH(K_CELL_SCAN, scan_apply_kernel, dim3(nb), dim3(1024), 0, s, ba.cell_count, nc1, bsum,
+                reinterpret_cast<int*>(cm.ws + cm.L.cell_start));
+    if (int32_t st = dvgo::launch_status()) return st;
+    DVGO_LAUNCH(K_BIN_PLACE, bin_place_kernel, dim3(grid_for(cm.cap, 256, cus * 16)), dim3(256), 0, s, ba);
+    if (int32_t st = dvgo::launch_status()) return st;
+    const int64_t nv = static_cast<int64_t>(field->box.n[0]) * field->box.n[1] * field->box.n[2];
+    DVGO_LAUNCH(K_SCATTER, vertex_gather_kernel, dim3(grid_for(nv, 256, cus * 16)), dim3(256), 0, s, ba);
+    return dvgo::launch_status();
 }
 
 }  // namespace
@@ -597,9 +823,9 @@ int64_t dvgo_mlp_param_count(int32_t channels, int32_t hidden) {
     return hidden * in + hidden + static_cast<int64_t>(hidden) * hidden + hidden + 3LL * hidden + 3;
 }
 
-size_t dvgo_render_workspace_bytes(int32_t B, int64_t capacity, int32_t channels) {
-    if (B < 0 || capacity < 0 || channels != kC) return 0;
-    return ws_layout(B, capacity).total;
+size_t dvgo_render_workspace_bytes(int32_t B, int64_t capacity, int32_t channels, const dvgo_box* grid) {
+    if (B < 0 || capacity < 0 || channels != kC || !dvgo::box_ok(grid, 2)) return 0;
+    return ws_layout(B, capacity, cell_count_of(*grid)).total;
 }
 
 int32_t dvgo_render_fwd(const dvgo_field* field, const dvgo_mlp* mlp, const float* rays_o, const float* rays_d,
@@ -674,20 +900,9 @@ int32_t dvgo_render_bwd(const dvgo_field* field, const dvgo_mlp* mlp, const floa
         launch_mlp_bwd(ma, nblk, s);
         if (int32_t st = dvgo::launch_status()) return st;
     }
-    ScatterArgs sc;
-    sc.sa = cm.sa;
-    sc.g = cm.g;
-    sc.n_kept = n_kept;
-    sc.cap = capacity;
-    sc.draw = reinterpret_cast<const float*>(cm.ws + cm.L.raw);
-    sc.dfeat = mlp ? reinterpret_cast<const float*>(cm.ws + cm.L.feat) : nullptr;
-    sc.grad_density = grad_density;
-    sc.grad_feat = grad_feat;
-    const int blocks = grid_for(capacity, 256, dvgo::device_cu_count() * 16);
-    DVGO_LAUNCH(K_SCATTER, scatter_kernel, dim3(blocks), dim3(256), 0, s, sc);
-    if (int32_t st = dvgo::launch_status()) return st;
+    if (int32_t st = run_scatter(cm, field, mlp != nullptr, n_kept, grad_density, grad_feat, s)) return st;
     if (mlp) {
-        DVGO_LAUNCH(K_REDUCE, reduce_partials_kernel, dim3((kMlpParams + 255) / 256), dim3(256), 0, s,
+        DVGO_LAUNCH(K_REDUCE, reduce_partials_kernel, dim3((kMlpParams + 63) / 64), dim3(256), 0, s,
                            reinterpret_cast<const float*>(cm.ws + cm.L.partial), nblk, grad_mlp);
         if (int32_t st = dvgo::launch_status()) return st;
     }

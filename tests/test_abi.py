@@ -48,8 +48,11 @@ def test_param_counts(lib):
 
 def test_workspace_queries(lib):
     assert lib.dvgo_sample_workspace_bytes(8192) >= 8192 * 8
-    assert lib.dvgo_render_workspace_bytes(8192, 8192 * 552, 12) >= 8192 * 552 * 64
-    assert lib.dvgo_render_workspace_bytes(8192, 100, 11) == 0
+    from paper_2111_11215_amd import _lib
+    g = _lib.make_box((-1, -1, -1), (1, 1, 1), (160, 160, 160))
+    assert lib.dvgo_render_workspace_bytes(8192, 8192 * 552, 12, ctypes.byref(g)) >= 8192 * 552 * 128
+    assert lib.dvgo_render_workspace_bytes(8192, 100, 11, ctypes.byref(g)) == 0
+    assert lib.dvgo_render_workspace_bytes(8192, 100, 12, None) == 0
     assert lib.dvgo_proposal_workspace_bytes(1024) > 0
 
 
