@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--morton", type=int, default=0)
     ap.add_argument("--profile-steps", type=int, default=10,
                     help="steps per kernel of the event-timed pass (0: skip it)")
+    ap.add_argument("--compare-iters", type=int, default=1000,
+                    help="iterations of the plain-fp32 / bf16 / bf16+proposal training comparison (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -105,13 +107,123 @@ def setup(args):
         bt["n_uniform"] = int(s.n_uniform.sum().item())
         bt["n_kept"] = int(s.n_kept.item())
     return dict(model=model, batches=batches, step=step, max_samples=max_samples, b=b, raw=raw, bits=bits,
-                coarse=coarse, spheres=sp, bmin=bmin, bmax=bmax, n=n)
+                coarse=coarse, spheres=sp, spheres_t=spheres, bmin=bmin, bmax=bmax, n=n, cams=cams, held=held)
 
 
 def run_steps(model, batches, k0, k):
     for i in range(k):
         bt = batches[(k0 + i) % len(batches)]
         model.train_step(bt["o"], bt["d"], bt["target"], bt["j"])
+
+
+def make_batches(ctx, n_iter, rays, seed0=1000):
+    """Per-iteration batches (pixels with replacement, then jitter, from
+    default_rng(seed0 + t)) with targets rendered by the scene generator."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2111_11215_amd import api, experiment
+    cams = ctx["cams"]
+    flats, jits = [], []
+    for t in range(n_iter):
+        rng = np.random.default_rng(seed0 + t)
+        flats.append(rng.integers(0, len(cams) * 800 * 800, size=rays))
+        jits.append(rng.random(rays).astype(np.float32))
+    o, d, *_ = synth.scenes._rays_for_flat_pixels(cams, 800, 800, 1000.0, np.concatenate(flats))
+    dev = torch.device("cuda:0")
+    ot, dt = torch.as_tensor(o).to(dev), torch.as_tensor(d).to(dev)
+    jt = torch.as_tensor(np.concatenate(jits)).to(dev)
+    tgt = api.scene_render(ot, dt, ctx["spheres_t"], ctx["bmin"], ctx["bmax"], ctx["step"] / 4)
+    return [experiment.Batch(ot[t * rays:(t + 1) * rays], dt[t * rays:(t + 1) * rays],
+                             jt[t * rays:(t + 1) * rays], tgt[t * rays:(t + 1) * rays]) for t in range(n_iter)]
+
+
+def make_views(ctx):
+    """The 10 held-out 800x800 views and their scene renders."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2111_11215_amd import api, experiment
+    dev = torch.device("cuda:0")
+    views = []
+    for c in ctx["held"]:
+        o, d = synth.scenes.image_rays(c, 800, 800, 1000.0)
+        ot = torch.as_tensor(np.ascontiguousarray(o)).to(dev).contiguous()
+        dt = torch.as_tensor(np.ascontiguousarray(d)).to(dev).contiguous()
+        views.append(experiment.View(ot, dt, api.scene_render(ot, dt, ctx["spheres_t"], ctx["bmin"], ctx["bmax"],
+                                                              ctx["step"] / 4)))
+    return views
+
+
+def new_model(ctx, bf16):
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2111_11215_amd import api, train
+    from paper_2111_11215_amd._lib import DVGO_BF16, DVGO_F32
+    dev = torch.device("cuda:0")
+    n = ctx["n"]
+    Ws, bs = synth.xavier_uniform_mlp(np.random.default_rng(7), (39, 128, 128, 3))
+    flat = api.flat_from([Ws[0], bs[0], Ws[1], bs[1], Ws[2], bs[2]], api.MLP_SHAPES, dev)
+    cfg = train.FineConfig(step=ctx["step"], max_samples=ctx["max_samples"],
+                           precision=DVGO_BF16 if bf16 else DVGO_F32, bf16_feat=bf16)
+    return train.FineModel(torch.zeros((n, n, n), device=dev), torch.zeros((n, n, n, 12), device=dev), flat,
+                           ctx["bmin"], ctx["bmax"], ctx["b"], cfg, coarse=ctx["coarse"])
+
+
+def new_proposal(ctx):
+    import numpy as np
+
+    import synth
+    from paper_2111_11215_amd import api, train
+    Ws, bs = synth.xavier_uniform_mlp(np.random.default_rng(11), (54, 64, 64, 32))
+    flat = api.flat_from([Ws[0], bs[0], Ws[1], bs[1], Ws[2], bs[2]], api.PROP_SHAPES, "cuda:0")
+    return train.ProposalModel(flat, ctx["bmin"], ctx["bmax"])
+
+
+def compare_forms(ctx, iters, rays):
+    """Train the plain fp32 form, the bf16 form and the bf16 + learned
+    proposal form from identical initial states on identical batches;
+    report throughput (uniform-equivalent ray-samples/s of the whole
+    iteration, proposal work included) and mean PSNR on the 10 held-out
+    views, plus what the trained proposal gains over an untrained one and
+    over none."""
+    from paper_2111_11215_amd import experiment
+    log(f"bench: comparison, {iters} iterations per form")
+    batches = make_batches(ctx, iters, rays)
+    views = make_views(ctx)
+    res = {"iters": iters, "rays_per_iter": rays, "views": len(views)}
+    for name, bf16, use_prop in (("plain_fp32", False, False), ("bf16", True, False), ("bf16_proposal", True, True)):
+        model = new_model(ctx, bf16)
+        if name == "plain_fp32":
+            experiment.count_uniform(model, batches)
+        prop = new_proposal(ctx) if use_prop else None
+        st = experiment.run(model, batches, iters, prop=prop, record_every=100)
+        entry = {"seconds": st.seconds, "ms_per_step": 1e3 * st.seconds / iters,
+                 "ray_samples_per_s": st.samples_per_s, "psnr_db": experiment.psnr_views(model, views),
+                 "loss_first_last": [st.losses[0][1], st.losses[-1][1]],
+                 "evaluated_per_step_end": experiment.evaluated_per_step(model, batches[-4:], prop)}
+        if prop is not None:
+            entry["all_segments_rate_end"] = st.fallback_rate[-1][1]
+            entry["prop_loss_first_last"] = [st.prop_losses[0][1], st.prop_losses[-1][1]]
+            fresh = new_proposal(ctx)
+            entry["gain"] = {
+                "evaluated_per_step": {"no_proposal": experiment.evaluated_per_step(model, batches[-4:]),
+                                       "untrained": experiment.evaluated_per_step(model, batches[-4:], fresh),
+                                       "trained": entry["evaluated_per_step_end"]},
+                "render_psnr_vs_plain_sampling_db": {
+                    "untrained": experiment.proposal_render_psnr(model, fresh, views[:2]),
+                    "trained": experiment.proposal_render_psnr(model, prop, views[:2])}}
+        res[name] = entry
+        log(f"bench: {name}: {entry['ms_per_step']:.3f} ms/step, psnr {entry['psnr_db']:.3f} dB")
+        del model, prop
+    res["delta_psnr_db"] = res["bf16_proposal"]["psnr_db"] - res["plain_fp32"]["psnr_db"]
+    res["speedup_vs_plain_fp32"] = res["bf16_proposal"]["ray_samples_per_s"] / res["plain_fp32"]["ray_samples_per_s"]
+    res["gate_pass"] = bool(res["delta_psnr_db"] >= -0.1 and res["speedup_vs_plain_fp32"] > 1.0)
+    return res
 
 
 def cpu_baseline(ctx, rays):
@@ -276,6 +388,11 @@ def main():
         "rays_per_s": args.rays * args.steps / elapsed,
     }
     out.update(out_extra)
+    if args.compare_iters > 0:
+        del model
+        ctx["model"] = None
+        torch.cuda.empty_cache()
+        out["proposal_comparison"] = compare_forms(ctx, args.compare_iters, args.rays)
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(ctx, args.cpu_rays)

@@ -368,11 +368,10 @@ def mlp_backward(Ws, cache, dc):
     ReLU'(0) is taken as 0.  Returns (dx, [dW1,dW2,dW3], [db1,db2,db3]); dx
     holds only the feature part in the bfloat16 form.
 
-    bfloat16 form: the backward products take bfloat16-rounded weights and
-    bfloat16-rounded propagated gradients where a product consumes them as a
-    matrix operand (dz2 into W2^T, and both factors of every weight
-    gradient); the first-layer input's gradient uses bfloat16 W1 with the
-    unrounded dz1; bias gradients sum the rounded dz (dz3 unrounded)."""
+    bfloat16 form: every backward product takes bfloat16-rounded weights
+    and bfloat16-rounded propagated gradients (dz3 into W3^T, dz2 into W2^T,
+    dz1 into W1^T, and both factors of every weight gradient); bias
+    gradients sum the rounded dz (dz3 unrounded)."""
     W1, W2, W3 = [np.asarray(w, np.float64) for w in Ws]
     c = cache["c"]
     dz3 = dc * c * (1.0 - c)
@@ -391,13 +390,13 @@ def mlp_backward(Ws, cache, dc):
     bf = bf16_round
     dW3 = bf(dz3).T @ bf(cache["h2"])
     db3 = dz3.sum(0)
-    dz2 = (dz3 @ bf(W3)) * (cache["z2"] > 0)
+    dz2 = (bf(dz3) @ bf(W3)) * (cache["z2"] > 0)
     dW2 = bf(dz2).T @ bf(cache["h1"])
     db2 = bf(dz2).sum(0)
     dz1 = (bf(dz2) @ bf(W2)) * (cache["z1"] > 0)
     dW1 = bf(dz1).T @ bf(cache["x"])
     db1 = bf(dz1).sum(0)
-    dx = dz1 @ bf(W1[:, :nf])
+    dx = bf(dz1) @ bf(W1[:, :nf])
     return dx, [dW1, dW2, dW3], [db1, db2, db3]
 
 
@@ -635,16 +634,19 @@ def proposal_encoding(o, d, t_near, box_min, box_max, n_freq=4):
     return np.concatenate([positional_encoding(u, n_freq), positional_encoding(d, n_freq)], axis=1)
 
 
-def proposal_forward(Ws, bs, enc):
-    """Proposal MLP enc -> 64 ReLU -> 64 ReLU -> 32 logits."""
+def proposal_forward(Ws, bs, enc, bf16=False):
+    """Proposal MLP enc -> 64 ReLU -> 64 ReLU -> 32 logits.  bf16=True rounds
+    the input encoding, the hidden activations and the weights to bfloat16
+    before each product (exact sums), as the bfloat16 form does."""
     W1, W2, W3 = [np.asarray(w, np.float64) for w in Ws]
     b1, b2, b3 = [np.asarray(b, np.float64) for b in bs]
-    z1 = enc @ W1.T + b1
+    r = bf16_round if bf16 else (lambda a: np.asarray(a, np.float64))
+    z1 = r(enc) @ r(W1).T + b1
     h1 = np.maximum(z1, 0.0)
-    z2 = h1 @ W2.T + b2
+    z2 = r(h1) @ r(W2).T + b2
     h2 = np.maximum(z2, 0.0)
-    z = h2 @ W3.T + b3
-    return z, dict(x=enc, z1=z1, h1=h1, z2=z2, h2=h2)
+    z = r(h2) @ r(W3).T + b3
+    return z, dict(x=r(enc), z1=z1, h1=r(h1), z2=z2, h2=r(h2), bf16=bf16)
 
 
 def proposal_probs(z):
@@ -710,16 +712,22 @@ def proposal_loss_grad(z, p):
 
 
 def proposal_backward(Ws, cache, dz):
-    """Reverse-mode derivative of ``proposal_forward``."""
+    """Reverse-mode derivative of ``proposal_forward``.  In the bfloat16 form
+    both operands of every product are bfloat16 values, as in the forward:
+    the propagated gradient is rounded before it meets a bfloat16 weight
+    matrix and before it multiplies the bfloat16 activations that give the
+    weight gradients (bias gradients sum the rounded gradient)."""
     W1, W2, W3 = [np.asarray(w, np.float64) for w in Ws]
-    dW3 = dz.T @ cache["h2"]
-    db3 = dz.sum(0)
-    dz2 = (dz @ W3) * (cache["z2"] > 0)
-    dW2 = dz2.T @ cache["h1"]
-    db2 = dz2.sum(0)
-    dz1 = (dz2 @ W2) * (cache["z1"] > 0)
-    dW1 = dz1.T @ cache["x"]
-    db1 = dz1.sum(0)
+    r = bf16_round if cache.get("bf16") else (lambda a: np.asarray(a, np.float64))
+    g3 = r(dz)
+    dW3 = g3.T @ cache["h2"]
+    db3 = g3.sum(0)
+    g2 = r((g3 @ r(W3)) * (cache["z2"] > 0))
+    dW2 = g2.T @ cache["h1"]
+    db2 = g2.sum(0)
+    g1 = r((g2 @ r(W2)) * (cache["z1"] > 0))
+    dW1 = g1.T @ cache["x"]
+    db1 = g1.sum(0)
     return [dW1, dW2, dW3], [db1, db2, db3]
 
 

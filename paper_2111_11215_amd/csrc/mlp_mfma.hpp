@@ -35,6 +35,9 @@ constexpr int kW1PackF32 = 4 * 2 * 64 * 4;
 constexpr int kW2PackF32 = 4 * 16 * 64 * 4;
 constexpr int kW1PackBF16 = 4 * 64 * 8;
 constexpr int kW2PackBF16 = 4 * 8 * 64 * 8;
+constexpr int kW3PackBF16 = 8 * 64 * 8;    // layer 3 as a 32-row tile (rows >= 3 zero)
+constexpr int kW3TPackBF16 = 4 * 64 * 8;   // W3^T, one K step (k >= 3 zero)
+constexpr int kW1TPackBF16 = 8 * 64 * 8;   // W1[:, :12]^T as a 32-row tile (rows >= 12 zero)
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -77,6 +80,10 @@ __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(stati
 struct PackArgs {
     const float* w1;
     const float* w2;
+    const float* w3;
+    uint16_t* w3pb;
+    uint16_t* w3tpb;
+    uint16_t* w1tpb;
     float* w1p;
     float* w2p;
     float* w2tp;
@@ -112,6 +119,21 @@ __global__ void pack_weights_kernel(PackArgs a) {
         const int kk = 2 * st + h;
         a.w1p[gid] = kk < kC ? a.w1[(32 * mt + m) * kIn + kk] : 0.0f;
     }
+    if (a.bf16 && gid < kW3PackBF16) {
+        // index (st*64 + lane)*8 + i; lane (m, h), element i
+        const int i = gid & 7, lane = (gid >> 3) & 63, st = gid >> 9;
+        const int m = lane & 31, h = lane >> 5;
+        const int k = phi16(st, i, h);
+        a.w3pb[gid] = m < 3 ? f2bf(a.w3[m * kH + k]) : static_cast<uint16_t>(0);
+        a.w1tpb[gid] = m < kC ? f2bf(a.w1[k * kIn + m]) : static_cast<uint16_t>(0);
+    }
+    if (a.bf16 && gid < kW3TPackBF16) {
+        // index (mt*64 + lane)*8 + i, k = 8h + i (< 3)
+        const int i = gid & 7, lane = (gid >> 3) & 63, mt = gid >> 9;
+        const int m = lane & 31, h = lane >> 5;
+        const int k = 8 * h + i;
+        a.w3tpb[gid] = k < 3 ? f2bf(a.w3[k * kH + 32 * mt + m]) : static_cast<uint16_t>(0);
+    }
     if (a.bf16 && gid < kW1PackBF16) {
         // bfloat16 layer 1: index (mt*64 + lane)*8 + i, k = 8h + i (< 12)
         const int i = gid & 7, lane = (gid >> 3) & 63, mt = gid >> 9;
@@ -141,6 +163,9 @@ struct MlpArgs {
     const uint16_t* w1pb;
     const uint16_t* w2pb;
     const uint16_t* w2tpb;
+    const uint16_t* w3pb;
+    const uint16_t* w3tpb;
+    const uint16_t* w1tpb;
     float* feat;          // [cap][12]: features in; dL/dfeat out (backward)
     float* col;           // [cap][4]: colour out (forward) / dL/dc in (backward)
     float* partial;       // [blocks][kPStride] weight-gradient partials
@@ -159,6 +184,9 @@ __device__ __forceinline__ MlpArgs refresh(const MlpArgs& a) {
     l.w1pb = opaque(a.w1pb);
     l.w2pb = opaque(a.w2pb);
     l.w2tpb = opaque(a.w2tpb);
+    l.w3pb = opaque(a.w3pb);
+    l.w3tpb = opaque(a.w3tpb);
+    l.w1tpb = opaque(a.w1tpb);
     return l;
 }
 
@@ -553,25 +581,25 @@ __device__ __forceinline__ void forward_chain_bf16(const MlpArgs& a, const bf16x
     for (int mt = 0; mt < 4; ++mt) c.z2[mt] = chain_tile_bf16(sW2, lane, mt, hb, c.z2[mt]);
 }
 
-// Layer 3 with bfloat16-rounded inputs and weights (float32 products).
-__device__ __forceinline__ void head_bf16(const MlpArgs& a, const f32x16 z2[4], int h, float c[3]) {
-    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
+// Layer 3 on matrix cores: logits of sample m land in lane m (half 0),
+// registers 0..2; bfloat16 relu(z2) and W3, float32 accumulation.
+__device__ __forceinline__ f32x16 head_bf16(const MlpArgs& a, const f32x16 z2[4], int lane, float c[3]) {
+    const int h = lane >> 5;
+    f32x16 z3;
     #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
+    for (int rr = 0; rr < 16; ++rr) z3[rr] = (h == 0 && rr < 3) ? a.b3[rr] : 0.0f;
+    const bf16x8* w3 = reinterpret_cast<const bf16x8*>(a.w3pb);
+    #pragma unroll
+    for (int st = 0; st < 8; ++st) {
+        bf16x8 hv;
         #pragma unroll
-        for (int rr = 0; rr < 16; ++rr) {
-            const int j = 32 * mt + acc_row(rr, h);
-            const float hv = bf16r(fmaxf(z2[mt][rr], 0.0f));
-            s0 += bf16r(a.w3[j]) * hv;
-            s1 += bf16r(a.w3[kH + j]) * hv;
-            s2 += bf16r(a.w3[2 * kH + j]) * hv;
-        }
-    s0 += __shfl_xor(s0, 32, 64);
-    s1 += __shfl_xor(s1, 32, 64);
-    s2 += __shfl_xor(s2, 32, 64);
-    c[0] = 1.0f / (1.0f + expf(-(s0 + a.b3[0])));
-    c[1] = 1.0f / (1.0f + expf(-(s1 + a.b3[1])));
-    c[2] = 1.0f / (1.0f + expf(-(s2 + a.b3[2])));
+        for (int e = 0; e < 8; ++e) hv[e] = static_cast<__bf16>(fmaxf(z2[st >> 1][8 * (st & 1) + e], 0.0f));
+        z3 = mma_bf16(w3[st * 64 + lane], hv, z3);
+    }
+    c[0] = 1.0f / (1.0f + expf(-z3[0]));
+    c[1] = 1.0f / (1.0f + expf(-z3[1]));
+    c[2] = 1.0f / (1.0f + expf(-z3[2]));
+    return z3;
 }
 
 __device__ __forceinline__ void load_packed_bf16(const MlpArgs& a, bf16x8* sW1, bf16x8* sW2, bf16x8* sW2T) {
@@ -605,7 +633,7 @@ __global__ __launch_bounds__(256, 2) void mlp_fwd_bf16_kernel(MlpArgs a0) {
         ChainF32 c;
         forward_chain_bf16(a, sW1, sW2, r, f, lane, c);
         float col[3];
-        head_bf16(a, c.z2, h, col);
+        head_bf16(a, c.z2, lane, col);
         if (ok && h == 0) reinterpret_cast<float4*>(a.col)[s] = make_float4(col[0], col[1], col[2], 0.0f);
     }
 }
@@ -652,9 +680,9 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_bf16_kernel(MlpArgs a0) {
         ChainF32 c;
         forward_chain_bf16(a, sW1, sW2, r, f, lane, c);
         float col[3];
-        head_bf16(a, c.z2, h, col);
+        head_bf16(a, c.z2, lane, col);
         float dz3[3] = {0, 0, 0};
-        if (ok) {
+        if (ok && h == 0) {
             const float4 dc = reinterpret_cast<const float4*>(a.col)[s];
             dz3[0] = dc.x * col[0] * (1.0f - col[0]);
             dz3[1] = dc.y * col[1] * (1.0f - col[1]);
@@ -676,16 +704,22 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_bf16_kernel(MlpArgs a0) {
                 db3[t] += dz3[t];
             }
         }
-        // dz2 = (W3^T dz3) * relu'(z2), in place of z2 (bf16-rounded W3)
-        #pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
+        // dz2 = (W3^T bf16(dz3)) * relu'(z2) on matrix cores, in place of z2
+        {
+            bf16x8 dzb;
             #pragma unroll
-            for (int rr = 0; rr < 16; ++rr) {
-                const int j = 32 * mt + acc_row(rr, h);
-                const float dh = bf16r(a.w3[j]) * dz3[0] + bf16r(a.w3[kH + j]) * dz3[1] +
-                                 bf16r(a.w3[2 * kH + j]) * dz3[2];
-                c.z2[mt][rr] = c.z2[mt][rr] > 0.0f ? dh : 0.0f;
+            for (int e = 0; e < 8; ++e) dzb[e] = static_cast<__bf16>(e < 3 ? dz3[e < 3 ? e : 0] : 0.0f);
+            const bf16x8* w3t = reinterpret_cast<const bf16x8*>(a.w3tpb);
+            #pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                f32x16 dh;
+                #pragma unroll
+                for (int rr = 0; rr < 16; ++rr) dh[rr] = 0.0f;
+                dh = mma_bf16(w3t[mt * 64 + lane], dzb, dh);
+                #pragma unroll
+                for (int rr = 0; rr < 16; ++rr) c.z2[mt][rr] = c.z2[mt][rr] > 0.0f ? dh[rr] : 0.0f;
             }
+        }
         __syncthreads();
         // dW3^T[j in tile `wave`][c] over the 128 staged samples
         #pragma unroll
@@ -727,21 +761,17 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_bf16_kernel(MlpArgs a0) {
                 for (int rr = 0; rr < 16; ++rr) c.h1[mt][rr] = c.h1[mt][rr] > 0.0f ? dh1[rr] : 0.0f;
             }
         }
-        // dL/dfeat = bf16(W1[:, :12])^T dz1
-        float df[12];
-        #pragma unroll
-        for (int cc = 0; cc < 12; ++cc) df[cc] = 0.0f;
-        #pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
+        // dL/dfeat = bf16(W1[:, :12])^T bf16(dz1) on matrix cores: rows c < 12
+        // of the output tile (half 0: registers 0-7 -> c 0-3, 8-11; half 1:
+        // registers 0-3 -> c 4-7)
+        f32x16 dft;
+        {
             #pragma unroll
-            for (int rr = 0; rr < 16; ++rr) {
-                const int i = 32 * mt + acc_row(rr, h);
-                const float d = c.h1[mt][rr];
-                #pragma unroll
-                for (int cc = 0; cc < 12; ++cc) df[cc] += bf16r(a.w1[i * kIn + cc]) * d;
-            }
-        #pragma unroll
-        for (int cc = 0; cc < 12; ++cc) df[cc] += __shfl_xor(df[cc], 32, 64);
+            for (int rr = 0; rr < 16; ++rr) dft[rr] = 0.0f;
+            const bf16x8* w1t = reinterpret_cast<const bf16x8*>(a.w1tpb);
+            #pragma unroll
+            for (int st = 0; st < 8; ++st) dft = mma_bf16(w1t[st * 64 + lane], pack8(c.h1[st >> 1], st & 1), dft);
+        }
         __syncthreads();
         // stage dz1 -> sA, x' = [f, PE, 1, 0...] -> sB (64 columns)
         #pragma unroll
@@ -762,11 +792,14 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_bf16_kernel(MlpArgs a0) {
                 sB[cidx * kBP + col_s] = static_cast<__bf16>(v);
             }
         }
-        if (ok && h == 0) {
+        if (ok) {
             float4* out = reinterpret_cast<float4*>(a.feat + s * 12);
-            out[0] = make_float4(df[0], df[1], df[2], df[3]);
-            out[1] = make_float4(df[4], df[5], df[6], df[7]);
-            out[2] = make_float4(df[8], df[9], df[10], df[11]);
+            if (h == 0) {
+                out[0] = make_float4(dft[0], dft[1], dft[2], dft[3]);
+                out[2] = make_float4(dft[4], dft[5], dft[6], dft[7]);
+            } else {
+                out[1] = make_float4(dft[0], dft[1], dft[2], dft[3]);
+            }
         }
         __syncthreads();
         #pragma unroll

@@ -1,8 +1,9 @@
 // Learned proposal (not in the paper): a small network that predicts, per
 // ray, how the compositing weight is spread over 32 equal-count segments of
 // its uniform samples, and the segment mask that keeps the segments holding
-// most of it.  Inputs and weights are rounded to bfloat16, products are
-// accumulated in float32; the selection runs in float64 so that it is
+// most of it.  The network runs on bfloat16 matrix cores (inputs, hidden
+// activations and weights rounded to bfloat16, float32 accumulation), one
+// wavefront per 32 rays; the selection runs in float64 so that it is
 // reproducible from the float32 logits.
 #include "common.hpp"
 
@@ -12,14 +13,6 @@ constexpr int kIn = 54, kH = 64, kS = 32;
 constexpr int kOffW1 = 0, kOffB1 = kOffW1 + kH * kIn, kOffW2 = kOffB1 + kH, kOffB2 = kOffW2 + kH * kH,
               kOffW3 = kOffB2 + kH, kOffB3 = kOffW3 + kS * kH, kParams = kOffB3 + kS;
 constexpr int kPStride = (kParams + 63) / 64 * 64;
-constexpr int kRaysPerBlock = 64;
-
-__device__ __forceinline__ float bf16_round(float f) {   // round to nearest even, keep as float
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7F800000u) == 0x7F800000u) return f;
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return __uint_as_float(u & 0xFFFF0000u);
-}
 
 struct PropArgs {
     const float* rays_o;
@@ -32,17 +25,63 @@ struct PropArgs {
     const float* b[3];
 };
 
-// Load weights (bf16-rounded) and biases (float32) into LDS, flat layout.
-__device__ void load_weights(const PropArgs& a, float* sw) {
-    for (int i = threadIdx.x; i < kParams; i += blockDim.x) {
-        float v;
-        if (i < kOffB1) v = bf16_round(a.w[0][i - kOffW1]);
-        else if (i < kOffW2) v = a.b[0][i - kOffB1];
-        else if (i < kOffB2) v = bf16_round(a.w[1][i - kOffW2]);
-        else if (i < kOffW3) v = a.b[1][i - kOffB2];
-        else if (i < kOffB3) v = bf16_round(a.w[2][i - kOffW3]);
-        else v = a.b[2][i - kOffB3];
-        sw[i] = v;
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f32x16 mma(bf16x8 a, bf16x8 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+// Row within a 32-row accumulator tile of register r in lane half h.
+__device__ __forceinline__ int acc_row(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
+// Feature consumed at chained step st, element i, by lane half h.
+__device__ __forceinline__ int phi16(int st, int i, int h) { return 32 * (st >> 1) + acc_row(8 * (st & 1) + i, h); }
+
+__device__ __forceinline__ f32x16 zero16() {
+    f32x16 z;
+    #pragma unroll
+    for (int r = 0; r < 16; ++r) z[r] = 0.0f;
+    return z;
+}
+
+__device__ __forceinline__ bf16x8 pack8(const f32x16& v, int g) {
+    bf16x8 r;
+    #pragma unroll
+    for (int e = 0; e < 8; ++e) r[e] = static_cast<__bf16>(v[8 * g + e]);
+    return r;
+}
+
+// Matrix-core operands in LDS (bf16x8 per lane and step):
+//   W1 [mt 2][st 4][lane]: W1[32mt+m][16st+8h+i] (k >= 54 zero)
+//   W2 [mt 2][st 4][lane]: W2[32mt+m][phi16(st,i,h)]
+//   W3 [st 4][lane]:       W3[m][phi16(st,i,h)]
+//   W2T[mt 2][st 4][lane]: W2[phi16(st,i,h)][32mt+m]
+//   W3T[mt 2][st 2][lane]: W3[phi16(st,i,h)][32mt+m]
+struct PropLds {
+    bf16x8 w1[2 * 4 * 64];
+    bf16x8 w2[2 * 4 * 64];
+    bf16x8 w3[4 * 64];
+    bf16x8 w2t[2 * 4 * 64];
+    bf16x8 w3t[2 * 2 * 64];
+};
+
+__device__ void pack_weights(const PropArgs& a, PropLds& L, bool transposed) {
+    for (int idx = threadIdx.x; idx < 2 * 4 * 64 * 8; idx += blockDim.x) {
+        const int i = idx & 7, lane = (idx >> 3) & 63, st = (idx >> 9) & 3, mt = idx >> 11;
+        const int m = lane & 31, h = lane >> 5;
+        const int k1 = 16 * st + 8 * h + i;
+        const int row = 32 * mt + m, k2 = phi16(st, i, h);
+        reinterpret_cast<__bf16*>(L.w1)[idx] = static_cast<__bf16>(k1 < kIn ? a.w[0][row * kIn + k1] : 0.0f);
+        reinterpret_cast<__bf16*>(L.w2)[idx] = static_cast<__bf16>(a.w[1][row * kH + k2]);
+        if (transposed) reinterpret_cast<__bf16*>(L.w2t)[idx] = static_cast<__bf16>(a.w[1][k2 * kH + row]);
+        if (idx < 4 * 64 * 8) {
+            const int st3 = idx >> 9;
+            reinterpret_cast<__bf16*>(L.w3)[idx] = static_cast<__bf16>(a.w[2][m * kH + phi16(st3, i, h)]);
+        }
+        if (transposed && idx < 2 * 2 * 64 * 8) {
+            const int st3 = (idx >> 9) & 1, mt3 = idx >> 10;
+            reinterpret_cast<__bf16*>(L.w3t)[idx] =
+                static_cast<__bf16>(a.w[2][phi16(st3, i, h) * kH + 32 * mt3 + m]);
+        }
     }
 }
 
@@ -55,56 +94,97 @@ __device__ void encode(const PropArgs& a, int r, float e[kIn]) {
         const float x0 = a.rays_o[3 * r + i] + tn * d[i];
         u[i] = (x0 - 0.5f * (a.mn[i] + a.mx[i])) / (0.5f * (a.mx[i] - a.mn[i]));
     }
-    const float* src[2] = {u, d};
+    #pragma unroll
     for (int part = 0; part < 2; ++part) {
+        const float* src = part == 0 ? u : d;
         float* out = e + 27 * part;
-        for (int c = 0; c < 3; ++c) out[c] = src[part][c];
+        #pragma unroll
+        for (int c = 0; c < 3; ++c) out[c] = src[c];
+        #pragma unroll
         for (int fq = 0; fq < 4; ++fq)
+            #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 float sv, cv;
-                sincosf(src[part][c] * static_cast<float>(1 << fq), &sv, &cv);
+                sincosf(src[c] * static_cast<float>(1 << fq), &sv, &cv);
                 out[3 + 6 * fq + c] = sv;
                 out[6 + 6 * fq + c] = cv;
             }
     }
-    for (int i = 0; i < kIn; ++i) e[i] = bf16_round(e[i]);
 }
 
-// Forward of one ray; h1, h2 are post-ReLU and rounded to bfloat16.
-__device__ void forward(const float* sw, const float e[kIn], float h1[kH], float h2[kH], float z[kS]) {
-    for (int o = 0; o < kH; ++o) {
-        float acc = sw[kOffB1 + o];
-        for (int k = 0; k < kIn; ++k) acc += sw[kOffW1 + o * kIn + k] * e[k];
-        h1[o] = bf16_round(fmaxf(acc, 0.0f));
+struct PropFwd {
+    bf16x8 enc[4];   // layer-1 B operand
+    f32x16 h1[2], h2[2], z;
+};
+
+// Forward of the 32 rays of a wave (ray = lane % 32).
+__device__ void prop_forward(const PropArgs& a, const PropLds& L, int r, bool ray_ok, int lane, PropFwd& f) {
+    const int h = lane >> 5;
+    float e[kIn];
+    if (ray_ok) encode(a, r, e);
+    #pragma unroll
+    for (int st = 0; st < 4; ++st)
+        #pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            // both candidate indices are compile-time constants: no private-array indexing
+            const int k0 = 16 * st + i, k1 = k0 + 8;
+            const float v0 = k0 < kIn ? e[k0 < kIn ? k0 : 0] : 0.0f;
+            const float v1 = k1 < kIn ? e[k1 < kIn ? k1 : 0] : 0.0f;
+            f.enc[st][i] = static_cast<__bf16>(ray_ok ? (h ? v1 : v0) : 0.0f);
+        }
+    #pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+        f32x16 acc;
+        #pragma unroll
+        for (int rr = 0; rr < 16; ++rr) acc[rr] = a.b[0][32 * mt + acc_row(rr, h)];
+        #pragma unroll
+        for (int st = 0; st < 4; ++st) acc = mma(L.w1[(mt * 4 + st) * 64 + lane], f.enc[st], acc);
+        #pragma unroll
+        for (int rr = 0; rr < 16; ++rr) f.h1[mt][rr] = fmaxf(acc[rr], 0.0f);
     }
-    for (int o = 0; o < kH; ++o) {
-        float acc = sw[kOffB2 + o];
-        for (int k = 0; k < kH; ++k) acc += sw[kOffW2 + o * kH + k] * h1[k];
-        h2[o] = bf16_round(fmaxf(acc, 0.0f));
+    bf16x8 hb[4];
+    #pragma unroll
+    for (int st = 0; st < 4; ++st) hb[st] = pack8(f.h1[st >> 1], st & 1);
+    #pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+        f32x16 acc;
+        #pragma unroll
+        for (int rr = 0; rr < 16; ++rr) acc[rr] = a.b[1][32 * mt + acc_row(rr, h)];
+        #pragma unroll
+        for (int st = 0; st < 4; ++st) acc = mma(L.w2[(mt * 4 + st) * 64 + lane], hb[st], acc);
+        f.h2[mt] = acc;   // pre-activation kept for the ReLU mask
     }
-    for (int o = 0; o < kS; ++o) {
-        float acc = sw[kOffB3 + o];
-        for (int k = 0; k < kH; ++k) acc += sw[kOffW3 + o * kH + k] * h2[k];
-        z[o] = acc;
+    #pragma unroll
+    for (int st = 0; st < 4; ++st) {
+        bf16x8 v;
+        #pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = static_cast<__bf16>(fmaxf(f.h2[st >> 1][8 * (st & 1) + i], 0.0f));
+        hb[st] = v;
     }
+    #pragma unroll
+    for (int rr = 0; rr < 16; ++rr) f.z[rr] = a.b[2][acc_row(rr, h)];
+    #pragma unroll
+    for (int st = 0; st < 4; ++st) f.z = mma(L.w3[st * 64 + lane], hb[st], f.z);
 }
 
-// Segment mask from float32 logits, float64 arithmetic, sequential sums.
+// Segment mask from float32 logits; float64 arithmetic, sums in index
+// order (transmitted entry last), ties to the lower index.  Registers only.
 __device__ uint32_t select_mask(const float z[kS], double cum_frac, double min_mass, float* pred_mass) {
     double m = 0.0;
+    #pragma unroll
     for (int s = 0; s < kS; ++s) m = fmax(m, static_cast<double>(z[s]));
-    double e[kS + 1];
-    double tot = 0.0;
-    for (int s = 0; s < kS; ++s) {
-        e[s] = exp(static_cast<double>(z[s]) - m);
-        tot += e[s];
-    }
-    e[kS] = exp(0.0 - m);
-    tot += e[kS];
     double q[kS];
-    double mass = 0.0;
+    double tot = 0.0;
+    #pragma unroll
     for (int s = 0; s < kS; ++s) {
-        q[s] = e[s] / tot;
+        q[s] = exp(static_cast<double>(z[s]) - m);
+        tot += q[s];
+    }
+    tot += exp(0.0 - m);
+    double mass = 0.0;
+    #pragma unroll
+    for (int s = 0; s < kS; ++s) {
+        q[s] = q[s] / tot;
         mass += q[s];
     }
     *pred_mass = static_cast<float>(mass);
@@ -113,163 +193,200 @@ __device__ uint32_t select_mask(const float z[kS], double cum_frac, double min_m
     double acc = 0.0;
     const double target = cum_frac * mass;
     for (int it = 0; it < kS; ++it) {
-        int best = -1;
+        int best = 0;
+        double bq = -1.0;
+        #pragma unroll
         for (int s = 0; s < kS; ++s)
-            if (!((chosen >> s) & 1u) && (best < 0 || q[s] > q[best])) best = s;
+            if (!((chosen >> s) & 1u) && q[s] > bq) {
+                bq = q[s];
+                best = s;
+            }
         chosen |= 1u << best;
-        acc += q[best];
+        acc += bq;
         if (acc >= target) break;
     }
     return chosen;
 }
 
-__global__ __launch_bounds__(kRaysPerBlock) void proposal_fwd_kernel(PropArgs a, int run_net, float cum_frac,
-                                                                     float min_mass, float* __restrict__ logits,
-                                                                     float* __restrict__ pred_mass,
-                                                                     uint32_t* __restrict__ seg_mask) {
-    __shared__ float sw[kParams];
-    if (run_net) load_weights(a, sw);
+constexpr int kRaysPerWave = 32;
+constexpr int kWaves = 4;
+
+__global__ __launch_bounds__(256) void proposal_fwd_kernel(PropArgs a, int run_net, float cum_frac, float min_mass,
+                                                           float* __restrict__ logits, float* __restrict__ pred_mass,
+                                                           uint32_t* __restrict__ seg_mask) {
+    __shared__ PropLds L;
+    __shared__ float sZ[kWaves][kRaysPerWave][kS + 1];
+    if (run_net) pack_weights(a, L, false);
     __syncthreads();
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= a.B) return;
-    float z[kS];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 31, h = lane >> 5;
+    const int r = (blockIdx.x * kWaves + wave) * kRaysPerWave + m;
+    const bool ray_ok = r < a.B;
     if (run_net) {
-        float e[kIn], h1[kH], h2[kH];
-        encode(a, r, e);
-        forward(sw, e, h1, h2, z);
-        for (int s = 0; s < kS; ++s) logits[static_cast<int64_t>(r) * kS + s] = z[s];
-    } else {
-        for (int s = 0; s < kS; ++s) z[s] = logits[static_cast<int64_t>(r) * kS + s];
+        PropFwd f;
+        prop_forward(a, L, r, ray_ok, lane, f);
+        #pragma unroll
+        for (int rr = 0; rr < 16; ++rr) {
+            const int sg = acc_row(rr, h);
+            sZ[wave][m][sg] = f.z[rr];
+            if (ray_ok) logits[static_cast<int64_t>(r) * kS + sg] = f.z[rr];
+        }
+    } else if (ray_ok) {
+        #pragma unroll
+        for (int q = 0; q < 16; ++q) sZ[wave][m][16 * h + q] = logits[static_cast<int64_t>(r) * kS + 16 * h + q];
     }
-    float pm;
-    uint32_t mask = select_mask(z, cum_frac, min_mass, &pm);
-    if (a.valid && !a.valid[r]) mask = 0xFFFFFFFFu;
-    if (pred_mass) pred_mass[r] = pm;
-    if (seg_mask) seg_mask[r] = mask;
+    __syncthreads();
+    if (h == 0 && ray_ok) {
+        float z[kS];
+        #pragma unroll
+        for (int s = 0; s < kS; ++s) z[s] = sZ[wave][m][s];
+        float pm;
+        uint32_t mask = select_mask(z, cum_frac, min_mass, &pm);
+        if (a.valid && !a.valid[r]) mask = 0xFFFFFFFFu;
+        if (pred_mass) pred_mass[r] = pm;
+        if (seg_mask) seg_mask[r] = mask;
+    }
 }
 
-// Backward over 64 rays per block: per-ray adjoint in registers, activations
-// staged in LDS, each lane then accumulates whole weight rows over the rays.
-__global__ __launch_bounds__(kRaysPerBlock) void proposal_bwd_kernel(PropArgs a, const float* __restrict__ seg_w,
-                                                                     const float* __restrict__ log_t_end,
-                                                                     float* __restrict__ partial,
-                                                                     float* __restrict__ loss_part) {
-    __shared__ float sw[kParams];
-    __shared__ float sE[kRaysPerBlock * kIn];
-    __shared__ float sH1[kRaysPerBlock * kH];
-    __shared__ float sH2[kRaysPerBlock * kH];
-    __shared__ float sD1[kRaysPerBlock * kH];
-    __shared__ float sD2[kRaysPerBlock * kH];
-    __shared__ float sDz[kRaysPerBlock * kS];
-    load_weights(a, sw);
+// Backward: per wave 32 rays; the KL gradient (q - p)/B, the adjoint chain
+// on matrix cores, and the weight gradients with the ray index as the
+// contraction dimension through [feature][ray] bfloat16 LDS staging.  Each
+// wave writes its own partial of the flat gradient.
+constexpr int kRP = 40;   // LDS pitch (bf16) of a staged feature row of 32 rays
+
+__global__ __launch_bounds__(256) void proposal_bwd_kernel(PropArgs a, const float* __restrict__ seg_w,
+                                                           const float* __restrict__ log_t_end,
+                                                           float* __restrict__ partial,
+                                                           float* __restrict__ loss_part) {
+    __shared__ PropLds L;
+    __shared__ __attribute__((aligned(16))) __bf16 sT[kWaves][(64 * 5 + 32) * kRP];
+    pack_weights(a, L, true);
     __syncthreads();
-    const int t = threadIdx.x;
-    const int r = blockIdx.x * blockDim.x + t;
-    const bool ok = r < a.B && (!a.valid || a.valid[r]);
-    float e[kIn], h1[kH], h2[kH], z[kS];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 31, h = lane >> 5;
+    const int wglob = blockIdx.x * kWaves + wave;
+    const int r = wglob * kRaysPerWave + m;
+    const bool in_batch = r < a.B;
+    const bool ok = in_batch && (!a.valid || a.valid[r]);
+    PropFwd f;
+    prop_forward(a, L, r, in_batch, lane, f);
+    // softmax over the 32 logits and the implicit 0, split over the two halves
+    float mx = 0.0f;
+    #pragma unroll
+    for (int rr = 0; rr < 16; ++rr) mx = fmaxf(mx, f.z[rr]);
+    mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+    float tot = 0.0f;
+    #pragma unroll
+    for (int rr = 0; rr < 16; ++rr) tot += expf(f.z[rr] - mx);
+    tot += __shfl_xor(tot, 32, 64);
+    tot += expf(-mx);
+    const float logtot = logf(tot) + mx;
+    const float invB = 1.0f / static_cast<float>(a.B);
+    f32x16 dz;
     float kl = 0.0f;
-    if (r < a.B) {
-        encode(a, r, e);
-        forward(sw, e, h1, h2, z);
-    } else {
-        for (int i = 0; i < kIn; ++i) e[i] = 0.0f;
-        for (int i = 0; i < kH; ++i) h1[i] = h2[i] = 0.0f;
-        for (int i = 0; i < kS; ++i) z[i] = 0.0f;
+    #pragma unroll
+    for (int rr = 0; rr < 16; ++rr) {
+        const int sg = acc_row(rr, h);
+        const float lq = f.z[rr] - logtot;
+        const float p = ok ? seg_w[static_cast<int64_t>(r) * kS + sg] : 0.0f;
+        dz[rr] = ok ? (expf(lq) - p) * invB : 0.0f;
+        if (ok && p > 0.0f) kl += p * (logf(p) - lq);
     }
-    float dz[kS];
-    {
-        float m = 0.0f;
-        for (int s = 0; s < kS; ++s) m = fmaxf(m, z[s]);
-        float tot = expf(-m);
-        for (int s = 0; s < kS; ++s) tot += expf(z[s] - m);
-        const float invB = 1.0f / static_cast<float>(a.B);
-        const float logtot = logf(tot) + m;   // log of the softmax denominator
-        for (int s = 0; s < kS; ++s) {
-            const float q = expf(z[s] - logtot);
-            const float p = ok ? seg_w[static_cast<int64_t>(r) * kS + s] : 0.0f;
-            dz[s] = ok ? (q - p) * invB : 0.0f;
-            if (ok && p > 0.0f) kl += p * (logf(p) - (z[s] - logtot));
+    if (ok && h == 0) {
+        const float lt = log_t_end[r];
+        const float pt = expf(lt);
+        if (pt > 0.0f) kl += pt * (lt + logtot);
+    }
+    kl *= invB;
+    // adjoint chain: d2 = (W3^T dz) * relu'(z2), d1 = (W2^T d2) * relu'(z1)
+    bf16x8 zb[2] = {pack8(dz, 0), pack8(dz, 1)};
+    f32x16 d2[2], d1[2];
+    #pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+        f32x16 acc = zero16();
+        #pragma unroll
+        for (int st = 0; st < 2; ++st) acc = mma(L.w3t[(mt * 2 + st) * 64 + lane], zb[st], acc);
+        #pragma unroll
+        for (int rr = 0; rr < 16; ++rr) d2[mt][rr] = f.h2[mt][rr] > 0.0f ? acc[rr] : 0.0f;
+    }
+    bf16x8 db[4];
+    #pragma unroll
+    for (int st = 0; st < 4; ++st) db[st] = pack8(d2[st >> 1], st & 1);
+    #pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+        f32x16 acc = zero16();
+        #pragma unroll
+        for (int st = 0; st < 4; ++st) acc = mma(L.w2t[(mt * 4 + st) * 64 + lane], db[st], acc);
+        #pragma unroll
+        for (int rr = 0; rr < 16; ++rr) d1[mt][rr] = f.h1[mt][rr] > 0.0f ? acc[rr] : 0.0f;
+    }
+    // stage [feature][ray] rows: enc 0..63, h1 64..127, h2 128..191, d1 192..255,
+    // d2 256..319, dz 320..351 (bf16)
+    __bf16* T = sT[wave];
+    #pragma unroll
+    for (int st = 0; st < 4; ++st)
+        #pragma unroll
+        for (int i = 0; i < 8; ++i) T[(16 * st + 8 * h + i) * kRP + m] = f.enc[st][i];
+    #pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+        #pragma unroll
+        for (int rr = 0; rr < 16; ++rr) {
+            const int j = 32 * mt + acc_row(rr, h);
+            T[(64 + j) * kRP + m] = static_cast<__bf16>(f.h1[mt][rr]);
+            T[(128 + j) * kRP + m] = static_cast<__bf16>(fmaxf(f.h2[mt][rr], 0.0f));
+            T[(192 + j) * kRP + m] = static_cast<__bf16>(d1[mt][rr]);
+            T[(256 + j) * kRP + m] = static_cast<__bf16>(d2[mt][rr]);
         }
-        if (ok) {
-            const float pt = expf(log_t_end[r]);
-            if (pt > 0.0f) kl += pt * (log_t_end[r] + logtot);
-        }
-        kl *= invB;
-    }
-    float d2[kH], d1[kH];
-    for (int k = 0; k < kH; ++k) {
-        float acc = 0.0f;
-        for (int o = 0; o < kS; ++o) acc += sw[kOffW3 + o * kH + k] * dz[o];
-        d2[k] = h2[k] > 0.0f ? acc : 0.0f;
-    }
-    for (int k = 0; k < kH; ++k) {
-        float acc = 0.0f;
-        for (int o = 0; o < kH; ++o) acc += sw[kOffW2 + o * kH + k] * d2[o];
-        d1[k] = h1[k] > 0.0f ? acc : 0.0f;
-    }
-    for (int i = 0; i < kIn; ++i) sE[t * kIn + i] = e[i];
-    for (int i = 0; i < kH; ++i) {
-        sH1[t * kH + i] = h1[i];
-        sH2[t * kH + i] = h2[i];
-        sD1[t * kH + i] = d1[i];
-        sD2[t * kH + i] = d2[i];
-    }
-    for (int i = 0; i < kS; ++i) sDz[t * kS + i] = dz[i];
+    #pragma unroll
+    for (int rr = 0; rr < 16; ++rr) T[(320 + acc_row(rr, h)) * kRP + m] = static_cast<__bf16>(dz[rr]);
     for (int off = 32; off > 0; off >>= 1) kl += __shfl_xor(kl, off, 64);
     __syncthreads();
-    float* out = partial + static_cast<int64_t>(blockIdx.x) * kPStride;
-    // lane o owns row o of W1 and W2 (and of W3 for o < 32), plus the biases
-    const int o = t;
-    {
-        float acc[kIn];
-        for (int k = 0; k < kIn; ++k) acc[k] = 0.0f;
-        float bacc = 0.0f;
-        for (int rr = 0; rr < kRaysPerBlock; ++rr) {
-            const float g = sD1[rr * kH + o];
-            bacc += g;
-            for (int k = 0; k < kIn; ++k) acc[k] += g * sE[rr * kIn + k];
+    float* out = partial + static_cast<int64_t>(wglob) * kPStride;
+    bf16x8 ones;
+    #pragma unroll
+    for (int e = 0; e < 8; ++e) ones[e] = static_cast<__bf16>(m == 0 ? 1.0f : 0.0f);
+    auto rowv = [&](int row, int st) { return *reinterpret_cast<const bf16x8*>(T + row * kRP + 16 * st + 8 * h); };
+    // (gradient rows, activation rows, weight offset, bias offset, out rows, in cols)
+    #pragma unroll
+    for (int layer = 0; layer < 3; ++layer) {
+        const int grow = layer == 0 ? 192 : (layer == 1 ? 256 : 320);
+        const int arow = layer == 0 ? 0 : (layer == 1 ? 64 : 128);
+        const int woff = layer == 0 ? kOffW1 : (layer == 1 ? kOffW2 : kOffW3);
+        const int boff = layer == 0 ? kOffB1 : (layer == 1 ? kOffB2 : kOffB3);
+        const int nout = layer == 2 ? kS : kH;
+        const int nin = layer == 0 ? kIn : kH;
+        for (int mt = 0; mt < nout / 32; ++mt) {
+            f32x16 acc0 = zero16(), acc1 = zero16(), accb = zero16();
+            #pragma unroll
+            for (int st = 0; st < 2; ++st) {
+                const bf16x8 av = rowv(grow + 32 * mt + m, st);
+                acc0 = mma(av, rowv(arow + m, st), acc0);
+                acc1 = mma(av, rowv(arow + 32 + m, st), acc1);
+                accb = mma(av, ones, accb);
+            }
+            #pragma unroll
+            for (int rr = 0; rr < 16; ++rr) {
+                const int o = 32 * mt + acc_row(rr, h);
+                if (m < nin) out[woff + o * nin + m] = acc0[rr];
+                if (32 + m < nin) out[woff + o * nin + 32 + m] = acc1[rr];
+                if (m == 0) out[boff + o] = accb[rr];
+            }
         }
-        for (int k = 0; k < kIn; ++k) out[kOffW1 + o * kIn + k] = acc[k];
-        out[kOffB1 + o] = bacc;
     }
-    {
-        float acc[kH];
-        for (int k = 0; k < kH; ++k) acc[k] = 0.0f;
-        float bacc = 0.0f;
-        for (int rr = 0; rr < kRaysPerBlock; ++rr) {
-            const float g = sD2[rr * kH + o];
-            bacc += g;
-            for (int k = 0; k < kH; ++k) acc[k] += g * sH1[rr * kH + k];
-        }
-        for (int k = 0; k < kH; ++k) out[kOffW2 + o * kH + k] = acc[k];
-        out[kOffB2 + o] = bacc;
-    }
-    if (o < kS) {
-        float acc[kH];
-        for (int k = 0; k < kH; ++k) acc[k] = 0.0f;
-        float bacc = 0.0f;
-        for (int rr = 0; rr < kRaysPerBlock; ++rr) {
-            const float g = sDz[rr * kS + o];
-            bacc += g;
-            for (int k = 0; k < kH; ++k) acc[k] += g * sH2[rr * kH + k];
-        }
-        for (int k = 0; k < kH; ++k) out[kOffW3 + o * kH + k] = acc[k];
-        out[kOffB3 + o] = bacc;
-    }
-    if (t == 0) loss_part[blockIdx.x] = kl;
+    if (lane == 0) loss_part[wglob] = kl;
 }
 
 __global__ void proposal_reduce_kernel(const float* __restrict__ partial, const float* __restrict__ loss_part,
-                                       int nblk, float* __restrict__ grad, float* __restrict__ loss) {
+                                       int nwaves, float* __restrict__ grad, float* __restrict__ loss) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p < kParams) {
         float s = 0.0f;
-        for (int b = 0; b < nblk; ++b) s += partial[static_cast<int64_t>(b) * kPStride + p];
+        for (int b = 0; b < nwaves; ++b) s += partial[static_cast<int64_t>(b) * kPStride + p];
         grad[p] += s;
     }
     if (p == 0 && loss) {
         float s = 0.0f;
-        for (int b = 0; b < nblk; ++b) s += loss_part[b];
+        for (int b = 0; b < nwaves; ++b) s += loss_part[b];
         *loss = s;
     }
 }
@@ -307,8 +424,8 @@ int64_t dvgo_prop_param_count(void) { return kParams; }
 
 size_t dvgo_proposal_workspace_bytes(int32_t B) {
     if (B < 0) return 0;
-    const size_t nblk = (static_cast<size_t>(B) + kRaysPerBlock - 1) / kRaysPerBlock;
-    return dvgo::align_up(nblk * kPStride * 4, 256) + dvgo::align_up(nblk * 4, 256);
+    const size_t nw = (static_cast<size_t>(B) + kRaysPerWave * kWaves - 1) / (kRaysPerWave * kWaves) * kWaves;
+    return dvgo::align_up(nw * kPStride * 4, 256) + dvgo::align_up(nw * 4, 256);
 }
 
 // prop == NULL: `logits` is an input and only the selection runs.
@@ -320,7 +437,7 @@ int32_t dvgo_proposal_fwd(const float* rays_o, const float* rays_d, const float*
     if (B > 0 && !logits) return DVGO_E_ARG;
     if (!(cum_frac > 0.0f && cum_frac <= 1.0f) || !(min_mass >= 0.0f && min_mass <= 1.0f)) return DVGO_E_ARG;
     if (B == 0) return DVGO_OK;
-    DVGO_LAUNCH(K_PROP_FWD, proposal_fwd_kernel, dim3((B + kRaysPerBlock - 1) / kRaysPerBlock), dim3(kRaysPerBlock), 0,
+    DVGO_LAUNCH(K_PROP_FWD, proposal_fwd_kernel, dim3((B + 127) / 128), dim3(256), 0,
                        dvgo::as_stream(stream), a, prop != nullptr, cum_frac, min_mass, logits, pred_mass, seg_mask);
     return dvgo::launch_status();
 }
@@ -334,16 +451,16 @@ int32_t dvgo_proposal_bwd(const float* rays_o, const float* rays_d, const float*
     if (B > 0 && (!seg_w || !log_t_end || !grad_prop)) return DVGO_E_ARG;
     if (workspace_bytes < dvgo_proposal_workspace_bytes(B) || (B > 0 && !workspace)) return DVGO_E_CAPACITY;
     if (B == 0) return DVGO_OK;
-    const int nblk = (B + kRaysPerBlock - 1) / kRaysPerBlock;
+    const int nblk = (B + 127) / 128;
+    const int nw = nblk * kWaves;
     float* partial = static_cast<float*>(workspace);
     float* loss_part = reinterpret_cast<float*>(static_cast<char*>(workspace) +
-                                                dvgo::align_up(static_cast<size_t>(nblk) * kPStride * 4, 256));
+                                                dvgo::align_up(static_cast<size_t>(nw) * kPStride * 4, 256));
     hipStream_t s = dvgo::as_stream(stream);
-    DVGO_LAUNCH(K_PROP_BWD, proposal_bwd_kernel, dim3(nblk), dim3(kRaysPerBlock), 0, s, a, seg_w, log_t_end, partial,
-                       loss_part);
+    DVGO_LAUNCH(K_PROP_BWD, proposal_bwd_kernel, dim3(nblk), dim3(256), 0, s, a, seg_w, log_t_end, partial, loss_part);
     if (int32_t st = dvgo::launch_status()) return st;
     DVGO_LAUNCH(K_PROP_REDUCE, proposal_reduce_kernel, dim3((kParams + 255) / 256), dim3(256), 0, s, partial, loss_part,
-                       nblk, grad_prop, loss);
+                nw, grad_prop, loss);
     return dvgo::launch_status();
 }
 

@@ -26,7 +26,8 @@ namespace {
 constexpr int kMaxBwdBlocks = 256;
 
 struct WsLayout {
-    size_t base, pe, w1p, w2p, w2tp, w1pb, w2pb, w2tpb, raw, feat, col, partial, cell_count, cell_start, scan_tmp,
+    size_t base, pe, w1p, w2p, w2tp, w1pb, w2pb, w2tpb, w3pb, w3tpb, w1tpb, raw, feat, col, partial, cell_count,
+        cell_start, scan_tmp,
         cell_rank, rec, total;
 };
 
@@ -48,6 +49,9 @@ WsLayout ws_layout(int64_t B, int64_t cap, int64_t ncell) {
     L.w1pb = take(kW1PackBF16 * 2);
     L.w2pb = take(kW2PackBF16 * 2);
     L.w2tpb = take(kW2PackBF16 * 2);
+    L.w3pb = take(kW3PackBF16 * 2);
+    L.w3tpb = take(kW3TPackBF16 * 2);
+    L.w1tpb = take(kW1TPackBF16 * 2);
     L.raw = take(static_cast<size_t>(cap) * 4);
     L.feat = take(static_cast<size_t>(cap) * kC * 4);
     L.col = take(static_cast<size_t>(cap) * 4 * 4);
@@ -678,6 +682,10 @@ int32_t run_prep(const Common& cm, const dvgo_mlp* mlp, hipStream_t s) {
         pk.w1pb = reinterpret_cast<uint16_t*>(cm.ws + cm.L.w1pb);
         pk.w2pb = reinterpret_cast<uint16_t*>(cm.ws + cm.L.w2pb);
         pk.w2tpb = reinterpret_cast<uint16_t*>(cm.ws + cm.L.w2tpb);
+        pk.w3 = mlp->w3;
+        pk.w3pb = reinterpret_cast<uint16_t*>(cm.ws + cm.L.w3pb);
+        pk.w3tpb = reinterpret_cast<uint16_t*>(cm.ws + cm.L.w3tpb);
+        pk.w1tpb = reinterpret_cast<uint16_t*>(cm.ws + cm.L.w1tpb);
         pk.bf16 = mlp->precision == DVGO_BF16;
         launch_pack(pk, s);
         if (int32_t st = dvgo::launch_status()) return st;
@@ -727,6 +735,9 @@ MlpArgs make_mlp_args(const Common& cm, const dvgo_mlp* mlp, const int64_t* n_ke
     ma.w1pb = reinterpret_cast<const uint16_t*>(cm.ws + cm.L.w1pb);
     ma.w2pb = reinterpret_cast<const uint16_t*>(cm.ws + cm.L.w2pb);
     ma.w2tpb = reinterpret_cast<const uint16_t*>(cm.ws + cm.L.w2tpb);
+    ma.w3pb = reinterpret_cast<const uint16_t*>(cm.ws + cm.L.w3pb);
+    ma.w3tpb = reinterpret_cast<const uint16_t*>(cm.ws + cm.L.w3tpb);
+    ma.w1tpb = reinterpret_cast<const uint16_t*>(cm.ws + cm.L.w1tpb);
     ma.feat = reinterpret_cast<float*>(cm.ws + cm.L.feat);
     ma.col = reinterpret_cast<float*>(cm.ws + cm.L.col);
     ma.partial = reinterpret_cast<float*>(cm.ws + cm.L.partial);

@@ -70,10 +70,11 @@ class FineModel:
     def lr(self, base: float) -> float:
         return base * 0.1 ** (self.t / self.cfg.decay_steps)
 
-    def sample(self, rays_o, rays_d, jitter, seg_mask=None) -> api.Samples:
+    def sample(self, rays_o, rays_d, jitter, seg_mask=None, capacity=None) -> api.Samples:
         c = self.cfg
         return api.sample_rays(rays_o, rays_d, jitter, self.grid.box_min, self.grid.box_max, c.step, c.max_samples,
-                               coarse=self.coarse, seg_mask=seg_mask, morton=c.morton, capacity=c.capacity)
+                               coarse=self.coarse, seg_mask=seg_mask, morton=c.morton,
+                               capacity=c.capacity if capacity is None else capacity)
 
     def render(self, s: api.Samples, **kw) -> dict:
         c = self.cfg
@@ -100,3 +101,64 @@ class FineModel:
         self.backward(s, out, grad)
         self.adam()
         return {"loss": loss, "samples": s, "rgb": out["rgb"]}
+
+
+class ProposalModel:
+    """Learned segment proposal (not in the paper): network weights with
+    their Adam state and the selection thresholds.  Each training step it
+    predicts a segment mask for every ray of the batch, and learns from a
+    density-only pass of the fine model on a sub-batch (KL to the segment
+    weight sums and the final transmittance)."""
+
+    def __init__(self, flat: torch.Tensor, box_min, box_max, lr: float = 1e-3, cum_frac: float = 0.99,
+                 min_mass: float = 0.9, sub_fraction: int = 8):
+        self.st = AdamState.of(flat)
+        self.box_min, self.box_max = tuple(box_min), tuple(box_max)
+        self.lr, self.cum_frac, self.min_mass, self.sub = lr, cum_frac, min_mass, sub_fraction
+        self.t = 0
+
+    @property
+    def flat(self) -> torch.Tensor:
+        return self.st.p
+
+    def masks(self, s: api.Samples):
+        return api.proposal_fwd(s, self.box_min, self.box_max, self.flat, self.cum_frac, self.min_mass)
+
+    def learn(self, model: "FineModel", rays_o, rays_d, jitter) -> torch.Tensor:
+        """One proposal update from a density-only pass on the given rays."""
+        s = model.sample(rays_o, rays_d, jitter)
+        tgt = api.render_fwd(model.grid, None, s, model.cfg.bg, want_seg_w=True, want_depth_acc=False)
+        loss = api.proposal_bwd(s, self.box_min, self.box_max, self.flat, tgt["seg_w"], tgt["log_t_end"],
+                                self.st.g)
+        self.t += 1
+        api.adam_step(self.st.p, self.st.g, self.st.m, self.st.v, self.lr, self.t)
+        return loss
+
+
+def proposal_train_step(model: FineModel, prop: ProposalModel, rays_o, rays_d, target, jitter=None,
+                        learn: bool = True) -> dict:
+    """One iteration of the proposal form: clip and count (no list), predict
+    segment masks, sample only the selected segments (all of them where the
+    proposal falls back), render / adjoint / Adam, then update the proposal
+    on the first 1/sub of the batch."""
+    s0 = api.sample_rays(rays_o, rays_d, jitter, model.grid.box_min, model.grid.box_max, model.cfg.step,
+                         model.cfg.max_samples, capacity=0)
+    _, mass, mask = prop.masks(s0)
+    res = model.train_step(rays_o, rays_d, target, jitter, seg_mask=mask)
+    if learn:
+        k = max(rays_o.shape[0] // prop.sub, 1)
+        res["prop_loss"] = prop.learn(model, rays_o[:k], rays_d[:k], jitter[:k] if jitter is not None else None)
+    res["mask"] = mask
+    res["mass"] = mass
+    return res
+
+
+@torch.no_grad()
+def render_rays(model: FineModel, rays_o, rays_d, chunk: int = 1 << 16) -> torch.Tensor:
+    """Colour of every ray with the plain sampler (no jitter), in chunks."""
+    out = torch.empty((rays_o.shape[0], 3), dtype=torch.float32, device=rays_o.device)
+    for a in range(0, rays_o.shape[0], chunk):
+        b = min(a + chunk, rays_o.shape[0])
+        s = model.sample(rays_o[a:b].contiguous(), rays_d[a:b].contiguous(), None)
+        out[a:b] = model.render(s, want_depth_acc=False)["rgb"]
+    return out

@@ -47,7 +47,7 @@ def pixel_rays(c2w: np.ndarray, center, H: int, W: int, focal: float, pi, pj):
     d = dc @ np.asarray(c2w, dtype=np.float64).T
     d /= np.linalg.norm(d, axis=-1, keepdims=True)
     o = np.broadcast_to(np.asarray(center, dtype=np.float64), d.shape)
-    return o.astype(np.float32), d.astype(np.float32)
+    return np.ascontiguousarray(o, dtype=np.float32), np.ascontiguousarray(d, dtype=np.float32)
 
 
 def cube_vertex_cameras(radius: float = 4.0) -> np.ndarray:

@@ -1,0 +1,88 @@
+"""GPU parity of the learned proposal: the segment selection bit-exact from
+the same float32 logits, the bfloat16 network forward and backward against
+the oracle's bfloat16 form (tolerance 1e-3 normwise: the float32 encoding
+may round to a neighbouring bfloat16 value; measured values printed)."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from tests.helpers import np_of, report, to_dev
+
+pytestmark = pytest.mark.gpu
+F32 = np.float32
+
+
+def _prop_weights(seed):
+    rng = np.random.default_rng(seed)
+    Ws, bs = synth.xavier_uniform_mlp(rng, (54, 64, 64, 32))
+    Ws = [(w * 3).astype(F32) for w in Ws]
+    bs = [(rng.normal(size=b.shape) * 0.5).astype(F32) for b in bs]
+    flat = np.concatenate([Ws[0].ravel(), bs[0], Ws[1].ravel(), bs[1], Ws[2].ravel(), bs[2]]).astype(F32)
+    return Ws, bs, flat
+
+
+def _samples(P):
+    from paper_2111_11215_amd import api
+    return api.sample_rays(to_dev(P.rays.o), to_dev(P.rays.d), None, P.box_min, P.box_max, P.step, P.max_samples)
+
+
+def test_selection_bit_exact_from_logits(gpu_lib):
+    from paper_2111_11215_amd import api
+    P = synth.tiny_config(0, n_rays=2048)
+    s = _samples(P)
+    rng = np.random.default_rng(4)
+    z = (rng.normal(size=(2048, 32)) * rng.uniform(0.1, 6, (2048, 1)) + rng.normal(size=(2048, 1)) * 3).astype(F32)
+    z[:64] = -20.0         # one dominant segment and ten tied ones: nine of the
+    z[:64, 10] = 20.0      # ties are needed, so the lower indices must win
+    z[:64, 0:10] = 15.4
+    z[64:128] = -20.0      # tiny mass: fallback
+    _, mass, mask = api.proposal_fwd(s, P.box_min, P.box_max, None, logits=to_dev(z))
+    want = O.proposal_select(z.astype(np.float64))
+    valid = np_of(s.valid).astype(bool)
+    want = np.where(valid, want, np.uint32(0xFFFFFFFF))
+    assert np.array_equal(np_of(mask).view(np.uint32), want)
+    tie_rows = np.where(valid[:64])[0]
+    assert np.all(want[tie_rows] == np.uint32((1 << 10) | 0x1FF))
+    _, m_ref = O.proposal_probs(z.astype(np.float64))
+    assert np.max(np.abs(np_of(mass) - m_ref)) < 1e-6
+
+
+def test_proposal_forward_backward_bf16(gpu_lib):
+    import torch
+    from paper_2111_11215_amd import api
+    P = synth.tiny_config(1, n_rays=1024)
+    s = _samples(P)
+    Ws, bs, flat = _prop_weights(2)
+    ft = to_dev(flat)
+    logits, mass, mask = api.proposal_fwd(s, P.box_min, P.box_max, ft)
+    tn, tf, v = O.ray_box_clip(P.rays.o, P.rays.d, P.box_min, P.box_max)
+    enc = O.proposal_encoding(P.rays.o, P.rays.d, tn, P.box_min, P.box_max)
+    z, cache = O.proposal_forward(Ws, bs, enc, bf16=True)
+    assert report("logits", np_of(logits)[v], z[v])[0] <= 1e-3
+    # targets from the oracle's density-only render of a random grid
+    prm = O.Params(P.density, P.feat, P.Ws, P.bs, P.box_min, P.box_max, 0.0)
+    samp = O.sample_rays(P.rays.o, P.rays.d, None, P.box_min, P.box_max, P.step, P.max_samples)
+    ref = O.render_forward(prm, P.rays.o, P.rays.d, None, samp, P.step, P.bg, with_color=False)
+    seg_w = ref["seg_w"].astype(F32)
+    lte = ref["log_t_end"].astype(F32)
+    grad = torch.zeros_like(ft)
+    loss = api.proposal_bwd(s, P.box_min, P.box_max, ft, to_dev(seg_w), to_dev(lte), grad)
+    p = O.proposal_targets(seg_w.astype(np.float64), np.exp(lte.astype(np.float64)))
+    zc = z.copy()
+    L, dz = O.proposal_loss_grad(zc[v], p[v])
+    # the device averages over the whole batch (invalid rays contribute 0)
+    L = L * v.sum() / len(v)
+    dz_full = np.zeros_like(z)
+    dz_full[v] = dz * v.sum() / len(v)
+    cache_v = cache
+    dWs, dbs = O.proposal_backward(Ws, cache_v, dz_full)
+    assert abs(float(np_of(loss)[0]) - L) <= 1e-3 * abs(L) + 1e-6
+    g = np_of(grad)
+    off = 0
+    for name, ref_t in zip(["W1", "b1", "W2", "b2", "W3", "b3"], [dWs[0], dbs[0], dWs[1], dbs[1], dWs[2], dbs[2]]):
+        n = ref_t.size
+        nw, _ = report(name, g[off:off + n].reshape(ref_t.shape), ref_t)
+        assert nw <= 1e-3, name
+        off += n

@@ -543,3 +543,29 @@ def test_bf16_backward_close_to_exact():
     assert np.linalg.norm(d1[:, :12] - d0[:, :12]) / np.linalg.norm(d0[:, :12]) < 2e-2
     for a, b in zip(W1g + b1g, W0g + b0g):
         assert np.linalg.norm(a - b) / np.linalg.norm(b) < 2e-2
+
+
+def test_proposal_bf16_backward_close_to_exact():
+    """Proposal network: with the same ReLU masks and activations the
+    bfloat16 form's gradients differ from the exact ones only by operand
+    rounding; with bfloat16-exact gradients and weights it is exact."""
+    rng = np.random.default_rng(5)
+    Ws, bs = synth.xavier_uniform_mlp(rng, (54, 64, 64, 32))
+    enc = rng.normal(size=(300, 54))
+    dz = rng.normal(size=(300, 32))
+    z1, c1 = O.proposal_forward(Ws, bs, enc, bf16=True)
+    g1 = O.proposal_backward(Ws, c1, dz)
+    g0 = O.proposal_backward(Ws, dict(c1, bf16=False), dz)
+    for a, b in zip(g1[0] + g1[1], g0[0] + g0[1]):
+        assert np.linalg.norm(a - b) / np.linalg.norm(b) < 2e-2
+    # a single nonzero logit gradient of 1 per ray, one-hot W3 rows and W2 = I/2:
+    # every propagated gradient is a power of two, so no rounding happens
+    Wx = [O.bf16_round(Ws[0]), np.eye(64) * 0.5, np.zeros((32, 64))]
+    Wx[2][np.arange(32), np.arange(32)] = 1.0
+    dz1 = np.zeros((300, 32))
+    dz1[np.arange(300), rng.integers(0, 32, 300)] = 1.0
+    _, cx = O.proposal_forward(Wx, bs, enc, bf16=True)
+    ga = O.proposal_backward(Wx, cx, dz1)
+    gb = O.proposal_backward(Wx, dict(cx, bf16=False), dz1)
+    for a, b in zip(ga[0] + ga[1], gb[0] + gb[1]):
+        assert np.array_equal(a, b)
