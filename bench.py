@@ -1,17 +1,27 @@
 """Benchmark of the fine-stage per-ray training step on one MI355X.
 
-Workload (default): the full plain configuration - synthetic scene of 64
-soft spheres, 160^3 float32 density and 12-channel feature grids initialised
-as in the paper's fine stage (zero grids, low-density shift with
-alpha_init 1e-2), frozen 100^3 coarse density rasterised from the scene
-with the alpha-mask threshold 1e-4, 8192 rays per iteration drawn with
-replacement from 100 cameras of 800x800 pixels, step half a voxel, the
-39-128-128-3 colour network.  One step = sample + forward + loss + adjoint +
-Adam over all 53.2M grid values and the network, inputs resident in HBM.
+Workload: the full configuration - synthetic scene of 64 soft spheres,
+160^3 float32 density and 12-channel feature grids initialised as in the
+paper's fine stage (zero grids, low-density shift with alpha_init 1e-2),
+frozen 100^3 coarse density rasterised from the scene with the alpha-mask
+threshold 1e-4, 8192 rays per iteration drawn with replacement from 100
+cameras of 800x800 pixels, step half a voxel, the 39-128-128-3 colour
+network.  One step = the whole hot path over one batch, inputs resident in
+HBM: in the default form (bfloat16 features and network plus the learned
+proposal) clip and count, proposal forward and segment masks, sampling of
+the selected segments, forward, loss, adjoint with the grids' Adam step,
+the network's Adam step, and the proposal's own update from a density-only
+pass on 1/8 of the batch.  Forms: proposal (default), bf16, plain (float32,
+no proposal).
+
+Before timing, the comparison trains the plain float32, the bfloat16 and the
+bfloat16 + proposal forms for --compare-iters iterations each from identical
+states on identical batches (throughput and held-out PSNR of each); the
+timed steps continue training the selected form from its trained state.
 
 Metric: ray-samples/s = (sum over the timed iterations of the uniform
-in-box samples of each batch, before coarse skipping) / wall time of the
-timed iterations (HIP-synchronised on both sides).
+in-box samples of each batch, before coarse or proposal skipping) / wall
+time of the timed iterations (HIP-synchronised on both sides).
 
 Prints one JSON line.
 """
@@ -35,6 +45,10 @@ FLOP_MLP_BWD = FLOP_MLP_FWD + 2 * (3 * 128 + 128 * 128 + 12 * 128) + 2 * (3 * 12
 BYTES_SCATTER = 8 * (1 + 12) * 4 * 2 + (4 + 48) + 8
 BYTES_GATHER_F32 = 8 * 4 + 8 * 48 + (4 + 48) + 8
 BYTES_GATHER_BF16 = 8 * 4 + 8 * 24 + (4 + 48) + 8
+# fused grid Adam per vertex: density and 12 features, each p, m, v read and
+# written (24 B); bfloat16 copy 2 B per feature; binned sample records 64 B
+BYTES_GRID_ADAM_VERTEX = 24 * 13
+BYTES_REC = 64
 PEAK = {"hbm": 8000.0, "f32": 157.3, "bf16": 2500.0}
 
 
@@ -47,29 +61,28 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--form", choices=["plain", "bf16"], default="plain")
-    ap.add_argument("--batches", type=int, default=8)
+    ap.add_argument("--form", choices=["proposal", "bf16", "plain"], default="proposal")
+    ap.add_argument("--pretrain", type=int, default=0,
+                    help="with --compare-iters 0: training iterations of the timed form before timing")
     ap.add_argument("--rays", type=int, default=8192)
     ap.add_argument("--profile-kernel", default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=256)
-    ap.add_argument("--morton", type=int, default=0)
     ap.add_argument("--profile-steps", type=int, default=10,
                     help="steps per kernel of the event-timed pass (0: skip it)")
     ap.add_argument("--compare-iters", type=int, default=1000,
-                    help="iterations of the plain-fp32 / bf16 / bf16+proposal training comparison (0: skip)")
+                    help="iterations of the plain-fp32 / bf16 / bf16+proposal training comparison (0: skip);"
+                         " the timed form continues from its trained state")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
 
 
 def setup(args):
-    import numpy as np
     import torch
 
     import synth
-    from paper_2111_11215_amd import api, train
-    from paper_2111_11215_amd._lib import DVGO_BF16, DVGO_F32
+    from paper_2111_11215_amd import api
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -85,35 +98,8 @@ def setup(args):
     bits = api.coarse_mask_build(raw_t, bmin, bmax, thr)
     coarse = (bits, bmin, bmax, raw.shape)
     spheres = torch.as_tensor(sp.as_f32_table()).to(dev)
-    batches = []
-    for i in range(args.batches):
-        rng = np.random.default_rng(1000 + i)
-        o, d, *_ = synth.draw_pixels_with_replacement(rng, cams, 800, 800, 1000.0, args.rays)
-        jit = rng.random(args.rays).astype(np.float32)
-        ot, dt, jt = (torch.as_tensor(a).to(dev) for a in (o, d, jit))
-        tgt = api.scene_render(ot, dt, spheres, bmin, bmax, step / 4)
-        batches.append(dict(o=ot, d=dt, j=jt, target=tgt, o_np=o, d_np=d, j_np=jit))
-    rng_w = np.random.default_rng(7)
-    Ws, bs = synth.xavier_uniform_mlp(rng_w, (39, 128, 128, 3))
-    flat = api.flat_from([Ws[0], bs[0], Ws[1], bs[1], Ws[2], bs[2]], api.MLP_SHAPES, dev)
-    bf16 = args.form == "bf16"
-    cfg = train.FineConfig(step=step, max_samples=max_samples, precision=DVGO_BF16 if bf16 else DVGO_F32,
-                           bf16_feat=bf16, morton=bool(args.morton))
-    model = train.FineModel(torch.zeros((n, n, n), device=dev), torch.zeros((n, n, n, 12), device=dev), flat,
-                            bmin, bmax, b, cfg, coarse=coarse)
-    # numerators: uniform in-box samples and evaluated samples of each batch
-    for bt in batches:
-        s = model.sample(bt["o"], bt["d"], bt["j"])
-        bt["n_uniform"] = int(s.n_uniform.sum().item())
-        bt["n_kept"] = int(s.n_kept.item())
-    return dict(model=model, batches=batches, step=step, max_samples=max_samples, b=b, raw=raw, bits=bits,
-                coarse=coarse, spheres=sp, spheres_t=spheres, bmin=bmin, bmax=bmax, n=n, cams=cams, held=held)
-
-
-def run_steps(model, batches, k0, k):
-    for i in range(k):
-        bt = batches[(k0 + i) % len(batches)]
-        model.train_step(bt["o"], bt["d"], bt["target"], bt["j"])
+    return dict(step=step, max_samples=max_samples, b=b, raw=raw, bits=bits, coarse=coarse, spheres=sp,
+                spheres_t=spheres, bmin=bmin, bmax=bmax, n=n, cams=cams, held=held)
 
 
 def make_batches(ctx, n_iter, rays, seed0=1000):
@@ -184,21 +170,27 @@ def new_proposal(ctx):
     return train.ProposalModel(flat, ctx["bmin"], ctx["bmax"])
 
 
-def compare_forms(ctx, iters, rays):
+FORMS = {"plain": ("plain_fp32", False, False), "bf16": ("bf16", True, False),
+         "proposal": ("bf16_proposal", True, True)}
+
+
+def compare_forms(ctx, iters, rays, keep):
     """Train the plain fp32 form, the bf16 form and the bf16 + learned
     proposal form from identical initial states on identical batches;
     report throughput (uniform-equivalent ray-samples/s of the whole
     iteration, proposal work included) and mean PSNR on the 10 held-out
     views, plus what the trained proposal gains over an untrained one and
-    over none."""
+    over none.  Returns (report, (model, proposal) of the form ``keep``)."""
     from paper_2111_11215_amd import experiment
     log(f"bench: comparison, {iters} iterations per form")
     batches = make_batches(ctx, iters, rays)
     views = make_views(ctx)
     res = {"iters": iters, "rays_per_iter": rays, "views": len(views)}
-    for name, bf16, use_prop in (("plain_fp32", False, False), ("bf16", True, False), ("bf16_proposal", True, True)):
+    kept = None
+    for form in ("plain", "bf16", "proposal"):
+        name, bf16, use_prop = FORMS[form]
         model = new_model(ctx, bf16)
-        if name == "plain_fp32":
+        if form == "plain":
             experiment.count_uniform(model, batches)
         prop = new_proposal(ctx) if use_prop else None
         st = experiment.run(model, batches, iters, prop=prop, record_every=100)
@@ -219,31 +211,34 @@ def compare_forms(ctx, iters, rays):
                     "trained": experiment.proposal_render_psnr(model, prop, views[:2])}}
         res[name] = entry
         log(f"bench: {name}: {entry['ms_per_step']:.3f} ms/step, psnr {entry['psnr_db']:.3f} dB")
-        del model, prop
+        if form == keep:
+            kept = (model, prop)
+        else:
+            del model, prop
     res["delta_psnr_db"] = res["bf16_proposal"]["psnr_db"] - res["plain_fp32"]["psnr_db"]
     res["speedup_vs_plain_fp32"] = res["bf16_proposal"]["ray_samples_per_s"] / res["plain_fp32"]["ray_samples_per_s"]
     res["gate_pass"] = bool(res["delta_psnr_db"] >= -0.1 and res["speedup_vs_plain_fp32"] > 1.0)
-    return res
+    return res, kept
 
 
-def cpu_baseline(ctx, rays):
-    """The oracle as it stands, one thread, on a bounded sample: the full
-    step (sample, forward, loss, adjoint) for the first `rays` rays of batch 0
-    scaled to the 8192-ray batch, plus one oracle Adam step over every
-    parameter of the configuration."""
+def cpu_baseline(ctx, rays, B):
+    """The oracle as it stands, one thread, on a bounded sample: the plain
+    float64 step (sample, forward, loss, adjoint) for ``rays`` rays drawn as
+    the first batch is drawn, scaled to the B-ray batch, plus one oracle Adam
+    step over every parameter of the configuration."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     import oracle as O
     import synth
 
-    bt = ctx["batches"][0]
-    B = bt["o_np"].shape[0]
-    o, d, j = bt["o_np"][:rays], bt["d_np"][:rays], bt["j_np"][:rays]
+    rng = np.random.default_rng(1000)
+    flat = rng.integers(0, len(ctx["cams"]) * 800 * 800, size=B)[:rays]
+    o, d, *_ = synth.scenes._rays_for_flat_pixels(ctx["cams"], 800, 800, 1000.0, flat)
+    j = rng.random(B).astype(np.float32)[:rays]
     n = ctx["n"]
-    tgt = bt["target"][:rays].cpu().numpy()
-    rng_w = np.random.default_rng(7)
-    Ws, bs = synth.xavier_uniform_mlp(rng_w, (39, 128, 128, 3))
+    tgt = np.zeros((rays, 3))
+    Ws, bs = synth.xavier_uniform_mlp(np.random.default_rng(7), (39, 128, 128, 3))
     thr = O.coarse_raw_threshold(synth.FULL_TAU, ctx["step"])
     bits = O.coarse_cell_bits(ctx["raw"], thr)
     dens = np.zeros((n, n, n), np.float32)
@@ -263,11 +258,13 @@ def cpu_baseline(ctx, rays):
         for w_, gw in zip(Ws + bs, gr["Ws"] + gr["bs"]):
             O.adam_step(w_, gw, np.zeros(w_.shape), np.zeros(w_.shape), 1e-3, 0.9, 0.999, 1e-8, 1)
         t_adam = time.perf_counter() - t0
-    per_iter = t_rays * (B / rays) + t_adam
-    return {"value": bt["n_uniform"] / per_iter, "unit": "ray-samples/s", "cores": 1, "kind": "oracle",
-            "sample": (f"first {rays} of the {B} rays of batch 0 (sample, forward, loss, adjoint: "
-                       f"{t_rays:.2f} s, scaled x{B / rays:.0f}) + one Adam step over all parameters "
-                       f"({t_adam:.2f} s); 1 thread")}
+    scale = B / rays
+    per_iter = t_rays * scale + t_adam
+    n_uni = float(np.sum(samp["n_uniform"])) * scale
+    return {"value": n_uni / per_iter, "unit": "ray-samples/s", "cores": 1, "kind": "oracle",
+            "sample": (f"plain float64 step of the first {rays} of the {B} rays of the first batch (sample, "
+                       f"forward, loss, adjoint: {t_rays:.2f} s, scaled x{scale:.0f}) + one Adam step over all "
+                       f"{dens.size + feat.size + 22019} parameters ({t_adam:.2f} s); 1 thread")}
 
 
 def calibrate_copy(mib):
@@ -283,32 +280,42 @@ def calibrate_copy(mib):
     print(json.dumps({"copy_mib": mib, "launches": 3}))
 
 
-def roofline(args, model, batches, per_kernel, kname, n_prof, bf16):
+def roofline(per_kernel, kname, n_prof, kept, nv, n_mlp, bf16):
     """Achieved rate of the named kernel: algorithmic work per launch over
-    its event-timed average launch duration."""
-    kept_prof = sum(batches[(args.warmup + i) % len(batches)]["n_kept"] for i in range(n_prof)) / n_prof
+    its event-timed average launch duration.  ``kept`` = evaluated samples
+    per step, ``nv`` = grid vertices."""
     k = per_kernel[kname]
-    # launches per step of the named kernel
-    lps = k["launches"] / n_prof
+    lps = k["launches"] / n_prof            # launches per step
     if kname in ("mlp_bwd", "mlp_fwd"):
-        flop = (FLOP_MLP_BWD if kname == "mlp_bwd" else FLOP_MLP_FWD) * kept_prof / lps
-        achieved = flop / (k["ms_avg"] * 1e-3) / 1e12
+        work = (FLOP_MLP_BWD if kname == "mlp_bwd" else FLOP_MLP_FWD) * kept / lps
+        achieved = work / (k["ms_avg"] * 1e-3) / 1e12
         peak = PEAK["bf16" if bf16 else "f32"]
-        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": None}
+        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak}
     else:
-        per = {"scatter": BYTES_SCATTER, "gather": BYTES_GATHER_BF16 if bf16 else BYTES_GATHER_F32}.get(kname)
-        if kname == "adam":
-            nparam = model.st_density.p.numel() + model.st_feat.p.numel() + model.st_mlp.p.numel()
-            bytes_ = (32 * nparam + (2 * model.st_feat.p.numel() if bf16 else 0)) / lps
+        if kname == "grid_adam":
+            work = BYTES_GRID_ADAM_VERTEX * nv + (2 * 12 * nv if bf16 else 0) + BYTES_REC * kept
+        elif kname == "adam":
+            work = 32 * n_mlp + ((32 * 13 * nv + (2 * 12 * nv if bf16 else 0)) if "grid_adam" not in per_kernel
+                                 or per_kernel["grid_adam"]["launches"] == 0 else 0)
+        elif kname == "gather":
+            work = (BYTES_GATHER_BF16 if bf16 else BYTES_GATHER_F32) * kept
         else:
-            bytes_ = per * kept_prof / lps
-        achieved = bytes_ / (k["ms_avg"] * 1e-3) / 1e9
+            work = BYTES_SCATTER * kept
+        work /= lps
+        achieved = work / (k["ms_avg"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm"], "unit": "GB/s",
-                "frac": achieved / PEAK["hbm"], "traffic": None}
+                "frac": achieved / PEAK["hbm"]}
+    roof["traffic"] = None
     roof["kernel"] = kname
     roof["launch_ms"] = k["ms_avg"]
+    roof["launches_per_step"] = lps
     return roof
+
+
+PROFILED = ("ray_setup", "count_kept", "scan", "fill_kept", "prop_fwd", "prop_bwd", "prop_reduce", "pack",
+            "ray_base", "gather", "mlp_fwd", "compose_fwd", "photo_loss", "compose_bwd", "mlp_bwd", "reduce",
+            "bin_count", "cell_scan", "bin_place", "scatter", "grid_adam", "adam")
+ROOFLINE_MODELS = ("mlp_bwd", "mlp_fwd", "gather", "grid_adam", "adam", "scatter")
 
 
 def main():
@@ -321,49 +328,52 @@ def main():
         print(json.dumps({"error": "this build measures one GPU only: the training step is data-parallel over "
                                    "rays but no multi-GPU path is built; run with --gpus 1"}))
         sys.exit(2)
+    import ctypes
+
     import torch
 
-    from paper_2111_11215_amd import _lib
+    from paper_2111_11215_amd import _lib, experiment
     lib = _lib.load()
     log("bench: setup")
     ctx = setup(args)
-    model, batches = ctx["model"], ctx["batches"]
+    name, bf16, use_prop = FORMS[args.form]
+    out_cmp = None
+    if args.compare_iters > 0:
+        out_cmp, (model, prop) = compare_forms(ctx, args.compare_iters, args.rays, args.form)
+        seed0 = 1000 + args.compare_iters
+    else:
+        model = new_model(ctx, bf16)
+        prop = new_proposal(ctx) if use_prop else None
+        seed0 = 1000
+        if args.pretrain > 0:
+            log(f"bench: pretrain {args.pretrain}")
+            experiment.run(model, make_batches(ctx, args.pretrain, args.rays, seed0), args.pretrain, prop=prop,
+                           record_every=0)
+            seed0 += args.pretrain
+    n_prof = args.profile_steps
+    batches = make_batches(ctx, args.warmup + args.steps, args.rays, seed0)
+    experiment.count_uniform(model, batches)
     log(f"bench: warmup {args.warmup}")
-    run_steps(model, batches, 0, args.warmup)
-    torch.cuda.synchronize()
-    log(f"bench: timed {args.steps}")
-    t0 = time.perf_counter()
-    run_steps(model, batches, args.warmup, args.steps)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    used = [batches[(args.warmup + i) % len(batches)] for i in range(args.steps)]
-    total_uniform = sum(b["n_uniform"] for b in used)
-    total_kept = sum(b["n_kept"] for b in used)
-    value = total_uniform / elapsed
-    ms = 1e3 * elapsed / args.steps
-    log(f"bench: {value:.4e} ray-samples/s, {ms:.3f} ms/step, kept {total_kept / args.steps:.0f}/step")
+    experiment.run(model, batches, args.warmup, prop=prop, record_every=0)
+    log(f"bench: timed {args.steps} ({name})")
+    st = experiment.run(model, batches, args.steps, prop=prop, record_every=0, start=args.warmup)
+    value = st.samples_per_s
+    ms = 1e3 * st.seconds / args.steps
+    timed = [batches[args.warmup + i] for i in range(args.steps)]
+    kept = experiment.evaluated_per_step(model, timed, prop, n=min(8, len(timed)))
+    log(f"bench: {value:.4e} ray-samples/s, {ms:.3f} ms/step, evaluated {kept:.0f}/step")
 
-    # dominant-kernel timing: events around that kernel, on its own stream
-    bf16 = args.form == "bf16"
-    kname = args.profile_kernel if args.profile_kernel != "auto" else "mlp_bwd"
+    # per-kernel timing: HIP events around each launch of one kernel at a
+    # time, recorded on the launch's own stream, over n_prof more steps
     per_kernel = {}
-    names = ("gather", "mlp_fwd", "compose_fwd", "compose_bwd", "mlp_bwd", "scatter", "bin_count", "cell_scan",
-             "bin_place", "adam", "fill_kept", "count_kept", "ray_setup", "scan", "reduce", "pack", "ray_base",
-             "photo_loss")
-    n_prof = min(args.steps, args.profile_steps)
-    for name in names if n_prof > 0 else ():
-        _lib.check("dvgo_profile_enable", lib.dvgo_profile_enable(_lib.KERNEL_IDS[name]))
-        run_steps(model, batches, args.warmup, n_prof)
-        tot = ctypes_double()
-        cnt = ctypes_int64()
-        _lib.check("dvgo_profile_read", lib.dvgo_profile_read(tot, cnt))
-        per_kernel[name] = {"ms_total": tot.value, "launches": cnt.value,
-                            "ms_avg": tot.value / max(cnt.value, 1)}
+    for kn in PROFILED if n_prof > 0 else ():
+        _lib.check("dvgo_profile_enable", lib.dvgo_profile_enable(_lib.KERNEL_IDS[kn]))
+        experiment.run(model, batches, n_prof, prop=prop, record_every=0, start=args.warmup)
+        tot, cnt = ctypes.c_double(), ctypes.c_int64()
+        _lib.check("dvgo_profile_read", lib.dvgo_profile_read(ctypes.byref(tot), ctypes.byref(cnt)))
+        if cnt.value:
+            per_kernel[kn] = {"ms_total": tot.value, "launches": cnt.value, "ms_avg": tot.value / cnt.value}
     lib.dvgo_profile_enable(-1)
-    out_extra = {}
-    if n_prof > 0:
-        out_extra["roofline"] = roofline(args, model, batches, per_kernel, kname, n_prof, bf16)
-        out_extra["kernels_ms_per_step"] = {n_: v["ms_total"] / n_prof for n_, v in per_kernel.items()}
     out = {
         "metric": "fwd+bwd ray-samples/s per train iter",
         "value": value,
@@ -377,36 +387,34 @@ def main():
         "vs_baseline": None,
         "dtype": "bf16" if bf16 else "f32",
         "data": "synthetic",
-        "config": {"workload": ("full plain configuration: 64-sphere synthetic scene, 160^3 fp32 density + "
-                                "12-ch feature grids, 100^3 coarse alpha mask (tau 1e-4), 8192 rays/iter from "
-                                "100 cameras 800x800, step 0.5 voxel, 39-128-128-3 MLP, Adam")
-                   + (" [BF16 features + BF16 MLP]" if bf16 else ""),
-                   "rays_per_iter": args.rays, "grid": 160, "coarse": 100, "max_samples": ctx["max_samples"],
-                   "morton": bool(args.morton)},
-        "evaluated_samples_per_step": total_kept / args.steps,
-        "uniform_samples_per_step": total_uniform / args.steps,
-        "rays_per_s": args.rays * args.steps / elapsed,
+        "config": {"workload": ("full configuration: 64-sphere synthetic scene, 160^3 fp32 density + 12-ch "
+                                "feature grids, 100^3 coarse alpha mask (tau 1e-4), 8192 rays/iter from 100 "
+                                "cameras 800x800, step 0.5 voxel, 39-128-128-3 MLP, Adam; form: "
+                                + {"plain": "plain float32",
+                                   "bf16": "bfloat16 features + bfloat16 MLP",
+                                   "proposal": "bfloat16 features + bfloat16 MLP + learned proposal "
+                                               "(54-64-64-32, top-99% segments, fallback at mass < 0.9)"}[args.form]
+                                + (f", timed after {args.compare_iters} training iterations"
+                                   if args.compare_iters > 0 else f", timed after {args.pretrain} iterations")),
+                   "form": name, "rays_per_iter": args.rays, "grid": ctx["n"], "coarse": 100,
+                   "max_samples": ctx["max_samples"]},
+        "evaluated_samples_per_step": kept,
+        "uniform_samples_per_step": st.uniform_samples / args.steps,
+        "rays_per_s": args.rays * args.steps / st.seconds,
     }
-    out.update(out_extra)
-    if args.compare_iters > 0:
-        del model
-        ctx["model"] = None
-        torch.cuda.empty_cache()
-        out["proposal_comparison"] = compare_forms(ctx, args.compare_iters, args.rays)
+    if per_kernel:
+        kname = args.profile_kernel
+        if kname == "auto":
+            kname = max((k for k in ROOFLINE_MODELS if k in per_kernel), key=lambda k: per_kernel[k]["ms_total"])
+        nv = ctx["n"] ** 3
+        out["roofline"] = roofline(per_kernel, kname, n_prof, kept, nv, model.st_mlp.p.numel(), bf16)
+        out["kernels_ms_per_step"] = {k: v["ms_total"] / n_prof for k, v in per_kernel.items()}
+    if out_cmp is not None:
+        out["proposal_comparison"] = out_cmp
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(ctx, args.cpu_rays)
+        out["cpu_baseline"] = cpu_baseline(ctx, args.cpu_rays, args.rays)
     print(json.dumps(out), flush=True)
-
-
-def ctypes_double():
-    import ctypes
-    return ctypes.c_double()
-
-
-def ctypes_int64():
-    import ctypes
-    return ctypes.c_int64()
 
 
 if __name__ == "__main__":

@@ -209,6 +209,47 @@ int32_t dvgo_render_bwd(const dvgo_field* field /*host*/, const dvgo_mlp* mlp /*
                         const float* grad_acc, float* grad_density, float* grad_feat,
                         float* grad_mlp, void* workspace, size_t workspace_bytes, void* stream);
 
+/* Grid parameters and their Adam moments for dvgo_render_bwd_adam (all
+ * device pointers, float32, updated in place):
+ *   density, density_m, density_v  [nx][ny][nz];
+ *   feat, feat_m, feat_v           [nx][ny][nz][C], 16-byte aligned;
+ *   feat_shadow_bf16               [nx][ny][nz][C] bfloat16 bits, 8-byte
+ *                                  aligned, or NULL (rewritten as bf16(feat)).
+ * lr, beta1, beta2, eps and the step count t >= 1 as in dvgo_adam_step. */
+typedef struct {
+    float* density;
+    float* density_m;
+    float* density_v;
+    float* feat;
+    float* feat_m;
+    float* feat_v;
+    uint16_t* feat_shadow_bf16;
+    float lr, beta1, beta2, eps;
+    int32_t t;
+} dvgo_grid_adam;
+
+/* Backward pass and Adam step of both grids in one call: the result is that
+ * of dvgo_render_bwd into zeroed grid gradients followed by dvgo_adam_step
+ * on the density and the feature grid (the paper's optimiser, Sec. 5.2;
+ * every vertex takes the step, with a zero gradient where no sample touches
+ * it), but the grid gradients never reach memory: each vertex sums its
+ * binned samples' contributions and updates its parameters and moments in
+ * the same thread.  The network gradient is accumulated into grad_mlp as in
+ * dvgo_render_bwd (its Adam step stays a separate dvgo_adam_step).  mlp must
+ * not be NULL.  The field may read the same arrays opt updates (field->density
+ * == opt->density, field->feat == opt->feat or its bfloat16 shadow): all
+ * reads of the grids finish before the update within the call. */
+int32_t dvgo_render_bwd_adam(const dvgo_field* field /*host*/, const dvgo_mlp* mlp /*host*/,
+                             const float* rays_o, const float* rays_d, const float* jitter,
+                             const float* t_near, const int32_t* n_uniform, const int32_t* perm,
+                             const int32_t* ray_offset, const int32_t* sample_ray,
+                             const int32_t* sample_k, const int64_t* n_kept, int64_t capacity,
+                             int32_t B, float step, const float* bg /*host[3]*/,
+                             const float* log_t_end, const float* grad_rgb,
+                             const float* grad_depth, const float* grad_acc,
+                             const dvgo_grid_adam* opt /*host*/, float* grad_mlp,
+                             void* workspace, size_t workspace_bytes, void* stream);
+
 /* Photometric loss of paper Eq. photo_loss: loss = (1/B) sum_r
  * ||rgb_r - target_r||^2 and grad_rgb = 2 (rgb - target)/B.  grad_rgb [B][3]
  * is overwritten; loss (device float, or NULL) is overwritten. */
@@ -237,9 +278,10 @@ int32_t dvgo_proposal_fwd(const float* rays_o, const float* rays_d, const float*
                           const dvgo_prop* prop /*host*/, float cum_frac, float min_mass,
                           float* logits, float* pred_mass, uint32_t* seg_mask, void* stream);
 
-/* Proposal backward: KL(p || q) averaged over the valid rays, with target
+/* Proposal backward: KL(p || q) summed over the valid rays and divided by
+ * the batch size B (invalid rays contribute nothing), with target
  * p = (seg_w[r][0..31], exp(log_t_end[r])) from a density-only render;
- * dL/dz_s = (q_s - p_s)/n_valid.  grad_prop (flat, dvgo_prop_param_count) is
+ * dL/dz_s = (q_s - p_s)/B.  grad_prop (flat, dvgo_prop_param_count) is
  * ACCUMULATED; loss (device float or NULL) is overwritten. */
 int32_t dvgo_proposal_bwd(const float* rays_o, const float* rays_d, const float* t_near,
                           const uint8_t* valid, int32_t B, const dvgo_box* box /*host*/,
@@ -275,7 +317,8 @@ int32_t dvgo_version(void);
  *   10 compose forward, 11 compose backward, 12 MLP backward, 13 vertex
  *   gather (gradient scatter), 14 partial reduce, 15 photo loss, 16 Adam,
  *   17 proposal forward, 18 proposal backward, 19 proposal reduce, 20 scene
- *   render, 21 cell binning count, 22 cell scan, 23 cell binning place. */
+ *   render, 21 cell binning count, 22 cell scan, 23 cell binning place,
+ *   24 vertex gather with the grids' Adam step (dvgo_render_bwd_adam). */
 int32_t dvgo_profile_enable(int32_t kernel_id);
 int32_t dvgo_profile_read(double* total_ms, int64_t* launches);
 

@@ -38,6 +38,12 @@ class Prop(ctypes.Structure):
                 ("b3", c_void_p)]
 
 
+class GridAdam(ctypes.Structure):
+    _fields_ = [("density", c_void_p), ("density_m", c_void_p), ("density_v", c_void_p), ("feat", c_void_p),
+                ("feat_m", c_void_p), ("feat_v", c_void_p), ("feat_shadow_bf16", c_void_p), ("lr", c_float),
+                ("beta1", c_float), ("beta2", c_float), ("eps", c_float), ("t", c_int32)]
+
+
 class DvgoError(RuntimeError):
     def __init__(self, fn: str, status: int, text: str, last: str):
         super().__init__(f"{fn} returned {STATUS.get(status, status)} ({text}) {last}".strip())
@@ -58,6 +64,8 @@ SIGNATURES = {
                                   c_float, POINTER(c_float), P, P, P, P, P, P, P, c_size_t, P]),
     "dvgo_render_bwd": (c_int32, [POINTER(Field), POINTER(Mlp), P, P, P, P, P, P, P, P, P, P, c_int64, c_int32,
                                   c_float, POINTER(c_float), P, P, P, P, P, P, P, P, c_size_t, P]),
+    "dvgo_render_bwd_adam": (c_int32, [POINTER(Field), POINTER(Mlp), P, P, P, P, P, P, P, P, P, P, c_int64, c_int32,
+                                       c_float, POINTER(c_float), P, P, P, P, POINTER(GridAdam), P, P, c_size_t, P]),
     "dvgo_photo_loss": (c_int32, [P, P, c_int32, P, P, P]),
     "dvgo_adam_step": (c_int32, [P, P, P, P, P, c_int64, c_float, c_float, c_float, c_float, c_int32, P]),
     "dvgo_proposal_fwd": (c_int32, [P, P, P, P, c_int32, POINTER(Box), POINTER(Prop), c_float, c_float, P, P, P, P]),
@@ -75,7 +83,7 @@ SIGNATURES = {
 KERNEL_IDS = {name: i for i, name in enumerate([
     "ray_setup", "morton_sort", "count_kept", "scan", "fill_kept", "coarse_mask", "pack", "ray_base", "gather",
     "mlp_fwd", "compose_fwd", "compose_bwd", "mlp_bwd", "scatter", "reduce", "photo_loss", "adam", "prop_fwd",
-    "prop_bwd", "prop_reduce", "scene", "bin_count", "cell_scan", "bin_place"])}
+    "prop_bwd", "prop_reduce", "scene", "bin_count", "cell_scan", "bin_place", "grid_adam"])}
 
 _lib = None
 

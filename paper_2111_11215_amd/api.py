@@ -16,7 +16,7 @@ from typing import Optional
 import torch
 
 from . import _lib
-from ._lib import DVGO_BF16, DVGO_F32, Box, Field, Mlp, Prop, check, load, make_box
+from ._lib import DVGO_BF16, DVGO_F32, Box, Field, GridAdam, Mlp, Prop, check, load, make_box
 
 NSEG = 32
 HIDDEN = 128
@@ -265,6 +265,30 @@ def render_bwd(grid: Grid, mlp_flat: Optional[torch.Tensor], s: Samples, log_t_e
         _ptr(s.sample_k), _ptr(s.n_kept), s.capacity, s.B, s.step, _bg(bg), _ptr(log_t_end), _ptr(grad_rgb),
         _ptr(grad_depth), _ptr(grad_acc), _ptr(grad_density), _ptr(grad_feat), _ptr(grad_mlp), _ptr(ws), nws,
         _stream(dev)))
+
+
+def render_bwd_adam(grid: Grid, mlp_flat: torch.Tensor, s: Samples, log_t_end: torch.Tensor,
+                    grad_rgb: torch.Tensor, density_m: torch.Tensor, density_v: torch.Tensor,
+                    feat_m: torch.Tensor, feat_v: torch.Tensor, grad_mlp: torch.Tensor, lr: float, t: int,
+                    betas=(0.9, 0.999), eps=1e-8, bg=(1.0, 1.0, 1.0), precision: int = DVGO_F32,
+                    use_shadow: bool = False, grad_depth=None, grad_acc=None) -> None:
+    """Adjoint plus the Adam step of both grids (parameters and moments
+    updated in place, the bfloat16 feature copy rewritten when the grid has
+    one); accumulates (+=) the network gradient into grad_mlp."""
+    lib = load()
+    dev = s.rays_o.device
+    field = grid.field(use_shadow)
+    mlp = mlp_struct(mlp_flat, precision)
+    opt = GridAdam(_ptr(grid.density), _ptr(density_m), _ptr(density_v), _ptr(grid.feat), _ptr(feat_m),
+                   _ptr(feat_v), _ptr(grid.feat_shadow), float(lr), float(betas[0]), float(betas[1]), float(eps),
+                   int(t))
+    nws = lib.dvgo_render_workspace_bytes(s.B, s.capacity, CHANNELS, ctypes.byref(field.box))
+    ws = workspace(nws, dev)
+    check("dvgo_render_bwd_adam", lib.dvgo_render_bwd_adam(
+        ctypes.byref(field), ctypes.byref(mlp), _ptr(s.rays_o), _ptr(s.rays_d), _ptr(s.jitter), _ptr(s.t_near),
+        _ptr(s.n_uniform), _ptr(s.perm), _ptr(s.ray_offset), _ptr(s.sample_ray), _ptr(s.sample_k), _ptr(s.n_kept),
+        s.capacity, s.B, s.step, _bg(bg), _ptr(log_t_end), _ptr(grad_rgb), _ptr(grad_depth), _ptr(grad_acc),
+        ctypes.byref(opt), _ptr(grad_mlp), _ptr(ws), nws, _stream(dev)))
 
 
 def photo_loss(rgb: torch.Tensor, target: torch.Tensor):

@@ -1,16 +1,10 @@
 // Photometric loss (paper Eq. photo_loss) and the fused Adam step (the
 // paper's optimiser, Sec. 5.2; update rule of Kingma and Ba with bias
 // correction).  Both are streaming kernels bound by HBM bandwidth.
+#include "adam.hpp"
 #include "common.hpp"
 
 namespace {
-
-__device__ __forceinline__ uint16_t to_bf16(float f) {   // round to nearest even
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7F800000u) == 0x7F800000u) return static_cast<uint16_t>((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return static_cast<uint16_t>(u >> 16);
-}
 
 struct AdamArgs {
     float* p;
@@ -19,16 +13,8 @@ struct AdamArgs {
     float* v;
     uint16_t* shadow;
     int64_t n;
-    float lr, b1, b2, eps, inv_bc1, inv_bc2;
+    dvgo::AdamCoef c;
 };
-
-__device__ __forceinline__ void adam_one(const AdamArgs& a, float& p, float g, float& m, float& v) {
-    m = a.b1 * m + (1.0f - a.b1) * g;
-    v = a.b2 * v + (1.0f - a.b2) * g * g;
-    const float mh = m * a.inv_bc1;
-    const float vh = v * a.inv_bc2;
-    p -= a.lr * mh / (sqrtf(vh) + a.eps);
-}
 
 // 16-byte vectors: every pointer 16-byte aligned, n4 = n/4 vectors.
 __global__ __launch_bounds__(256) void adam_vec_kernel(AdamArgs a) {
@@ -40,20 +26,15 @@ __global__ __launch_bounds__(256) void adam_vec_kernel(AdamArgs a) {
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n4;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         float4 p = P[i], g = G[i], m = M[i], v = V[i];
-        adam_one(a, p.x, g.x, m.x, v.x);
-        adam_one(a, p.y, g.y, m.y, v.y);
-        adam_one(a, p.z, g.z, m.z, v.z);
-        adam_one(a, p.w, g.w, m.w, v.w);
+        dvgo::adam_update(a.c, p.x, g.x, m.x, v.x);
+        dvgo::adam_update(a.c, p.y, g.y, m.y, v.y);
+        dvgo::adam_update(a.c, p.z, g.z, m.z, v.z);
+        dvgo::adam_update(a.c, p.w, g.w, m.w, v.w);
         P[i] = p;
         M[i] = m;
         V[i] = v;
         G[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (a.shadow) {
-            uint2 sh;
-            sh.x = static_cast<uint32_t>(to_bf16(p.x)) | (static_cast<uint32_t>(to_bf16(p.y)) << 16);
-            sh.y = static_cast<uint32_t>(to_bf16(p.z)) | (static_cast<uint32_t>(to_bf16(p.w)) << 16);
-            reinterpret_cast<uint2*>(a.shadow)[i] = sh;
-        }
+        if (a.shadow) reinterpret_cast<uint2*>(a.shadow)[i] = dvgo::bf16x4_bits(p);
     }
 }
 
@@ -61,12 +42,12 @@ __global__ __launch_bounds__(256) void adam_scalar_kernel(AdamArgs a, int64_t st
     for (int64_t i = start + static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < a.n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         float p = a.p[i], m = a.m[i], v = a.v[i];
-        adam_one(a, p, a.g[i], m, v);
+        dvgo::adam_update(a.c, p, a.g[i], m, v);
         a.p[i] = p;
         a.m[i] = m;
         a.v[i] = v;
         a.g[i] = 0.0f;
-        if (a.shadow) a.shadow[i] = to_bf16(p);
+        if (a.shadow) a.shadow[i] = dvgo::bf16_bits(p);
     }
 }
 
@@ -110,7 +91,7 @@ int32_t dvgo_adam_step(float* p, float* g, float* m, float* v, uint16_t* shadow_
                        float beta1, float beta2, float eps, int32_t t, void* stream) {
     if (n < 0 || t < 1) return DVGO_E_ARG;
     if (n > 0 && (!p || !g || !m || !v)) return DVGO_E_ARG;
-    if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f) || !(eps >= 0.0f)) return DVGO_E_ARG;
+    if (!dvgo::adam_hyper_ok(beta1, beta2, eps, t)) return DVGO_E_ARG;
     if (n == 0) return DVGO_OK;
     AdamArgs a;
     a.p = p;
@@ -119,12 +100,7 @@ int32_t dvgo_adam_step(float* p, float* g, float* m, float* v, uint16_t* shadow_
     a.v = v;
     a.shadow = shadow_bf16;
     a.n = n;
-    a.lr = lr;
-    a.b1 = beta1;
-    a.b2 = beta2;
-    a.eps = eps;
-    a.inv_bc1 = static_cast<float>(1.0 / (1.0 - std::pow(static_cast<double>(beta1), t)));
-    a.inv_bc2 = static_cast<float>(1.0 / (1.0 - std::pow(static_cast<double>(beta2), t)));
+    a.c = dvgo::adam_coef(lr, beta1, beta2, eps, t);
     hipStream_t s = dvgo::as_stream(stream);
     auto al16 = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
     const bool vec = al16(p) && al16(g) && al16(m) && al16(v) &&

@@ -15,6 +15,7 @@
 //   mlp'     network adjoint, per-block weight-gradient partials
 //   scatter  transpose of the trilinear interpolation, float atomics
 //   reduce   deterministic sum of the per-block weight-gradient partials
+#include "adam.hpp"
 #include "common.hpp"
 #include "mlp_mfma.hpp"
 
@@ -493,11 +494,43 @@ __global__ __launch_bounds__(256) void bin_place_kernel(BinArgs a) {
     }
 }
 
-// One thread per vertex (i,j,k): corner (dx,dy,dz) of cell (i-dx, j-dy, k-dz).
+// Gradient of one vertex (i,j,k): it is corner (dx,dy,dz) of cell
+// (i-dx, j-dy, k-dz); the samples binned in those cells are summed with the
+// vertex's trilinear weight.  acc[0] density, acc[1..12] features.  Returns
+// whether any sample touches the vertex.
+__device__ __forceinline__ bool vertex_grad(const BinArgs& a, int i, int j, int k, bool feat, float acc[13]) {
+    const int nx = a.g.n[0], cy = a.g.n[1] - 1, cz = a.g.n[2] - 1;
+    #pragma unroll
+    for (int q = 0; q < 13; ++q) acc[q] = 0.0f;
+    bool any = false;
+    #pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int dx = (c >> 2) & 1, dy = (c >> 1) & 1, dz = c & 1;
+        const int ci = i - dx, cj = j - dy, ck = k - dz;
+        if (ci < 0 || cj < 0 || ck < 0 || ci >= nx - 1 || cj >= cy || ck >= cz) continue;
+        const int cell = (ci * cy + cj) * cz + ck;
+        const int p0 = a.cell_start[cell], p1 = a.cell_start[cell + 1];
+        for (int p = p0; p < p1; ++p) {
+            const float4* r = a.rec + static_cast<int64_t>(p) * 4;
+            const float4 h = r[0];
+            const float w = (dx ? h.x : 1.0f - h.x) * (dy ? h.y : 1.0f - h.y) * (dz ? h.z : 1.0f - h.z);
+            acc[0] += w * h.w;
+            if (feat) {
+                const float4 q0 = r[1], q1 = r[2], q2 = r[3];
+                acc[1] += w * q0.x; acc[2] += w * q0.y; acc[3] += w * q0.z; acc[4] += w * q0.w;
+                acc[5] += w * q1.x; acc[6] += w * q1.y; acc[7] += w * q1.z; acc[8] += w * q1.w;
+                acc[9] += w * q2.x; acc[10] += w * q2.y; acc[11] += w * q2.z; acc[12] += w * q2.w;
+            }
+            any = true;
+        }
+    }
+    return any;
+}
+
+// One thread per vertex: add its gradient into the gradient grids.
 __global__ __launch_bounds__(256) void vertex_gather_kernel(BinArgs a) {
-    const int nx = a.g.n[0], ny = a.g.n[1], nz = a.g.n[2];
-    const int64_t nv = static_cast<int64_t>(nx) * ny * nz;
-    const int cy = ny - 1, cz = nz - 1;
+    const int ny = a.g.n[1], nz = a.g.n[2];
+    const int64_t nv = static_cast<int64_t>(a.g.n[0]) * ny * nz;
     const bool feat = a.dfeat != nullptr;
     for (int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; v < nv;
          v += static_cast<int64_t>(gridDim.x) * blockDim.x) {
@@ -505,30 +538,7 @@ __global__ __launch_bounds__(256) void vertex_gather_kernel(BinArgs a) {
         const int j = static_cast<int>((v / nz) % ny);
         const int i = static_cast<int>(v / (static_cast<int64_t>(nz) * ny));
         float acc[13];
-        #pragma unroll
-        for (int q = 0; q < 13; ++q) acc[q] = 0.0f;
-        bool any = false;
-        #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const int dx = (c >> 2) & 1, dy = (c >> 1) & 1, dz = c & 1;
-            const int ci = i - dx, cj = j - dy, ck = k - dz;
-            if (ci < 0 || cj < 0 || ck < 0 || ci >= nx - 1 || cj >= cy || ck >= cz) continue;
-            const int cell = (ci * cy + cj) * cz + ck;
-            const int p0 = a.cell_start[cell], p1 = a.cell_start[cell + 1];
-            for (int p = p0; p < p1; ++p) {
-                const float4* r = a.rec + static_cast<int64_t>(p) * 4;
-                const float4 h = r[0];
-                const float w = (dx ? h.x : 1.0f - h.x) * (dy ? h.y : 1.0f - h.y) * (dz ? h.z : 1.0f - h.z);
-                acc[0] += w * h.w;
-                if (feat) {
-                    const float4 q0 = r[1], q1 = r[2], q2 = r[3];
-                    acc[1] += w * q0.x; acc[2] += w * q0.y; acc[3] += w * q0.z; acc[4] += w * q0.w;
-                    acc[5] += w * q1.x; acc[6] += w * q1.y; acc[7] += w * q1.z; acc[8] += w * q1.w;
-                    acc[9] += w * q2.x; acc[10] += w * q2.y; acc[11] += w * q2.z; acc[12] += w * q2.w;
-                }
-                any = true;
-            }
-        }
+        const bool any = vertex_grad(a, i, j, k, feat, acc);
         if (!any) continue;
         a.grad_density[v] += acc[0];
         if (feat) {
@@ -540,6 +550,60 @@ __global__ __launch_bounds__(256) void vertex_gather_kernel(BinArgs a) {
             gf[0] = g0;
             gf[1] = g1;
             gf[2] = g2;
+        }
+    }
+}
+
+// Grid parameters with their Adam moments, updated in place.
+struct GridAdamArgs {
+    float* pd;
+    float* md;
+    float* vd;
+    float* pf;
+    float* mf;
+    float* vf;
+    uint16_t* shadow;
+    dvgo::AdamCoef c;
+};
+
+// One thread per vertex: its gradient as in vertex_gather_kernel, then the
+// Adam step of its density and its 12 features (and their bfloat16 copy);
+// a vertex no sample touches takes the step with a zero gradient, as dense
+// Adam does.  The gradient never reaches memory.
+__global__ __launch_bounds__(256) void vertex_adam_kernel(BinArgs a, GridAdamArgs o) {
+    const int ny = a.g.n[1], nz = a.g.n[2];
+    const int64_t nv = static_cast<int64_t>(a.g.n[0]) * ny * nz;
+    for (int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; v < nv;
+         v += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int k = static_cast<int>(v % nz);
+        const int j = static_cast<int>((v / nz) % ny);
+        const int i = static_cast<int>(v / (static_cast<int64_t>(nz) * ny));
+        float acc[13];
+        if (a.cell_start) {
+            vertex_grad(a, i, j, k, true, acc);
+        } else {   // no samples in the batch
+            #pragma unroll
+            for (int q = 0; q < 13; ++q) acc[q] = 0.0f;
+        }
+        float p = o.pd[v], m = o.md[v], w = o.vd[v];
+        dvgo::adam_update(o.c, p, acc[0], m, w);
+        o.pd[v] = p;
+        o.md[v] = m;
+        o.vd[v] = w;
+        float4* P = reinterpret_cast<float4*>(o.pf + v * kC);
+        float4* M = reinterpret_cast<float4*>(o.mf + v * kC);
+        float4* V = reinterpret_cast<float4*>(o.vf + v * kC);
+        #pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            float4 pq = P[q], mq = M[q], vq = V[q];
+            dvgo::adam_update(o.c, pq.x, acc[1 + 4 * q], mq.x, vq.x);
+            dvgo::adam_update(o.c, pq.y, acc[2 + 4 * q], mq.y, vq.y);
+            dvgo::adam_update(o.c, pq.z, acc[3 + 4 * q], mq.z, vq.z);
+            dvgo::adam_update(o.c, pq.w, acc[4 + 4 * q], mq.w, vq.w);
+            P[q] = pq;
+            M[q] = mq;
+            V[q] = vq;
+            if (o.shadow) reinterpret_cast<uint2*>(o.shadow + v * kC)[q] = dvgo::bf16x4_bits(pq);
         }
     }
 }
@@ -788,7 +852,7 @@ Common make_common(const dvgo_field* field, const float* rays_o, const float* ra
 }
 
 int32_t run_scatter(const Common& cm, const dvgo_field* field, bool with_feat, const int64_t* n_kept,
-                    float* grad_density, float* grad_feat, hipStream_t s) {
+                    float* grad_density, float* grad_feat, const GridAdamArgs* opt, hipStream_t s) {
     BinArgs ba;
     ba.sa = cm.sa;
     ba.g = cm.g;
@@ -820,8 +884,69 @@ int32_t run_scatter(const Common& cm, const dvgo_field* field, bool with_feat, c
     DVGO_LAUNCH(K_BIN_PLACE, bin_place_kernel, dim3(grid_for(cm.cap, 256, cus * 16)), dim3(256), 0, s, ba);
     if (int32_t st = dvgo::launch_status()) return st;
     const int64_t nv = static_cast<int64_t>(field->box.n[0]) * field->box.n[1] * field->box.n[2];
-    DVGO_LAUNCH(K_SCATTER, vertex_gather_kernel, dim3(grid_for(nv, 256, cus * 16)), dim3(256), 0, s, ba);
+    if (opt)
+        DVGO_LAUNCH(K_GRID_ADAM, vertex_adam_kernel, dim3(grid_for(nv, 256, cus * 16)), dim3(256), 0, s, ba, *opt);
+    else
+        DVGO_LAUNCH(K_SCATTER, vertex_gather_kernel, dim3(grid_for(nv, 256, cus * 16)), dim3(256), 0, s, ba);
     return dvgo::launch_status();
+}
+
+int32_t render_bwd_impl(const dvgo_field* field, const dvgo_mlp* mlp, const float* rays_o, const float* rays_d,
+                        const float* jitter, const float* t_near, const int32_t* n_uniform, const int32_t* perm,
+                        const int32_t* ray_offset, const int32_t* sample_ray, const int32_t* sample_k,
+                        const int64_t* n_kept, int64_t capacity, int32_t B, float step, const float* bg,
+                        const float* log_t_end, const float* grad_rgb, const float* grad_depth,
+                        const float* grad_acc, float* grad_density, float* grad_feat, const GridAdamArgs* opt,
+                        float* grad_mlp, void* workspace, size_t workspace_bytes, void* stream) {
+    if (int32_t st = validate(field, mlp, rays_o, rays_d, t_near, n_uniform, perm, ray_offset, sample_ray, sample_k,
+                              n_kept, capacity, B, step, bg, workspace, workspace_bytes))
+        return st;
+    if (B > 0 && (!log_t_end || (!opt && !grad_density))) return DVGO_E_ARG;
+    if (mlp && ((!opt && !grad_feat) || !grad_mlp)) return DVGO_E_ARG;
+    if (opt && !mlp) return DVGO_E_ARG;
+    if (!mlp && grad_rgb) return DVGO_E_ARG;
+    hipStream_t s = dvgo::as_stream(stream);
+    if (B == 0 || capacity == 0) {
+        if (!opt) return DVGO_OK;
+        // no samples: every vertex still takes its zero-gradient Adam step
+        BinArgs ba{};
+        ba.g = dvgo::make_grid(field->box);
+        const int64_t nv = static_cast<int64_t>(field->box.n[0]) * field->box.n[1] * field->box.n[2];
+        DVGO_LAUNCH(K_GRID_ADAM, vertex_adam_kernel, dim3(grid_for(nv, 256, dvgo::device_cu_count() * 16)), dim3(256),
+                    0, s, ba, *opt);
+        return dvgo::launch_status();
+    }
+    Common cm = make_common(field, rays_o, rays_d, jitter, t_near, sample_ray, sample_k, capacity, B, step,
+                            workspace);
+    if (int32_t st = run_prep(cm, mlp, s)) return st;
+    if (int32_t st = run_gather(cm, field, mlp != nullptr, n_kept, s)) return st;
+    MlpArgs ma;
+    if (mlp) {
+        ma = make_mlp_args(cm, mlp, n_kept);
+        launch_mlp_fwd(ma, dvgo::device_cu_count(), s);
+        if (int32_t st = dvgo::launch_status()) return st;
+    }
+    ComposeArgs ca = make_compose(cm, perm, ray_offset, n_uniform, n_kept, field->act_shift, bg, mlp != nullptr);
+    ca.log_t_end_in = log_t_end;
+    ca.grad_rgb = grad_rgb;
+    ca.grad_depth = grad_depth;
+    ca.grad_acc = grad_acc;
+    DVGO_LAUNCH(K_COMPOSE_BWD, compose_bwd_kernel, dim3((B + 3) / 4), dim3(256), 0, s, ca);
+    if (int32_t st = dvgo::launch_status()) return st;
+    int nblk = 0;
+    if (mlp) {
+        nblk = dvgo::device_cu_count();
+        if (nblk > kMaxBwdBlocks) nblk = kMaxBwdBlocks;
+        launch_mlp_bwd(ma, nblk, s);
+        if (int32_t st = dvgo::launch_status()) return st;
+    }
+    if (int32_t st = run_scatter(cm, field, mlp != nullptr, n_kept, grad_density, grad_feat, opt, s)) return st;
+    if (mlp) {
+        DVGO_LAUNCH(K_REDUCE, reduce_partials_kernel, dim3((kMlpParams + 63) / 64), dim3(256), 0, s,
+                           reinterpret_cast<const float*>(cm.ws + cm.L.partial), nblk, grad_mlp);
+        if (int32_t st = dvgo::launch_status()) return st;
+    }
+    return DVGO_OK;
 }
 
 }  // namespace
@@ -879,45 +1004,38 @@ int32_t dvgo_render_bwd(const dvgo_field* field, const dvgo_mlp* mlp, const floa
                         const float* log_t_end, const float* grad_rgb, const float* grad_depth,
                         const float* grad_acc, float* grad_density, float* grad_feat, float* grad_mlp,
                         void* workspace, size_t workspace_bytes, void* stream) {
-    if (int32_t st = validate(field, mlp, rays_o, rays_d, t_near, n_uniform, perm, ray_offset, sample_ray, sample_k,
-                              n_kept, capacity, B, step, bg, workspace, workspace_bytes))
-        return st;
-    if (B > 0 && (!log_t_end || !grad_density)) return DVGO_E_ARG;
-    if (mlp && (!grad_feat || !grad_mlp)) return DVGO_E_ARG;
-    if (!mlp && grad_rgb) return DVGO_E_ARG;
-    hipStream_t s = dvgo::as_stream(stream);
-    if (B == 0 || capacity == 0) return DVGO_OK;
-    Common cm = make_common(field, rays_o, rays_d, jitter, t_near, sample_ray, sample_k, capacity, B, step,
-                            workspace);
-    if (int32_t st = run_prep(cm, mlp, s)) return st;
-    if (int32_t st = run_gather(cm, field, mlp != nullptr, n_kept, s)) return st;
-    MlpArgs ma;
-    if (mlp) {
-        ma = make_mlp_args(cm, mlp, n_kept);
-        launch_mlp_fwd(ma, dvgo::device_cu_count(), s);
-        if (int32_t st = dvgo::launch_status()) return st;
-    }
-    ComposeArgs ca = make_compose(cm, perm, ray_offset, n_uniform, n_kept, field->act_shift, bg, mlp != nullptr);
-    ca.log_t_end_in = log_t_end;
-    ca.grad_rgb = grad_rgb;
-    ca.grad_depth = grad_depth;
-    ca.grad_acc = grad_acc;
-    DVGO_LAUNCH(K_COMPOSE_BWD, compose_bwd_kernel, dim3((B + 3) / 4), dim3(256), 0, s, ca);
-    if (int32_t st = dvgo::launch_status()) return st;
-    int nblk = 0;
-    if (mlp) {
-        nblk = dvgo::device_cu_count();
-        if (nblk > kMaxBwdBlocks) nblk = kMaxBwdBlocks;
-        launch_mlp_bwd(ma, nblk, s);
-        if (int32_t st = dvgo::launch_status()) return st;
-    }
-    if (int32_t st = run_scatter(cm, field, mlp != nullptr, n_kept, grad_density, grad_feat, s)) return st;
-    if (mlp) {
-        DVGO_LAUNCH(K_REDUCE, reduce_partials_kernel, dim3((kMlpParams + 63) / 64), dim3(256), 0, s,
-                           reinterpret_cast<const float*>(cm.ws + cm.L.partial), nblk, grad_mlp);
-        if (int32_t st = dvgo::launch_status()) return st;
-    }
-    return DVGO_OK;
+    return render_bwd_impl(field, mlp, rays_o, rays_d, jitter, t_near, n_uniform, perm, ray_offset, sample_ray,
+                           sample_k, n_kept, capacity, B, step, bg, log_t_end, grad_rgb, grad_depth, grad_acc,
+                           grad_density, grad_feat, nullptr, grad_mlp, workspace, workspace_bytes, stream);
+}
+
+int32_t dvgo_render_bwd_adam(const dvgo_field* field, const dvgo_mlp* mlp, const float* rays_o,
+                             const float* rays_d, const float* jitter, const float* t_near, const int32_t* n_uniform,
+                             const int32_t* perm, const int32_t* ray_offset, const int32_t* sample_ray,
+                             const int32_t* sample_k, const int64_t* n_kept, int64_t capacity, int32_t B, float step,
+                             const float* bg, const float* log_t_end, const float* grad_rgb, const float* grad_depth,
+                             const float* grad_acc, const dvgo_grid_adam* opt, float* grad_mlp, void* workspace,
+                             size_t workspace_bytes, void* stream) {
+    if (!opt || !field) return DVGO_E_ARG;
+    if (!opt->density || !opt->density_m || !opt->density_v || !opt->feat || !opt->feat_m || !opt->feat_v)
+        return DVGO_E_ARG;
+    if (!dvgo::adam_hyper_ok(opt->beta1, opt->beta2, opt->eps, opt->t)) return DVGO_E_ARG;
+    auto al16 = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
+    if (!al16(opt->feat) || !al16(opt->feat_m) || !al16(opt->feat_v) ||
+        (opt->feat_shadow_bf16 && (reinterpret_cast<uintptr_t>(opt->feat_shadow_bf16) & 7u) != 0))
+        return DVGO_E_ARG;
+    GridAdamArgs o;
+    o.pd = opt->density;
+    o.md = opt->density_m;
+    o.vd = opt->density_v;
+    o.pf = opt->feat;
+    o.mf = opt->feat_m;
+    o.vf = opt->feat_v;
+    o.shadow = opt->feat_shadow_bf16;
+    o.c = dvgo::adam_coef(opt->lr, opt->beta1, opt->beta2, opt->eps, opt->t);
+    return render_bwd_impl(field, mlp, rays_o, rays_d, jitter, t_near, n_uniform, perm, ray_offset, sample_ray,
+                           sample_k, n_kept, capacity, B, step, bg, log_t_end, grad_rgb, grad_depth, grad_acc, nullptr,
+                           nullptr, &o, grad_mlp, workspace, workspace_bytes, stream);
 }
 
 }  // extern "C"

@@ -50,6 +50,7 @@ class FineConfig:
     bf16_feat: bool = False          # gather features from a bfloat16 shadow
     morton: bool = False
     capacity: Optional[int] = None
+    fused_grid_adam: bool = True     # backward and grid Adam in one call (no grid gradient in memory)
 
 
 class FineModel:
@@ -92,14 +93,29 @@ class FineModel:
         for st, lr in ((self.st_density, lg), (self.st_feat, lg), (self.st_mlp, lm)):
             api.adam_step(st.p, st.g, st.m, st.v, lr, self.t, c.betas, c.eps, shadow=st.shadow)
 
+    def backward_adam(self, s: api.Samples, out: dict, grad_rgb: torch.Tensor) -> None:
+        """Adjoint with the grids' Adam step fused in, then the network's
+        Adam step (same result as ``backward`` followed by ``adam``)."""
+        c = self.cfg
+        self.t += 1
+        lg, lm = self.lr(c.lr_grid), self.lr(c.lr_mlp)
+        d, f = self.st_density, self.st_feat
+        api.render_bwd_adam(self.grid, self.mlp, s, out["log_t_end"], grad_rgb, d.m, d.v, f.m, f.v, self.st_mlp.g,
+                            lg, self.t, c.betas, c.eps, c.bg, precision=c.precision, use_shadow=c.bf16_feat)
+        m = self.st_mlp
+        api.adam_step(m.p, m.g, m.m, m.v, lm, self.t, c.betas, c.eps)
+
     def train_step(self, rays_o, rays_d, target, jitter=None, seg_mask=None) -> dict:
         """One full iteration: sample, render, photometric loss, adjoint,
         Adam.  Returns the loss (device tensor) and the sample list."""
         s = self.sample(rays_o, rays_d, jitter, seg_mask)
         out = self.render(s, want_depth_acc=False)
         loss, grad = api.photo_loss(out["rgb"], target)
-        self.backward(s, out, grad)
-        self.adam()
+        if self.cfg.fused_grid_adam:
+            self.backward_adam(s, out, grad)
+        else:
+            self.backward(s, out, grad)
+            self.adam()
         return {"loss": loss, "samples": s, "rgb": out["rgb"]}
 
 

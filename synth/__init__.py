@@ -26,6 +26,7 @@ from .scenes import (  # noqa: F401
     tiny_config,
     full_config,
     full_scene,
+    stress_config,
     Problem,
     RayBatch,
     Spheres,
@@ -35,4 +36,7 @@ from .scenes import (  # noqa: F401
     FULL_COARSE_N,
     FULL_ALPHA_INIT,
     FULL_TAU,
+    STRESS_N,
+    STRESS_MAX_SAMPLES,
+    STRESS_ALPHA_INIT,
 )

@@ -273,3 +273,34 @@ def full_config(seed: int = 0, n_rays: int = 8192, n: int = FULL_N, batch_seed: 
     prob.extra.update(spheres=sp, cams=cams, held=held, alpha_init=FULL_ALPHA_INIT,
                       voxel=2.0 / (n - 1), tau=FULL_TAU)
     return prob
+
+
+STRESS_N = 256
+STRESS_MAX_SAMPLES = 800
+STRESS_ALPHA_INIT = 1e-2
+
+
+def stress_config(seed: int = 0, n_rays: int = 32768, n: int = STRESS_N, batch_seed: int = 2000,
+                  max_samples: int = STRESS_MAX_SAMPLES) -> Problem:
+    """Differentiation stress shapes: 256^3 density and 12-channel feature
+    grids with values uniform in [-1, 1] from default_rng(seed) (density
+    first), Xavier network with N(0, 0.1) biases from default_rng(seed + 7),
+    step half a voxel, at most 800 samples per ray (the diagonal would need
+    884), and ``n_rays`` pixels drawn with replacement over the 100 training
+    cameras of the sphere scene from default_rng(batch_seed), jitter next.
+    No coarse mask: every in-box sample is evaluated."""
+    rng = np.random.default_rng(seed)
+    dens = rng.uniform(-1.0, 1.0, (n, n, n)).astype(np.float32)
+    feat = rng.uniform(-1.0, 1.0, (n, n, n, 12)).astype(np.float32)
+    rng_w = np.random.default_rng(seed + 7)
+    Ws, bs = xavier_uniform_mlp(rng_w, (39, 128, 128, 3))
+    bs = [(rng_w.normal(size=b.shape) * 0.1).astype(np.float32) for b in bs]
+    cams = hemisphere_cameras(100, 1)
+    rng = np.random.default_rng(batch_seed)
+    o, d, *_ = draw_pixels_with_replacement(rng, cams, 800, 800, 1000.0, n_rays)
+    jit = rng.random(n_rays).astype(np.float32)
+    step = 0.5 * 2.0 / (n - 1)
+    prob = Problem(BOX_MIN.copy(), BOX_MAX.copy(), dens, feat, Ws, bs, step, max_samples, 0.0,
+                   np.ones(3, np.float32), RayBatch(o, d, np.zeros((n_rays, 3), np.float32), jit))
+    prob.extra.update(alpha_init=STRESS_ALPHA_INIT, voxel=2.0 / (n - 1))
+    return prob

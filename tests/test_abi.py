@@ -104,3 +104,21 @@ def test_host_validation_rejects_before_launch(lib):
     # proposal: bad selection fraction
     assert lib.dvgo_proposal_fwd(fake, fake, fake, nul, 1, ctypes.byref(box), nul, 1.5, 0.9, fake, nul, nul,
                                  nul) == -1
+    # fused backward + grid Adam: missing optimiser state, bad beta, misaligned
+    # feature pointer, then a shape error from the shared validation
+    ga = _lib.GridAdam(16, 16, 16, 16, 16, 16, None, 0.1, 0.9, 0.999, 1e-8, 1)
+    bargs = [fake, fake, nul, fake, fake, fake, fake, fake, fake, fake, 10, 4, 0.1, bg, fake, fake, nul, nul]
+    f.channels = 12
+    m.precision = 0
+    assert lib.dvgo_render_bwd_adam(ctypes.byref(f), ctypes.byref(m), *bargs, None, fake, fake, 1 << 30, nul) == -1
+    ga.beta1 = 1.0
+    assert lib.dvgo_render_bwd_adam(ctypes.byref(f), ctypes.byref(m), *bargs, ctypes.byref(ga), fake, fake, 1 << 30,
+                                    nul) == -1
+    ga.beta1 = 0.9
+    ga.feat = 20
+    assert lib.dvgo_render_bwd_adam(ctypes.byref(f), ctypes.byref(m), *bargs, ctypes.byref(ga), fake, fake, 1 << 30,
+                                    nul) == -1
+    ga.feat = 16
+    f.channels = 11
+    assert lib.dvgo_render_bwd_adam(ctypes.byref(f), ctypes.byref(m), *bargs, ctypes.byref(ga), fake, fake, 1 << 30,
+                                    nul) == -2

@@ -1,0 +1,95 @@
+"""The fused adjoint + grid Adam call against the separate calls it
+replaces (dvgo_render_bwd into zeroed gradients, then dvgo_adam_step on
+both grids): same network gradient bit for bit, same parameter updates and
+moments up to the summation order of the grid gradients (1e-5 normwise on
+the update), the bfloat16 copy equal to the rounded new parameters; with no
+sample in the batch every vertex takes the zero-gradient step."""
+
+import numpy as np
+import pytest
+
+from tests.helpers import np_of, report, to_dev
+from tests.test_gpu_render import _gpu, _problem
+
+pytestmark = pytest.mark.gpu
+F32 = np.float32
+
+
+def _state(rng, shape):
+    return to_dev((rng.normal(size=shape) * 1e-3).astype(F32)), to_dev((rng.random(shape) * 1e-5).astype(F32))
+
+
+def _clone_grid(api, grid):
+    g = api.Grid(grid.density.clone(), grid.feat.clone(), grid.box_min, grid.box_max, grid.act_shift)
+    g.feat_shadow = None if grid.feat_shadow is None else grid.feat_shadow.clone()
+    return g
+
+
+def _bf16_bits(x):
+    u = np.ascontiguousarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    return ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_fused_backward_adam_equals_separate(gpu_lib, bf16):
+    import torch
+    from paper_2111_11215_amd import api
+    from paper_2111_11215_amd._lib import DVGO_BF16, DVGO_F32
+    prec = DVGO_BF16 if bf16 else DVGO_F32
+    P = _problem(7, n_rays=2048, bias=0.3)
+    grid, flat, s = _gpu(P, bf16=bf16)
+    rng = np.random.default_rng(3)
+    mD, vD = _state(rng, P.density.shape)
+    mF, vF = _state(rng, P.feat.shape)
+    out = api.render_fwd(grid, flat, s, P.bg, precision=prec, use_shadow=bf16)
+    g = to_dev((rng.normal(size=(P.rays.o.shape[0], 3)) * 1e-3).astype(F32))
+    lr, t = 0.1, 4
+
+    ga = _clone_grid(api, grid)
+    gd, gf, gm = torch.zeros_like(grid.density), torch.zeros_like(grid.feat), torch.zeros_like(flat)
+    api.render_bwd(ga, flat, s, out["log_t_end"], g, gd, gf, gm, P.bg, precision=prec, use_shadow=bf16)
+    mDa, vDa, mFa, vFa = mD.clone(), vD.clone(), mF.clone(), vF.clone()
+    api.adam_step(ga.density, gd, mDa, vDa, lr, t)
+    api.adam_step(ga.feat, gf, mFa, vFa, lr, t, shadow=ga.feat_shadow)
+
+    gb = _clone_grid(api, grid)
+    gmb = torch.zeros_like(flat)
+    mDb, vDb, mFb, vFb = mD.clone(), vD.clone(), mF.clone(), vF.clone()
+    api.render_bwd_adam(gb, flat, s, out["log_t_end"], g, mDb, vDb, mFb, vFb, gmb, lr, t, bg=P.bg, precision=prec,
+                        use_shadow=bf16)
+
+    assert torch.equal(gm, gmb)
+    for name, p0, pa, pb in (("density", grid.density, ga.density, gb.density), ("feat", grid.feat, ga.feat,
+                                                                                   gb.feat)):
+        assert report(f"{name} update", np_of(pb - p0), np_of(pa - p0))[0] <= 1e-5, name
+    for name, a, b in (("m density", mDa, mDb), ("v density", vDa, vDb), ("m feat", mFa, mFb), ("v feat", vFa, vFb)):
+        assert report(name, np_of(b), np_of(a))[0] <= 1e-5, name
+    if bf16:
+        assert np.array_equal(np_of(gb.feat_shadow).view(np.uint16), _bf16_bits(np_of(gb.feat)))
+
+
+def test_fused_backward_adam_without_samples(gpu_lib):
+    """Every ray misses the box: the call is the zero-gradient Adam step of
+    every vertex (compared with dvgo_adam_step on zero gradients)."""
+    import torch
+    from paper_2111_11215_amd import api
+    P = _problem(8, n_rays=256)
+    P.rays.o = (P.rays.o + np.float32(10.0)).astype(F32)        # all rays start beyond the box ...
+    P.rays.d = np.abs(P.rays.d).astype(F32)                      # ... and point away from it
+    grid, flat, s = _gpu(P)
+    assert int(s.n_kept.item()) == 0
+    rng = np.random.default_rng(5)
+    mD, vD = _state(rng, P.density.shape)
+    mF, vF = _state(rng, P.feat.shape)
+    out = api.render_fwd(grid, flat, s, P.bg)
+    g = torch.ones((256, 3), device="cuda")
+    ga = _clone_grid(api, grid)
+    mDa, vDa, mFa, vFa = mD.clone(), vD.clone(), mF.clone(), vF.clone()
+    api.adam_step(ga.density, torch.zeros_like(ga.density), mDa, vDa, 0.1, 2)
+    api.adam_step(ga.feat, torch.zeros_like(ga.feat), mFa, vFa, 0.1, 2)
+    gb = _clone_grid(api, grid)
+    gm = torch.zeros_like(flat)
+    api.render_bwd_adam(gb, flat, s, out["log_t_end"], g, mD, vD, mF, vF, gm, 0.1, 2, bg=P.bg)
+    for a, b in ((ga.density, gb.density), (ga.feat, gb.feat), (mDa, mD), (vDa, vD), (mFa, mF), (vFa, vF)):
+        assert torch.allclose(a, b, rtol=1e-6, atol=0)
+    assert float(gm.abs().max()) == 0.0

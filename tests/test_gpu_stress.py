@@ -1,0 +1,175 @@
+"""Differentiation stress at 256^3 with a 12-channel bfloat16 feature grid,
+32768 rays per batch and up to 800 samples per ray (no coarse mask, so every
+in-box sample is evaluated; the float32 network).
+
+1. FP64 central finite differences (eps 1e-4) of the oracle's loss on 256
+   random grid entries (128 density, 128 feature) touched by the checked rays
+   and 16 network parameters, against the oracle's hand-written adjoint:
+   relative 1e-6 (an entry whose +eps and -eps evaluations take different
+   ReLU branches somewhere is a kink of the function and is skipped, counted).
+2. The GPU adjoint of the full launch (grad_rgb non-zero on 64 random rays,
+   the rest zero, so the oracle can compute the exact result on those rays)
+   against the oracle's adjoint on the whole of both grid gradients and the
+   network gradient with the ReLU-kink budget, at 3e-5: the adjoint's
+   transmittance and suffix sums run over up to 800 float32 terms per ray,
+   whose rounding bound n*u is 800 * 6e-8 = 4.8e-5 (measured 1.2e-5 for the
+   density gradient; the 1e-5 of the other tests covers rays of <= 551).
+3. Peak device memory of the step (recompute adjoint) against the estimate
+   for a variant that stores every sample's intermediate state (printed).
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from tests.helpers import check_grid_grad, check_weight_grads, kink_budget, mlp_flat_np, np_of, report, to_dev
+
+pytestmark = pytest.mark.gpu
+F32 = np.float32
+EPS = 1e-4
+TOL32 = 1e-5
+TOL_LONG = 3e-5    # float32 sums over up to 800 terms per ray
+ZETA = 1e-4
+# bytes per evaluated sample a store-everything backward keeps: 8 corner
+# indices and weights (64), raw/sigma/alpha/T (16), features (48), network
+# input (156), two hidden layers (1024), colour pre- and post-sigmoid (24)
+STORE_ALL_BYTES_PER_SAMPLE = 64 + 16 + 48 + 156 + 1024 + 24
+
+
+def _loss(prm, o, d, j, rays, g, P):
+    samp = O.sample_rays(o[rays], d[rays], j[rays], P.box_min, P.box_max, P.step, P.max_samples, morton=False)
+    ref = O.render_forward(prm, o[rays], d[rays], j[rays], samp, P.step, P.bg)
+    mc = ref["cache"].get("mcache")
+    masks = (mc["z1"] > 0, mc["z2"] > 0) if mc is not None else None
+    return float(np.sum(g[rays] * ref["rgb"])), masks
+
+
+def _central(prm, arr, idx, o, d, j, rays, g, P):
+    v0 = arr[idx]
+    arr[idx] = v0 + EPS
+    lp, mp = _loss(prm, o, d, j, rays, g, P)
+    arr[idx] = v0 - EPS
+    lm, mm = _loss(prm, o, d, j, rays, g, P)
+    arr[idx] = v0
+    kink = not (np.array_equal(mp[0], mm[0]) and np.array_equal(mp[1], mm[1]))
+    return (lp - lm) / (2 * EPS), kink
+
+
+def oracle_fd_check(P, sel, g_sub, rng, rgb_sel=None, n_entries=256, n_params=16):
+    """Oracle forward/adjoint on the rays ``sel`` with float64 grids holding
+    the stored values (features rounded to bfloat16), then central finite
+    differences against the adjoint.  Returns (params, forward, adjoint)."""
+    n = P.density.shape[0]
+    dens64 = P.density.astype(np.float64)
+    feat64 = O.bf16_round(P.feat)
+    Ws64 = [w.astype(np.float64) for w in P.Ws]
+    bs64 = [b.astype(np.float64) for b in P.bs]
+    prm = O.Params(dens64, feat64, Ws64, bs64, P.box_min, P.box_max, P.act_shift)
+    o, d, j = P.rays.o[sel], P.rays.d[sel], P.rays.jitter[sel]
+    samp = O.sample_rays(o, d, j, P.box_min, P.box_max, P.step, P.max_samples, morton=False)
+    ref = O.render_forward(prm, o, d, j, samp, P.step, P.bg)
+    ref["_samp"] = samp
+    if rgb_sel is not None:
+        assert report("rgb (checked rays)", rgb_sel, ref["rgb"])[0] <= TOL32
+    gr = O.render_backward(prm, o, d, j, samp, P.step, P.bg, ref, g_sub)
+
+    # ---- 1. finite differences of the oracle against its adjoint
+    x = ref["cache"]["x"]
+    ray_of = np.asarray(ref["_sample_ray"])
+    i0, wts, offs = O.trilinear_corners(x, P.box_min, P.box_max, (n, n, n))
+    pick = rng.choice(x.shape[0], n_entries, replace=False)
+    corner = rng.integers(0, 8, n_entries)
+    verts = i0[pick] + offs[corner]
+    verts_all = i0[:, None, :] + offs[None, :, :]              # [S, 8, 3]
+    rays_local = np.arange(len(sel))
+    fd, adj, kinks = [], [], 0
+    for e in range(n_entries):
+        v = verts[e]
+        hit = np.any(np.all(verts_all == v, axis=2) & (wts > 0), axis=1)
+        rays = np.unique(ray_of[hit])
+        if e < n_entries // 2:
+            idx, arr, a = tuple(v), dens64, gr["density"][tuple(v)]
+        else:
+            ch = int(rng.integers(0, 12))
+            idx, arr, a = (v[0], v[1], v[2], ch), feat64, gr["feat"][v[0], v[1], v[2], ch]
+        f, kink = _central(prm, arr, idx, o, d, j, rays, g_sub, P)
+        if kink:
+            kinks += 1
+            continue
+        fd.append(f)
+        adj.append(a)
+    flat64 = mlp_flat_np(P.Ws, P.bs).astype(np.float64)
+    shapes = [w.shape for w in P.Ws]
+    offsets = np.cumsum([0] + [int(np.prod(s_)) + s_[0] for s_ in shapes])
+    grad_flat = np.concatenate([gr["Ws"][0].ravel(), gr["bs"][0], gr["Ws"][1].ravel(), gr["bs"][1],
+                                gr["Ws"][2].ravel(), gr["bs"][2]])
+    for q in rng.choice(flat64.size, n_params, replace=False):
+        layer = int(np.searchsorted(offsets, q, side="right") - 1)
+        r = q - offsets[layer]
+        nW = int(np.prod(shapes[layer]))
+        arr, idx = (Ws64[layer], np.unravel_index(r, shapes[layer])) if r < nW else (bs64[layer], (r - nW,))
+        f, kink = _central(prm, arr, idx, o, d, j, rays_local, g_sub, P)
+        if kink:
+            kinks += 1
+            continue
+        fd.append(f)
+        adj.append(grad_flat[q])
+    fd, adj = np.array(fd), np.array(adj)
+    rel = np.abs(fd - adj) / np.maximum(np.abs(adj), 1e-3 * np.max(np.abs(adj)))
+    print(f"  finite differences: {fd.size} checked, {kinks} kinks skipped, max rel err {rel.max():.3e}, "
+          f"normwise {np.linalg.norm(fd - adj) / np.linalg.norm(adj):.3e}", flush=True)
+    assert fd.size >= 0.8 * (n_entries + n_params)
+    assert rel.max() <= 1e-6
+    return prm, ref, gr
+
+
+@pytest.mark.timeout(600)
+def test_stress_finite_differences_and_adjoint(gpu_lib):
+    import torch
+    from paper_2111_11215_amd import api
+    from paper_2111_11215_amd._lib import DVGO_F32
+    P = synth.stress_config(0)
+    P.act_shift = O.low_density_bias(P.extra["alpha_init"], P.extra["voxel"])
+    B, n = P.rays.o.shape[0], P.density.shape[0]
+    rng = np.random.default_rng(9)
+    sel = np.sort(rng.choice(B, 64, replace=False))
+    g_sub = rng.normal(size=(64, 3)).astype(F32).astype(np.float64)
+
+    print(f"  GPU step: {n}^3 grids, bf16 features, {B} rays, <= {P.max_samples} samples/ray", flush=True)
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
+    base = torch.cuda.memory_allocated()
+    grid = api.Grid(to_dev(P.density), to_dev(P.feat), tuple(P.box_min), tuple(P.box_max), P.act_shift)
+    grid.feat_shadow = grid.feat.to(torch.bfloat16).view(torch.int16).contiguous()
+    flat = to_dev(mlp_flat_np(P.Ws, P.bs))
+    s = api.sample_rays(to_dev(P.rays.o), to_dev(P.rays.d), to_dev(P.rays.jitter), P.box_min, P.box_max, P.step,
+                        P.max_samples)
+    out = api.render_fwd(grid, flat, s, P.bg, precision=DVGO_F32, use_shadow=True, want_depth_acc=False)
+    g = np.zeros((B, 3), F32)
+    g[sel] = g_sub
+    gd, gf, gm = torch.zeros_like(grid.density), torch.zeros_like(grid.feat), torch.zeros_like(flat)
+    api.render_bwd(grid, flat, s, out["log_t_end"], to_dev(g), gd, gf, gm, P.bg, precision=DVGO_F32,
+                   use_shadow=True)
+    torch.cuda.synchronize()
+    peak = torch.cuda.max_memory_allocated() - base
+    n_kept = int(s.n_kept.item())
+    fixed = 4 * n ** 3 * (1 + 12) * 2 + 2 * n ** 3 * 12       # grids, their gradients, bf16 shadow
+    store_all = fixed + n_kept * STORE_ALL_BYTES_PER_SAMPLE
+    print(f"  evaluated samples {n_kept}; peak device memory {peak / 2**30:.2f} GiB "
+          f"(grids+grads+shadow {fixed / 2**30:.2f} GiB); store-all estimate {store_all / 2**30:.2f} GiB "
+          f"({STORE_ALL_BYTES_PER_SAMPLE} B/sample)", flush=True)
+    assert peak < store_all
+    rgb_sel = np_of(out["rgb"])[sel]
+    gd, gf, gm = np_of(gd), np_of(gf), np_of(gm)
+    del grid, s, out
+    torch.cuda.empty_cache()
+
+    prm, ref, gr = oracle_fd_check(P, sel, g_sub, rng, rgb_sel)
+
+    # ---- 2. the GPU adjoint against the oracle's
+    assert report("grad_density", gd, gr["density"])[0] <= TOL_LONG
+    budget, wb, frac = kink_budget(prm, ref, g_sub, ZETA, P.feat.shape, P.box_min, P.box_max)
+    print(f"  samples with an ambiguous ReLU unit: {frac:.2e}", flush=True)
+    check_grid_grad("grad_feat", gf, gr["feat"], budget, TOL_LONG)
+    check_weight_grads(gm, gr["Ws"], gr["bs"], wb, TOL_LONG)
