@@ -569,42 +569,99 @@ struct GridAdamArgs {
 // One thread per vertex: its gradient as in vertex_gather_kernel, then the
 // Adam step of its density and its 12 features (and their bfloat16 copy);
 // a vertex no sample touches takes the step with a zero gradient, as dense
-// Adam does.  The gradient never reaches memory.
+// Adam does.  The gradient never reaches memory.  Feature streams are
+// walked in wave-contiguous float4 chunks (the 64 vertices of a wave own
+// 768 consecutive values): the wave's gradients go through LDS so that every
+// load and store of p, m, v and the copy covers whole cache lines.
 __global__ __launch_bounds__(256) void vertex_adam_kernel(BinArgs a, GridAdamArgs o) {
+    __shared__ float4 sg[4][64 * 3];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int ny = a.g.n[1], nz = a.g.n[2];
     const int64_t nv = static_cast<int64_t>(a.g.n[0]) * ny * nz;
-    for (int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; v < nv;
-         v += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const int k = static_cast<int>(v % nz);
-        const int j = static_cast<int>((v / nz) % ny);
-        const int i = static_cast<int>(v / (static_cast<int64_t>(nz) * ny));
-        float acc[13];
-        if (a.cell_start) {
-            vertex_grad(a, i, j, k, true, acc);
-        } else {   // no samples in the batch
-            #pragma unroll
-            for (int q = 0; q < 13; ++q) acc[q] = 0.0f;
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+    f4* P = reinterpret_cast<f4*>(o.pf);
+    f4* M = reinterpret_cast<f4*>(o.mf);
+    f4* V = reinterpret_cast<f4*>(o.vf);
+    u2* S = reinterpret_cast<u2*>(o.shadow);
+    // Workgroups are dealt to the 8 XCDs round robin (block b on XCD b % 8):
+    // give each XCD one contiguous eighth of the vertices, so the cell starts
+    // and sample records that neighbouring vertices share stay in that XCD's
+    // L2.  gridDim.x is a multiple of 8.
+    const int xcd = blockIdx.x & 7, nloc = gridDim.x >> 3, loc = blockIdx.x >> 3;
+    const int64_t span = (nv + 8 * 256 - 1) / (8 * 256) * 256;
+    const int64_t lo = xcd * span, hi = lo + span < nv ? lo + span : nv;
+    for (int64_t base = lo + static_cast<int64_t>(loc) * blockDim.x; base < hi;
+         base += static_cast<int64_t>(nloc) * blockDim.x) {
+        const int64_t v = base + threadIdx.x;
+        const int64_t vbase = base + 64 * wave;
+        const int64_t nwave = hi - vbase < 64 ? hi - vbase : 64;   // vertices of this wave (may be <= 0)
+        // issue the parameter streams first: they do not depend on the
+        // gradient and overlap the latency of the sample gather below
+        float p = 0.0f, m = 0.0f, w = 0.0f;
+        if (v < hi) {
+            p = __builtin_nontemporal_load(o.pd + v);
+            m = __builtin_nontemporal_load(o.md + v);
+            w = __builtin_nontemporal_load(o.vd + v);
         }
-        float p = o.pd[v], m = o.md[v], w = o.vd[v];
-        dvgo::adam_update(o.c, p, acc[0], m, w);
-        o.pd[v] = p;
-        o.md[v] = m;
-        o.vd[v] = w;
-        float4* P = reinterpret_cast<float4*>(o.pf + v * kC);
-        float4* M = reinterpret_cast<float4*>(o.mf + v * kC);
-        float4* V = reinterpret_cast<float4*>(o.vf + v * kC);
+        f4 pq[3], mq[3], vq[3];
         #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            float4 pq = P[q], mq = M[q], vq = V[q];
-            dvgo::adam_update(o.c, pq.x, acc[1 + 4 * q], mq.x, vq.x);
-            dvgo::adam_update(o.c, pq.y, acc[2 + 4 * q], mq.y, vq.y);
-            dvgo::adam_update(o.c, pq.z, acc[3 + 4 * q], mq.z, vq.z);
-            dvgo::adam_update(o.c, pq.w, acc[4 + 4 * q], mq.w, vq.w);
-            P[q] = pq;
-            M[q] = mq;
-            V[q] = vq;
-            if (o.shadow) reinterpret_cast<uint2*>(o.shadow + v * kC)[q] = dvgo::bf16x4_bits(pq);
+            const int c = 64 * q + lane;
+            if (c < 3 * nwave) {
+                const int64_t gi = 3 * vbase + c;
+                pq[q] = __builtin_nontemporal_load(P + gi);
+                mq[q] = __builtin_nontemporal_load(M + gi);
+                vq[q] = __builtin_nontemporal_load(V + gi);
+            }
         }
+        float acc[13];
+        #pragma unroll
+        for (int q = 0; q < 13; ++q) acc[q] = 0.0f;
+        if (v < hi) {
+            if (a.cell_start) {   // else no samples in the batch
+                const int k = static_cast<int>(v % nz);
+                const int j = static_cast<int>((v / nz) % ny);
+                const int i = static_cast<int>(v / (static_cast<int64_t>(nz) * ny));
+                vertex_grad(a, i, j, k, true, acc);
+            }
+            dvgo::adam_update(o.c, p, acc[0], m, w);
+            __builtin_nontemporal_store(p, o.pd + v);
+            __builtin_nontemporal_store(m, o.md + v);
+            __builtin_nontemporal_store(w, o.vd + v);
+        }
+        #pragma unroll
+        for (int q = 0; q < 3; ++q)
+            sg[wave][3 * lane + q] = make_float4(acc[1 + 4 * q], acc[2 + 4 * q], acc[3 + 4 * q], acc[4 + 4 * q]);
+        __syncthreads();
+        #pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int c = 64 * q + lane;
+            if (c < 3 * nwave) {
+                const int64_t gi = 3 * vbase + c;
+                const float4 g = sg[wave][c];
+                const float gg[4] = {g.x, g.y, g.z, g.w};
+                #pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    float pe = pq[q][e], me = mq[q][e], ve = vq[q][e];
+                    dvgo::adam_update(o.c, pe, gg[e], me, ve);
+                    pq[q][e] = pe;
+                    mq[q][e] = me;
+                    vq[q][e] = ve;
+                }
+                __builtin_nontemporal_store(pq[q], P + gi);
+                __builtin_nontemporal_store(mq[q], M + gi);
+                __builtin_nontemporal_store(vq[q], V + gi);
+                if (S) {
+                    const uint2 b = dvgo::bf16x4_bits(make_float4(pq[q].x, pq[q].y, pq[q].z, pq[q].w));
+                    u2 bv;
+                    bv.x = b.x;
+                    bv.y = b.y;
+                    __builtin_nontemporal_store(bv, S + gi);
+                }
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -731,6 +788,16 @@ int grid_for(int64_t work, int per_block, int max_blocks) {
     if (b < 1) b = 1;
     if (b > max_blocks) b = max_blocks;
     return static_cast<int>(b);
+}
+
+// Workgroups of the fused grid Adam: a multiple of 8 (one share per XCD),
+// at most 16 per compute unit, no more than the vertices need.
+int grid_adam_blocks(int64_t nv) {
+    const int64_t per_xcd = (nv + 8 * 256 - 1) / (8 * 256);
+    int64_t b = static_cast<int64_t>(dvgo::device_cu_count()) * 16 / 8;
+    if (b > per_xcd) b = per_xcd;
+    if (b < 1) b = 1;
+    return static_cast<int>(8 * b);
 }
 
 int32_t run_prep(const Common& cm, const dvgo_mlp* mlp, hipStream_t s) {
@@ -885,7 +952,7 @@ int32_t run_scatter(const Common& cm, const dvgo_field* field, bool with_feat, c
     if (int32_t st = dvgo::launch_status()) return st;
     const int64_t nv = static_cast<int64_t>(field->box.n[0]) * field->box.n[1] * field->box.n[2];
     if (opt)
-        DVGO_LAUNCH(K_GRID_ADAM, vertex_adam_kernel, dim3(grid_for(nv, 256, cus * 16)), dim3(256), 0, s, ba, *opt);
+        DVGO_LAUNCH(K_GRID_ADAM, vertex_adam_kernel, dim3(grid_adam_blocks(nv)), dim3(256), 0, s, ba, *opt);
     else
         DVGO_LAUNCH(K_SCATTER, vertex_gather_kernel, dim3(grid_for(nv, 256, cus * 16)), dim3(256), 0, s, ba);
     return dvgo::launch_status();
@@ -912,7 +979,7 @@ int32_t render_bwd_impl(const dvgo_field* field, const dvgo_mlp* mlp, const floa
         BinArgs ba{};
         ba.g = dvgo::make_grid(field->box);
         const int64_t nv = static_cast<int64_t>(field->box.n[0]) * field->box.n[1] * field->box.n[2];
-        DVGO_LAUNCH(K_GRID_ADAM, vertex_adam_kernel, dim3(grid_for(nv, 256, dvgo::device_cu_count() * 16)), dim3(256),
+        DVGO_LAUNCH(K_GRID_ADAM, vertex_adam_kernel, dim3(grid_adam_blocks(nv)), dim3(256),
                     0, s, ba, *opt);
         return dvgo::launch_status();
     }
