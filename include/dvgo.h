@@ -136,6 +136,9 @@ int32_t dvgo_coarse_mask_build(const float* raw, const dvgo_box* cbox /*host*/,
  *   is truncated (samples at index >= capacity are not written) and the
  *   caller must retry with a larger capacity; capacity = B*max_samples never
  *   overflows.
+ * Clip only: with capacity == 0 and ray_offset == n_kept == NULL, only
+ *   t_near, t_far, valid, n_uniform and perm are produced (no counting of
+ *   kept samples, no list).
  * jitter: [B] per-ray p in [0,1), or NULL for p = 0.
  * workspace: dvgo_sample_workspace_bytes(B) bytes. */
 size_t dvgo_sample_workspace_bytes(int32_t B);

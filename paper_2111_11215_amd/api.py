@@ -184,11 +184,14 @@ def coarse_mask_build(raw: torch.Tensor, cmin, cmax, raw_threshold: float) -> to
 
 
 def sample_rays(rays_o, rays_d, jitter, box_min, box_max, step, max_samples, coarse=None, seg_mask=None,
-                morton=False, capacity=None) -> Samples:
-    """``coarse`` = (bits, cmin, cmax, cn) or None; seg_mask int32 [B] or None."""
+                morton=False, capacity=None, clip_only=False) -> Samples:
+    """``coarse`` = (bits, cmin, cmax, cn) or None; seg_mask int32 [B] or None.
+    ``clip_only``: t_near, t_far, valid, n_uniform and perm only (no list)."""
     lib = load()
     dev = rays_o.device
     B = rays_o.shape[0]
+    if clip_only:
+        capacity = 0
     if capacity is None:
         capacity = B * int(max_samples)
     t_near = torch.empty(B, dtype=torch.float32, device=dev)
@@ -196,10 +199,13 @@ def sample_rays(rays_o, rays_d, jitter, box_min, box_max, step, max_samples, coa
     valid = torch.empty(B, dtype=torch.uint8, device=dev)
     n_uniform = torch.empty(B, dtype=torch.int32, device=dev)
     perm = torch.empty(B, dtype=torch.int32, device=dev)
-    ray_offset = torch.empty(B + 1, dtype=torch.int32, device=dev)
-    sample_ray = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
-    sample_k = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
-    n_kept = torch.empty(1, dtype=torch.int64, device=dev)
+    if clip_only:
+        ray_offset = sample_ray = sample_k = n_kept = None
+    else:
+        ray_offset = torch.empty(B + 1, dtype=torch.int32, device=dev)
+        sample_ray = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+        sample_k = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+        n_kept = torch.empty(1, dtype=torch.int64, device=dev)
     box = make_box(box_min, box_max)
     cbits, cbox = None, None
     if coarse is not None:

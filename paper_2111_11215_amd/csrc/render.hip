@@ -133,30 +133,38 @@ __device__ __forceinline__ int64_t live_count(const int64_t* n_kept, int64_t cap
 // prep: per-ray encodings and first-layer per-ray part
 // ---------------------------------------------------------------------------
 // base[r][i] = b1[i] + sum_q W1[i][C+q] * PE(d_r)[q];  pe[r][0..31] (27 used)
-__global__ void ray_base_kernel(const float* __restrict__ rays_d, int B, const float* __restrict__ w1,
-                                const float* __restrict__ b1, float* __restrict__ base, float* __restrict__ pe) {
-    const int64_t gid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (gid >= static_cast<int64_t>(B) * kH) return;
-    const int r = static_cast<int>(gid / kH);
-    const int i = static_cast<int>(gid % kH);
-    float d[3] = {rays_d[3 * r], rays_d[3 * r + 1], rays_d[3 * r + 2]};
-    float e[kPE];
-    for (int c = 0; c < 3; ++c) e[c] = d[c];
-    for (int fq = 0; fq < 4; ++fq) {
-        const float sc = static_cast<float>(1 << fq);
-        for (int c = 0; c < 3; ++c) {
+// Two rays per 256-thread workgroup: 24 threads evaluate the rays' 24
+// sines and cosines once into LDS, then thread (ray, i) forms output i.
+__global__ __launch_bounds__(256) void ray_base_kernel(const float* __restrict__ rays_d, int B,
+                                                       const float* __restrict__ w1, const float* __restrict__ b1,
+                                                       float* __restrict__ base, float* __restrict__ pe) {
+    __shared__ float se[2][32];
+    const int t = threadIdx.x;
+    const int r0 = 2 * blockIdx.x;
+    if (t < 24) {
+        const int rr = t / 12, q = t % 12, fq = q / 3, c = q % 3;
+        const int r = r0 + rr;
+        if (r < B) {
+            const float dc = rays_d[3 * r + c];
             float sv, cv;
-            sincosf(d[c] * sc, &sv, &cv);
-            e[3 + 6 * fq + c] = sv;
-            e[6 + 6 * fq + c] = cv;
+            sincosf(dc * static_cast<float>(1 << fq), &sv, &cv);
+            se[rr][3 + 6 * fq + c] = sv;
+            se[rr][6 + 6 * fq + c] = cv;
+            if (fq == 0) se[rr][c] = dc;
         }
+    } else if (t < 34) {
+        se[(t - 24) / 5][kPE + (t - 24) % 5] = 0.0f;   // pad 27..31
     }
+    __syncthreads();
+    const int rr = t >> 7, i = t & (kH - 1);
+    const int r = r0 + rr;
+    if (r >= B) return;
     if (w1) {
         float acc = b1[i];
-        for (int q = 0; q < kPE; ++q) acc += w1[i * kIn + kC + q] * e[q];
+        for (int q = 0; q < kPE; ++q) acc += w1[i * kIn + kC + q] * se[rr][q];
         base[static_cast<int64_t>(r) * kH + i] = acc;
     }
-    if (i < 32) pe[static_cast<int64_t>(r) * 32 + i] = i < kPE ? e[i] : 0.0f;
+    if (i < 32) pe[static_cast<int64_t>(r) * 32 + i] = se[rr][i];
 }
 
 // ---------------------------------------------------------------------------

@@ -302,7 +302,9 @@ int32_t dvgo_sample_rays(const float* rays_o, const float* rays_d, const float* 
     for (int i = 0; i < 3; ++i)
         if (!(box->xyz_max[i] > box->xyz_min[i])) return DVGO_E_ARG;
     if (coarse_bits && !dvgo::box_ok(coarse_box, 2)) return DVGO_E_ARG;
-    if (!n_kept || !ray_offset) return DVGO_E_ARG;
+    // clip only: no sample list asked for (capacity 0, ray_offset and n_kept NULL)
+    const bool clip_only = capacity == 0 && !ray_offset && !n_kept;
+    if (!clip_only && (!n_kept || !ray_offset)) return DVGO_E_ARG;
     if (B > 0 && (!rays_o || !rays_d || !t_near || !t_far || !valid || !n_uniform || !perm)) return DVGO_E_ARG;
     if (capacity > 0 && (!sample_ray || !sample_k)) return DVGO_E_ARG;
     if (morton && B > kMaxMortonRays) return DVGO_E_UNSUPPORTED;
@@ -311,6 +313,7 @@ int32_t dvgo_sample_rays(const float* rays_o, const float* rays_d, const float* 
 
     hipStream_t s = dvgo::as_stream(stream);
     if (B == 0) {
+        if (clip_only) return DVGO_OK;
         DVGO_LAUNCH(K_SCAN, scan_offsets_kernel, dim3(1), dim3(kScanThreads), 0, s,
                            static_cast<const int*>(nullptr), 0, ray_offset, n_kept);
         return dvgo::launch_status();
@@ -337,6 +340,7 @@ int32_t dvgo_sample_rays(const float* rays_o, const float* rays_d, const float* 
         DVGO_LAUNCH(K_MORTON_SORT, morton_sort_kernel, dim3(1), dim3(1024), 0, s, keys, B, np2, perm);
         if (int32_t st = dvgo::launch_status()) return st;
     }
+    if (clip_only) return DVGO_OK;
     KeepArgs ka;
     ka.rays_o = rays_o;
     ka.rays_d = rays_d;

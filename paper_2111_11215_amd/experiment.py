@@ -13,7 +13,7 @@ from dataclasses import dataclass, field
 
 import torch
 
-from . import train
+from . import api, train
 
 
 @dataclass
@@ -49,7 +49,8 @@ class RunStats:
 def count_uniform(model: train.FineModel, batches) -> None:
     """Fill each batch's uniform-sample count (clip and count, no list)."""
     for b in batches:
-        s = model.sample(b.o, b.d, b.j, capacity=0)
+        s = api.sample_rays(b.o, b.d, b.j, model.grid.box_min, model.grid.box_max, model.cfg.step,
+                            model.cfg.max_samples, clip_only=True)
         b.n_uniform = int(s.n_uniform.sum().item())
 
 
@@ -87,7 +88,8 @@ def evaluated_per_step(model: train.FineModel, batches, prop: train.ProposalMode
         if prop is None:
             s = model.sample(b.o, b.d, b.j)
         else:
-            s0 = model.sample(b.o, b.d, b.j, capacity=0)
+            s0 = api.sample_rays(b.o, b.d, b.j, model.grid.box_min, model.grid.box_max, model.cfg.step,
+                                 model.cfg.max_samples, clip_only=True)
             _, _, mask = prop.masks(s0)
             s = model.sample(b.o, b.d, b.j, seg_mask=mask)
         tot += int(s.n_kept.item())
@@ -114,7 +116,8 @@ def proposal_render_psnr(model: train.FineModel, prop: train.ProposalModel, view
         for a in range(0, v.o.shape[0], 1 << 16):
             b = min(a + (1 << 16), v.o.shape[0])
             o, d = v.o[a:b].contiguous(), v.d[a:b].contiguous()
-            s0 = model.sample(o, d, None, capacity=0)
+            s0 = api.sample_rays(o, d, None, model.grid.box_min, model.grid.box_max, model.cfg.step,
+                                 model.cfg.max_samples, clip_only=True)
             _, _, mask = prop.masks(s0)
             s = model.sample(o, d, None, seg_mask=mask)
             out[a:b] = model.render(s, want_depth_acc=False)["rgb"]

@@ -153,12 +153,12 @@ class ProposalModel:
 
 def proposal_train_step(model: FineModel, prop: ProposalModel, rays_o, rays_d, target, jitter=None,
                         learn: bool = True) -> dict:
-    """One iteration of the proposal form: clip and count (no list), predict
+    """One iteration of the proposal form: clip (no list), predict
     segment masks, sample only the selected segments (all of them where the
     proposal falls back), render / adjoint / Adam, then update the proposal
     on the first 1/sub of the batch."""
     s0 = api.sample_rays(rays_o, rays_d, jitter, model.grid.box_min, model.grid.box_max, model.cfg.step,
-                         model.cfg.max_samples, capacity=0)
+                         model.cfg.max_samples, clip_only=True)
     _, mass, mask = prop.masks(s0)
     res = model.train_step(rays_o, rays_d, target, jitter, seg_mask=mask)
     if learn:

@@ -87,6 +87,25 @@ def test_sampler_empty_batch_and_all_missing(gpu_lib):
     assert int(np_of(s.n_kept)[0]) == 0 and not np_of(s.valid).any()
 
 
+def test_sampler_clip_only(gpu_lib):
+    """Clip only (no list): t_near, t_far, valid and n_uniform equal those of
+    the full call and of the oracle; an empty batch is accepted."""
+    import torch
+    from paper_2111_11215_amd import api
+    P = synth.tiny_config(2, jitter=True, n_rays=1024)
+    args = (to_dev(P.rays.o), to_dev(P.rays.d), to_dev(P.rays.jitter), P.box_min, P.box_max, P.step,
+            P.max_samples)
+    c = api.sample_rays(*args, clip_only=True)
+    f = api.sample_rays(*args)
+    ref = O.sample_rays(P.rays.o, P.rays.d, P.rays.jitter, P.box_min, P.box_max, P.step, P.max_samples)
+    for k in ("t_near", "t_far", "valid", "n_uniform"):
+        assert np.array_equal(np_of(getattr(c, k)), np_of(getattr(f, k))), k
+    for k in ("t_near", "valid", "n_uniform"):
+        assert np.array_equal(np_of(getattr(c, k)).astype(ref[k].dtype), ref[k]), k
+    z = torch.zeros((0, 3), dtype=torch.float32, device="cuda")
+    api.sample_rays(z, z, None, P.box_min, P.box_max, P.step, 10, clip_only=True)
+
+
 def test_sampler_capacity_overflow_reported(gpu_lib):
     """A capacity below the kept count truncates the list and reports the
     true count, leaving memory past the capacity untouched."""
