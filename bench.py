@@ -269,7 +269,8 @@ def cpu_baseline(ctx, rays, B):
 
 def calibrate_copy(mib):
     """A plain device-to-device copy of known size, to scale the HBM
-    traffic counters (FETCH_SIZE, WRITE_SIZE) of a profiled run."""
+    traffic counters (FETCH_SIZE, WRITE_SIZE) of a profiled run; also
+    prints the copy's own bandwidth (read + write bytes / time)."""
     import torch
     n = mib * (1 << 20) // 4
     a = torch.ones(n, device="cuda:0")
@@ -277,7 +278,47 @@ def calibrate_copy(mib):
     for _ in range(3):
         b.copy_(a)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_mib": mib, "launches": 3}))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    print(json.dumps({"copy_mib": mib, "launches": 13, "ms_per_copy": ms,
+                      "copy_gb_per_s": 2 * mib * (1 << 20) / (ms * 1e-3) / 1e9}))
+
+
+TRAFFIC_SOURCES = {"grid_adam": ("paper_2111_11215_amd/csrc/render.hip", "paper_2111_11215_amd/csrc/adam.hpp",
+                                 "paper_2111_11215_amd/csrc/common.hpp"),
+                   "mlp_bwd": ("paper_2111_11215_amd/csrc/render.hip", "paper_2111_11215_amd/csrc/mlp_mfma.hpp",
+                               "paper_2111_11215_amd/csrc/common.hpp")}
+
+
+def sources_digest(kname):
+    """sha256 over the sources that define the kernel (None if unknown)."""
+    import hashlib
+    if kname not in TRAFFIC_SOURCES:
+        return None
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES[kname]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kname):
+    """HBM bytes per launch of the kernel from the committed rocprofv3 --pmc
+    summary (FETCH_SIZE scaled by the copy calibration, plus WRITE_SIZE), or
+    None when there is none or the kernel's sources changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh).get(kname)
+    if not rec or rec.get("sources_sha256") != sources_digest(kname):
+        return None
+    return rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
 def roofline(per_kernel, kname, n_prof, kept, nv, n_mlp, bf16):
@@ -305,7 +346,7 @@ def roofline(per_kernel, kname, n_prof, kept, nv, n_mlp, bf16):
         achieved = work / (k["ms_avg"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm"], "unit": "GB/s",
                 "frac": achieved / PEAK["hbm"]}
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(kname)
     roof["kernel"] = kname
     roof["launch_ms"] = k["ms_avg"]
     roof["launches_per_step"] = lps

@@ -275,10 +275,11 @@ int32_t dvgo_adam_step(float* p, float* g, float* m, float* v, uint16_t* shadow_
  * seg_mask[r] = the smallest set of segments, by descending q (ties to the
  * lower index), whose q sum reaches cum_frac * pred_mass, or all ones when
  * pred_mass < min_mass or the ray is invalid.  The selection runs in float64
- * from the float32 logits.  valid/t_near come from dvgo_sample_rays. */
+ * from the float32 logits, with cum_frac and min_mass as passed (float64).
+ * valid/t_near come from dvgo_sample_rays. */
 int32_t dvgo_proposal_fwd(const float* rays_o, const float* rays_d, const float* t_near,
                           const uint8_t* valid, int32_t B, const dvgo_box* box /*host*/,
-                          const dvgo_prop* prop /*host*/, float cum_frac, float min_mass,
+                          const dvgo_prop* prop /*host*/, double cum_frac, double min_mass,
                           float* logits, float* pred_mass, uint32_t* seg_mask, void* stream);
 
 /* Proposal backward: KL(p || q) summed over the valid rays and divided by

@@ -8,7 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, c_char_p, c_float, c_int32, c_int64, c_size_t, c_void_p
+from ctypes import POINTER, c_char_p, c_double, c_float, c_int32, c_int64, c_size_t, c_void_p
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libdvgo.so")
@@ -68,7 +68,8 @@ SIGNATURES = {
                                        c_float, POINTER(c_float), P, P, P, P, POINTER(GridAdam), P, P, c_size_t, P]),
     "dvgo_photo_loss": (c_int32, [P, P, c_int32, P, P, P]),
     "dvgo_adam_step": (c_int32, [P, P, P, P, P, c_int64, c_float, c_float, c_float, c_float, c_int32, P]),
-    "dvgo_proposal_fwd": (c_int32, [P, P, P, P, c_int32, POINTER(Box), POINTER(Prop), c_float, c_float, P, P, P, P]),
+    "dvgo_proposal_fwd": (c_int32, [P, P, P, P, c_int32, POINTER(Box), POINTER(Prop), c_double, c_double, P, P, P,
+                                    P]),
     "dvgo_proposal_bwd": (c_int32, [P, P, P, P, c_int32, POINTER(Box), POINTER(Prop), P, P, P, P, P, c_size_t, P]),
     "dvgo_proposal_workspace_bytes": (c_size_t, [c_int32]),
     "dvgo_scene_render": (c_int32, [P, P, c_int32, POINTER(Box), P, c_int32, c_float, c_float, POINTER(c_float), P,

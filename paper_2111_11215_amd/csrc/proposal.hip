@@ -211,7 +211,7 @@ __device__ uint32_t select_mask(const float z[kS], double cum_frac, double min_m
 constexpr int kRaysPerWave = 32;
 constexpr int kWaves = 4;
 
-__global__ __launch_bounds__(256) void proposal_fwd_kernel(PropArgs a, int run_net, float cum_frac, float min_mass,
+__global__ __launch_bounds__(256) void proposal_fwd_kernel(PropArgs a, int run_net, double cum_frac, double min_mass,
                                                            float* __restrict__ logits, float* __restrict__ pred_mass,
                                                            uint32_t* __restrict__ seg_mask) {
     __shared__ PropLds L;
@@ -430,12 +430,12 @@ size_t dvgo_proposal_workspace_bytes(int32_t B) {
 
 // prop == NULL: `logits` is an input and only the selection runs.
 int32_t dvgo_proposal_fwd(const float* rays_o, const float* rays_d, const float* t_near, const uint8_t* valid,
-                          int32_t B, const dvgo_box* box, const dvgo_prop* prop, float cum_frac, float min_mass,
+                          int32_t B, const dvgo_box* box, const dvgo_prop* prop, double cum_frac, double min_mass,
                           float* logits, float* pred_mass, uint32_t* seg_mask, void* stream) {
     PropArgs a;
     if (!fill_args(a, rays_o, rays_d, t_near, valid, B, box, prop)) return DVGO_E_ARG;
     if (B > 0 && !logits) return DVGO_E_ARG;
-    if (!(cum_frac > 0.0f && cum_frac <= 1.0f) || !(min_mass >= 0.0f && min_mass <= 1.0f)) return DVGO_E_ARG;
+    if (!(cum_frac > 0.0 && cum_frac <= 1.0) || !(min_mass >= 0.0 && min_mass <= 1.0)) return DVGO_E_ARG;
     if (B == 0) return DVGO_OK;
     DVGO_LAUNCH(K_PROP_FWD, proposal_fwd_kernel, dim3((B + 127) / 128), dim3(256), 0,
                        dvgo::as_stream(stream), a, prop != nullptr, cum_frac, min_mass, logits, pred_mass, seg_mask);
