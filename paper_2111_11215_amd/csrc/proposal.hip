@@ -50,39 +50,54 @@ __device__ __forceinline__ bf16x8 pack8(const f32x16& v, int g) {
     return r;
 }
 
-// Matrix-core operands in LDS (bf16x8 per lane and step):
-//   W1 [mt 2][st 4][lane]: W1[32mt+m][16st+8h+i] (k >= 54 zero)
-//   W2 [mt 2][st 4][lane]: W2[32mt+m][phi16(st,i,h)]
-//   W3 [st 4][lane]:       W3[m][phi16(st,i,h)]
-//   W2T[mt 2][st 4][lane]: W2[phi16(st,i,h)][32mt+m]
-//   W3T[mt 2][st 2][lane]: W3[phi16(st,i,h)][32mt+m]
-struct PropLds {
-    bf16x8 w1[2 * 4 * 64];
-    bf16x8 w2[2 * 4 * 64];
-    bf16x8 w3[4 * 64];
-    bf16x8 w2t[2 * 4 * 64];
-    bf16x8 w3t[2 * 2 * 64];
-};
-
-__device__ void pack_weights(const PropArgs& a, PropLds& L, bool transposed) {
-    for (int idx = threadIdx.x; idx < 2 * 4 * 64 * 8; idx += blockDim.x) {
-        const int i = idx & 7, lane = (idx >> 3) & 63, st = (idx >> 9) & 3, mt = idx >> 11;
-        const int m = lane & 31, h = lane >> 5;
-        const int k1 = 16 * st + 8 * h + i;
-        const int row = 32 * mt + m, k2 = phi16(st, i, h);
-        reinterpret_cast<__bf16*>(L.w1)[idx] = static_cast<__bf16>(k1 < kIn ? a.w[0][row * kIn + k1] : 0.0f);
-        reinterpret_cast<__bf16*>(L.w2)[idx] = static_cast<__bf16>(a.w[1][row * kH + k2]);
-        if (transposed) reinterpret_cast<__bf16*>(L.w2t)[idx] = static_cast<__bf16>(a.w[1][k2 * kH + row]);
-        if (idx < 4 * 64 * 8) {
-            const int st3 = idx >> 9;
-            reinterpret_cast<__bf16*>(L.w3)[idx] = static_cast<__bf16>(a.w[2][m * kH + phi16(st3, i, h)]);
-        }
-        if (transposed && idx < 2 * 2 * 64 * 8) {
-            const int st3 = (idx >> 9) & 1, mt3 = idx >> 10;
-            reinterpret_cast<__bf16*>(L.w3t)[idx] =
-                static_cast<__bf16>(a.w[2][phi16(st3, i, h) * kH + 32 * mt3 + m]);
-        }
+// Matrix-core operand fragments, built per lane straight from the float32
+// weights (row-major [out][in]) with vector loads and rounded to bfloat16:
+//   w1(mt, st):  W1[32mt+m][16st+8h+i]   (k >= 54 zero)
+//   w2(mt, st):  W2[32mt+m][phi16(st,i,h)]
+//   w3(st):      W3[m][phi16(st,i,h)]
+//   w2t(mt, st): W2[phi16(st,i,h)][32mt+m]
+//   w3t(mt, st): W3[phi16(st,i,h)][32mt+m]
+// phi16(st, i, h) for i = 0..3 and 4..7 is two runs of 4 consecutive inputs.
+__device__ __forceinline__ bf16x8 frag_w1(const float* w1, int mt, int st, int m, int h) {
+    const float* row = w1 + (32 * mt + m) * kIn;
+    const int k0 = 16 * st + 8 * h;
+    bf16x8 r;
+    #pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        float2 v = make_float2(0.0f, 0.0f);
+        if (k0 + 2 * j < kIn) v = *reinterpret_cast<const float2*>(row + k0 + 2 * j);   // kIn is even
+        r[2 * j] = static_cast<__bf16>(v.x);
+        r[2 * j + 1] = static_cast<__bf16>(v.y);
     }
+    return r;
+}
+
+__device__ __forceinline__ bf16x8 frag_rows(const float* row0) {
+    const float4 a = *reinterpret_cast<const float4*>(row0);
+    const float4 b = *reinterpret_cast<const float4*>(row0 + 8);
+    bf16x8 r;
+    r[0] = static_cast<__bf16>(a.x); r[1] = static_cast<__bf16>(a.y);
+    r[2] = static_cast<__bf16>(a.z); r[3] = static_cast<__bf16>(a.w);
+    r[4] = static_cast<__bf16>(b.x); r[5] = static_cast<__bf16>(b.y);
+    r[6] = static_cast<__bf16>(b.z); r[7] = static_cast<__bf16>(b.w);
+    return r;
+}
+
+__device__ __forceinline__ int phi16_base(int st, int h) { return 32 * (st >> 1) + 16 * (st & 1) + 4 * h; }
+
+__device__ __forceinline__ bf16x8 frag_w2(const float* w2, int mt, int st, int m, int h) {
+    return frag_rows(w2 + (32 * mt + m) * kH + phi16_base(st, h));
+}
+
+__device__ __forceinline__ bf16x8 frag_w3(const float* w3, int st, int m, int h) {
+    return frag_rows(w3 + m * kH + phi16_base(st, h));
+}
+
+__device__ __forceinline__ bf16x8 frag_cols(const float* w, int st, int col, int h) {
+    bf16x8 r;
+    #pragma unroll
+    for (int i = 0; i < 8; ++i) r[i] = static_cast<__bf16>(w[phi16(st, i, h) * kH + col]);
+    return r;
 }
 
 // Encoding: PE4 of the box-entry point in box coordinates, then PE4 of d.
@@ -118,8 +133,8 @@ struct PropFwd {
 };
 
 // Forward of the 32 rays of a wave (ray = lane % 32).
-__device__ void prop_forward(const PropArgs& a, const PropLds& L, int r, bool ray_ok, int lane, PropFwd& f) {
-    const int h = lane >> 5;
+__device__ void prop_forward(const PropArgs& a, int r, bool ray_ok, int lane, PropFwd& f) {
+    const int h = lane >> 5, m = lane & 31;
     float e[kIn];
     if (ray_ok) encode(a, r, e);
     #pragma unroll
@@ -138,7 +153,7 @@ __device__ void prop_forward(const PropArgs& a, const PropLds& L, int r, bool ra
         #pragma unroll
         for (int rr = 0; rr < 16; ++rr) acc[rr] = a.b[0][32 * mt + acc_row(rr, h)];
         #pragma unroll
-        for (int st = 0; st < 4; ++st) acc = mma(L.w1[(mt * 4 + st) * 64 + lane], f.enc[st], acc);
+        for (int st = 0; st < 4; ++st) acc = mma(frag_w1(a.w[0], mt, st, m, h), f.enc[st], acc);
         #pragma unroll
         for (int rr = 0; rr < 16; ++rr) f.h1[mt][rr] = fmaxf(acc[rr], 0.0f);
     }
@@ -151,7 +166,7 @@ __device__ void prop_forward(const PropArgs& a, const PropLds& L, int r, bool ra
         #pragma unroll
         for (int rr = 0; rr < 16; ++rr) acc[rr] = a.b[1][32 * mt + acc_row(rr, h)];
         #pragma unroll
-        for (int st = 0; st < 4; ++st) acc = mma(L.w2[(mt * 4 + st) * 64 + lane], hb[st], acc);
+        for (int st = 0; st < 4; ++st) acc = mma(frag_w2(a.w[1], mt, st, m, h), hb[st], acc);
         f.h2[mt] = acc;   // pre-activation kept for the ReLU mask
     }
     #pragma unroll
@@ -164,7 +179,7 @@ __device__ void prop_forward(const PropArgs& a, const PropLds& L, int r, bool ra
     #pragma unroll
     for (int rr = 0; rr < 16; ++rr) f.z[rr] = a.b[2][acc_row(rr, h)];
     #pragma unroll
-    for (int st = 0; st < 4; ++st) f.z = mma(L.w3[st * 64 + lane], hb[st], f.z);
+    for (int st = 0; st < 4; ++st) f.z = mma(frag_w3(a.w[2], st, m, h), hb[st], f.z);
 }
 
 // Segment mask from float32 logits; float64 arithmetic, sums in index
@@ -209,22 +224,19 @@ __device__ uint32_t select_mask(const float z[kS], double cum_frac, double min_m
 }
 
 constexpr int kRaysPerWave = 32;
-constexpr int kWaves = 4;
+constexpr int kWaves = 1;   // one wavefront (32 rays) per workgroup
 
-__global__ __launch_bounds__(256) void proposal_fwd_kernel(PropArgs a, int run_net, double cum_frac, double min_mass,
-                                                           float* __restrict__ logits, float* __restrict__ pred_mass,
-                                                           uint32_t* __restrict__ seg_mask) {
-    __shared__ PropLds L;
+__global__ __launch_bounds__(64) void proposal_fwd_kernel(PropArgs a, int run_net, double cum_frac, double min_mass,
+                                                          float* __restrict__ logits, float* __restrict__ pred_mass,
+                                                          uint32_t* __restrict__ seg_mask) {
     __shared__ float sZ[kWaves][kRaysPerWave][kS + 1];
-    if (run_net) pack_weights(a, L, false);
-    __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m = lane & 31, h = lane >> 5;
     const int r = (blockIdx.x * kWaves + wave) * kRaysPerWave + m;
     const bool ray_ok = r < a.B;
     if (run_net) {
         PropFwd f;
-        prop_forward(a, L, r, ray_ok, lane, f);
+        prop_forward(a, r, ray_ok, lane, f);
         #pragma unroll
         for (int rr = 0; rr < 16; ++rr) {
             const int sg = acc_row(rr, h);
@@ -254,14 +266,11 @@ __global__ __launch_bounds__(256) void proposal_fwd_kernel(PropArgs a, int run_n
 // wave writes its own partial of the flat gradient.
 constexpr int kRP = 40;   // LDS pitch (bf16) of a staged feature row of 32 rays
 
-__global__ __launch_bounds__(256) void proposal_bwd_kernel(PropArgs a, const float* __restrict__ seg_w,
-                                                           const float* __restrict__ log_t_end,
-                                                           float* __restrict__ partial,
-                                                           float* __restrict__ loss_part) {
-    __shared__ PropLds L;
+__global__ __launch_bounds__(64) void proposal_bwd_kernel(PropArgs a, const float* __restrict__ seg_w,
+                                                          const float* __restrict__ log_t_end,
+                                                          float* __restrict__ partial,
+                                                          float* __restrict__ loss_part) {
     __shared__ __attribute__((aligned(16))) __bf16 sT[kWaves][(64 * 5 + 32) * kRP];
-    pack_weights(a, L, true);
-    __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m = lane & 31, h = lane >> 5;
     const int wglob = blockIdx.x * kWaves + wave;
@@ -269,7 +278,7 @@ __global__ __launch_bounds__(256) void proposal_bwd_kernel(PropArgs a, const flo
     const bool in_batch = r < a.B;
     const bool ok = in_batch && (!a.valid || a.valid[r]);
     PropFwd f;
-    prop_forward(a, L, r, in_batch, lane, f);
+    prop_forward(a, r, in_batch, lane, f);
     // softmax over the 32 logits and the implicit 0, split over the two halves
     float mx = 0.0f;
     #pragma unroll
@@ -305,7 +314,7 @@ __global__ __launch_bounds__(256) void proposal_bwd_kernel(PropArgs a, const flo
     for (int mt = 0; mt < 2; ++mt) {
         f32x16 acc = zero16();
         #pragma unroll
-        for (int st = 0; st < 2; ++st) acc = mma(L.w3t[(mt * 2 + st) * 64 + lane], zb[st], acc);
+        for (int st = 0; st < 2; ++st) acc = mma(frag_cols(a.w[2], st, 32 * mt + m, h), zb[st], acc);
         #pragma unroll
         for (int rr = 0; rr < 16; ++rr) d2[mt][rr] = f.h2[mt][rr] > 0.0f ? acc[rr] : 0.0f;
     }
@@ -316,7 +325,7 @@ __global__ __launch_bounds__(256) void proposal_bwd_kernel(PropArgs a, const flo
     for (int mt = 0; mt < 2; ++mt) {
         f32x16 acc = zero16();
         #pragma unroll
-        for (int st = 0; st < 4; ++st) acc = mma(L.w2t[(mt * 4 + st) * 64 + lane], db[st], acc);
+        for (int st = 0; st < 4; ++st) acc = mma(frag_cols(a.w[1], st, 32 * mt + m, h), db[st], acc);
         #pragma unroll
         for (int rr = 0; rr < 16; ++rr) d1[mt][rr] = f.h1[mt][rr] > 0.0f ? acc[rr] : 0.0f;
     }
@@ -408,6 +417,10 @@ bool fill_args(PropArgs& a, const float* rays_o, const float* rays_d, const floa
     }
     if (prop) {
         if (!prop->w1 || !prop->b1 || !prop->w2 || !prop->b2 || !prop->w3 || !prop->b3) return false;
+        // vector loads of the weight rows: W1 8-byte, W2 and W3 16-byte aligned
+        if ((reinterpret_cast<uintptr_t>(prop->w1) & 7u) || (reinterpret_cast<uintptr_t>(prop->w2) & 15u) ||
+            (reinterpret_cast<uintptr_t>(prop->w3) & 15u))
+            return false;
         a.w[0] = prop->w1; a.w[1] = prop->w2; a.w[2] = prop->w3;
         a.b[0] = prop->b1; a.b[1] = prop->b2; a.b[2] = prop->b3;
     } else {
@@ -437,7 +450,7 @@ int32_t dvgo_proposal_fwd(const float* rays_o, const float* rays_d, const float*
     if (B > 0 && !logits) return DVGO_E_ARG;
     if (!(cum_frac > 0.0 && cum_frac <= 1.0) || !(min_mass >= 0.0 && min_mass <= 1.0)) return DVGO_E_ARG;
     if (B == 0) return DVGO_OK;
-    DVGO_LAUNCH(K_PROP_FWD, proposal_fwd_kernel, dim3((B + 127) / 128), dim3(256), 0,
+    DVGO_LAUNCH(K_PROP_FWD, proposal_fwd_kernel, dim3((B + kRaysPerWave - 1) / kRaysPerWave), dim3(64 * kWaves), 0,
                        dvgo::as_stream(stream), a, prop != nullptr, cum_frac, min_mass, logits, pred_mass, seg_mask);
     return dvgo::launch_status();
 }
@@ -451,13 +464,14 @@ int32_t dvgo_proposal_bwd(const float* rays_o, const float* rays_d, const float*
     if (B > 0 && (!seg_w || !log_t_end || !grad_prop)) return DVGO_E_ARG;
     if (workspace_bytes < dvgo_proposal_workspace_bytes(B) || (B > 0 && !workspace)) return DVGO_E_CAPACITY;
     if (B == 0) return DVGO_OK;
-    const int nblk = (B + 127) / 128;
+    const int nblk = (B + kRaysPerWave * kWaves - 1) / (kRaysPerWave * kWaves);
     const int nw = nblk * kWaves;
     float* partial = static_cast<float*>(workspace);
     float* loss_part = reinterpret_cast<float*>(static_cast<char*>(workspace) +
                                                 dvgo::align_up(static_cast<size_t>(nw) * kPStride * 4, 256));
     hipStream_t s = dvgo::as_stream(stream);
-    DVGO_LAUNCH(K_PROP_BWD, proposal_bwd_kernel, dim3(nblk), dim3(256), 0, s, a, seg_w, log_t_end, partial, loss_part);
+    DVGO_LAUNCH(K_PROP_BWD, proposal_bwd_kernel, dim3(nblk), dim3(64 * kWaves), 0, s, a, seg_w, log_t_end, partial,
+                loss_part);
     if (int32_t st = dvgo::launch_status()) return st;
     DVGO_LAUNCH(K_PROP_REDUCE, proposal_reduce_kernel, dim3((kParams + 255) / 256), dim3(256), 0, s, partial, loss_part,
                 nw, grad_prop, loss);

@@ -22,6 +22,45 @@ struct BoxF {
 };
 
 // One thread per ray: clip, uniform count, Morton key or identity order.
+// Slab clip and uniform count of one ray (float32 recipe, no contraction).
+struct Clip {
+    float tn, tx;
+    bool v;
+    int n;
+};
+
+__device__ __forceinline__ Clip clip_ray(const float o[3], const float d[3], float p, const BoxF& box, float step,
+                                         int max_samples) {
+#pragma clang fp contract(off)
+    float te = -INFINITY, tx = INFINITY;
+    bool miss = false;
+    for (int i = 0; i < 3; ++i) {
+        if (d[i] == 0.0f) {
+            if (o[i] < box.mn[i] || o[i] > box.mx[i]) miss = true;
+        } else {
+            const float inv = 1.0f / d[i];
+            const float t0 = (box.mn[i] - o[i]) * inv;
+            const float t1 = (box.mx[i] - o[i]) * inv;
+            te = fmaxf(te, fminf(t0, t1));
+            tx = fminf(tx, fmaxf(t0, t1));
+        }
+    }
+    Clip c;
+    c.tn = fmaxf(te, 0.0f);
+    c.tx = tx;
+    c.v = !miss && (c.tn < tx);
+    c.n = 0;
+    if (c.v) {
+        // estimate, then settle on the exact prefix length (t_k is monotone in k)
+        const float est = (tx - c.tn) / step - p;
+        int k = static_cast<int>(fminf(fmaxf(floorf(est) - 2.0f, 0.0f), static_cast<float>(max_samples)));
+        while (k > 0 && !(recipe_tk(c.tn, p, k - 1, step) < tx)) --k;
+        while (k < max_samples && recipe_tk(c.tn, p, k, step) < tx) ++k;
+        c.n = k;
+    }
+    return c;
+}
+
 __global__ void ray_setup_kernel(const float* __restrict__ rays_o, const float* __restrict__ rays_d,
                                  const float* __restrict__ jitter, int B, BoxF box, float step,
                                  int max_samples, int morton, float* __restrict__ t_near,
@@ -36,35 +75,13 @@ __global__ void ray_setup_kernel(const float* __restrict__ rays_o, const float* 
         o[i] = rays_o[3 * r + i];
         d[i] = rays_d[3 * r + i];
     }
-    float te = -INFINITY, tx = INFINITY;
-    bool miss = false;
-    for (int i = 0; i < 3; ++i) {
-        if (d[i] == 0.0f) {
-            if (o[i] < box.mn[i] || o[i] > box.mx[i]) miss = true;
-        } else {
-            const float inv = 1.0f / d[i];
-            const float t0 = (box.mn[i] - o[i]) * inv;
-            const float t1 = (box.mx[i] - o[i]) * inv;
-            te = fmaxf(te, fminf(t0, t1));
-            tx = fminf(tx, fmaxf(t0, t1));
-        }
-    }
-    const float tn = fmaxf(te, 0.0f);
-    const bool v = !miss && (tn < tx);
-    int n = 0;
-    if (v) {
-        const float p = jitter ? jitter[r] : 0.0f;
-        // estimate, then settle on the exact prefix length (t_k is monotone in k)
-        const float est = (tx - tn) / step - p;
-        int k = static_cast<int>(fminf(fmaxf(floorf(est) - 2.0f, 0.0f), static_cast<float>(max_samples)));
-        while (k > 0 && !(recipe_tk(tn, p, k - 1, step) < tx)) --k;
-        while (k < max_samples && recipe_tk(tn, p, k, step) < tx) ++k;
-        n = k;
-    }
+    const Clip c = clip_ray(o, d, jitter ? jitter[r] : 0.0f, box, step, max_samples);
+    const float tn = c.tn, tx = c.tx;
+    const bool v = c.v;
     t_near[r] = v ? tn : 0.0f;
     t_far[r] = v ? tx : 0.0f;
     valid[r] = v ? 1 : 0;
-    n_uniform[r] = n;
+    n_uniform[r] = c.n;
     if (morton) {
         uint32_t key = kMortonInvalid;
         if (v) {
@@ -163,6 +180,38 @@ __device__ __forceinline__ bool keep_sample(const KeepArgs& a, const RayView& v,
         if (!((a.coarse_bits[c >> 5] >> (c & 31)) & 1u)) return false;
     }
     return true;
+}
+
+// Identity order: one wavefront per ray clips it (every lane the same
+// float32 recipe; lane 0 writes) and counts its kept samples, in one pass.
+__global__ __launch_bounds__(256) void setup_count_kernel(KeepArgs a, BoxF box, int max_samples,
+                                                          float* __restrict__ t_near, float* __restrict__ t_far,
+                                                          uint8_t* __restrict__ valid, int* __restrict__ n_uniform,
+                                                          int* __restrict__ perm, int* __restrict__ counts) {
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (r >= a.B) return;
+    RayView v;
+    v.r = r;
+    for (int i = 0; i < 3; ++i) {
+        v.o[i] = a.rays_o[3 * r + i];
+        v.d[i] = a.rays_d[3 * r + i];
+    }
+    v.p = a.jitter ? a.jitter[r] : 0.0f;
+    v.seg = a.seg_mask ? a.seg_mask[r] : 0xFFFFFFFFu;
+    const Clip c = clip_ray(v.o, v.d, v.p, box, a.step, max_samples);
+    v.tn = c.v ? c.tn : 0.0f;
+    v.n = c.n;
+    if (lane == 0) {
+        t_near[r] = v.tn;
+        t_far[r] = c.v ? c.tx : 0.0f;
+        valid[r] = c.v ? 1 : 0;
+        n_uniform[r] = c.n;
+        perm[r] = r;
+    }
+    int cnt = 0;
+    for (int base = 0; base < v.n; base += 64) cnt += __popcll(__ballot(keep_sample(a, v, base + lane)));
+    if (lane == 0) counts[r] = cnt;
 }
 
 // One wavefront per ray slot: number of kept samples.
@@ -330,17 +379,6 @@ int32_t dvgo_sample_rays(const float* rays_o, const float* rays_d, const float* 
         volatile float q = static_cast<float>(1 << kMortonBits);
         bf.mscale[i] = q / span;
     }
-    const int t1 = 256;
-    DVGO_LAUNCH(K_RAY_SETUP, ray_setup_kernel, dim3((B + t1 - 1) / t1), dim3(t1), 0, s, rays_o, rays_d, jitter, B, bf,
-                       step, max_samples, morton, t_near, t_far, valid, n_uniform, keys, perm);
-    if (int32_t st = dvgo::launch_status()) return st;
-    if (morton) {
-        int np2 = 2;
-        while (np2 < B) np2 <<= 1;
-        DVGO_LAUNCH(K_MORTON_SORT, morton_sort_kernel, dim3(1), dim3(1024), 0, s, keys, B, np2, perm);
-        if (int32_t st = dvgo::launch_status()) return st;
-    }
-    if (clip_only) return DVGO_OK;
     KeepArgs ka;
     ka.rays_o = rays_o;
     ka.rays_d = rays_d;
@@ -354,8 +392,25 @@ int32_t dvgo_sample_rays(const float* rays_o, const float* rays_d, const float* 
     ka.step = step;
     ka.B = B;
     const unsigned wblocks = static_cast<unsigned>((B + 3) / 4);
-    DVGO_LAUNCH(K_COUNT_KEPT, count_kept_kernel, dim3(wblocks), dim3(256), 0, s, ka, counts);
-    if (int32_t st = dvgo::launch_status()) return st;
+    if (!morton && !clip_only) {
+        DVGO_LAUNCH(K_RAY_SETUP, setup_count_kernel, dim3(wblocks), dim3(256), 0, s, ka, bf, max_samples, t_near,
+                    t_far, valid, n_uniform, perm, counts);
+        if (int32_t st = dvgo::launch_status()) return st;
+    } else {
+        const int t1 = 256;
+        DVGO_LAUNCH(K_RAY_SETUP, ray_setup_kernel, dim3((B + t1 - 1) / t1), dim3(t1), 0, s, rays_o, rays_d, jitter, B,
+                    bf, step, max_samples, morton, t_near, t_far, valid, n_uniform, keys, perm);
+        if (int32_t st = dvgo::launch_status()) return st;
+        if (morton) {
+            int np2 = 2;
+            while (np2 < B) np2 <<= 1;
+            DVGO_LAUNCH(K_MORTON_SORT, morton_sort_kernel, dim3(1), dim3(1024), 0, s, keys, B, np2, perm);
+            if (int32_t st = dvgo::launch_status()) return st;
+        }
+        if (clip_only) return DVGO_OK;
+        DVGO_LAUNCH(K_COUNT_KEPT, count_kept_kernel, dim3(wblocks), dim3(256), 0, s, ka, counts);
+        if (int32_t st = dvgo::launch_status()) return st;
+    }
     DVGO_LAUNCH(K_SCAN, scan_offsets_kernel, dim3(1), dim3(kScanThreads), 0, s, counts, B, ray_offset, n_kept);
     if (int32_t st = dvgo::launch_status()) return st;
     DVGO_LAUNCH(K_FILL_KEPT, fill_kept_kernel, dim3(wblocks), dim3(256), 0, s, ka, ray_offset, capacity, sample_ray,
