@@ -62,6 +62,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--form", choices=["proposal", "bf16", "plain"], default="proposal")
+    ap.add_argument("--morton", type=int, default=0, help="1: Morton-ordered ray slots in every form")
     ap.add_argument("--pretrain", type=int, default=0,
                     help="with --compare-iters 0: training iterations of the timed form before timing")
     ap.add_argument("--rays", type=int, default=8192)
@@ -99,7 +100,7 @@ def setup(args):
     coarse = (bits, bmin, bmax, raw.shape)
     spheres = torch.as_tensor(sp.as_f32_table()).to(dev)
     return dict(step=step, max_samples=max_samples, b=b, raw=raw, bits=bits, coarse=coarse, spheres=sp,
-                spheres_t=spheres, bmin=bmin, bmax=bmax, n=n, cams=cams, held=held)
+                spheres_t=spheres, bmin=bmin, bmax=bmax, n=n, cams=cams, held=held, morton=bool(args.morton))
 
 
 def make_batches(ctx, n_iter, rays, seed0=1000):
@@ -155,7 +156,7 @@ def new_model(ctx, bf16):
     Ws, bs = synth.xavier_uniform_mlp(np.random.default_rng(7), (39, 128, 128, 3))
     flat = api.flat_from([Ws[0], bs[0], Ws[1], bs[1], Ws[2], bs[2]], api.MLP_SHAPES, dev)
     cfg = train.FineConfig(step=ctx["step"], max_samples=ctx["max_samples"],
-                           precision=DVGO_BF16 if bf16 else DVGO_F32, bf16_feat=bf16)
+                           precision=DVGO_BF16 if bf16 else DVGO_F32, bf16_feat=bf16, morton=ctx["morton"])
     return train.FineModel(torch.zeros((n, n, n), device=dev), torch.zeros((n, n, n, 12), device=dev), flat,
                            ctx["bmin"], ctx["bmax"], ctx["b"], cfg, coarse=ctx["coarse"])
 
@@ -438,7 +439,7 @@ def main():
                                 + (f", timed after {args.compare_iters} training iterations"
                                    if args.compare_iters > 0 else f", timed after {args.pretrain} iterations")),
                    "form": name, "rays_per_iter": args.rays, "grid": ctx["n"], "coarse": 100,
-                   "max_samples": ctx["max_samples"]},
+                   "max_samples": ctx["max_samples"], "morton": bool(args.morton)},
         "evaluated_samples_per_step": kept,
         "uniform_samples_per_step": st.uniform_samples / args.steps,
         "rays_per_s": args.rays * args.steps / st.seconds,
@@ -449,6 +450,10 @@ def main():
             kname = max((k for k in ROOFLINE_MODELS if k in per_kernel), key=lambda k: per_kernel[k]["ms_total"])
         nv = ctx["n"] ** 3
         out["roofline"] = roofline(per_kernel, kname, n_prof, kept, nv, model.st_mlp.p.numel(), bf16)
+        out["kernels_roofline"] = {
+            k: {f: v for f, v in roofline(per_kernel, k, n_prof, kept, nv, model.st_mlp.p.numel(), bf16).items()
+                if f in ("bound", "achieved", "unit", "frac", "launch_ms", "launches_per_step")}
+            for k in ROOFLINE_MODELS if k in per_kernel and k != "adam"}
         out["kernels_ms_per_step"] = {k: v["ms_total"] / n_prof for k, v in per_kernel.items()}
     if out_cmp is not None:
         out["proposal_comparison"] = out_cmp

@@ -119,7 +119,7 @@ def proposal_render_psnr(model: train.FineModel, prop: train.ProposalModel, view
             s0 = api.sample_rays(o, d, None, model.grid.box_min, model.grid.box_max, model.cfg.step,
                                  model.cfg.max_samples, clip_only=True)
             _, _, mask = prop.masks(s0)
-            s = model.sample(o, d, None, seg_mask=mask)
+            s = model.sample(o, d, None, seg_mask=mask, morton=False)
             out[a:b] = model.render(s, want_depth_acc=False)["rgb"]
         mse = float(((out - ref) ** 2).mean().item())
         vals.append(-10.0 * math.log10(max(mse, 1e-12)))

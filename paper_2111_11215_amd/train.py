@@ -71,10 +71,10 @@ class FineModel:
     def lr(self, base: float) -> float:
         return base * 0.1 ** (self.t / self.cfg.decay_steps)
 
-    def sample(self, rays_o, rays_d, jitter, seg_mask=None, capacity=None) -> api.Samples:
+    def sample(self, rays_o, rays_d, jitter, seg_mask=None, capacity=None, morton=None) -> api.Samples:
         c = self.cfg
         return api.sample_rays(rays_o, rays_d, jitter, self.grid.box_min, self.grid.box_max, c.step, c.max_samples,
-                               coarse=self.coarse, seg_mask=seg_mask, morton=c.morton,
+                               coarse=self.coarse, seg_mask=seg_mask, morton=c.morton if morton is None else morton,
                                capacity=c.capacity if capacity is None else capacity)
 
     def render(self, s: api.Samples, **kw) -> dict:
@@ -175,6 +175,6 @@ def render_rays(model: FineModel, rays_o, rays_d, chunk: int = 1 << 16) -> torch
     out = torch.empty((rays_o.shape[0], 3), dtype=torch.float32, device=rays_o.device)
     for a in range(0, rays_o.shape[0], chunk):
         b = min(a + chunk, rays_o.shape[0])
-        s = model.sample(rays_o[a:b].contiguous(), rays_d[a:b].contiguous(), None)
+        s = model.sample(rays_o[a:b].contiguous(), rays_d[a:b].contiguous(), None, morton=False)
         out[a:b] = model.render(s, want_depth_acc=False)["rgb"]
     return out
