@@ -16,15 +16,16 @@ struct AdamArgs {
     dvgo::AdamCoef c;
 };
 
-// 16-byte vectors: every pointer 16-byte aligned, n4 = n/4 vectors.
+// 16-byte vectors: every pointer 16-byte aligned, n4 = n/4 vectors; the
+// last n % 4 values are taken by the first threads of the grid.
 __global__ __launch_bounds__(256) void adam_vec_kernel(AdamArgs a) {
     const int64_t n4 = a.n >> 2;
     float4* P = reinterpret_cast<float4*>(a.p);
     float4* G = reinterpret_cast<float4*>(a.g);
     float4* M = reinterpret_cast<float4*>(a.m);
     float4* V = reinterpret_cast<float4*>(a.v);
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n4;
-         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t tid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (int64_t i = tid; i < n4; i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         float4 p = P[i], g = G[i], m = M[i], v = V[i];
         dvgo::adam_update(a.c, p.x, g.x, m.x, v.x);
         dvgo::adam_update(a.c, p.y, g.y, m.y, v.y);
@@ -35,6 +36,16 @@ __global__ __launch_bounds__(256) void adam_vec_kernel(AdamArgs a) {
         V[i] = v;
         G[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         if (a.shadow) reinterpret_cast<uint2*>(a.shadow)[i] = dvgo::bf16x4_bits(p);
+    }
+    const int64_t t = 4 * n4 + tid;
+    if (t < a.n) {
+        float p = a.p[t], m = a.m[t], v = a.v[t];
+        dvgo::adam_update(a.c, p, a.g[t], m, v);
+        a.p[t] = p;
+        a.m[t] = m;
+        a.v[t] = v;
+        a.g[t] = 0.0f;
+        if (a.shadow) a.shadow[t] = dvgo::bf16_bits(p);
     }
 }
 
@@ -113,7 +124,7 @@ int32_t dvgo_adam_step(float* p, float* g, float* m, float* v, uint16_t* shadow_
         if (blocks > static_cast<int64_t>(cus) * 8) blocks = static_cast<int64_t>(cus) * 8;
         DVGO_LAUNCH(K_ADAM, adam_vec_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, a);
         if (int32_t st = dvgo::launch_status()) return st;
-        done = n4 * 4;
+        done = n;   // the tail (n % 4 < 256 values) is handled in the same launch
     }
     if (done < n) {
         int64_t blocks = (n - done + 255) / 256;

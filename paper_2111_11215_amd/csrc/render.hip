@@ -693,67 +693,87 @@ __device__ __forceinline__ int block_excl_scan_1024(int v, int* sh, int* total) 
     return woff + incl - v;
 }
 
+// Eight consecutive counts of one thread (zero past n); 32-byte aligned.
+__device__ __forceinline__ void load8(const int* __restrict__ in, int64_t base, int64_t n, int v[8]) {
+    if (base + 8 <= n) {
+        const int4 a = *reinterpret_cast<const int4*>(in + base);
+        const int4 b = *reinterpret_cast<const int4*>(in + base + 4);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+        for (int u = 0; u < 8; ++u) v[u] = base + u < n ? in[base + u] : 0;
+    }
+}
+
 __global__ __launch_bounds__(1024) void scan_block_sums_kernel(const int* __restrict__ in, int64_t n,
                                                                long long* __restrict__ bsum) {
     __shared__ int sh[16];
     const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanPer + threadIdx.x * 8;
+    int v8[8];
+    load8(in, base, n, v8);
     int v = 0;
-    for (int u = 0; u < 8; ++u)
-        if (base + u < n) v += in[base + u];
+    for (int u = 0; u < 8; ++u) v += v8[u];
     int tot;
     block_excl_scan_1024(v, sh, &tot);
     if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(1024) void scan_bsum_kernel(long long* __restrict__ bsum, int nb) {
-    __shared__ long long carry;
-    __shared__ int sh[16];
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int b0 = 0; b0 < nb; b0 += 1024) {
-        const int b = b0 + threadIdx.x;
-        const int v = b < nb ? static_cast<int>(bsum[b]) : 0;
-        int tot;
-        const int ex = block_excl_scan_1024(v, sh, &tot);
-        if (b < nb) bsum[b] = carry + ex;
-        __syncthreads();
-        if (threadIdx.x == 0) carry += tot;
-        __syncthreads();
-    }
-}
-
+// Exclusive scan of the counts: each workgroup adds the totals of all the
+// workgroups before it (read from bsum, summed in the workgroup) to its own
+// in-workgroup scan.
 __global__ __launch_bounds__(1024) void scan_apply_kernel(const int* __restrict__ in, int64_t n,
                                                           const long long* __restrict__ bsum, int* __restrict__ out) {
     __shared__ int sh[16];
+    __shared__ long long sp[16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    long long pre = 0;
+    for (int b = threadIdx.x; b < static_cast<int>(blockIdx.x); b += 1024) pre += bsum[b];
+    for (int off = 32; off > 0; off >>= 1) pre += __shfl_xor(pre, off, 64);
+    if (lane == 0) sp[wave] = pre;
     const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanPer + threadIdx.x * 8;
     int v[8];
+    load8(in, base, n, v);
     int loc = 0;
-    for (int u = 0; u < 8; ++u) {
-        v[u] = base + u < n ? in[base + u] : 0;
-        loc += v[u];
-    }
+    for (int u = 0; u < 8; ++u) loc += v[u];
     int tot;
-    int run = static_cast<int>(bsum[blockIdx.x]) + block_excl_scan_1024(loc, sh, &tot);
+    const int ex = block_excl_scan_1024(loc, sh, &tot);   // its barriers also publish sp
+    long long blk = 0;
+    for (int w = 0; w < 16; ++w) blk += sp[w];
+    int run = static_cast<int>(blk) + ex;
+    int o[8];
     for (int u = 0; u < 8; ++u) {
-        if (base + u < n) out[base + u] = run;
+        o[u] = run;
         run += v[u];
+    }
+    if (base + 8 <= n) {
+        *reinterpret_cast<int4*>(out + base) = make_int4(o[0], o[1], o[2], o[3]);
+        *reinterpret_cast<int4*>(out + base + 4) = make_int4(o[4], o[5], o[6], o[7]);
+    } else {
+        for (int u = 0; u < 8; ++u)
+            if (base + u < n) out[base + u] = o[u];
     }
 }
 
 // Deterministic sum of the per-block weight-gradient partials (+= into out):
 // 64 parameters per workgroup, each of the 4 waves sums every 4th partial,
 // then the 4 wave sums are added in a fixed order.
-__global__ __launch_bounds__(256) void reduce_partials_kernel(const float* __restrict__ partial, int nblk,
-                                                              float* __restrict__ out) {
-    __shared__ float sh[4][64];
+// 64 parameters per workgroup, 16 wavefronts each summing every 16th
+// partial row, then a fixed-order sum of the 16 (deterministic).
+__global__ __launch_bounds__(1024) void reduce_partials_kernel(const float* __restrict__ partial, int nblk,
+                                                               float* __restrict__ out) {
+    __shared__ float sh[16][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int p = blockIdx.x * 64 + lane;
     float s = 0.0f;
     if (p < kMlpParams)
-        for (int b = wave; b < nblk; b += 4) s += partial[static_cast<int64_t>(b) * kPStride + p];
+        for (int b = wave; b < nblk; b += 16) s += partial[static_cast<int64_t>(b) * kPStride + p];
     sh[wave][lane] = s;
     __syncthreads();
-    if (wave == 0 && p < kMlpParams) out[p] += (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
+    if (wave == 0 && p < kMlpParams) {
+        float t = 0.0f;
+        for (int w = 0; w < 16; ++w) t += sh[w][lane];
+        out[p] += t;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -799,10 +819,11 @@ int grid_for(int64_t work, int per_block, int max_blocks) {
 }
 
 // Workgroups of the fused grid Adam: a multiple of 8 (one share per XCD),
-// at most 16 per compute unit, no more than the vertices need.
+// 4 per compute unit (its register use allows 4 wavefronts per SIMD; more
+// resident workgroups measured slower), no more than the vertices need.
 int grid_adam_blocks(int64_t nv) {
     const int64_t per_xcd = (nv + 8 * 256 - 1) / (8 * 256);
-    int64_t b = static_cast<int64_t>(dvgo::device_cu_count()) * 16 / 8;
+    int64_t b = static_cast<int64_t>(dvgo::device_cu_count()) * 4 / 8;
     if (b > per_xcd) b = per_xcd;
     if (b < 1) b = 1;
     return static_cast<int>(8 * b);
@@ -952,7 +973,6 @@ int32_t run_scatter(const Common& cm, const dvgo_field* field, bool with_feat, c
     const int nb = static_cast<int>((nc1 + kScanPer - 1) / kScanPer);
     long long* bsum = reinterpret_cast<long long*>(cm.ws + cm.L.scan_tmp);
     DVGO_LAUNCH(K_CELL_SCAN, scan_block_sums_kernel, dim3(nb), dim3(1024), 0, s, ba.cell_count, nc1, bsum);
-    DVGO_LAUNCH(K_CELL_SCAN, scan_bsum_kernel, dim3(1), dim3(1024), 0, s, bsum, nb);
     DVGO_LAUNCH(K_CELL_SCAN, scan_apply_kernel, dim3(nb), dim3(1024), 0, s, ba.cell_count, nc1, bsum,
                 reinterpret_cast<int*>(cm.ws + cm.L.cell_start));
     if (int32_t st = dvgo::launch_status()) return st;
@@ -1017,7 +1037,7 @@ int32_t render_bwd_impl(const dvgo_field* field, const dvgo_mlp* mlp, const floa
     }
     if (int32_t st = run_scatter(cm, field, mlp != nullptr, n_kept, grad_density, grad_feat, opt, s)) return st;
     if (mlp) {
-        DVGO_LAUNCH(K_REDUCE, reduce_partials_kernel, dim3((kMlpParams + 63) / 64), dim3(256), 0, s,
+        DVGO_LAUNCH(K_REDUCE, reduce_partials_kernel, dim3((kMlpParams + 63) / 64), dim3(1024), 0, s,
                            reinterpret_cast<const float*>(cm.ws + cm.L.partial), nblk, grad_mlp);
         if (int32_t st = dvgo::launch_status()) return st;
     }
