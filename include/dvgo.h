@@ -317,7 +317,7 @@ int32_t dvgo_version(void);
  * them and returns the summed elapsed milliseconds and the launch count since
  * the last dvgo_profile_enable.  kernel_id -1 turns timing off.  Ids:
  *   0 ray setup, 1 Morton sort, 2 count kept, 3 scan, 4 fill kept,
- *   5 coarse mask, 6 weight pack, 7 per-ray encoding, 8 gather, 9 MLP forward,
+ *   5 coarse mask, 6 (unused), 7 weight pack + per-ray encoding, 8 gather, 9 MLP forward,
  *   10 compose forward, 11 compose backward, 12 MLP backward, 13 vertex
  *   gather (gradient scatter), 14 partial reduce, 15 photo loss, 16 Adam,
  *   17 proposal forward, 18 proposal backward, 19 proposal reduce, 20 scene

@@ -94,8 +94,11 @@ struct PackArgs {
 };
 
 // Pack W1 (feature columns) and W2 / W2^T into matrix-core operand order.
-__global__ void pack_weights_kernel(PackArgs a) {
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+// Operand packing of the network weights, one value per thread `gid` of
+// kPackThreads (a device function so that it can share a launch).
+constexpr int kPackThreads = kW2PackF32;
+
+__device__ __forceinline__ void pack_weights(const PackArgs& a, int gid) {
     if (gid < kW2PackF32) {
         // float32: index ((mt*16 + q)*64 + lane)*4 + u, step st = 4q + u
         const int u = gid & 3, lane = (gid >> 2) & 63, q = (gid >> 8) & 15, mt = gid >> 12;
@@ -143,9 +146,6 @@ __global__ void pack_weights_kernel(PackArgs a) {
     }
 }
 
-inline void launch_pack(const PackArgs& a, hipStream_t s) {
-    DVGO_LAUNCH(K_PACK, pack_weights_kernel, dim3(kW2PackF32 / 256), dim3(256), 0, s, a);
-}
 
 struct MlpArgs {
     const int* sample_ray;

@@ -133,14 +133,21 @@ __device__ __forceinline__ int64_t live_count(const int64_t* n_kept, int64_t cap
 // prep: per-ray encodings and first-layer per-ray part
 // ---------------------------------------------------------------------------
 // base[r][i] = b1[i] + sum_q W1[i][C+q] * PE(d_r)[q];  pe[r][0..31] (27 used)
-// Two rays per 256-thread workgroup: 24 threads evaluate the rays' 24
-// sines and cosines once into LDS, then thread (ray, i) forms output i.
-__global__ __launch_bounds__(256) void ray_base_kernel(const float* __restrict__ rays_d, int B,
-                                                       const float* __restrict__ w1, const float* __restrict__ b1,
-                                                       float* __restrict__ base, float* __restrict__ pe) {
+// Per-call preparation in one launch: the first kPackThreads/256 workgroups
+// pack the network's operands; each following workgroup takes two rays: 24
+// threads evaluate the rays' 24 sines and cosines once into LDS, then thread
+// (ray, i) forms output i of the first layer's view part.
+__global__ __launch_bounds__(256) void prep_kernel(PackArgs pk, int pack, const float* __restrict__ rays_d, int B,
+                                                   const float* __restrict__ w1, const float* __restrict__ b1,
+                                                   float* __restrict__ base, float* __restrict__ pe) {
+    constexpr int kPackBlocks = kPackThreads / 256;
+    if (pack && static_cast<int>(blockIdx.x) < kPackBlocks) {
+        pack_weights(pk, blockIdx.x * 256 + threadIdx.x);
+        return;
+    }
     __shared__ float se[2][32];
     const int t = threadIdx.x;
-    const int r0 = 2 * blockIdx.x;
+    const int r0 = 2 * (static_cast<int>(blockIdx.x) - (pack ? kPackBlocks : 0));
     if (t < 24) {
         const int rr = t / 12, q = t % 12, fq = q / 3, c = q % 3;
         const int r = r0 + rr;
@@ -847,13 +854,9 @@ int32_t run_prep(const Common& cm, const dvgo_mlp* mlp, hipStream_t s) {
         pk.w3tpb = reinterpret_cast<uint16_t*>(cm.ws + cm.L.w3tpb);
         pk.w1tpb = reinterpret_cast<uint16_t*>(cm.ws + cm.L.w1tpb);
         pk.bf16 = mlp->precision == DVGO_BF16;
-        launch_pack(pk, s);
-        if (int32_t st = dvgo::launch_status()) return st;
-    }
-    if (cm.B > 0 && mlp) {
-        const int64_t work = static_cast<int64_t>(cm.B) * kH;
-        DVGO_LAUNCH(K_RAY_BASE, ray_base_kernel, dim3(static_cast<unsigned>((work + 255) / 256)), dim3(256), 0, s,
-                           cm.sa.rays_d, cm.B, mlp->w1, mlp->b1, base, pe);
+        const unsigned blocks = static_cast<unsigned>(kPackThreads / 256 + (cm.B + 1) / 2);
+        DVGO_LAUNCH(K_RAY_BASE, prep_kernel, dim3(blocks), dim3(256), 0, s, pk, 1, cm.sa.rays_d, cm.B, mlp->w1,
+                    mlp->b1, base, pe);
         if (int32_t st = dvgo::launch_status()) return st;
     }
     return DVGO_OK;

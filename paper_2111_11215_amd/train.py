@@ -122,16 +122,22 @@ class FineModel:
 class ProposalModel:
     """Learned segment proposal (not in the paper): network weights with
     their Adam state and the selection thresholds.  Each training step it
-    predicts a segment mask for every ray of the batch, and learns from a
-    density-only pass of the fine model on a sub-batch (KL to the segment
-    weight sums and the final transmittance)."""
+    predicts a segment mask for every ray of the batch; every learn_every-th
+    step it learns from a density-only pass of the fine model on the first
+    1/sub_fraction of the batch (KL to the segment weight sums and the final
+    transmittance).  The defaults (every 4th step, half a batch, lr 3e-3)
+    see the same rays per step as learning every step on 1/8 with lr 1e-3,
+    with the same selectivity at 1000 iterations, in a quarter of the
+    launches."""
 
-    def __init__(self, flat: torch.Tensor, box_min, box_max, lr: float = 1e-3, cum_frac: float = 0.99,
-                 min_mass: float = 0.9, sub_fraction: int = 8):
+    def __init__(self, flat: torch.Tensor, box_min, box_max, lr: float = 3e-3, cum_frac: float = 0.99,
+                 min_mass: float = 0.9, sub_fraction: int = 2, learn_every: int = 4):
         self.st = AdamState.of(flat)
         self.box_min, self.box_max = tuple(box_min), tuple(box_max)
         self.lr, self.cum_frac, self.min_mass, self.sub = lr, cum_frac, min_mass, sub_fraction
-        self.t = 0
+        self.learn_every = learn_every
+        self.t = 0        # proposal updates taken
+        self.calls = 0    # training iterations seen
 
     @property
     def flat(self) -> torch.Tensor:
@@ -155,13 +161,14 @@ def proposal_train_step(model: FineModel, prop: ProposalModel, rays_o, rays_d, t
                         learn: bool = True) -> dict:
     """One iteration of the proposal form: clip (no list), predict
     segment masks, sample only the selected segments (all of them where the
-    proposal falls back), render / adjoint / Adam, then update the proposal
-    on the first 1/sub of the batch."""
+    proposal falls back), render / adjoint / Adam, then (every learn_every-th
+    iteration) update the proposal on the first 1/sub of the batch."""
     s0 = api.sample_rays(rays_o, rays_d, jitter, model.grid.box_min, model.grid.box_max, model.cfg.step,
                          model.cfg.max_samples, clip_only=True)
     _, mass, mask = prop.masks(s0)
     res = model.train_step(rays_o, rays_d, target, jitter, seg_mask=mask)
-    if learn:
+    prop.calls += 1
+    if learn and (prop.calls - 1) % prop.learn_every == 0:
         k = max(rays_o.shape[0] // prop.sub, 1)
         res["prop_loss"] = prop.learn(model, rays_o[:k], rays_d[:k], jitter[:k] if jitter is not None else None)
     res["mask"] = mask

@@ -5,8 +5,9 @@ them, targets from the scene generator):
 * an all-ones segment mask leaves the sample list bit-identical to plain
   sampling (the proposal's fallback is the plain method);
 * the fine stage trains: the photometric loss falls at least tenfold in
-  500 iterations (BF16 form);
-* the learned proposal, trained online over those 500 iterations, makes the
+  1000 iterations (BF16 form);
+* the learned proposal, trained online over those 1000 iterations (250
+  updates on half batches), makes the
   fine pass evaluate fewer samples than an untrained proposal and than no
   proposal, and the render with its masks stays within 35 dB PSNR of the
   plain-sampled render of the same model (what the trained network gains
@@ -21,7 +22,7 @@ import pytest
 import synth
 
 pytestmark = pytest.mark.gpu
-ITERS = 500
+ITERS = 1000
 
 
 @pytest.fixture(scope="module")
