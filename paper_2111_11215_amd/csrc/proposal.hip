@@ -182,45 +182,63 @@ __device__ void prop_forward(const PropArgs& a, int r, bool ray_ok, int lane, Pr
     for (int st = 0; st < 4; ++st) f.z = mma(frag_w3(a.w[2], st, m, h), hb[st], f.z);
 }
 
-// Segment mask from float32 logits; float64 arithmetic, sums in index
-// order (transmitted entry last), ties to the lower index.  Registers only.
-__device__ uint32_t select_mask(const float z[kS], double cum_frac, double min_mass, float* pred_mass) {
-    double m = 0.0;
+// Segment mask of one ray from its float32 logits, computed by the ray's two
+// lanes (m, h = 0/1): each holds 16 logits, z[rr] of segment acc_row(rr, h).
+// float64 arithmetic; the softmax sums run in index order (transmitted entry
+// last) over both halves, so both lanes hold the identical sums; the
+// selection takes the largest unchosen q each round (ties to the lower
+// index), comparing the two halves' candidates.  Registers only.
+__device__ __forceinline__ int seg_rr(int s) { return 4 * (s >> 3) + (s & 3); }   // inverse of acc_row
+__device__ __forceinline__ int seg_h(int s) { return (s >> 2) & 1; }
+
+__device__ uint32_t select_mask_pair(const float z[16], int h, double cum_frac, double min_mass, float* pred_mass) {
+    double mx = 0.0;
     #pragma unroll
-    for (int s = 0; s < kS; ++s) m = fmax(m, static_cast<double>(z[s]));
-    double q[kS];
+    for (int rr = 0; rr < 16; ++rr) mx = fmax(mx, static_cast<double>(z[rr]));
+    mx = fmax(mx, __shfl_xor(mx, 32, 64));
+    double e[16], pe[16];
+    #pragma unroll
+    for (int rr = 0; rr < 16; ++rr) e[rr] = exp(static_cast<double>(z[rr]) - mx);
+    #pragma unroll
+    for (int rr = 0; rr < 16; ++rr) pe[rr] = __shfl_xor(e[rr], 32, 64);
     double tot = 0.0;
     #pragma unroll
-    for (int s = 0; s < kS; ++s) {
-        q[s] = exp(static_cast<double>(z[s]) - m);
-        tot += q[s];
-    }
-    tot += exp(0.0 - m);
+    for (int s = 0; s < kS; ++s) tot += seg_h(s) == h ? e[seg_rr(s)] : pe[seg_rr(s)];
+    tot += exp(0.0 - mx);
+    double q[16], pq[16];
+    #pragma unroll
+    for (int rr = 0; rr < 16; ++rr) q[rr] = e[rr] / tot;
+    #pragma unroll
+    for (int rr = 0; rr < 16; ++rr) pq[rr] = __shfl_xor(q[rr], 32, 64);
     double mass = 0.0;
     #pragma unroll
-    for (int s = 0; s < kS; ++s) {
-        q[s] = q[s] / tot;
-        mass += q[s];
-    }
+    for (int s = 0; s < kS; ++s) mass += seg_h(s) == h ? q[seg_rr(s)] : pq[seg_rr(s)];
     *pred_mass = static_cast<float>(mass);
     if (!(mass >= min_mass)) return 0xFFFFFFFFu;
-    uint32_t chosen = 0;
-    double acc = 0.0;
     const double target = cum_frac * mass;
+    uint32_t own = 0, mask = 0;   // own: chosen bits over rr
+    double acc = 0.0;
     for (int it = 0; it < kS; ++it) {
-        int best = 0;
         double bq = -1.0;
+        int bs = 64, brr = -1;
         #pragma unroll
-        for (int s = 0; s < kS; ++s)
-            if (!((chosen >> s) & 1u) && q[s] > bq) {
-                bq = q[s];
-                best = s;
+        for (int rr = 0; rr < 16; ++rr)
+            if (!((own >> rr) & 1u) && q[rr] > bq) {
+                bq = q[rr];
+                bs = acc_row(rr, h);
+                brr = rr;
             }
-        chosen |= 1u << best;
-        acc += bq;
+        const double oq = __shfl_xor(bq, 32, 64);
+        const int os = __shfl_xor(bs, 32, 64);
+        const bool theirs = oq > bq || (oq == bq && os < bs);
+        const double wq = theirs ? oq : bq;
+        const int ws = theirs ? os : bs;
+        if (!theirs && brr >= 0) own |= 1u << brr;
+        if (ws < kS) mask |= 1u << ws;
+        acc += wq;
         if (acc >= target) break;
     }
-    return chosen;
+    return mask;
 }
 
 constexpr int kRaysPerWave = 32;
@@ -229,31 +247,26 @@ constexpr int kWaves = 1;   // one wavefront (32 rays) per workgroup
 __global__ __launch_bounds__(64) void proposal_fwd_kernel(PropArgs a, int run_net, double cum_frac, double min_mass,
                                                           float* __restrict__ logits, float* __restrict__ pred_mass,
                                                           uint32_t* __restrict__ seg_mask) {
-    __shared__ float sZ[kWaves][kRaysPerWave][kS + 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m = lane & 31, h = lane >> 5;
     const int r = (blockIdx.x * kWaves + wave) * kRaysPerWave + m;
     const bool ray_ok = r < a.B;
+    float z[16];
     if (run_net) {
         PropFwd f;
         prop_forward(a, r, ray_ok, lane, f);
         #pragma unroll
         for (int rr = 0; rr < 16; ++rr) {
-            const int sg = acc_row(rr, h);
-            sZ[wave][m][sg] = f.z[rr];
-            if (ray_ok) logits[static_cast<int64_t>(r) * kS + sg] = f.z[rr];
+            z[rr] = f.z[rr];
+            if (ray_ok) logits[static_cast<int64_t>(r) * kS + acc_row(rr, h)] = f.z[rr];
         }
-    } else if (ray_ok) {
+    } else {
         #pragma unroll
-        for (int q = 0; q < 16; ++q) sZ[wave][m][16 * h + q] = logits[static_cast<int64_t>(r) * kS + 16 * h + q];
+        for (int rr = 0; rr < 16; ++rr) z[rr] = ray_ok ? logits[static_cast<int64_t>(r) * kS + acc_row(rr, h)] : 0.0f;
     }
-    __syncthreads();
-    if (h == 0 && ray_ok) {
-        float z[kS];
-        #pragma unroll
-        for (int s = 0; s < kS; ++s) z[s] = sZ[wave][m][s];
-        float pm;
-        uint32_t mask = select_mask(z, cum_frac, min_mass, &pm);
+    float pm;
+    uint32_t mask = select_mask_pair(z, h, cum_frac, min_mass, &pm);
+    if (ray_ok && h == 0) {
         if (a.valid && !a.valid[r]) mask = 0xFFFFFFFFu;
         if (pred_mass) pred_mass[r] = pm;
         if (seg_mask) seg_mask[r] = mask;
@@ -385,18 +398,29 @@ __global__ __launch_bounds__(64) void proposal_bwd_kernel(PropArgs a, const floa
     if (lane == 0) loss_part[wglob] = kl;
 }
 
-__global__ void proposal_reduce_kernel(const float* __restrict__ partial, const float* __restrict__ loss_part,
-                                       int nwaves, float* __restrict__ grad, float* __restrict__ loss) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < kParams) {
-        float s = 0.0f;
-        for (int b = 0; b < nwaves; ++b) s += partial[static_cast<int64_t>(b) * kPStride + p];
-        grad[p] += s;
+// 64 parameters per workgroup, 16 wavefronts each summing every 16th
+// partial row, then a fixed-order sum of the 16 (deterministic); the
+// first workgroup also sums the loss partials.
+__global__ __launch_bounds__(1024) void proposal_reduce_kernel(const float* __restrict__ partial,
+                                                               const float* __restrict__ loss_part, int nwaves,
+                                                               float* __restrict__ grad, float* __restrict__ loss) {
+    __shared__ float sh[16][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int p = blockIdx.x * 64 + lane;
+    float s = 0.0f;
+    if (p < kParams)
+        for (int b = wave; b < nwaves; b += 16) s += partial[static_cast<int64_t>(b) * kPStride + p];
+    sh[wave][lane] = s;
+    __syncthreads();
+    if (wave == 0 && p < kParams) {
+        float t = 0.0f;
+        for (int w = 0; w < 16; ++w) t += sh[w][lane];
+        grad[p] += t;
     }
-    if (p == 0 && loss) {
-        float s = 0.0f;
-        for (int b = 0; b < nwaves; ++b) s += loss_part[b];
-        *loss = s;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && loss) {
+        float l = 0.0f;
+        for (int b = 0; b < nwaves; ++b) l += loss_part[b];
+        *loss = l;
     }
 }
 
@@ -473,7 +497,7 @@ int32_t dvgo_proposal_bwd(const float* rays_o, const float* rays_d, const float*
     DVGO_LAUNCH(K_PROP_BWD, proposal_bwd_kernel, dim3(nblk), dim3(64 * kWaves), 0, s, a, seg_w, log_t_end, partial,
                 loss_part);
     if (int32_t st = dvgo::launch_status()) return st;
-    DVGO_LAUNCH(K_PROP_REDUCE, proposal_reduce_kernel, dim3((kParams + 255) / 256), dim3(256), 0, s, partial, loss_part,
+    DVGO_LAUNCH(K_PROP_REDUCE, proposal_reduce_kernel, dim3((kParams + 63) / 64), dim3(1024), 0, s, partial, loss_part,
                 nw, grad_prop, loss);
     return dvgo::launch_status();
 }
