@@ -321,7 +321,8 @@ int32_t dvgo_version(void);
  *   10 compose forward, 11 compose backward, 12 MLP backward, 13 vertex
  *   gather (gradient scatter), 14 partial reduce, 15 photo loss, 16 Adam,
  *   17 proposal forward, 18 proposal backward, 19 proposal reduce, 20 scene
- *   render, 21 cell binning count, 22 cell scan, 23 cell binning place,
+ *   render, 21 (unused: cell binning counts run inside 11), 22 cell scan,
+ *   23 record placement when there is no network,
  *   24 vertex gather with the grids' Adam step (dvgo_render_bwd_adam). */
 int32_t dvgo_profile_enable(int32_t kernel_id);
 int32_t dvgo_profile_read(double* total_ms, int64_t* launches);

@@ -166,11 +166,21 @@ struct MlpArgs {
     const uint16_t* w3pb;
     const uint16_t* w3tpb;
     const uint16_t* w1tpb;
-    float* feat;          // [cap][12]: features in; dL/dfeat out (backward)
+    float* feat;          // [cap][12]: gathered features in
     float* col;           // [cap][4]: colour out (forward) / dL/dc in (backward)
     float* partial;       // [blocks][kPStride] weight-gradient partials
     int bf16;
+    // backward: each sample's record (head, dL/dfeat) goes to its binned slot
+    const int2* cell_rank;    // [cap] (cell, rank within cell)
+    const int* cell_start;    // [ncell + 1]
+    const float4* rec_head;   // [cap] (fx, fy, fz, dL/draw)
+    float4* rec;              // [cap][4] binned records
 };
+
+__device__ __forceinline__ float4* binned_record(const MlpArgs& a, int64_t s) {
+    const int2 cr = a.cell_rank[s];
+    return a.rec + (static_cast<int64_t>(a.cell_start[cr.x]) + cr.y) * 4;
+}
 
 __device__ __forceinline__ MlpArgs refresh(const MlpArgs& a) {
     MlpArgs l = a;
@@ -468,10 +478,11 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_f32_kernel(MlpArgs a0) {
             }
         }
         if (ok && h == 0) {
-            float4* out = reinterpret_cast<float4*>(a.feat + s * 12);
-            out[0] = make_float4(df[0], df[1], df[2], df[3]);
-            out[1] = make_float4(df[4], df[5], df[6], df[7]);
-            out[2] = make_float4(df[8], df[9], df[10], df[11]);
+            float4* rec = binned_record(a, s);
+            rec[0] = a.rec_head[s];
+            rec[1] = make_float4(df[0], df[1], df[2], df[3]);
+            rec[2] = make_float4(df[4], df[5], df[6], df[7]);
+            rec[3] = make_float4(df[8], df[9], df[10], df[11]);
         }
         __syncthreads();
         // dW1[i in tile `wave`][col] (col 39 = bias) over the 128 staged samples
@@ -793,12 +804,13 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_bf16_kernel(MlpArgs a0) {
             }
         }
         if (ok) {
-            float4* out = reinterpret_cast<float4*>(a.feat + s * 12);
+            float4* rec = binned_record(a, s);
             if (h == 0) {
-                out[0] = make_float4(dft[0], dft[1], dft[2], dft[3]);
-                out[2] = make_float4(dft[4], dft[5], dft[6], dft[7]);
+                rec[0] = a.rec_head[s];
+                rec[1] = make_float4(dft[0], dft[1], dft[2], dft[3]);
+                rec[3] = make_float4(dft[4], dft[5], dft[6], dft[7]);
             } else {
-                out[1] = make_float4(dft[0], dft[1], dft[2], dft[3]);
+                rec[2] = make_float4(dft[0], dft[1], dft[2], dft[3]);
             }
         }
         __syncthreads();

@@ -28,8 +28,7 @@ constexpr int kMaxBwdBlocks = 256;
 
 struct WsLayout {
     size_t base, pe, w1p, w2p, w2tp, w1pb, w2pb, w2tpb, w3pb, w3tpb, w1tpb, raw, feat, col, partial, cell_count,
-        cell_start, scan_tmp,
-        cell_rank, rec, total;
+        cell_start, scan_tmp, cell_rank, rec_head, rec, total;
 };
 
 constexpr int kScanPer = 8192;   // elements per block of the device-wide scan
@@ -61,6 +60,7 @@ WsLayout ws_layout(int64_t B, int64_t cap, int64_t ncell) {
     L.cell_start = take(static_cast<size_t>(ncell + 1) * 4);
     L.scan_tmp = take(static_cast<size_t>((ncell + 1 + kScanPer - 1) / kScanPer + 1) * 8);
     L.cell_rank = take(static_cast<size_t>(cap) * 8);
+    L.rec_head = take(static_cast<size_t>(cap) * 16);
     L.rec = take(static_cast<size_t>(cap) * 64);
     L.total = off;
     return L;
@@ -139,10 +139,18 @@ __device__ __forceinline__ int64_t live_count(const int64_t* n_kept, int64_t cap
 // (ray, i) forms output i of the first layer's view part.
 __global__ __launch_bounds__(256) void prep_kernel(PackArgs pk, int pack, const float* __restrict__ rays_d, int B,
                                                    const float* __restrict__ w1, const float* __restrict__ b1,
-                                                   float* __restrict__ base, float* __restrict__ pe) {
+                                                   float* __restrict__ base, float* __restrict__ pe,
+                                                   int* __restrict__ zero, int64_t nzero, int zblocks) {
     constexpr int kPackBlocks = kPackThreads / 256;
     if (pack && static_cast<int>(blockIdx.x) < kPackBlocks) {
         pack_weights(pk, blockIdx.x * 256 + threadIdx.x);
+        return;
+    }
+    const int ray_blocks = (B + 1) / 2;
+    const int zb = static_cast<int>(blockIdx.x) - (pack ? kPackBlocks : 0) - ray_blocks;
+    if (zb >= 0) {   // the last zblocks workgroups clear `zero` (the backward's cell counts)
+        for (int64_t i = static_cast<int64_t>(zb) * 256 + threadIdx.x; i < nzero; i += static_cast<int64_t>(zblocks) * 256)
+            zero[i] = 0;
         return;
     }
     __shared__ float se[2][32];
@@ -266,6 +274,11 @@ struct ComposeArgs {
     const float* grad_rgb;
     const float* grad_depth;
     const float* grad_acc;
+    // backward binning by fine cell (cell_count == nullptr: off)
+    GridArgs g;
+    int* cell_count;       // [ncell + 1], zero on entry
+    int2* cell_rank;       // [cap] (cell, rank within cell)
+    float4* rec_head;      // [cap] (fx, fy, fz, dL/draw)
 };
 
 __device__ __forceinline__ float wave_incl_scan(float v, int lane) {
@@ -286,6 +299,39 @@ __device__ __forceinline__ float wave_incl_suffix(float v, int lane) {
 __device__ __forceinline__ float wave_sum(float v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
+}
+
+// Fine cell of a point (its vertex (0,0,0)) and the fractional position f
+// inside it, clamped like the trilinear interpolation.
+__device__ __forceinline__ int cell_of(const GridArgs& g, const float x[3], float f[3]) {
+    int i0[3];
+    for (int i = 0; i < 3; ++i) {
+        const float u = (x[i] - g.mn[i]) * g.scale[i];
+        const float fl = fminf(fmaxf(floorf(u), 0.0f), static_cast<float>(g.n[i] - 2));
+        i0[i] = static_cast<int>(fl);
+        f[i] = fminf(fmaxf(u - fl, 0.0f), 1.0f);
+    }
+    return (i0[0] * (g.n[1] - 1) + i0[1]) * (g.n[2] - 1) + i0[2];
+}
+
+// Rank of this lane's sample among the samples of its cell.  Lanes hold
+// consecutive samples, so equal cells form runs; each run's first lane adds
+// the run length to the cell's count with one atomic, and the run shares the
+// returned base.  All 64 lanes must call it; lanes with ok == false take part
+// in the vote only.
+__device__ __forceinline__ int run_rank(int cell, bool ok, int lane, int* __restrict__ counts) {
+    const int prev = __shfl_up(cell, 1, 64);
+    const bool head = !ok || lane == 0 || prev != cell;
+    const uint64_t heads = __ballot(head);
+    const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1);
+    const uint64_t le = heads & upto;
+    const int leader = 63 - __clzll(static_cast<long long>(le));
+    const uint64_t gt = heads & ~upto;
+    const int next = gt ? __ffsll(static_cast<long long>(gt)) - 1 : 64;
+    int rbase = 0;
+    if (ok && lane == leader) rbase = atomicAdd(counts + cell, next - lane);
+    rbase = __shfl(rbase, leader, 64);
+    return rbase + lane - leader;
 }
 
 __global__ __launch_bounds__(256) void compose_fwd_kernel(ComposeArgs a) {
@@ -405,12 +451,23 @@ __global__ __launch_bounds__(256) void compose_bwd_kernel(ComposeArgs a) {
             dsig += g[ch] * (Tafter * v[ch] - (S[ch] + sfx_ex));
             tot[ch] = __shfl(sfx, 0, 64);
         }
+        const float draw = step * dsig * sigmoid_f(raw + a.act_shift);
         if (ok) {
-            const float draw = step * dsig * sigmoid_f(raw + a.act_shift);
             a.raw[s] = draw;
             if (a.with_color) {
                 reinterpret_cast<float4*>(a.col)[s] = make_float4(w * g[0], w * g[1], w * g[2], 0.0f);
             }
+        }
+        if (a.cell_count) {   // bin the sample by fine cell (wave-uniform branch)
+            int cell = -1;
+            if (ok) {
+                float x[3], f[3];
+                sample_point(a.sa, r, a.sa.sample_k[s], x, nullptr);
+                cell = cell_of(a.g, x, f);
+                a.rec_head[s] = make_float4(f[0], f[1], f[2], draw);
+            }
+            const int rank = run_rank(cell, ok, lane, a.cell_count);
+            if (ok) a.cell_rank[s] = make_int2(cell, rank);
         }
         logTa += __shfl(suf, 0, 64);
         for (int ch = 0; ch < 5; ++ch) S[ch] += tot[ch];
@@ -432,24 +489,14 @@ struct BinArgs {
     int* cell_count;       // [ncell + 1]
     const int* cell_start; // [ncell + 1]
     int2* cell_rank;       // [cap] (cell, rank within cell)
-    const float* draw;     // [cap]
-    const float* dfeat;    // [cap][12] or null
-    float4* rec;           // [cap][4]: (fx, fy, fz, draw), df[0..11]
+    const float4* rec_head;  // [cap] (fx, fy, fz, draw)
+    int with_feat;         // records carry dL/dfeat
+    float4* rec;           // [cap][4] in binned order: (fx, fy, fz, draw), df[0..11]
     float* grad_density;
     float* grad_feat;
     int64_t ncell;
 };
 
-__device__ __forceinline__ int cell_of(const GridArgs& g, const float x[3], float f[3]) {
-    int i0[3];
-    for (int i = 0; i < 3; ++i) {
-        const float u = (x[i] - g.mn[i]) * g.scale[i];
-        const float fl = fminf(fmaxf(floorf(u), 0.0f), static_cast<float>(g.n[i] - 2));
-        i0[i] = static_cast<int>(fl);
-        f[i] = fminf(fmaxf(u - fl, 0.0f), 1.0f);
-    }
-    return (i0[0] * (g.n[1] - 1) + i0[1]) * (g.n[2] - 1) + i0[2];
-}
 
 __global__ __launch_bounds__(256) void fill_int_kernel(int* __restrict__ p, int64_t n, int v) {
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
@@ -457,55 +504,16 @@ __global__ __launch_bounds__(256) void fill_int_kernel(int* __restrict__ p, int6
         p[i] = v;
 }
 
-// Per sample: its cell and its rank among the cell's samples.  Lanes hold
-// consecutive samples, so equal cells form runs; each run's first lane adds
-// the run length with one atomic and the run shares the returned base.
-__global__ __launch_bounds__(256) void bin_count_kernel(BinArgs a) {
-    const int64_t n = live_count(a.n_kept, a.cap);
-    const int lane = threadIdx.x & 63;
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-    for (int64_t base = static_cast<int64_t>(blockIdx.x) * blockDim.x + (threadIdx.x & ~63); base < n;
-         base += stride) {
-        const int64_t s = base + lane;
-        const bool ok = s < n;
-        int cell = -1;
-        if (ok) {
-            float x[3], f[3];
-            sample_point(a.sa, a.sa.sample_ray[s], a.sa.sample_k[s], x, nullptr);
-            cell = cell_of(a.g, x, f);
-        }
-        const int prev = __shfl_up(cell, 1, 64);
-        const bool head = !ok || lane == 0 || prev != cell;
-        const uint64_t heads = __ballot(head);
-        const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1);
-        const uint64_t le = heads & upto;
-        const int leader = 63 - __clzll(static_cast<long long>(le));
-        const uint64_t gt = heads & ~upto;
-        const int next = gt ? __ffsll(static_cast<long long>(gt)) - 1 : 64;
-        int rbase = 0;
-        if (ok && lane == leader) rbase = atomicAdd(a.cell_count + cell, next - lane);
-        rbase = __shfl(rbase, leader, 64);
-        if (ok) a.cell_rank[s] = make_int2(cell, rbase + lane - leader);
-    }
-}
 
+// Records in binned order when no network backward places them (density
+// only): the head (fractional position, dL/draw) at cell start + rank.
 __global__ __launch_bounds__(256) void bin_place_kernel(BinArgs a) {
     const int64_t n = live_count(a.n_kept, a.cap);
     for (int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; s < n;
          s += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        float x[3], f[3];
-        sample_point(a.sa, a.sa.sample_ray[s], a.sa.sample_k[s], x, nullptr);
-        cell_of(a.g, x, f);
         const int2 cr = a.cell_rank[s];
         const int64_t pos = static_cast<int64_t>(a.cell_start[cr.x]) + cr.y;
-        float4* r = a.rec + pos * 4;
-        r[0] = make_float4(f[0], f[1], f[2], a.draw[s]);
-        if (a.dfeat) {
-            const float4* df = reinterpret_cast<const float4*>(a.dfeat + s * kC);
-            r[1] = df[0];
-            r[2] = df[1];
-            r[3] = df[2];
-        }
+        a.rec[pos * 4] = a.rec_head[s];
     }
 }
 
@@ -546,7 +554,7 @@ __device__ __forceinline__ bool vertex_grad(const BinArgs& a, int i, int j, int 
 __global__ __launch_bounds__(256) void vertex_gather_kernel(BinArgs a) {
     const int ny = a.g.n[1], nz = a.g.n[2];
     const int64_t nv = static_cast<int64_t>(a.g.n[0]) * ny * nz;
-    const bool feat = a.dfeat != nullptr;
+    const bool feat = a.with_feat != 0;
     for (int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; v < nv;
          v += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const int k = static_cast<int>(v % nz);
@@ -836,7 +844,7 @@ int grid_adam_blocks(int64_t nv) {
     return static_cast<int>(8 * b);
 }
 
-int32_t run_prep(const Common& cm, const dvgo_mlp* mlp, hipStream_t s) {
+int32_t run_prep(const Common& cm, const dvgo_mlp* mlp, hipStream_t s, int* zero = nullptr, int64_t nzero = 0) {
     float* base = reinterpret_cast<float*>(cm.ws + cm.L.base);
     float* pe = reinterpret_cast<float*>(cm.ws + cm.L.pe);
     if (mlp) {
@@ -854,9 +862,14 @@ int32_t run_prep(const Common& cm, const dvgo_mlp* mlp, hipStream_t s) {
         pk.w3tpb = reinterpret_cast<uint16_t*>(cm.ws + cm.L.w3tpb);
         pk.w1tpb = reinterpret_cast<uint16_t*>(cm.ws + cm.L.w1tpb);
         pk.bf16 = mlp->precision == DVGO_BF16;
-        const unsigned blocks = static_cast<unsigned>(kPackThreads / 256 + (cm.B + 1) / 2);
+        const int zblocks = zero ? grid_for(nzero, 256, dvgo::device_cu_count() * 4) : 0;
+        const unsigned blocks = static_cast<unsigned>(kPackThreads / 256 + (cm.B + 1) / 2 + zblocks);
         DVGO_LAUNCH(K_RAY_BASE, prep_kernel, dim3(blocks), dim3(256), 0, s, pk, 1, cm.sa.rays_d, cm.B, mlp->w1,
-                    mlp->b1, base, pe);
+                    mlp->b1, base, pe, zero, nzero, zblocks);
+        if (int32_t st = dvgo::launch_status()) return st;
+    } else if (zero) {
+        DVGO_LAUNCH(K_CELL_SCAN, fill_int_kernel, dim3(grid_for(nzero, 256, dvgo::device_cu_count() * 8)), dim3(256),
+                    0, s, zero, nzero, 0);
         if (int32_t st = dvgo::launch_status()) return st;
     }
     return DVGO_OK;
@@ -950,37 +963,62 @@ Common make_common(const dvgo_field* field, const float* rays_o, const float* ra
     return cm;
 }
 
-int32_t run_scatter(const Common& cm, const dvgo_field* field, bool with_feat, const int64_t* n_kept,
-                    float* grad_density, float* grad_feat, const GridAdamArgs* opt, hipStream_t s) {
+// Binning state of a backward call inside the workspace.
+struct Bins {
+    int64_t ncell;
+    int* cell_count;
+    int* cell_start;
+    int2* cell_rank;
+    float4* rec_head;
+    float4* rec;
+};
+
+Bins bins_of(const Common& cm, const dvgo_field* field) {
+    Bins b;
+    b.ncell = cell_count_of(field->box);
+    b.cell_count = reinterpret_cast<int*>(cm.ws + cm.L.cell_count);
+    b.cell_start = reinterpret_cast<int*>(cm.ws + cm.L.cell_start);
+    b.cell_rank = reinterpret_cast<int2*>(cm.ws + cm.L.cell_rank);
+    b.rec_head = reinterpret_cast<float4*>(cm.ws + cm.L.rec_head);
+    b.rec = reinterpret_cast<float4*>(cm.ws + cm.L.rec);
+    return b;
+}
+
+// Exclusive scan of the per-cell counts into cell starts.
+int32_t run_cell_scan(const Common& cm, const Bins& b, hipStream_t s) {
+    const int64_t nc1 = b.ncell + 1;
+    const int nb = static_cast<int>((nc1 + kScanPer - 1) / kScanPer);
+    long long* bsum = reinterpret_cast<long long*>(cm.ws + cm.L.scan_tmp);
+    DVGO_LAUNCH(K_CELL_SCAN, scan_block_sums_kernel, dim3(nb), dim3(1024), 0, s, b.cell_count, nc1, bsum);
+    DVGO_LAUNCH(K_CELL_SCAN, scan_apply_kernel, dim3(nb), dim3(1024), 0, s, b.cell_count, nc1, bsum, b.cell_start);
+    return dvgo::launch_status();
+}
+
+// Records placed in binned order (by the network backward, or here when
+// there is none), then one thread per vertex: gradient into the grids, or
+// the grids' fused Adam step.
+int32_t run_vertex(const Common& cm, const dvgo_field* field, const Bins& b, bool with_feat, bool place,
+                   const int64_t* n_kept, float* grad_density, float* grad_feat, const GridAdamArgs* opt,
+                   hipStream_t s) {
     BinArgs ba;
     ba.sa = cm.sa;
     ba.g = cm.g;
     ba.n_kept = n_kept;
     ba.cap = cm.cap;
-    ba.ncell = cell_count_of(field->box);
-    ba.cell_count = reinterpret_cast<int*>(cm.ws + cm.L.cell_count);
-    ba.cell_start = reinterpret_cast<const int*>(cm.ws + cm.L.cell_start);
-    ba.cell_rank = reinterpret_cast<int2*>(cm.ws + cm.L.cell_rank);
-    ba.draw = reinterpret_cast<const float*>(cm.ws + cm.L.raw);
-    ba.dfeat = with_feat ? reinterpret_cast<const float*>(cm.ws + cm.L.feat) : nullptr;
-    ba.rec = reinterpret_cast<float4*>(cm.ws + cm.L.rec);
+    ba.ncell = b.ncell;
+    ba.cell_count = b.cell_count;
+    ba.cell_start = b.cell_start;
+    ba.cell_rank = b.cell_rank;
+    ba.rec_head = b.rec_head;
+    ba.with_feat = with_feat;
+    ba.rec = b.rec;
     ba.grad_density = grad_density;
     ba.grad_feat = grad_feat;
     const int cus = dvgo::device_cu_count();
-    const int64_t nc1 = ba.ncell + 1;
-    DVGO_LAUNCH(K_CELL_SCAN, fill_int_kernel, dim3(grid_for(nc1, 256, cus * 8)), dim3(256), 0, s, ba.cell_count, nc1,
-                0);
-    if (int32_t st = dvgo::launch_status()) return st;
-    DVGO_LAUNCH(K_BIN_COUNT, bin_count_kernel, dim3(grid_for(cm.cap, 256, cus * 16)), dim3(256), 0, s, ba);
-    if (int32_t st = dvgo::launch_status()) return st;
-    const int nb = static_cast<int>((nc1 + kScanPer - 1) / kScanPer);
-    long long* bsum = reinterpret_cast<long long*>(cm.ws + cm.L.scan_tmp);
-    DVGO_LAUNCH(K_CELL_SCAN, scan_block_sums_kernel, dim3(nb), dim3(1024), 0, s, ba.cell_count, nc1, bsum);
-    DVGO_LAUNCH(K_CELL_SCAN, scan_apply_kernel, dim3(nb), dim3(1024), 0, s, ba.cell_count, nc1, bsum,
-                reinterpret_cast<int*>(cm.ws + cm.L.cell_start));
-    if (int32_t st = dvgo::launch_status()) return st;
-    DVGO_LAUNCH(K_BIN_PLACE, bin_place_kernel, dim3(grid_for(cm.cap, 256, cus * 16)), dim3(256), 0, s, ba);
-    if (int32_t st = dvgo::launch_status()) return st;
+    if (place) {
+        DVGO_LAUNCH(K_BIN_PLACE, bin_place_kernel, dim3(grid_for(cm.cap, 256, cus * 16)), dim3(256), 0, s, ba);
+        if (int32_t st = dvgo::launch_status()) return st;
+    }
     const int64_t nv = static_cast<int64_t>(field->box.n[0]) * field->box.n[1] * field->box.n[2];
     if (opt)
         DVGO_LAUNCH(K_GRID_ADAM, vertex_adam_kernel, dim3(grid_adam_blocks(nv)), dim3(256), 0, s, ba, *opt);
@@ -1016,7 +1054,9 @@ int32_t render_bwd_impl(const dvgo_field* field, const dvgo_mlp* mlp, const floa
     }
     Common cm = make_common(field, rays_o, rays_d, jitter, t_near, sample_ray, sample_k, capacity, B, step,
                             workspace);
-    if (int32_t st = run_prep(cm, mlp, s)) return st;
+    const Bins bins = bins_of(cm, field);
+    // prep (packing, per-ray encoding) also clears the cell counts
+    if (int32_t st = run_prep(cm, mlp, s, bins.cell_count, bins.ncell + 1)) return st;
     if (int32_t st = run_gather(cm, field, mlp != nullptr, n_kept, s)) return st;
     MlpArgs ma;
     if (mlp) {
@@ -1024,21 +1064,33 @@ int32_t render_bwd_impl(const dvgo_field* field, const dvgo_mlp* mlp, const floa
         launch_mlp_fwd(ma, dvgo::device_cu_count(), s);
         if (int32_t st = dvgo::launch_status()) return st;
     }
+    // adjoint of the compositing; bins every sample by fine cell on the way
     ComposeArgs ca = make_compose(cm, perm, ray_offset, n_uniform, n_kept, field->act_shift, bg, mlp != nullptr);
     ca.log_t_end_in = log_t_end;
     ca.grad_rgb = grad_rgb;
     ca.grad_depth = grad_depth;
     ca.grad_acc = grad_acc;
+    ca.g = cm.g;
+    ca.cell_count = bins.cell_count;
+    ca.cell_rank = bins.cell_rank;
+    ca.rec_head = bins.rec_head;
     DVGO_LAUNCH(K_COMPOSE_BWD, compose_bwd_kernel, dim3((B + 3) / 4), dim3(256), 0, s, ca);
     if (int32_t st = dvgo::launch_status()) return st;
+    if (int32_t st = run_cell_scan(cm, bins, s)) return st;
     int nblk = 0;
-    if (mlp) {
+    if (mlp) {   // the network adjoint writes each sample's record at its binned position
+        ma.cell_rank = bins.cell_rank;
+        ma.cell_start = bins.cell_start;
+        ma.rec_head = bins.rec_head;
+        ma.rec = bins.rec;
         nblk = dvgo::device_cu_count();
         if (nblk > kMaxBwdBlocks) nblk = kMaxBwdBlocks;
         launch_mlp_bwd(ma, nblk, s);
         if (int32_t st = dvgo::launch_status()) return st;
     }
-    if (int32_t st = run_scatter(cm, field, mlp != nullptr, n_kept, grad_density, grad_feat, opt, s)) return st;
+    if (int32_t st = run_vertex(cm, field, bins, mlp != nullptr, mlp == nullptr, n_kept, grad_density, grad_feat, opt,
+                                s))
+        return st;
     if (mlp) {
         DVGO_LAUNCH(K_REDUCE, reduce_partials_kernel, dim3((kMlpParams + 63) / 64), dim3(1024), 0, s,
                            reinterpret_cast<const float*>(cm.ws + cm.L.partial), nblk, grad_mlp);
