@@ -253,6 +253,27 @@ int32_t dvgo_render_bwd_adam(const dvgo_field* field /*host*/, const dvgo_mlp* m
                              const dvgo_grid_adam* opt /*host*/, float* grad_mlp,
                              void* workspace, size_t workspace_bytes, void* stream);
 
+/* One whole training step of the fine stage in one call: dvgo_render_fwd
+ * (colour and log T_end only), dvgo_photo_loss against target [B][3]
+ * (Eq. photo_loss), and dvgo_render_bwd_adam, with the same result.  Inside
+ * the call the adjoint reuses what the forward left in the workspace (the
+ * packed network, the per-ray encodings, every sample's gathered density
+ * and features and its colour) instead of evaluating them again; the
+ * transmittance is still recomputed from each ray's end.  rgb [B][3] (or
+ * NULL) receives the rendered colour, loss (device float or NULL) the loss;
+ * the grids take their Adam step through opt and the network gradient is
+ * accumulated into grad_mlp (its Adam step is the caller's dvgo_adam_step).
+ * Same arguments, workspace and errors as the separate calls. */
+int32_t dvgo_train_step(const dvgo_field* field /*host*/, const dvgo_mlp* mlp /*host*/,
+                        const float* rays_o, const float* rays_d, const float* jitter,
+                        const float* t_near, const int32_t* n_uniform, const int32_t* perm,
+                        const int32_t* ray_offset, const int32_t* sample_ray,
+                        const int32_t* sample_k, const int64_t* n_kept, int64_t capacity,
+                        int32_t B, float step, const float* bg /*host[3]*/,
+                        const float* target, float* rgb, float* loss,
+                        const dvgo_grid_adam* opt /*host*/, float* grad_mlp,
+                        void* workspace, size_t workspace_bytes, void* stream);
+
 /* Photometric loss of paper Eq. photo_loss: loss = (1/B) sum_r
  * ||rgb_r - target_r||^2 and grad_rgb = 2 (rgb - target)/B.  grad_rgb [B][3]
  * is overwritten; loss (device float, or NULL) is overwritten. */

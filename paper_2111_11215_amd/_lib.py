@@ -66,6 +66,8 @@ SIGNATURES = {
                                   c_float, POINTER(c_float), P, P, P, P, P, P, P, P, c_size_t, P]),
     "dvgo_render_bwd_adam": (c_int32, [POINTER(Field), POINTER(Mlp), P, P, P, P, P, P, P, P, P, P, c_int64, c_int32,
                                        c_float, POINTER(c_float), P, P, P, P, POINTER(GridAdam), P, P, c_size_t, P]),
+    "dvgo_train_step": (c_int32, [POINTER(Field), POINTER(Mlp), P, P, P, P, P, P, P, P, P, P, c_int64, c_int32,
+                                  c_float, POINTER(c_float), P, P, P, POINTER(GridAdam), P, P, c_size_t, P]),
     "dvgo_photo_loss": (c_int32, [P, P, c_int32, P, P, P]),
     "dvgo_adam_step": (c_int32, [P, P, P, P, P, c_int64, c_float, c_float, c_float, c_float, c_int32, P]),
     "dvgo_proposal_fwd": (c_int32, [P, P, P, P, c_int32, POINTER(Box), POINTER(Prop), c_double, c_double, P, P, P,

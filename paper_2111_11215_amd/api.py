@@ -297,6 +297,32 @@ def render_bwd_adam(grid: Grid, mlp_flat: torch.Tensor, s: Samples, log_t_end: t
         ctypes.byref(opt), _ptr(grad_mlp), _ptr(ws), nws, _stream(dev)))
 
 
+def train_step(grid: Grid, mlp_flat: torch.Tensor, s: Samples, target: torch.Tensor, density_m: torch.Tensor,
+               density_v: torch.Tensor, feat_m: torch.Tensor, feat_v: torch.Tensor, grad_mlp: torch.Tensor,
+               lr: float, t: int, betas=(0.9, 0.999), eps=1e-8, bg=(1.0, 1.0, 1.0), precision: int = DVGO_F32,
+               use_shadow: bool = False, want_rgb: bool = True):
+    """Forward, photometric loss, adjoint and the grids' Adam step in one
+    library call; accumulates (+=) the network gradient into grad_mlp.
+    Returns (loss [1], rgb [B,3] or None)."""
+    lib = load()
+    dev = s.rays_o.device
+    field = grid.field(use_shadow)
+    mlp = mlp_struct(mlp_flat, precision)
+    opt = GridAdam(_ptr(grid.density), _ptr(density_m), _ptr(density_v), _ptr(grid.feat), _ptr(feat_m),
+                   _ptr(feat_v), _ptr(grid.feat_shadow), float(lr), float(betas[0]), float(betas[1]), float(eps),
+                   int(t))
+    rgb = torch.empty((s.B, 3), dtype=torch.float32, device=dev) if want_rgb else None
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    nws = lib.dvgo_render_workspace_bytes(s.B, s.capacity, CHANNELS, ctypes.byref(field.box))
+    ws = workspace(nws, dev)
+    check("dvgo_train_step", lib.dvgo_train_step(
+        ctypes.byref(field), ctypes.byref(mlp), _ptr(s.rays_o), _ptr(s.rays_d), _ptr(s.jitter), _ptr(s.t_near),
+        _ptr(s.n_uniform), _ptr(s.perm), _ptr(s.ray_offset), _ptr(s.sample_ray), _ptr(s.sample_k), _ptr(s.n_kept),
+        s.capacity, s.B, s.step, _bg(bg), _ptr(target), _ptr(rgb), _ptr(loss), ctypes.byref(opt), _ptr(grad_mlp),
+        _ptr(ws), nws, _stream(dev)))
+    return loss, rgb
+
+
 def photo_loss(rgb: torch.Tensor, target: torch.Tensor):
     lib = load()
     grad = torch.empty_like(rgb)

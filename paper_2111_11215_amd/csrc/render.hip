@@ -28,7 +28,7 @@ constexpr int kMaxBwdBlocks = 256;
 
 struct WsLayout {
     size_t base, pe, w1p, w2p, w2tp, w1pb, w2pb, w2tpb, w3pb, w3tpb, w1tpb, raw, feat, col, partial, cell_count,
-        cell_start, scan_tmp, cell_rank, rec_head, rec, total;
+        cell_start, scan_tmp, cell_rank, rec_head, rec, step_rgb, step_grad, step_logt, total;
 };
 
 constexpr int kScanPer = 8192;   // elements per block of the device-wide scan
@@ -62,6 +62,9 @@ WsLayout ws_layout(int64_t B, int64_t cap, int64_t ncell) {
     L.cell_rank = take(static_cast<size_t>(cap) * 8);
     L.rec_head = take(static_cast<size_t>(cap) * 16);
     L.rec = take(static_cast<size_t>(cap) * 64);
+    L.step_rgb = take(static_cast<size_t>(B) * 3 * 4);    // per-ray state of dvgo_train_step
+    L.step_grad = take(static_cast<size_t>(B) * 3 * 4);
+    L.step_logt = take(static_cast<size_t>(B) * 4);
     L.total = off;
     return L;
 }
@@ -1033,7 +1036,8 @@ int32_t render_bwd_impl(const dvgo_field* field, const dvgo_mlp* mlp, const floa
                         const int64_t* n_kept, int64_t capacity, int32_t B, float step, const float* bg,
                         const float* log_t_end, const float* grad_rgb, const float* grad_depth,
                         const float* grad_acc, float* grad_density, float* grad_feat, const GridAdamArgs* opt,
-                        float* grad_mlp, void* workspace, size_t workspace_bytes, void* stream) {
+                        float* grad_mlp, void* workspace, size_t workspace_bytes, void* stream,
+                        bool forward_done = false) {
     if (int32_t st = validate(field, mlp, rays_o, rays_d, t_near, n_uniform, perm, ray_offset, sample_ray, sample_k,
                               n_kept, capacity, B, step, bg, workspace, workspace_bytes))
         return st;
@@ -1055,14 +1059,16 @@ int32_t render_bwd_impl(const dvgo_field* field, const dvgo_mlp* mlp, const floa
     Common cm = make_common(field, rays_o, rays_d, jitter, t_near, sample_ray, sample_k, capacity, B, step,
                             workspace);
     const Bins bins = bins_of(cm, field);
-    // prep (packing, per-ray encoding) also clears the cell counts
-    if (int32_t st = run_prep(cm, mlp, s, bins.cell_count, bins.ncell + 1)) return st;
-    if (int32_t st = run_gather(cm, field, mlp != nullptr, n_kept, s)) return st;
     MlpArgs ma;
-    if (mlp) {
-        ma = make_mlp_args(cm, mlp, n_kept);
-        launch_mlp_fwd(ma, dvgo::device_cu_count(), s);
-        if (int32_t st = dvgo::launch_status()) return st;
+    if (mlp) ma = make_mlp_args(cm, mlp, n_kept);
+    if (!forward_done) {
+        // prep (packing, per-ray encoding) also clears the cell counts
+        if (int32_t st = run_prep(cm, mlp, s, bins.cell_count, bins.ncell + 1)) return st;
+        if (int32_t st = run_gather(cm, field, mlp != nullptr, n_kept, s)) return st;
+        if (mlp) {
+            launch_mlp_fwd(ma, dvgo::device_cu_count(), s);
+            if (int32_t st = dvgo::launch_status()) return st;
+        }
     }
     // adjoint of the compositing; bins every sample by fine cell on the way
     ComposeArgs ca = make_compose(cm, perm, ray_offset, n_uniform, n_kept, field->act_shift, bg, mlp != nullptr);
@@ -1186,6 +1192,69 @@ int32_t dvgo_render_bwd_adam(const dvgo_field* field, const dvgo_mlp* mlp, const
     return render_bwd_impl(field, mlp, rays_o, rays_d, jitter, t_near, n_uniform, perm, ray_offset, sample_ray,
                            sample_k, n_kept, capacity, B, step, bg, log_t_end, grad_rgb, grad_depth, grad_acc, nullptr,
                            nullptr, &o, grad_mlp, workspace, workspace_bytes, stream);
+}
+
+int32_t dvgo_train_step(const dvgo_field* field, const dvgo_mlp* mlp, const float* rays_o, const float* rays_d,
+                        const float* jitter, const float* t_near, const int32_t* n_uniform, const int32_t* perm,
+                        const int32_t* ray_offset, const int32_t* sample_ray, const int32_t* sample_k,
+                        const int64_t* n_kept, int64_t capacity, int32_t B, float step, const float* bg,
+                        const float* target, float* rgb, float* loss, const dvgo_grid_adam* opt, float* grad_mlp,
+                        void* workspace, size_t workspace_bytes, void* stream) {
+    if (int32_t st = validate(field, mlp, rays_o, rays_d, t_near, n_uniform, perm, ray_offset, sample_ray, sample_k,
+                              n_kept, capacity, B, step, bg, workspace, workspace_bytes))
+        return st;
+    if (!mlp || !opt || !grad_mlp || (B > 0 && !target)) return DVGO_E_ARG;
+    char* ws = static_cast<char*>(workspace);
+    const WsLayout L = ws_layout(B, capacity, cell_count_of(field->box));
+    float* rgb_w = rgb ? rgb : reinterpret_cast<float*>(ws + L.step_rgb);
+    float* grad_w = reinterpret_cast<float*>(ws + L.step_grad);
+    float* logt_w = reinterpret_cast<float*>(ws + L.step_logt);
+    if (B == 0 || capacity == 0) {   // nothing shared to reuse: the separate calls
+        if (int32_t st = dvgo_render_fwd(field, mlp, rays_o, rays_d, jitter, t_near, n_uniform, perm, ray_offset,
+                                         sample_ray, sample_k, n_kept, capacity, B, step, bg, rgb_w, nullptr,
+                                         nullptr, logt_w, nullptr, nullptr, workspace, workspace_bytes, stream))
+            return st;
+        if (int32_t st = dvgo_photo_loss(rgb_w, target, B, grad_w, loss, stream)) return st;
+        return dvgo_render_bwd_adam(field, mlp, rays_o, rays_d, jitter, t_near, n_uniform, perm, ray_offset,
+                                    sample_ray, sample_k, n_kept, capacity, B, step, bg, logt_w, grad_w, nullptr,
+                                    nullptr, opt, grad_mlp, workspace, workspace_bytes, stream);
+    }
+    if (!opt->density || !opt->density_m || !opt->density_v || !opt->feat || !opt->feat_m || !opt->feat_v)
+        return DVGO_E_ARG;
+    if (!dvgo::adam_hyper_ok(opt->beta1, opt->beta2, opt->eps, opt->t)) return DVGO_E_ARG;
+    auto al16 = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
+    if (!al16(opt->feat) || !al16(opt->feat_m) || !al16(opt->feat_v) ||
+        (opt->feat_shadow_bf16 && (reinterpret_cast<uintptr_t>(opt->feat_shadow_bf16) & 7u) != 0))
+        return DVGO_E_ARG;
+    hipStream_t s = dvgo::as_stream(stream);
+    // forward: prep (also clears the cell counts), gather, network, compositing
+    Common cm = make_common(field, rays_o, rays_d, jitter, t_near, sample_ray, sample_k, capacity, B, step,
+                            workspace);
+    const Bins bins = bins_of(cm, field);
+    if (int32_t st = run_prep(cm, mlp, s, bins.cell_count, bins.ncell + 1)) return st;
+    if (int32_t st = run_gather(cm, field, true, n_kept, s)) return st;
+    MlpArgs ma = make_mlp_args(cm, mlp, n_kept);
+    launch_mlp_fwd(ma, dvgo::device_cu_count(), s);
+    if (int32_t st = dvgo::launch_status()) return st;
+    ComposeArgs ca = make_compose(cm, perm, ray_offset, n_uniform, n_kept, field->act_shift, bg, true);
+    ca.rgb = rgb_w;
+    ca.log_t_end = logt_w;
+    DVGO_LAUNCH(K_COMPOSE_FWD, compose_fwd_kernel, dim3((B + 3) / 4), dim3(256), 0, s, ca);
+    if (int32_t st = dvgo::launch_status()) return st;
+    if (int32_t st = dvgo_photo_loss(rgb_w, target, B, grad_w, loss, stream)) return st;
+    // adjoint and Adam, reusing the forward's gathered features, colours and prep
+    GridAdamArgs o;
+    o.pd = opt->density;
+    o.md = opt->density_m;
+    o.vd = opt->density_v;
+    o.pf = opt->feat;
+    o.mf = opt->feat_m;
+    o.vf = opt->feat_v;
+    o.shadow = opt->feat_shadow_bf16;
+    o.c = dvgo::adam_coef(opt->lr, opt->beta1, opt->beta2, opt->eps, opt->t);
+    return render_bwd_impl(field, mlp, rays_o, rays_d, jitter, t_near, n_uniform, perm, ray_offset, sample_ray,
+                           sample_k, n_kept, capacity, B, step, bg, logt_w, grad_w, nullptr, nullptr, nullptr,
+                           nullptr, &o, grad_mlp, workspace, workspace_bytes, stream, true);
 }
 
 }  // extern "C"

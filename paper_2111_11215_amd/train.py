@@ -50,7 +50,8 @@ class FineConfig:
     bf16_feat: bool = False          # gather features from a bfloat16 shadow
     morton: bool = False
     capacity: Optional[int] = None
-    fused_grid_adam: bool = True     # backward and grid Adam in one call (no grid gradient in memory)
+    fused_grid_adam: bool = True     # the whole step in one call (dvgo_train_step): no grid gradient in
+                                     # memory, the adjoint reuses the forward's gathers and colours
 
 
 class FineModel:
@@ -109,6 +110,15 @@ class FineModel:
         """One full iteration: sample, render, photometric loss, adjoint,
         Adam.  Returns the loss (device tensor) and the sample list."""
         s = self.sample(rays_o, rays_d, jitter, seg_mask)
+        if self.cfg.fused_grid_adam:
+            c = self.cfg
+            self.t += 1
+            lg, lm = self.lr(c.lr_grid), self.lr(c.lr_mlp)
+            d, f, m = self.st_density, self.st_feat, self.st_mlp
+            loss, rgb = api.train_step(self.grid, self.mlp, s, target, d.m, d.v, f.m, f.v, m.g, lg, self.t, c.betas,
+                                       c.eps, c.bg, precision=c.precision, use_shadow=c.bf16_feat)
+            api.adam_step(m.p, m.g, m.m, m.v, lm, self.t, c.betas, c.eps)
+            return {"loss": loss, "samples": s, "rgb": rgb}
         out = self.render(s, want_depth_acc=False)
         loss, grad = api.photo_loss(out["rgb"], target)
         if self.cfg.fused_grid_adam:

@@ -93,3 +93,46 @@ def test_fused_backward_adam_without_samples(gpu_lib):
     for a, b in ((ga.density, gb.density), (ga.feat, gb.feat), (mDa, mD), (vDa, vD), (mFa, mF), (vFa, vF)):
         assert torch.allclose(a, b, rtol=1e-6, atol=0)
     assert float(gm.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_train_step_equals_separate_calls(gpu_lib, bf16):
+    """dvgo_train_step (the adjoint reusing the forward's gathers, colours and
+    prep inside one call) against dvgo_render_fwd + dvgo_photo_loss +
+    dvgo_render_bwd_adam: identical colour, loss and network gradient; the
+    same grid update up to the summation order of the grid gradients."""
+    import torch
+    from paper_2111_11215_amd import api
+    from paper_2111_11215_amd._lib import DVGO_BF16, DVGO_F32
+    prec = DVGO_BF16 if bf16 else DVGO_F32
+    P = _problem(9, n_rays=2048, bias=0.3)
+    grid, flat, s = _gpu(P, bf16=bf16)
+    rng = np.random.default_rng(11)
+    mD, vD = _state(rng, P.density.shape)
+    mF, vF = _state(rng, P.feat.shape)
+    target = to_dev(P.rays.target.astype(F32))
+    lr, t = 0.1, 3
+
+    ga = _clone_grid(api, grid)
+    out = api.render_fwd(ga, flat, s, P.bg, precision=prec, use_shadow=bf16, want_depth_acc=False)
+    loss_a, g = api.photo_loss(out["rgb"], target)
+    gma = torch.zeros_like(flat)
+    mDa, vDa, mFa, vFa = mD.clone(), vD.clone(), mF.clone(), vF.clone()
+    api.render_bwd_adam(ga, flat, s, out["log_t_end"], g, mDa, vDa, mFa, vFa, gma, lr, t, bg=P.bg, precision=prec,
+                        use_shadow=bf16)
+
+    gb = _clone_grid(api, grid)
+    gmb = torch.zeros_like(flat)
+    mDb, vDb, mFb, vFb = mD.clone(), vD.clone(), mF.clone(), vF.clone()
+    loss_b, rgb_b = api.train_step(gb, flat, s, target, mDb, vDb, mFb, vFb, gmb, lr, t, bg=P.bg, precision=prec,
+                                   use_shadow=bf16)
+    assert torch.equal(out["rgb"], rgb_b)
+    assert torch.equal(loss_a, loss_b)
+    assert torch.equal(gma, gmb)
+    for name, p0, pa, pb in (("density", grid.density, ga.density, gb.density),
+                             ("feat", grid.feat, ga.feat, gb.feat)):
+        assert report(f"{name} update", np_of(pb - p0), np_of(pa - p0))[0] <= 1e-5, name
+    for name, a, b in (("m density", mDa, mDb), ("v density", vDa, vDb), ("m feat", mFa, mFb), ("v feat", vFa, vFb)):
+        assert report(name, np_of(b), np_of(a))[0] <= 1e-5, name
+    if bf16:
+        assert np.array_equal(np_of(gb.feat_shadow).view(np.uint16), _bf16_bits(np_of(gb.feat)))
