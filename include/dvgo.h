@@ -260,7 +260,9 @@ int32_t dvgo_render_bwd_adam(const dvgo_field* field /*host*/, const dvgo_mlp* m
  * packed network, the per-ray encodings, every sample's gathered density
  * and features and its colour) instead of evaluating them again; the
  * transmittance is still recomputed from each ray's end.  rgb [B][3] (or
- * NULL) receives the rendered colour, loss (device float or NULL) the loss;
+ * NULL) receives the rendered colour, loss (device float or NULL) the loss
+ * (its gradient is formed inside the compositing, bit-identical to
+ * dvgo_photo_loss's; the loss sum itself runs in another fixed order);
  * the grids take their Adam step through opt and the network gradient is
  * accumulated into grad_mlp (its Adam step is the caller's dvgo_adam_step).
  * Same arguments, workspace and errors as the separate calls. */

@@ -28,7 +28,7 @@ constexpr int kMaxBwdBlocks = 256;
 
 struct WsLayout {
     size_t base, pe, w1p, w2p, w2tp, w1pb, w2pb, w2tpb, w3pb, w3tpb, w1tpb, raw, feat, col, partial, cell_count,
-        cell_start, scan_tmp, cell_rank, rec_head, rec, step_rgb, step_grad, step_logt, total;
+        cell_start, scan_tmp, cell_rank, rec_head, rec, step_rgb, step_grad, step_logt, step_sqerr, total;
 };
 
 constexpr int kScanPer = 8192;   // elements per block of the device-wide scan
@@ -65,6 +65,7 @@ WsLayout ws_layout(int64_t B, int64_t cap, int64_t ncell) {
     L.step_rgb = take(static_cast<size_t>(B) * 3 * 4);    // per-ray state of dvgo_train_step
     L.step_grad = take(static_cast<size_t>(B) * 3 * 4);
     L.step_logt = take(static_cast<size_t>(B) * 4);
+    L.step_sqerr = take(static_cast<size_t>(B) * 4);
     L.total = off;
     return L;
 }
@@ -272,6 +273,11 @@ struct ComposeArgs {
     float* log_t_end;
     float* seg_w;
     float* sample_w;
+    // forward, inside dvgo_train_step: the photometric loss's gradient and
+    // each ray's squared error (summed later in a fixed order)
+    const float* target;
+    float* grad_rgb_out;
+    float* sq_err;
     // backward inputs
     const float* log_t_end_in;
     const float* grad_rgb;
@@ -388,9 +394,20 @@ __global__ __launch_bounds__(256) void compose_fwd_kernel(ComposeArgs a) {
     if (lane == 0) {
         const float T = expf(logT);
         if (a.rgb) {
-            a.rgb[3 * r + 0] = cr + T * a.bg[0];
-            a.rgb[3 * r + 1] = cg + T * a.bg[1];
-            a.rgb[3 * r + 2] = cb + T * a.bg[2];
+            const float c3[3] = {cr + T * a.bg[0], cg + T * a.bg[1], cb + T * a.bg[2]};
+            a.rgb[3 * r + 0] = c3[0];
+            a.rgb[3 * r + 1] = c3[1];
+            a.rgb[3 * r + 2] = c3[2];
+            if (a.target) {   // Eq. photo_loss: gradient 2 (C - C*)/B, as dvgo_photo_loss forms it
+                const float invB = 1.0f / static_cast<float>(a.B);
+                float e2 = 0.0f;
+                for (int c = 0; c < 3; ++c) {
+                    const float d = c3[c] - a.target[3 * r + c];
+                    a.grad_rgb_out[3 * r + c] = 2.0f * d * invB;
+                    e2 += d * d;
+                }
+                a.sq_err[r] = e2;
+            }
         }
         if (a.depth) a.depth[r] = dep;
         if (a.acc) a.acc[r] = accw;
@@ -776,9 +793,12 @@ __global__ __launch_bounds__(1024) void scan_apply_kernel(const int* __restrict_
 // 64 parameters per workgroup, each of the 4 waves sums every 4th partial,
 // then the 4 wave sums are added in a fixed order.
 // 64 parameters per workgroup, 16 wavefronts each summing every 16th
-// partial row, then a fixed-order sum of the 16 (deterministic).
+// partial row, then a fixed-order sum of the 16 (deterministic).  With
+// sq_err, workgroup 0 also forms the photometric loss (1/B) sum of the
+// rays' squared errors, in a fixed order.
 __global__ __launch_bounds__(1024) void reduce_partials_kernel(const float* __restrict__ partial, int nblk,
-                                                               float* __restrict__ out) {
+                                                               float* __restrict__ out, const float* __restrict__ sq_err,
+                                                               int B, float* __restrict__ loss) {
     __shared__ float sh[16][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int p = blockIdx.x * 64 + lane;
@@ -791,6 +811,19 @@ __global__ __launch_bounds__(1024) void reduce_partials_kernel(const float* __re
         float t = 0.0f;
         for (int w = 0; w < 16; ++w) t += sh[w][lane];
         out[p] += t;
+    }
+    if (blockIdx.x == 0 && sq_err) {
+        __syncthreads();
+        float e = 0.0f;
+        for (int i = threadIdx.x; i < B; i += 1024) e += sq_err[i];
+        for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
+        if (lane == 0) sh[0][wave] = e;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float t = 0.0f;
+            for (int w = 0; w < 16; ++w) t += sh[0][w];
+            if (loss) *loss = t * (1.0f / static_cast<float>(B));
+        }
     }
 }
 
@@ -1037,7 +1070,7 @@ int32_t render_bwd_impl(const dvgo_field* field, const dvgo_mlp* mlp, const floa
                         const float* log_t_end, const float* grad_rgb, const float* grad_depth,
                         const float* grad_acc, float* grad_density, float* grad_feat, const GridAdamArgs* opt,
                         float* grad_mlp, void* workspace, size_t workspace_bytes, void* stream,
-                        bool forward_done = false) {
+                        bool forward_done = false, const float* sq_err = nullptr, float* loss = nullptr) {
     if (int32_t st = validate(field, mlp, rays_o, rays_d, t_near, n_uniform, perm, ray_offset, sample_ray, sample_k,
                               n_kept, capacity, B, step, bg, workspace, workspace_bytes))
         return st;
@@ -1099,7 +1132,7 @@ int32_t render_bwd_impl(const dvgo_field* field, const dvgo_mlp* mlp, const floa
         return st;
     if (mlp) {
         DVGO_LAUNCH(K_REDUCE, reduce_partials_kernel, dim3((kMlpParams + 63) / 64), dim3(1024), 0, s,
-                           reinterpret_cast<const float*>(cm.ws + cm.L.partial), nblk, grad_mlp);
+                    reinterpret_cast<const float*>(cm.ws + cm.L.partial), nblk, grad_mlp, sq_err, B, loss);
         if (int32_t st = dvgo::launch_status()) return st;
     }
     return DVGO_OK;
@@ -1236,12 +1269,15 @@ int32_t dvgo_train_step(const dvgo_field* field, const dvgo_mlp* mlp, const floa
     MlpArgs ma = make_mlp_args(cm, mlp, n_kept);
     launch_mlp_fwd(ma, dvgo::device_cu_count(), s);
     if (int32_t st = dvgo::launch_status()) return st;
+    float* sq_w = reinterpret_cast<float*>(ws + L.step_sqerr);
     ComposeArgs ca = make_compose(cm, perm, ray_offset, n_uniform, n_kept, field->act_shift, bg, true);
     ca.rgb = rgb_w;
     ca.log_t_end = logt_w;
+    ca.target = target;          // the loss gradient comes out of the compositing
+    ca.grad_rgb_out = grad_w;
+    ca.sq_err = sq_w;
     DVGO_LAUNCH(K_COMPOSE_FWD, compose_fwd_kernel, dim3((B + 3) / 4), dim3(256), 0, s, ca);
     if (int32_t st = dvgo::launch_status()) return st;
-    if (int32_t st = dvgo_photo_loss(rgb_w, target, B, grad_w, loss, stream)) return st;
     // adjoint and Adam, reusing the forward's gathered features, colours and prep
     GridAdamArgs o;
     o.pd = opt->density;
@@ -1254,7 +1290,7 @@ int32_t dvgo_train_step(const dvgo_field* field, const dvgo_mlp* mlp, const floa
     o.c = dvgo::adam_coef(opt->lr, opt->beta1, opt->beta2, opt->eps, opt->t);
     return render_bwd_impl(field, mlp, rays_o, rays_d, jitter, t_near, n_uniform, perm, ray_offset, sample_ray,
                            sample_k, n_kept, capacity, B, step, bg, logt_w, grad_w, nullptr, nullptr, nullptr,
-                           nullptr, &o, grad_mlp, workspace, workspace_bytes, stream, true);
+                           nullptr, &o, grad_mlp, workspace, workspace_bytes, stream, true, sq_w, loss);
 }
 
 }  // extern "C"

@@ -99,8 +99,9 @@ def test_fused_backward_adam_without_samples(gpu_lib):
 def test_train_step_equals_separate_calls(gpu_lib, bf16):
     """dvgo_train_step (the adjoint reusing the forward's gathers, colours and
     prep inside one call) against dvgo_render_fwd + dvgo_photo_loss +
-    dvgo_render_bwd_adam: identical colour, loss and network gradient; the
-    same grid update up to the summation order of the grid gradients."""
+    dvgo_render_bwd_adam: identical colour, loss gradient and network
+    gradient; the loss to float32 rounding (its sum runs in another order);
+    the same grid update up to the summation order of the grid gradients."""
     import torch
     from paper_2111_11215_amd import api
     from paper_2111_11215_amd._lib import DVGO_BF16, DVGO_F32
@@ -127,7 +128,7 @@ def test_train_step_equals_separate_calls(gpu_lib, bf16):
     loss_b, rgb_b = api.train_step(gb, flat, s, target, mDb, vDb, mFb, vFb, gmb, lr, t, bg=P.bg, precision=prec,
                                    use_shadow=bf16)
     assert torch.equal(out["rgb"], rgb_b)
-    assert torch.equal(loss_a, loss_b)
+    assert abs(float(loss_a[0]) - float(loss_b[0])) <= 1e-6 * float(loss_a[0])
     assert torch.equal(gma, gmb)
     for name, p0, pa, pb in (("density", grid.density, ga.density, gb.density),
                              ("feat", grid.feat, ga.feat, gb.feat)):
