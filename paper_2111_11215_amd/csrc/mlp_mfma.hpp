@@ -549,6 +549,42 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_f32_kernel(MlpArgs a0) {
 // a lane's 8 consecutive samples are one 16-byte LDS read.
 // ---------------------------------------------------------------------------
 constexpr int kBP = 136;   // LDS pitch (bf16 elements) of a staged feature row
+constexpr int kTP = 144;   // LDS pitch (bf16) of a staged sample row [sample][feature]: the four rows a
+                           // 16-lane group reads at once fall on disjoint LDS banks
+
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
+
+// This lane's packed operand fragment of step st (features phi16(st, 0..7, h),
+// two runs of four) into its sample's row: two 8-byte stores.
+__device__ __forceinline__ void stage_row(__bf16* T, int col_s, int st, int h, const bf16x8& v) {
+    __bf16* row = T + col_s * kTP + 32 * (st >> 1) + 16 * (st & 1) + 4 * h;
+    bf16x4 lo, hi;
+    #pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        lo[e] = v[e];
+        hi[e] = v[4 + e];
+    }
+    *reinterpret_cast<bf16x4*>(row) = lo;
+    *reinterpret_cast<bf16x4*>(row + 8) = hi;
+}
+
+// K-major operand from [sample][feature] rows with two LDS transpose reads:
+// lane (m, h) receives feature col0 + m of samples row0 + 8h .. row0 + 8h + 7.
+// Each read transposes a 16x4 block within a 16-lane group: source lane t of
+// group G addresses sample row0 + 8(G/2) + t/4, features col0 + 16(G%2) + 4(t%4)
+// .. +3, and output lane i of the group receives feature col0 + 16(G%2) + i of
+// those four samples.
+__device__ __forceinline__ bf16x8 tr_operand(const __bf16* T, int row0, int col0, int lane) {
+    const int G = lane >> 4, t = lane & 15;
+    const __bf16* p = T + (row0 + 8 * (G >> 1) + (t >> 2)) * kTP + col0 + 16 * (G & 1) + 4 * (t & 3);
+    const s16x4 a = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)p);
+    const s16x4 b = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(p + 4 * kTP));
+    typedef short s16x8 __attribute__((ext_vector_type(8)));
+    const s16x8 ab = __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7);
+    return __builtin_bit_cast(bf16x8, ab);
+}
 
 __device__ __forceinline__ bf16x8 pack8(const f32x16& v, int g) {
     bf16x8 r;
@@ -566,8 +602,14 @@ __device__ __forceinline__ f32x16 chain_tile_bf16(const bf16x8* w, int lane, int
     return acc;
 }
 
+struct ChainBF16 {
+    f32x16 h1[4];   // relu(layer-1) per 32-feature tile
+    f32x16 z2[4];   // layer-2 pre-activation
+    bf16x8 hb[8];   // bf16(h1) in chained operand order
+};
+
 __device__ __forceinline__ void forward_chain_bf16(const MlpArgs& a, const bf16x8* sW1, const bf16x8* sW2, int r,
-                                                   const float f[12], int lane, ChainF32& c) {
+                                                   const float f[12], int lane, ChainBF16& c) {
     const int h = lane >> 5;
     load_base(a.base, r, h, c.h1);
     bf16x8 fb;
@@ -585,16 +627,16 @@ __device__ __forceinline__ void forward_chain_bf16(const MlpArgs& a, const bf16x
             c.h1[mt][rr] = fmaxf(c.h1[mt][rr], 0.0f);
             c.z2[mt][rr] = a.b2[32 * mt + acc_row(rr, h)];
         }
-    bf16x8 hb[8];
     #pragma unroll
-    for (int st = 0; st < 8; ++st) hb[st] = pack8(c.h1[st >> 1], st & 1);
+    for (int st = 0; st < 8; ++st) c.hb[st] = pack8(c.h1[st >> 1], st & 1);
     #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) c.z2[mt] = chain_tile_bf16(sW2, lane, mt, hb, c.z2[mt]);
+    for (int mt = 0; mt < 4; ++mt) c.z2[mt] = chain_tile_bf16(sW2, lane, mt, c.hb, c.z2[mt]);
 }
 
 // Layer 3 on matrix cores: logits of sample m land in lane m (half 0),
 // registers 0..2; bfloat16 relu(z2) and W3, float32 accumulation.
-__device__ __forceinline__ f32x16 head_bf16(const MlpArgs& a, const f32x16 z2[4], int lane, float c[3]) {
+__device__ __forceinline__ f32x16 head_bf16(const MlpArgs& a, const f32x16 z2[4], int lane, float c[3],
+                                            bf16x8 h2b[8]) {
     const int h = lane >> 5;
     f32x16 z3;
     #pragma unroll
@@ -605,6 +647,7 @@ __device__ __forceinline__ f32x16 head_bf16(const MlpArgs& a, const f32x16 z2[4]
         bf16x8 hv;
         #pragma unroll
         for (int e = 0; e < 8; ++e) hv[e] = static_cast<__bf16>(fmaxf(z2[st >> 1][8 * (st & 1) + e], 0.0f));
+        h2b[st] = hv;
         z3 = mma_bf16(w3[st * 64 + lane], hv, z3);
     }
     c[0] = 1.0f / (1.0f + expf(-z3[0]));
@@ -641,10 +684,11 @@ __global__ __launch_bounds__(256, 2) void mlp_fwd_bf16_kernel(MlpArgs a0) {
         const int r = a.sample_ray[sc];
         float f[12];
         load_feat(a.feat, sc, f);
-        ChainF32 c;
+        ChainBF16 c;
         forward_chain_bf16(a, sW1, sW2, r, f, lane, c);
         float col[3];
-        head_bf16(a, c.z2, lane, col);
+        bf16x8 h2b[8];
+        head_bf16(a, c.z2, lane, col, h2b);
         if (ok && h == 0) reinterpret_cast<float4*>(a.col)[s] = make_float4(col[0], col[1], col[2], 0.0f);
     }
 }
@@ -653,9 +697,9 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_bf16_kernel(MlpArgs a0) {
     __shared__ bf16x8 sW2[kW2PackBF16 / 8];
     __shared__ bf16x8 sW2T[kW2PackBF16 / 8];
     __shared__ bf16x8 sW1[kW1PackBF16 / 8];
-    __shared__ __attribute__((aligned(16))) __bf16 sA[128 * kBP];   // h1 then dL/dz1, [feature][sample]
-    __shared__ __attribute__((aligned(16))) __bf16 sB[128 * kBP];   // h2, then dL/dz2, then x'
-    __shared__ __attribute__((aligned(16))) __bf16 sC[32 * kBP];    // dL/dz3 in rows 0..2, zero rows 3..31
+    __shared__ __attribute__((aligned(16))) __bf16 tA[128 * kTP];   // h1 then dL/dz1, [sample][feature]
+    __shared__ __attribute__((aligned(16))) __bf16 tB[128 * kTP];   // h2, then dL/dz2, then x'
+    __shared__ __attribute__((aligned(16))) __bf16 sC[32 * kBP];    // dL/dz3 [feature][sample], rows 0..2
     __shared__ float sRed[4 * 4];
     load_packed_bf16(a0, sW1, sW2, sW2T);
     for (int i = threadIdx.x; i < 32 * kBP; i += blockDim.x) sC[i] = static_cast<__bf16>(0.0f);
@@ -688,10 +732,11 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_bf16_kernel(MlpArgs a0) {
         const int r = a.sample_ray[sc];
         float f[12];
         load_feat(a.feat, sc, f);
-        ChainF32 c;
+        ChainBF16 c;
         forward_chain_bf16(a, sW1, sW2, r, f, lane, c);
         float col[3];
-        head_bf16(a, c.z2, lane, col);
+        bf16x8 h2b[8];
+        head_bf16(a, c.z2, lane, col, h2b);
         float dz3[3] = {0, 0, 0};
         if (ok && h == 0) {
             const float4 dc = reinterpret_cast<const float4*>(a.col)[s];
@@ -699,15 +744,12 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_bf16_kernel(MlpArgs a0) {
             dz3[1] = dc.y * col[1] * (1.0f - col[1]);
             dz3[2] = dc.z * col[2] * (1.0f - col[2]);
         }
-        // stage h1 -> sA, h2 -> sB, dz3 -> sC
+        // stage h1 -> tA, h2 -> tB (sample rows, from the packed operands), dz3 -> sC
         #pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
-            #pragma unroll
-            for (int rr = 0; rr < 16; ++rr) {
-                const int j = 32 * mt + acc_row(rr, h);
-                sA[j * kBP + col_s] = static_cast<__bf16>(c.h1[mt][rr]);
-                sB[j * kBP + col_s] = static_cast<__bf16>(fmaxf(c.z2[mt][rr], 0.0f));
-            }
+        for (int st = 0; st < 8; ++st) {
+            stage_row(tA, col_s, st, h, c.hb[st]);
+            stage_row(tB, col_s, st, h, h2b[st]);
+        }
         if (h == 0) {
             #pragma unroll
             for (int t = 0; t < 3; ++t) {
@@ -735,33 +777,27 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_bf16_kernel(MlpArgs a0) {
         // dW3^T[j in tile `wave`][c] over the 128 staged samples
         #pragma unroll
         for (int st = 0; st < 8; ++st) {
-            const bf16x8 av = *reinterpret_cast<const bf16x8*>(sB + (32 * wave + m) * kBP + 16 * st + 8 * h);
+            const bf16x8 av = tr_operand(tB, 16 * st, 32 * wave, lane);
             const bf16x8 bv = *reinterpret_cast<const bf16x8*>(sC + m * kBP + 16 * st + 8 * h);
             dW3 = mma_bf16(av, bv, dW3);
         }
+        bf16x8 zb[8];
+        #pragma unroll
+        for (int st = 0; st < 8; ++st) zb[st] = pack8(c.z2[st >> 1], st & 1);
         __syncthreads();
         #pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
-            #pragma unroll
-            for (int rr = 0; rr < 16; ++rr)
-                sB[(32 * mt + acc_row(rr, h)) * kBP + col_s] = static_cast<__bf16>(c.z2[mt][rr]);
+        for (int st = 0; st < 8; ++st) stage_row(tB, col_s, st, h, zb[st]);
         __syncthreads();
         // dW2[j in tile `wave`][i], and db2 through a constant ones column
         #pragma unroll 2
         for (int st = 0; st < 8; ++st) {
-            const bf16x8 av = *reinterpret_cast<const bf16x8*>(sB + (32 * wave + m) * kBP + 16 * st + 8 * h);
+            const bf16x8 av = tr_operand(tB, 16 * st, 32 * wave, lane);
             #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                const bf16x8 bv = *reinterpret_cast<const bf16x8*>(sA + (32 * nt + m) * kBP + 16 * st + 8 * h);
-                dW2[nt] = mma_bf16(av, bv, dW2[nt]);
-            }
+            for (int nt = 0; nt < 4; ++nt) dW2[nt] = mma_bf16(av, tr_operand(tA, 16 * st, 32 * nt, lane), dW2[nt]);
             dB2 = mma_bf16(av, ones, dB2);
         }
         // dh1 = W2^T dz2 (chained), dz1 = dh1 * relu'(h1) in place of h1
         {
-            bf16x8 zb[8];
-            #pragma unroll
-            for (int st = 0; st < 8; ++st) zb[st] = pack8(c.z2[st >> 1], st & 1);
             #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
                 f32x16 dh1;
@@ -781,26 +817,31 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_bf16_kernel(MlpArgs a0) {
             for (int rr = 0; rr < 16; ++rr) dft[rr] = 0.0f;
             const bf16x8* w1t = reinterpret_cast<const bf16x8*>(a.w1tpb);
             #pragma unroll
-            for (int st = 0; st < 8; ++st) dft = mma_bf16(w1t[st * 64 + lane], pack8(c.h1[st >> 1], st & 1), dft);
+            for (int st = 0; st < 8; ++st) c.hb[st] = pack8(c.h1[st >> 1], st & 1);   // bf16(dz1)
+            #pragma unroll
+            for (int st = 0; st < 8; ++st) dft = mma_bf16(w1t[st * 64 + lane], c.hb[st], dft);
         }
         __syncthreads();
-        // stage dz1 -> sA, x' = [f, PE, 1, 0...] -> sB (64 columns)
+        // stage dz1 -> tA, x' = [f, PE, 1, 0...] -> tB (64 columns, this lane's half)
         #pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
-            #pragma unroll
-            for (int rr = 0; rr < 16; ++rr)
-                sA[(32 * mt + acc_row(rr, h)) * kBP + col_s] = static_cast<__bf16>(c.h1[mt][rr]);
+        for (int st = 0; st < 8; ++st) stage_row(tA, col_s, st, h, c.hb[st]);
         {
             const float* per = a.pe + static_cast<int64_t>(r) * 32;
-            #pragma unroll 4
-            for (int cc = 0; cc < 32; ++cc) {
-                const int cidx = 32 * h + cc;
-                float v;
-                if (cidx < kC) v = f[cidx < kC ? cidx : 0];
-                else if (cidx < kIn) v = per[cidx - kC];
-                else if (cidx == kIn) v = 1.0f;
-                else v = 0.0f;
-                sB[cidx * kBP + col_s] = static_cast<__bf16>(v);
+            #pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                bf16x8 xv;
+                #pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int cc = 8 * q + e;
+                    const int cidx = 32 * h + cc;
+                    float v;
+                    if (cidx < kC) v = f[cc < kC ? cc : 0];
+                    else if (cidx < kIn) v = per[cidx - kC];
+                    else if (cidx == kIn) v = 1.0f;
+                    else v = 0.0f;
+                    xv[e] = static_cast<__bf16>(v);
+                }
+                *reinterpret_cast<bf16x8*>(tB + col_s * kTP + 32 * h + 8 * q) = xv;
             }
         }
         if (ok) {
@@ -816,11 +857,9 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_bf16_kernel(MlpArgs a0) {
         __syncthreads();
         #pragma unroll
         for (int st = 0; st < 8; ++st) {
-            const bf16x8 av = *reinterpret_cast<const bf16x8*>(sA + (32 * wave + m) * kBP + 16 * st + 8 * h);
-            const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(sB + m * kBP + 16 * st + 8 * h);
-            const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(sB + (32 + m) * kBP + 16 * st + 8 * h);
-            dW1[0] = mma_bf16(av, b0, dW1[0]);
-            dW1[1] = mma_bf16(av, b1, dW1[1]);
+            const bf16x8 av = tr_operand(tA, 16 * st, 32 * wave, lane);
+            dW1[0] = mma_bf16(av, tr_operand(tB, 16 * st, 0, lane), dW1[0]);
+            dW1[1] = mma_bf16(av, tr_operand(tB, 16 * st, 32, lane), dW1[1]);
         }
         __syncthreads();
     }
