@@ -593,6 +593,26 @@ __device__ __forceinline__ bf16x8 pack8(const f32x16& v, int g) {
     return r;
 }
 
+// bf16(relu(x)) for 8 accumulator values: round first, then clamp the signed
+// 16-bit patterns at 0 (two values per packed integer max).  Rounding is
+// monotone and maps no positive float32 to a negative bfloat16, so this
+// equals rounding relu(x) (a negative input gives +0 either way).
+__device__ __forceinline__ bf16x8 relu_pack8(const f32x16& v, int g) {
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    typedef short s16x2 __attribute__((ext_vector_type(2)));
+    const s16x2 zero = {0, 0};
+    s16x2 q[4];
+    #pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const f32x2 x = {v[8 * g + 2 * p], v[8 * g + 2 * p + 1]};
+        q[p] = __builtin_elementwise_max(__builtin_bit_cast(s16x2, __builtin_convertvector(x, bf16x2)), zero);
+    }
+    const s16x4 lo = __builtin_shufflevector(q[0], q[1], 0, 1, 2, 3);
+    const s16x4 hi = __builtin_shufflevector(q[2], q[3], 0, 1, 2, 3);
+    return __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+}
+
 __device__ __forceinline__ float bf16r(float x) { return static_cast<float>(static_cast<__bf16>(x)); }
 
 __device__ __forceinline__ f32x16 chain_tile_bf16(const bf16x8* w, int lane, int mt, const bf16x8 in[8],
@@ -603,32 +623,41 @@ __device__ __forceinline__ f32x16 chain_tile_bf16(const bf16x8* w, int lane, int
 }
 
 struct ChainBF16 {
-    f32x16 h1[4];   // relu(layer-1) per 32-feature tile
     f32x16 z2[4];   // layer-2 pre-activation
-    bf16x8 hb[8];   // bf16(h1) in chained operand order
+    bf16x8 hb[8];   // bf16(relu(layer 1)) in chained operand order
 };
 
-__device__ __forceinline__ void forward_chain_bf16(const MlpArgs& a, const bf16x8* sW1, const bf16x8* sW2, int r,
-                                                   const float f[12], int lane, ChainBF16& c) {
+// Zero the entries of 8 accumulator values (g-th half of a tile) whose
+// activation, in its bfloat16 relu copy, is zero: the relu derivative.
+__device__ __forceinline__ void relu_mask(f32x16& d, const bf16x8& act, int g) {
+    const i16x8 s = __builtin_bit_cast(i16x8, act);
+    #pragma unroll
+    for (int e = 0; e < 8; ++e) d[8 * g + e] = s[e] > 0 ? d[8 * g + e] : 0.0f;
+}
+
+__device__ __forceinline__ void forward_chain_bf16(const MlpArgs& a, const bf16x8* sW1, const bf16x8* sW2,
+                                                   const float* sB2, int r, const float f[12], int lane,
+                                                   ChainBF16& c) {
     const int h = lane >> 5;
-    load_base(a.base, r, h, c.h1);
-    bf16x8 fb;
+    f32x16 h1[4];
+    load_base(a.base, r, h, h1);
+    bf16x8 fb;   // features 8h .. 8h+7 (zero beyond 12), selected with constant indices
     #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int k = 8 * h + e;
-        fb[e] = static_cast<__bf16>(k < kC ? f[k < kC ? k : 0] : 0.0f);
-    }
+    for (int e = 0; e < 8; ++e) fb[e] = static_cast<__bf16>(h ? (e < kC - 8 ? f[8 + (e < kC - 8 ? e : 0)] : 0.0f) : f[e]);
     #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) c.h1[mt] = mma_bf16(sW1[mt * 64 + lane], fb, c.h1[mt]);
+    for (int mt = 0; mt < 4; ++mt) h1[mt] = mma_bf16(sW1[mt * 64 + lane], fb, h1[mt]);
     #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
         #pragma unroll
-        for (int rr = 0; rr < 16; ++rr) {
-            c.h1[mt][rr] = fmaxf(c.h1[mt][rr], 0.0f);
-            c.z2[mt][rr] = a.b2[32 * mt + acc_row(rr, h)];
+        for (int q = 0; q < 4; ++q) {
+            const float4 b = *reinterpret_cast<const float4*>(sB2 + 32 * mt + 8 * q + 4 * h);
+            c.z2[mt][4 * q] = b.x;
+            c.z2[mt][4 * q + 1] = b.y;
+            c.z2[mt][4 * q + 2] = b.z;
+            c.z2[mt][4 * q + 3] = b.w;
         }
     #pragma unroll
-    for (int st = 0; st < 8; ++st) c.hb[st] = pack8(c.h1[st >> 1], st & 1);
+    for (int st = 0; st < 8; ++st) c.hb[st] = relu_pack8(h1[st >> 1], st & 1);
     #pragma unroll
     for (int mt = 0; mt < 4; ++mt) c.z2[mt] = chain_tile_bf16(sW2, lane, mt, c.hb, c.z2[mt]);
 }
@@ -644,9 +673,7 @@ __device__ __forceinline__ f32x16 head_bf16(const MlpArgs& a, const f32x16 z2[4]
     const bf16x8* w3 = reinterpret_cast<const bf16x8*>(a.w3pb);
     #pragma unroll
     for (int st = 0; st < 8; ++st) {
-        bf16x8 hv;
-        #pragma unroll
-        for (int e = 0; e < 8; ++e) hv[e] = static_cast<__bf16>(fmaxf(z2[st >> 1][8 * (st & 1) + e], 0.0f));
+        const bf16x8 hv = relu_pack8(z2[st >> 1], st & 1);
         h2b[st] = hv;
         z3 = mma_bf16(w3[st * 64 + lane], hv, z3);
     }
@@ -656,7 +683,9 @@ __device__ __forceinline__ f32x16 head_bf16(const MlpArgs& a, const f32x16 z2[4]
     return z3;
 }
 
-__device__ __forceinline__ void load_packed_bf16(const MlpArgs& a, bf16x8* sW1, bf16x8* sW2, bf16x8* sW2T) {
+__device__ __forceinline__ void load_packed_bf16(const MlpArgs& a, bf16x8* sW1, bf16x8* sW2, bf16x8* sW2T,
+                                                 float* sB2) {
+    if (threadIdx.x < kH) sB2[threadIdx.x] = a.b2[threadIdx.x];
     const bf16x8* g1 = reinterpret_cast<const bf16x8*>(a.w1pb);
     const bf16x8* g2 = reinterpret_cast<const bf16x8*>(a.w2pb);
     const bf16x8* g2t = reinterpret_cast<const bf16x8*>(a.w2tpb);
@@ -670,7 +699,8 @@ __device__ __forceinline__ void load_packed_bf16(const MlpArgs& a, bf16x8* sW1, 
 __global__ __launch_bounds__(256, 2) void mlp_fwd_bf16_kernel(MlpArgs a0) {
     __shared__ bf16x8 sW2[kW2PackBF16 / 8];
     __shared__ bf16x8 sW1[kW1PackBF16 / 8];
-    load_packed_bf16(a0, sW1, sW2, nullptr);
+    __shared__ __attribute__((aligned(16))) float sB2[kH];
+    load_packed_bf16(a0, sW1, sW2, nullptr, sB2);
     __syncthreads();
     const int64_t n = *a0.n_kept < a0.cap ? *a0.n_kept : a0.cap;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -685,7 +715,7 @@ __global__ __launch_bounds__(256, 2) void mlp_fwd_bf16_kernel(MlpArgs a0) {
         float f[12];
         load_feat(a.feat, sc, f);
         ChainBF16 c;
-        forward_chain_bf16(a, sW1, sW2, r, f, lane, c);
+        forward_chain_bf16(a, sW1, sW2, sB2, r, f, lane, c);
         float col[3];
         bf16x8 h2b[8];
         head_bf16(a, c.z2, lane, col, h2b);
@@ -700,8 +730,9 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_bf16_kernel(MlpArgs a0) {
     __shared__ __attribute__((aligned(16))) __bf16 tA[128 * kTP];   // h1 then dL/dz1, [sample][feature]
     __shared__ __attribute__((aligned(16))) __bf16 tB[128 * kTP];   // h2, then dL/dz2, then x'
     __shared__ __attribute__((aligned(16))) __bf16 sC[32 * kBP];    // dL/dz3 [feature][sample], rows 0..2
+    __shared__ __attribute__((aligned(16))) float sB2[kH];
     __shared__ float sRed[4 * 4];
-    load_packed_bf16(a0, sW1, sW2, sW2T);
+    load_packed_bf16(a0, sW1, sW2, sW2T, sB2);
     for (int i = threadIdx.x; i < 32 * kBP; i += blockDim.x) sC[i] = static_cast<__bf16>(0.0f);
     __syncthreads();
     const int64_t n = *a0.n_kept < a0.cap ? *a0.n_kept : a0.cap;
@@ -733,7 +764,7 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_bf16_kernel(MlpArgs a0) {
         float f[12];
         load_feat(a.feat, sc, f);
         ChainBF16 c;
-        forward_chain_bf16(a, sW1, sW2, r, f, lane, c);
+        forward_chain_bf16(a, sW1, sW2, sB2, r, f, lane, c);
         float col[3];
         bf16x8 h2b[8];
         head_bf16(a, c.z2, lane, col, h2b);
@@ -757,7 +788,9 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_bf16_kernel(MlpArgs a0) {
                 db3[t] += dz3[t];
             }
         }
-        // dz2 = (W3^T bf16(dz3)) * relu'(z2) on matrix cores, in place of z2
+        // dz2 = (W3^T bf16(dz3)) * relu'(z2) on matrix cores, packed as the
+        // chain's and the staging's operands
+        bf16x8 zb[8];
         {
             bf16x8 dzb;
             #pragma unroll
@@ -770,7 +803,10 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_bf16_kernel(MlpArgs a0) {
                 for (int rr = 0; rr < 16; ++rr) dh[rr] = 0.0f;
                 dh = mma_bf16(w3t[mt * 64 + lane], dzb, dh);
                 #pragma unroll
-                for (int rr = 0; rr < 16; ++rr) c.z2[mt][rr] = c.z2[mt][rr] > 0.0f ? dh[rr] : 0.0f;
+                for (int g = 0; g < 2; ++g) {
+                    relu_mask(dh, h2b[2 * mt + g], g);
+                    zb[2 * mt + g] = pack8(dh, g);
+                }
             }
         }
         __syncthreads();
@@ -781,9 +817,6 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_bf16_kernel(MlpArgs a0) {
             const bf16x8 bv = *reinterpret_cast<const bf16x8*>(sC + m * kBP + 16 * st + 8 * h);
             dW3 = mma_bf16(av, bv, dW3);
         }
-        bf16x8 zb[8];
-        #pragma unroll
-        for (int st = 0; st < 8; ++st) zb[st] = pack8(c.z2[st >> 1], st & 1);
         __syncthreads();
         #pragma unroll
         for (int st = 0; st < 8; ++st) stage_row(tB, col_s, st, h, zb[st]);
@@ -796,16 +829,18 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_bf16_kernel(MlpArgs a0) {
             for (int nt = 0; nt < 4; ++nt) dW2[nt] = mma_bf16(av, tr_operand(tA, 16 * st, 32 * nt, lane), dW2[nt]);
             dB2 = mma_bf16(av, ones, dB2);
         }
-        // dh1 = W2^T dz2 (chained), dz1 = dh1 * relu'(h1) in place of h1
-        {
+        // dh1 = W2^T dz2 (chained), dz1 = dh1 * relu'(z1), packed in place of
+        // bf16(relu(z1)) once its tile's mask is read
+        #pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            f32x16 dh1;
             #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) {
-                f32x16 dh1;
-                #pragma unroll
-                for (int rr = 0; rr < 16; ++rr) dh1[rr] = 0.0f;
-                dh1 = chain_tile_bf16(sW2T, lane, mt, zb, dh1);
-                #pragma unroll
-                for (int rr = 0; rr < 16; ++rr) c.h1[mt][rr] = c.h1[mt][rr] > 0.0f ? dh1[rr] : 0.0f;
+            for (int rr = 0; rr < 16; ++rr) dh1[rr] = 0.0f;
+            dh1 = chain_tile_bf16(sW2T, lane, mt, zb, dh1);
+            #pragma unroll
+            for (int g = 0; g < 2; ++g) {
+                relu_mask(dh1, c.hb[2 * mt + g], g);
+                c.hb[2 * mt + g] = pack8(dh1, g);
             }
         }
         // dL/dfeat = bf16(W1[:, :12])^T bf16(dz1) on matrix cores: rows c < 12
@@ -816,8 +851,6 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_bf16_kernel(MlpArgs a0) {
             #pragma unroll
             for (int rr = 0; rr < 16; ++rr) dft[rr] = 0.0f;
             const bf16x8* w1t = reinterpret_cast<const bf16x8*>(a.w1tpb);
-            #pragma unroll
-            for (int st = 0; st < 8; ++st) c.hb[st] = pack8(c.h1[st >> 1], st & 1);   // bf16(dz1)
             #pragma unroll
             for (int st = 0; st < 8; ++st) dft = mma_bf16(w1t[st * 64 + lane], c.hb[st], dft);
         }
