@@ -586,11 +586,24 @@ __device__ __forceinline__ bf16x8 tr_operand(const __bf16* T, int row0, int col0
     return __builtin_bit_cast(bf16x8, ab);
 }
 
+// Round-to-nearest-even bfloat16 pairs of accumulator values, as the packed
+// 32-bit words of an 8-element operand (one v_cvt_pk_bf16_f32 per pair).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ u16x2 cvt_pair(const f32x16& v, int i) {
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    const f32x2 x = {v[i], v[i + 1]};
+    return __builtin_bit_cast(u16x2, __builtin_convertvector(x, bf16x2));
+}
+
 __device__ __forceinline__ bf16x8 pack8(const f32x16& v, int g) {
-    bf16x8 r;
+    u32x4 w;
     #pragma unroll
-    for (int e = 0; e < 8; ++e) r[e] = static_cast<__bf16>(v[8 * g + e]);
-    return r;
+    for (int p = 0; p < 4; ++p) w[p] = __builtin_bit_cast(unsigned int, cvt_pair(v, 8 * g + 2 * p));
+    return __builtin_bit_cast(bf16x8, w);
 }
 
 // bf16(relu(x)) for 8 accumulator values: round first, then clamp the signed
@@ -598,42 +611,80 @@ __device__ __forceinline__ bf16x8 pack8(const f32x16& v, int g) {
 // monotone and maps no positive float32 to a negative bfloat16, so this
 // equals rounding relu(x) (a negative input gives +0 either way).
 __device__ __forceinline__ bf16x8 relu_pack8(const f32x16& v, int g) {
-    typedef float f32x2 __attribute__((ext_vector_type(2)));
-    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-    typedef short s16x2 __attribute__((ext_vector_type(2)));
     const s16x2 zero = {0, 0};
-    s16x2 q[4];
+    u32x4 w;
     #pragma unroll
     for (int p = 0; p < 4; ++p) {
-        const f32x2 x = {v[8 * g + 2 * p], v[8 * g + 2 * p + 1]};
-        q[p] = __builtin_elementwise_max(__builtin_bit_cast(s16x2, __builtin_convertvector(x, bf16x2)), zero);
+        const s16x2 q = __builtin_elementwise_max(__builtin_bit_cast(s16x2, cvt_pair(v, 8 * g + 2 * p)), zero);
+        w[p] = __builtin_bit_cast(unsigned int, q);
     }
-    const s16x4 lo = __builtin_shufflevector(q[0], q[1], 0, 1, 2, 3);
-    const s16x4 hi = __builtin_shufflevector(q[2], q[3], 0, 1, 2, 3);
-    return __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+    return __builtin_bit_cast(bf16x8, w);
+}
+
+// bf16(d) where the activation (a bf16 relu output, so a non-negative
+// pattern) is non-zero, else +0: the relu derivative applied after
+// rounding, with packed 16-bit min(act, 1) as the 0/1 factor (written as
+// the two packed instructions; the optimiser would otherwise split each
+// pair into compares and selects).  The constant 1 goes in a register
+// holding it in both halves: an inline constant of a packed instruction
+// would give the high half 0.
+__device__ __forceinline__ bf16x8 relu_grad_pack8(const f32x16& d, int g, const bf16x8& act) {
+    const u32x4 aw = __builtin_bit_cast(u32x4, act);
+    const unsigned int ones = 0x00010001u;
+    u32x4 w;
+    #pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        unsigned int m, r;
+        asm("v_pk_min_u16 %0, %1, %2" : "=v"(m) : "v"(aw[p]), "v"(ones));
+        asm("v_pk_mul_lo_u16 %0, %1, %2" : "=v"(r) : "v"(__builtin_bit_cast(unsigned int, cvt_pair(d, 8 * g + 2 * p))),
+            "v"(m));
+        w[p] = r;
+    }
+    return __builtin_bit_cast(bf16x8, w);
 }
 
 __device__ __forceinline__ float bf16r(float x) { return static_cast<float>(static_cast<__bf16>(x)); }
 
-__device__ __forceinline__ f32x16 chain_tile_bf16(const bf16x8* w, int lane, int mt, const bf16x8 in[8],
-                                                  f32x16 acc) {
+// NT output tiles mt0 .. mt0+NT-1 of a chained 128-wide layer, K step
+// outermost: the NT weight fragments of step st+1 are read from LDS while
+// the NT matrix-core ops of step st run (the order is pinned with
+// scheduling-group barriers: the register allocator would otherwise
+// serialise every read with its consumer).
+template <int NT>
+__device__ __forceinline__ void chain_tiles_bf16(const bf16x8* w, int lane, int mt0, const bf16x8 in[8],
+                                                 f32x16 acc[NT]) {
+    __builtin_amdgcn_sched_barrier(0);
+    bf16x8 cur[NT];
     #pragma unroll
-    for (int st = 0; st < 8; ++st) acc = mma_bf16(w[(mt * 8 + st) * 64 + lane], in[st], acc);
-    return acc;
+    for (int t = 0; t < NT; ++t) cur[t] = w[((mt0 + t) * 8) * 64 + lane];
+    #pragma unroll
+    for (int st = 0; st < 8; ++st) {
+        bf16x8 nxt[NT];
+        if (st < 7) {
+            #pragma unroll
+            for (int t = 0; t < NT; ++t) nxt[t] = w[((mt0 + t) * 8 + st + 1) * 64 + lane];
+        }
+        #pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = mma_bf16(cur[t], in[st], acc[t]);
+        if (st < 7) {
+            #pragma unroll
+            for (int t = 0; t < NT; ++t) cur[t] = nxt[t];
+        }
+    }
+    __builtin_amdgcn_sched_group_barrier(0x100, NT, 0);       // LDS reads of step 0
+    #pragma unroll
+    for (int st = 0; st < 7; ++st) {
+        __builtin_amdgcn_sched_group_barrier(0x100, NT, 0);   // LDS reads of step st+1
+        __builtin_amdgcn_sched_group_barrier(0x008, NT, 0);   // matrix-core ops of step st
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, NT, 0);
+    __builtin_amdgcn_sched_barrier(0);
 }
 
 struct ChainBF16 {
     f32x16 z2[4];   // layer-2 pre-activation
     bf16x8 hb[8];   // bf16(relu(layer 1)) in chained operand order
 };
-
-// Zero the entries of 8 accumulator values (g-th half of a tile) whose
-// activation, in its bfloat16 relu copy, is zero: the relu derivative.
-__device__ __forceinline__ void relu_mask(f32x16& d, const bf16x8& act, int g) {
-    const i16x8 s = __builtin_bit_cast(i16x8, act);
-    #pragma unroll
-    for (int e = 0; e < 8; ++e) d[8 * g + e] = s[e] > 0 ? d[8 * g + e] : 0.0f;
-}
 
 __device__ __forceinline__ void forward_chain_bf16(const MlpArgs& a, const bf16x8* sW1, const bf16x8* sW2,
                                                    const float* sB2, int r, const float f[12], int lane,
@@ -658,8 +709,7 @@ __device__ __forceinline__ void forward_chain_bf16(const MlpArgs& a, const bf16x
         }
     #pragma unroll
     for (int st = 0; st < 8; ++st) c.hb[st] = relu_pack8(h1[st >> 1], st & 1);
-    #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) c.z2[mt] = chain_tile_bf16(sW2, lane, mt, c.hb, c.z2[mt]);
+    chain_tiles_bf16<4>(sW2, lane, 0, c.hb, c.z2);
 }
 
 // Layer 3 on matrix cores: logits of sample m land in lane m (half 0),
@@ -803,10 +853,7 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_bf16_kernel(MlpArgs a0) {
                 for (int rr = 0; rr < 16; ++rr) dh[rr] = 0.0f;
                 dh = mma_bf16(w3t[mt * 64 + lane], dzb, dh);
                 #pragma unroll
-                for (int g = 0; g < 2; ++g) {
-                    relu_mask(dh, h2b[2 * mt + g], g);
-                    zb[2 * mt + g] = pack8(dh, g);
-                }
+                for (int g = 0; g < 2; ++g) zb[2 * mt + g] = relu_grad_pack8(dh, g, h2b[2 * mt + g]);
             }
         }
         __syncthreads();
@@ -832,16 +879,18 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_bf16_kernel(MlpArgs a0) {
         // dh1 = W2^T dz2 (chained), dz1 = dh1 * relu'(z1), packed in place of
         // bf16(relu(z1)) once its tile's mask is read
         #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            f32x16 dh1;
+        for (int m0 = 0; m0 < 4; m0 += 2) {
+            f32x16 dh1[2];
             #pragma unroll
-            for (int rr = 0; rr < 16; ++rr) dh1[rr] = 0.0f;
-            dh1 = chain_tile_bf16(sW2T, lane, mt, zb, dh1);
+            for (int t = 0; t < 2; ++t)
+                #pragma unroll
+                for (int rr = 0; rr < 16; ++rr) dh1[t][rr] = 0.0f;
+            chain_tiles_bf16<2>(sW2T, lane, m0, zb, dh1);
             #pragma unroll
-            for (int g = 0; g < 2; ++g) {
-                relu_mask(dh1, c.hb[2 * mt + g], g);
-                c.hb[2 * mt + g] = pack8(dh1, g);
-            }
+            for (int t = 0; t < 2; ++t)
+                #pragma unroll
+                for (int g = 0; g < 2; ++g)
+                    c.hb[2 * (m0 + t) + g] = relu_grad_pack8(dh1[t], g, c.hb[2 * (m0 + t) + g]);
         }
         // dL/dfeat = bf16(W1[:, :12])^T bf16(dz1) on matrix cores: rows c < 12
         // of the output tile (half 0: registers 0-7 -> c 0-3, 8-11; half 1:
