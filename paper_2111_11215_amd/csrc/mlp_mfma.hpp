@@ -805,12 +805,23 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_bf16_kernel(MlpArgs a0) {
     bf16x8 ones;
     #pragma unroll
     for (int e = 0; e < 8; ++e) ones[e] = static_cast<__bf16>(m == 0 ? 1.0f : 0.0f);
+    // the ray index of this lane's sample one block ahead: the per-ray loads
+    // at the top of each block then wait on one round trip, not two
+    int r_next = 0;
+    if (static_cast<int64_t>(blockIdx.x) * 128 < n) {
+        const int64_t s0 = static_cast<int64_t>(blockIdx.x) * 128 + col_s;
+        r_next = a0.sample_ray[s0 < n ? s0 : n - 1];
+    }
     for (int64_t blk = blockIdx.x; blk * 128 < n; blk += gridDim.x) {
         const MlpArgs a = refresh(a0);
         const int64_t s = blk * 128 + col_s;
         const bool ok = s < n;
         const int64_t sc = ok ? s : n - 1;
-        const int r = a.sample_ray[sc];
+        const int r = r_next;
+        if ((blk + gridDim.x) * 128 < n) {
+            const int64_t s1 = (blk + gridDim.x) * 128 + col_s;
+            r_next = a.sample_ray[s1 < n ? s1 : n - 1];
+        }
         float f[12];
         load_feat(a.feat, sc, f);
         ChainBF16 c;
@@ -869,12 +880,36 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_bf16_kernel(MlpArgs a0) {
         for (int st = 0; st < 8; ++st) stage_row(tB, col_s, st, h, zb[st]);
         __syncthreads();
         // dW2[j in tile `wave`][i], and db2 through a constant ones column
-        #pragma unroll 2
-        for (int st = 0; st < 8; ++st) {
-            const bf16x8 av = tr_operand(tB, 16 * st, 32 * wave, lane);
+        {
+            __builtin_amdgcn_sched_barrier(0);
+            bf16x8 ca = tr_operand(tB, 0, 32 * wave, lane), cb[4];
             #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) dW2[nt] = mma_bf16(av, tr_operand(tA, 16 * st, 32 * nt, lane), dW2[nt]);
-            dB2 = mma_bf16(av, ones, dB2);
+            for (int nt = 0; nt < 4; ++nt) cb[nt] = tr_operand(tA, 0, 32 * nt, lane);
+            #pragma unroll
+            for (int st = 0; st < 8; ++st) {
+                bf16x8 na, nb[4];
+                if (st < 7) {
+                    na = tr_operand(tB, 16 * (st + 1), 32 * wave, lane);
+                    #pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) nb[nt] = tr_operand(tA, 16 * (st + 1), 32 * nt, lane);
+                }
+                #pragma unroll
+                for (int nt = 0; nt < 4; ++nt) dW2[nt] = mma_bf16(ca, cb[nt], dW2[nt]);
+                dB2 = mma_bf16(ca, ones, dB2);
+                if (st < 7) {
+                    ca = na;
+                    #pragma unroll
+                    for (int nt = 0; nt < 4; ++nt) cb[nt] = nb[nt];
+                }
+            }
+            __builtin_amdgcn_sched_group_barrier(0x100, 10, 0);
+            #pragma unroll
+            for (int st = 0; st < 7; ++st) {
+                __builtin_amdgcn_sched_group_barrier(0x100, 10, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 5, 0);
+            }
+            __builtin_amdgcn_sched_group_barrier(0x008, 5, 0);
+            __builtin_amdgcn_sched_barrier(0);
         }
         // dh1 = W2^T dz2 (chained), dz1 = dh1 * relu'(z1), packed in place of
         // bf16(relu(z1)) once its tile's mask is read
@@ -937,11 +972,36 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_bf16_kernel(MlpArgs a0) {
             }
         }
         __syncthreads();
-        #pragma unroll
-        for (int st = 0; st < 8; ++st) {
-            const bf16x8 av = tr_operand(tA, 16 * st, 32 * wave, lane);
-            dW1[0] = mma_bf16(av, tr_operand(tB, 16 * st, 0, lane), dW1[0]);
-            dW1[1] = mma_bf16(av, tr_operand(tB, 16 * st, 32, lane), dW1[1]);
+        // dW1 over the staged samples, the next K step's operands read while
+        // this step's matrix ops run
+        {
+            __builtin_amdgcn_sched_barrier(0);
+            bf16x8 ca = tr_operand(tA, 0, 32 * wave, lane);
+            bf16x8 cb0 = tr_operand(tB, 0, 0, lane), cb1 = tr_operand(tB, 0, 32, lane);
+            #pragma unroll
+            for (int st = 0; st < 8; ++st) {
+                bf16x8 na, nb0, nb1;
+                if (st < 7) {
+                    na = tr_operand(tA, 16 * (st + 1), 32 * wave, lane);
+                    nb0 = tr_operand(tB, 16 * (st + 1), 0, lane);
+                    nb1 = tr_operand(tB, 16 * (st + 1), 32, lane);
+                }
+                dW1[0] = mma_bf16(ca, cb0, dW1[0]);
+                dW1[1] = mma_bf16(ca, cb1, dW1[1]);
+                if (st < 7) {
+                    ca = na;
+                    cb0 = nb0;
+                    cb1 = nb1;
+                }
+            }
+            __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
+            #pragma unroll
+            for (int st = 0; st < 7; ++st) {
+                __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+            }
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+            __builtin_amdgcn_sched_barrier(0);
         }
         __syncthreads();
     }
