@@ -549,25 +549,35 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_f32_kernel(MlpArgs a0) {
 // a lane's 8 consecutive samples are one 16-byte LDS read.
 // ---------------------------------------------------------------------------
 constexpr int kBP = 136;   // LDS pitch (bf16 elements) of a staged feature row
-constexpr int kTP = 144;   // LDS pitch (bf16) of a staged sample row [sample][feature]: the four rows a
-                           // 16-lane group reads at once fall on disjoint LDS banks
+constexpr int kTP = 128;   // LDS pitch (bf16) of a staged sample row [sample][feature]
 
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef short s16x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
 
+// A staged row is 32 chunks of 8 bytes (4 features); chunk j of sample row r
+// sits at chunk j ^ swz(r).  swz swaps the two low 2-bit fields of the row
+// index, so that both the 16 rows one staging store covers per 16 lanes and
+// the 4 rows x 4 chunks one transpose read covers per 16 lanes land on 16
+// distinct chunk positions modulo 16 (all 32 LDS banks).
+__device__ __forceinline__ int swz(int r) { return ((r & 3) << 2) | ((r >> 2) & 3); }
+__device__ __forceinline__ __bf16* chunk_at(__bf16* T, int r, int j) { return T + r * kTP + 4 * (j ^ swz(r)); }
+__device__ __forceinline__ const __bf16* chunk_at(const __bf16* T, int r, int j) {
+    return T + r * kTP + 4 * (j ^ swz(r));
+}
+
 // This lane's packed operand fragment of step st (features phi16(st, 0..7, h),
 // two runs of four) into its sample's row: two 8-byte stores.
 __device__ __forceinline__ void stage_row(__bf16* T, int col_s, int st, int h, const bf16x8& v) {
-    __bf16* row = T + col_s * kTP + 32 * (st >> 1) + 16 * (st & 1) + 4 * h;
+    const int j = 8 * (st >> 1) + 4 * (st & 1) + h;   // chunk of features 32(st/2) + 16(st%2) + 4h ..
     bf16x4 lo, hi;
     #pragma unroll
     for (int e = 0; e < 4; ++e) {
         lo[e] = v[e];
         hi[e] = v[4 + e];
     }
-    *reinterpret_cast<bf16x4*>(row) = lo;
-    *reinterpret_cast<bf16x4*>(row + 8) = hi;
+    *reinterpret_cast<bf16x4*>(chunk_at(T, col_s, j)) = lo;
+    *reinterpret_cast<bf16x4*>(chunk_at(T, col_s, j + 2)) = hi;
 }
 
 // K-major operand from [sample][feature] rows with two LDS transpose reads:
@@ -578,9 +588,9 @@ __device__ __forceinline__ void stage_row(__bf16* T, int col_s, int st, int h, c
 // those four samples.
 __device__ __forceinline__ bf16x8 tr_operand(const __bf16* T, int row0, int col0, int lane) {
     const int G = lane >> 4, t = lane & 15;
-    const __bf16* p = T + (row0 + 8 * (G >> 1) + (t >> 2)) * kTP + col0 + 16 * (G & 1) + 4 * (t & 3);
-    const s16x4 a = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)p);
-    const s16x4 b = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(p + 4 * kTP));
+    const int r = row0 + 8 * (G >> 1) + (t >> 2), j = (col0 + 16 * (G & 1)) / 4 + (t & 3);
+    const s16x4 a = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)chunk_at(T, r, j));
+    const s16x4 b = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)chunk_at(T, r + 4, j));
     typedef short s16x8 __attribute__((ext_vector_type(8)));
     const s16x8 ab = __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7);
     return __builtin_bit_cast(bf16x8, ab);
@@ -958,7 +968,14 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_bf16_kernel(MlpArgs a0) {
                     else v = 0.0f;
                     xv[e] = static_cast<__bf16>(v);
                 }
-                *reinterpret_cast<bf16x8*>(tB + col_s * kTP + 32 * h + 8 * q) = xv;
+                bf16x4 lo, hi;
+                #pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    lo[e] = xv[e];
+                    hi[e] = xv[4 + e];
+                }
+                *reinterpret_cast<bf16x4*>(chunk_at(tB, col_s, 8 * h + 2 * q)) = lo;
+                *reinterpret_cast<bf16x4*>(chunk_at(tB, col_s, 8 * h + 2 * q + 1)) = hi;
             }
         }
         if (ok) {
