@@ -322,10 +322,12 @@ def measured_traffic(kname):
     return rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
-def roofline(per_kernel, kname, n_prof, kept, nv, n_mlp, bf16):
+def roofline(per_kernel, kname, n_prof, kept, nv, n_mlp, bf16, n_step=None):
     """Achieved rate of the named kernel: algorithmic work per launch over
     its event-timed average launch duration.  ``kept`` = evaluated samples
-    per step, ``nv`` = grid vertices."""
+    per step, ``nv`` = grid vertices, ``n_step`` = vertices that take the
+    grid Adam step (those with non-zero moments or samples; the others'
+    step changes nothing and moves no byte), all of them when None."""
     k = per_kernel[kname]
     lps = k["launches"] / n_prof            # launches per step
     if kname in ("mlp_bwd", "mlp_fwd"):
@@ -335,7 +337,10 @@ def roofline(per_kernel, kname, n_prof, kept, nv, n_mlp, bf16):
         roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak}
     else:
         if kname == "grid_adam":
-            work = BYTES_GRID_ADAM_VERTEX * nv + (2 * 12 * nv if bf16 else 0) + BYTES_REC * kept
+            ns = nv if n_step is None else n_step
+            work = BYTES_GRID_ADAM_VERTEX * ns + (2 * 12 * ns if bf16 else 0) + BYTES_REC * kept
+            if n_step is not None:
+                work += 2 * ((nv + 31) // 32) * 4      # activity mask read and written
         elif kname == "adam":
             work = 32 * n_mlp + ((32 * 13 * nv + (2 * 12 * nv if bf16 else 0)) if "grid_adam" not in per_kernel
                                  or per_kernel["grid_adam"]["launches"] == 0 else 0)
@@ -352,6 +357,16 @@ def roofline(per_kernel, kname, n_prof, kept, nv, n_mlp, bf16):
     roof["launch_ms"] = k["ms_avg"]
     roof["launches_per_step"] = lps
     return roof
+
+
+def active_vertices(model):
+    """Vertices whose activity bit is set (they take the fused grid Adam
+    step), or None without a mask."""
+    import torch
+    if getattr(model, "active", None) is None:
+        return None
+    b = model.active.view(torch.uint8).to(torch.int32)
+    return int(sum(((b >> i) & 1).sum().item() for i in range(8)))
 
 
 PROFILED = ("ray_setup", "count_kept", "scan", "fill_kept", "prop_fwd", "prop_bwd", "prop_reduce", "pack",
@@ -403,6 +418,7 @@ def main():
     ms = 1e3 * st.seconds / args.steps
     timed = [batches[args.warmup + i] for i in range(args.steps)]
     kept = experiment.evaluated_per_step(model, timed, prop, n=min(8, len(timed)))
+    n_active = active_vertices(model)
     log(f"bench: {value:.4e} ray-samples/s, {ms:.3f} ms/step, evaluated {kept:.0f}/step")
 
     # per-kernel timing: HIP events around each launch of one kernel at a
@@ -441,6 +457,8 @@ def main():
                    "form": name, "rays_per_iter": args.rays, "grid": ctx["n"], "coarse": 100,
                    "max_samples": ctx["max_samples"], "morton": bool(args.morton)},
         "evaluated_samples_per_step": kept,
+        "grid_vertices_stepped": n_active,
+        "grid_vertices": ctx["n"] ** 3,
         "uniform_samples_per_step": st.uniform_samples / args.steps,
         "rays_per_s": args.rays * args.steps / st.seconds,
     }
@@ -449,9 +467,10 @@ def main():
         if kname == "auto":
             kname = max((k for k in ROOFLINE_MODELS if k in per_kernel), key=lambda k: per_kernel[k]["ms_total"])
         nv = ctx["n"] ** 3
-        out["roofline"] = roofline(per_kernel, kname, n_prof, kept, nv, model.st_mlp.p.numel(), bf16)
+        out["roofline"] = roofline(per_kernel, kname, n_prof, kept, nv, model.st_mlp.p.numel(), bf16, n_active)
         out["kernels_roofline"] = {
-            k: {f: v for f, v in roofline(per_kernel, k, n_prof, kept, nv, model.st_mlp.p.numel(), bf16).items()
+            k: {f: v for f, v in roofline(per_kernel, k, n_prof, kept, nv, model.st_mlp.p.numel(), bf16,
+                                          n_active).items()
                 if f in ("bound", "achieved", "unit", "frac", "launch_ms", "launches_per_step")}
             for k in ROOFLINE_MODELS if k in per_kernel and k != "adam"}
         out["kernels_ms_per_step"] = {k: v["ms_total"] / n_prof for k, v in per_kernel.items()}

@@ -218,6 +218,21 @@ int32_t dvgo_render_bwd(const dvgo_field* field /*host*/, const dvgo_mlp* mlp /*
  *   feat, feat_m, feat_v           [nx][ny][nz][C], 16-byte aligned;
  *   feat_shadow_bf16               [nx][ny][nz][C] bfloat16 bits, 8-byte
  *                                  aligned, or NULL (rewritten as bf16(feat)).
+ *   active                         [ceil(nx*ny*nz/32)] uint32 words, or NULL:
+ *                                  bit v (word v/32, bit v%32) must be set
+ *                                  whenever any of vertex v's moments (its
+ *                                  density's and its C features' m and v) is
+ *                                  non-zero.  A vertex whose bit is clear and
+ *                                  that no sample touches would take a step
+ *                                  with m = v = 0 and a zero gradient, which
+ *                                  leaves p, m and v unchanged bit for bit; it
+ *                                  is skipped without reading them.  The call
+ *                                  sets the bit of every vertex that steps with
+ *                                  a non-zero gradient, so the mask stays valid
+ *                                  across calls.  Zero-fill it together with
+ *                                  zero moments, or derive it from given
+ *                                  moments with dvgo_grid_active_init.  NULL:
+ *                                  every vertex steps (dense Adam).
  * lr, beta1, beta2, eps and the step count t >= 1 as in dvgo_adam_step. */
 typedef struct {
     float* density;
@@ -229,7 +244,16 @@ typedef struct {
     uint16_t* feat_shadow_bf16;
     float lr, beta1, beta2, eps;
     int32_t t;
+    uint32_t* active;
 } dvgo_grid_adam;
+
+/* The activity mask of dvgo_grid_adam from given moments: active[v/32] bit
+ * v%32 = 1 iff any of density_m[v], density_v[v], feat_m[v][0..C-1],
+ * feat_v[v][0..C-1] is non-zero (C = 12).  Every word of active
+ * [ceil(n_vertices/32)] is rewritten.  feat_m and feat_v 16-byte aligned,
+ * active 4-byte aligned; n_vertices >= 0. */
+int32_t dvgo_grid_active_init(const float* density_m, const float* density_v, const float* feat_m,
+                              const float* feat_v, int64_t n_vertices, uint32_t* active, void* stream);
 
 /* Backward pass and Adam step of both grids in one call: the result is that
  * of dvgo_render_bwd into zeroed grid gradients followed by dvgo_adam_step
@@ -346,7 +370,8 @@ int32_t dvgo_version(void);
  *   17 proposal forward, 18 proposal backward, 19 proposal reduce, 20 scene
  *   render, 21 (unused: cell binning counts run inside 11), 22 cell scan,
  *   23 record placement when there is no network,
- *   24 vertex gather with the grids' Adam step (dvgo_render_bwd_adam). */
+ *   24 vertex gather with the grids' Adam step (dvgo_render_bwd_adam),
+ *   25 activity mask from moments (dvgo_grid_active_init). */
 int32_t dvgo_profile_enable(int32_t kernel_id);
 int32_t dvgo_profile_read(double* total_ms, int64_t* launches);
 

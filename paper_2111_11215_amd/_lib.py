@@ -41,7 +41,7 @@ class Prop(ctypes.Structure):
 class GridAdam(ctypes.Structure):
     _fields_ = [("density", c_void_p), ("density_m", c_void_p), ("density_v", c_void_p), ("feat", c_void_p),
                 ("feat_m", c_void_p), ("feat_v", c_void_p), ("feat_shadow_bf16", c_void_p), ("lr", c_float),
-                ("beta1", c_float), ("beta2", c_float), ("eps", c_float), ("t", c_int32)]
+                ("beta1", c_float), ("beta2", c_float), ("eps", c_float), ("t", c_int32), ("active", c_void_p)]
 
 
 class DvgoError(RuntimeError):
@@ -70,6 +70,7 @@ SIGNATURES = {
                                   c_float, POINTER(c_float), P, P, P, POINTER(GridAdam), P, P, c_size_t, P]),
     "dvgo_photo_loss": (c_int32, [P, P, c_int32, P, P, P]),
     "dvgo_adam_step": (c_int32, [P, P, P, P, P, c_int64, c_float, c_float, c_float, c_float, c_int32, P]),
+    "dvgo_grid_active_init": (c_int32, [P, P, P, P, c_int64, P, P]),
     "dvgo_proposal_fwd": (c_int32, [P, P, P, P, c_int32, POINTER(Box), POINTER(Prop), c_double, c_double, P, P, P,
                                     P]),
     "dvgo_proposal_bwd": (c_int32, [P, P, P, P, c_int32, POINTER(Box), POINTER(Prop), P, P, P, P, P, c_size_t, P]),
@@ -86,7 +87,7 @@ SIGNATURES = {
 KERNEL_IDS = {name: i for i, name in enumerate([
     "ray_setup", "morton_sort", "count_kept", "scan", "fill_kept", "coarse_mask", "pack", "ray_base", "gather",
     "mlp_fwd", "compose_fwd", "compose_bwd", "mlp_bwd", "scatter", "reduce", "photo_loss", "adam", "prop_fwd",
-    "prop_bwd", "prop_reduce", "scene", "bin_count", "cell_scan", "bin_place", "grid_adam"])}
+    "prop_bwd", "prop_reduce", "scene", "bin_count", "cell_scan", "bin_place", "grid_adam", "grid_active"])}
 
 _lib = None
 

@@ -273,21 +273,42 @@ def render_bwd(grid: Grid, mlp_flat: Optional[torch.Tensor], s: Samples, log_t_e
         _stream(dev)))
 
 
+def grid_active_words(n_vertices: int) -> int:
+    return (n_vertices + 31) // 32
+
+
+def grid_active_init(density_m: torch.Tensor, density_v: torch.Tensor, feat_m: torch.Tensor,
+                     feat_v: torch.Tensor, active: torch.Tensor) -> None:
+    """Rewrite the activity mask (int32 words, one bit per vertex) from the
+    given moments: bit set iff any of the vertex's moments is non-zero."""
+    lib = load()
+    nv = density_m.numel()
+    assert active.dtype == torch.int32 and active.numel() >= grid_active_words(nv)
+    check("dvgo_grid_active_init", lib.dvgo_grid_active_init(_ptr(density_m), _ptr(density_v), _ptr(feat_m),
+                                                             _ptr(feat_v), nv, _ptr(active), _stream(active.device)))
+
+
+def _grid_adam(grid: Grid, density_m, density_v, feat_m, feat_v, lr, t, betas, eps, active) -> GridAdam:
+    return GridAdam(_ptr(grid.density), _ptr(density_m), _ptr(density_v), _ptr(grid.feat), _ptr(feat_m),
+                    _ptr(feat_v), _ptr(grid.feat_shadow), float(lr), float(betas[0]), float(betas[1]), float(eps),
+                    int(t), _ptr(active))
+
+
 def render_bwd_adam(grid: Grid, mlp_flat: torch.Tensor, s: Samples, log_t_end: torch.Tensor,
                     grad_rgb: torch.Tensor, density_m: torch.Tensor, density_v: torch.Tensor,
                     feat_m: torch.Tensor, feat_v: torch.Tensor, grad_mlp: torch.Tensor, lr: float, t: int,
                     betas=(0.9, 0.999), eps=1e-8, bg=(1.0, 1.0, 1.0), precision: int = DVGO_F32,
-                    use_shadow: bool = False, grad_depth=None, grad_acc=None) -> None:
+                    use_shadow: bool = False, grad_depth=None, grad_acc=None, active=None) -> None:
     """Adjoint plus the Adam step of both grids (parameters and moments
     updated in place, the bfloat16 feature copy rewritten when the grid has
-    one); accumulates (+=) the network gradient into grad_mlp."""
+    one); accumulates (+=) the network gradient into grad_mlp.  ``active``:
+    the optional per-vertex activity mask (int32 words) that lets the step
+    skip vertices with zero moments and no samples."""
     lib = load()
     dev = s.rays_o.device
     field = grid.field(use_shadow)
     mlp = mlp_struct(mlp_flat, precision)
-    opt = GridAdam(_ptr(grid.density), _ptr(density_m), _ptr(density_v), _ptr(grid.feat), _ptr(feat_m),
-                   _ptr(feat_v), _ptr(grid.feat_shadow), float(lr), float(betas[0]), float(betas[1]), float(eps),
-                   int(t))
+    opt = _grid_adam(grid, density_m, density_v, feat_m, feat_v, lr, t, betas, eps, active)
     nws = lib.dvgo_render_workspace_bytes(s.B, s.capacity, CHANNELS, ctypes.byref(field.box))
     ws = workspace(nws, dev)
     check("dvgo_render_bwd_adam", lib.dvgo_render_bwd_adam(
@@ -300,17 +321,15 @@ def render_bwd_adam(grid: Grid, mlp_flat: torch.Tensor, s: Samples, log_t_end: t
 def train_step(grid: Grid, mlp_flat: torch.Tensor, s: Samples, target: torch.Tensor, density_m: torch.Tensor,
                density_v: torch.Tensor, feat_m: torch.Tensor, feat_v: torch.Tensor, grad_mlp: torch.Tensor,
                lr: float, t: int, betas=(0.9, 0.999), eps=1e-8, bg=(1.0, 1.0, 1.0), precision: int = DVGO_F32,
-               use_shadow: bool = False, want_rgb: bool = True):
+               use_shadow: bool = False, want_rgb: bool = True, active=None):
     """Forward, photometric loss, adjoint and the grids' Adam step in one
     library call; accumulates (+=) the network gradient into grad_mlp.
-    Returns (loss [1], rgb [B,3] or None)."""
+    ``active`` as in render_bwd_adam.  Returns (loss [1], rgb [B,3] or None)."""
     lib = load()
     dev = s.rays_o.device
     field = grid.field(use_shadow)
     mlp = mlp_struct(mlp_flat, precision)
-    opt = GridAdam(_ptr(grid.density), _ptr(density_m), _ptr(density_v), _ptr(grid.feat), _ptr(feat_m),
-                   _ptr(feat_v), _ptr(grid.feat_shadow), float(lr), float(betas[0]), float(betas[1]), float(eps),
-                   int(t))
+    opt = _grid_adam(grid, density_m, density_v, feat_m, feat_v, lr, t, betas, eps, active)
     rgb = torch.empty((s.B, 3), dtype=torch.float32, device=dev) if want_rgb else None
     loss = torch.empty(1, dtype=torch.float32, device=dev)
     nws = lib.dvgo_render_workspace_bytes(s.B, s.capacity, CHANNELS, ctypes.byref(field.box))

@@ -606,6 +606,7 @@ struct GridAdamArgs {
     float* mf;
     float* vf;
     uint16_t* shadow;
+    uint32_t* active;   // per-vertex bit: moments may be non-zero (NULL: every vertex steps)
     dvgo::AdamCoef c;
 };
 
@@ -616,6 +617,12 @@ struct GridAdamArgs {
 // walked in wave-contiguous float4 chunks (the 64 vertices of a wave own
 // 768 consecutive values): the wave's gradients go through LDS so that every
 // load and store of p, m, v and the copy covers whole cache lines.
+//
+// With an activity mask, a vertex whose bit is clear (both moments zero)
+// and that no sample touches is skipped: its step would compute m = v = 0
+// and p - lr * 0 / (0 + eps) = p, so skipping it changes no bit, and its
+// parameters and moments are neither read nor written.  A vertex that takes
+// a step with any non-zero gradient gets its bit set.
 __global__ __launch_bounds__(256) void vertex_adam_kernel(BinArgs a, GridAdamArgs o) {
     __shared__ float4 sg[4][64 * 3];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -630,7 +637,8 @@ __global__ __launch_bounds__(256) void vertex_adam_kernel(BinArgs a, GridAdamArg
     // Workgroups are dealt to the 8 XCDs round robin (block b on XCD b % 8):
     // give each XCD one contiguous eighth of the vertices, so the cell starts
     // and sample records that neighbouring vertices share stay in that XCD's
-    // L2.  gridDim.x is a multiple of 8.
+    // L2.  gridDim.x is a multiple of 8; every wave's first vertex is a
+    // multiple of 64, so a wave owns two whole words of the activity mask.
     const int xcd = blockIdx.x & 7, nloc = gridDim.x >> 3, loc = blockIdx.x >> 3;
     const int64_t span = (nv + 8 * 256 - 1) / (8 * 256) * 256;
     const int64_t lo = xcd * span, hi = lo + span < nv ? lo + span : nv;
@@ -639,10 +647,14 @@ __global__ __launch_bounds__(256) void vertex_adam_kernel(BinArgs a, GridAdamArg
         const int64_t v = base + threadIdx.x;
         const int64_t vbase = base + 64 * wave;
         const int64_t nwave = hi - vbase < 64 ? hi - vbase : 64;   // vertices of this wave (may be <= 0)
-        // issue the parameter streams first: they do not depend on the
-        // gradient and overlap the latency of the sample gather below
+        const bool in = v < hi;
+        const bool was_active = in && (!o.active || ((o.active[v >> 5] >> (v & 31)) & 1u));
+        // issue the parameter streams of the active vertices first: they do
+        // not depend on the gradient and overlap the latency of the sample
+        // gather below
+        const uint64_t act_mask = __ballot(was_active);
         float p = 0.0f, m = 0.0f, w = 0.0f;
-        if (v < hi) {
+        if (was_active) {
             p = __builtin_nontemporal_load(o.pd + v);
             m = __builtin_nontemporal_load(o.md + v);
             w = __builtin_nontemporal_load(o.vd + v);
@@ -651,7 +663,7 @@ __global__ __launch_bounds__(256) void vertex_adam_kernel(BinArgs a, GridAdamArg
         #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const int c = 64 * q + lane;
-            if (c < 3 * nwave) {
+            if (c < 3 * nwave && ((act_mask >> (c / 3)) & 1u)) {
                 const int64_t gi = 3 * vbase + c;
                 pq[q] = __builtin_nontemporal_load(P + gi);
                 mq[q] = __builtin_nontemporal_load(M + gi);
@@ -661,13 +673,35 @@ __global__ __launch_bounds__(256) void vertex_adam_kernel(BinArgs a, GridAdamArg
         float acc[13];
         #pragma unroll
         for (int q = 0; q < 13; ++q) acc[q] = 0.0f;
-        if (v < hi) {
-            if (a.cell_start) {   // else no samples in the batch
-                const int k = static_cast<int>(v % nz);
-                const int j = static_cast<int>((v / nz) % ny);
-                const int i = static_cast<int>(v / (static_cast<int64_t>(nz) * ny));
-                vertex_grad(a, i, j, k, true, acc);
+        bool touched = false;
+        if (in && a.cell_start) {   // else no samples in the batch
+            const int k = static_cast<int>(v % nz);
+            const int j = static_cast<int>((v / nz) % ny);
+            const int i = static_cast<int>(v / (static_cast<int64_t>(nz) * ny));
+            touched = vertex_grad(a, i, j, k, true, acc);
+        }
+        // vertices newly reached by a sample: their streams now
+        const bool need = was_active || touched;
+        const uint64_t need_mask = __ballot(need);
+        const uint64_t late_mask = need_mask & ~act_mask;
+        if (need && !was_active) {
+            p = __builtin_nontemporal_load(o.pd + v);
+            m = __builtin_nontemporal_load(o.md + v);
+            w = __builtin_nontemporal_load(o.vd + v);
+        }
+        if (late_mask) {
+            #pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int c = 64 * q + lane;
+                if (c < 3 * nwave && ((late_mask >> (c / 3)) & 1u)) {
+                    const int64_t gi = 3 * vbase + c;
+                    pq[q] = __builtin_nontemporal_load(P + gi);
+                    mq[q] = __builtin_nontemporal_load(M + gi);
+                    vq[q] = __builtin_nontemporal_load(V + gi);
+                }
             }
+        }
+        if (need) {
             dvgo::adam_update(o.c, p, acc[0], m, w);
             __builtin_nontemporal_store(p, o.pd + v);
             __builtin_nontemporal_store(m, o.md + v);
@@ -680,7 +714,7 @@ __global__ __launch_bounds__(256) void vertex_adam_kernel(BinArgs a, GridAdamArg
         #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const int c = 64 * q + lane;
-            if (c < 3 * nwave) {
+            if (c < 3 * nwave && ((need_mask >> (c / 3)) & 1u)) {
                 const int64_t gi = 3 * vbase + c;
                 const float4 g = sg[wave][c];
                 const float gg[4] = {g.x, g.y, g.z, g.w};
@@ -704,7 +738,43 @@ __global__ __launch_bounds__(256) void vertex_adam_kernel(BinArgs a, GridAdamArg
                 }
             }
         }
+        if (o.active) {
+            bool nonzero = false;
+            #pragma unroll
+            for (int q = 0; q < 13; ++q) nonzero |= acc[q] != 0.0f;
+            const uint64_t now = __ballot(was_active || (touched && nonzero));
+            if (lane == 0 && nwave > 0) o.active[vbase >> 5] = static_cast<uint32_t>(now);
+            if (lane == 1 && nwave > 32) o.active[(vbase >> 5) + 1] = static_cast<uint32_t>(now >> 32);
+        }
         __syncthreads();
+    }
+}
+
+// Activity mask from given moments: bit v set iff any of vertex v's 26
+// moments (density and 12 features, m and v) is non-zero.  Each wave covers
+// 64 consecutive vertices, two whole words.
+__global__ __launch_bounds__(256) void grid_active_kernel(const float* __restrict__ md, const float* __restrict__ vd,
+                                                          const float* __restrict__ mf, const float* __restrict__ vf,
+                                                          int64_t nv, uint32_t* __restrict__ active) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t v0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + (threadIdx.x & ~63); v0 < nv;
+         v0 += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t v = v0 + lane;
+        bool nz = false;
+        if (v < nv) {
+            nz = md[v] != 0.0f || vd[v] != 0.0f;
+            const float4* a = reinterpret_cast<const float4*>(mf + v * kC);
+            const float4* b = reinterpret_cast<const float4*>(vf + v * kC);
+            #pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const float4 x = a[q], y = b[q];
+                nz |= x.x != 0.0f || x.y != 0.0f || x.z != 0.0f || x.w != 0.0f;
+                nz |= y.x != 0.0f || y.y != 0.0f || y.z != 0.0f || y.w != 0.0f;
+            }
+        }
+        const uint64_t bits = __ballot(nz);
+        if (lane == 0) active[v0 >> 5] = static_cast<uint32_t>(bits);
+        if (lane == 1 && v0 + 32 < nv) active[(v0 >> 5) + 1] = static_cast<uint32_t>(bits >> 32);
     }
 }
 
@@ -867,6 +937,28 @@ int grid_for(int64_t work, int per_block, int max_blocks) {
     if (b < 1) b = 1;
     if (b > max_blocks) b = max_blocks;
     return static_cast<int>(b);
+}
+
+// Host-side checks of a dvgo_grid_adam and its kernel arguments.
+int32_t grid_adam_args(const dvgo_grid_adam* opt, GridAdamArgs* o) {
+    if (!opt->density || !opt->density_m || !opt->density_v || !opt->feat || !opt->feat_m || !opt->feat_v)
+        return DVGO_E_ARG;
+    if (!dvgo::adam_hyper_ok(opt->beta1, opt->beta2, opt->eps, opt->t)) return DVGO_E_ARG;
+    auto al16 = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
+    if (!al16(opt->feat) || !al16(opt->feat_m) || !al16(opt->feat_v) ||
+        (opt->feat_shadow_bf16 && (reinterpret_cast<uintptr_t>(opt->feat_shadow_bf16) & 7u) != 0) ||
+        (opt->active && (reinterpret_cast<uintptr_t>(opt->active) & 3u) != 0))
+        return DVGO_E_ARG;
+    o->pd = opt->density;
+    o->md = opt->density_m;
+    o->vd = opt->density_v;
+    o->pf = opt->feat;
+    o->mf = opt->feat_m;
+    o->vf = opt->feat_v;
+    o->shadow = opt->feat_shadow_bf16;
+    o->active = opt->active;
+    o->c = dvgo::adam_coef(opt->lr, opt->beta1, opt->beta2, opt->eps, opt->t);
+    return DVGO_OK;
 }
 
 // Workgroups of the fused grid Adam: a multiple of 8 (one share per XCD),
@@ -1198,6 +1290,22 @@ int32_t dvgo_render_bwd(const dvgo_field* field, const dvgo_mlp* mlp, const floa
                            grad_density, grad_feat, nullptr, grad_mlp, workspace, workspace_bytes, stream);
 }
 
+int32_t dvgo_grid_active_init(const float* density_m, const float* density_v, const float* feat_m,
+                              const float* feat_v, int64_t n_vertices, uint32_t* active, void* stream) {
+    if (n_vertices < 0) return DVGO_E_ARG;
+    if (n_vertices == 0) return DVGO_OK;
+    if (!density_m || !density_v || !feat_m || !feat_v || !active) return DVGO_E_ARG;
+    if ((reinterpret_cast<uintptr_t>(feat_m) & 15u) || (reinterpret_cast<uintptr_t>(feat_v) & 15u) ||
+        (reinterpret_cast<uintptr_t>(active) & 3u))
+        return DVGO_E_ARG;
+    const int64_t want = (n_vertices + 255) / 256;
+    const int64_t cap = static_cast<int64_t>(dvgo::device_cu_count()) * 8;
+    const int blocks = static_cast<int>(want < cap ? want : cap);
+    DVGO_LAUNCH(K_GRID_ACTIVE, grid_active_kernel, dim3(blocks), dim3(256), 0, dvgo::as_stream(stream), density_m,
+                density_v, feat_m, feat_v, n_vertices, active);
+    return dvgo::launch_status();
+}
+
 int32_t dvgo_render_bwd_adam(const dvgo_field* field, const dvgo_mlp* mlp, const float* rays_o,
                              const float* rays_d, const float* jitter, const float* t_near, const int32_t* n_uniform,
                              const int32_t* perm, const int32_t* ray_offset, const int32_t* sample_ray,
@@ -1206,22 +1314,8 @@ int32_t dvgo_render_bwd_adam(const dvgo_field* field, const dvgo_mlp* mlp, const
                              const float* grad_acc, const dvgo_grid_adam* opt, float* grad_mlp, void* workspace,
                              size_t workspace_bytes, void* stream) {
     if (!opt || !field) return DVGO_E_ARG;
-    if (!opt->density || !opt->density_m || !opt->density_v || !opt->feat || !opt->feat_m || !opt->feat_v)
-        return DVGO_E_ARG;
-    if (!dvgo::adam_hyper_ok(opt->beta1, opt->beta2, opt->eps, opt->t)) return DVGO_E_ARG;
-    auto al16 = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
-    if (!al16(opt->feat) || !al16(opt->feat_m) || !al16(opt->feat_v) ||
-        (opt->feat_shadow_bf16 && (reinterpret_cast<uintptr_t>(opt->feat_shadow_bf16) & 7u) != 0))
-        return DVGO_E_ARG;
     GridAdamArgs o;
-    o.pd = opt->density;
-    o.md = opt->density_m;
-    o.vd = opt->density_v;
-    o.pf = opt->feat;
-    o.mf = opt->feat_m;
-    o.vf = opt->feat_v;
-    o.shadow = opt->feat_shadow_bf16;
-    o.c = dvgo::adam_coef(opt->lr, opt->beta1, opt->beta2, opt->eps, opt->t);
+    if (int32_t st = grid_adam_args(opt, &o)) return st;
     return render_bwd_impl(field, mlp, rays_o, rays_d, jitter, t_near, n_uniform, perm, ray_offset, sample_ray,
                            sample_k, n_kept, capacity, B, step, bg, log_t_end, grad_rgb, grad_depth, grad_acc, nullptr,
                            nullptr, &o, grad_mlp, workspace, workspace_bytes, stream);
@@ -1252,13 +1346,8 @@ int32_t dvgo_train_step(const dvgo_field* field, const dvgo_mlp* mlp, const floa
                                     sample_ray, sample_k, n_kept, capacity, B, step, bg, logt_w, grad_w, nullptr,
                                     nullptr, opt, grad_mlp, workspace, workspace_bytes, stream);
     }
-    if (!opt->density || !opt->density_m || !opt->density_v || !opt->feat || !opt->feat_m || !opt->feat_v)
-        return DVGO_E_ARG;
-    if (!dvgo::adam_hyper_ok(opt->beta1, opt->beta2, opt->eps, opt->t)) return DVGO_E_ARG;
-    auto al16 = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
-    if (!al16(opt->feat) || !al16(opt->feat_m) || !al16(opt->feat_v) ||
-        (opt->feat_shadow_bf16 && (reinterpret_cast<uintptr_t>(opt->feat_shadow_bf16) & 7u) != 0))
-        return DVGO_E_ARG;
+    GridAdamArgs o;
+    if (int32_t st = grid_adam_args(opt, &o)) return st;
     hipStream_t s = dvgo::as_stream(stream);
     // forward: prep (also clears the cell counts), gather, network, compositing
     Common cm = make_common(field, rays_o, rays_d, jitter, t_near, sample_ray, sample_k, capacity, B, step,
@@ -1279,15 +1368,6 @@ int32_t dvgo_train_step(const dvgo_field* field, const dvgo_mlp* mlp, const floa
     DVGO_LAUNCH(K_COMPOSE_FWD, compose_fwd_kernel, dim3((B + 3) / 4), dim3(256), 0, s, ca);
     if (int32_t st = dvgo::launch_status()) return st;
     // adjoint and Adam, reusing the forward's gathered features, colours and prep
-    GridAdamArgs o;
-    o.pd = opt->density;
-    o.md = opt->density_m;
-    o.vd = opt->density_v;
-    o.pf = opt->feat;
-    o.mf = opt->feat_m;
-    o.vf = opt->feat_v;
-    o.shadow = opt->feat_shadow_bf16;
-    o.c = dvgo::adam_coef(opt->lr, opt->beta1, opt->beta2, opt->eps, opt->t);
     return render_bwd_impl(field, mlp, rays_o, rays_d, jitter, t_near, n_uniform, perm, ray_offset, sample_ray,
                            sample_k, n_kept, capacity, B, step, bg, logt_w, grad_w, nullptr, nullptr, nullptr,
                            nullptr, &o, grad_mlp, workspace, workspace_bytes, stream, true, sq_w, loss);

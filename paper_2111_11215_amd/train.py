@@ -52,6 +52,8 @@ class FineConfig:
     capacity: Optional[int] = None
     fused_grid_adam: bool = True     # the whole step in one call (dvgo_train_step): no grid gradient in
                                      # memory, the adjoint reuses the forward's gathers and colours
+    skip_idle: bool = True           # the fused grid Adam skips vertices with zero moments that no sample
+                                     # touches (their step changes no bit), tracked by an activity mask
 
 
 class FineModel:
@@ -67,6 +69,11 @@ class FineModel:
         self.st_feat = AdamState.of(feat, shadow=cfg.bf16_feat)
         self.st_mlp = AdamState.of(mlp_flat)
         self.grid.feat_shadow = self.st_feat.shadow
+        # one bit per vertex: its moments may be non-zero (all clear with the zero moments above)
+        self.active = None
+        if cfg.fused_grid_adam and cfg.skip_idle:
+            self.active = torch.zeros(api.grid_active_words(density.numel()), dtype=torch.int32,
+                                      device=density.device)
         self.t = 0
 
     def lr(self, base: float) -> float:
@@ -93,6 +100,9 @@ class FineModel:
         lg, lm = self.lr(c.lr_grid), self.lr(c.lr_mlp)
         for st, lr in ((self.st_density, lg), (self.st_feat, lg), (self.st_mlp, lm)):
             api.adam_step(st.p, st.g, st.m, st.v, lr, self.t, c.betas, c.eps, shadow=st.shadow)
+        if self.active is not None:   # dense steps moved moments the mask does not know of
+            d, f = self.st_density, self.st_feat
+            api.grid_active_init(d.m, d.v, f.m, f.v, self.active)
 
     def backward_adam(self, s: api.Samples, out: dict, grad_rgb: torch.Tensor) -> None:
         """Adjoint with the grids' Adam step fused in, then the network's
@@ -102,7 +112,8 @@ class FineModel:
         lg, lm = self.lr(c.lr_grid), self.lr(c.lr_mlp)
         d, f = self.st_density, self.st_feat
         api.render_bwd_adam(self.grid, self.mlp, s, out["log_t_end"], grad_rgb, d.m, d.v, f.m, f.v, self.st_mlp.g,
-                            lg, self.t, c.betas, c.eps, c.bg, precision=c.precision, use_shadow=c.bf16_feat)
+                            lg, self.t, c.betas, c.eps, c.bg, precision=c.precision, use_shadow=c.bf16_feat,
+                            active=self.active)
         m = self.st_mlp
         api.adam_step(m.p, m.g, m.m, m.v, lm, self.t, c.betas, c.eps)
 
@@ -116,7 +127,8 @@ class FineModel:
             lg, lm = self.lr(c.lr_grid), self.lr(c.lr_mlp)
             d, f, m = self.st_density, self.st_feat, self.st_mlp
             loss, rgb = api.train_step(self.grid, self.mlp, s, target, d.m, d.v, f.m, f.v, m.g, lg, self.t, c.betas,
-                                       c.eps, c.bg, precision=c.precision, use_shadow=c.bf16_feat)
+                                       c.eps, c.bg, precision=c.precision, use_shadow=c.bf16_feat,
+                                       active=self.active)
             api.adam_step(m.p, m.g, m.m, m.v, lm, self.t, c.betas, c.eps)
             return {"loss": loss, "samples": s, "rgb": rgb}
         out = self.render(s, want_depth_acc=False)

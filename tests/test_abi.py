@@ -119,6 +119,17 @@ def test_host_validation_rejects_before_launch(lib):
     assert lib.dvgo_render_bwd_adam(ctypes.byref(f), ctypes.byref(m), *bargs, ctypes.byref(ga), fake, fake, 1 << 30,
                                     nul) == -1
     ga.feat = 16
+    ga.active = 18   # activity mask not 4-byte aligned
+    assert lib.dvgo_render_bwd_adam(ctypes.byref(f), ctypes.byref(m), *bargs, ctypes.byref(ga), fake, fake, 1 << 30,
+                                    nul) == -1
+    ga.active = None
     f.channels = 11
     assert lib.dvgo_render_bwd_adam(ctypes.byref(f), ctypes.byref(m), *bargs, ctypes.byref(ga), fake, fake, 1 << 30,
                                     nul) == -2
+    # activity mask from moments: negative count, missing or misaligned
+    # pointers; an empty grid is a no-op
+    assert lib.dvgo_grid_active_init(fake, fake, fake, fake, -1, fake, nul) == -1
+    assert lib.dvgo_grid_active_init(fake, fake, None, fake, 10, fake, nul) == -1
+    assert lib.dvgo_grid_active_init(fake, fake, 20, fake, 10, fake, nul) == -1
+    assert lib.dvgo_grid_active_init(fake, fake, fake, fake, 10, 18, nul) == -1
+    assert lib.dvgo_grid_active_init(None, None, None, None, 0, None, nul) == 0

@@ -137,3 +137,72 @@ def test_train_step_equals_separate_calls(gpu_lib, bf16):
         assert report(name, np_of(b), np_of(a))[0] <= 1e-5, name
     if bf16:
         assert np.array_equal(np_of(gb.feat_shadow).view(np.uint16), _bf16_bits(np_of(gb.feat)))
+
+
+def _mask_np(mD, vD, mF, vF):
+    """Activity bits written out from their definition: any non-zero moment."""
+    nz = (mD.reshape(-1) != 0) | (vD.reshape(-1) != 0)
+    nz |= (mF.reshape(nz.size, -1) != 0).any(1) | (vF.reshape(nz.size, -1) != 0).any(1)
+    words = np.zeros((nz.size + 31) // 32, np.uint32)
+    idx = np.nonzero(nz)[0]
+    np.bitwise_or.at(words, idx // 32, (np.uint32(1) << (idx % 32).astype(np.uint32)))
+    return words
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_activity_mask_skips_idle_vertices_exactly(gpu_lib, bf16):
+    """The fused grid Adam with an activity mask against the same call
+    without one (every vertex steps) over two consecutive steps, from
+    moments that are non-zero on a random 30 % of the vertices only: vertices
+    with zero moments that no sample touches keep their parameters, moments
+    and bf16 copy bit for bit in both; every other value agrees to the
+    summation order of the grid gradients (1e-6 normwise); the mask from
+    dvgo_grid_active_init equals its definition, and after each step every
+    vertex with a non-zero moment has its bit set."""
+    import torch
+    from paper_2111_11215_amd import api
+    from paper_2111_11215_amd._lib import DVGO_BF16, DVGO_F32
+    prec = DVGO_BF16 if bf16 else DVGO_F32
+    P = _problem(12, n_rays=512, bias=0.3)
+    grid, flat, s = _gpu(P, bf16=bf16)
+    rng = np.random.default_rng(21)
+    nv = P.density.size
+    keep = rng.random(nv) < 0.3
+    mD, vD = _state(rng, P.density.shape)
+    mF, vF = _state(rng, P.feat.shape)
+    kd = to_dev(keep.reshape(P.density.shape).astype(F32))
+    mD, vD, mF, vF = mD * kd, vD * kd, mF * kd[..., None], vF * kd[..., None]
+    active = torch.zeros(api.grid_active_words(nv), dtype=torch.int32, device="cuda")
+    api.grid_active_init(mD, vD, mF, vF, active)
+    assert np.array_equal(np_of(active).view(np.uint32), _mask_np(np_of(mD), np_of(vD), np_of(mF), np_of(vF)))
+    out = api.render_fwd(grid, flat, s, P.bg, precision=prec, use_shadow=bf16)
+    g = to_dev((rng.normal(size=(P.rays.o.shape[0], 3)) * 1e-3).astype(F32))
+
+    ga, gb = _clone_grid(api, grid), _clone_grid(api, grid)
+    sa = [x.clone() for x in (mD, vD, mF, vF)]
+    sb = [x.clone() for x in (mD, vD, mF, vF)]
+    for t in (5, 6):
+        api.render_bwd_adam(ga, flat, s, out["log_t_end"], g, *sa, torch.zeros_like(flat), 0.1, t, bg=P.bg,
+                            precision=prec, use_shadow=bf16)
+        api.render_bwd_adam(gb, flat, s, out["log_t_end"], g, *sb, torch.zeros_like(flat), 0.1, t, bg=P.bg,
+                            precision=prec, use_shadow=bf16, active=active)
+        bits = np_of(active).view(np.uint32)
+        need = _mask_np(*(np_of(x) for x in sb))
+        assert np.array_equal(need & ~bits, np.zeros_like(need)), "a vertex with non-zero moments lost its bit"
+    idle = np.ones(nv, bool)
+    for x in sa:
+        idle &= (np_of(x).reshape(nv, -1) == 0).all(1)
+    print(f"  idle vertices after two steps: {idle.mean():.3f}", flush=True)
+    assert 0.2 < idle.mean() < 0.95
+    pairs = [("density", grid.density, ga.density, gb.density), ("feat", grid.feat, ga.feat, gb.feat)]
+    for name, p0, pa, pb in pairs:
+        a, b, z = np_of(pa).reshape(nv, -1), np_of(pb).reshape(nv, -1), np_of(p0).reshape(nv, -1)
+        assert np.array_equal(a[idle], z[idle]) and np.array_equal(b[idle], z[idle]), name
+        assert report(f"{name} update", (b - z), (a - z))[0] <= 1e-6, name
+    for name, a, b in zip(("m density", "v density", "m feat", "v feat"), sa, sb):
+        assert report(name, np_of(b), np_of(a))[0] <= 1e-6, name
+        assert np.all(np_of(b).reshape(nv, -1)[idle] == 0), name
+    if bf16:
+        assert np.array_equal(np_of(gb.feat_shadow).view(np.uint16), _bf16_bits(np_of(gb.feat)))
+        assert np.array_equal(np_of(gb.feat_shadow).view(np.uint16), np_of(ga.feat_shadow).view(np.uint16)) or \
+            report("shadow", np_of(gb.feat), np_of(ga.feat))[0] <= 1e-6
