@@ -540,32 +540,42 @@ __global__ __launch_bounds__(256) void bin_place_kernel(BinArgs a) {
 // Gradient of one vertex (i,j,k): it is corner (dx,dy,dz) of cell
 // (i-dx, j-dy, k-dz); the samples binned in those cells are summed with the
 // vertex's trilinear weight.  acc[0] density, acc[1..12] features.  Returns
-// whether any sample touches the vertex.
+// whether any sample touches the vertex.  For each (dx, dy) the cells k-1
+// (dz = 1) and k (dz = 0) are neighbours in the cell order, so their records
+// form one run, split at the start of cell k; the run is walked two records
+// at a time so that two records' loads are in flight together.
+__device__ __forceinline__ void add_record(const float4* r, int dx, int dy, int dz, bool feat, float acc[13]) {
+    const float4 h = r[0];
+    const float w = (dx ? h.x : 1.0f - h.x) * (dy ? h.y : 1.0f - h.y) * (dz ? h.z : 1.0f - h.z);
+    acc[0] += w * h.w;
+    if (feat) {
+        const float4 q0 = r[1], q1 = r[2], q2 = r[3];
+        acc[1] += w * q0.x; acc[2] += w * q0.y; acc[3] += w * q0.z; acc[4] += w * q0.w;
+        acc[5] += w * q1.x; acc[6] += w * q1.y; acc[7] += w * q1.z; acc[8] += w * q1.w;
+        acc[9] += w * q2.x; acc[10] += w * q2.y; acc[11] += w * q2.z; acc[12] += w * q2.w;
+    }
+}
+
 __device__ __forceinline__ bool vertex_grad(const BinArgs& a, int i, int j, int k, bool feat, float acc[13]) {
     const int nx = a.g.n[0], cy = a.g.n[1] - 1, cz = a.g.n[2] - 1;
     #pragma unroll
     for (int q = 0; q < 13; ++q) acc[q] = 0.0f;
     bool any = false;
     #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        const int dx = (c >> 2) & 1, dy = (c >> 1) & 1, dz = c & 1;
-        const int ci = i - dx, cj = j - dy, ck = k - dz;
-        if (ci < 0 || cj < 0 || ck < 0 || ci >= nx - 1 || cj >= cy || ck >= cz) continue;
-        const int cell = (ci * cy + cj) * cz + ck;
-        const int p0 = a.cell_start[cell], p1 = a.cell_start[cell + 1];
-        for (int p = p0; p < p1; ++p) {
-            const float4* r = a.rec + static_cast<int64_t>(p) * 4;
-            const float4 h = r[0];
-            const float w = (dx ? h.x : 1.0f - h.x) * (dy ? h.y : 1.0f - h.y) * (dz ? h.z : 1.0f - h.z);
-            acc[0] += w * h.w;
-            if (feat) {
-                const float4 q0 = r[1], q1 = r[2], q2 = r[3];
-                acc[1] += w * q0.x; acc[2] += w * q0.y; acc[3] += w * q0.z; acc[4] += w * q0.w;
-                acc[5] += w * q1.x; acc[6] += w * q1.y; acc[7] += w * q1.z; acc[8] += w * q1.w;
-                acc[9] += w * q2.x; acc[10] += w * q2.y; acc[11] += w * q2.z; acc[12] += w * q2.w;
-            }
-            any = true;
+    for (int c = 0; c < 4; ++c) {
+        const int dx = (c >> 1) & 1, dy = c & 1;
+        const int ci = i - dx, cj = j - dy;
+        if (ci < 0 || cj < 0 || ci >= nx - 1 || cj >= cy) continue;
+        const int row = (ci * cy + cj) * cz;
+        const int klo = k > 0 ? k - 1 : 0, khi = k < cz ? k + 1 : cz;   // cells k-1 and k, where they exist
+        const int p0 = a.cell_start[row + klo], pm = a.cell_start[row + k], p1 = a.cell_start[row + khi];
+        int p = p0;
+        for (; p + 1 < p1; p += 2) {
+            add_record(a.rec + static_cast<int64_t>(p) * 4, dx, dy, p < pm, feat, acc);
+            add_record(a.rec + static_cast<int64_t>(p + 1) * 4, dx, dy, p + 1 < pm, feat, acc);
         }
+        if (p < p1) add_record(a.rec + static_cast<int64_t>(p) * 4, dx, dy, p < pm, feat, acc);
+        any |= p1 > p0;
     }
     return any;
 }
@@ -634,16 +644,23 @@ __global__ __launch_bounds__(256) void vertex_adam_kernel(BinArgs a, GridAdamArg
     f4* M = reinterpret_cast<f4*>(o.mf);
     f4* V = reinterpret_cast<f4*>(o.vf);
     u2* S = reinterpret_cast<u2*>(o.shadow);
-    // Workgroups are dealt to the 8 XCDs round robin (block b on XCD b % 8):
-    // give each XCD one contiguous eighth of the vertices, so the cell starts
-    // and sample records that neighbouring vertices share stay in that XCD's
-    // L2.  gridDim.x is a multiple of 8; every wave's first vertex is a
+    // Workgroups are dealt to the 8 XCDs round robin (block b on XCD b % 8).
+    // The vertices are cut into chunks of kChunk, dealt to the XCDs round
+    // robin as well: within a chunk neighbouring vertices share cell starts
+    // and sample records in one XCD's L2, and every XCD gets an even share of
+    // the grid's busy middle (its vertices with moments and samples) and of
+    // its idle rim.  The blocks of an XCD walk its chunks in 256-vertex
+    // steps.  gridDim.x is a multiple of 8; every wave's first vertex is a
     // multiple of 64, so a wave owns two whole words of the activity mask.
+    constexpr int64_t kChunk = 4096;
     const int xcd = blockIdx.x & 7, nloc = gridDim.x >> 3, loc = blockIdx.x >> 3;
-    const int64_t span = (nv + 8 * 256 - 1) / (8 * 256) * 256;
-    const int64_t lo = xcd * span, hi = lo + span < nv ? lo + span : nv;
-    for (int64_t base = lo + static_cast<int64_t>(loc) * blockDim.x; base < hi;
-         base += static_cast<int64_t>(nloc) * blockDim.x) {
+    const int64_t nchunk = (nv + kChunk - 1) / kChunk;
+    const int64_t mine = nchunk > xcd ? (nchunk - xcd + 7) / 8 : 0;   // chunks of this XCD
+    const int64_t hi = nv;
+    for (int64_t l = static_cast<int64_t>(loc) * blockDim.x; l < mine * kChunk;
+         l += static_cast<int64_t>(nloc) * blockDim.x) {
+        const int64_t base = ((l / kChunk) * 8 + xcd) * kChunk + l % kChunk;   // increases with l
+        if (base >= hi) break;
         const int64_t v = base + threadIdx.x;
         const int64_t vbase = base + 64 * wave;
         const int64_t nwave = hi - vbase < 64 ? hi - vbase : 64;   // vertices of this wave (may be <= 0)
