@@ -277,6 +277,18 @@ int32_t dvgo_render_bwd_adam(const dvgo_field* field /*host*/, const dvgo_mlp* m
                              const dvgo_grid_adam* opt /*host*/, float* grad_mlp,
                              void* workspace, size_t workspace_bytes, void* stream);
 
+/* Adam state of a flat float32 parameter array for dvgo_train_step's fused
+ * network step: param, m, v [n] device pointers (n = dvgo_mlp_param_count),
+ * param in the flat layout of the network gradient; lr, beta1, beta2, eps
+ * and t >= 1 as in dvgo_adam_step. */
+typedef struct {
+    float* param;
+    float* m;
+    float* v;
+    float lr, beta1, beta2, eps;
+    int32_t t;
+} dvgo_adam_state;
+
 /* One whole training step of the fine stage in one call: dvgo_render_fwd
  * (colour and log T_end only), dvgo_photo_loss against target [B][3]
  * (Eq. photo_loss), and dvgo_render_bwd_adam, with the same result.  Inside
@@ -288,8 +300,13 @@ int32_t dvgo_render_bwd_adam(const dvgo_field* field /*host*/, const dvgo_mlp* m
  * (its gradient is formed inside the compositing, bit-identical to
  * dvgo_photo_loss's; the loss sum itself runs in another fixed order);
  * the grids take their Adam step through opt and the network gradient is
- * accumulated into grad_mlp (its Adam step is the caller's dvgo_adam_step).
- * Same arguments, workspace and errors as the separate calls. */
+ * accumulated into grad_mlp.  With mlp_opt NULL the network's Adam step is
+ * the caller's dvgo_adam_step; otherwise the call also takes it, with the
+ * same result bit for bit as dvgo_adam_step(mlp_opt->param, grad_mlp,
+ * mlp_opt->m, mlp_opt->v, NULL, n, ...) after the accumulation (grad_mlp is
+ * left zero).  The network weights that mlp points at must be
+ * mlp_opt->param's (every read of them ends before the update within the
+ * call).  Same arguments, workspace and errors as the separate calls. */
 int32_t dvgo_train_step(const dvgo_field* field /*host*/, const dvgo_mlp* mlp /*host*/,
                         const float* rays_o, const float* rays_d, const float* jitter,
                         const float* t_near, const int32_t* n_uniform, const int32_t* perm,
@@ -298,6 +315,7 @@ int32_t dvgo_train_step(const dvgo_field* field /*host*/, const dvgo_mlp* mlp /*
                         int32_t B, float step, const float* bg /*host[3]*/,
                         const float* target, float* rgb, float* loss,
                         const dvgo_grid_adam* opt /*host*/, float* grad_mlp,
+                        const dvgo_adam_state* mlp_opt /*host or NULL*/,
                         void* workspace, size_t workspace_bytes, void* stream);
 
 /* Photometric loss of paper Eq. photo_loss: loss = (1/B) sum_r

@@ -44,6 +44,11 @@ class GridAdam(ctypes.Structure):
                 ("beta1", c_float), ("beta2", c_float), ("eps", c_float), ("t", c_int32), ("active", c_void_p)]
 
 
+class AdamState(ctypes.Structure):
+    _fields_ = [("param", c_void_p), ("m", c_void_p), ("v", c_void_p), ("lr", c_float), ("beta1", c_float),
+                ("beta2", c_float), ("eps", c_float), ("t", c_int32)]
+
+
 class DvgoError(RuntimeError):
     def __init__(self, fn: str, status: int, text: str, last: str):
         super().__init__(f"{fn} returned {STATUS.get(status, status)} ({text}) {last}".strip())
@@ -67,7 +72,8 @@ SIGNATURES = {
     "dvgo_render_bwd_adam": (c_int32, [POINTER(Field), POINTER(Mlp), P, P, P, P, P, P, P, P, P, P, c_int64, c_int32,
                                        c_float, POINTER(c_float), P, P, P, P, POINTER(GridAdam), P, P, c_size_t, P]),
     "dvgo_train_step": (c_int32, [POINTER(Field), POINTER(Mlp), P, P, P, P, P, P, P, P, P, P, c_int64, c_int32,
-                                  c_float, POINTER(c_float), P, P, P, POINTER(GridAdam), P, P, c_size_t, P]),
+                                  c_float, POINTER(c_float), P, P, P, POINTER(GridAdam), P, POINTER(AdamState), P,
+                                  c_size_t, P]),
     "dvgo_photo_loss": (c_int32, [P, P, c_int32, P, P, P]),
     "dvgo_adam_step": (c_int32, [P, P, P, P, P, c_int64, c_float, c_float, c_float, c_float, c_int32, P]),
     "dvgo_grid_active_init": (c_int32, [P, P, P, P, c_int64, P, P]),

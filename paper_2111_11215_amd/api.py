@@ -16,7 +16,7 @@ from typing import Optional
 import torch
 
 from . import _lib
-from ._lib import DVGO_BF16, DVGO_F32, Box, Field, GridAdam, Mlp, Prop, check, load, make_box
+from ._lib import DVGO_BF16, DVGO_F32, AdamState, Box, Field, GridAdam, Mlp, Prop, check, load, make_box
 
 NSEG = 32
 HIDDEN = 128
@@ -321,15 +321,23 @@ def render_bwd_adam(grid: Grid, mlp_flat: torch.Tensor, s: Samples, log_t_end: t
 def train_step(grid: Grid, mlp_flat: torch.Tensor, s: Samples, target: torch.Tensor, density_m: torch.Tensor,
                density_v: torch.Tensor, feat_m: torch.Tensor, feat_v: torch.Tensor, grad_mlp: torch.Tensor,
                lr: float, t: int, betas=(0.9, 0.999), eps=1e-8, bg=(1.0, 1.0, 1.0), precision: int = DVGO_F32,
-               use_shadow: bool = False, want_rgb: bool = True, active=None):
+               use_shadow: bool = False, want_rgb: bool = True, active=None, mlp_adam=None):
     """Forward, photometric loss, adjoint and the grids' Adam step in one
     library call; accumulates (+=) the network gradient into grad_mlp.
-    ``active`` as in render_bwd_adam.  Returns (loss [1], rgb [B,3] or None)."""
+    ``active`` as in render_bwd_adam.  ``mlp_adam`` = (m, v, lr): the network
+    (``mlp_flat``) also takes its Adam step in the call, with the same t,
+    betas and eps, and grad_mlp is left zero.  Returns (loss [1], rgb [B,3]
+    or None)."""
     lib = load()
     dev = s.rays_o.device
     field = grid.field(use_shadow)
     mlp = mlp_struct(mlp_flat, precision)
     opt = _grid_adam(grid, density_m, density_v, feat_m, feat_v, lr, t, betas, eps, active)
+    net = None
+    if mlp_adam is not None:
+        m_, v_, lr_ = mlp_adam
+        net = AdamState(_ptr(mlp_flat), _ptr(m_), _ptr(v_), float(lr_), float(betas[0]), float(betas[1]), float(eps),
+                        int(t))
     rgb = torch.empty((s.B, 3), dtype=torch.float32, device=dev) if want_rgb else None
     loss = torch.empty(1, dtype=torch.float32, device=dev)
     nws = lib.dvgo_render_workspace_bytes(s.B, s.capacity, CHANNELS, ctypes.byref(field.box))
@@ -338,7 +346,7 @@ def train_step(grid: Grid, mlp_flat: torch.Tensor, s: Samples, target: torch.Ten
         ctypes.byref(field), ctypes.byref(mlp), _ptr(s.rays_o), _ptr(s.rays_d), _ptr(s.jitter), _ptr(s.t_near),
         _ptr(s.n_uniform), _ptr(s.perm), _ptr(s.ray_offset), _ptr(s.sample_ray), _ptr(s.sample_k), _ptr(s.n_kept),
         s.capacity, s.B, s.step, _bg(bg), _ptr(target), _ptr(rgb), _ptr(loss), ctypes.byref(opt), _ptr(grad_mlp),
-        _ptr(ws), nws, _stream(dev)))
+        ctypes.byref(net) if net is not None else None, _ptr(ws), nws, _stream(dev)))
     return loss, rgb
 
 

@@ -29,12 +29,15 @@ inline AdamCoef adam_coef(float lr, float beta1, float beta2, float eps, int32_t
     return c;
 }
 
+// The moment updates are written as explicit fused multiply-adds (the new
+// gradient's share rounded first), so that every kernel that inlines this
+// function computes the same bits whatever the compiler would contract.
 __device__ __forceinline__ void adam_update(const AdamCoef& c, float& p, float g, float& m, float& v) {
-    m = c.b1 * m + (1.0f - c.b1) * g;
-    v = c.b2 * v + (1.0f - c.b2) * g * g;
+    m = __builtin_fmaf(c.b1, m, (1.0f - c.b1) * g);
+    v = __builtin_fmaf(c.b2, v, ((1.0f - c.b2) * g) * g);
     const float mh = m * c.inv_bc1;
     const float vh = v * c.inv_bc2;
-    p -= c.lr * mh / (sqrtf(vh) + c.eps);
+    p = p - (c.lr * mh) / (sqrtf(vh) + c.eps);
 }
 
 // float32 -> bfloat16 bits, round to nearest even (NaN stays NaN).

@@ -883,9 +883,19 @@ __global__ __launch_bounds__(1024) void scan_apply_kernel(const int* __restrict_
 // partial row, then a fixed-order sum of the 16 (deterministic).  With
 // sq_err, workgroup 0 also forms the photometric loss (1/B) sum of the
 // rays' squared errors, in a fixed order.
+// With net.param, the summed gradient also takes the network's Adam step
+// (the update dvgo_adam_step makes, on the same float32 gradient) and out
+// is left zero.
+struct NetAdam {
+    float* param;
+    float* m;
+    float* v;
+    dvgo::AdamCoef c;
+};
+
 __global__ __launch_bounds__(1024) void reduce_partials_kernel(const float* __restrict__ partial, int nblk,
                                                                float* __restrict__ out, const float* __restrict__ sq_err,
-                                                               int B, float* __restrict__ loss) {
+                                                               int B, float* __restrict__ loss, NetAdam net) {
     __shared__ float sh[16][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int p = blockIdx.x * 64 + lane;
@@ -897,7 +907,17 @@ __global__ __launch_bounds__(1024) void reduce_partials_kernel(const float* __re
     if (wave == 0 && p < kMlpParams) {
         float t = 0.0f;
         for (int w = 0; w < 16; ++w) t += sh[w][lane];
-        out[p] += t;
+        const float g = out[p] + t;
+        if (net.param) {
+            float pp = net.param[p], mm = net.m[p], vv = net.v[p];
+            dvgo::adam_update(net.c, pp, g, mm, vv);
+            net.param[p] = pp;
+            net.m[p] = mm;
+            net.v[p] = vv;
+            out[p] = 0.0f;
+        } else {
+            out[p] = g;
+        }
     }
     if (blockIdx.x == 0 && sq_err) {
         __syncthreads();
@@ -1179,7 +1199,8 @@ int32_t render_bwd_impl(const dvgo_field* field, const dvgo_mlp* mlp, const floa
                         const float* log_t_end, const float* grad_rgb, const float* grad_depth,
                         const float* grad_acc, float* grad_density, float* grad_feat, const GridAdamArgs* opt,
                         float* grad_mlp, void* workspace, size_t workspace_bytes, void* stream,
-                        bool forward_done = false, const float* sq_err = nullptr, float* loss = nullptr) {
+                        bool forward_done = false, const float* sq_err = nullptr, float* loss = nullptr,
+                        const NetAdam* net = nullptr) {
     if (int32_t st = validate(field, mlp, rays_o, rays_d, t_near, n_uniform, perm, ray_offset, sample_ray, sample_k,
                               n_kept, capacity, B, step, bg, workspace, workspace_bytes))
         return st;
@@ -1240,8 +1261,10 @@ int32_t render_bwd_impl(const dvgo_field* field, const dvgo_mlp* mlp, const floa
                                 s))
         return st;
     if (mlp) {
+        NetAdam na{};
+        if (net) na = *net;
         DVGO_LAUNCH(K_REDUCE, reduce_partials_kernel, dim3((kMlpParams + 63) / 64), dim3(1024), 0, s,
-                    reinterpret_cast<const float*>(cm.ws + cm.L.partial), nblk, grad_mlp, sq_err, B, loss);
+                    reinterpret_cast<const float*>(cm.ws + cm.L.partial), nblk, grad_mlp, sq_err, B, loss, na);
         if (int32_t st = dvgo::launch_status()) return st;
     }
     return DVGO_OK;
@@ -1343,11 +1366,21 @@ int32_t dvgo_train_step(const dvgo_field* field, const dvgo_mlp* mlp, const floa
                         const int32_t* ray_offset, const int32_t* sample_ray, const int32_t* sample_k,
                         const int64_t* n_kept, int64_t capacity, int32_t B, float step, const float* bg,
                         const float* target, float* rgb, float* loss, const dvgo_grid_adam* opt, float* grad_mlp,
-                        void* workspace, size_t workspace_bytes, void* stream) {
+                        const dvgo_adam_state* mlp_opt, void* workspace, size_t workspace_bytes, void* stream) {
     if (int32_t st = validate(field, mlp, rays_o, rays_d, t_near, n_uniform, perm, ray_offset, sample_ray, sample_k,
                               n_kept, capacity, B, step, bg, workspace, workspace_bytes))
         return st;
     if (!mlp || !opt || !grad_mlp || (B > 0 && !target)) return DVGO_E_ARG;
+    NetAdam net{};
+    if (mlp_opt) {
+        if (!mlp_opt->param || !mlp_opt->m || !mlp_opt->v ||
+            !dvgo::adam_hyper_ok(mlp_opt->beta1, mlp_opt->beta2, mlp_opt->eps, mlp_opt->t))
+            return DVGO_E_ARG;
+        net.param = mlp_opt->param;
+        net.m = mlp_opt->m;
+        net.v = mlp_opt->v;
+        net.c = dvgo::adam_coef(mlp_opt->lr, mlp_opt->beta1, mlp_opt->beta2, mlp_opt->eps, mlp_opt->t);
+    }
     char* ws = static_cast<char*>(workspace);
     const WsLayout L = ws_layout(B, capacity, cell_count_of(field->box));
     float* rgb_w = rgb ? rgb : reinterpret_cast<float*>(ws + L.step_rgb);
@@ -1359,9 +1392,15 @@ int32_t dvgo_train_step(const dvgo_field* field, const dvgo_mlp* mlp, const floa
                                          nullptr, logt_w, nullptr, nullptr, workspace, workspace_bytes, stream))
             return st;
         if (int32_t st = dvgo_photo_loss(rgb_w, target, B, grad_w, loss, stream)) return st;
-        return dvgo_render_bwd_adam(field, mlp, rays_o, rays_d, jitter, t_near, n_uniform, perm, ray_offset,
-                                    sample_ray, sample_k, n_kept, capacity, B, step, bg, logt_w, grad_w, nullptr,
-                                    nullptr, opt, grad_mlp, workspace, workspace_bytes, stream);
+        if (int32_t st = dvgo_render_bwd_adam(field, mlp, rays_o, rays_d, jitter, t_near, n_uniform, perm,
+                                              ray_offset, sample_ray, sample_k, n_kept, capacity, B, step, bg, logt_w,
+                                              grad_w, nullptr, nullptr, opt, grad_mlp, workspace, workspace_bytes,
+                                              stream))
+            return st;
+        if (!mlp_opt) return DVGO_OK;
+        return dvgo_adam_step(mlp_opt->param, grad_mlp, mlp_opt->m, mlp_opt->v, nullptr,
+                              dvgo_mlp_param_count(field->channels, mlp->hidden), mlp_opt->lr, mlp_opt->beta1,
+                              mlp_opt->beta2, mlp_opt->eps, mlp_opt->t, stream);
     }
     GridAdamArgs o;
     if (int32_t st = grid_adam_args(opt, &o)) return st;
@@ -1387,7 +1426,8 @@ int32_t dvgo_train_step(const dvgo_field* field, const dvgo_mlp* mlp, const floa
     // adjoint and Adam, reusing the forward's gathered features, colours and prep
     return render_bwd_impl(field, mlp, rays_o, rays_d, jitter, t_near, n_uniform, perm, ray_offset, sample_ray,
                            sample_k, n_kept, capacity, B, step, bg, logt_w, grad_w, nullptr, nullptr, nullptr,
-                           nullptr, &o, grad_mlp, workspace, workspace_bytes, stream, true, sq_w, loss);
+                           nullptr, &o, grad_mlp, workspace, workspace_bytes, stream, true, sq_w, loss,
+                           mlp_opt ? &net : nullptr);
 }
 
 }  // extern "C"

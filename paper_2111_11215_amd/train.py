@@ -128,8 +128,7 @@ class FineModel:
             d, f, m = self.st_density, self.st_feat, self.st_mlp
             loss, rgb = api.train_step(self.grid, self.mlp, s, target, d.m, d.v, f.m, f.v, m.g, lg, self.t, c.betas,
                                        c.eps, c.bg, precision=c.precision, use_shadow=c.bf16_feat,
-                                       active=self.active)
-            api.adam_step(m.p, m.g, m.m, m.v, lm, self.t, c.betas, c.eps)
+                                       active=self.active, mlp_adam=(m.m, m.v, lm))
             return {"loss": loss, "samples": s, "rgb": rgb}
         out = self.render(s, want_depth_acc=False)
         loss, grad = api.photo_loss(out["rgb"], target)

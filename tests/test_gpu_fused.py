@@ -206,3 +206,44 @@ def test_activity_mask_skips_idle_vertices_exactly(gpu_lib, bf16):
         assert np.array_equal(np_of(gb.feat_shadow).view(np.uint16), _bf16_bits(np_of(gb.feat)))
         assert np.array_equal(np_of(gb.feat_shadow).view(np.uint16), np_of(ga.feat_shadow).view(np.uint16)) or \
             report("shadow", np_of(gb.feat), np_of(ga.feat))[0] <= 1e-6
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_train_step_network_adam_equals_separate(gpu_lib, bf16):
+    """dvgo_train_step taking the network's Adam step inside the call (fused
+    into the partial reduction) against the same call followed by
+    dvgo_adam_step on the accumulated gradient: network weights and moments
+    bit for bit, the gradient left zero; the grids as the same call."""
+    import torch
+    from paper_2111_11215_amd import api
+    from paper_2111_11215_amd._lib import DVGO_BF16, DVGO_F32
+    prec = DVGO_BF16 if bf16 else DVGO_F32
+    P = _problem(13, n_rays=1024, bias=0.3)
+    grid, flat, s = _gpu(P, bf16=bf16)
+    rng = np.random.default_rng(17)
+    mD, vD = _state(rng, P.density.shape)
+    mF, vF = _state(rng, P.feat.shape)
+    mW = to_dev((rng.normal(size=flat.shape) * 1e-3).astype(F32))
+    vW = to_dev((rng.random(flat.shape) * 1e-5).astype(F32))
+    target = to_dev(P.rays.target.astype(F32))
+    lr, lrw, t = 0.1, 1e-3, 7
+    gw0 = to_dev((rng.normal(size=flat.shape) * 1e-4).astype(F32))   # gradient already accumulated
+
+    ga, fa = _clone_grid(api, grid), flat.clone()
+    gma, mWa, vWa = gw0.clone(), mW.clone(), vW.clone()
+    sa = [x.clone() for x in (mD, vD, mF, vF)]
+    la, _ = api.train_step(ga, fa, s, target, *sa, gma, lr, t, bg=P.bg, precision=prec, use_shadow=bf16)
+    api.adam_step(fa, gma, mWa, vWa, lrw, t)
+
+    gb, fb = _clone_grid(api, grid), flat.clone()
+    gmb, mWb, vWb = gw0.clone(), mW.clone(), vW.clone()
+    sb = [x.clone() for x in (mD, vD, mF, vF)]
+    lb, _ = api.train_step(gb, fb, s, target, *sb, gmb, lr, t, bg=P.bg, precision=prec, use_shadow=bf16,
+                           mlp_adam=(mWb, vWb, lrw))
+    assert torch.equal(fa, fb) and torch.equal(mWa, mWb) and torch.equal(vWa, vWb)
+    assert float(gmb.abs().max()) == 0.0 and float(gma.abs().max()) == 0.0
+    assert not torch.equal(fa, flat)
+    assert abs(float(la[0]) - float(lb[0])) <= 1e-6 * float(la[0])
+    for name, p0, pa, pb in (("density", grid.density, ga.density, gb.density), ("feat", grid.feat, ga.feat,
+                                                                                   gb.feat)):
+        assert report(f"{name} update", np_of(pb - p0), np_of(pa - p0))[0] <= 1e-5, name
