@@ -247,3 +247,112 @@ def test_train_step_network_adam_equals_separate(gpu_lib, bf16):
     for name, p0, pa, pb in (("density", grid.density, ga.density, gb.density), ("feat", grid.feat, ga.feat,
                                                                                    gb.feat)):
         assert report(f"{name} update", np_of(pb - p0), np_of(pa - p0))[0] <= 1e-5, name
+
+
+def test_activity_mask_without_samples(gpu_lib):
+    """No sample in the batch: with the activity mask only the vertices whose
+    bit is set step (their zero-gradient step equals the dense call's), the
+    others keep p, m, v bit for bit."""
+    import torch
+    from paper_2111_11215_amd import api
+    P = _problem(14, n_rays=128)
+    P.rays.o = (P.rays.o + np.float32(10.0)).astype(F32)
+    P.rays.d = np.abs(P.rays.d).astype(F32)
+    grid, flat, s = _gpu(P)
+    assert int(s.n_kept.item()) == 0
+    rng = np.random.default_rng(23)
+    nv = P.density.size
+    keep = to_dev((rng.random(nv) < 0.3).reshape(P.density.shape).astype(F32))
+    mD, vD = _state(rng, P.density.shape)
+    mF, vF = _state(rng, P.feat.shape)
+    mD, vD, mF, vF = mD * keep, vD * keep, mF * keep[..., None], vF * keep[..., None]
+    active = torch.zeros(api.grid_active_words(nv), dtype=torch.int32, device="cuda")
+    api.grid_active_init(mD, vD, mF, vF, active)
+    out = api.render_fwd(grid, flat, s, P.bg)
+    g = torch.ones((128, 3), device="cuda")
+    ga, gb = _clone_grid(api, grid), _clone_grid(api, grid)
+    sa = [x.clone() for x in (mD, vD, mF, vF)]
+    sb = [x.clone() for x in (mD, vD, mF, vF)]
+    api.render_bwd_adam(ga, flat, s, out["log_t_end"], g, *sa, torch.zeros_like(flat), 0.1, 2, bg=P.bg)
+    api.render_bwd_adam(gb, flat, s, out["log_t_end"], g, *sb, torch.zeros_like(flat), 0.1, 2, bg=P.bg,
+                        active=active)
+    for a, b in zip((ga.density, ga.feat, *sa), (gb.density, gb.feat, *sb)):
+        assert torch.equal(a, b)
+    idle = np_of(keep).reshape(-1) == 0
+    assert np.array_equal(np_of(gb.density).reshape(-1)[idle], P.density.reshape(-1)[idle])
+
+
+def test_train_step_full_size_matches_separate(gpu_lib):
+    """The benchmark's configuration (160^3 grids, bfloat16 copy and
+    network, 8192 rays of the scene, 100^3 coarse mask): one
+    dvgo_train_step with the activity mask and the fused network Adam step
+    against the separate calls (render forward, loss, backward into zeroed
+    gradients, dense dvgo_adam_step on both grids and on the network), from
+    moments that are non-zero on a random 40 % of the vertices.  Same loss
+    and colour; network weights and moments bit for bit; grid updates and
+    moments to the summation order of the grid gradients (1e-5)."""
+    import math
+
+    import torch
+
+    import synth
+    from paper_2111_11215_amd import api
+    from paper_2111_11215_amd._lib import DVGO_BF16
+    sp, cams, held, raw = synth.full_scene(0)
+    n = synth.FULL_N
+    voxel = 2.0 / (n - 1)
+    step = 0.5 * voxel
+    max_samples = int(math.ceil(2.0 * math.sqrt(3.0) / step)) + 1
+    bmin, bmax = tuple(synth.BOX_MIN), tuple(synth.BOX_MAX)
+    bits = api.coarse_mask_build(torch.as_tensor(raw).cuda(), bmin, bmax, api.coarse_raw_threshold(synth.FULL_TAU,
+                                                                                                   step))
+    coarse = (bits, bmin, bmax, raw.shape)
+    rng = np.random.default_rng(1000)
+    o, d, *_ = synth.draw_pixels_with_replacement(rng, cams, 800, 800, 1000.0, 8192)
+    jit = torch.as_tensor(rng.random(8192).astype(F32)).cuda()
+    ot, dt = torch.as_tensor(o).cuda(), torch.as_tensor(d).cuda()
+    spheres = torch.as_tensor(sp.as_f32_table()).cuda()
+    target = api.scene_render(ot, dt, spheres, bmin, bmax, step / 4)
+    s = api.sample_rays(ot, dt, jit, bmin, bmax, step, max_samples, coarse=coarse)
+    g0 = torch.Generator(device="cpu").manual_seed(5)
+    dens = (torch.rand((n, n, n), generator=g0) * 4 - 3).cuda()
+    feat = (torch.rand((n, n, n, 12), generator=g0) * 2 - 1).cuda()
+    grid = api.Grid(dens, feat, bmin, bmax, api.low_density_bias(synth.FULL_ALPHA_INIT, voxel))
+    grid.feat_shadow = feat.to(torch.bfloat16).view(torch.int16).contiguous()
+    Ws, bs = synth.xavier_uniform_mlp(np.random.default_rng(7), (39, 128, 128, 3))
+    flat = api.flat_from([Ws[0], bs[0], Ws[1], bs[1], Ws[2], bs[2]], api.MLP_SHAPES, "cuda:0")
+    keep = (torch.rand((n, n, n), generator=g0) < 0.4).float().cuda()
+    mD = torch.randn((n, n, n), generator=g0).cuda() * 1e-3 * keep
+    vD = torch.rand((n, n, n), generator=g0).cuda() * 1e-5 * keep
+    mF = torch.randn((n, n, n, 12), generator=g0).cuda() * 1e-3 * keep[..., None]
+    vF = torch.rand((n, n, n, 12), generator=g0).cuda() * 1e-5 * keep[..., None]
+    mW = torch.randn(flat.shape, generator=g0).cuda() * 1e-3
+    vW = torch.rand(flat.shape, generator=g0).cuda() * 1e-5
+    lr, lrw, t = 0.1, 1e-3, 9
+
+    ga, fa = _clone_grid(api, grid), flat.clone()
+    out = api.render_fwd(ga, fa, s, precision=DVGO_BF16, use_shadow=True, want_depth_acc=False)
+    loss_a, grad = api.photo_loss(out["rgb"], target)
+    gd, gf, gm = torch.zeros_like(dens), torch.zeros_like(feat), torch.zeros_like(flat)
+    api.render_bwd(ga, fa, s, out["log_t_end"], grad, gd, gf, gm, precision=DVGO_BF16, use_shadow=True)
+    sa = [x.clone() for x in (mD, vD, mF, vF, mW, vW)]
+    api.adam_step(ga.density, gd, sa[0], sa[1], lr, t)
+    api.adam_step(ga.feat, gf, sa[2], sa[3], lr, t, shadow=ga.feat_shadow)
+    api.adam_step(fa, gm, sa[4], sa[5], lrw, t)
+
+    gb, fb = _clone_grid(api, grid), flat.clone()
+    sb = [x.clone() for x in (mD, vD, mF, vF, mW, vW)]
+    active = torch.zeros(api.grid_active_words(n ** 3), dtype=torch.int32, device="cuda")
+    api.grid_active_init(*sb[:4], active)
+    gmb = torch.zeros_like(flat)
+    loss_b, rgb_b = api.train_step(gb, fb, s, target, *sb[:4], gmb, lr, t, precision=DVGO_BF16, use_shadow=True,
+                                   active=active, mlp_adam=(sb[4], sb[5], lrw))
+    print(f"  {int(s.n_kept.item())} samples; loss {float(loss_a[0]):.6f}", flush=True)
+    assert torch.equal(out["rgb"], rgb_b)
+    assert abs(float(loss_a[0]) - float(loss_b[0])) <= 1e-6 * float(loss_a[0])
+    assert torch.equal(fa, fb) and torch.equal(sa[4], sb[4]) and torch.equal(sa[5], sb[5])
+    for name, p0, pa, pb in (("density", dens, ga.density, gb.density), ("feat", feat, ga.feat, gb.feat)):
+        assert report(f"{name} update", np_of(pb - p0), np_of(pa - p0))[0] <= 1e-5, name
+    for name, a, b in zip(("m density", "v density", "m feat", "v feat"), sa[:4], sb[:4]):
+        assert report(name, np_of(b), np_of(a))[0] <= 1e-5, name
+    assert np.array_equal(np_of(gb.feat_shadow).view(np.uint16), _bf16_bits(np_of(gb.feat)))
