@@ -153,8 +153,15 @@ __global__ __launch_bounds__(256) void prep_kernel(PackArgs pk, int pack, const 
     const int ray_blocks = (B + 1) / 2;
     const int zb = static_cast<int>(blockIdx.x) - (pack ? kPackBlocks : 0) - ray_blocks;
     if (zb >= 0) {   // the last zblocks workgroups clear `zero` (the backward's cell counts)
-        for (int64_t i = static_cast<int64_t>(zb) * 256 + threadIdx.x; i < nzero; i += static_cast<int64_t>(zblocks) * 256)
-            zero[i] = 0;
+        const int64_t stride = static_cast<int64_t>(zblocks) * 256, first = static_cast<int64_t>(zb) * 256 + threadIdx.x;
+        int64_t done = 0;
+        if ((reinterpret_cast<uintptr_t>(zero) & 15u) == 0) {   // 16-byte stores, then the tail
+            int4* z4 = reinterpret_cast<int4*>(zero);
+            const int64_t n4 = nzero / 4;
+            for (int64_t i = first; i < n4; i += stride) z4[i] = make_int4(0, 0, 0, 0);
+            done = 4 * n4;
+        }
+        for (int64_t i = done + first; i < nzero; i += stride) zero[i] = 0;
         return;
     }
     __shared__ float se[2][32];
