@@ -58,7 +58,9 @@ typedef struct dvgo_box {
 /* Fine scene representation of the paper's Sec. 4.2 (Eq. fine_queries):
  * the density grid with post-activation (Eq. post_activation, shift b of
  * Eq. density_activation) and the feature grid.  `feat` is float32 or a
- * bfloat16 shadow (feat_dtype), channel-last; `channels` must be 12. */
+ * bfloat16 shadow (feat_dtype), channel-last; `channels` must be 12.  The
+ * render calls index vertices and cells in 32 bits: a grid of 2^31 or more
+ * vertices is DVGO_E_UNSUPPORTED. */
 typedef struct dvgo_field {
     const float* density;
     const void* feat;

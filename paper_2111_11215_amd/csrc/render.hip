@@ -959,6 +959,9 @@ int32_t validate(const dvgo_field* field, const dvgo_mlp* mlp, const float* rays
                  int32_t B, float step, const float* bg, void* workspace, size_t workspace_bytes) {
     if (!field || !bg || B < 0 || capacity < 0 || !(step > 0.0f)) return DVGO_E_ARG;
     if (!dvgo::box_ok(&field->box, 2) || !field->density) return DVGO_E_ARG;
+    // vertex and cell indices, cell starts and record positions are int32
+    if (static_cast<int64_t>(field->box.n[0]) * field->box.n[1] * field->box.n[2] >= (1LL << 31))
+        return DVGO_E_UNSUPPORTED;
     if (mlp) {
         if (field->channels != kC) return DVGO_E_SHAPE;
         if (!field->feat) return DVGO_E_ARG;

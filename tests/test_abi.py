@@ -97,6 +97,10 @@ def test_host_validation_rejects_before_launch(lib):
     m.hidden = 64
     assert lib.dvgo_render_fwd(ctypes.byref(f), ctypes.byref(m), fake, fake, nul, *args[3:]) == -2
     m.hidden = 128
+    # a grid of 2^31 vertices or more is beyond the int32 vertex and cell indexing
+    f.box = _lib.make_box((-1, -1, -1), (1, 1, 1), (2048, 2048, 512))
+    assert lib.dvgo_render_fwd(ctypes.byref(f), ctypes.byref(m), fake, fake, nul, *args[3:]) == -6
+    f.box = _lib.make_box((-1, -1, -1), (1, 1, 1), (4, 4, 4))
     m.precision = 7
     assert lib.dvgo_render_fwd(ctypes.byref(f), ctypes.byref(m), fake, fake, nul, *args[3:]) == -3
     # scene: too many spheres
