@@ -9,9 +9,9 @@
 // B operand; the K order this implies is folded into the packed weights
 // (phi() below), so a layer chain never leaves registers.  Weight gradients
 // need the sample index as the contraction dimension, so the activations of
-// the four waves of a workgroup are staged through LDS once per 128 samples
-// and each wave accumulates its own 32-row slice of dW in registers across
-// the whole persistent loop; per-workgroup partials are summed afterwards.
+// a workgroup's 128 samples are staged through LDS once per block and each
+// wave accumulates its own slice of dW in registers across the whole
+// persistent loop; per-workgroup partials are summed afterwards.
 #pragma once
 
 #include "common.hpp"
@@ -783,7 +783,55 @@ __global__ __launch_bounds__(256, 2) void mlp_fwd_bf16_kernel(MlpArgs a0) {
     }
 }
 
-__global__ __launch_bounds__(256, 1) void mlp_bwd_bf16_kernel(MlpArgs a0) {
+// NT output tiles of a chained 128-wide layer without the explicit read
+// pipelining (for kernels with two wavefronts per SIMD, where the other
+// wavefront covers the LDS latency).
+template <int NT>
+__device__ __forceinline__ void chain_tiles_plain_bf16(const bf16x8* w, int lane, int mt0, const bf16x8 in[8],
+                                                       f32x16 acc[NT]) {
+    #pragma unroll
+    for (int st = 0; st < 8; ++st)
+        #pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = mma_bf16(w[((mt0 + t) * 8 + st) * 64 + lane], in[st], acc[t]);
+}
+
+// Inverse of stage_row: this lane's operand fragment of step st read back
+// from its sample's row.
+__device__ __forceinline__ bf16x8 read_row(const __bf16* T, int col_s, int st, int h) {
+    const int j = 8 * (st >> 1) + 4 * (st & 1) + h;
+    const s16x4 lo = *reinterpret_cast<const s16x4*>(chunk_at(T, col_s, j));
+    const s16x4 hi = *reinterpret_cast<const s16x4*>(chunk_at(T, col_s, j + 2));
+    typedef short s16x8 __attribute__((ext_vector_type(8)));
+    const s16x8 v = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+// The per-ray first-layer part of two output tiles mt0, mt0 + 1.
+__device__ __forceinline__ void load_base2(const float* base, int r, int h, int mt0, f32x16 acc[2]) {
+    const float* br = base + static_cast<int64_t>(r) * kH;
+    #pragma unroll
+    for (int t = 0; t < 2; ++t)
+        #pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 v = *reinterpret_cast<const float4*>(br + 32 * (mt0 + t) + 8 * q + 4 * h);
+            acc[t][4 * q + 0] = v.x;
+            acc[t][4 * q + 1] = v.y;
+            acc[t][4 * q + 2] = v.z;
+            acc[t][4 * q + 3] = v.w;
+        }
+}
+
+// bfloat16 network adjoint with eight wavefronts per workgroup (two per
+// SIMD, so that one wavefront's LDS and matrix-core latency hides behind the
+// other's work).  The 128 samples of a block form four groups of 32
+// (g = wave % 4); the two wavefronts of a group split every layer's output
+// features in halves (q = wave / 4: tiles 2q, 2q + 1 of 32), exchanging the
+// other half through the sample-row staging that the weight gradients read
+// anyway.  Weight-gradient accumulators per wavefront: dW2 rows 32g, columns
+// of tiles 2q, 2q + 1; dW1 rows 32g, x' columns of tile q; dW3 (q = 0) or
+// db2 (q = 1) rows 32g.  The two halves of the head's logits and of
+// dL/dfeat are summed through LDS.
+__global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
     __shared__ bf16x8 sW2[kW2PackBF16 / 8];
     __shared__ bf16x8 sW2T[kW2PackBF16 / 8];
     __shared__ bf16x8 sW1[kW1PackBF16 / 8];
@@ -791,32 +839,33 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_bf16_kernel(MlpArgs a0) {
     __shared__ __attribute__((aligned(16))) __bf16 tB[128 * kTP];   // h2, then dL/dz2, then x'
     __shared__ __attribute__((aligned(16))) __bf16 sC[32 * kBP];    // dL/dz3 [feature][sample], rows 0..2
     __shared__ __attribute__((aligned(16))) float sB2[kH];
+    __shared__ __attribute__((aligned(16))) float4 sZ[2][128];      // the halves' logit partials
+    __shared__ __attribute__((aligned(16))) float sD[128][kC];      // the second half's dL/dfeat partial
     __shared__ float sRed[4 * 4];
     load_packed_bf16(a0, sW1, sW2, sW2T, sB2);
     for (int i = threadIdx.x; i < 32 * kBP; i += blockDim.x) sC[i] = static_cast<__bf16>(0.0f);
     __syncthreads();
     const int64_t n = *a0.n_kept < a0.cap ? *a0.n_kept : a0.cap;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // The wavefront index in a scalar register: the role branches below are
+    // then scalar branches.  Under a vector-masked branch a matrix
+    // instruction still updates its accumulator in a wavefront whose mask is
+    // empty.
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int g = wave & 3, q = wave >> 2;
     const int m = lane & 31, h = lane >> 5;
-    const int col_s = wave * 32 + m;     // this lane's sample column in the staged block
-    f32x16 dW2[4], dB2, dW1[2], dW3;
-    #pragma unroll
-    for (int t = 0; t < 4; ++t)
-        #pragma unroll
-        for (int rr = 0; rr < 16; ++rr) dW2[t][rr] = 0.0f;
+    const int col_s = g * 32 + m;     // this lane's sample column in the staged block
+    f32x16 dW2[2], dW1, dX;           // dX: dW3 (q = 0) or db2 (q = 1)
     #pragma unroll
     for (int rr = 0; rr < 16; ++rr) {
-        dB2[rr] = 0.0f;
-        dW1[0][rr] = 0.0f;
-        dW1[1][rr] = 0.0f;
-        dW3[rr] = 0.0f;
+        dW2[0][rr] = 0.0f;
+        dW2[1][rr] = 0.0f;
+        dW1[rr] = 0.0f;
+        dX[rr] = 0.0f;
     }
     float db3[3] = {0, 0, 0};
     bf16x8 ones;
     #pragma unroll
     for (int e = 0; e < 8; ++e) ones[e] = static_cast<__bf16>(m == 0 ? 1.0f : 0.0f);
-    // the ray index of this lane's sample one block ahead: the per-ray loads
-    // at the top of each block then wait on one round trip, not two
     int r_next = 0;
     if (static_cast<int64_t>(blockIdx.x) * 128 < n) {
         const int64_t s0 = static_cast<int64_t>(blockIdx.x) * 128 + col_s;
@@ -832,134 +881,167 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_bf16_kernel(MlpArgs a0) {
             const int64_t s1 = (blk + gridDim.x) * 128 + col_s;
             r_next = a.sample_ray[s1 < n ? s1 : n - 1];
         }
-        float f[12];
-        load_feat(a.feat, sc, f);
-        ChainBF16 c;
-        forward_chain_bf16(a, sW1, sW2, sB2, r, f, lane, c);
-        float col[3];
-        bf16x8 h2b[8];
-        head_bf16(a, c.z2, lane, col, h2b);
-        float dz3[3] = {0, 0, 0};
-        if (ok && h == 0) {
-            const float4 dc = reinterpret_cast<const float4*>(a.col)[s];
-            dz3[0] = dc.x * col[0] * (1.0f - col[0]);
-            dz3[1] = dc.y * col[1] * (1.0f - col[1]);
-            dz3[2] = dc.z * col[2] * (1.0f - col[2]);
-        }
-        // stage h1 -> tA, h2 -> tB (sample rows, from the packed operands), dz3 -> sC
-        #pragma unroll
-        for (int st = 0; st < 8; ++st) {
-            stage_row(tA, col_s, st, h, c.hb[st]);
-            stage_row(tB, col_s, st, h, h2b[st]);
-        }
-        if (h == 0) {
+        // ---- layer 1, this half's two tiles, staged as h1 rows
+        {
+            float f[12];
+            load_feat(a.feat, sc, f);
+            f32x16 h1[2];
+            load_base2(a.base, r, h, 2 * q, h1);
+            bf16x8 fb;
             #pragma unroll
-            for (int t = 0; t < 3; ++t) {
-                sC[t * kBP + col_s] = static_cast<__bf16>(dz3[t]);
-                db3[t] += dz3[t];
+            for (int e = 0; e < 8; ++e)
+                fb[e] = static_cast<__bf16>(h ? (e < kC - 8 ? f[8 + (e < kC - 8 ? e : 0)] : 0.0f) : f[e]);
+            #pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                h1[t] = mma_bf16(sW1[(2 * q + t) * 64 + lane], fb, h1[t]);
+                #pragma unroll
+                for (int gg = 0; gg < 2; ++gg) stage_row(tA, col_s, 4 * q + 2 * t + gg, h, relu_pack8(h1[t], gg));
             }
         }
-        // dz2 = (W3^T bf16(dz3)) * relu'(z2) on matrix cores, packed as the
-        // chain's and the staging's operands
-        bf16x8 zb[8];
+        __syncthreads();   // B1: h1 rows complete
+        // ---- layer 2 and the head on this half
+        f32x16 z2[2];
+        #pragma unroll
+        for (int t = 0; t < 2; ++t)
+            #pragma unroll
+            for (int qq = 0; qq < 4; ++qq) {
+                const float4 b = *reinterpret_cast<const float4*>(sB2 + 32 * (2 * q + t) + 8 * qq + 4 * h);
+                z2[t][4 * qq] = b.x;
+                z2[t][4 * qq + 1] = b.y;
+                z2[t][4 * qq + 2] = b.z;
+                z2[t][4 * qq + 3] = b.w;
+            }
+        {
+            bf16x8 hb[8];
+            #pragma unroll
+            for (int st = 0; st < 8; ++st) hb[st] = read_row(tA, col_s, st, h);
+            chain_tiles_plain_bf16<2>(sW2, lane, 2 * q, hb, z2);
+        }
+        bf16x8 h2h[4];   // bf16(relu(z2)) of this half, steps 4q .. 4q + 3
+        f32x16 z3;
+        #pragma unroll
+        for (int rr = 0; rr < 16; ++rr) z3[rr] = (q == 0 && h == 0 && rr < 3) ? a.b3[rr] : 0.0f;
+        {
+            const bf16x8* w3 = reinterpret_cast<const bf16x8*>(a.w3pb);
+            #pragma unroll
+            for (int t = 0; t < 2; ++t)
+                #pragma unroll
+                for (int gg = 0; gg < 2; ++gg) {
+                    const int st = 4 * q + 2 * t + gg;
+                    h2h[2 * t + gg] = relu_pack8(z2[t], gg);
+                    stage_row(tB, col_s, st, h, h2h[2 * t + gg]);
+                    z3 = mma_bf16(w3[st * 64 + lane], h2h[2 * t + gg], z3);
+                }
+        }
+        if (h == 0) sZ[q][col_s] = make_float4(z3[0], z3[1], z3[2], 0.0f);
+        __syncthreads();   // B2: h2 rows and both logit halves complete
+        float dz3[3] = {0, 0, 0};
+        if (h == 0) {
+            const float4 z0 = sZ[0][col_s], z1 = sZ[1][col_s];
+            const float zz[3] = {z0.x + z1.x, z0.y + z1.y, z0.z + z1.z};
+            if (ok) {
+                const float4 dc = reinterpret_cast<const float4*>(a.col)[s];
+                const float dcc[3] = {dc.x, dc.y, dc.z};
+                #pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    const float cv = 1.0f / (1.0f + expf(-zz[t]));
+                    dz3[t] = dcc[t] * cv * (1.0f - cv);
+                }
+            }
+            if (q == 0) {
+                #pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    sC[t * kBP + col_s] = static_cast<__bf16>(dz3[t]);
+                    db3[t] += dz3[t];
+                }
+            }
+        }
+        // dz2 of this half = (W3^T bf16(dz3)) * relu'(z2)
+        bf16x8 zh[4];
         {
             bf16x8 dzb;
             #pragma unroll
             for (int e = 0; e < 8; ++e) dzb[e] = static_cast<__bf16>(e < 3 ? dz3[e < 3 ? e : 0] : 0.0f);
             const bf16x8* w3t = reinterpret_cast<const bf16x8*>(a.w3tpb);
             #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) {
+            for (int t = 0; t < 2; ++t) {
                 f32x16 dh;
                 #pragma unroll
                 for (int rr = 0; rr < 16; ++rr) dh[rr] = 0.0f;
-                dh = mma_bf16(w3t[mt * 64 + lane], dzb, dh);
+                dh = mma_bf16(w3t[(2 * q + t) * 64 + lane], dzb, dh);
                 #pragma unroll
-                for (int g = 0; g < 2; ++g) zb[2 * mt + g] = relu_grad_pack8(dh, g, h2b[2 * mt + g]);
+                for (int gg = 0; gg < 2; ++gg) zh[2 * t + gg] = relu_grad_pack8(dh, gg, h2h[2 * t + gg]);
             }
         }
-        __syncthreads();
-        // dW3^T[j in tile `wave`][c] over the 128 staged samples
-        #pragma unroll
-        for (int st = 0; st < 8; ++st) {
-            const bf16x8 av = tr_operand(tB, 16 * st, 32 * wave, lane);
-            const bf16x8 bv = *reinterpret_cast<const bf16x8*>(sC + m * kBP + 16 * st + 8 * h);
-            dW3 = mma_bf16(av, bv, dW3);
-        }
-        __syncthreads();
-        #pragma unroll
-        for (int st = 0; st < 8; ++st) stage_row(tB, col_s, st, h, zb[st]);
-        __syncthreads();
-        // dW2[j in tile `wave`][i], and db2 through a constant ones column
-        {
-            __builtin_amdgcn_sched_barrier(0);
-            bf16x8 ca = tr_operand(tB, 0, 32 * wave, lane), cb[4];
-            #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) cb[nt] = tr_operand(tA, 0, 32 * nt, lane);
+        __syncthreads();   // B3: dz3 rows complete
+        if (q == 0) {      // dW3^T rows 32g over the 128 staged samples
             #pragma unroll
             for (int st = 0; st < 8; ++st) {
-                bf16x8 na, nb[4];
-                if (st < 7) {
-                    na = tr_operand(tB, 16 * (st + 1), 32 * wave, lane);
-                    #pragma unroll
-                    for (int nt = 0; nt < 4; ++nt) nb[nt] = tr_operand(tA, 16 * (st + 1), 32 * nt, lane);
-                }
-                #pragma unroll
-                for (int nt = 0; nt < 4; ++nt) dW2[nt] = mma_bf16(ca, cb[nt], dW2[nt]);
-                dB2 = mma_bf16(ca, ones, dB2);
-                if (st < 7) {
-                    ca = na;
-                    #pragma unroll
-                    for (int nt = 0; nt < 4; ++nt) cb[nt] = nb[nt];
-                }
+                const bf16x8 av = tr_operand(tB, 16 * st, 32 * g, lane);
+                const bf16x8 bv = *reinterpret_cast<const bf16x8*>(sC + m * kBP + 16 * st + 8 * h);
+                dX = mma_bf16(av, bv, dX);
             }
-            __builtin_amdgcn_sched_group_barrier(0x100, 10, 0);
-            #pragma unroll
-            for (int st = 0; st < 7; ++st) {
-                __builtin_amdgcn_sched_group_barrier(0x100, 10, 0);
-                __builtin_amdgcn_sched_group_barrier(0x008, 5, 0);
-            }
-            __builtin_amdgcn_sched_group_barrier(0x008, 5, 0);
-            __builtin_amdgcn_sched_barrier(0);
         }
-        // dh1 = W2^T dz2 (chained), dz1 = dh1 * relu'(z1), packed in place of
-        // bf16(relu(z1)) once its tile's mask is read
+        __syncthreads();   // B4: h2 rows read
         #pragma unroll
-        for (int m0 = 0; m0 < 4; m0 += 2) {
+        for (int u = 0; u < 4; ++u) stage_row(tB, col_s, 4 * q + u, h, zh[u]);
+        __syncthreads();   // B5: dz2 rows complete
+        // dW2 rows 32g, columns of tiles 2q, 2q + 1 (and db2 through a ones column)
+        #pragma unroll 2
+        for (int st = 0; st < 8; ++st) {
+            const bf16x8 av = tr_operand(tB, 16 * st, 32 * g, lane);
+            #pragma unroll
+            for (int t = 0; t < 2; ++t) dW2[t] = mma_bf16(av, tr_operand(tA, 16 * st, 32 * (2 * q + t), lane), dW2[t]);
+            if (q == 1) dX = mma_bf16(av, ones, dX);
+        }
+        // dh1 = W2^T dz2 on this half's tiles, dz1 = dh1 * relu'(z1), and this
+        // half's share of dL/dfeat = W1[:, :12]^T dz1
+        bf16x8 d1[4];
+        f32x16 dft;
+        #pragma unroll
+        for (int rr = 0; rr < 16; ++rr) dft[rr] = 0.0f;
+        {
+            bf16x8 zb[8];
+            #pragma unroll
+            for (int st = 0; st < 8; ++st) zb[st] = read_row(tB, col_s, st, h);
             f32x16 dh1[2];
             #pragma unroll
             for (int t = 0; t < 2; ++t)
                 #pragma unroll
                 for (int rr = 0; rr < 16; ++rr) dh1[t][rr] = 0.0f;
-            chain_tiles_bf16<2>(sW2T, lane, m0, zb, dh1);
+            chain_tiles_plain_bf16<2>(sW2T, lane, 2 * q, zb, dh1);
+            const bf16x8* w1t = reinterpret_cast<const bf16x8*>(a.w1tpb);
             #pragma unroll
             for (int t = 0; t < 2; ++t)
                 #pragma unroll
-                for (int g = 0; g < 2; ++g)
-                    c.hb[2 * (m0 + t) + g] = relu_grad_pack8(dh1[t], g, c.hb[2 * (m0 + t) + g]);
+                for (int gg = 0; gg < 2; ++gg) {
+                    const int st = 4 * q + 2 * t + gg;
+                    d1[2 * t + gg] = relu_grad_pack8(dh1[t], gg, read_row(tA, col_s, st, h));
+                    dft = mma_bf16(w1t[st * 64 + lane], d1[2 * t + gg], dft);
+                }
         }
-        // dL/dfeat = bf16(W1[:, :12])^T bf16(dz1) on matrix cores: rows c < 12
-        // of the output tile (half 0: registers 0-7 -> c 0-3, 8-11; half 1:
-        // registers 0-3 -> c 4-7)
-        f32x16 dft;
-        {
-            #pragma unroll
-            for (int rr = 0; rr < 16; ++rr) dft[rr] = 0.0f;
-            const bf16x8* w1t = reinterpret_cast<const bf16x8*>(a.w1tpb);
-            #pragma unroll
-            for (int st = 0; st < 8; ++st) dft = mma_bf16(w1t[st * 64 + lane], c.hb[st], dft);
+        if (q == 1) {
+            if (h == 0) {
+                *reinterpret_cast<float4*>(&sD[col_s][0]) = make_float4(dft[0], dft[1], dft[2], dft[3]);
+                *reinterpret_cast<float4*>(&sD[col_s][8]) = make_float4(dft[4], dft[5], dft[6], dft[7]);
+            } else {
+                *reinterpret_cast<float4*>(&sD[col_s][4]) = make_float4(dft[0], dft[1], dft[2], dft[3]);
+            }
         }
-        __syncthreads();
-        // stage dz1 -> tA, x' = [f, PE, 1, 0...] -> tB (64 columns, this lane's half)
+        __syncthreads();   // B6: h1 and dz2 rows read; the second half's dL/dfeat in sD
         #pragma unroll
-        for (int st = 0; st < 8; ++st) stage_row(tA, col_s, st, h, c.hb[st]);
-        {
+        for (int u = 0; u < 4; ++u) stage_row(tA, col_s, 4 * q + u, h, d1[u]);
+        if (q == 0) {
+            // x' = [f, PE, 1, 0...] -> tB (64 columns, this lane's half)
+            float f[12];
+            load_feat(a.feat, sc, f);
             const float* per = a.pe + static_cast<int64_t>(r) * 32;
             #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int qq = 0; qq < 4; ++qq) {
                 bf16x8 xv;
                 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
-                    const int cc = 8 * q + e;
+                    const int cc = 8 * qq + e;
                     const int cidx = 32 * h + cc;
                     float v;
                     if (cidx < kC) v = f[cc < kC ? cc : 0];
@@ -974,77 +1056,51 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_bf16_kernel(MlpArgs a0) {
                     lo[e] = xv[e];
                     hi[e] = xv[4 + e];
                 }
-                *reinterpret_cast<bf16x4*>(chunk_at(tB, col_s, 8 * h + 2 * q)) = lo;
-                *reinterpret_cast<bf16x4*>(chunk_at(tB, col_s, 8 * h + 2 * q + 1)) = hi;
+                *reinterpret_cast<bf16x4*>(chunk_at(tB, col_s, 8 * h + 2 * qq)) = lo;
+                *reinterpret_cast<bf16x4*>(chunk_at(tB, col_s, 8 * h + 2 * qq + 1)) = hi;
             }
-        }
-        if (ok) {
-            float4* rec = binned_record(a, s);
-            if (h == 0) {
-                rec[0] = a.rec_head[s];
-                rec[1] = make_float4(dft[0], dft[1], dft[2], dft[3]);
-                rec[3] = make_float4(dft[4], dft[5], dft[6], dft[7]);
-            } else {
-                rec[2] = make_float4(dft[0], dft[1], dft[2], dft[3]);
-            }
-        }
-        __syncthreads();
-        // dW1 over the staged samples, the next K step's operands read while
-        // this step's matrix ops run
-        {
-            __builtin_amdgcn_sched_barrier(0);
-            bf16x8 ca = tr_operand(tA, 0, 32 * wave, lane);
-            bf16x8 cb0 = tr_operand(tB, 0, 0, lane), cb1 = tr_operand(tB, 0, 32, lane);
-            #pragma unroll
-            for (int st = 0; st < 8; ++st) {
-                bf16x8 na, nb0, nb1;
-                if (st < 7) {
-                    na = tr_operand(tA, 16 * (st + 1), 32 * wave, lane);
-                    nb0 = tr_operand(tB, 16 * (st + 1), 0, lane);
-                    nb1 = tr_operand(tB, 16 * (st + 1), 32, lane);
-                }
-                dW1[0] = mma_bf16(ca, cb0, dW1[0]);
-                dW1[1] = mma_bf16(ca, cb1, dW1[1]);
-                if (st < 7) {
-                    ca = na;
-                    cb0 = nb0;
-                    cb1 = nb1;
+            if (ok) {
+                float4* rec = binned_record(a, s);
+                if (h == 0) {
+                    const float4 o0 = *reinterpret_cast<const float4*>(&sD[col_s][0]);
+                    const float4 o8 = *reinterpret_cast<const float4*>(&sD[col_s][8]);
+                    rec[0] = a.rec_head[s];
+                    rec[1] = make_float4(dft[0] + o0.x, dft[1] + o0.y, dft[2] + o0.z, dft[3] + o0.w);
+                    rec[3] = make_float4(dft[4] + o8.x, dft[5] + o8.y, dft[6] + o8.z, dft[7] + o8.w);
+                } else {
+                    const float4 o4 = *reinterpret_cast<const float4*>(&sD[col_s][4]);
+                    rec[2] = make_float4(dft[0] + o4.x, dft[1] + o4.y, dft[2] + o4.z, dft[3] + o4.w);
                 }
             }
-            __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
-            #pragma unroll
-            for (int st = 0; st < 7; ++st) {
-                __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
-                __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
-            }
-            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
-            __builtin_amdgcn_sched_barrier(0);
         }
-        __syncthreads();
+        __syncthreads();   // B7: dz1 and x' rows complete
+        #pragma unroll
+        for (int st = 0; st < 8; ++st)
+            dW1 = mma_bf16(tr_operand(tA, 16 * st, 32 * g, lane), tr_operand(tB, 16 * st, 32 * q, lane), dW1);
+        __syncthreads();   // B8: rows read before the next block's staging
     }
     // ---- epilogue: this workgroup's partial of the flat gradient
     float* out = a0.partial + static_cast<int64_t>(blockIdx.x) * kPStride;
     #pragma unroll
     for (int rr = 0; rr < 16; ++rr) {
-        const int row = 32 * wave + acc_row(rr, h);
+        const int row = 32 * g + acc_row(rr, h);
         #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) out[kOffW2 + row * kH + 32 * nt + m] = dW2[nt][rr];
-        if (m == 0) out[kOffB2 + row] = dB2[rr];
+        for (int t = 0; t < 2; ++t) out[kOffW2 + row * kH + 32 * (2 * q + t) + m] = dW2[t][rr];
+        const int cidx = 32 * q + m;
+        if (cidx < kIn) out[kOffW1 + row * kIn + cidx] = dW1[rr];
+        else if (cidx == kIn) out[kOffB1 + row] = dW1[rr];
+        if (q == 0 && m < 3) out[kOffW3 + m * kH + row] = dX[rr];
+        if (q == 1 && m == 0) out[kOffB2 + row] = dX[rr];
+    }
+    if (q == 0) {
         #pragma unroll
-        for (int nt = 0; nt < 2; ++nt) {
-            const int cidx = 32 * nt + m;
-            if (cidx < kIn) out[kOffW1 + row * kIn + cidx] = dW1[nt][rr];
-            else if (cidx == kIn) out[kOffB1 + row] = dW1[nt][rr];
+        for (int t = 0; t < 3; ++t) {
+            db3[t] += __shfl_xor(db3[t], 32, 64);
+            for (int off = 16; off > 0; off >>= 1) db3[t] += __shfl_xor(db3[t], off, 64);
         }
-        if (m < 3) out[kOffW3 + m * kH + row] = dW3[rr];
+        if (lane == 0)
+            for (int t = 0; t < 3; ++t) sRed[g * 4 + t] = db3[t];
     }
-    #pragma unroll
-    for (int t = 0; t < 3; ++t) {
-        db3[t] += __shfl_xor(db3[t], 32, 64);
-        for (int off = 16; off > 0; off >>= 1) db3[t] += __shfl_xor(db3[t], off, 64);
-    }
-    if (lane == 0)
-        for (int t = 0; t < 3; ++t) sRed[wave * 4 + t] = db3[t];
     __syncthreads();
     if (threadIdx.x < 3)
         out[kOffB3 + threadIdx.x] = sRed[threadIdx.x] + sRed[4 + threadIdx.x] + sRed[8 + threadIdx.x] +
@@ -1056,7 +1112,7 @@ inline void launch_mlp_fwd(const MlpArgs& a, int cus, hipStream_t s) {
     else DVGO_LAUNCH(K_MLP_FWD, mlp_fwd_f32_kernel, dim3(cus * 2), dim3(256), 0, s, a);
 }
 inline void launch_mlp_bwd(const MlpArgs& a, int blocks, hipStream_t s) {
-    if (a.bf16) DVGO_LAUNCH(K_MLP_BWD, mlp_bwd_bf16_kernel, dim3(blocks), dim3(256), 0, s, a);
+    if (a.bf16) DVGO_LAUNCH(K_MLP_BWD, mlp_bwd_bf16_kernel, dim3(blocks), dim3(512), 0, s, a);
     else DVGO_LAUNCH(K_MLP_BWD, mlp_bwd_f32_kernel, dim3(blocks), dim3(256), 0, s, a);
 }
 

@@ -209,8 +209,6 @@ struct GatherArgs {
     float* feat_out;
 };
 
-__device__ __forceinline__ float bf16_to_f(uint16_t b) { return __uint_as_float(static_cast<uint32_t>(b) << 16); }
-
 __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
     const int64_t n = live_count(a.n_kept, a.cap);
     for (int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; s < n;
