@@ -54,10 +54,15 @@ __device__ __forceinline__ f32x16 mma_bf16(bf16x8 a, bf16x8 b, f32x16 c) {
 // persistent-loop iteration so weight loads are issued where they are
 // consumed instead of being hoisted out of the loop into hundreds of
 // registers.
+// The pointer is passed through as a global-memory one, so that the loads
+// through it stay global loads (a generic pointer would make them flat
+// loads, which every LDS wait then has to include).
 template <typename T>
 __device__ __forceinline__ T* opaque(T* p) {
-    asm volatile("" : "+s"(p));
-    return p;
+    typedef __attribute__((address_space(1))) T GT;
+    GT* g = (GT*)p;
+    asm volatile("" : "+s"(g));
+    return (T*)g;
 }
 
 // Row within a 32-row accumulator tile of register r in lane half h.
@@ -881,6 +886,15 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
             const int64_t s1 = (blk + gridDim.x) * 128 + col_s;
             r_next = a.sample_ray[s1 < n ? s1 : n - 1];
         }
+        // per-sample inputs of the head and of the record, issued here so
+        // that their latency hides behind layers 1 and 2
+        const float4 dc = ok && h == 0 ? reinterpret_cast<const float4*>(a.col)[s] : make_float4(0, 0, 0, 0);
+        int2 cr = make_int2(0, 0);
+        float4 rh = make_float4(0, 0, 0, 0);
+        if (q == 0 && ok) {
+            cr = a.cell_rank[s];
+            if (h == 0) rh = a.rec_head[s];
+        }
         // ---- layer 1, this half's two tiles, staged as h1 rows
         {
             float f[12];
@@ -935,12 +949,12 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
         }
         if (h == 0) sZ[q][col_s] = make_float4(z3[0], z3[1], z3[2], 0.0f);
         __syncthreads();   // B2: h2 rows and both logit halves complete
+        const int slot0 = q == 0 && ok ? a.cell_start[cr.x] : 0;
         float dz3[3] = {0, 0, 0};
         if (h == 0) {
             const float4 z0 = sZ[0][col_s], z1 = sZ[1][col_s];
             const float zz[3] = {z0.x + z1.x, z0.y + z1.y, z0.z + z1.z};
             if (ok) {
-                const float4 dc = reinterpret_cast<const float4*>(a.col)[s];
                 const float dcc[3] = {dc.x, dc.y, dc.z};
                 #pragma unroll
                 for (int t = 0; t < 3; ++t) {
@@ -1060,11 +1074,11 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
                 *reinterpret_cast<bf16x4*>(chunk_at(tB, col_s, 8 * h + 2 * qq + 1)) = hi;
             }
             if (ok) {
-                float4* rec = binned_record(a, s);
+                float4* rec = a.rec + (static_cast<int64_t>(slot0) + cr.y) * 4;
                 if (h == 0) {
                     const float4 o0 = *reinterpret_cast<const float4*>(&sD[col_s][0]);
                     const float4 o8 = *reinterpret_cast<const float4*>(&sD[col_s][8]);
-                    rec[0] = a.rec_head[s];
+                    rec[0] = rh;
                     rec[1] = make_float4(dft[0] + o0.x, dft[1] + o0.y, dft[2] + o0.z, dft[3] + o0.w);
                     rec[3] = make_float4(dft[4] + o8.x, dft[5] + o8.y, dft[6] + o8.z, dft[7] + o8.w);
                 } else {
