@@ -842,13 +842,34 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
     __shared__ bf16x8 sW1[kW1PackBF16 / 8];
     __shared__ __attribute__((aligned(16))) __bf16 tA[128 * kTP];   // h1 then dL/dz1, [sample][feature]
     __shared__ __attribute__((aligned(16))) __bf16 tB[128 * kTP];   // h2, then dL/dz2, then x'
-    __shared__ __attribute__((aligned(16))) __bf16 sC[32 * kBP];    // dL/dz3 [feature][sample], rows 0..2
+    // dL/dz3 [channel][sample]: rows 0..2, row 3 zero (the B operand rows of
+    // lanes m >= 3)
+    __shared__ __attribute__((aligned(16))) __bf16 sC[4 * kBP];
     __shared__ __attribute__((aligned(16))) float sB2[kH];
-    __shared__ __attribute__((aligned(16))) float4 sZ[2][128];      // the halves' logit partials
-    __shared__ __attribute__((aligned(16))) float sD[128][kC];      // the second half's dL/dfeat partial
+    __shared__ float sB3[4];
+    // The halves' logit partials (until B3) and the second half's dL/dfeat
+    // partial (B6 .. B7) share one buffer.
+    __shared__ __attribute__((aligned(16))) float sX[128 * kC];
+    float4 (*sZ)[128] = reinterpret_cast<float4 (*)[128]>(sX);
+    float (*sD)[kC] = reinterpret_cast<float (*)[kC]>(sX);
+    // Packed operands of the head (W3, W3^T) and of dL/dfeat (W1[:, :12]^T).
+    __shared__ bf16x8 sW3[8 * 64];
+    __shared__ bf16x8 sW3T[4 * 64];
+    __shared__ bf16x8 sW1T[8 * 64];
     __shared__ float sRed[4 * 4];
     load_packed_bf16(a0, sW1, sW2, sW2T, sB2);
-    for (int i = threadIdx.x; i < 32 * kBP; i += blockDim.x) sC[i] = static_cast<__bf16>(0.0f);
+    for (int i = threadIdx.x; i < 4 * kBP; i += blockDim.x) sC[i] = static_cast<__bf16>(0.0f);
+    {
+        const bf16x8* g3 = reinterpret_cast<const bf16x8*>(a0.w3pb);
+        const bf16x8* g3t = reinterpret_cast<const bf16x8*>(a0.w3tpb);
+        const bf16x8* g1t = reinterpret_cast<const bf16x8*>(a0.w1tpb);
+        if (threadIdx.x < 3) sB3[threadIdx.x] = a0.b3[threadIdx.x];
+        for (int i = threadIdx.x; i < 8 * 64; i += blockDim.x) {
+            sW3[i] = g3[i];
+            sW1T[i] = g1t[i];
+            if (i < 4 * 64) sW3T[i] = g3t[i];
+        }
+    }
     __syncthreads();
     const int64_t n = *a0.n_kept < a0.cap ? *a0.n_kept : a0.cap;
     // The wavefront index in a scalar register: the role branches below are
@@ -934,9 +955,8 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
         bf16x8 h2h[4];   // bf16(relu(z2)) of this half, steps 4q .. 4q + 3
         f32x16 z3;
         #pragma unroll
-        for (int rr = 0; rr < 16; ++rr) z3[rr] = (q == 0 && h == 0 && rr < 3) ? a.b3[rr] : 0.0f;
+        for (int rr = 0; rr < 16; ++rr) z3[rr] = (q == 0 && h == 0 && rr < 3) ? sB3[rr < 3 ? rr : 0] : 0.0f;
         {
-            const bf16x8* w3 = reinterpret_cast<const bf16x8*>(a.w3pb);
             #pragma unroll
             for (int t = 0; t < 2; ++t)
                 #pragma unroll
@@ -944,7 +964,7 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
                     const int st = 4 * q + 2 * t + gg;
                     h2h[2 * t + gg] = relu_pack8(z2[t], gg);
                     stage_row(tB, col_s, st, h, h2h[2 * t + gg]);
-                    z3 = mma_bf16(w3[st * 64 + lane], h2h[2 * t + gg], z3);
+                    z3 = mma_bf16(sW3[st * 64 + lane], h2h[2 * t + gg], z3);
                 }
         }
         if (h == 0) sZ[q][col_s] = make_float4(z3[0], z3[1], z3[2], 0.0f);
@@ -976,13 +996,12 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
             bf16x8 dzb;
             #pragma unroll
             for (int e = 0; e < 8; ++e) dzb[e] = static_cast<__bf16>(e < 3 ? dz3[e < 3 ? e : 0] : 0.0f);
-            const bf16x8* w3t = reinterpret_cast<const bf16x8*>(a.w3tpb);
             #pragma unroll
             for (int t = 0; t < 2; ++t) {
                 f32x16 dh;
                 #pragma unroll
                 for (int rr = 0; rr < 16; ++rr) dh[rr] = 0.0f;
-                dh = mma_bf16(w3t[(2 * q + t) * 64 + lane], dzb, dh);
+                dh = mma_bf16(sW3T[(2 * q + t) * 64 + lane], dzb, dh);
                 #pragma unroll
                 for (int gg = 0; gg < 2; ++gg) zh[2 * t + gg] = relu_grad_pack8(dh, gg, h2h[2 * t + gg]);
             }
@@ -992,7 +1011,7 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
             #pragma unroll
             for (int st = 0; st < 8; ++st) {
                 const bf16x8 av = tr_operand(tB, 16 * st, 32 * g, lane);
-                const bf16x8 bv = *reinterpret_cast<const bf16x8*>(sC + m * kBP + 16 * st + 8 * h);
+                const bf16x8 bv = *reinterpret_cast<const bf16x8*>(sC + (m < 3 ? m : 3) * kBP + 16 * st + 8 * h);
                 dX = mma_bf16(av, bv, dX);
             }
         }
@@ -1024,14 +1043,13 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
                 #pragma unroll
                 for (int rr = 0; rr < 16; ++rr) dh1[t][rr] = 0.0f;
             chain_tiles_plain_bf16<2>(sW2T, lane, 2 * q, zb, dh1);
-            const bf16x8* w1t = reinterpret_cast<const bf16x8*>(a.w1tpb);
             #pragma unroll
             for (int t = 0; t < 2; ++t)
                 #pragma unroll
                 for (int gg = 0; gg < 2; ++gg) {
                     const int st = 4 * q + 2 * t + gg;
                     d1[2 * t + gg] = relu_grad_pack8(dh1[t], gg, read_row(tA, col_s, st, h));
-                    dft = mma_bf16(w1t[st * 64 + lane], d1[2 * t + gg], dft);
+                    dft = mma_bf16(sW1T[st * 64 + lane], d1[2 * t + gg], dft);
                 }
         }
         if (q == 1) {
@@ -1046,32 +1064,29 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
         #pragma unroll
         for (int u = 0; u < 4; ++u) stage_row(tA, col_s, 4 * q + u, h, d1[u]);
         if (q == 0) {
-            // x' = [f, PE, 1, 0...] -> tB (64 columns, this lane's half)
-            float f[12];
-            load_feat(a.feat, sc, f);
-            const float* per = a.pe + static_cast<int64_t>(r) * 32;
+            // x' = [f, PE, 1, 0...] -> tB (64 columns, this lane's half of
+            // 8 float4 chunks): half 0 takes f[0..11] and PE[0..19], half 1
+            // PE[20..26] and the constant 1 (stored after the PE) and zeros.
+            // Every lane issues the same unconditional loads; half 1 then
+            // zeroes chunks 2..7.
+            const float4* f4 = reinterpret_cast<const float4*>(a.feat + sc * kC);
+            const float4* p4 = reinterpret_cast<const float4*>(a.pe + static_cast<int64_t>(r) * 32);
+            const float4* c01 = h ? p4 + 5 : f4;
+            float4 v[8] = {c01[0], c01[1], f4[2], p4[0], p4[1], p4[2], p4[3], p4[4]};
+            const uint32_t keep = static_cast<uint32_t>(h) - 1u;   // all ones in half 0, zero in half 1
             #pragma unroll
-            for (int qq = 0; qq < 4; ++qq) {
-                bf16x8 xv;
-                #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int cc = 8 * qq + e;
-                    const int cidx = 32 * h + cc;
-                    float v;
-                    if (cidx < kC) v = f[cc < kC ? cc : 0];
-                    else if (cidx < kIn) v = per[cidx - kC];
-                    else if (cidx == kIn) v = 1.0f;
-                    else v = 0.0f;
-                    xv[e] = static_cast<__bf16>(v);
+            for (int k = 0; k < 8; ++k) {
+                bf16x4 b;
+                b[0] = static_cast<__bf16>(v[k].x);
+                b[1] = static_cast<__bf16>(v[k].y);
+                b[2] = static_cast<__bf16>(v[k].z);
+                b[3] = static_cast<__bf16>(v[k].w);
+                uint2 bits = __builtin_bit_cast(uint2, b);
+                if (k >= 2) {   // a mask, not a branch: both halves run the same code
+                    bits.x &= keep;
+                    bits.y &= keep;
                 }
-                bf16x4 lo, hi;
-                #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    lo[e] = xv[e];
-                    hi[e] = xv[4 + e];
-                }
-                *reinterpret_cast<bf16x4*>(chunk_at(tB, col_s, 8 * h + 2 * qq)) = lo;
-                *reinterpret_cast<bf16x4*>(chunk_at(tB, col_s, 8 * h + 2 * qq + 1)) = hi;
+                *reinterpret_cast<uint2*>(chunk_at(tB, col_s, 8 * h + k)) = bits;
             }
             if (ok) {
                 float4* rec = a.rec + (static_cast<int64_t>(slot0) + cr.y) * 4;

@@ -136,7 +136,7 @@ __device__ __forceinline__ int64_t live_count(const int64_t* n_kept, int64_t cap
 // ---------------------------------------------------------------------------
 // prep: per-ray encodings and first-layer per-ray part
 // ---------------------------------------------------------------------------
-// base[r][i] = b1[i] + sum_q W1[i][C+q] * PE(d_r)[q];  pe[r][0..31] (27 used)
+// base[r][i] = b1[i] + sum_q W1[i][C+q] * PE(d_r)[q];  pe[r] = [PE(d_r) (27), 1, 0, 0, 0, 0]
 // Per-call preparation in one launch: the first kPackThreads/256 workgroups
 // pack the network's operands; each following workgroup takes two rays: 24
 // threads evaluate the rays' 24 sines and cosines once into LDS, then thread
@@ -178,8 +178,8 @@ __global__ __launch_bounds__(256) void prep_kernel(PackArgs pk, int pack, const 
             se[rr][6 + 6 * fq + c] = cv;
             if (fq == 0) se[rr][c] = dc;
         }
-    } else if (t < 34) {
-        se[(t - 24) / 5][kPE + (t - 24) % 5] = 0.0f;   // pad 27..31
+    } else if (t < 34) {   // entry 27: the first layer's constant input; 28..31 zero
+        se[(t - 24) / 5][kPE + (t - 24) % 5] = (t - 24) % 5 == 0 ? 1.0f : 0.0f;
     }
     __syncthreads();
     const int rr = t >> 7, i = t & (kH - 1);
