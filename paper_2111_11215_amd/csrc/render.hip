@@ -565,22 +565,31 @@ __device__ __forceinline__ bool vertex_grad(const BinArgs& a, int i, int j, int 
     const int nx = a.g.n[0], cy = a.g.n[1] - 1, cz = a.g.n[2] - 1;
     #pragma unroll
     for (int q = 0; q < 13; ++q) acc[q] = 0.0f;
-    bool any = false;
+    // the twelve cell starts first, all in flight together
+    int p0[4], pm[4], p1[4];
     #pragma unroll
     for (int c = 0; c < 4; ++c) {
         const int dx = (c >> 1) & 1, dy = c & 1;
         const int ci = i - dx, cj = j - dy;
+        p0[c] = pm[c] = p1[c] = 0;
         if (ci < 0 || cj < 0 || ci >= nx - 1 || cj >= cy) continue;
         const int row = (ci * cy + cj) * cz;
         const int klo = k > 0 ? k - 1 : 0, khi = k < cz ? k + 1 : cz;   // cells k-1 and k, where they exist
-        const int p0 = a.cell_start[row + klo], pm = a.cell_start[row + k], p1 = a.cell_start[row + khi];
-        int p = p0;
-        for (; p + 1 < p1; p += 2) {
-            add_record(a.rec + static_cast<int64_t>(p) * 4, dx, dy, p < pm, feat, acc);
-            add_record(a.rec + static_cast<int64_t>(p + 1) * 4, dx, dy, p + 1 < pm, feat, acc);
+        p0[c] = a.cell_start[row + klo];
+        pm[c] = a.cell_start[row + k];
+        p1[c] = a.cell_start[row + khi];
+    }
+    bool any = false;
+    #pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int dx = (c >> 1) & 1, dy = c & 1;
+        int p = p0[c];
+        for (; p + 1 < p1[c]; p += 2) {
+            add_record(a.rec + static_cast<int64_t>(p) * 4, dx, dy, p < pm[c], feat, acc);
+            add_record(a.rec + static_cast<int64_t>(p + 1) * 4, dx, dy, p + 1 < pm[c], feat, acc);
         }
-        if (p < p1) add_record(a.rec + static_cast<int64_t>(p) * 4, dx, dy, p < pm, feat, acc);
-        any |= p1 > p0;
+        if (p < p1[c]) add_record(a.rec + static_cast<int64_t>(p) * 4, dx, dy, p < pm[c], feat, acc);
+        any |= p1[c] > p0[c];
     }
     return any;
 }
