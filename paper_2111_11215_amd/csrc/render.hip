@@ -209,6 +209,10 @@ struct GatherArgs {
     float* feat_out;
 };
 
+// kFeat: 0 density only, 1 float32 features, 2 bfloat16 features.  One
+// instantiation per case, so that every corner load of a sample (density and
+// features) is issued before any of them is consumed.
+template <int kFeat>
 __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
     const int64_t n = live_count(a.n_kept, a.cap);
     for (int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; s < n;
@@ -218,40 +222,48 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
         float x[3];
         sample_point(a.sa, r, k, x, nullptr);
         const Tri t = trilinear(a.g, x);
-        float raw = 0.0f;
-        for (int c = 0; c < 8; ++c) raw += t.w[c] * a.density[corner(t, c)];
-        a.raw_out[s] = raw;
-        if (!a.with_feat) continue;
-        float f[kC];
-        for (int ch = 0; ch < kC; ++ch) f[ch] = 0.0f;
-        if (!a.feat_bf16) {
-            const float4* F = static_cast<const float4*>(a.feat);
-            for (int c = 0; c < 8; ++c) {
-                const int64_t v = corner(t, c) * 3;
-                const float4 q0 = F[v], q1 = F[v + 1], q2 = F[v + 2];
-                const float w = t.w[c];
-                f[0] += w * q0.x; f[1] += w * q0.y; f[2] += w * q0.z; f[3] += w * q0.w;
-                f[4] += w * q1.x; f[5] += w * q1.y; f[6] += w * q1.z; f[7] += w * q1.w;
-                f[8] += w * q2.x; f[9] += w * q2.y; f[10] += w * q2.z; f[11] += w * q2.w;
-            }
-        } else {
-            const uint2* F = static_cast<const uint2*>(a.feat);
-            for (int c = 0; c < 8; ++c) {
-                const int64_t v = corner(t, c) * 3;
-                const float w = t.w[c];
-                for (int q = 0; q < 3; ++q) {
-                    const uint2 u = F[v + q];
-                    f[4 * q + 0] += w * __uint_as_float(u.x << 16);
-                    f[4 * q + 1] += w * __uint_as_float(u.x & 0xFFFF0000u);
-                    f[4 * q + 2] += w * __uint_as_float(u.y << 16);
-                    f[4 * q + 3] += w * __uint_as_float(u.y & 0xFFFF0000u);
+        float d[8];
+        float4 q[8][3];
+        #pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int64_t v = corner(t, c);
+            d[c] = a.density[v];
+            if (kFeat == 1) {
+                const float4* F = static_cast<const float4*>(a.feat) + 3 * v;
+                q[c][0] = F[0];
+                q[c][1] = F[1];
+                q[c][2] = F[2];
+            } else if (kFeat == 2) {
+                const uint2* F = static_cast<const uint2*>(a.feat) + 3 * v;
+                #pragma unroll
+                for (int e = 0; e < 3; ++e) {
+                    const uint2 u = F[e];
+                    q[c][e] = make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xFFFF0000u),
+                                          __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xFFFF0000u));
                 }
             }
         }
+        float raw = 0.0f;
+        #pragma unroll
+        for (int c = 0; c < 8; ++c) raw += t.w[c] * d[c];
+        a.raw_out[s] = raw;
+        if (kFeat == 0) continue;
+        float4 f[3] = {make_float4(0, 0, 0, 0), make_float4(0, 0, 0, 0), make_float4(0, 0, 0, 0)};
+        #pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const float w = t.w[c];
+            #pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                f[e].x += w * q[c][e].x;
+                f[e].y += w * q[c][e].y;
+                f[e].z += w * q[c][e].z;
+                f[e].w += w * q[c][e].w;
+            }
+        }
         float4* out = reinterpret_cast<float4*>(a.feat_out + s * kC);
-        out[0] = make_float4(f[0], f[1], f[2], f[3]);
-        out[1] = make_float4(f[4], f[5], f[6], f[7]);
-        out[2] = make_float4(f[8], f[9], f[10], f[11]);
+        out[0] = f[0];
+        out[1] = f[1];
+        out[2] = f[2];
     }
 }
 
@@ -431,7 +443,9 @@ __global__ __launch_bounds__(256) void compose_bwd_kernel(ComposeArgs a) {
     int64_t s0 = a.ray_offset[slot], s1 = a.ray_offset[slot + 1];
     s0 = s0 < n ? s0 : n;
     s1 = s1 < n ? s1 : n;
-    if (s1 <= s0) return;
+    // (r < 0 never holds; testing it keeps the ray's load in flight with
+    // the offsets' instead of after this test)
+    if (s1 <= s0 || r < 0) return;
     const float tn = a.sa.t_near[r];
     const float p = a.sa.jitter ? a.sa.jitter[r] : 0.0f;
     const float step = a.sa.step;
@@ -442,6 +456,13 @@ __global__ __launch_bounds__(256) void compose_bwd_kernel(ComposeArgs a) {
     g[3] = a.grad_depth ? a.grad_depth[r] : 0.0f;
     g[4] = a.grad_acc ? a.grad_acc[r] : 0.0f;
     float logTa = a.log_t_end_in[r];          // log T after the walked suffix
+    float ro[3] = {0.0f, 0.0f, 0.0f}, rd[3] = {0.0f, 0.0f, 0.0f};   // the ray, for the binning
+    if (a.cell_count) {
+        for (int i = 0; i < 3; ++i) {
+            ro[i] = a.sa.rays_o[3 * r + i];
+            rd[i] = a.sa.rays_d[3 * r + i];
+        }
+    }
     const float Tend = expf(logTa);
     float S[5] = {Tend * a.bg[0], Tend * a.bg[1], Tend * a.bg[2], 0.0f, 0.0f};
     const int64_t nsteps = (s1 - s0 + 63) / 64;
@@ -487,7 +508,7 @@ __global__ __launch_bounds__(256) void compose_bwd_kernel(ComposeArgs a) {
             int cell = -1;
             if (ok) {
                 float x[3], f[3];
-                sample_point(a.sa, r, a.sa.sample_k[s], x, nullptr);
+                recipe_x(ro, rd, tk, x);   // the sample's point, as sample_point forms it
                 cell = cell_of(a.g, x, f);
                 a.rec_head[s] = make_float4(f[0], f[1], f[2], draw);
             }
@@ -1072,7 +1093,9 @@ int32_t run_gather(const Common& cm, const dvgo_field* field, bool with_feat, co
     ga.raw_out = reinterpret_cast<float*>(cm.ws + cm.L.raw);
     ga.feat_out = reinterpret_cast<float*>(cm.ws + cm.L.feat);
     const int blocks = grid_for(cm.cap, 256, dvgo::device_cu_count() * 16);
-    DVGO_LAUNCH(K_GATHER, gather_kernel, dim3(blocks), dim3(256), 0, s, ga);
+    if (!with_feat) DVGO_LAUNCH(K_GATHER, gather_kernel<0>, dim3(blocks), dim3(256), 0, s, ga);
+    else if (!ga.feat_bf16) DVGO_LAUNCH(K_GATHER, gather_kernel<1>, dim3(blocks), dim3(256), 0, s, ga);
+    else DVGO_LAUNCH(K_GATHER, gather_kernel<2>, dim3(blocks), dim3(256), 0, s, ga);
     return dvgo::launch_status();
 }
 
