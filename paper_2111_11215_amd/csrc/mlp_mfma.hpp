@@ -897,6 +897,9 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
         const int64_t s0 = static_cast<int64_t>(blockIdx.x) * 128 + col_s;
         r_next = a0.sample_ray[s0 < n ? s0 : n - 1];
     }
+    // (consumed here for the same reason as inside the loop: otherwise the
+    // loop head waits for every outstanding store on each iteration)
+    asm volatile("" ::"v"(r_next));
     for (int64_t blk = blockIdx.x; blk * 128 < n; blk += gridDim.x) {
         const MlpArgs a = refresh(a0);
         const int64_t s = blk * 128 + col_s;
@@ -908,14 +911,12 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
             r_next = a.sample_ray[s1 < n ? s1 : n - 1];
         }
         // per-sample inputs of the head and of the record, issued here so
-        // that their latency hides behind layers 1 and 2
-        const float4 dc = ok && h == 0 ? reinterpret_cast<const float4*>(a.col)[s] : make_float4(0, 0, 0, 0);
-        int2 cr = make_int2(0, 0);
-        float4 rh = make_float4(0, 0, 0, 0);
-        if (q == 0 && ok) {
-            cr = a.cell_rank[s];
-            if (h == 0) rh = a.rec_head[s];
-        }
+        // that their latency hides behind layers 1 and 2.  Every lane loads
+        // (at a clamped, valid index): a load under a lane-dependent branch
+        // is waited on inside that branch.
+        const float4 dc = reinterpret_cast<const float4*>(a.col)[sc];
+        const int2 cr = a.cell_rank[sc];
+        const float4 rh = a.rec_head[sc];
         // ---- layer 1, this half's two tiles, staged as h1 rows
         {
             float f[12];
@@ -969,7 +970,7 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
         }
         if (h == 0) sZ[q][col_s] = make_float4(z3[0], z3[1], z3[2], 0.0f);
         __syncthreads();   // B2: h2 rows and both logit halves complete
-        const int slot0 = q == 0 && ok ? a.cell_start[cr.x] : 0;
+        const int slot0 = a.cell_start[cr.x];   // every lane, as above
         float dz3[3] = {0, 0, 0};
         if (h == 0) {
             const float4 z0 = sZ[0][col_s], z1 = sZ[1][col_s];
@@ -1061,6 +1062,11 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
             }
         }
         __syncthreads();   // B6: h1 and dz2 rows read; the second half's dL/dfeat in sD
+        // Take delivery of the next block's ray index here, long after its
+        // load: the memory counter that a later wait on it would use also
+        // counts the record stores below, so consuming it at the top of the
+        // next block would wait for those stores to complete.
+        asm volatile("" ::"v"(r_next));
         #pragma unroll
         for (int u = 0; u < 4; ++u) stage_row(tA, col_s, 4 * q + u, h, d1[u]);
         if (q == 0) {
