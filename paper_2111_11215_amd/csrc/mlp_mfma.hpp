@@ -748,24 +748,49 @@ __device__ __forceinline__ f32x16 head_bf16(const MlpArgs& a, const f32x16 z2[4]
     return z3;
 }
 
-__device__ __forceinline__ void load_packed_bf16(const MlpArgs& a, bf16x8* sW1, bf16x8* sW2, bf16x8* sW2T,
-                                                 float* sB2) {
-    if (threadIdx.x < kH) sB2[threadIdx.x] = a.b2[threadIdx.x];
-    const bf16x8* g1 = reinterpret_cast<const bf16x8*>(a.w1pb);
-    const bf16x8* g2 = reinterpret_cast<const bf16x8*>(a.w2pb);
-    const bf16x8* g2t = reinterpret_cast<const bf16x8*>(a.w2tpb);
-    for (int i = threadIdx.x; i < kW2PackBF16 / 8; i += blockDim.x) {
-        sW2[i] = g2[i];
-        if (sW2T) sW2T[i] = g2t[i];
+// kN 16-byte operand fragments copied from global memory to LDS by a
+// workgroup of kThreads, in two steps: load() issues a thread's loads into
+// registers, store() writes them to LDS.  Trip counts are compile-time
+// constants, so loads of several copies can all be issued before the first
+// store (a runtime-bounded copy loop waits on each load in turn).
+template <int kThreads, int kN>
+struct Frags {
+    static constexpr int kPer = (kN + kThreads - 1) / kThreads;
+    bf16x8 t[kPer];
+    __device__ __forceinline__ void load(const bf16x8* src) {
+        #pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int i = static_cast<int>(threadIdx.x) + u * kThreads;
+            if (kN % kThreads == 0 || i < kN) t[u] = src[i];
+        }
     }
-    for (int i = threadIdx.x; i < kW1PackBF16 / 8; i += blockDim.x) sW1[i] = g1[i];
+    __device__ __forceinline__ void store(bf16x8* dst) const {
+        #pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int i = static_cast<int>(threadIdx.x) + u * kThreads;
+            if (kN % kThreads == 0 || i < kN) dst[i] = t[u];
+        }
+    }
+};
+
+// The forward's operands: packed W1, W2 and b2 (float32).
+template <int kThreads>
+__device__ __forceinline__ void load_packed_bf16(const MlpArgs& a, bf16x8* sW1, bf16x8* sW2, float* sB2) {
+    Frags<kThreads, kW2PackBF16 / 8> f2;
+    Frags<kThreads, kW1PackBF16 / 8> f1;
+    f2.load(reinterpret_cast<const bf16x8*>(a.w2pb));
+    f1.load(reinterpret_cast<const bf16x8*>(a.w1pb));
+    const float b2 = threadIdx.x < kH ? a.b2[threadIdx.x] : 0.0f;
+    f2.store(sW2);
+    f1.store(sW1);
+    if (threadIdx.x < kH) sB2[threadIdx.x] = b2;
 }
 
 __global__ __launch_bounds__(256, 2) void mlp_fwd_bf16_kernel(MlpArgs a0) {
     __shared__ bf16x8 sW2[kW2PackBF16 / 8];
     __shared__ bf16x8 sW1[kW1PackBF16 / 8];
     __shared__ __attribute__((aligned(16))) float sB2[kH];
-    load_packed_bf16(a0, sW1, sW2, nullptr, sB2);
+    load_packed_bf16<256>(a0, sW1, sW2, sB2);
     __syncthreads();
     const int64_t n = *a0.n_kept < a0.cap ? *a0.n_kept : a0.cap;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -857,19 +882,29 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
     __shared__ bf16x8 sW3T[4 * 64];
     __shared__ bf16x8 sW1T[8 * 64];
     __shared__ float sRed[4 * 4];
-    load_packed_bf16(a0, sW1, sW2, sW2T, sB2);
-    for (int i = threadIdx.x; i < 4 * kBP; i += blockDim.x) sC[i] = static_cast<__bf16>(0.0f);
-    {
-        const bf16x8* g3 = reinterpret_cast<const bf16x8*>(a0.w3pb);
-        const bf16x8* g3t = reinterpret_cast<const bf16x8*>(a0.w3tpb);
-        const bf16x8* g1t = reinterpret_cast<const bf16x8*>(a0.w1tpb);
-        if (threadIdx.x < 3) sB3[threadIdx.x] = a0.b3[threadIdx.x];
-        for (int i = threadIdx.x; i < 8 * 64; i += blockDim.x) {
-            sW3[i] = g3[i];
-            sW1T[i] = g1t[i];
-            if (i < 4 * 64) sW3T[i] = g3t[i];
-        }
+    {   // every operand this kernel keeps in LDS: all loads first, then the stores
+        Frags<512, kW2PackBF16 / 8> f2, f2t;
+        Frags<512, kW1PackBF16 / 8> f1;
+        Frags<512, 8 * 64> f3, f1t;
+        Frags<512, 4 * 64> f3t;
+        f2.load(reinterpret_cast<const bf16x8*>(a0.w2pb));
+        f2t.load(reinterpret_cast<const bf16x8*>(a0.w2tpb));
+        f1.load(reinterpret_cast<const bf16x8*>(a0.w1pb));
+        f3.load(reinterpret_cast<const bf16x8*>(a0.w3pb));
+        f1t.load(reinterpret_cast<const bf16x8*>(a0.w1tpb));
+        f3t.load(reinterpret_cast<const bf16x8*>(a0.w3tpb));
+        const float b2 = threadIdx.x < kH ? a0.b2[threadIdx.x] : 0.0f;
+        const float b3 = threadIdx.x < 3 ? a0.b3[threadIdx.x] : 0.0f;
+        f2.store(sW2);
+        f2t.store(sW2T);
+        f1.store(sW1);
+        f3.store(sW3);
+        f1t.store(sW1T);
+        f3t.store(sW3T);
+        if (threadIdx.x < kH) sB2[threadIdx.x] = b2;
+        if (threadIdx.x < 3) sB3[threadIdx.x] = b3;
     }
+    for (int i = threadIdx.x; i < 4 * kBP; i += blockDim.x) sC[i] = static_cast<__bf16>(0.0f);
     __syncthreads();
     const int64_t n = *a0.n_kept < a0.cap ? *a0.n_kept : a0.cap;
     // The wavefront index in a scalar register: the role branches below are

@@ -410,9 +410,20 @@ __global__ __launch_bounds__(1024) void proposal_reduce_kernel(const float* __re
     __shared__ float sh[16][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int p = blockIdx.x * 64 + lane;
+    // (rows are summed in order, eight rows' loads in flight at a time; a
+    // runtime-bounded one-row loop waits on each load)
     float s = 0.0f;
     if (p < kParams)
-        for (int b = wave; b < nwaves; b += 16) s += partial[static_cast<int64_t>(b) * kPStride + p];
+        for (int b0 = wave; b0 < nwaves; b0 += 16 * 8) {
+            float v[8];
+            #pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int b = b0 + 16 * u;
+                v[u] = b < nwaves ? partial[static_cast<int64_t>(b) * kPStride + p] : 0.0f;
+            }
+            #pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
     sh[wave][lane] = s;
     __syncthreads();
     if (wave == 0 && p < kParams) {
@@ -422,7 +433,13 @@ __global__ __launch_bounds__(1024) void proposal_reduce_kernel(const float* __re
     }
     if (blockIdx.x == 0 && threadIdx.x == 0 && loss) {
         float l = 0.0f;
-        for (int b = 0; b < nwaves; ++b) l += loss_part[b];
+        for (int b0 = 0; b0 < nwaves; b0 += 8) {
+            float v[8];
+            #pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = b0 + u < nwaves ? loss_part[b0 + u] : 0.0f;
+            #pragma unroll
+            for (int u = 0; u < 8; ++u) l += v[u];
+        }
         *loss = l;
     }
 }

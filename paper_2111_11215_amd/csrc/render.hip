@@ -912,10 +912,9 @@ __global__ __launch_bounds__(1024) void scan_apply_kernel(const int* __restrict_
 }
 
 // Deterministic sum of the per-block weight-gradient partials (+= into out):
-// 64 parameters per workgroup, each of the 4 waves sums every 4th partial,
-// then the 4 wave sums are added in a fixed order.
 // 64 parameters per workgroup, 16 wavefronts each summing every 16th
-// partial row, then a fixed-order sum of the 16 (deterministic).  With
+// partial row (all its loads issued before the sum, which keeps the row
+// order), then a fixed-order sum of the 16 (deterministic).  With
 // sq_err, workgroup 0 also forms the photometric loss (1/B) sum of the
 // rays' squared errors, in a fixed order.
 // With net.param, the summed gradient also takes the network's Adam step
@@ -934,9 +933,18 @@ __global__ __launch_bounds__(1024) void reduce_partials_kernel(const float* __re
     __shared__ float sh[16][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int p = blockIdx.x * 64 + lane;
+    static_assert(kMaxBwdBlocks <= 16 * 16, "a wavefront sums at most 16 partial rows");
     float s = 0.0f;
-    if (p < kMlpParams)
-        for (int b = wave; b < nblk; b += 16) s += partial[static_cast<int64_t>(b) * kPStride + p];
+    if (p < kMlpParams) {
+        float v[16];
+        #pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int b = wave + 16 * u;
+            v[u] = b < nblk ? partial[static_cast<int64_t>(b) * kPStride + p] : 0.0f;
+        }
+        #pragma unroll
+        for (int u = 0; u < 16; ++u) s += v[u];
+    }
     sh[wave][lane] = s;
     __syncthreads();
     if (wave == 0 && p < kMlpParams) {
