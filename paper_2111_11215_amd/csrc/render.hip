@@ -965,7 +965,13 @@ __global__ __launch_bounds__(1024) void reduce_partials_kernel(const float* __re
     if (blockIdx.x == 0 && sq_err) {
         __syncthreads();
         float e = 0.0f;
-        for (int i = threadIdx.x; i < B; i += 1024) e += sq_err[i];
+        for (int i0 = threadIdx.x; i0 < B; i0 += 1024 * 8) {   // eight loads in flight, summed in order
+            float v[8];
+            #pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = i0 + 1024 * u < B ? sq_err[i0 + 1024 * u] : 0.0f;
+            #pragma unroll
+            for (int u = 0; u < 8; ++u) e += v[u];
+        }
         for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
         if (lane == 0) sh[0][wave] = e;
         __syncthreads();
