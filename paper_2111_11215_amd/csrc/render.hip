@@ -307,24 +307,47 @@ struct ComposeArgs {
     float4* rec_head;      // [cap] (fx, fy, fz, dL/draw)
 };
 
+// Wavefront scans on DPP lane shifts (VALU operands, no LDS round trip):
+// a Hillis-Steele scan inside each row of 16 lanes (row_shr / row_shl by 1,
+// 2, 4, 8; a lane whose source is outside its row reads 0), then each row
+// adds the totals of the rows before (prefix) or after (suffix) it, read
+// from one lane of each row.
+template <int kCtrl>
+__device__ __forceinline__ float dpp_in_row(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), kCtrl, 0xf, 0xf, true));
+}
+// whole-wavefront shift by one lane (wave_shr:1 / wave_shl:1); the lane
+// without a source reads 0
+template <int kCtrl>
+__device__ __forceinline__ float dpp_wave(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), kCtrl, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float lane_value(float v, int l) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
+// inclusive prefix sum: sum over lanes <= lane
 __device__ __forceinline__ float wave_incl_scan(float v, int lane) {
-    for (int off = 1; off < 64; off <<= 1) {
-        const float y = __shfl_up(v, off, 64);
-        if (lane >= off) v += y;
-    }
-    return v;
+    v += dpp_in_row<0x111>(v);   // row_shr:1
+    v += dpp_in_row<0x112>(v);   // row_shr:2
+    v += dpp_in_row<0x114>(v);   // row_shr:4
+    v += dpp_in_row<0x118>(v);   // row_shr:8
+    const float t0 = lane_value(v, 15), t1 = lane_value(v, 31), t2 = lane_value(v, 47);
+    const int row = lane >> 4;
+    return v + (row == 0 ? 0.0f : row == 1 ? t0 : row == 2 ? t0 + t1 : (t0 + t1) + t2);
 }
 // inclusive suffix sum: sum over lanes >= lane
 __device__ __forceinline__ float wave_incl_suffix(float v, int lane) {
-    for (int off = 1; off < 64; off <<= 1) {
-        const float y = __shfl_down(v, off, 64);
-        if (lane + off < 64) v += y;
-    }
-    return v;
+    v += dpp_in_row<0x101>(v);   // row_shl:1
+    v += dpp_in_row<0x102>(v);   // row_shl:2
+    v += dpp_in_row<0x104>(v);   // row_shl:4
+    v += dpp_in_row<0x108>(v);   // row_shl:8
+    const float s1 = lane_value(v, 16), s2 = lane_value(v, 32), s3 = lane_value(v, 48);
+    const int row = lane >> 4;
+    return v + (row == 3 ? 0.0f : row == 2 ? s3 : row == 1 ? s2 + s3 : s1 + (s2 + s3));
 }
 __device__ __forceinline__ float wave_sum(float v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    return lane_value(wave_incl_scan(v, static_cast<int>(threadIdx.x & 63)), 63);
 }
 
 // Fine cell of a point (its vertex (0,0,0)) and the fractional position f
@@ -394,15 +417,14 @@ __global__ __launch_bounds__(256) void compose_fwd_kernel(ComposeArgs a) {
             }
         }
         const float incl = wave_incl_scan(sd, lane);
-        float excl = __shfl_up(incl, 1, 64);
-        if (lane == 0) excl = 0.0f;
+        const float excl = dpp_wave<0x138>(incl);   // wave_shr:1, lane 0 reads 0
         const float w = ok ? expf(logT - excl) * alpha : 0.0f;
         cr += w * c0; cg += w * c1; cb += w * c2;
         dep += w * tk;
         accw += w;
         if (ok && a.seg_w) atomicAdd(&segs[wave][(32LL * k) / nu], w);
         if (ok && a.sample_w) a.sample_w[s] = w;
-        logT -= __shfl(incl, 63, 64);
+        logT -= lane_value(incl, 63);
     }
     cr = wave_sum(cr); cg = wave_sum(cg); cb = wave_sum(cb);
     dep = wave_sum(dep);
@@ -483,8 +505,7 @@ __global__ __launch_bounds__(256) void compose_bwd_kernel(ComposeArgs a) {
         }
         // log T_{k+1} = logTa + sum of sd over later samples of this step
         const float suf = wave_incl_suffix(sd, lane);
-        float suf_ex = __shfl_down(suf, 1, 64);
-        if (lane == 63) suf_ex = 0.0f;
+        const float suf_ex = dpp_wave<0x130>(suf);   // wave_shl:1, lane 63 reads 0
         const float Tafter = expf(logTa + suf_ex);
         const float w = ok ? Tafter * expm1f(sd) : 0.0f;
         float dsig = 0.0f;
@@ -492,10 +513,9 @@ __global__ __launch_bounds__(256) void compose_bwd_kernel(ComposeArgs a) {
         for (int ch = 0; ch < 5; ++ch) {
             const float wv = w * v[ch];
             const float sfx = wave_incl_suffix(wv, lane);
-            float sfx_ex = __shfl_down(sfx, 1, 64);
-            if (lane == 63) sfx_ex = 0.0f;
+            const float sfx_ex = dpp_wave<0x130>(sfx);
             dsig += g[ch] * (Tafter * v[ch] - (S[ch] + sfx_ex));
-            tot[ch] = __shfl(sfx, 0, 64);
+            tot[ch] = lane_value(sfx, 0);
         }
         const float draw = step * dsig * sigmoid_f(raw + a.act_shift);
         if (ok) {
@@ -515,7 +535,7 @@ __global__ __launch_bounds__(256) void compose_bwd_kernel(ComposeArgs a) {
             const int rank = run_rank(cell, ok, lane, a.cell_count);
             if (ok) a.cell_rank[s] = make_int2(cell, rank);
         }
-        logTa += __shfl(suf, 0, 64);
+        logTa += lane_value(suf, 0);
         for (int ch = 0; ch < 5; ++ch) S[ch] += tot[ch];
     }
 }
