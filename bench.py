@@ -180,8 +180,9 @@ def compare_forms(ctx, iters, rays, keep):
     proposal form from identical initial states on identical batches;
     report throughput (uniform-equivalent ray-samples/s of the whole
     iteration, proposal work included) and mean PSNR on the 10 held-out
-    views, plus what the trained proposal gains over an untrained one and
-    over none.  Returns (report, (model, proposal) of the form ``keep``)."""
+    views, the time of one 800x800 inference frame, plus what the trained
+    proposal gains over an untrained one and over none.  Returns (report,
+    (model, proposal) of the form ``keep``)."""
     from paper_2111_11215_amd import experiment
     log(f"bench: comparison, {iters} iterations per form")
     batches = make_batches(ctx, iters, rays)
@@ -198,7 +199,8 @@ def compare_forms(ctx, iters, rays, keep):
         entry = {"seconds": st.seconds, "ms_per_step": 1e3 * st.seconds / iters,
                  "ray_samples_per_s": st.samples_per_s, "psnr_db": experiment.psnr_views(model, views),
                  "loss_first_last": [st.losses[0][1], st.losses[-1][1]],
-                 "evaluated_per_step_end": experiment.evaluated_per_step(model, batches[-4:], prop)}
+                 "evaluated_per_step_end": experiment.evaluated_per_step(model, batches[-4:], prop),
+                 "render_frame_ms": experiment.frame_ms(model, views[0])}
         if prop is not None:
             entry["all_segments_rate_end"] = st.fallback_rate[-1][1]
             entry["prop_loss_first_last"] = [st.prop_losses[0][1], st.prop_losses[-1][1]]
@@ -211,7 +213,8 @@ def compare_forms(ctx, iters, rays, keep):
                     "untrained": experiment.proposal_render_psnr(model, fresh, views[:2]),
                     "trained": experiment.proposal_render_psnr(model, prop, views[:2])}}
         res[name] = entry
-        log(f"bench: {name}: {entry['ms_per_step']:.3f} ms/step, psnr {entry['psnr_db']:.3f} dB")
+        log(f"bench: {name}: {entry['ms_per_step']:.3f} ms/step, psnr {entry['psnr_db']:.3f} dB, "
+            f"800x800 frame {entry['render_frame_ms']:.1f} ms")
         if form == keep:
             kept = (model, prop)
         else:

@@ -106,6 +106,19 @@ def psnr_views(model: train.FineModel, views) -> float:
     return sum(vals) / len(vals)
 
 
+def frame_ms(model: train.FineModel, view, reps: int = 3) -> float:
+    """Wall time of rendering one held-out view with the plain sampler and
+    no jitter (the inference path: sample, gather, network, compositing),
+    in ms per frame, averaged over `reps` renders after one untimed one."""
+    train.render_rays(model, view.o, view.d)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        train.render_rays(model, view.o, view.d)
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0) / reps
+
+
 def proposal_render_psnr(model: train.FineModel, prop: train.ProposalModel, views) -> float:
     """PSNR of the proposal-sampled render against the plain-sampled render
     of the same model (how much of the image the proposal keeps)."""
