@@ -1,5 +1,8 @@
 """Device-code checks on the gfx950 assembly of the library's own sources.
 
+Two checks: no matrix instruction under an unguarded exec mask (below), and
+no write through the scalar data cache anywhere (vector stores only).
+
 A matrix instruction (v_mfma_*) placed in a region where EXEC has been
 narrowed by a vector branch, with no branch that skips the region when EXEC
 is empty, still updates its accumulator in a wavefront that should have
@@ -22,6 +25,7 @@ import pytest
 from paper_2111_11215_amd import build as B
 
 MFMA_SOURCES = ["render.hip", "proposal.hip"]
+ALL_SOURCES = ["abi.hip", "sampler.hip", "render.hip", "optim.hip", "proposal.hip", "scene.hip"]
 
 _NARROW = re.compile(r"s_(and|or|andn2|xor|nand|nor|orn2)_saveexec_b64|s_mov_b64 exec, (?!-1)|"
                      r"s_(and|andn2|xor)_b64 exec, ")
@@ -89,4 +93,26 @@ def test_no_matrix_instruction_under_an_unguarded_exec_mask(tmp_path):
     total = sum(a.count("v_mfma") for a in asms)
     assert total > 100, "expected the network kernels' matrix instructions in the assembly"
     bad = [x for a in asms for x in masked_mfmas(a)]
+    assert bad == [], bad[:5]
+
+
+_SCALAR_WRITE = re.compile(r"^\s*(s_store_|s_buffer_store|s_scratch_store|s_atomic_|s_buffer_atomic_|s_dcache_wb|s_dcache_discard)")
+
+
+def test_scalar_write_pattern():
+    assert _SCALAR_WRITE.match("\ts_store_dword s4, s[2:3], 0x10")
+    assert _SCALAR_WRITE.match("\ts_atomic_add s4, s[2:3], 0x0")
+    assert _SCALAR_WRITE.match("\ts_dcache_wb")
+    assert not _SCALAR_WRITE.match("\ts_load_dwordx2 s[0:1], s[4:5], 0x0")
+    assert not _SCALAR_WRITE.match("\tglobal_store_dword v0, v1, s[2:3]")
+
+
+@pytest.mark.skipif(not _have_hipcc(), reason="hipcc not available")
+def test_no_scalar_cache_writes(tmp_path):
+    """Device code writes memory through vector stores only: no scalar-cache
+    stores, atomics, write-backs or discards in any kernel."""
+    with ThreadPoolExecutor(max_workers=len(ALL_SOURCES)) as ex:
+        asms = list(ex.map(lambda s: _device_asm(s, str(tmp_path)), ALL_SOURCES))
+    bad = [(src, no, line.strip()) for src, asm in zip(ALL_SOURCES, asms)
+           for no, line in enumerate(asm.splitlines(), 1) if _SCALAR_WRITE.match(line)]
     assert bad == [], bad[:5]
