@@ -180,6 +180,7 @@ struct MlpArgs {
     const int* cell_start;    // [ncell + 1]
     const float4* rec_head;   // [cap] (fx, fy, fz, dL/draw)
     float4* rec;              // [cap][4] binned records
+    int nrays;                // rows of base and pe
 };
 
 __device__ __forceinline__ float4* binned_record(const MlpArgs& a, int64_t s) {
@@ -877,30 +878,45 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
     __shared__ __attribute__((aligned(16))) float sX[128 * kC];
     float4 (*sZ)[128] = reinterpret_cast<float4 (*)[128]>(sX);
     float (*sD)[kC] = reinterpret_cast<float (*)[kC]>(sX);
-    // Packed operands of the head (W3, W3^T) and of dL/dfeat (W1[:, :12]^T).
-    __shared__ bf16x8 sW3[8 * 64];
-    __shared__ bf16x8 sW3T[4 * 64];
-    __shared__ bf16x8 sW1T[8 * 64];
+    // Packed operands of the head (W3, W3^T) and of dL/dfeat (W1[:, :12]^T),
+    // only the lanes whose fragments are not zero: W3 rows 0..2 and W1^T
+    // rows 0..11 (both lane halves), W3^T's lane half 0 (its K is the three
+    // colour channels).  Other lanes use a zero fragment.
+    __shared__ bf16x8 sW3c[8 * 2 * 3];
+    __shared__ bf16x8 sW3Tc[4 * 32];
+    __shared__ bf16x8 sW1Tc[8 * 2 * kC];
+    // The next block's layer-1 inputs, copied straight from global memory to
+    // LDS during the current block (no registers): the first-layer rows of
+    // the rays r0 .. r0 + kPreRays - 1 (r0: the ray of the block's first
+    // sample) and the features of the block's 128 samples.
+    constexpr int kPreRays = 8;
+    __shared__ __attribute__((aligned(16))) float sPB[kPreRays * kH];
+    __shared__ __attribute__((aligned(16))) float sPF[128 * kC];
     __shared__ float sRed[4 * 4];
     {   // every operand this kernel keeps in LDS: all loads first, then the stores
         Frags<512, kW2PackBF16 / 8> f2, f2t;
         Frags<512, kW1PackBF16 / 8> f1;
-        Frags<512, 8 * 64> f3, f1t;
-        Frags<512, 4 * 64> f3t;
         f2.load(reinterpret_cast<const bf16x8*>(a0.w2pb));
         f2t.load(reinterpret_cast<const bf16x8*>(a0.w2tpb));
         f1.load(reinterpret_cast<const bf16x8*>(a0.w1pb));
-        f3.load(reinterpret_cast<const bf16x8*>(a0.w3pb));
-        f1t.load(reinterpret_cast<const bf16x8*>(a0.w1tpb));
-        f3t.load(reinterpret_cast<const bf16x8*>(a0.w3tpb));
+        // the compact operands, at most one fragment per thread each;
+        // fragment (st, lane) of a packed operand is at st * 64 + lane
+        const int ti = static_cast<int>(threadIdx.x);
+        const bf16x8* g3 = reinterpret_cast<const bf16x8*>(a0.w3pb);
+        const bf16x8* g3t = reinterpret_cast<const bf16x8*>(a0.w3tpb);
+        const bf16x8* g1t = reinterpret_cast<const bf16x8*>(a0.w1tpb);
+        bf16x8 c3, c3t, c1t;
+        if (ti < 8 * 2 * 3) c3 = g3[(ti / 6) * 64 + 32 * ((ti / 3) & 1) + ti % 3];
+        if (ti < 4 * 32) c3t = g3t[(ti / 32) * 64 + ti % 32];
+        if (ti < 8 * 2 * kC) c1t = g1t[(ti / (2 * kC)) * 64 + 32 * ((ti / kC) & 1) + ti % kC];
         const float b2 = threadIdx.x < kH ? a0.b2[threadIdx.x] : 0.0f;
         const float b3 = threadIdx.x < 3 ? a0.b3[threadIdx.x] : 0.0f;
         f2.store(sW2);
         f2t.store(sW2T);
         f1.store(sW1);
-        f3.store(sW3);
-        f1t.store(sW1T);
-        f3t.store(sW3T);
+        if (ti < 8 * 2 * 3) sW3c[ti] = c3;
+        if (ti < 4 * 32) sW3Tc[ti] = c3t;
+        if (ti < 8 * 2 * kC) sW1Tc[ti] = c1t;
         if (threadIdx.x < kH) sB2[threadIdx.x] = b2;
         if (threadIdx.x < 3) sB3[threadIdx.x] = b3;
     }
@@ -924,26 +940,55 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
         dX[rr] = 0.0f;
     }
     float db3[3] = {0, 0, 0};
-    bf16x8 ones;
+    bf16x8 ones, zero8;
     #pragma unroll
-    for (int e = 0; e < 8; ++e) ones[e] = static_cast<__bf16>(m == 0 ? 1.0f : 0.0f);
-    int r_next = 0;
+    for (int e = 0; e < 8; ++e) {
+        ones[e] = static_cast<__bf16>(m == 0 ? 1.0f : 0.0f);
+        zero8[e] = static_cast<__bf16>(0.0f);
+    }
+    // Block b's layer-1 inputs into sPB / sPF, by every wavefront: waves
+    // 0..3 copy a 1 KB piece of sPB each (two 512-byte rows; rows past the
+    // last ray read the last), waves 4..7 and 0..1 the six 1 KB pieces of
+    // sPF (addresses past the capacity read the last feature quad).  The
+    // copies land asynchronously; a wait on all memory operations precedes
+    // the barrier before their use.
+    typedef __attribute__((address_space(3))) void lds_void;
+    auto prefetch = [&](const MlpArgs& a, int64_t b, int r0) {
+        if (wave < 4) {
+            const int row = 2 * wave + (lane >> 5);
+            const int rr = r0 + row < a.nrays ? r0 + row : a.nrays - 1;
+            __builtin_amdgcn_global_load_lds(a.base + static_cast<int64_t>(rr) * kH + 4 * (lane & 31),
+                                             (lds_void*)(sPB + 256 * wave), 16, 0, 0);
+        }
+        if (wave >= 4 || wave < 2) {
+            const int piece = wave >= 4 ? wave - 4 : wave + 4;
+            const int64_t fmax = a.cap * kC - 4;
+            int64_t fo = b * 128 * kC + 256 * piece + 4 * lane;
+            fo = fo < fmax ? fo : fmax;
+            __builtin_amdgcn_global_load_lds(a.feat + fo, (lds_void*)(sPF + 256 * piece), 16, 0, 0);
+        }
+    };
+    int r_next = 0, r0 = 0;   // r0: the ray of the current block's first sample (scalar)
     if (static_cast<int64_t>(blockIdx.x) * 128 < n) {
         const int64_t s0 = static_cast<int64_t>(blockIdx.x) * 128 + col_s;
         r_next = a0.sample_ray[s0 < n ? s0 : n - 1];
+        r0 = __builtin_amdgcn_readfirstlane(a0.sample_ray[static_cast<int64_t>(blockIdx.x) * 128]);
+        prefetch(a0, blockIdx.x, r0);
     }
-    // (consumed here for the same reason as inside the loop: otherwise the
-    // loop head waits for every outstanding store on each iteration)
-    asm volatile("" ::"v"(r_next));
+    __builtin_amdgcn_s_waitcnt(0);   // the first block's copies (and r_next)
+    __syncthreads();
     for (int64_t blk = blockIdx.x; blk * 128 < n; blk += gridDim.x) {
         const MlpArgs a = refresh(a0);
         const int64_t s = blk * 128 + col_s;
         const bool ok = s < n;
         const int64_t sc = ok ? s : n - 1;
         const int r = r_next;
-        if ((blk + gridDim.x) * 128 < n) {
+        const bool more = (blk + gridDim.x) * 128 < n;
+        int r0_next = r0;
+        if (more) {
             const int64_t s1 = (blk + gridDim.x) * 128 + col_s;
             r_next = a.sample_ray[s1 < n ? s1 : n - 1];
+            r0_next = a.sample_ray[(blk + gridDim.x) * 128];
         }
         // per-sample inputs of the head and of the record, issued here so
         // that their latency hides behind layers 1 and 2.  Every lane loads
@@ -954,14 +999,19 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
         const float4 rh = a.rec_head[sc];
         // ---- layer 1, this half's two tiles, staged as h1 rows
         {
+            // features and the ray's first-layer row from the copies in LDS
+            // (a ray outside the copied rows reads global memory); a sample
+            // past the end takes zero features, its copy may be stale
             float f[12];
-            load_feat(a.feat, sc, f);
+            load_feat(sPF, col_s, f);
             f32x16 h1[2];
-            load_base2(a.base, r, h, 2 * q, h1);
+            const unsigned d = static_cast<unsigned>(r - r0);
+            if (d < static_cast<unsigned>(kPreRays)) load_base2(sPB, static_cast<int>(d), h, 2 * q, h1);
+            else load_base2(a.base, r, h, 2 * q, h1);
             bf16x8 fb;
             #pragma unroll
             for (int e = 0; e < 8; ++e)
-                fb[e] = static_cast<__bf16>(h ? (e < kC - 8 ? f[8 + (e < kC - 8 ? e : 0)] : 0.0f) : f[e]);
+                fb[e] = static_cast<__bf16>(!ok ? 0.0f : h ? (e < kC - 8 ? f[8 + (e < kC - 8 ? e : 0)] : 0.0f) : f[e]);
             #pragma unroll
             for (int t = 0; t < 2; ++t) {
                 h1[t] = mma_bf16(sW1[(2 * q + t) * 64 + lane], fb, h1[t]);
@@ -969,7 +1019,7 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
                 for (int gg = 0; gg < 2; ++gg) stage_row(tA, col_s, 4 * q + 2 * t + gg, h, relu_pack8(h1[t], gg));
             }
         }
-        __syncthreads();   // B1: h1 rows complete
+        __syncthreads();   // B1: h1 rows complete; sPB, sPF read
         // ---- layer 2 and the head on this half
         f32x16 z2[2];
         #pragma unroll
@@ -1000,11 +1050,16 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
                     const int st = 4 * q + 2 * t + gg;
                     h2h[2 * t + gg] = relu_pack8(z2[t], gg);
                     stage_row(tB, col_s, st, h, h2h[2 * t + gg]);
-                    z3 = mma_bf16(sW3[st * 64 + lane], h2h[2 * t + gg], z3);
+                    z3 = mma_bf16(m < 3 ? sW3c[(st * 2 + h) * 3 + (m < 3 ? m : 0)] : zero8, h2h[2 * t + gg], z3);
                 }
         }
         if (h == 0) sZ[q][col_s] = make_float4(z3[0], z3[1], z3[2], 0.0f);
         __syncthreads();   // B2: h2 rows and both logit halves complete
+        // The next block's copies, issued after layers 1 and 2 (the wait on
+        // its first ray, loaded with this block's first loads, then costs
+        // little) and before this block's record-slot load (which that wait
+        // would otherwise include).
+        if (more) prefetch(a, blk + gridDim.x, __builtin_amdgcn_readfirstlane(r0_next));
         const int slot0 = a.cell_start[cr.x];   // every lane, as above
         float dz3[3] = {0, 0, 0};
         if (h == 0) {
@@ -1037,7 +1092,7 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
                 f32x16 dh;
                 #pragma unroll
                 for (int rr = 0; rr < 16; ++rr) dh[rr] = 0.0f;
-                dh = mma_bf16(sW3T[(2 * q + t) * 64 + lane], dzb, dh);
+                dh = mma_bf16(h == 0 ? sW3Tc[(2 * q + t) * 32 + m] : zero8, dzb, dh);
                 #pragma unroll
                 for (int gg = 0; gg < 2; ++gg) zh[2 * t + gg] = relu_grad_pack8(dh, gg, h2h[2 * t + gg]);
             }
@@ -1085,7 +1140,7 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
                 for (int gg = 0; gg < 2; ++gg) {
                     const int st = 4 * q + 2 * t + gg;
                     d1[2 * t + gg] = relu_grad_pack8(dh1[t], gg, read_row(tA, col_s, st, h));
-                    dft = mma_bf16(sW1T[st * 64 + lane], d1[2 * t + gg], dft);
+                    dft = mma_bf16(m < kC ? sW1Tc[(st * 2 + h) * kC + (m < kC ? m : 0)] : zero8, d1[2 * t + gg], dft);
                 }
         }
         if (q == 1) {
@@ -1147,7 +1202,9 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
         #pragma unroll
         for (int st = 0; st < 8; ++st)
             dW1 = mma_bf16(tr_operand(tA, 16 * st, 32 * g, lane), tr_operand(tB, 16 * st, 32 * q, lane), dW1);
+        __builtin_amdgcn_s_waitcnt(0);   // the next block's copies to sPB, sPF have landed
         __syncthreads();   // B8: rows read before the next block's staging
+        r0 = __builtin_amdgcn_readfirstlane(r0_next);
     }
     // ---- epilogue: this workgroup's partial of the flat gradient
     float* out = a0.partial + static_cast<int64_t>(blockIdx.x) * kPStride;

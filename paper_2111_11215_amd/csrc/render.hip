@@ -1135,6 +1135,7 @@ int32_t run_gather(const Common& cm, const dvgo_field* field, bool with_feat, co
 
 MlpArgs make_mlp_args(const Common& cm, const dvgo_mlp* mlp, const int64_t* n_kept) {
     MlpArgs ma;
+    ma.nrays = cm.B;
     ma.sample_ray = cm.sa.sample_ray;
     ma.n_kept = n_kept;
     ma.cap = cm.cap;
