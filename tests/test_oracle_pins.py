@@ -219,6 +219,75 @@ def test_positional_encoding_values():
     assert abs(pe[0, 3] - 0.5646424733950354) < 1e-15
 
 
+@pytest.mark.parametrize("channels", [0, 3])
+def test_interp_scatter_is_the_transpose_of_interp(channels):
+    """<interp(V, x), u> = <V, scatter(x, u)> for every V and u (the
+    definition of the adjoint the grid gradients use), with points inside,
+    on the faces of and outside the box (clamped cells)."""
+    rng = np.random.default_rng(7)
+    shape = (5, 4, 6) + ((channels,) if channels else ())
+    bmin, bmax = np.array([-1.0, 0.0, 2.0]), np.array([1.0, 3.0, 4.5])
+    x = bmin + (bmax - bmin) * rng.uniform(-0.2, 1.2, size=(200, 3))
+    x[:4] = [bmin, bmax, [0.0, 1.5, 3.0], [bmin[0], bmax[1], 3.3]]
+    V = rng.normal(size=shape)
+    u = rng.normal(size=(200, channels) if channels else (200,))
+    lhs = np.sum(O.interp(V, x, bmin, bmax) * u)
+    rhs = np.sum(V * O.interp_scatter(shape, x, bmin, bmax, u))
+    assert abs(lhs - rhs) < 1e-10 * (1.0 + abs(lhs))
+
+
+def test_interp_scatter_hand_example():
+    """One sample at the centre of the single cell of a 2x2x2 grid puts an
+    eighth of its value on each vertex; one on a vertex puts all of it there."""
+    out = O.interp_scatter((2, 2, 2), np.array([[0.5, 0.5, 0.5]]), [0, 0, 0], [1, 1, 1], np.array([8.0]))
+    assert np.array_equal(out, np.ones((2, 2, 2)))
+    out = O.interp_scatter((3, 3, 3), np.array([[1.0, 0.0, 0.5]]), [0, 0, 0], [1, 1, 1], np.array([2.0]))
+    want = np.zeros((3, 3, 3))
+    want[2, 0, 1] = 2.0
+    assert np.allclose(out, want, atol=1e-15)
+
+
+def test_lr_decay_reaches_a_tenth_at_20k():
+    """The learning rate decays exponentially to 0.1x over 20k iterations
+    (supplementary implementation details)."""
+    assert O.lr_at(1e-3, 0) == 1e-3
+    assert abs(O.lr_at(1e-3, 20000) - 1e-4) < 1e-18
+    assert abs(O.lr_at(1e-3, 10000) - 1e-3 / math.sqrt(10.0)) < 1e-18
+    lrs = [O.lr_at(0.1, it) for it in range(0, 20001, 1000)]
+    assert all(a > b for a, b in zip(lrs, lrs[1:]))
+    assert all(abs(b / a - 0.1 ** 0.05) < 1e-12 for a, b in zip(lrs, lrs[1:]))
+
+
+def test_psnr_decibels():
+    """PSNR of images in [0, 1] is -10 log10(MSE): 0 dB at MSE 1, 10 dB per
+    decade."""
+    assert O.psnr(1.0) == 0.0
+    assert abs(O.psnr(1e-2) - 20.0) < 1e-12
+    assert abs(O.psnr(1e-3) - 30.0) < 1e-12
+    assert abs(O.psnr(0.5) - 3.010299956639812) < 1e-12
+
+
+def test_proposal_encoding_entry_point_and_layout():
+    """The proposal input is PE of the box-entry point in [-1, 1]^3 box
+    coordinates followed by PE of the direction: rays entering at a face
+    centre give known coordinates."""
+    o = np.array([[-2.0, 0.0, 0.0], [1.0, 1.0, -1.0]])
+    d = np.array([[1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    tn = np.array([1.0, 1.0])
+    enc = O.proposal_encoding(o[:1], d[:1], tn[:1], [-1, -1, -1], [1, 1, 1])
+    assert enc.shape == (1, 54)
+    assert np.allclose(enc[0, :3], [-1.0, 0.0, 0.0])
+    assert np.allclose(enc[0, 3:6], [math.sin(-1.0), 0.0, 0.0])
+    assert np.allclose(enc[0, 6:9], [math.cos(-1.0), 1.0, 1.0])
+    assert np.allclose(enc[0, 27:30], d[0])
+    assert np.allclose(enc[0, 48:51], np.sin(8 * d[0]))
+    # box [0,2]^3: entry point (1, 1, 0) is (0, 0, -1) in box coordinates
+    enc = O.proposal_encoding(o[1:], d[1:], tn[1:], [0, 0, 0], [2, 2, 2])
+    assert np.allclose(enc[0, :3], [0.0, 0.0, -1.0])
+    assert np.allclose(enc[0, 27:30], [0.0, 0.0, 1.0])
+    assert np.allclose(enc[0, 51:54], np.cos(8 * d[1]))
+
+
 def test_mlp_matches_torch_functional():
     rng = np.random.default_rng(2)
     Ws, bs = synth.xavier_uniform_mlp(rng, (39, 128, 128, 3))
