@@ -228,48 +228,71 @@ __global__ __launch_bounds__(256) void count_kept_kernel(KeepArgs a, int* __rest
     if (lane == 0) counts[slot] = cnt;
 }
 
-// Single-workgroup exclusive scan: ray_offset[i] = sum_{j<i} counts[j].
+// Inclusive prefix sum over a wavefront on DPP lane shifts: a Hillis-Steele
+// scan inside each row of 16 lanes (row_shr by 1, 2, 4, 8; a lane whose
+// source lies outside its row reads 0), then each row adds the totals of the
+// rows before it, read from their last lanes.
+template <int kCtrl>
+__device__ __forceinline__ int dpp_row_shr(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, kCtrl, 0xf, 0xf, true);
+}
+__device__ __forceinline__ int wave_incl_scan_int(int v, int lane) {
+    v += dpp_row_shr<0x111>(v);
+    v += dpp_row_shr<0x112>(v);
+    v += dpp_row_shr<0x114>(v);
+    v += dpp_row_shr<0x118>(v);
+    const int t0 = __builtin_amdgcn_readlane(v, 15), t1 = __builtin_amdgcn_readlane(v, 31),
+              t2 = __builtin_amdgcn_readlane(v, 47);
+    const int row = lane >> 4;
+    return v + (row == 0 ? 0 : row == 1 ? t0 : row == 2 ? t0 + t1 : t0 + t1 + t2);
+}
+
+// Single-workgroup exclusive scan: ray_offset[i] = sum_{j<i} counts[j].  The
+// total is below 2^31 (the host bounds B * max_samples), so the scan runs in
+// 32-bit integers.  Each thread takes kPer consecutive counts, so one pass
+// covers kScanThreads * kPer = 8192 rays.
 __global__ __launch_bounds__(kScanThreads) void scan_offsets_kernel(const int* __restrict__ counts, int B,
                                                                    int* __restrict__ ray_offset,
                                                                    int64_t* __restrict__ n_kept) {
-    __shared__ long long wsum[kScanThreads / 64];
-    __shared__ long long carry_s;
+    constexpr int kPer = 8;
+    __shared__ int wsum[kScanThreads / 64];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    if (tid == 0) carry_s = 0;
-    __syncthreads();
-    constexpr int kPer = 4;
-    for (int base = 0; base < B; base += kScanThreads * kPer) {
-        long long v[kPer];
-        long long local = 0;
-        for (int u = 0; u < kPer; ++u) {
-            const int i = base + tid * kPer + u;
-            v[u] = i < B ? counts[i] : 0;
-            local += v[u];
+    const bool vec = (reinterpret_cast<uintptr_t>(counts) & 15u) == 0;
+    int carry = 0;   // same value in every thread
+    for (int64_t base = 0; base < B; base += kScanThreads * kPer) {
+        const int64_t i0 = base + tid * kPer;
+        int v[kPer];
+        if (vec && i0 + kPer <= B) {
+            const int4 a = *reinterpret_cast<const int4*>(counts + i0);
+            const int4 b = *reinterpret_cast<const int4*>(counts + i0 + 4);
+            v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+            v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+        } else {
+            for (int u = 0; u < kPer; ++u) v[u] = i0 + u < B ? counts[i0 + u] : 0;
         }
-        // inclusive wave scan of `local`
-        long long incl = local;
-        for (int off = 1; off < 64; off <<= 1) {
-            const long long y = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += y;
-        }
+        int local = 0;
+        for (int u = 0; u < kPer; ++u) local += v[u];
+        const int incl = wave_incl_scan_int(local, lane);
         if (lane == 63) wsum[wave] = incl;
         __syncthreads();
-        long long wave_off = 0;
-        for (int w = 0; w < wave; ++w) wave_off += wsum[w];
-        long long run = carry_s + wave_off + incl - local;
+        int wave_off = 0, total = 0;
+        for (int w = 0; w < kScanThreads / 64; ++w) {
+            const int t = wsum[w];
+            wave_off += w < wave ? t : 0;
+            total += t;
+        }
+        int run = carry + wave_off + incl - local;
         for (int u = 0; u < kPer; ++u) {
-            const int i = base + tid * kPer + u;
-            if (i < B) ray_offset[i] = static_cast<int>(run);
+            if (i0 + u < B) ray_offset[i0 + u] = run;
             run += v[u];
         }
-        __syncthreads();
-        if (tid == kScanThreads - 1) carry_s = run;
-        __syncthreads();
+        carry += total;
+        __syncthreads();   // wsum is rewritten by the next pass
     }
     if (tid == 0) {
-        ray_offset[B] = static_cast<int>(carry_s);
-        *n_kept = carry_s;
+        ray_offset[B] = carry;
+        *n_kept = carry;
     }
 }
 

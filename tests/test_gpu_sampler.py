@@ -153,3 +153,24 @@ def test_sampler_full_size_scene(gpu_lib):
         want = sub["sample_k"][sub["ray_offset"][i]:sub["ray_offset"][i + 1]]
         assert np.array_equal(got, want), slot
     print(f"  kept {int(np_of(s.n_kept)[0])} of {int(nu.sum())} uniform samples", flush=True)
+
+
+@pytest.mark.parametrize("n_rays", [1, 7, 8193, 20001])
+def test_sampler_offsets_span_several_scan_passes(gpu_lib, n_rays):
+    """Ray offsets over batches that take one, two and three passes of the
+    single-workgroup scan (8192 rays each), ragged tails included.  Without a
+    coarse or segment mask every uniform sample is kept, so the offsets are
+    the exclusive cumulative sum of the oracle's uniform counts."""
+    from paper_2111_11215_amd import api
+    P = synth.tiny_config(3, jitter=True, n_rays=n_rays)
+    s = api.sample_rays(to_dev(P.rays.o), to_dev(P.rays.d), to_dev(P.rays.jitter), P.box_min, P.box_max, P.step,
+                        P.max_samples)
+    tn, tf, v = O.ray_box_clip(P.rays.o, P.rays.d, P.box_min, P.box_max)
+    nu = O.uniform_count(tn, tf, v, P.rays.jitter, P.step, P.max_samples).astype(np.int64)
+    want = np.concatenate([[0], np.cumsum(nu)])
+    print(f"  B={n_rays} kept={int(want[-1])}", flush=True)
+    assert np.array_equal(np_of(s.n_uniform), nu)
+    assert np.array_equal(np_of(s.ray_offset).astype(np.int64), want)
+    assert int(np_of(s.n_kept)[0]) == int(want[-1])
+    sr = np_of(s.sample_ray)[:int(want[-1])]
+    assert np.array_equal(sr, np.repeat(np.arange(n_rays), nu))
