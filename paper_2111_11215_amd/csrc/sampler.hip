@@ -296,15 +296,10 @@ __global__ __launch_bounds__(kScanThreads) void scan_offsets_kernel(const int* _
     }
 }
 
-// One wavefront per ray slot: write the kept (ray, k) pairs in ascending k.
-__global__ __launch_bounds__(256) void fill_kept_kernel(KeepArgs a, const int* __restrict__ ray_offset,
-                                                        int64_t capacity, int* __restrict__ sample_ray,
-                                                        int* __restrict__ sample_k) {
-    const int slot = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (slot >= a.B) return;
-    const RayView v = load_ray(a, slot);
-    int64_t pos0 = ray_offset[slot];
+// Kept (ray, k) pairs of one ray in ascending k from list position pos0
+// (one wavefront; pairs past the capacity are dropped).
+__device__ __forceinline__ void fill_ray(const KeepArgs& a, const RayView& v, int64_t pos0, int64_t capacity,
+                                         int* __restrict__ sample_ray, int* __restrict__ sample_k, int lane) {
     for (int base = 0; base < v.n; base += 64) {
         const int k = base + lane;
         const bool keep = keep_sample(a, v, k);
@@ -316,6 +311,87 @@ __global__ __launch_bounds__(256) void fill_kept_kernel(KeepArgs a, const int* _
         }
         pos0 += __popcll(mask);
     }
+}
+
+// One wavefront per ray slot: write the kept (ray, k) pairs in ascending k.
+__global__ __launch_bounds__(256) void fill_kept_kernel(KeepArgs a, const int* __restrict__ ray_offset,
+                                                        int64_t capacity, int* __restrict__ sample_ray,
+                                                        int* __restrict__ sample_k) {
+    const int slot = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (slot >= a.B) return;
+    const RayView v = load_ray(a, slot);
+    fill_ray(a, v, ray_offset[slot], capacity, sample_ray, sample_k, lane);
+}
+
+// Ray offsets and the kept pairs in one launch, for batches of at most
+// kFusedMaxRays rays.  A workgroup takes kFillRays consecutive ray slots, one
+// per wavefront.  It sums the counts of every slot before its first (at most
+// kFusedMaxRays / 1024 loads per thread, all issued before the sum), adds the
+// counts of the slots before each wavefront's own, writes the slots' offsets
+// (the workgroup holding the last slot also writes ray_offset[B] and n_kept)
+// and fills.  Integer sums, so every offset equals the scan's.
+constexpr int kFillRays = 16;
+constexpr int kFusedMaxRays = 16384;
+
+__global__ __launch_bounds__(1024) void offsets_fill_kernel(KeepArgs a, const int* __restrict__ counts,
+                                                            int* __restrict__ ray_offset,
+                                                            int64_t* __restrict__ n_kept, int64_t capacity,
+                                                            int* __restrict__ sample_ray,
+                                                            int* __restrict__ sample_k) {
+    constexpr int kLoads = kFusedMaxRays / 1024;
+    __shared__ int wpart[16];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int first = blockIdx.x * kFillRays;
+    const int slot = first + wave;
+    // counts of this workgroup's slots (lanes 0..15; clamped, masked below)
+    const int own_i = first + (lane & (kFillRays - 1));
+    const int own = counts[own_i < a.B ? own_i : a.B - 1];
+    // counts of all slots before the workgroup's first
+    int c[kLoads];
+    #pragma unroll
+    for (int u = 0; u < kLoads; ++u) {
+        c[u] = 0;
+        if (1024 * u < first) {   // workgroup-uniform
+            const int i = tid + 1024 * u;
+            c[u] = counts[i < first ? i : first - 1];
+        }
+    }
+    int part = 0;
+    #pragma unroll
+    for (int u = 0; u < kLoads; ++u) part += tid + 1024 * u < first ? c[u] : 0;
+    // workgroup sum: row scans, then the rows' totals, then the wavefronts'
+    part += __builtin_amdgcn_update_dpp(0, part, 0x111, 0xf, 0xf, true);
+    part += __builtin_amdgcn_update_dpp(0, part, 0x112, 0xf, 0xf, true);
+    part += __builtin_amdgcn_update_dpp(0, part, 0x114, 0xf, 0xf, true);
+    part += __builtin_amdgcn_update_dpp(0, part, 0x118, 0xf, 0xf, true);
+    const int wsum = __builtin_amdgcn_readlane(part, 15) + __builtin_amdgcn_readlane(part, 31) +
+                     __builtin_amdgcn_readlane(part, 47) + __builtin_amdgcn_readlane(part, 63);
+    if (lane == 0) wpart[wave] = wsum;
+    __syncthreads();
+    int prefix = 0;
+    for (int w = 0; w < 16; ++w) prefix += wpart[w];
+    if (slot >= a.B) return;
+    // slots of this workgroup before this wavefront's: inclusive row scan of
+    // the own counts in lanes 0..15
+    int oc = lane < kFillRays && first + lane < a.B ? own : 0;
+    oc += __builtin_amdgcn_update_dpp(0, oc, 0x111, 0xf, 0xf, true);
+    oc += __builtin_amdgcn_update_dpp(0, oc, 0x112, 0xf, 0xf, true);
+    oc += __builtin_amdgcn_update_dpp(0, oc, 0x114, 0xf, 0xf, true);
+    oc += __builtin_amdgcn_update_dpp(0, oc, 0x118, 0xf, 0xf, true);
+    const int before = wave > 0 ? __builtin_amdgcn_readlane(oc, wave - 1) : 0;
+    const int pos0 = prefix + before;
+    if (lane == 0) {
+        ray_offset[slot] = pos0;
+        if (slot == a.B - 1) {
+            const int total = prefix + __builtin_amdgcn_readlane(oc, wave);
+            ray_offset[a.B] = total;
+            *n_kept = total;
+        }
+    }
+    const RayView v = load_ray(a, slot);
+    fill_ray(a, v, pos0, capacity, sample_ray, sample_k, lane);
 }
 
 // One thread per 32-cell word of the coarse keep mask.
@@ -433,6 +509,11 @@ int32_t dvgo_sample_rays(const float* rays_o, const float* rays_d, const float* 
         if (clip_only) return DVGO_OK;
         DVGO_LAUNCH(K_COUNT_KEPT, count_kept_kernel, dim3(wblocks), dim3(256), 0, s, ka, counts);
         if (int32_t st = dvgo::launch_status()) return st;
+    }
+    if (B <= kFusedMaxRays) {
+        DVGO_LAUNCH(K_FILL_KEPT, offsets_fill_kernel, dim3((B + kFillRays - 1) / kFillRays), dim3(1024), 0, s, ka,
+                    counts, ray_offset, n_kept, capacity, sample_ray, sample_k);
+        return dvgo::launch_status();
     }
     DVGO_LAUNCH(K_SCAN, scan_offsets_kernel, dim3(1), dim3(kScanThreads), 0, s, counts, B, ray_offset, n_kept);
     if (int32_t st = dvgo::launch_status()) return st;
