@@ -383,7 +383,8 @@ int32_t dvgo_version(void);
  * HIP events recorded on the launch's own stream; dvgo_profile_read waits for
  * them and returns the summed elapsed milliseconds and the launch count since
  * the last dvgo_profile_enable.  kernel_id -1 turns timing off.  Ids:
- *   0 ray setup, 1 Morton sort, 2 count kept, 3 scan, 4 fill kept,
+ *   0 ray setup, 1 Morton sort, 2 count kept, 3 ray-offset scan (batches above 16384 rays), 4 fill kept (up
+ *   to 16384 rays with the offsets in the same launch),
  *   5 coarse mask, 6 (unused), 7 weight pack + per-ray encoding, 8 gather, 9 MLP forward,
  *   10 compose forward, 11 compose backward, 12 MLP backward, 13 vertex
  *   gather (gradient scatter), 14 partial reduce, 15 photo loss, 16 Adam,
