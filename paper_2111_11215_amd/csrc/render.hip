@@ -138,9 +138,11 @@ __device__ __forceinline__ int64_t live_count(const int64_t* n_kept, int64_t cap
 // ---------------------------------------------------------------------------
 // base[r][i] = b1[i] + sum_q W1[i][C+q] * PE(d_r)[q];  pe[r] = [PE(d_r) (27), 1, 0, 0, 0, 0]
 // Per-call preparation in one launch: the first kPackThreads/256 workgroups
-// pack the network's operands; each following workgroup takes two rays: 24
-// threads evaluate the rays' 24 sines and cosines once into LDS, then thread
-// (ray, i) forms output i of the first layer's view part.
+// pack the network's operands; each following workgroup takes kPrepRays
+// rays: 12 threads per ray evaluate its 24 sines and cosines once into LDS,
+// then each thread forms one output of the first layer's view part for half
+// of the rays.
+constexpr int kPrepRays = 16;   // rays per workgroup of prep_kernel
 __global__ __launch_bounds__(256) void prep_kernel(PackArgs pk, int pack, const float* __restrict__ rays_d, int B,
                                                    const float* __restrict__ w1, const float* __restrict__ b1,
                                                    float* __restrict__ base, float* __restrict__ pe,
@@ -150,7 +152,7 @@ __global__ __launch_bounds__(256) void prep_kernel(PackArgs pk, int pack, const 
         pack_weights(pk, blockIdx.x * 256 + threadIdx.x);
         return;
     }
-    const int ray_blocks = (B + 1) / 2;
+    const int ray_blocks = (B + kPrepRays - 1) / kPrepRays;
     const int zb = static_cast<int>(blockIdx.x) - (pack ? kPackBlocks : 0) - ray_blocks;
     if (zb >= 0) {   // the last zblocks workgroups clear `zero` (the backward's cell counts)
         const int64_t stride = static_cast<int64_t>(zblocks) * 256, first = static_cast<int64_t>(zb) * 256 + threadIdx.x;
@@ -164,10 +166,10 @@ __global__ __launch_bounds__(256) void prep_kernel(PackArgs pk, int pack, const 
         for (int64_t i = done + first; i < nzero; i += stride) zero[i] = 0;
         return;
     }
-    __shared__ float se[2][32];
+    __shared__ float se[kPrepRays][32];
     const int t = threadIdx.x;
-    const int r0 = 2 * (static_cast<int>(blockIdx.x) - (pack ? kPackBlocks : 0));
-    if (t < 24) {
+    const int r0 = kPrepRays * (static_cast<int>(blockIdx.x) - (pack ? kPackBlocks : 0));
+    if (t < 12 * kPrepRays) {
         const int rr = t / 12, q = t % 12, fq = q / 3, c = q % 3;
         const int r = r0 + rr;
         if (r < B) {
@@ -178,19 +180,30 @@ __global__ __launch_bounds__(256) void prep_kernel(PackArgs pk, int pack, const 
             se[rr][6 + 6 * fq + c] = cv;
             if (fq == 0) se[rr][c] = dc;
         }
-    } else if (t < 34) {   // entry 27: the first layer's constant input; 28..31 zero
-        se[(t - 24) / 5][kPE + (t - 24) % 5] = (t - 24) % 5 == 0 ? 1.0f : 0.0f;
     }
+    if (t < 5 * kPrepRays)   // entry 27: the first layer's constant input; 28..31 zero
+        se[t / 5][kPE + t % 5] = t % 5 == 0 ? 1.0f : 0.0f;
     __syncthreads();
-    const int rr = t >> 7, i = t & (kH - 1);
-    const int r = r0 + rr;
-    if (r >= B) return;
+    // thread (h, i) forms output i for rays h, h + 2, ...; its weights stay in
+    // registers across the rays
+    const int h = t >> 7, i = t & (kH - 1);
+    float wv[kPE];
+    const float bi = w1 ? b1[i] : 0.0f;
     if (w1) {
-        float acc = b1[i];
-        for (int q = 0; q < kPE; ++q) acc += w1[i * kIn + kC + q] * se[rr][q];
-        base[static_cast<int64_t>(r) * kH + i] = acc;
+        #pragma unroll
+        for (int q = 0; q < kPE; ++q) wv[q] = w1[i * kIn + kC + q];
     }
-    if (i < 32) pe[static_cast<int64_t>(r) * 32 + i] = se[rr][i];
+    for (int rr = h; rr < kPrepRays; rr += 2) {
+        const int r = r0 + rr;
+        if (r >= B) break;
+        if (w1) {
+            float acc = bi;
+            #pragma unroll
+            for (int q = 0; q < kPE; ++q) acc += wv[q] * se[rr][q];
+            base[static_cast<int64_t>(r) * kH + i] = acc;
+        }
+        if (i < 32) pe[static_cast<int64_t>(r) * 32 + i] = se[rr][i];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1100,7 +1113,7 @@ int32_t run_prep(const Common& cm, const dvgo_mlp* mlp, hipStream_t s, int* zero
         pk.w1tpb = reinterpret_cast<uint16_t*>(cm.ws + cm.L.w1tpb);
         pk.bf16 = mlp->precision == DVGO_BF16;
         const int zblocks = zero ? grid_for(nzero, 256, dvgo::device_cu_count() * 4) : 0;
-        const unsigned blocks = static_cast<unsigned>(kPackThreads / 256 + (cm.B + 1) / 2 + zblocks);
+        const unsigned blocks = static_cast<unsigned>(kPackThreads / 256 + (cm.B + kPrepRays - 1) / kPrepRays + zblocks);
         DVGO_LAUNCH(K_RAY_BASE, prep_kernel, dim3(blocks), dim3(256), 0, s, pk, 1, cm.sa.rays_d, cm.B, mlp->w1,
                     mlp->b1, base, pe, zero, nzero, zblocks);
         if (int32_t st = dvgo::launch_status()) return st;
