@@ -651,22 +651,65 @@ def proposal_forward(Ws, bs, enc, bf16=False):
 
 def proposal_probs(z):
     """33-way softmax of the 32 segment logits and an implicit transmitted
-    logit fixed at 0; returns (q [B,33], predicted mass sum_{s<32} q_s).
-    Sums run sequentially in index order (the transmitted entry last), the
-    reading under which the selection is reproducible in float64."""
+    logit fixed at 0, in float64 (the continuous part: the KL loss and its
+    gradient); returns (q [B,33], predicted mass sum_{s<32} q_s)."""
     z = np.asarray(z, np.float64)
     zz = np.concatenate([z, np.zeros((z.shape[0], 1))], axis=1)
-    m = np.zeros(z.shape[0])
-    for s in range(NSEG):
-        m = np.maximum(m, zz[:, s])
+    m = np.max(zz, axis=1)
     e = np.exp(zz - m[:, None])
-    tot = np.zeros(z.shape[0])
-    for s in range(NSEG + 1):
-        tot = tot + e[:, s]
-    q = e / tot[:, None]
-    mass = np.zeros(z.shape[0])
+    q = e / e.sum(axis=1, keepdims=True)
+    return q, q[:, :NSEG].sum(axis=1)
+
+
+# float32 constants of the exponential recipe below (hexadecimal: exact)
+_LOG2E = F32(float.fromhex("0x1.715476p+0"))      # log2(e) rounded to float32
+_LN2_HI = F32(float.fromhex("0x1.62e4p-1"))       # ln 2 with its low mantissa bits cleared
+_LN2_LO = F32(float.fromhex("0x1.7f7d1cp-20"))    # ln 2 - _LN2_HI rounded to float32
+_EXP_TAYLOR = [F32(1.0 / math.factorial(j)) for j in range(7, -1, -1)]   # 1/7!, ..., 1/1!, 1/0!
+
+
+def exp_f32(x):
+    """exp(x) for float32 x <= 0 in an explicit float32 recipe (every
+    operation rounded to float32 in the order written, no fused multiply-add),
+    so that a float32 GPU implementation of the same steps gives the same
+    bits.  Method: Cody-Waite range reduction x = k ln2 + r with ln 2 split in
+    two parts (k ln2_hi is exact for |k| < 2^9), then the Taylor polynomial of
+    e^r to degree 7 by Horner's rule (|r| <= ln2/2, truncation error below
+    1e-8 relative), scaled by 2^k.  Arguments below -87 return 0 (the result
+    would leave the normal float32 range)."""
+    x = np.asarray(x, F32)
+    with np.errstate(over="ignore", invalid="ignore"):
+        k = np.rint((x * _LOG2E).astype(F32)).astype(F32)
+        r = (x - (k * _LN2_HI).astype(F32)).astype(F32)
+        r = (r - (k * _LN2_LO).astype(F32)).astype(F32)
+        p = np.full(x.shape, _EXP_TAYLOR[0], F32)
+        for c in _EXP_TAYLOR[1:]:
+            p = ((p * r).astype(F32) + c).astype(F32)
+        out = np.ldexp(p, np.where(np.isfinite(k), k, 0).astype(np.int32)).astype(F32)
+    return np.where(x < F32(-87.0), F32(0.0), out).astype(F32)
+
+
+def proposal_select_probs(z):
+    """The selection's float32 softmax (reading of the benchmark spec's
+    proposal: an implicit transmitted logit 0 beside the 32 segment logits).
+    float32 recipe: m = max(0, z_s); e_s = exp_f32(z_s - m), e_T = exp_f32(-m);
+    tot = the sum of e_0..e_31 then e_T, added one at a time in that order;
+    q_s = e_s / tot (correctly rounded); mass = q_0 + ... + q_31 in index
+    order.  Returns (q [B,32] float32, mass [B] float32)."""
+    z = np.asarray(z, F32)
+    B = z.shape[0]
+    m = np.zeros(B, F32)
     for s in range(NSEG):
-        mass = mass + q[:, s]
+        m = np.maximum(m, z[:, s])
+    e = exp_f32((z - m[:, None]).astype(F32))
+    tot = np.zeros(B, F32)
+    for s in range(NSEG):
+        tot = (tot + e[:, s]).astype(F32)
+    tot = (tot + exp_f32((F32(0.0) - m).astype(F32))).astype(F32)
+    q = (e / tot[:, None]).astype(F32)
+    mass = np.zeros(B, F32)
+    for s in range(NSEG):
+        mass = (mass + q[:, s]).astype(F32)
     return q, mass
 
 
@@ -674,21 +717,27 @@ def proposal_select(z, cum_frac=0.99, min_mass=0.9):
     """Segment mask per ray: the smallest set of segments, taken by
     descending probability (ties to the lower index), whose probability
     reaches cum_frac of the predicted mass; all 32 segments when the mass is
-    below min_mass (uniform fallback).  Returns uint32 masks."""
-    q, mass = proposal_probs(z)
+    below min_mass (uniform fallback).  float32 recipe from the float32
+    logits: the probabilities of ``proposal_select_probs``, target =
+    cum_frac * mass rounded to float32, the chosen probabilities added one
+    at a time in the order chosen, stopping once the sum reaches the target.
+    Returns uint32 masks."""
+    q, mass = proposal_select_probs(z)
+    cf, mm = F32(cum_frac), F32(min_mass)
     B = q.shape[0]
     out = np.zeros(B, np.uint32)
     for r in range(B):
-        if not mass[r] >= min_mass:
+        if not mass[r] >= mm:
             out[r] = np.uint32(0xFFFFFFFF)
             continue
-        order = sorted(range(NSEG), key=lambda s: (-q[r, s], s))
-        acc = 0.0
+        target = F32(cf * mass[r])
+        order = sorted(range(NSEG), key=lambda s: (-float(q[r, s]), s))
+        acc = F32(0.0)
         bits = 0
         for s in order:
             bits |= 1 << s
-            acc += q[r, s]
-            if acc >= cum_frac * mass[r]:
+            acc = F32(acc + q[r, s])
+            if acc >= target:
                 break
         out[r] = np.uint32(bits)
     return out
