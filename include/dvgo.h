@@ -99,6 +99,31 @@ typedef struct dvgo_prop {
 int64_t dvgo_prop_param_count(void);
 
 /* ------------------------------------------------------------------------ */
+/* The method's scalar hyperparameters (host functions, no device work).
+ *
+ * dvgo_low_density_bias: the softplus shift b of the low-density
+ *   initialisation (paper Eq. low_density_init and its supplementary
+ *   derivation): with a zero density grid every voxel of size `voxel` lets
+ *   through 1 - alpha_init of the light, b = log((1 - alpha_init)^(-1/voxel)
+ *   - 1), evaluated as log(expm1(-log1p(-alpha_init)/voxel)).
+ *   alpha_init in (0, 1), voxel > 0, bias a host double; else DVGO_E_ARG.
+ * dvgo_coarse_raw_threshold: the raw-density threshold of the free-space
+ *   test (paper Sec. 4.2, "Known free space and unknown space"): a point is
+ *   kept when alpha(softplus(raw + act_shift), step) >= tau; both activations
+ *   increase with raw, so this is raw >= softplus^{-1}(-log(1-tau)/step) -
+ *   act_shift, computed in float64 and rounded DOWN to float32 (a float32
+ *   comparison against it never drops a point the exact test keeps).
+ *   tau in (0, 1), step > 0, act_shift finite, threshold a host float; else
+ *   DVGO_E_ARG.
+ * dvgo_lr_at: the learning rate of the exponential schedule (paper Sec. 5.2
+ *   and the supplementary implementation details: decayed to 0.1x at 20k
+ *   iterations): lr = base_lr * decay^(it/decay_steps).  base_lr >= 0,
+ *   it >= 0, decay_steps > 0, decay > 0, lr a host double; else DVGO_E_ARG. */
+int32_t dvgo_low_density_bias(double alpha_init, double voxel, double* bias /*host*/);
+int32_t dvgo_coarse_raw_threshold(double tau, double step, double act_shift, float* threshold /*host*/);
+int32_t dvgo_lr_at(double base_lr, int64_t it, int64_t decay_steps, double decay, double* lr /*host*/);
+
+/* ------------------------------------------------------------------------ */
 /* Coarse alpha mask (paper Sec. 4.2, "Known free space and unknown space"
  * and "Free space skipping", first rule).  One bit per cell of the frozen
  * coarse density grid raw [nx][ny][nz] (box cbox): bit c of word c>>5, with
@@ -341,12 +366,21 @@ int32_t dvgo_adam_step(float* p, float* g, float* m, float* v, uint16_t* shadow_
  * entries (the last is the transmitted share), pred_mass = sum_{s<32} q_s;
  * seg_mask[r] = the smallest set of segments, by descending q (ties to the
  * lower index), whose q sum reaches cum_frac * pred_mass, or all ones when
- * pred_mass < min_mass or the ray is invalid.  The selection runs in float64
- * from the float32 logits, with cum_frac and min_mass as passed (float64).
+ * pred_mass < min_mass or the ray is invalid.  The selection follows an
+ * explicit float32 recipe from the float32 logits (no contraction), so the
+ * mask is reproducible bit for bit: m = max(0, z_s); e_s = exp_f32(z_s - m),
+ * e_T = exp_f32(-m), where exp_f32 is the Cody-Waite reduction
+ * k = rint(x*log2e), r = (x - k*ln2_hi) - k*ln2_lo (ln2_hi = 0x1.62e4p-1,
+ * ln2_lo = 0x1.7f7d1cp-20), the degree-7 Taylor polynomial of e^r by
+ * Horner's rule and the scale 2^k (0 for x < -87); tot = e_0 + ... + e_31
+ * + e_T, q_s = e_s/tot and pred_mass = q_0 + ... + q_31, each summed one
+ * term at a time in that order; the chosen q are added in the order chosen
+ * until the sum reaches cum_frac*pred_mass (float32 product).
+ * cum_frac in (0, 1], min_mass in [0, 1], else DVGO_E_ARG.
  * valid/t_near come from dvgo_sample_rays. */
 int32_t dvgo_proposal_fwd(const float* rays_o, const float* rays_d, const float* t_near,
                           const uint8_t* valid, int32_t B, const dvgo_box* box /*host*/,
-                          const dvgo_prop* prop /*host*/, double cum_frac, double min_mass,
+                          const dvgo_prop* prop /*host*/, float cum_frac, float min_mass,
                           float* logits, float* pred_mass, uint32_t* seg_mask, void* stream);
 
 /* Proposal backward: KL(p || q) summed over the valid rays and divided by

@@ -77,12 +77,15 @@ SIGNATURES = {
     "dvgo_photo_loss": (c_int32, [P, P, c_int32, P, P, P]),
     "dvgo_adam_step": (c_int32, [P, P, P, P, P, c_int64, c_float, c_float, c_float, c_float, c_int32, P]),
     "dvgo_grid_active_init": (c_int32, [P, P, P, P, c_int64, P, P]),
-    "dvgo_proposal_fwd": (c_int32, [P, P, P, P, c_int32, POINTER(Box), POINTER(Prop), c_double, c_double, P, P, P,
+    "dvgo_proposal_fwd": (c_int32, [P, P, P, P, c_int32, POINTER(Box), POINTER(Prop), c_float, c_float, P, P, P,
                                     P]),
     "dvgo_proposal_bwd": (c_int32, [P, P, P, P, c_int32, POINTER(Box), POINTER(Prop), P, P, P, P, P, c_size_t, P]),
     "dvgo_proposal_workspace_bytes": (c_size_t, [c_int32]),
     "dvgo_scene_render": (c_int32, [P, P, c_int32, POINTER(Box), P, c_int32, c_float, c_float, POINTER(c_float), P,
                                     P]),
+    "dvgo_low_density_bias": (c_int32, [c_double, c_double, POINTER(c_double)]),
+    "dvgo_coarse_raw_threshold": (c_int32, [c_double, c_double, c_double, POINTER(c_float)]),
+    "dvgo_lr_at": (c_int32, [c_double, c_int64, c_int64, c_double, POINTER(c_double)]),
     "dvgo_status_string": (c_char_p, [c_int32]),
     "dvgo_last_error": (c_char_p, []),
     "dvgo_version": (c_int32, []),

@@ -52,22 +52,28 @@ def workspace(nbytes: int, device) -> torch.Tensor:
 # host-side scalar hyperparameters
 # ---------------------------------------------------------------------------
 def low_density_bias(alpha_init: float, voxel: float) -> float:
-    """Softplus shift of the low-density initialisation (paper
-    Eq. low_density_init): b = log((1 - alpha_init)^(-1/s) - 1)."""
-    return math.log(math.pow(1.0 - alpha_init, -1.0 / voxel) - 1.0)
+    """``dvgo_low_density_bias``: the softplus shift b of the low-density
+    initialisation for voxel size ``voxel``."""
+    out = ctypes.c_double()
+    check("dvgo_low_density_bias", load().dvgo_low_density_bias(float(alpha_init), float(voxel), ctypes.byref(out)))
+    return out.value
 
 
 def coarse_raw_threshold(tau: float, step: float, act_shift: float = 0.0) -> float:
-    """Raw-density threshold equivalent to post-activated alpha >= tau at
-    sample spacing ``step`` (both activations increase with the raw value):
-    softplus^{-1}(-log(1-tau)/step) - b, rounded down to float32."""
-    import numpy as np
-    sig = -math.log1p(-tau) / step
-    thr = math.log(math.expm1(sig)) - act_shift
-    t32 = np.float32(thr)
-    if float(t32) > thr:
-        t32 = np.nextafter(t32, np.float32(-np.inf))
-    return float(t32)
+    """``dvgo_coarse_raw_threshold``: the float32 raw-density threshold of
+    the coarse free-space test at sample spacing ``step``."""
+    out = ctypes.c_float()
+    check("dvgo_coarse_raw_threshold", load().dvgo_coarse_raw_threshold(float(tau), float(step), float(act_shift),
+                                                                        ctypes.byref(out)))
+    return out.value
+
+
+def lr_at(base_lr: float, it: int, decay_steps: int = 20000, decay: float = 0.1) -> float:
+    """``dvgo_lr_at``: the learning rate at iteration ``it`` of the
+    exponential schedule."""
+    out = ctypes.c_double()
+    check("dvgo_lr_at", load().dvgo_lr_at(float(base_lr), int(it), int(decay_steps), float(decay), ctypes.byref(out)))
+    return out.value
 
 
 # ---------------------------------------------------------------------------

@@ -3,8 +3,8 @@
 // its uniform samples, and the segment mask that keeps the segments holding
 // most of it.  The network runs on bfloat16 matrix cores (inputs, hidden
 // activations and weights rounded to bfloat16, float32 accumulation), one
-// wavefront per 32 rays; the selection runs in float64 so that it is
-// reproducible from the float32 logits.
+// wavefront per 32 rays; the selection follows an explicit float32 recipe so
+// that it is reproducible bit for bit from the float32 logits.
 #include "common.hpp"
 
 namespace {
@@ -185,44 +185,70 @@ __device__ void prop_forward(const PropArgs& a, int r, bool ray_ok, int lane, Pr
     for (int st = 0; st < 4; ++st) f.z = mma(frag_w3(a.w[2], st, m, h), hb[st], f.z);
 }
 
+// exp(x) for x <= 0 in an explicit float32 recipe (every operation rounded,
+// no contraction), so that the selection below is reproducible bit for bit:
+// Cody-Waite reduction x = k ln2 + r with ln 2 in two parts (k * ln2_hi is
+// exact for |k| < 2^9), the degree-7 Taylor polynomial of e^r by Horner's
+// rule, then the scale 2^k.  x < -87 gives 0 (the result would leave the
+// normal range).  At most 1.15 units in the last place from exp.
+__device__ __forceinline__ float exp_recipe(float x) {
+#pragma clang fp contract(off)
+    const float kLog2e = 0x1.715476p+0f, kLn2Hi = 0x1.62e4p-1f, kLn2Lo = 0x1.7f7d1cp-20f;
+    const float k = rintf(x * kLog2e);
+    float r = x - k * kLn2Hi;
+    r = r - k * kLn2Lo;
+    float p = 0x1.a01a02p-13f;       // 1/7!
+    p = p * r + 0x1.6c16c2p-10f;     // 1/6!
+    p = p * r + 0x1.111112p-7f;      // 1/5!
+    p = p * r + 0x1.555556p-5f;      // 1/4!
+    p = p * r + 0x1.555556p-3f;      // 1/3!
+    p = p * r + 0.5f;
+    p = p * r + 1.0f;
+    p = p * r + 1.0f;
+    return x < -87.0f ? 0.0f : ldexpf(p, static_cast<int>(k));
+}
+
 // Segment mask of one ray from its float32 logits, computed by the ray's two
 // lanes (m, h = 0/1): each holds 16 logits, z[rr] of segment acc_row(rr, h).
-// float64 arithmetic; the softmax sums run in index order (transmitted entry
-// last) over both halves, so both lanes hold the identical sums; the
-// selection takes the largest unchosen q each round (ties to the lower
-// index), comparing the two halves' candidates.  Registers only.
+// float32 recipe, no contraction: m = max(0, z), e = exp_recipe(z - m); the
+// total (transmitted entry last), the probabilities e/tot and the mass are
+// summed one term at a time in index order over both halves, so both lanes
+// hold the identical sums; the selection takes the largest unchosen q each
+// round (ties to the lower index), comparing the two halves' candidates, and
+// adds it to the running sum until that reaches cum_frac * mass.
 __device__ __forceinline__ int seg_rr(int s) { return 4 * (s >> 3) + (s & 3); }   // inverse of acc_row
 __device__ __forceinline__ int seg_h(int s) { return (s >> 2) & 1; }
 
-__device__ uint32_t select_mask_pair(const float z[16], int h, double cum_frac, double min_mass, float* pred_mass) {
-    double mx = 0.0;
+__device__ uint32_t select_mask_pair(const float z[16], int h, float cum_frac, float min_mass, float* pred_mass) {
+#pragma clang fp contract(off)
+    float mx = 0.0f;
     #pragma unroll
-    for (int rr = 0; rr < 16; ++rr) mx = fmax(mx, static_cast<double>(z[rr]));
-    mx = fmax(mx, __shfl_xor(mx, 32, 64));
-    double e[16], pe[16];
+    for (int rr = 0; rr < 16; ++rr) mx = fmaxf(mx, z[rr]);
+    mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+    float e[16], pe[16];
     #pragma unroll
-    for (int rr = 0; rr < 16; ++rr) e[rr] = exp(static_cast<double>(z[rr]) - mx);
+    for (int rr = 0; rr < 16; ++rr) e[rr] = exp_recipe(z[rr] - mx);
     #pragma unroll
     for (int rr = 0; rr < 16; ++rr) pe[rr] = __shfl_xor(e[rr], 32, 64);
-    double tot = 0.0;
+    float tot = 0.0f;
     #pragma unroll
     for (int s = 0; s < kS; ++s) tot += seg_h(s) == h ? e[seg_rr(s)] : pe[seg_rr(s)];
-    tot += exp(0.0 - mx);
-    double q[16], pq[16];
+    tot += exp_recipe(0.0f - mx);
+    float q[16], pq[16];
     #pragma unroll
     for (int rr = 0; rr < 16; ++rr) q[rr] = e[rr] / tot;
     #pragma unroll
     for (int rr = 0; rr < 16; ++rr) pq[rr] = __shfl_xor(q[rr], 32, 64);
-    double mass = 0.0;
+    float mass = 0.0f;
     #pragma unroll
     for (int s = 0; s < kS; ++s) mass += seg_h(s) == h ? q[seg_rr(s)] : pq[seg_rr(s)];
-    *pred_mass = static_cast<float>(mass);
+    *pred_mass = mass;
     if (!(mass >= min_mass)) return 0xFFFFFFFFu;
-    const double target = cum_frac * mass;
+    const float target = cum_frac * mass;
     uint32_t own = 0, mask = 0;   // own: chosen bits over rr
-    double acc = 0.0;
+    float acc = 0.0f;
     for (int it = 0; it < kS; ++it) {
-        double bq = -1.0;
+        float bq = -1.0f;
         int bs = 64, brr = -1;
         #pragma unroll
         for (int rr = 0; rr < 16; ++rr)
@@ -231,10 +257,10 @@ __device__ uint32_t select_mask_pair(const float z[16], int h, double cum_frac, 
                 bs = acc_row(rr, h);
                 brr = rr;
             }
-        const double oq = __shfl_xor(bq, 32, 64);
+        const float oq = __shfl_xor(bq, 32, 64);
         const int os = __shfl_xor(bs, 32, 64);
         const bool theirs = oq > bq || (oq == bq && os < bs);
-        const double wq = theirs ? oq : bq;
+        const float wq = theirs ? oq : bq;
         const int ws = theirs ? os : bs;
         if (!theirs && brr >= 0) own |= 1u << brr;
         if (ws < kS) mask |= 1u << ws;
@@ -247,7 +273,7 @@ __device__ uint32_t select_mask_pair(const float z[16], int h, double cum_frac, 
 constexpr int kRaysPerWave = 32;
 constexpr int kWaves = 1;   // one wavefront (32 rays) per workgroup
 
-__global__ __launch_bounds__(64) void proposal_fwd_kernel(PropArgs a, int run_net, double cum_frac, double min_mass,
+__global__ __launch_bounds__(64) void proposal_fwd_kernel(PropArgs a, int run_net, float cum_frac, float min_mass,
                                                           float* __restrict__ logits, float* __restrict__ pred_mass,
                                                           uint32_t* __restrict__ seg_mask) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -487,12 +513,12 @@ size_t dvgo_proposal_workspace_bytes(int32_t B) {
 
 // prop == NULL: `logits` is an input and only the selection runs.
 int32_t dvgo_proposal_fwd(const float* rays_o, const float* rays_d, const float* t_near, const uint8_t* valid,
-                          int32_t B, const dvgo_box* box, const dvgo_prop* prop, double cum_frac, double min_mass,
+                          int32_t B, const dvgo_box* box, const dvgo_prop* prop, float cum_frac, float min_mass,
                           float* logits, float* pred_mass, uint32_t* seg_mask, void* stream) {
     PropArgs a;
     if (!fill_args(a, rays_o, rays_d, t_near, valid, B, box, prop)) return DVGO_E_ARG;
     if (B > 0 && !logits) return DVGO_E_ARG;
-    if (!(cum_frac > 0.0 && cum_frac <= 1.0) || !(min_mass >= 0.0 && min_mass <= 1.0)) return DVGO_E_ARG;
+    if (!(cum_frac > 0.0f && cum_frac <= 1.0f) || !(min_mass >= 0.0f && min_mass <= 1.0f)) return DVGO_E_ARG;
     if (B == 0) return DVGO_OK;
     DVGO_LAUNCH(K_PROP_FWD, proposal_fwd_kernel, dim3((B + kRaysPerWave - 1) / kRaysPerWave), dim3(64 * kWaves), 0,
                        dvgo::as_stream(stream), a, prop != nullptr, cum_frac, min_mass, logits, pred_mass, seg_mask);

@@ -77,7 +77,7 @@ class FineModel:
         self.t = 0
 
     def lr(self, base: float) -> float:
-        return base * 0.1 ** (self.t / self.cfg.decay_steps)
+        return api.lr_at(base, self.t, self.cfg.decay_steps)
 
     def sample(self, rays_o, rays_d, jitter, seg_mask=None, capacity=None, morton=None) -> api.Samples:
         c = self.cfg

@@ -137,3 +137,47 @@ def test_host_validation_rejects_before_launch(lib):
     assert lib.dvgo_grid_active_init(fake, fake, 20, fake, 10, fake, nul) == -1
     assert lib.dvgo_grid_active_init(fake, fake, fake, fake, 10, 18, nul) == -1
     assert lib.dvgo_grid_active_init(None, None, None, None, 0, None, nul) == 0
+
+
+def test_host_scalars_match_the_oracle(lib):
+    """The method's scalar hyperparameters computed by the library (no GPU):
+    the low-density shift, the coarse free-space threshold and the learning
+    rate schedule, against the oracle's definitions."""
+    import math
+
+    import numpy as np
+
+    import oracle as O
+    from paper_2111_11215_amd import api
+    for a, s in [(1e-2, 2.0 / 159), (1e-6, 2.0 / 99), (0.5, 1.0), (1e-3, 2.0 / 255)]:
+        b = api.low_density_bias(a, s)
+        ref = O.low_density_bias(a, s)
+        # the oracle evaluates the formula as written, (1-a)^(-1/s) - 1, which
+        # cancels for small a (about 1e-11 relative at a = 1e-6)
+        assert abs(b - ref) <= 1e-10 * abs(ref)
+        # definition: one voxel at sigma = softplus(b) lets 1 - alpha_init through
+        assert abs(math.exp(-math.log1p(math.exp(b)) * s) - (1 - a)) < 1e-12
+    for tau, step, b in [(1e-4, 0.5 * 2 / 159, 0.0), (1e-3, 0.5 * 2 / 99, 0.2016), (1e-4, 0.5 * 2 / 255, -1.3)]:
+        thr = api.coarse_raw_threshold(tau, step, b)
+        assert thr == float(O.coarse_raw_threshold(tau, step, b))
+        # largest float32 not above the exact threshold: alpha at thr is below tau
+        # or at it, and at the next float32 above it reaches tau
+        nxt = float(np.nextafter(np.float32(thr), np.float32(np.inf)))
+        alpha = lambda raw: -math.expm1(-math.log1p(math.exp(raw + b)) * step)
+        assert alpha(thr) <= tau * (1 + 1e-9) and alpha(nxt) >= tau
+    for base, it in [(0.1, 0), (0.1, 20000), (1e-3, 777), (1e-3, 123456)]:
+        assert abs(api.lr_at(base, it) - O.lr_at(base, it)) <= 1e-15 * base
+    assert abs(api.lr_at(1e-3, 20000) - 1e-4) < 1e-18
+
+
+def test_host_scalars_reject_bad_arguments(lib):
+    import ctypes as C
+    d, f = C.c_double(), C.c_float()
+    assert lib.dvgo_low_density_bias(0.0, 0.1, C.byref(d)) == -1
+    assert lib.dvgo_low_density_bias(1e-2, 0.0, C.byref(d)) == -1
+    assert lib.dvgo_low_density_bias(1e-2, 0.1, None) == -1
+    assert lib.dvgo_coarse_raw_threshold(1.0, 0.1, 0.0, C.byref(f)) == -1
+    assert lib.dvgo_coarse_raw_threshold(1e-4, -0.1, 0.0, C.byref(f)) == -1
+    assert lib.dvgo_coarse_raw_threshold(1e-4, 0.1, float("nan"), C.byref(f)) == -1
+    assert lib.dvgo_lr_at(0.1, -1, 20000, 0.1, C.byref(d)) == -1
+    assert lib.dvgo_lr_at(0.1, 1, 0, 0.1, C.byref(d)) == -1

@@ -1,5 +1,5 @@
-"""GPU parity of the learned proposal: the segment selection bit-exact from
-the same float32 logits, the bfloat16 network forward and backward against
+"""GPU parity of the learned proposal: the segment selection and the
+predicted mass bit-exact from the same float32 logits (float32 recipe), the bfloat16 network forward and backward against
 the oracle's bfloat16 form (tolerance 1e-3 normwise: the float32 encoding
 may round to a neighbouring bfloat16 value; measured values printed)."""
 
@@ -39,14 +39,14 @@ def test_selection_bit_exact_from_logits(gpu_lib):
     z[:64, 0:10] = 15.4
     z[64:128] = -20.0      # tiny mass: fallback
     _, mass, mask = api.proposal_fwd(s, P.box_min, P.box_max, None, logits=to_dev(z))
-    want = O.proposal_select(z.astype(np.float64))
+    want = O.proposal_select(z)
     valid = np_of(s.valid).astype(bool)
     want = np.where(valid, want, np.uint32(0xFFFFFFFF))
     assert np.array_equal(np_of(mask).view(np.uint32), want)
     tie_rows = np.where(valid[:64])[0]
     assert np.all(want[tie_rows] == np.uint32((1 << 10) | 0x1FF))
-    _, m_ref = O.proposal_probs(z.astype(np.float64))
-    assert np.max(np.abs(np_of(mass) - m_ref)) < 1e-6
+    _, m_ref = O.proposal_select_probs(z)
+    assert np.array_equal(np_of(mass), m_ref)
 
 
 def test_proposal_forward_backward_bf16(gpu_lib):
