@@ -468,7 +468,19 @@ __global__ __launch_bounds__(256) void compose_fwd_kernel(ComposeArgs a) {
     if (a.seg_w && lane < 32) a.seg_w[static_cast<int64_t>(r) * 32 + lane] = segs[wave][lane];
 }
 
-// Backward of compose: walk each ray from its end in 64-sample steps.
+// Backward of compose: walk each ray from its end in 64-sample steps,
+// carrying the suffix sums S.  The transmittance is recomputed from the
+// samples' densities as the forward forms it, by prefix sums from the ray's
+// start: log T at the start of each 64-sample step comes from a first pass
+// over the ray's steps (lane j keeps the start of step j), so T_k, T_{k+1}
+// and w_k are the forward's values bit for bit.  (Forming log T_k as
+// log T_end plus the suffix of sigma*delta would cancel: with an optical
+// depth D along the ray it loses D*2^-24 of absolute accuracy in log T.)
+// Rays of more than 64 steps take the first pass once per group of 64.
+__device__ __forceinline__ float sd_of(const ComposeArgs& a, int64_t s, int64_t s1) {
+    return s < s1 ? softplus_f(a.raw[s] + a.act_shift) * a.sa.step : 0.0f;
+}
+
 __global__ __launch_bounds__(256) void compose_bwd_kernel(ComposeArgs a) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int slot = blockIdx.x * 4 + wave;
@@ -490,7 +502,6 @@ __global__ __launch_bounds__(256) void compose_bwd_kernel(ComposeArgs a) {
     g[2] = a.grad_rgb ? a.grad_rgb[3 * r + 2] : 0.0f;
     g[3] = a.grad_depth ? a.grad_depth[r] : 0.0f;
     g[4] = a.grad_acc ? a.grad_acc[r] : 0.0f;
-    float logTa = a.log_t_end_in[r];          // log T after the walked suffix
     float ro[3] = {0.0f, 0.0f, 0.0f}, rd[3] = {0.0f, 0.0f, 0.0f};   // the ray, for the binning
     if (a.cell_count) {
         for (int i = 0; i < 3; ++i) {
@@ -498,58 +509,69 @@ __global__ __launch_bounds__(256) void compose_bwd_kernel(ComposeArgs a) {
             rd[i] = a.sa.rays_d[3 * r + i];
         }
     }
-    const float Tend = expf(logTa);
+    const float Tend = expf(a.log_t_end_in[r]);
     float S[5] = {Tend * a.bg[0], Tend * a.bg[1], Tend * a.bg[2], 0.0f, 0.0f};
     const int64_t nsteps = (s1 - s0 + 63) / 64;
-    for (int64_t it = nsteps - 1; it >= 0; --it) {
-        const int64_t s = s0 + it * 64 + lane;
-        const bool ok = s < s1;
-        float sd = 0.0f, raw = 0.0f, tk = 0.0f, v[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-        if (ok) {
-            raw = a.raw[s];
-            sd = softplus_f(raw + a.act_shift) * step;
-            tk = recipe_tk(tn, p, a.sa.sample_k[s], step);
-            if (a.with_color) {
-                const float4 c = reinterpret_cast<const float4*>(a.col)[s];
-                v[0] = c.x; v[1] = c.y; v[2] = c.z;
-            }
-            v[3] = tk;
-            v[4] = 1.0f;
+    const int64_t ngroups = (nsteps + 63) / 64;
+    for (int64_t grp = ngroups - 1; grp >= 0; --grp) {
+        // log T at the start of steps 64*grp .. 64*grp+63, lane j holding step 64*grp+j
+        const int64_t first = 64 * grp, last = first + 63 < nsteps - 1 ? first + 63 : nsteps - 1;
+        float start = 0.0f;
+        float logT = 0.0f;
+        for (int64_t j = 0; j < last; ++j) {
+            if (j >= first && lane == static_cast<int>(j - first)) start = logT;
+            logT -= wave_sum(sd_of(a, s0 + j * 64 + lane, s1));
         }
-        // log T_{k+1} = logTa + sum of sd over later samples of this step
-        const float suf = wave_incl_suffix(sd, lane);
-        const float suf_ex = dpp_wave<0x130>(suf);   // wave_shl:1, lane 63 reads 0
-        const float Tafter = expf(logTa + suf_ex);
-        const float w = ok ? Tafter * expm1f(sd) : 0.0f;
-        float dsig = 0.0f;
-        float tot[5];
-        for (int ch = 0; ch < 5; ++ch) {
-            const float wv = w * v[ch];
-            const float sfx = wave_incl_suffix(wv, lane);
-            const float sfx_ex = dpp_wave<0x130>(sfx);
-            dsig += g[ch] * (Tafter * v[ch] - (S[ch] + sfx_ex));
-            tot[ch] = lane_value(sfx, 0);
-        }
-        const float draw = step * dsig * sigmoid_f(raw + a.act_shift);
-        if (ok) {
-            a.raw[s] = draw;
-            if (a.with_color) {
-                reinterpret_cast<float4*>(a.col)[s] = make_float4(w * g[0], w * g[1], w * g[2], 0.0f);
-            }
-        }
-        if (a.cell_count) {   // bin the sample by fine cell (wave-uniform branch)
-            int cell = -1;
+        if (lane == static_cast<int>(last - first)) start = logT;
+        for (int64_t it = last; it >= first; --it) {
+            const int64_t s = s0 + it * 64 + lane;
+            const bool ok = s < s1;
+            float sd = 0.0f, raw = 0.0f, tk = 0.0f, v[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
             if (ok) {
-                float x[3], f[3];
-                recipe_x(ro, rd, tk, x);   // the sample's point, as sample_point forms it
-                cell = cell_of(a.g, x, f);
-                a.rec_head[s] = make_float4(f[0], f[1], f[2], draw);
+                raw = a.raw[s];
+                sd = softplus_f(raw + a.act_shift) * step;
+                tk = recipe_tk(tn, p, a.sa.sample_k[s], step);
+                if (a.with_color) {
+                    const float4 c = reinterpret_cast<const float4*>(a.col)[s];
+                    v[0] = c.x; v[1] = c.y; v[2] = c.z;
+                }
+                v[3] = tk;
+                v[4] = 1.0f;
             }
-            const int rank = run_rank(cell, ok, lane, a.cell_count);
-            if (ok) a.cell_rank[s] = make_int2(cell, rank);
+            const float logT0 = lane_value(start, static_cast<int>(it - first));
+            const float incl = wave_incl_scan(sd, lane);
+            const float excl = dpp_wave<0x138>(incl);   // wave_shr:1, lane 0 reads 0
+            const float Tafter = expf(logT0 - incl);     // T_{k+1}
+            const float w = ok ? expf(logT0 - excl) * -expm1f(-sd) : 0.0f;   // T_k alpha_k, as the forward
+            float dsig = 0.0f;
+            float tot[5];
+            for (int ch = 0; ch < 5; ++ch) {
+                const float wv = w * v[ch];
+                const float sfx = wave_incl_suffix(wv, lane);
+                const float sfx_ex = dpp_wave<0x130>(sfx);   // wave_shl:1, lane 63 reads 0
+                dsig += g[ch] * (Tafter * v[ch] - (S[ch] + sfx_ex));
+                tot[ch] = lane_value(sfx, 0);
+            }
+            const float draw = step * dsig * sigmoid_f(raw + a.act_shift);
+            if (ok) {
+                a.raw[s] = draw;
+                if (a.with_color) {
+                    reinterpret_cast<float4*>(a.col)[s] = make_float4(w * g[0], w * g[1], w * g[2], 0.0f);
+                }
+            }
+            if (a.cell_count) {   // bin the sample by fine cell (wave-uniform branch)
+                int cell = -1;
+                if (ok) {
+                    float x[3], f[3];
+                    recipe_x(ro, rd, tk, x);   // the sample's point, as sample_point forms it
+                    cell = cell_of(a.g, x, f);
+                    a.rec_head[s] = make_float4(f[0], f[1], f[2], draw);
+                }
+                const int rank = run_rank(cell, ok, lane, a.cell_count);
+                if (ok) a.cell_rank[s] = make_int2(cell, rank);
+            }
+            for (int ch = 0; ch < 5; ++ch) S[ch] += tot[ch];
         }
-        logTa += lane_value(suf, 0);
-        for (int ch = 0; ch < 5; ++ch) S[ch] += tot[ch];
     }
 }
 
