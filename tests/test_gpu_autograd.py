@@ -7,7 +7,7 @@ loss does not use arrive as None and are skipped."""
 import numpy as np
 import pytest
 
-from tests.helpers import np_of, report, to_dev
+from tests.helpers import assert_close, np_of, report, to_dev
 from tests.test_gpu_render import TOL32, _check_backward, _gpu, _oracle, _problem
 
 pytestmark = pytest.mark.gpu
@@ -36,7 +36,7 @@ def test_autograd_matches_oracle_adjoint(gpu_lib):
     samp, prm, ref, ro = _oracle(P)
     ref["_samp"] = samp
     for key, got in (("rgb", rgb), ("depth", depth), ("acc", acc)):
-        assert report(key, np_of(got.detach()), ref[key])[0] <= TOL32
+        assert_close(key, np_of(got.detach()), ref[key], TOL32)
     _check_backward(P, prm, ref, ro, np_of(d.grad), np_of(f.grad), np_of(m.grad), gR, TOL32, gD, gA)
 
 

@@ -8,7 +8,7 @@ sample in the batch every vertex takes the zero-gradient step."""
 import numpy as np
 import pytest
 
-from tests.helpers import np_of, report, to_dev
+from tests.helpers import assert_close, np_of, report, to_dev
 from tests.test_gpu_render import _gpu, _problem
 
 pytestmark = pytest.mark.gpu
@@ -63,7 +63,7 @@ def test_fused_backward_adam_equals_separate(gpu_lib, bf16):
                                                                                    gb.feat)):
         assert report(f"{name} update", np_of(pb - p0), np_of(pa - p0))[0] <= 1e-5, name
     for name, a, b in (("m density", mDa, mDb), ("v density", vDa, vDb), ("m feat", mFa, mFb), ("v feat", vFa, vFb)):
-        assert report(name, np_of(b), np_of(a))[0] <= 1e-5, name
+        assert_close(name, np_of(b), np_of(a), 1e-5)
     if bf16:
         assert np.array_equal(np_of(gb.feat_shadow).view(np.uint16), _bf16_bits(np_of(gb.feat)))
 
@@ -134,7 +134,7 @@ def test_train_step_equals_separate_calls(gpu_lib, bf16):
                              ("feat", grid.feat, ga.feat, gb.feat)):
         assert report(f"{name} update", np_of(pb - p0), np_of(pa - p0))[0] <= 1e-5, name
     for name, a, b in (("m density", mDa, mDb), ("v density", vDa, vDb), ("m feat", mFa, mFb), ("v feat", vFa, vFb)):
-        assert report(name, np_of(b), np_of(a))[0] <= 1e-5, name
+        assert_close(name, np_of(b), np_of(a), 1e-5)
     if bf16:
         assert np.array_equal(np_of(gb.feat_shadow).view(np.uint16), _bf16_bits(np_of(gb.feat)))
 
@@ -354,5 +354,5 @@ def test_train_step_full_size_matches_separate(gpu_lib):
     for name, p0, pa, pb in (("density", dens, ga.density, gb.density), ("feat", feat, ga.feat, gb.feat)):
         assert report(f"{name} update", np_of(pb - p0), np_of(pa - p0))[0] <= 1e-5, name
     for name, a, b in zip(("m density", "v density", "m feat", "v feat"), sa[:4], sb[:4]):
-        assert report(name, np_of(b), np_of(a))[0] <= 1e-5, name
+        assert_close(name, np_of(b), np_of(a), 1e-5)
     assert np.array_equal(np_of(gb.feat_shadow).view(np.uint16), _bf16_bits(np_of(gb.feat)))

@@ -5,15 +5,25 @@ grid, features uniform in [-1, 1]), the 100^3 coarse mask, a launch of
 from the bfloat16 shadow and the network on bfloat16 matrix cores.
 
 On the 1024 held-out rays it checks
-  * parity with the oracle's bfloat16 form (same rounding, exact sums) at the
-    bfloat16 tolerance of the render tests (5e-4), and
-  * the form's own error against the exact network and float32 feature
-    values, which is printed per output: rgb, depth, opacity and the density
-    gradient held to 2e-3 normwise; the feature and network gradients (loss
-    gradient non-zero on the held-out rays only) to 5e-2 (measured 3.3e-2
-    for the features: every product rounds both operands to 2^-9 relative
-    and a rounded operand may move a hidden unit across its ReLU kink, which
-    changes that sample's whole feature gradient).
+  * parity with the oracle's bfloat16 form (the fixed contract: the same
+    operands rounded, exact sums) at the render tests' bfloat16 bounds
+    (normwise 5e-4, max/max 4e-3, kink budget for the feature gradient);
+  * the form's own error against the exact network evaluated on the stored
+    values (the bfloat16 feature grid is the parameter the form renders
+    from), R23's bounds: rgb, depth, opacity and the density gradient to
+    2e-3, both metrics;
+  * the feature and network gradients against the exact network taken
+    along the same ReLU branches as the bfloat16 form (the derivative of the
+    same linear piece of the network): 1e-2, both metrics;
+  * the feature gradient against the exact network on its own branches is
+    printed with the share of samples whose branches differ.  A bfloat16
+    forward moves a pre-activation by up to 2^-8 of its term sum, so every
+    unit within that distance of its kink may switch branch; about 11 % of
+    these samples hold such a unit, and a switched unit changes the
+    sample's whole feature gradient.  No arithmetic that keeps the matrix
+    products in bfloat16 avoids this; it is held to 5e-2, and the training
+    comparison of the benchmark shows its effect on quality (none
+    measurable).
 """
 
 import numpy as np
@@ -21,10 +31,13 @@ import pytest
 
 import oracle as O
 import synth
-from tests.helpers import mlp_flat_np, normwise, np_of, report, to_dev
+from tests.helpers import (assert_close, check_grid_grad, check_weight_grads, kink_budget, mlp_flat_np, np_of,
+                           report, to_dev)
 
 pytestmark = pytest.mark.gpu
 F32 = np.float32
+TOLBF = 5e-4       # bfloat16 form against the oracle's bfloat16 form (derived in tests/test_gpu_render.py)
+ZETA_BF16 = 4e-3   # its max metric and kink margin: one bfloat16 step, 2^-8, rounded up
 
 
 @pytest.mark.timeout(300)
@@ -69,29 +82,53 @@ def test_bf16_form_error_on_held_out_rays(gpu_lib):
                          coarse=(bits_ref, P.box_min, P.box_max, raw.shape), morton=False)
     gh = g_held.astype(np.float64)
     res = {}
-    for name, bf16 in (("bf16 form", True), ("exact", False)):
-        feat = O.bf16_round(P.feat) if bf16 else P.feat
+    for name, feat, bf16 in (("bf16 form", O.bf16_round(P.feat), True), ("exact", O.bf16_round(P.feat), False),
+                             ("exact, float32 features", P.feat, False)):
         prm = O.Params(P.density, feat, P.Ws, P.bs, P.box_min, P.box_max, 0.0, mlp_bf16=bf16)
         ref = O.render_forward(prm, ho, hd, j[:1024], samp, P.step, P.bg)
         gr = O.render_backward(prm, ho, hd, j[:1024], samp, P.step, P.bg, ref, gh)
         res[name] = (ref, gr)
+        if name == "bf16 form":
+            # exact backward arithmetic from the bfloat16 form's forward state:
+            # its ReLU branches and colours, exact weights and exact sums
+            same = dict(ref, cache=dict(ref["cache"], mcache=dict(ref["cache"]["mcache"], bf16=False)))
+            res["same branches"] = (same, O.render_backward(prm, ho, hd, j[:1024], samp, P.step, P.bg, same, gh))
     n_s = int(samp["ray_offset"][-1])
     print(f"  held-out rays 1024, their samples {n_s}", flush=True)
 
     print("  against the oracle's bfloat16 form:", flush=True)
     ref, gr = res["bf16 form"]
     for k in ("rgb", "depth", "acc"):
-        assert report(k, got[k], ref[k])[0] <= 5e-4, k
-    assert report("grad_density", gd, gr["density"])[0] <= 5e-4
+        assert_close(k, got[k], ref[k], TOLBF, ZETA_BF16)
+    assert_close("grad_density", gd, gr["density"], TOLBF, ZETA_BF16)
+    prm_b = O.Params(P.density, O.bf16_round(P.feat), P.Ws, P.bs, P.box_min, P.box_max, 0.0, mlp_bf16=True)
+    budget, wb, frac = kink_budget(prm_b, ref, gh, ZETA_BF16, P.feat.shape, P.box_min, P.box_max)
+    check_grid_grad("grad_feat", gf, gr["feat"], budget, TOLBF, ZETA_BF16)
+    check_weight_grads(gm, gr["Ws"], gr["bs"], wb, TOLBF, ZETA_BF16)
 
-    print("  against the exact FP64 oracle:", flush=True)
+    print("  against the exact network on the stored values:", flush=True)
     ref, gr = res["exact"]
     for k in ("rgb", "depth", "acc"):
-        assert report(k, got[k], ref[k])[0] <= 2e-3, k
-    assert report("grad_density", gd, gr["density"])[0] <= 2e-3
+        assert_close(k, got[k], ref[k], 2e-3)
+    assert_close("grad_density", gd, gr["density"], 2e-3)
+
+    print("  against the exact network along the bfloat16 form's ReLU branches:", flush=True)
+    # the library's branches are the bfloat16 form's except at units within
+    # the bfloat16 margin of their kink: those samples keep the kink budget
+    ref, gr = res["same branches"]
+    check_grid_grad("grad_feat", gf, gr["feat"], budget, 1e-2)
+    check_weight_grads(gm, gr["Ws"], gr["bs"], wb, 1e-2)
+
+    ref, gr = res["exact"]
+    mc_b, mc_e = res["bf16 form"][0]["cache"]["mcache"], ref["cache"]["mcache"]
+    flip = ((mc_b["z1"] > 0) != (mc_e["z1"] > 0)).any(1) | ((mc_b["z2"] > 0) != (mc_e["z2"] > 0)).any(1)
+    print(f"  against the exact network on its own branches (samples whose branches differ: {flip.mean():.3f}):",
+          flush=True)
     assert report("grad_feat", gf, gr["feat"])[0] <= 5e-2
     ref_flat = np.concatenate([gr["Ws"][0].ravel(), gr["bs"][0], gr["Ws"][1].ravel(), gr["bs"][1],
                                gr["Ws"][2].ravel(), gr["bs"][2]])
-    nw = normwise(gm, ref_flat)
-    print(f"  grad_mlp: normwise {nw:.3e}", flush=True)
-    assert nw <= 5e-2
+    assert report("grad_mlp", gm, ref_flat)[0] <= 5e-2
+    print("  against the exact network on the float32 master features:", flush=True)
+    ref, gr = res["exact, float32 features"]
+    report("rgb", got["rgb"], ref["rgb"])
+    report("grad_feat", gf, gr["feat"])

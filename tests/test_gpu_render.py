@@ -1,36 +1,43 @@
 """GPU parity of forward rendering and its adjoint against the FP64 oracle.
 
-Tolerances.  float32 form: per-output normwise relative error
-||gpu - ref||_2 / ||ref||_2 <= 1e-5 for rgb, depth, acc, log T, segment and
-sample weights and for the density gradient.  The feature and network
+Every output tensor is held to both metrics of R23: the normwise relative
+error ||gpu - ref||_2 / ||ref||_2 and max|gpu - ref| / max|ref|.
+
+float32 form: both <= 1e-5 for rgb, depth, acc, log T, segment and sample
+weights and the density gradient; where rays reach max_samples terms the
+max metric takes the rounding bound of such sums, max_samples x 2^-24
+(3.3e-5 at the full configuration's 552).  The feature and network
 gradients pass through ReLU derivatives: a hidden unit whose pre-activation
 lies within the float32 error bound of zero (|z| <= 1e-4 x the sum of the
 absolute terms of its dot product) may take either branch, so entries and
 tensors reached by such samples are checked against a proven error budget
-(tests/helpers.kink_budget) and every other entry at 1e-5.
+(tests/helpers.kink_budget) and every other entry at the bounds above.
 
-bfloat16 form: compared with the oracle's bfloat16 form (same values rounded
-to bfloat16, exact arithmetic otherwise) at 5e-4 (float32 accumulation
-order and bfloat16 rounding-boundary cases; measured <= 1.2e-4), with the
-kink budget at a
-margin of 4e-3 x the term sum (an operand within float32 noise of a bf16
-rounding boundary may round to the neighbouring value, moving z by 2^-8 of
-that term); the
-form's own approximation error against the exact network is reported and
-held to 2e-3 for rgb, depth and opacity.  Actual errors are printed."""
+bfloat16 form, against the oracle's bfloat16 form (the fixed contract:
+the same operands rounded to bfloat16, exact arithmetic otherwise).  The
+library rounds float32 values that carry float32 accumulation error, at
+most K x 2^-24 relative for K = 128 terms; an operand rounds to the
+neighbouring bfloat16 value only when that error straddles a rounding
+boundary, which happens to a fraction p <= K 2^-24 / 2^-8 = 2e-3 of the
+operands, and moves its term by one bfloat16 step, 2^-8.  Such events are
+independent, so the normwise error is about 2^-8 sqrt(p) = 1.7e-4; the bound
+is three times that, 5e-4.  The max metric takes the single-event bound,
+ZETA_BF16 = 4e-3 (2^-8 rounded up), which is also the kink budget's margin.
+The form's own approximation error against the exact network is reported
+and held to 2e-3 for rgb, depth and opacity.  Actual errors are printed."""
 
 import numpy as np
 import pytest
 
 import oracle as O
 import synth
-from tests.helpers import (check_grid_grad, check_weight_grads, kink_budget, mlp_flat_np, np_of, report,
-                           to_dev)
+from tests.helpers import (assert_close, check_grid_grad, check_weight_grads, kink_budget, mlp_flat_np, np_of,
+                           report, to_dev)
 
 pytestmark = pytest.mark.gpu
 F32 = np.float32
 TOL32 = 1e-5
-TOLBF = 5e-4       # bf16 operands near a rounding boundary may round either way (2^-8 of a term)
+TOLBF = 5e-4       # 3 x 2^-8 sqrt(128 2^-24 / 2^-8): bf16 operands near a rounding boundary (docstring)
 ZETA = 1e-4        # float32: |z| within 1e-4 of its term sum may flip a ReLU
 ZETA_BF16 = 4e-3   # bfloat16: one operand may round to the neighbouring bf16 value (2^-8 of a term)
 
@@ -80,22 +87,30 @@ def _grads(api, grid, flat, s, out, g, P, bf16=False, gD=None, gA=None):
     return np_of(gd), np_of(gf), np_of(gm)
 
 
-def _check_backward(P, prm, ref, ro, gd, gf, gm, g_oracle, tol, gD=None, gA=None):
+def _check_backward(P, prm, ref, ro, gd, gf, gm, g_oracle, tol, gD=None, gA=None, tol_max=None):
     o, d, j = ro
+    tol_max = _tol_max(prm.mlp_bf16, tol) if tol_max is None else tol_max
     gr = O.render_backward(prm, o, d, j, ref["_samp"], P.step, P.bg, ref, g_oracle, gD, gA)
-    assert report("grad_density", gd, gr["density"])[0] <= tol
+    assert_close("grad_density", gd, gr["density"], tol, tol_max)
     zeta = ZETA_BF16 if prm.mlp_bf16 else ZETA
     budget, wb, frac = kink_budget(prm, ref, g_oracle, zeta, P.feat.shape, P.box_min, P.box_max)
     print(f"  samples with an ambiguous ReLU unit: {frac:.2e}", flush=True)
-    check_grid_grad("grad_feat", gf, gr["feat"], budget, tol)
-    check_weight_grads(gm, gr["Ws"], gr["bs"], wb, tol)
+    check_grid_grad("grad_feat", gf, gr["feat"], budget, tol, tol_max)
+    check_weight_grads(gm, gr["Ws"], gr["bs"], wb, tol, tol_max)
 
 
-def _fwd_keys(out, ref, keys, tol, sel=None):
+def _tol_max(bf16, tol):
+    """R23's second metric, max|gpu - ref| / max|ref|: the float32 bound
+    itself; for the bfloat16 form ZETA_BF16, since one operand that rounds
+    to the neighbouring bfloat16 value moves its product term by 2^-8 of
+    itself (the normwise bound averages such events, the max does not)."""
+    return ZETA_BF16 if bf16 else tol
+
+
+def _fwd_keys(out, ref, keys, tol, sel=None, tol_max=None):
     for key in keys:
         got = np_of(out[key]) if sel is None else np_of(out[key])[sel]
-        nw, _ = report(key, got, ref[key])
-        assert nw <= tol, key
+        assert_close(key, got, ref[key], tol, tol if tol_max is None else tol_max)
 
 
 @pytest.mark.parametrize("bf16", [False, True])
@@ -110,8 +125,8 @@ def test_render_forward_parity_tiny(gpu_lib, bf16):
     n = int(samp["ray_offset"][-1])
     print(f"  rays {P.rays.o.shape[0]} samples {n}", flush=True)
     tol = TOLBF if bf16 else TOL32
-    _fwd_keys(out, ref, ("rgb", "depth", "acc", "log_t_end", "seg_w"), tol)
-    assert report("sample_w", np_of(out["sample_w"])[:n], ref["sample_w"])[0] <= tol
+    _fwd_keys(out, ref, ("rgb", "depth", "acc", "log_t_end", "seg_w"), tol, tol_max=_tol_max(bf16, tol))
+    assert_close("sample_w", np_of(out["sample_w"])[:n], ref["sample_w"], tol, _tol_max(bf16, tol))
     if bf16:
         _, _, exact, _ = _oracle(P, bf16=False)
         print("  bf16 form vs exact network:", flush=True)
@@ -179,6 +194,37 @@ def test_render_with_coarse_mask_and_large_values(gpu_lib):
     _check_backward(P, prm, ref, ro, gd, gf, gm, g, TOL32)
 
 
+def test_render_opaque_samples(gpu_lib):
+    """Samples with sigma*delta from 100 to 150 (alpha = 1 in float32,
+    T behind them below the float32 range): the adjoint forms each weight
+    from the transmittance in front of the sample, so it stays finite, and
+    forward and backward stay at float32 tolerance."""
+    from paper_2111_11215_amd import api
+    P = _problem(6, n_rays=2048, bias=0.0)
+    rng = np.random.default_rng(9)
+    hot = np.zeros(P.density.shape, bool)   # whole cells hot: every point inside reaches sd >= 100
+    for i, j, k in rng.integers(0, P.density.shape[0] - 1, (40, 3)):
+        hot[i:i + 2, j:j + 2, k:k + 2] = True
+    sd_max = 150.0
+    P.density = np.where(hot, rng.uniform(100.0, sd_max, P.density.shape) / P.step, P.density).astype(F32)
+    # float32 interpolation of corners as large as sd_max/step moves a
+    # sample's sigma*delta by up to about 10 u sd_max (u = 2^-24), and with it
+    # the transmittance behind the sample by that much relative
+    tol = max(TOL32, 10 * 2.0 ** -24 * sd_max)
+    grid, flat, s = _gpu(P)
+    out = api.render_fwd(grid, flat, s, P.bg)
+    samp, prm, ref, ro = _oracle(P)
+    ref["_samp"] = samp
+    sd = O.softplus(ref["cache"]["raw"]) * P.step
+    print(f"  samples with sigma*delta >= 100: {int((sd >= 100).sum())}", flush=True)
+    assert (sd >= 100).sum() > 100
+    _fwd_keys(out, ref, ("rgb", "depth", "acc"), tol)
+    _, g = O.photo_loss(ref["rgb"], P.rays.target)
+    gd, gf, gm = _grads(api, grid, flat, s, out, g, P)
+    assert np.isfinite(gd).all() and np.isfinite(gf).all() and np.isfinite(gm).all()
+    _check_backward(P, prm, ref, ro, gd, gf, gm, g, tol)
+
+
 @pytest.mark.parametrize("bf16", [False, True])
 def test_render_full_size_sampled_rays(gpu_lib, bf16):
     """Full configuration (160^3 grids with random values, 8192 rays, coarse
@@ -206,12 +252,15 @@ def test_render_full_size_sampled_rays(gpu_lib, bf16):
                                  morton=False)
     ref["_samp"] = samp
     tol = TOLBF if bf16 else TOL32
-    _fwd_keys(out, ref, ("rgb", "depth", "acc", "log_t_end"), tol, sel=sel)
+    # max metric of the float32 form: the rounding bound of sums along rays
+    # of up to max_samples terms (n u), as for the stress shape
+    tol_max = ZETA_BF16 if bf16 else max(TOL32, P.max_samples * 2.0 ** -24)
+    _fwd_keys(out, ref, ("rgb", "depth", "acc", "log_t_end"), tol, sel=sel, tol_max=tol_max)
     g_sub = rng.normal(size=(256, 3)) * 1e-3
     g = np.zeros((B, 3))
     g[sel] = g_sub
     gd, gf, gm = _grads(api, grid, flat, s, out, g, P, bf16)
-    _check_backward(P, prm, ref, ro, gd, gf, gm, g_sub, tol)
+    _check_backward(P, prm, ref, ro, gd, gf, gm, g_sub, tol, tol_max=tol_max)
 
 
 def test_photo_loss_parity(gpu_lib):
@@ -221,4 +270,4 @@ def test_photo_loss_parity(gpu_lib):
     loss, grad = api.photo_loss(to_dev(c), to_dev(t))
     L, g = O.photo_loss(c, t)
     assert abs(float(np_of(loss)[0]) - L) <= 1e-5 * L
-    assert report("grad", np_of(grad), g)[0] <= 1e-6
+    assert_close("grad", np_of(grad), g, 1e-6)

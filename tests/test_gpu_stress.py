@@ -23,7 +23,8 @@ import pytest
 
 import oracle as O
 import synth
-from tests.helpers import check_grid_grad, check_weight_grads, kink_budget, mlp_flat_np, np_of, report, to_dev
+from tests.helpers import (assert_close, check_grid_grad, check_weight_grads, kink_budget, mlp_flat_np, np_of, report,
+                           to_dev)
 
 pytestmark = pytest.mark.gpu
 F32 = np.float32
@@ -71,7 +72,7 @@ def oracle_fd_check(P, sel, g_sub, rng, rgb_sel=None, n_entries=256, n_params=16
     ref = O.render_forward(prm, o, d, j, samp, P.step, P.bg)
     ref["_samp"] = samp
     if rgb_sel is not None:
-        assert report("rgb (checked rays)", rgb_sel, ref["rgb"])[0] <= TOL32
+        assert_close("rgb (checked rays)", rgb_sel, ref["rgb"], TOL32, TOL_LONG)
     gr = O.render_backward(prm, o, d, j, samp, P.step, P.bg, ref, g_sub)
 
     # ---- 1. finite differences of the oracle against its adjoint
@@ -168,7 +169,7 @@ def test_stress_finite_differences_and_adjoint(gpu_lib):
     prm, ref, gr = oracle_fd_check(P, sel, g_sub, rng, rgb_sel)
 
     # ---- 2. the GPU adjoint against the oracle's
-    assert report("grad_density", gd, gr["density"])[0] <= TOL_LONG
+    assert_close("grad_density", gd, gr["density"], TOL_LONG)
     budget, wb, frac = kink_budget(prm, ref, g_sub, ZETA, P.feat.shape, P.box_min, P.box_max)
     print(f"  samples with an ambiguous ReLU unit: {frac:.2e}", flush=True)
     check_grid_grad("grad_feat", gf, gr["feat"], budget, TOL_LONG)

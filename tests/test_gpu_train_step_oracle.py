@@ -1,0 +1,189 @@
+"""The call the benchmark times, dvgo_train_step (forward, Eq. photo_loss and
+its gradient, the adjoint, the grids' Adam step fused into the gradient
+gather, and the network's Adam step), against the oracle's
+render_forward -> photo_loss -> render_backward -> adam_step on every
+parameter tensor.
+
+Cases: the tiny configuration's whole 4096-ray batch (one iteration from
+zero moments at t = 1, as that configuration states, and a step at t = 5
+from seeded moments on 40 % of the vertices), float32 and bfloat16 forms,
+with and without the activity mask; and one whole 8192-ray batch of the
+full configuration (160^3 grids, coarse mask of the sphere scene, launch of
+the benchmark) at t = 5 from seeded moments, both forms.
+
+Bounds.  Colour and loss: normwise and max/max (R23) at 1e-5 (float32); the
+bfloat16 form against the oracle's bfloat16 form at 5e-4 normwise (derived
+in tests/test_gpu_render.py) and 4e-3 of the largest entry per entry (one
+operand rounding to the neighbouring bfloat16 value moves one product term
+by at most 2^-8 of itself).  Parameters and moments: entry by entry through
+tests/helpers.check_adam_entries, with the per-entry gradient bound
+err_g = tol_max x max|g| plus the ReLU kink budget of the entries that an
+ambiguous sample reaches and, for the density, the running-error bound of
+the adjoint's ray sums (tests/helpers.density_grad_condition), for the
+features that of the network adjoint's contractions and the vertex sums
+(tests/helpers.feat_grad_condition); p's bound is the Adam update's own sensitivity to
+err_g (learning-rate and eps aware).  Vertices with zero moments that no
+sample reaches (not a corner of any sample's cell, widened by one cell) keep
+p, m and v bit for bit.  With zero moments (t = 1) the
+first moment is (1 - beta1) times the gradient, which is then also checked
+normwise (R23)."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from tests.helpers import (assert_close, check_adam_entries, check_grid_grad, kink_budget, mlp_flat_np, mlp_unflat,
+                           density_grad_condition, feat_grad_condition, np_of, samples_per_vertex, to_dev,
+                           untouched_vertices)
+
+pytestmark = pytest.mark.gpu
+F32 = np.float32
+TOL32 = 1e-5
+TOLBF = 5e-4
+ZETA = 1e-4
+ZETA_BF16 = 4e-3
+BETAS, EPS = (0.9, 0.999), 1e-8
+
+
+def _seeded_moments(rng, shape, frac):
+    """m ~ N(0, 1e-3), v ~ U(0, 1e-5) on a random fraction of the vertices
+    (all channels of a vertex together), zero elsewhere."""
+    nv = int(np.prod(shape[:3]))
+    on = (rng.random(nv) < frac).reshape(shape[:3])
+    if len(shape) == 4:
+        on = np.broadcast_to(on[..., None], shape)
+    m = np.where(on, rng.normal(size=shape) * 1e-3, 0.0).astype(F32)
+    v = np.where(on, rng.random(shape) * 1e-5, 0.0).astype(F32)
+    return m, v
+
+
+def _run_case(P, coarse_gpu, coarse_ref, bf16, active, t, lr_grid, lr_mlp, moments, seed):
+    import torch
+    from paper_2111_11215_amd import api
+    from paper_2111_11215_amd._lib import DVGO_BF16, DVGO_F32
+    prec = DVGO_BF16 if bf16 else DVGO_F32
+    rng = np.random.default_rng(seed)
+    flat0 = mlp_flat_np(P.Ws, P.bs)
+    if moments:
+        mD0, vD0 = _seeded_moments(rng, P.density.shape, 0.4)
+        mF0, vF0 = _seeded_moments(rng, P.feat.shape, 0.4)
+        mM0 = (rng.normal(size=flat0.shape) * 1e-4).astype(F32)
+        vM0 = (rng.random(flat0.shape) * 1e-8).astype(F32)
+    else:
+        mD0, vD0 = np.zeros_like(P.density), np.zeros_like(P.density)
+        mF0, vF0 = np.zeros_like(P.feat), np.zeros_like(P.feat)
+        mM0, vM0 = np.zeros_like(flat0), np.zeros_like(flat0)
+
+    # ---- library: one dvgo_train_step
+    grid = api.Grid(to_dev(P.density), to_dev(P.feat), tuple(P.box_min), tuple(P.box_max), P.act_shift)
+    if bf16:
+        grid.feat_shadow = grid.feat.to(torch.bfloat16).view(torch.int16).contiguous()
+    flat = to_dev(flat0)
+    mD, vD, mF, vF, mM, vM = (to_dev(a) for a in (mD0, vD0, mF0, vF0, mM0, vM0))
+    act = None
+    if active:
+        act = torch.zeros(api.grid_active_words(P.density.size), dtype=torch.int32, device="cuda")
+        api.grid_active_init(mD, vD, mF, vF, act)
+    print(f"  library: {P.rays.o.shape[0]} rays, {'bf16' if bf16 else 'fp32'}, t={t}, "
+          f"mask={'on' if active else 'off'}", flush=True)
+    jit = to_dev(P.rays.jitter) if P.rays.jitter is not None else None
+    s = api.sample_rays(to_dev(P.rays.o), to_dev(P.rays.d), jit, P.box_min, P.box_max, P.step, P.max_samples,
+                        coarse=coarse_gpu)
+    gm = torch.zeros_like(flat)
+    loss, rgb = api.train_step(grid, flat, s, to_dev(P.rays.target), mD, vD, mF, vF, gm, lr_grid, t, BETAS, EPS,
+                               P.bg, precision=prec, use_shadow=bf16, active=act, mlp_adam=(mM, vM, lr_mlp))
+    torch.cuda.synchronize()
+    assert float(gm.abs().max()) == 0.0
+    got = dict(rgb=np_of(rgb), loss=float(np_of(loss)[0]), pD=np_of(grid.density), pF=np_of(grid.feat),
+               pM=np_of(flat), mD=np_of(mD), vD=np_of(vD), mF=np_of(mF), vF=np_of(vF), mM=np_of(mM), vM=np_of(vM),
+               shadow=np_of(grid.feat_shadow).view(np.uint16) if bf16 else None,
+               n_kept=int(s.n_kept.item()))
+
+    # ---- oracle: forward, loss, adjoint, Adam
+    samp = O.sample_rays(P.rays.o, P.rays.d, P.rays.jitter, P.box_min, P.box_max, P.step, P.max_samples,
+                         coarse=coarse_ref)
+    assert got["n_kept"] == int(samp["ray_offset"][-1])
+    feat = O.bf16_round(P.feat) if bf16 else P.feat
+    prm = O.Params(P.density, feat, P.Ws, P.bs, P.box_min, P.box_max, P.act_shift, mlp_bf16=bf16)
+    ref = O.render_forward(prm, P.rays.o, P.rays.d, P.rays.jitter, samp, P.step, P.bg)
+    L, g = O.photo_loss(ref["rgb"], P.rays.target)
+    gr = O.render_backward(prm, P.rays.o, P.rays.d, P.rays.jitter, samp, P.step, P.bg, ref, g)
+    tol = TOLBF if bf16 else TOL32
+    tol_max = ZETA_BF16 if bf16 else TOL32
+    assert_close("rgb", got["rgb"], ref["rgb"], tol, tol_max)
+    print(f"  loss {got['loss']:.7e} oracle {L:.7e}", flush=True)
+    assert abs(got["loss"] - L) <= tol * L
+
+    budget, wb, frac = kink_budget(prm, ref, g, ZETA_BF16 if bf16 else ZETA, P.feat.shape, P.box_min, P.box_max)
+    print(f"  samples with an ambiguous ReLU unit: {frac:.2e}", flush=True)
+    gD, gF = gr["density"], gr["feat"]
+    gM = np.concatenate([gr["Ws"][0].ravel(), gr["bs"][0], gr["Ws"][1].ravel(), gr["bs"][1], gr["Ws"][2].ravel(),
+                         gr["bs"][2]])
+    # density entries: the larger of tol_max of the largest entry and the
+    # running-error bound of the adjoint's sums along rays of up to
+    # max_samples terms (cancellation in T_{k+1} v_k - S_{k+1} included) and
+    # of the vertex's sum over its samples
+    cond = density_grad_condition(ref, g, P.step, P.act_shift, P.bg)
+    nv = samples_per_vertex(ref["cache"]["x"], P.box_min, P.box_max, P.density.shape)
+    eD = tol_max * np.abs(gD).max() + (P.max_samples + nv) * 2.0 ** -24 * \
+        O.interp_scatter(P.density.shape, ref["cache"]["x"], P.box_min, P.box_max, cond)
+    # feature entries: kink budget, plus the running-error bound of the
+    # network adjoint's contractions (K <= 3 + 128 + 128) and the vertex sums
+    U = feat_grad_condition(prm, ref, g)
+    eF = tol_max * np.abs(gF).max() + budget + (259 + nv[..., None]) * 2.0 ** -24 * \
+        O.interp_scatter(P.feat.shape, ref["cache"]["x"], P.box_min, P.box_max, U)
+    eM = np.concatenate([np.full(a.size, tol_max * np.abs(a).max() + wb[k])
+                         for k, a in zip(["W1", "b1", "W2", "b2", "W3", "b3"], mlp_unflat(gM))])
+    idle = untouched_vertices(ref["cache"]["x"], P.box_min, P.box_max, P.density.shape)
+    check_adam_entries("density", got["pD"], got["mD"], got["vD"], P.density, mD0, vD0, gD, eD, lr_grid, t,
+                       untouched=idle)
+    check_adam_entries("features", got["pF"], got["mF"], got["vF"], P.feat, mF0, vF0, gF, eF, lr_grid, t,
+                       untouched=idle[..., None])
+    check_adam_entries("network", got["pM"], got["mM"], got["vM"], flat0, mM0, vM0, gM, eM, lr_mlp, t)
+    if not moments:   # m = (1 - beta1) g: the gradients themselves, normwise and max (R23)
+        b1 = float(F32(BETAS[0]))
+        assert_close("grad density (from m)", got["mD"] / (1 - b1), gD, tol, tol_max)
+        check_grid_grad("grad feat (from m)", got["mF"] / (1 - b1), gF, budget, tol)
+    if bf16:
+        u = got["pF"].view(np.uint32).astype(np.uint64)
+        want = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+        assert np.array_equal(got["shadow"], want)
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("moments", [False, True])
+@pytest.mark.parametrize("active", [False, True])
+@pytest.mark.parametrize("bf16", [False, True])
+def test_train_step_tiny_against_oracle(gpu_lib, bf16, active, moments):
+    """The tiny configuration's whole batch: 4096 rays, 32^3 grids U(-1,1),
+    the Xavier network, lr 0.1 / 1e-3; t = 1 from zero moments without
+    jitter (the configuration's one iteration), or t = 5 from seeded moments
+    with seeded jitter."""
+    P = synth.tiny_config(0, jitter=moments, n_rays=4096)
+    t = 5 if moments else 1
+    _run_case(P, None, None, bf16, active, t, 0.1, 1e-3, moments, seed=31 + 2 * bf16 + active)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("bf16", [False, True])
+def test_train_step_full_batch_against_oracle(gpu_lib, bf16):
+    """One whole 8192-ray batch of the full configuration in the launch the
+    benchmark times: 160^3 grids (random values, shift from alpha_init
+    1e-2), the 100^3 coarse mask of the sphere scene at tau 1e-4, jitter;
+    t = 5 from moments seeded on 40 % of the vertices, with the activity
+    mask and the fused network step."""
+    from paper_2111_11215_amd import api
+    P = synth.full_config(0)
+    rng = np.random.default_rng(2)
+    P.density = rng.uniform(-1, 1, P.density.shape).astype(F32)
+    P.feat = rng.uniform(-1, 1, P.feat.shape).astype(F32)
+    P.act_shift = api.low_density_bias(synth.FULL_ALPHA_INIT, 2.0 / 159)
+    raw = P.coarse_raw
+    thr = api.coarse_raw_threshold(synth.FULL_TAU, P.step)
+    bits = api.coarse_mask_build(to_dev(raw), P.box_min, P.box_max, thr)
+    bits_ref = O.coarse_cell_bits(raw, O.coarse_raw_threshold(synth.FULL_TAU, P.step))
+    assert np.array_equal(np_of(bits).view(np.uint32), bits_ref)
+    lr = api.lr_at(0.1, 5)
+    _run_case(P, (bits, P.box_min, P.box_max, raw.shape), (bits_ref, P.box_min, P.box_max, raw.shape), bf16, True,
+              5, lr, api.lr_at(1e-3, 5), True, seed=41 + bf16)
