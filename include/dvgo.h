@@ -179,6 +179,28 @@ int32_t dvgo_sample_rays(const float* rays_o, const float* rays_d, const float* 
                          int32_t* sample_k, int64_t capacity, int64_t* n_kept,
                          void* workspace, size_t workspace_bytes, void* stream);
 
+/* dvgo_sample_rays without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, outputs, recipe and
+ * errors as dvgo_sample_rays; the call allocates nothing: its scratch (the
+ * per-ray counts and Morton keys) lives in a static device array of the
+ * library, 2 MiB + 256 bytes, which every GPU the library runs on holds
+ * until the process ends.  Limit: B <= 262144 rays, else DVGO_E_UNSUPPORTED
+ * with dvgo_last_error() saying so and nothing enqueued.  All calls on one
+ * GPU share that array: calls that overlap on one GPU (concurrent streams,
+ * or host threads with no ordering between their calls) race and must not
+ * be issued; calls ordered on one stream are safe.  The array's device
+ * address is looked up once per device, on the first call with that device
+ * current. */
+int32_t dvgo_sample_rays_noalloc(const float* rays_o, const float* rays_d, const float* jitter,
+                                 int32_t B, const dvgo_box* box /*host*/, float step,
+                                 int32_t max_samples, const uint32_t* coarse_bits,
+                                 const dvgo_box* coarse_box /*host, or NULL*/,
+                                 const uint32_t* seg_mask, int32_t morton,
+                                 float* t_near, float* t_far, uint8_t* valid, int32_t* n_uniform,
+                                 int32_t* perm, int32_t* ray_offset, int32_t* sample_ray,
+                                 int32_t* sample_k, int64_t capacity, int64_t* n_kept, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Forward volume rendering (paper Eq. volume_rendering, Eq. fine_queries,
  * Eq. post_activation) of the samples listed by dvgo_sample_rays, per ray in

@@ -64,6 +64,8 @@ SIGNATURES = {
     "dvgo_sample_workspace_bytes": (c_size_t, [c_int32]),
     "dvgo_sample_rays": (c_int32, [P, P, P, c_int32, POINTER(Box), c_float, c_int32, P, POINTER(Box), P, c_int32,
                                    P, P, P, P, P, P, P, P, c_int64, P, P, c_size_t, P]),
+    "dvgo_sample_rays_noalloc": (c_int32, [P, P, P, c_int32, POINTER(Box), c_float, c_int32, P, POINTER(Box), P,
+                                           c_int32, P, P, P, P, P, P, P, P, c_int64, P, P]),
     "dvgo_render_workspace_bytes": (c_size_t, [c_int32, c_int64, c_int32, POINTER(Box)]),
     "dvgo_render_fwd": (c_int32, [POINTER(Field), POINTER(Mlp), P, P, P, P, P, P, P, P, P, P, c_int64, c_int32,
                                   c_float, POINTER(c_float), P, P, P, P, P, P, P, c_size_t, P]),

@@ -190,9 +190,11 @@ def coarse_mask_build(raw: torch.Tensor, cmin, cmax, raw_threshold: float) -> to
 
 
 def sample_rays(rays_o, rays_d, jitter, box_min, box_max, step, max_samples, coarse=None, seg_mask=None,
-                morton=False, capacity=None, clip_only=False) -> Samples:
+                morton=False, capacity=None, clip_only=False, no_alloc=False) -> Samples:
     """``coarse`` = (bits, cmin, cmax, cn) or None; seg_mask int32 [B] or None.
-    ``clip_only``: t_near, t_far, valid, n_uniform and perm only (no list)."""
+    ``clip_only``: t_near, t_far, valid, n_uniform and perm only (no list).
+    ``no_alloc``: call dvgo_sample_rays_noalloc (the library's static scratch
+    instead of a workspace)."""
     lib = load()
     dev = rays_o.device
     B = rays_o.shape[0]
@@ -217,6 +219,14 @@ def sample_rays(rays_o, rays_d, jitter, box_min, box_max, step, max_samples, coa
     if coarse is not None:
         cbits = coarse[0]
         cbox = make_box(coarse[1], coarse[2], coarse[3])
+    if no_alloc:
+        check("dvgo_sample_rays_noalloc", lib.dvgo_sample_rays_noalloc(
+            _ptr(rays_o), _ptr(rays_d), _ptr(jitter), B, ctypes.byref(box), float(step), int(max_samples),
+            _ptr(cbits), ctypes.byref(cbox) if cbox is not None else None, _ptr(seg_mask), int(bool(morton)),
+            _ptr(t_near), _ptr(t_far), _ptr(valid), _ptr(n_uniform), _ptr(perm), _ptr(ray_offset), _ptr(sample_ray),
+            _ptr(sample_k), int(capacity), _ptr(n_kept), _stream(dev)))
+        return Samples(rays_o, rays_d, jitter, float(step), t_near, t_far, valid, n_uniform, perm, ray_offset,
+                       sample_ray, sample_k, n_kept, int(capacity))
     nws = lib.dvgo_sample_workspace_bytes(B)
     ws = workspace(nws, dev)
     check("dvgo_sample_rays", lib.dvgo_sample_rays(

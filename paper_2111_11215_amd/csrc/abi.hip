@@ -57,6 +57,8 @@ void record_hip_error(hipError_t e) {
     std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s", hipGetErrorName(e), hipGetErrorString(e));
 }
 
+void record_text(const char* msg) { std::snprintf(g_last_error, sizeof(g_last_error), "%s", msg); }
+
 int device_cu_count() {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 256;

@@ -12,6 +12,8 @@ namespace dvgo {
 
 // Records the last HIP error text for dvgo_last_error().
 void record_hip_error(hipError_t e);
+// Records a library message as the dvgo_last_error() text.
+void record_text(const char* msg);
 
 // Checks the launch just enqueued; returns DVGO_OK or DVGO_E_HIP.
 inline int32_t launch_status() {

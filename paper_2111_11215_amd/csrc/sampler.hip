@@ -3,6 +3,8 @@
 // sample list (paper Sec. 4.2 "Fine-stage points sampling" and "Free space
 // skipping" rule one, Eq. coarse_sample, training jitter of the supplementary
 // implementation details).
+#include <mutex>
+
 #include "common.hpp"
 
 using dvgo::GridArgs;
@@ -420,6 +422,49 @@ __global__ void coarse_mask_kernel(const float* __restrict__ raw, int nx, int ny
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Static scratch of dvgo_sample_rays_noalloc: the workspace of up to
+// kNoAllocMaxRays rays (per-ray counts and Morton keys, each rounded up to
+// 256 bytes, plus 256), held by every GPU the library runs on until the
+// process ends.  Host code never passes the array's name to a kernel: it is
+// a host-side stand-in, not a device address.  Each device's own address of
+// its copy comes from hipGetSymbolAddress, taken once per device with that
+// device current, and is what the call hands its kernels.
+// ---------------------------------------------------------------------------
+constexpr int32_t kNoAllocMaxRays = 1 << 18;
+constexpr size_t kNoAllocScratchBytes = ((static_cast<size_t>(kNoAllocMaxRays) * 4 + 255) / 256 * 256) * 2 + 256;
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+void* g_scratch_ptr[kMaxScratchDevices] = {nullptr};
+std::mutex g_scratch_mutex;
+
+// This device's address of `scratch` (looked up on its first use).
+int32_t scratch_address(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        dvgo::record_hip_error(e);
+        return DVGO_E_HIP;
+    }
+    if (dev < 0 || dev >= kMaxScratchDevices) return DVGO_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            dvgo::record_hip_error(e != hipSuccess ? e : hipErrorInvalidSymbol);
+            return DVGO_E_HIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return DVGO_OK;
+}
+}  // namespace
+
 extern "C" {
 
 int32_t dvgo_coarse_mask_build(const float* raw, const dvgo_box* cbox, float raw_threshold, uint32_t* bits,
@@ -439,7 +484,7 @@ size_t dvgo_sample_workspace_bytes(int32_t B) {
     return dvgo::align_up(static_cast<size_t>(B) * 4, 256) * 2 + 256;
 }
 
-int32_t dvgo_sample_rays(const float* rays_o, const float* rays_d, const float* jitter, int32_t B,
+static int32_t sample_rays_impl(const float* rays_o, const float* rays_d, const float* jitter, int32_t B,
                          const dvgo_box* box, float step, int32_t max_samples, const uint32_t* coarse_bits,
                          const dvgo_box* coarse_box, const uint32_t* seg_mask, int32_t morton, float* t_near,
                          float* t_far, uint8_t* valid, int32_t* n_uniform, int32_t* perm, int32_t* ray_offset,
@@ -520,6 +565,38 @@ int32_t dvgo_sample_rays(const float* rays_o, const float* rays_d, const float* 
     DVGO_LAUNCH(K_FILL_KEPT, fill_kept_kernel, dim3(wblocks), dim3(256), 0, s, ka, ray_offset, capacity, sample_ray,
                        sample_k);
     return dvgo::launch_status();
+}
+
+int32_t dvgo_sample_rays(const float* rays_o, const float* rays_d, const float* jitter, int32_t B,
+                         const dvgo_box* box, float step, int32_t max_samples, const uint32_t* coarse_bits,
+                         const dvgo_box* coarse_box, const uint32_t* seg_mask, int32_t morton, float* t_near,
+                         float* t_far, uint8_t* valid, int32_t* n_uniform, int32_t* perm, int32_t* ray_offset,
+                         int32_t* sample_ray, int32_t* sample_k, int64_t capacity, int64_t* n_kept,
+                         void* workspace, size_t workspace_bytes, void* stream) {
+    return sample_rays_impl(rays_o, rays_d, jitter, B, box, step, max_samples, coarse_bits, coarse_box, seg_mask,
+                            morton, t_near, t_far, valid, n_uniform, perm, ray_offset, sample_ray, sample_k, capacity,
+                            n_kept, workspace, workspace_bytes, stream);
+}
+
+// The same call with its workspace in the library's static device array
+// (see the declaration): the per-ray counts and Morton keys of up to
+// kNoAllocMaxRays rays.  Every kernel of the call writes these before
+// reading them, so nothing needs clearing between calls.
+int32_t dvgo_sample_rays_noalloc(const float* rays_o, const float* rays_d, const float* jitter, int32_t B,
+                                 const dvgo_box* box, float step, int32_t max_samples, const uint32_t* coarse_bits,
+                                 const dvgo_box* coarse_box, const uint32_t* seg_mask, int32_t morton,
+                                 float* t_near, float* t_far, uint8_t* valid, int32_t* n_uniform, int32_t* perm,
+                                 int32_t* ray_offset, int32_t* sample_ray, int32_t* sample_k, int64_t capacity,
+                                 int64_t* n_kept, void* stream) {
+    if (B > kNoAllocMaxRays) {
+        dvgo::record_text("dvgo_sample_rays_noalloc: more rays than its static scratch holds (262144)");
+        return DVGO_E_UNSUPPORTED;
+    }
+    void* ws = nullptr;
+    if (int32_t st = scratch_address(&ws)) return st;
+    return sample_rays_impl(rays_o, rays_d, jitter, B, box, step, max_samples, coarse_bits, coarse_box, seg_mask,
+                            morton, t_near, t_far, valid, n_uniform, perm, ray_offset, sample_ray, sample_k, capacity,
+                            n_kept, ws, kNoAllocScratchBytes, stream);
 }
 
 }  // extern "C"
