@@ -812,3 +812,81 @@ def scene_render(o, d, centers, radii, rho, rgb, box_min, box_max, step, bg, edg
         T = np.concatenate([[1.0], np.cumprod(1.0 - a)])
         out[r] = (T[:-1, None] * a[:, None] * col).sum(0) + T[-1] * np.asarray(bg, np.float64)
     return out
+
+
+# ===========================================================================
+# 6. Image-fitting toy of Sec. 3 ("Sharp decision boundary via
+#    post-activation"): a low-resolution 2D grid fitted to a binary image
+#    with pre-, in- or post-activation (Eq. pre_activation, in_activation,
+#    post_activation, with bilinear interpolation and no shift b)
+# ===========================================================================
+TOY_MODES = ("pre", "in", "post")
+
+
+def toy2d_weights(H, W, gh, gw):
+    """Bilinear weights of every pixel centre on a vertex grid of gh x gw
+    points spanning the image inclusively: pixel (i, j) sits at grid
+    coordinates u = (i + 1/2)(gh - 1)/H, v = (j + 1/2)(gw - 1)/W; cell
+    i0 = clamp(floor(u), 0, gh - 2) (likewise j0), fractions clamped to
+    [0, 1].  Returns (i0 [H*W], j0 [H*W], weights [H*W, 4]) for the corners
+    (i0, j0), (i0, j0+1), (i0+1, j0), (i0+1, j0+1)."""
+    ii, jj = np.meshgrid(np.arange(H, dtype=np.float64), np.arange(W, dtype=np.float64), indexing="ij")
+    u = (ii.ravel() + 0.5) * (gh - 1) / H
+    v = (jj.ravel() + 0.5) * (gw - 1) / W
+    i0 = np.clip(np.floor(u), 0, gh - 2).astype(np.int64)
+    j0 = np.clip(np.floor(v), 0, gw - 2).astype(np.int64)
+    fu = np.clip(u - i0, 0.0, 1.0)
+    fv = np.clip(v - j0, 0.0, 1.0)
+    w = np.stack([(1 - fu) * (1 - fv), (1 - fu) * fv, fu * (1 - fv), fu * fv], axis=1)
+    return i0, j0, w
+
+
+def _toy_corners(V, i0, j0):
+    V = np.asarray(V, np.float64)
+    return np.stack([V[i0, j0], V[i0, j0 + 1], V[i0 + 1, j0], V[i0 + 1, j0 + 1]], axis=1)
+
+
+def toy2d_forward(V, H, W, mode, delta=1.0):
+    """Predicted alpha image [H, W] of the grid V [gh, gw]:
+    pre:  interp(x, alpha(softplus(V)));   in: alpha(interp(x, softplus(V)));
+    post: alpha(softplus(interp(x, V))),   alpha(s) = 1 - exp(-s delta)."""
+    gh, gw = np.asarray(V).shape
+    i0, j0, w = toy2d_weights(H, W, gh, gw)
+    c = _toy_corners(V, i0, j0)
+    if mode == "pre":
+        a = np.sum(w * density_to_alpha(softplus(c), delta), axis=1)
+    elif mode == "in":
+        a = density_to_alpha(np.sum(w * softplus(c), axis=1), delta)
+    elif mode == "post":
+        a = density_to_alpha(softplus(np.sum(w * c, axis=1)), delta)
+    else:
+        raise ValueError(mode)
+    return a.reshape(H, W)
+
+
+def toy2d_loss_grad(V, target, mode, delta=1.0):
+    """Mean squared error of the predicted alpha image against ``target``
+    [H, W] and its gradient with respect to V, by the chain rule through the
+    mode's activation order (softplus' = sigmoid, alpha'(s) = delta e^{-s delta})
+    and the transpose of the bilinear interpolation."""
+    V = np.asarray(V, np.float64)
+    gh, gw = V.shape
+    H, W = np.asarray(target).shape
+    i0, j0, w = toy2d_weights(H, W, gh, gw)
+    c = _toy_corners(V, i0, j0)
+    a = toy2d_forward(V, H, W, mode, delta).ravel()
+    r = a - np.asarray(target, np.float64).ravel()
+    loss = float(np.mean(r * r))
+    da = 2.0 * r / r.size
+    if mode == "pre":
+        dc = da[:, None] * w * delta * np.exp(-delta * softplus(c)) * sigmoid(c)
+    elif mode == "in":
+        sbar = np.sum(w * softplus(c), axis=1)
+        dc = (da * delta * np.exp(-delta * sbar))[:, None] * w * sigmoid(c)
+    else:
+        vbar = np.sum(w * c, axis=1)
+        dc = (da * delta * np.exp(-delta * softplus(vbar)) * sigmoid(vbar))[:, None] * w
+    g = np.zeros_like(V)
+    for k, (di, dj) in enumerate(((0, 0), (0, 1), (1, 0), (1, 1))):
+        np.add.at(g, (i0 + di, j0 + dj), dc[:, k])
+    return loss, g
