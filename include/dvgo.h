@@ -47,6 +47,7 @@ typedef enum dvgo_status {
 } dvgo_status;
 
 enum { DVGO_F32 = 0, DVGO_BF16 = 1 };
+enum { DVGO_TOY_PRE = 0, DVGO_TOY_IN = 1, DVGO_TOY_POST = 2 };
 
 /* Axis-aligned box with n[i] grid vertices per axis spanning it inclusively. */
 typedef struct dvgo_box {
@@ -224,9 +225,13 @@ int32_t dvgo_sample_rays_noalloc(const float* rays_o, const float* rays_d, const
  *   min(n_kept, capacity) are ignored.
  * bg: host float[3].
  * workspace: dvgo_render_workspace_bytes(B, capacity, channels, &field.box)
- *   bytes (0 for an unsupported channel count or an invalid box). */
+ *   bytes (0 for an unsupported channel count or an invalid box), which the
+ *   backward needs; the forward alone needs only the smaller
+ *   dvgo_render_fwd_workspace_bytes. */
 size_t dvgo_render_workspace_bytes(int32_t B, int64_t capacity, int32_t channels,
                                    const dvgo_box* grid /*host*/);
+size_t dvgo_render_fwd_workspace_bytes(int32_t B, int64_t capacity, int32_t channels,
+                                       const dvgo_box* grid /*host*/);
 int32_t dvgo_render_fwd(const dvgo_field* field /*host*/, const dvgo_mlp* mlp /*host or NULL*/,
                         const float* rays_o, const float* rays_d, const float* jitter,
                         const float* t_near, const int32_t* n_uniform, const int32_t* perm,
@@ -418,6 +423,61 @@ int32_t dvgo_proposal_bwd(const float* rays_o, const float* rays_d, const float*
 size_t dvgo_proposal_workspace_bytes(int32_t B);
 
 /* ------------------------------------------------------------------------ */
+/* Test-time rendering of a whole image (paper Sec. 4.2 "Free space
+ * skipping" in testing, and the test-time rendering of Sec. 5): the same
+ * sampler and forward as training without jitter (p = 0) and without a
+ * proposal.  Pinhole camera: pixel (i, j) of an H x W image casts the ray
+ * from `origin` along normalize(c2w * ((j + 1/2 - W/2)/focal,
+ * -(i + 1/2 - H/2)/focal, -1)), c2w row-major (columns: camera right, up
+ * and back in world space), evaluated in float32.  Pixels are processed in
+ * chunks of `chunk` rays: each chunk casts its rays, runs dvgo_sample_rays
+ * (coarse_bits/coarse_box as there, or NULL) with capacity
+ * chunk*max_samples (no overflow possible) and dvgo_render_fwd.
+ * Outputs, row-major over pixels: rgb [H*W][3], depth and acc [H*W] (each
+ * NULL to skip, rgb required); rays_o, rays_d [H*W][3] (NULL to skip)
+ * receive the cast rays.  mlp required.  workspace:
+ * dvgo_render_image_workspace_bytes(chunk, max_samples, &field.box)
+ * (0 when chunk*max_samples reaches 2^31).  Errors as dvgo_render_fwd's. */
+typedef struct dvgo_camera {
+    float c2w[9];
+    float origin[3];
+    int32_t H, W;
+    float focal;
+} dvgo_camera;
+size_t dvgo_render_image_workspace_bytes(int32_t chunk, int32_t max_samples, const dvgo_box* grid /*host*/);
+int32_t dvgo_render_image(const dvgo_field* field /*host*/, const dvgo_mlp* mlp /*host*/,
+                          const dvgo_camera* cam /*host*/, float step, int32_t max_samples,
+                          const uint32_t* coarse_bits, const dvgo_box* coarse_box /*host, or NULL*/,
+                          const float* bg /*host[3]*/, int32_t chunk, float* rgb, float* depth, float* acc,
+                          float* rays_o, float* rays_d, void* workspace, size_t workspace_bytes,
+                          void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Image-fitting toy of the paper's Sec. 3 ("Sharp decision boundary via
+ * post-activation"; Eq. pre_activation, in_activation, post_activation):
+ * a grid V [gh][gw] (float32, gh, gw >= 2), its vertices spanning an H x W
+ * image inclusively, is interpolated bilinearly at the pixel centres: pixel
+ * (i, j) sits at u = (i + 1/2)*((gh-1)/H), v = (j + 1/2)*((gw-1)/W) (the
+ * ratios rounded once to float32), cell i0 = clamp(floor(u), 0, gh-2) (and
+ * j0), fractions clamped to [0, 1].  With softplus(x) = log(1 + e^x) (no
+ * shift) and alpha(s) = 1 - exp(-s*delta), the predicted alpha is
+ *   DVGO_TOY_PRE:  interp(alpha(softplus(V)));
+ *   DVGO_TOY_IN:   alpha(interp(softplus(V)));
+ *   DVGO_TOY_POST: alpha(softplus(interp(V))).
+ * dvgo_toy2d_forward writes image [H][W].  dvgo_toy2d_loss_grad writes
+ * loss (device float) = mean over pixels of (alpha - target)^2 and
+ * grad [gh][gw] = dloss/dV (overwritten; each vertex sums its pixels'
+ * contributions in row-major order, no atomics), with a workspace of
+ * dvgo_toy2d_workspace_bytes(H, W) bytes.  delta > 0; a bad mode or size
+ * is DVGO_E_ARG, H*W or gh*gw of 2^31 or more DVGO_E_UNSUPPORTED. */
+size_t dvgo_toy2d_workspace_bytes(int32_t H, int32_t W);
+int32_t dvgo_toy2d_forward(const float* V, int32_t gh, int32_t gw, int32_t H, int32_t W, int32_t mode,
+                           float delta, float* image, void* stream);
+int32_t dvgo_toy2d_loss_grad(const float* V, int32_t gh, int32_t gw, const float* target, int32_t H,
+                             int32_t W, int32_t mode, float delta, float* grad, float* loss,
+                             void* workspace, size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* Data generation (not part of the training step): colour of each ray
  * through an analytic scene of soft spheres, rows (cx,cy,cz,r,rho,R,G,B):
  * density sum_i rho_i*sigmoid((r_i - |x-c_i|)/edge), colour the density-
@@ -448,7 +508,8 @@ int32_t dvgo_version(void);
  *   render, 21 (unused: cell binning counts run inside 11), 22 cell scan,
  *   23 record placement when there is no network,
  *   24 vertex gather with the grids' Adam step (dvgo_render_bwd_adam),
- *   25 activity mask from moments (dvgo_grid_active_init). */
+ *   25 activity mask from moments (dvgo_grid_active_init), 26 toy pixels,
+ *   27 toy vertex gradients, 28 toy loss reduction. */
 int32_t dvgo_profile_enable(int32_t kernel_id);
 int32_t dvgo_profile_read(double* total_ms, int64_t* launches);
 

@@ -14,6 +14,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libdvgo.so")
 
 DVGO_F32, DVGO_BF16 = 0, 1
+DVGO_TOY_PRE, DVGO_TOY_IN, DVGO_TOY_POST = 0, 1, 2
 
 STATUS = {0: "DVGO_OK", -1: "DVGO_E_ARG", -2: "DVGO_E_SHAPE", -3: "DVGO_E_DTYPE",
           -4: "DVGO_E_CAPACITY", -5: "DVGO_E_HIP", -6: "DVGO_E_UNSUPPORTED"}
@@ -47,6 +48,10 @@ class GridAdam(ctypes.Structure):
 class AdamState(ctypes.Structure):
     _fields_ = [("param", c_void_p), ("m", c_void_p), ("v", c_void_p), ("lr", c_float), ("beta1", c_float),
                 ("beta2", c_float), ("eps", c_float), ("t", c_int32)]
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("c2w", c_float * 9), ("origin", c_float * 3), ("H", c_int32), ("W", c_int32), ("focal", c_float)]
 
 
 class DvgoError(RuntimeError):
@@ -88,6 +93,14 @@ SIGNATURES = {
     "dvgo_low_density_bias": (c_int32, [c_double, c_double, POINTER(c_double)]),
     "dvgo_coarse_raw_threshold": (c_int32, [c_double, c_double, c_double, POINTER(c_float)]),
     "dvgo_lr_at": (c_int32, [c_double, c_int64, c_int64, c_double, POINTER(c_double)]),
+    "dvgo_render_fwd_workspace_bytes": (c_size_t, [c_int32, c_int64, c_int32, POINTER(Box)]),
+    "dvgo_render_image_workspace_bytes": (c_size_t, [c_int32, c_int32, POINTER(Box)]),
+    "dvgo_render_image": (c_int32, [POINTER(Field), POINTER(Mlp), POINTER(Camera), c_float, c_int32, P, POINTER(Box),
+                                    POINTER(c_float), c_int32, P, P, P, P, P, P, c_size_t, P]),
+    "dvgo_toy2d_workspace_bytes": (c_size_t, [c_int32, c_int32]),
+    "dvgo_toy2d_forward": (c_int32, [P, c_int32, c_int32, c_int32, c_int32, c_int32, c_float, P, P]),
+    "dvgo_toy2d_loss_grad": (c_int32, [P, c_int32, c_int32, P, c_int32, c_int32, c_int32, c_float, P, P, P, c_size_t,
+                                       P]),
     "dvgo_status_string": (c_char_p, [c_int32]),
     "dvgo_last_error": (c_char_p, []),
     "dvgo_version": (c_int32, []),
@@ -98,7 +111,8 @@ SIGNATURES = {
 KERNEL_IDS = {name: i for i, name in enumerate([
     "ray_setup", "morton_sort", "count_kept", "scan", "fill_kept", "coarse_mask", "pack", "ray_base", "gather",
     "mlp_fwd", "compose_fwd", "compose_bwd", "mlp_bwd", "scatter", "reduce", "photo_loss", "adam", "prop_fwd",
-    "prop_bwd", "prop_reduce", "scene", "bin_count", "cell_scan", "bin_place", "grid_adam", "grid_active"])}
+    "prop_bwd", "prop_reduce", "scene", "bin_count", "cell_scan", "bin_place", "grid_adam", "grid_active",
+    "toy_pixel", "toy_vertex", "toy_reduce"])}
 
 _lib = None
 

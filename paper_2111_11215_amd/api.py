@@ -427,3 +427,62 @@ def scene_render(rays_o, rays_d, spheres_f32: torch.Tensor, box_min, box_max, st
                                                      _ptr(spheres_f32), spheres_f32.shape[0], float(edge),
                                                      float(step), _bg(bg), _ptr(rgb), _stream(dev)))
     return rgb
+
+
+def toy2d_forward(V: torch.Tensor, H: int, W: int, mode: int, delta: float = 1.0) -> torch.Tensor:
+    """``dvgo_toy2d_forward``: the predicted alpha image [H, W] of grid V."""
+    lib = load()
+    img = torch.empty((H, W), dtype=torch.float32, device=V.device)
+    check("dvgo_toy2d_forward", lib.dvgo_toy2d_forward(_ptr(V), V.shape[0], V.shape[1], H, W, int(mode),
+                                                       float(delta), _ptr(img), _stream(V.device)))
+    return img
+
+
+def toy2d_loss_grad(V: torch.Tensor, target: torch.Tensor, mode: int, delta: float = 1.0, grad=None):
+    """``dvgo_toy2d_loss_grad``: (loss [1], dloss/dV [gh, gw])."""
+    lib = load()
+    H, W = target.shape
+    grad = torch.empty_like(V) if grad is None else grad
+    loss = torch.empty(1, dtype=torch.float32, device=V.device)
+    nws = lib.dvgo_toy2d_workspace_bytes(H, W)
+    ws = workspace(nws, V.device)
+    check("dvgo_toy2d_loss_grad", lib.dvgo_toy2d_loss_grad(_ptr(V), V.shape[0], V.shape[1], _ptr(target), H, W,
+                                                           int(mode), float(delta), _ptr(grad), _ptr(loss), _ptr(ws),
+                                                           nws, _stream(V.device)))
+    return loss, grad
+
+
+def render_image(grid: Grid, mlp_flat: torch.Tensor, c2w, origin, H: int, W: int, focal: float, step: float,
+                 max_samples: int, coarse=None, bg=(1.0, 1.0, 1.0), precision: int = DVGO_F32,
+                 use_shadow: bool = False, chunk: int = 1 << 16, want_rays: bool = False) -> dict:
+    """``dvgo_render_image``: rgb [H*W, 3], depth and acc [H*W] of one
+    pinhole view (c2w: 3x3 camera-to-world rotation); with ``want_rays``
+    also the cast rays."""
+    lib = load()
+    dev = grid.density.device
+    field = grid.field(use_shadow)
+    mlp = mlp_struct(mlp_flat, precision)
+    cam = _lib.Camera()
+    for k, v in enumerate([float(x) for row in c2w for x in row]):
+        cam.c2w[k] = v
+    for k in range(3):
+        cam.origin[k] = float(origin[k])
+    cam.H, cam.W, cam.focal = int(H), int(W), float(focal)
+    n = H * W
+    out = {"rgb": torch.empty((n, 3), dtype=torch.float32, device=dev),
+           "depth": torch.empty(n, dtype=torch.float32, device=dev),
+           "acc": torch.empty(n, dtype=torch.float32, device=dev)}
+    if want_rays:
+        out["rays_o"] = torch.empty((n, 3), dtype=torch.float32, device=dev)
+        out["rays_d"] = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    cbits, cbox = None, None
+    if coarse is not None:
+        cbits = coarse[0]
+        cbox = make_box(coarse[1], coarse[2], coarse[3])
+    nws = lib.dvgo_render_image_workspace_bytes(int(chunk), int(max_samples), ctypes.byref(field.box))
+    ws = workspace(nws, dev)
+    check("dvgo_render_image", lib.dvgo_render_image(
+        ctypes.byref(field), ctypes.byref(mlp), ctypes.byref(cam), float(step), int(max_samples), _ptr(cbits),
+        ctypes.byref(cbox) if cbox is not None else None, _bg(bg), int(chunk), _ptr(out["rgb"]), _ptr(out["depth"]),
+        _ptr(out["acc"]), _ptr(out.get("rays_o")), _ptr(out.get("rays_d")), _ptr(ws), nws, _stream(dev)))
+    return out

@@ -1053,7 +1053,8 @@ struct Common {
 int32_t validate(const dvgo_field* field, const dvgo_mlp* mlp, const float* rays_o, const float* rays_d,
                  const float* t_near, const int32_t* n_uniform, const int32_t* perm, const int32_t* ray_offset,
                  const int32_t* sample_ray, const int32_t* sample_k, const int64_t* n_kept, int64_t capacity,
-                 int32_t B, float step, const float* bg, void* workspace, size_t workspace_bytes) {
+                 int32_t B, float step, const float* bg, void* workspace, size_t workspace_bytes,
+                 bool forward_only = false) {
     if (!field || !bg || B < 0 || capacity < 0 || !(step > 0.0f)) return DVGO_E_ARG;
     if (!dvgo::box_ok(&field->box, 2) || !field->density) return DVGO_E_ARG;
     // vertex and cell indices, cell starts and record positions are int32
@@ -1070,9 +1071,9 @@ int32_t validate(const dvgo_field* field, const dvgo_mlp* mlp, const float* rays
     if (B > 0 && (!rays_o || !rays_d || !t_near || !n_uniform || !perm || !ray_offset)) return DVGO_E_ARG;
     if (!n_kept) return DVGO_E_ARG;
     if (capacity > 0 && (!sample_ray || !sample_k)) return DVGO_E_ARG;
-    if (workspace_bytes < dvgo_render_workspace_bytes(B, capacity, kC, &field->box) ||
-        (!workspace && workspace_bytes))
-        return DVGO_E_CAPACITY;
+    const size_t need = forward_only ? dvgo_render_fwd_workspace_bytes(B, capacity, kC, &field->box)
+                                     : dvgo_render_workspace_bytes(B, capacity, kC, &field->box);
+    if (workspace_bytes < need || (!workspace && workspace_bytes)) return DVGO_E_CAPACITY;
     return DVGO_OK;
 }
 
@@ -1395,6 +1396,13 @@ size_t dvgo_render_workspace_bytes(int32_t B, int64_t capacity, int32_t channels
     return ws_layout(B, capacity, cell_count_of(*grid)).total;
 }
 
+// The forward uses the front of the layout only: per-ray encodings, packed
+// network, per-sample density, features and colour.
+size_t dvgo_render_fwd_workspace_bytes(int32_t B, int64_t capacity, int32_t channels, const dvgo_box* grid) {
+    if (B < 0 || capacity < 0 || channels != kC || !dvgo::box_ok(grid, 2)) return 0;
+    return ws_layout(B, capacity, cell_count_of(*grid)).partial;
+}
+
 int32_t dvgo_render_fwd(const dvgo_field* field, const dvgo_mlp* mlp, const float* rays_o, const float* rays_d,
                         const float* jitter, const float* t_near, const int32_t* n_uniform, const int32_t* perm,
                         const int32_t* ray_offset, const int32_t* sample_ray, const int32_t* sample_k,
@@ -1402,7 +1410,7 @@ int32_t dvgo_render_fwd(const dvgo_field* field, const dvgo_mlp* mlp, const floa
                         float* depth, float* acc, float* log_t_end, float* seg_w, float* sample_w, void* workspace,
                         size_t workspace_bytes, void* stream) {
     if (int32_t st = validate(field, mlp, rays_o, rays_d, t_near, n_uniform, perm, ray_offset, sample_ray, sample_k,
-                              n_kept, capacity, B, step, bg, workspace, workspace_bytes))
+                              n_kept, capacity, B, step, bg, workspace, workspace_bytes, true))
         return st;
     if (!log_t_end && B > 0) return DVGO_E_ARG;
     if (!mlp && rgb) return DVGO_E_ARG;

@@ -137,3 +137,26 @@ def proposal_render_psnr(model: train.FineModel, prop: train.ProposalModel, view
         mse = float(((out - ref) ** 2).mean().item())
         vals.append(-10.0 * math.log10(max(mse, 1e-12)))
     return sum(vals) / len(vals)
+
+
+def fit_toy2d(target: torch.Tensor, stride: float, mode: int, iters: int = 2000, lr: float = 0.1,
+              delta: float = 1.0) -> dict:
+    """The image-fitting toy of Sec. 3: a grid of (H/stride) x (W/stride)
+    vertices, zero-initialised (alpha 1/2 everywhere at delta 1), fitted to
+    the binary ``target`` [H, W] by Adam on the mean squared error.  Returns
+    the final loss, PSNR and the step time."""
+    H, W = target.shape
+    gh, gw = max(2, int(H / stride)), max(2, int(W / stride))
+    V = torch.zeros((gh, gw), dtype=torch.float32, device=target.device)
+    st = train.AdamState.of(V)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(1, iters + 1):
+        api.toy2d_loss_grad(st.p, target, mode, delta, grad=st.g)
+        api.adam_step(st.p, st.g, st.m, st.v, lr, it)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    img = api.toy2d_forward(st.p, H, W, mode, delta)
+    mse = float(((img - target) ** 2).mean().item())
+    return {"grid": (gh, gw), "mse": mse, "psnr": -10.0 * math.log10(max(mse, 1e-30)), "ms_per_step": 1e3 * sec / iters,
+            "V": st.p}

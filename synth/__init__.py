@@ -23,6 +23,7 @@ from .scenes import (  # noqa: F401
     coarse_raw_from_spheres,
     xavier_uniform_mlp,
     image_rays,
+    binary_image,
     tiny_config,
     full_config,
     full_scene,

@@ -304,3 +304,29 @@ def stress_config(seed: int = 0, n_rays: int = 32768, n: int = STRESS_N, batch_s
                    np.ones(3, np.float32), RayBatch(o, d, np.zeros((n_rays, 3), np.float32), jit))
     prob.extra.update(alpha_init=STRESS_ALPHA_INIT, voxel=2.0 / (n - 1))
     return prob
+
+
+# --------------------------------------------------------------------------
+# binary image of the image-fitting toy
+# --------------------------------------------------------------------------
+def binary_image(seed: int = 0, H: int = 256, W: int = 256, n_discs: int = 12, n_tris: int = 6) -> np.ndarray:
+    """A seeded binary image [H, W] float32 (1 inside any shape, else 0):
+    ``n_discs`` discs (centre U[0,1)^2 then radius U[0.03, 0.15), drawn disc
+    by disc) and ``n_tris`` triangles (three vertices U[0,1)^2 each), in
+    normalised image coordinates, tested at the pixel centres."""
+    rng = np.random.default_rng(seed)
+    y = (np.arange(H) + 0.5)[:, None] / H
+    x = (np.arange(W) + 0.5)[None, :] / W
+    img = np.zeros((H, W), bool)
+    for _ in range(n_discs):
+        cy, cx = rng.random(2)
+        r = rng.uniform(0.03, 0.15)
+        img |= (y - cy) ** 2 + (x - cx) ** 2 < r * r
+    for _ in range(n_tris):
+        p = rng.random((3, 2))
+        side = []
+        for k in range(3):
+            (ay, ax), (by, bx) = p[k], p[(k + 1) % 3]
+            side.append((bx - ax) * (y - ay) - (by - ay) * (x - ax) >= 0)
+        img |= (side[0] & side[1] & side[2]) | (~side[0] & ~side[1] & ~side[2])
+    return img.astype(np.float32)

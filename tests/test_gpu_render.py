@@ -113,11 +113,14 @@ def _fwd_keys(out, ref, keys, tol, sel=None, tol_max=None):
         assert_close(key, got, ref[key], tol, tol if tol_max is None else tol_max)
 
 
+@pytest.mark.parametrize("jitter", [True, False])
 @pytest.mark.parametrize("bf16", [False, True])
-def test_render_forward_parity_tiny(gpu_lib, bf16):
+def test_render_forward_parity_tiny(gpu_lib, bf16, jitter):
+    """Forward of the tiny configuration; jitter False is the test-time
+    path (p = 0, the sampler and the forward read no jitter at all)."""
     from paper_2111_11215_amd import api
     from paper_2111_11215_amd._lib import DVGO_BF16, DVGO_F32
-    P = _problem(0, bias=0.4)
+    P = _problem(0, jitter=jitter, bias=0.4)
     grid, flat, s = _gpu(P, bf16=bf16)
     out = api.render_fwd(grid, flat, s, P.bg, precision=DVGO_BF16 if bf16 else DVGO_F32, use_shadow=bf16,
                          want_seg_w=True, want_sample_w=True)
@@ -133,11 +136,12 @@ def test_render_forward_parity_tiny(gpu_lib, bf16):
         _fwd_keys(out, exact, ("rgb", "depth", "acc"), 2e-3)
 
 
+@pytest.mark.parametrize("jitter", [True, False])
 @pytest.mark.parametrize("bf16", [False, True])
-def test_render_backward_parity_tiny(gpu_lib, bf16):
+def test_render_backward_parity_tiny(gpu_lib, bf16, jitter):
     from paper_2111_11215_amd import api
     from paper_2111_11215_amd._lib import DVGO_BF16, DVGO_F32
-    P = _problem(1, bias=-0.3)
+    P = _problem(1, jitter=jitter, bias=-0.3)
     grid, flat, s = _gpu(P, bf16=bf16)
     out = api.render_fwd(grid, flat, s, P.bg, precision=DVGO_BF16 if bf16 else DVGO_F32, use_shadow=bf16)
     samp, prm, ref, ro = _oracle(P, bf16=bf16)
