@@ -74,6 +74,8 @@ def parse():
     ap.add_argument("--compare-iters", type=int, default=1000,
                     help="iterations of the plain-fp32 / bf16 / bf16+proposal training comparison (0: skip);"
                          " the timed form continues from its trained state")
+    ap.add_argument("--extra-configs", type=int, default=1, help="1: also time the precision and stress shapes")
+    ap.add_argument("--toy", type=int, default=1, help="1: also run the image-fitting toy")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -139,8 +141,10 @@ def make_views(ctx):
         o, d = synth.scenes.image_rays(c, 800, 800, 1000.0)
         ot = torch.as_tensor(np.ascontiguousarray(o)).to(dev).contiguous()
         dt = torch.as_tensor(np.ascontiguousarray(d)).to(dev).contiguous()
+        c2w = tuple(tuple(float(x) for x in row) for row in synth.look_at_c2w(c))
         views.append(experiment.View(ot, dt, api.scene_render(ot, dt, ctx["spheres_t"], ctx["bmin"], ctx["bmax"],
-                                                              ctx["step"] / 4)))
+                                                              ctx["step"] / 4),
+                                     center=tuple(float(x) for x in c), c2w=c2w))
     return views
 
 
@@ -372,6 +376,79 @@ def active_vertices(model):
     return int(sum(((b >> i) & 1).sum().item() for i in range(8)))
 
 
+def measure_config(ctx, model, batches, warmup, steps, bf16, n_prof=2):
+    """Throughput of ``model`` on its own batches (no proposal): uniform
+    ray-samples/s, ms/step, evaluated samples, and the event-timed roofline
+    of the gather, the network kernels and the fused grid Adam over n_prof
+    further steps per kernel."""
+    import ctypes
+
+    from paper_2111_11215_amd import _lib, experiment
+    lib = _lib.load()
+    experiment.count_uniform(model, batches)
+    experiment.run(model, batches, warmup, record_every=0)
+    st = experiment.run(model, batches, steps, record_every=0, start=warmup)
+    timed = batches[warmup:warmup + steps]
+    kept = experiment.evaluated_per_step(model, timed, None, n=min(4, len(timed)))
+    n_active = active_vertices(model)
+    per_kernel = {}
+    for kn in ("gather", "mlp_fwd", "mlp_bwd", "grid_adam"):
+        _lib.check("dvgo_profile_enable", lib.dvgo_profile_enable(_lib.KERNEL_IDS[kn]))
+        experiment.run(model, batches, n_prof, record_every=0, start=warmup)
+        tot, cnt = ctypes.c_double(), ctypes.c_int64()
+        _lib.check("dvgo_profile_read", lib.dvgo_profile_read(ctypes.byref(tot), ctypes.byref(cnt)))
+        if cnt.value:
+            per_kernel[kn] = {"ms_total": tot.value, "launches": cnt.value, "ms_avg": tot.value / cnt.value}
+    lib.dvgo_profile_enable(-1)
+    nv = model.grid.density.numel()
+    return {"rays_per_iter": int(batches[0].o.shape[0]), "steps": steps, "warmup": warmup,
+            "ms_per_step": 1e3 * st.seconds / steps, "ray_samples_per_s": st.samples_per_s,
+            "evaluated_samples_per_step": kept, "grid_vertices_stepped": n_active, "grid_vertices": nv,
+            "kernels_roofline": {k: {f: v for f, v in roofline(per_kernel, k, n_prof, kept, nv,
+                                                                model.st_mlp.p.numel(), bf16, n_active).items()
+                                     if f in ("bound", "achieved", "peak", "unit", "frac", "launch_ms")}
+                                 for k in per_kernel}}
+
+
+def stress_model(ctx):
+    """The differentiation-stress shapes as a trained-from-random model:
+    256^3 density and bfloat16 feature grids uniform in [-1, 1] (synth's
+    stress draw), the shift from alpha_init 1e-2 at that voxel size, step
+    half a voxel, at most 800 samples per ray, no coarse mask."""
+    import torch
+
+    import synth
+    from paper_2111_11215_amd import api, train
+    from paper_2111_11215_amd._lib import DVGO_BF16
+    P = synth.stress_config(0, n_rays=8)
+    dev = torch.device("cuda:0")
+    flat = api.flat_from([P.Ws[0], P.bs[0], P.Ws[1], P.bs[1], P.Ws[2], P.bs[2]], api.MLP_SHAPES, dev)
+    cfg = train.FineConfig(step=P.step, max_samples=P.max_samples, precision=DVGO_BF16, bf16_feat=True)
+    b = api.low_density_bias(P.extra["alpha_init"], P.extra["voxel"])
+    return train.FineModel(torch.as_tensor(P.density).to(dev), torch.as_tensor(P.feat).to(dev), flat, ctx["bmin"],
+                           ctx["bmax"], b, cfg, coarse=None), P.step
+
+
+def toy2d_report(iters=2000):
+    """The image-fitting toy of Sec. 3: the seeded 256 x 256 binary image
+    fitted by Adam (lr 0.1, zero start) at grid strides 2, 4, 8 and 16 with
+    each order of activation; PSNR and time per step (forward, loss,
+    gradient, Adam)."""
+    import torch
+
+    import synth
+    from paper_2111_11215_amd import experiment
+    T = torch.as_tensor(synth.binary_image(0, 256, 256)).to("cuda:0")
+    out = {"image": "256x256 binary (12 discs, 6 triangles, seed 0)", "iters": iters, "lr": 0.1}
+    for stride in (2, 4, 8, 16):
+        row = {}
+        for name, mode in (("pre", 0), ("in", 1), ("post", 2)):
+            r = experiment.fit_toy2d(T, stride, mode, iters=iters)
+            row[name] = {"psnr_db": r["psnr"], "us_per_step": 1e3 * r["ms_per_step"], "grid": list(r["grid"])}
+        out[f"stride_{stride}"] = row
+    return out
+
+
 PROFILED = ("ray_setup", "count_kept", "scan", "fill_kept", "prop_fwd", "prop_bwd", "prop_reduce", "pack",
             "ray_base", "gather", "mlp_fwd", "compose_fwd", "photo_loss", "compose_bwd", "mlp_bwd", "reduce",
             "bin_count", "cell_scan", "bin_place", "scatter", "grid_adam", "adam")
@@ -479,6 +556,25 @@ def main():
         out["kernels_ms_per_step"] = {k: v["ms_total"] / n_prof for k, v in per_kernel.items()}
     if out_cmp is not None:
         out["proposal_comparison"] = out_cmp
+    if args.extra_configs:
+        # the precision configuration's batch (16384 rays, bfloat16 form, no
+        # proposal) on the trained model, and the stress shapes (256^3,
+        # 32768 rays, <= 800 samples, no coarse mask)
+        log("bench: precision configuration, 16384 rays")
+        b16 = make_batches(ctx, 3 + 10, 16384, seed0 + 50000)
+        extra = {"precision_16384_rays": measure_config(ctx, model, b16, 3, 10, True)}
+        del b16
+        log("bench: stress configuration, 256^3, 32768 rays")
+        smodel, sstep = stress_model(ctx)
+        sctx = dict(ctx, step=sstep)
+        b32 = make_batches(sctx, 3 + 10, 32768, seed0 + 60000)
+        extra["stress_256_32768_rays"] = measure_config(ctx, smodel, b32, 3, 10, True)
+        del smodel, b32
+        torch.cuda.empty_cache()
+        out["configs"] = extra
+    if args.toy:
+        log("bench: image-fitting toy")
+        out["toy2d"] = toy2d_report()
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(ctx, args.cpu_rays, args.rays)

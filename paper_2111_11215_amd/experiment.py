@@ -30,6 +30,11 @@ class View:
     o: torch.Tensor
     d: torch.Tensor
     target: torch.Tensor
+    center: tuple = (0.0, 0.0, 4.0)     # camera centre (looking at the origin, up +z)
+    c2w: tuple = ((1.0, 0.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, 1.0))
+    H: int = 800
+    W: int = 800
+    focal: float = 1000.0
 
 
 @dataclass
@@ -106,15 +111,24 @@ def psnr_views(model: train.FineModel, views) -> float:
     return sum(vals) / len(vals)
 
 
+def render_view(model: train.FineModel, view, chunk: int = 1 << 16) -> dict:
+    """One held-out view through dvgo_render_image (rays cast on the GPU,
+    plain sampler without jitter, forward in chunks)."""
+    c = model.cfg
+    return api.render_image(model.grid, model.mlp, view.c2w, view.center, view.H, view.W, view.focal, c.step,
+                            c.max_samples, coarse=model.coarse, bg=c.bg, precision=c.precision,
+                            use_shadow=c.bf16_feat, chunk=chunk)
+
+
 def frame_ms(model: train.FineModel, view, reps: int = 3) -> float:
-    """Wall time of rendering one held-out view with the plain sampler and
-    no jitter (the inference path: sample, gather, network, compositing),
-    in ms per frame, averaged over `reps` renders after one untimed one."""
-    train.render_rays(model, view.o, view.d)
+    """Wall time of rendering one held-out view at test time
+    (dvgo_render_image), in ms per frame, averaged over `reps` renders after
+    one untimed one."""
+    render_view(model, view)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
-        train.render_rays(model, view.o, view.d)
+        render_view(model, view)
     torch.cuda.synchronize()
     return 1e3 * (time.perf_counter() - t0) / reps
 
