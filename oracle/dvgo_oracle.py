@@ -163,6 +163,44 @@ def coarse_keep(x, cmin, cmax, cn, bits):
     return ((bits[c >> 5] >> (c & 31).astype(np.uint32)) & 1).astype(bool)
 
 
+def trilinear_f32(grid, x, box_min, box_max):
+    """Trilinear interpolation of a float32 vertex grid [nx,ny,nz] in an
+    explicit float32 recipe (every operation rounded to float32 in the order
+    written, no fused multiply-add), for discrete decisions taken on an
+    interpolated value: per axis scale = (n-1)/(max-min) rounded once,
+    u = (x - min) * scale, fl = clamp(floor(u), 0, n-2), f = clamp(u - fl,
+    0, 1), g = (1 - f, f); corner c = (c>>2 &1, c>>1 &1, c &1) has weight
+    (gx * gy) * gz; the value is w_0 V_0 + w_1 V_1 + ... + w_7 V_7, added
+    one product at a time in corner order."""
+    g = np.asarray(grid, F32)
+    x = np.asarray(x, F32)
+    n = g.shape
+    i0, gw = [], []
+    for i in range(3):
+        s = F32(F32(n[i] - 1) / F32(F32(box_max[i]) - F32(box_min[i])))
+        u = ((x[..., i] - F32(box_min[i])).astype(F32) * s).astype(F32)
+        fl = np.clip(np.floor(u), F32(0.0), F32(n[i] - 2)).astype(F32)
+        f = np.clip((u - fl).astype(F32), F32(0.0), F32(1.0)).astype(F32)
+        i0.append(fl.astype(np.int64))
+        gw.append(((F32(1.0) - f).astype(F32), f))
+    val = None
+    for c in range(8):
+        bx, by, bz = (c >> 2) & 1, (c >> 1) & 1, c & 1
+        w = ((gw[0][bx] * gw[1][by]).astype(F32) * gw[2][bz]).astype(F32)
+        term = (w * g[i0[0] + bx, i0[1] + by, i0[2] + bz]).astype(F32)
+        val = term if val is None else (val + term).astype(F32)
+    return val
+
+
+def fine_keep(x, density, box_min, box_max, raw_thr):
+    """Second free-space rule of Sec. 4.2 ("Free space skipping"): a sample
+    in unknown space is skipped when its post-activated alpha from the fine
+    density grid is below tau^(f).  Both activations increase with the raw
+    value, so the test is raw >= raw_thr (``coarse_raw_threshold`` of tau^(f),
+    the fine step and the fine shift), with raw from ``trilinear_f32``."""
+    return trilinear_f32(density, x, box_min, box_max) >= F32(raw_thr)
+
+
 def segment_of(k, n_uniform):
     """Equal-count proposal segment of sample k on a ray with N_r uniform
     samples: floor(32 k / N_r), integer arithmetic."""
@@ -192,13 +230,15 @@ def morton_keys(o, d, t_near, t_far, valid, box_min, box_max):
 
 
 def sample_rays(o, d, jitter, box_min, box_max, step, max_samples, coarse=None,
-                seg_mask=None, morton=False):
+                seg_mask=None, morton=False, fine=None):
     """The fine-stage sampler (Sec. 4.2 "Fine-stage points sampling" and
-    "Free space skipping", rule one; Eq. coarse_sample): clip, count the
-    uniform samples, keep those whose coarse cell bit (and, when given, whose
-    proposal segment bit) is set, and list them per ray in ascending k.
+    "Free space skipping"; Eq. coarse_sample): clip, count the uniform
+    samples, keep those whose coarse cell bit (and, when given, whose
+    proposal segment bit) is set and, with ``fine``, that pass the second
+    rule (``fine_keep``), and list them per ray in ascending k.
 
-    ``coarse`` is (bits, cmin, cmax, cn) or None.  The ray order of the
+    ``coarse`` is (bits, cmin, cmax, cn) or None; ``fine`` is
+    (density [nx,ny,nz] float32 on the sampling box, raw_thr) or None.  The ray order of the
     compact list is the identity, or ascending (Morton key, ray id) when
     ``morton``.  Returns a dict of numpy arrays.
     """
@@ -227,6 +267,9 @@ def sample_rays(o, d, jitter, box_min, box_max, step, max_samples, coarse=None,
         if k.size and seg_mask is not None:
             seg = segment_of(k, n_uni[r])
             keep &= ((np.uint64(seg_mask[r]) >> seg.astype(np.uint64)) & np.uint64(1)).astype(bool)
+        if k.size and fine is not None:
+            x = sample_x(o[r][None, :], d[r][None, :], sample_t(t_near[r], p[r], k, step))
+            keep &= fine_keep(x, fine[0], box_min, box_max, fine[1])
         ks_per_ray.append(k[keep])
         counts[slot] = keep.sum()
     ray_offset = np.zeros(B + 1, np.int64)
@@ -554,6 +597,32 @@ def render_backward(P: Params, o, d, jitter, samp, step, bg, fwd, grad_rgb,
         grads["Ws"], grads["bs"] = dWs, dbs
     grads["sample_draw"] = draw
     return grads
+
+
+def grid_resample(grid, n_new, box_min, box_max):
+    """Progressive scaling (Sec. 4.2): a vertex grid [nx,ny,nz(,C)] resized
+    to n_new vertices per axis by trilinear interpolation (Eq. interp): new
+    vertex j of axis i sits at min_i + j (max_i - min_i)/(n_new_i - 1), both
+    grids spanning the box."""
+    g = np.asarray(grid, np.float64)
+    axes = [np.asarray(box_min[i], np.float64) + np.arange(n_new[i]) * (float(box_max[i]) - float(box_min[i])) /
+            (n_new[i] - 1) for i in range(3)]
+    X = np.stack(np.meshgrid(*axes, indexing="ij"), axis=-1).reshape(-1, 3)
+    out = interp(g, X, box_min, box_max)
+    return out.reshape(tuple(n_new) + g.shape[3:])
+
+
+def pg_resolutions(n_final, n_checkpoints):
+    """Vertices per axis of the progressively scaled grid (Sec. 4.2
+    "Progressive scaling"): the voxel count starts at 1/2^K of the final one
+    (K checkpoints) and doubles at each checkpoint, so before checkpoint k
+    (k = 0..K) the grid has floor((n_final^3 / 2^(K-k))^(1/3)) vertices per
+    axis (a cube root within 1e-9 of an integer counts as that integer)."""
+    out = []
+    for k in range(n_checkpoints + 1):
+        x = (float(n_final) ** 3 / 2.0 ** (n_checkpoints - k)) ** (1.0 / 3.0)
+        out.append(int(math.floor(x + 1e-9)))
+    return out
 
 
 def photo_loss(rgb, target):
