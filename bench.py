@@ -148,7 +148,7 @@ def make_views(ctx):
     return views
 
 
-def new_model(ctx, bf16):
+def new_model(ctx, bf16, skip_pg=False):
     import numpy as np
     import torch
 
@@ -161,6 +161,17 @@ def new_model(ctx, bf16):
     flat = api.flat_from([Ws[0], bs[0], Ws[1], bs[1], Ws[2], bs[2]], api.MLP_SHAPES, dev)
     cfg = train.FineConfig(step=ctx["step"], max_samples=ctx["max_samples"],
                            precision=DVGO_BF16 if bf16 else DVGO_F32, bf16_feat=bf16, morton=ctx["morton"])
+    if skip_pg:
+        # the paper's second free-space rule (tau^(f) = 1e-4) and progressive
+        # scaling, its checkpoints at 1k, 2k, 3k of 20k iterations scaled to
+        # this run's length
+        it = ctx.get("compare_iters", 1000)
+        cfg.fine_tau = 1e-4
+        cfg.pg_ckpt = tuple(max(1, it * k // 20) for k in (1, 2, 3))
+        cfg.pg_final_n = n
+        n = api.pg_resolution(n, 3, 0)
+        cfg.step = 0.5 * 2.0 / (n - 1)
+        cfg.max_samples = int(math.ceil(2.0 * math.sqrt(3.0) / cfg.step)) + 1
     return train.FineModel(torch.zeros((n, n, n), device=dev), torch.zeros((n, n, n, 12), device=dev), flat,
                            ctx["bmin"], ctx["bmax"], ctx["b"], cfg, coarse=ctx["coarse"])
 
@@ -177,6 +188,8 @@ def new_proposal(ctx):
 
 FORMS = {"plain": ("plain_fp32", False, False), "bf16": ("bf16", True, False),
          "proposal": ("bf16_proposal", True, True)}
+# forms trained in the comparison only: bf16 with the fine-density skip and progressive scaling
+EXTRA_FORMS = {"skip_pg": ("bf16_fine_skip_progressive", True, False)}
 
 
 def compare_forms(ctx, iters, rays, keep):
@@ -193,9 +206,10 @@ def compare_forms(ctx, iters, rays, keep):
     views = make_views(ctx)
     res = {"iters": iters, "rays_per_iter": rays, "views": len(views)}
     kept = None
-    for form in ("plain", "bf16", "proposal"):
-        name, bf16, use_prop = FORMS[form]
-        model = new_model(ctx, bf16)
+    ctx = dict(ctx, compare_iters=iters)
+    for form in ("plain", "bf16", "proposal", "skip_pg"):
+        name, bf16, use_prop = FORMS.get(form) or EXTRA_FORMS[form]
+        model = new_model(ctx, bf16, skip_pg=form == "skip_pg")
         if form == "plain":
             experiment.count_uniform(model, batches)
         prop = new_proposal(ctx) if use_prop else None
@@ -226,6 +240,9 @@ def compare_forms(ctx, iters, rays, keep):
     res["delta_psnr_db"] = res["bf16_proposal"]["psnr_db"] - res["plain_fp32"]["psnr_db"]
     res["speedup_vs_plain_fp32"] = res["bf16_proposal"]["ray_samples_per_s"] / res["plain_fp32"]["ray_samples_per_s"]
     res["gate_pass"] = bool(res["delta_psnr_db"] >= -0.1 and res["speedup_vs_plain_fp32"] > 1.0)
+    sp, b16 = res["bf16_fine_skip_progressive"], res["bf16"]
+    res["fine_skip_progressive_vs_bf16"] = {"speedup": sp["ray_samples_per_s"] / b16["ray_samples_per_s"],
+                                            "delta_psnr_db": sp["psnr_db"] - b16["psnr_db"]}
     return res, kept
 
 

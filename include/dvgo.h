@@ -123,6 +123,12 @@ int64_t dvgo_prop_param_count(void);
 int32_t dvgo_low_density_bias(double alpha_init, double voxel, double* bias /*host*/);
 int32_t dvgo_coarse_raw_threshold(double tau, double step, double act_shift, float* threshold /*host*/);
 int32_t dvgo_lr_at(double base_lr, int64_t it, int64_t decay_steps, double decay, double* lr /*host*/);
+/* dvgo_pg_resolution: vertices per axis of a progressively scaled grid
+ *   (paper Sec. 4.2, "Progressive scaling": the voxel count starts at
+ *   1/2^K of the final one for K checkpoints and doubles at each) before
+ *   checkpoint k = 0..K: floor((n_final^3 / 2^(K-k))^(1/3)), at least 2.
+ *   n_final >= 2, 0 <= k <= K, n a host int; else DVGO_E_ARG. */
+int32_t dvgo_pg_resolution(int32_t n_final, int32_t n_checkpoints, int32_t k, int32_t* n /*host*/);
 
 /* ------------------------------------------------------------------------ */
 /* Coarse alpha mask (paper Sec. 4.2, "Known free space and unknown space"
@@ -135,6 +141,22 @@ int32_t dvgo_lr_at(double base_lr, int64_t it, int64_t decay_steps, double decay
  * bits: ceil((nx-1)(ny-1)(nz-1)/32) words, fully overwritten. */
 int32_t dvgo_coarse_mask_build(const float* raw, const dvgo_box* cbox /*host*/,
                                float raw_threshold, uint32_t* bits, void* stream);
+
+/* Second free-space rule of the paper's Sec. 4.2 ("Free space skipping"): a
+ * sample in unknown space is skipped when the post-activated alpha of the
+ * fine density grid at it is below tau^(f).  Both activations increase with
+ * the raw value, so the sampler keeps a sample iff raw >= raw_threshold
+ * (dvgo_coarse_raw_threshold(tau_f, step, b)), with raw interpolated from
+ * `density` [n0][n1][n2] (box: its extent and vertex counts) in the float32
+ * recipe: per axis u = (x-min)*((n-1)/(max-min)), fl = clamp(floor(u), 0,
+ * n-2), f = clamp(u-fl, 0, 1); corner c = (c>>2 &1, c>>1 &1, c &1) has
+ * weight ((gx*gy)*gz) with g = (1-f, f); raw = w_0 V_0 + ... + w_7 V_7
+ * added one product at a time in corner order, no contraction. */
+typedef struct dvgo_fine_filter {
+    const float* density;
+    dvgo_box box;
+    float raw_threshold;
+} dvgo_fine_filter;
 
 /* ------------------------------------------------------------------------ */
 /* Ray sampling of the fine stage (paper Eq. coarse_sample with the training
@@ -151,7 +173,8 @@ int32_t dvgo_coarse_mask_build(const float* raw, const dvgo_box* cbox /*host*/,
  *   kept samples: x_k = o + t_k*d; kept when the coarse bit of its cell
  *     (cell = clamp(floor((x-min)*((n-1)/(max-min))), 0, n-2)) is set
  *     (coarse_bits NULL: all kept) and, with seg_mask, when bit
- *     floor(32k/n_uniform) of seg_mask[r] is set.
+ *     floor(32k/n_uniform) of seg_mask[r] is set, and, with `fine`, when
+ *     the second free-space rule keeps it (see dvgo_fine_filter).
  * Ray order of the compact list: slot i holds ray perm[i]; perm is the
  *   identity, or with `morton` != 0 the rays sorted by (key, ray id) where key
  *   is the 15-bit Morton code (x most significant) of the segment midpoint
@@ -174,7 +197,8 @@ int32_t dvgo_sample_rays(const float* rays_o, const float* rays_d, const float* 
                          int32_t B, const dvgo_box* box /*host*/, float step,
                          int32_t max_samples, const uint32_t* coarse_bits,
                          const dvgo_box* coarse_box /*host, or NULL*/,
-                         const uint32_t* seg_mask, int32_t morton,
+                         const uint32_t* seg_mask, const dvgo_fine_filter* fine /*host, or NULL*/,
+                         int32_t morton,
                          float* t_near, float* t_far, uint8_t* valid, int32_t* n_uniform,
                          int32_t* perm, int32_t* ray_offset, int32_t* sample_ray,
                          int32_t* sample_k, int64_t capacity, int64_t* n_kept,
@@ -197,7 +221,8 @@ int32_t dvgo_sample_rays_noalloc(const float* rays_o, const float* rays_d, const
                                  int32_t B, const dvgo_box* box /*host*/, float step,
                                  int32_t max_samples, const uint32_t* coarse_bits,
                                  const dvgo_box* coarse_box /*host, or NULL*/,
-                                 const uint32_t* seg_mask, int32_t morton,
+                                 const uint32_t* seg_mask, const dvgo_fine_filter* fine /*host, or NULL*/,
+                                 int32_t morton,
                                  float* t_near, float* t_far, uint8_t* valid, int32_t* n_uniform,
                                  int32_t* perm, int32_t* ray_offset, int32_t* sample_ray,
                                  int32_t* sample_k, int64_t capacity, int64_t* n_kept, void* stream);
@@ -423,6 +448,17 @@ int32_t dvgo_proposal_bwd(const float* rays_o, const float* rays_d, const float*
 size_t dvgo_proposal_workspace_bytes(int32_t B);
 
 /* ------------------------------------------------------------------------ */
+/* Progressive scaling (paper Sec. 4.2, "Progressive scaling": at each
+ * checkpoint the grids are resized by trilinear interpolation).  dst
+ * [dst_box->n][channels] receives, at each of its vertices
+ * x_j = min + j*((max-min)/(n-1)) (per axis, float32, on dst_box), the
+ * trilinear interpolation of src [src_box->n][channels] (channel-last;
+ * positions outside src_box clamp to its faces).  Every dst value is
+ * written.  A bad box or channel count is DVGO_E_ARG. */
+int32_t dvgo_grid_resample(const float* src, const dvgo_box* src_box /*host*/, int32_t channels, float* dst,
+                           const dvgo_box* dst_box /*host*/, void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* Test-time rendering of a whole image (paper Sec. 4.2 "Free space
  * skipping" in testing, and the test-time rendering of Sec. 5): the same
  * sampler and forward as training without jitter (p = 0) and without a
@@ -431,7 +467,7 @@ size_t dvgo_proposal_workspace_bytes(int32_t B);
  * -(i + 1/2 - H/2)/focal, -1)), c2w row-major (columns: camera right, up
  * and back in world space), evaluated in float32.  Pixels are processed in
  * chunks of `chunk` rays: each chunk casts its rays, runs dvgo_sample_rays
- * (coarse_bits/coarse_box as there, or NULL) with capacity
+ * (coarse_bits/coarse_box and the fine filter as there, or NULL) with capacity
  * chunk*max_samples (no overflow possible) and dvgo_render_fwd.
  * Outputs, row-major over pixels: rgb [H*W][3], depth and acc [H*W] (each
  * NULL to skip, rgb required); rays_o, rays_d [H*W][3] (NULL to skip)
@@ -448,7 +484,7 @@ size_t dvgo_render_image_workspace_bytes(int32_t chunk, int32_t max_samples, con
 int32_t dvgo_render_image(const dvgo_field* field /*host*/, const dvgo_mlp* mlp /*host*/,
                           const dvgo_camera* cam /*host*/, float step, int32_t max_samples,
                           const uint32_t* coarse_bits, const dvgo_box* coarse_box /*host, or NULL*/,
-                          const float* bg /*host[3]*/, int32_t chunk, float* rgb, float* depth, float* acc,
+                          const dvgo_fine_filter* fine /*host, or NULL*/, const float* bg /*host[3]*/, int32_t chunk, float* rgb, float* depth, float* acc,
                           float* rays_o, float* rays_d, void* workspace, size_t workspace_bytes,
                           void* stream);
 
@@ -509,7 +545,7 @@ int32_t dvgo_version(void);
  *   23 record placement when there is no network,
  *   24 vertex gather with the grids' Adam step (dvgo_render_bwd_adam),
  *   25 activity mask from moments (dvgo_grid_active_init), 26 toy pixels,
- *   27 toy vertex gradients, 28 toy loss reduction. */
+ *   27 toy vertex gradients, 28 toy loss reduction, 29 grid resample. */
 int32_t dvgo_profile_enable(int32_t kernel_id);
 int32_t dvgo_profile_read(double* total_ms, int64_t* launches);
 

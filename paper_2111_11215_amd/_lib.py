@@ -24,6 +24,10 @@ class Box(ctypes.Structure):
     _fields_ = [("xyz_min", c_float * 3), ("xyz_max", c_float * 3), ("n", c_int32 * 3)]
 
 
+class FineFilter(ctypes.Structure):
+    _fields_ = [("density", c_void_p), ("box", Box), ("raw_threshold", c_float)]
+
+
 class Field(ctypes.Structure):
     _fields_ = [("density", c_void_p), ("feat", c_void_p), ("feat_dtype", c_int32), ("channels", c_int32),
                 ("box", Box), ("act_shift", c_float)]
@@ -67,10 +71,10 @@ SIGNATURES = {
     "dvgo_prop_param_count": (c_int64, []),
     "dvgo_coarse_mask_build": (c_int32, [P, POINTER(Box), c_float, P, P]),
     "dvgo_sample_workspace_bytes": (c_size_t, [c_int32]),
-    "dvgo_sample_rays": (c_int32, [P, P, P, c_int32, POINTER(Box), c_float, c_int32, P, POINTER(Box), P, c_int32,
-                                   P, P, P, P, P, P, P, P, c_int64, P, P, c_size_t, P]),
+    "dvgo_sample_rays": (c_int32, [P, P, P, c_int32, POINTER(Box), c_float, c_int32, P, POINTER(Box), P,
+                                   POINTER(FineFilter), c_int32, P, P, P, P, P, P, P, P, c_int64, P, P, c_size_t, P]),
     "dvgo_sample_rays_noalloc": (c_int32, [P, P, P, c_int32, POINTER(Box), c_float, c_int32, P, POINTER(Box), P,
-                                           c_int32, P, P, P, P, P, P, P, P, c_int64, P, P]),
+                                           POINTER(FineFilter), c_int32, P, P, P, P, P, P, P, P, c_int64, P, P]),
     "dvgo_render_workspace_bytes": (c_size_t, [c_int32, c_int64, c_int32, POINTER(Box)]),
     "dvgo_render_fwd": (c_int32, [POINTER(Field), POINTER(Mlp), P, P, P, P, P, P, P, P, P, P, c_int64, c_int32,
                                   c_float, POINTER(c_float), P, P, P, P, P, P, P, c_size_t, P]),
@@ -93,10 +97,12 @@ SIGNATURES = {
     "dvgo_low_density_bias": (c_int32, [c_double, c_double, POINTER(c_double)]),
     "dvgo_coarse_raw_threshold": (c_int32, [c_double, c_double, c_double, POINTER(c_float)]),
     "dvgo_lr_at": (c_int32, [c_double, c_int64, c_int64, c_double, POINTER(c_double)]),
+    "dvgo_pg_resolution": (c_int32, [c_int32, c_int32, c_int32, POINTER(c_int32)]),
     "dvgo_render_fwd_workspace_bytes": (c_size_t, [c_int32, c_int64, c_int32, POINTER(Box)]),
     "dvgo_render_image_workspace_bytes": (c_size_t, [c_int32, c_int32, POINTER(Box)]),
     "dvgo_render_image": (c_int32, [POINTER(Field), POINTER(Mlp), POINTER(Camera), c_float, c_int32, P, POINTER(Box),
-                                    POINTER(c_float), c_int32, P, P, P, P, P, P, c_size_t, P]),
+                                    POINTER(FineFilter), POINTER(c_float), c_int32, P, P, P, P, P, P, c_size_t, P]),
+    "dvgo_grid_resample": (c_int32, [P, POINTER(Box), c_int32, P, POINTER(Box), P]),
     "dvgo_toy2d_workspace_bytes": (c_size_t, [c_int32, c_int32]),
     "dvgo_toy2d_forward": (c_int32, [P, c_int32, c_int32, c_int32, c_int32, c_int32, c_float, P, P]),
     "dvgo_toy2d_loss_grad": (c_int32, [P, c_int32, c_int32, P, c_int32, c_int32, c_int32, c_float, P, P, P, c_size_t,
@@ -112,7 +118,7 @@ KERNEL_IDS = {name: i for i, name in enumerate([
     "ray_setup", "morton_sort", "count_kept", "scan", "fill_kept", "coarse_mask", "pack", "ray_base", "gather",
     "mlp_fwd", "compose_fwd", "compose_bwd", "mlp_bwd", "scatter", "reduce", "photo_loss", "adam", "prop_fwd",
     "prop_bwd", "prop_reduce", "scene", "bin_count", "cell_scan", "bin_place", "grid_adam", "grid_active",
-    "toy_pixel", "toy_vertex", "toy_reduce"])}
+    "toy_pixel", "toy_vertex", "toy_reduce", "grid_resample"])}
 
 _lib = None
 

@@ -76,6 +76,15 @@ def lr_at(base_lr: float, it: int, decay_steps: int = 20000, decay: float = 0.1)
     return out.value
 
 
+def pg_resolution(n_final: int, n_checkpoints: int, k: int) -> int:
+    """``dvgo_pg_resolution``: vertices per axis before checkpoint k of a
+    progressively scaled grid."""
+    out = ctypes.c_int32()
+    check("dvgo_pg_resolution", load().dvgo_pg_resolution(int(n_final), int(n_checkpoints), int(k),
+                                                          ctypes.byref(out)))
+    return out.value
+
+
 # ---------------------------------------------------------------------------
 # parameters
 # ---------------------------------------------------------------------------
@@ -190,8 +199,10 @@ def coarse_mask_build(raw: torch.Tensor, cmin, cmax, raw_threshold: float) -> to
 
 
 def sample_rays(rays_o, rays_d, jitter, box_min, box_max, step, max_samples, coarse=None, seg_mask=None,
-                morton=False, capacity=None, clip_only=False, no_alloc=False) -> Samples:
-    """``coarse`` = (bits, cmin, cmax, cn) or None; seg_mask int32 [B] or None.
+                morton=False, capacity=None, clip_only=False, no_alloc=False, fine=None) -> Samples:
+    """``coarse`` = (bits, cmin, cmax, cn) or None; seg_mask int32 [B] or None;
+    ``fine`` = (fine density [n0,n1,n2], raw threshold) on the sampling box,
+    the second free-space rule, or None.
     ``clip_only``: t_near, t_far, valid, n_uniform and perm only (no list).
     ``no_alloc``: call dvgo_sample_rays_noalloc (the library's static scratch
     instead of a workspace)."""
@@ -219,10 +230,15 @@ def sample_rays(rays_o, rays_d, jitter, box_min, box_max, step, max_samples, coa
     if coarse is not None:
         cbits = coarse[0]
         cbox = make_box(coarse[1], coarse[2], coarse[3])
+    ff = None
+    if fine is not None:
+        assert fine[0].is_cuda and fine[0].is_contiguous()
+        ff = _lib.FineFilter(fine[0].data_ptr(), make_box(box_min, box_max, tuple(fine[0].shape)), float(fine[1]))
+    fptr = ctypes.byref(ff) if ff is not None else None
     if no_alloc:
         check("dvgo_sample_rays_noalloc", lib.dvgo_sample_rays_noalloc(
             _ptr(rays_o), _ptr(rays_d), _ptr(jitter), B, ctypes.byref(box), float(step), int(max_samples),
-            _ptr(cbits), ctypes.byref(cbox) if cbox is not None else None, _ptr(seg_mask), int(bool(morton)),
+            _ptr(cbits), ctypes.byref(cbox) if cbox is not None else None, _ptr(seg_mask), fptr, int(bool(morton)),
             _ptr(t_near), _ptr(t_far), _ptr(valid), _ptr(n_uniform), _ptr(perm), _ptr(ray_offset), _ptr(sample_ray),
             _ptr(sample_k), int(capacity), _ptr(n_kept), _stream(dev)))
         return Samples(rays_o, rays_d, jitter, float(step), t_near, t_far, valid, n_uniform, perm, ray_offset,
@@ -231,7 +247,7 @@ def sample_rays(rays_o, rays_d, jitter, box_min, box_max, step, max_samples, coa
     ws = workspace(nws, dev)
     check("dvgo_sample_rays", lib.dvgo_sample_rays(
         _ptr(rays_o), _ptr(rays_d), _ptr(jitter), B, ctypes.byref(box), float(step), int(max_samples),
-        _ptr(cbits), ctypes.byref(cbox) if cbox is not None else None, _ptr(seg_mask), int(bool(morton)),
+        _ptr(cbits), ctypes.byref(cbox) if cbox is not None else None, _ptr(seg_mask), fptr, int(bool(morton)),
         _ptr(t_near), _ptr(t_far), _ptr(valid), _ptr(n_uniform), _ptr(perm), _ptr(ray_offset), _ptr(sample_ray),
         _ptr(sample_k), int(capacity), _ptr(n_kept), _ptr(ws), nws, _stream(dev)))
     return Samples(rays_o, rays_d, jitter, float(step), t_near, t_far, valid, n_uniform, perm, ray_offset,
@@ -340,9 +356,10 @@ def train_step(grid: Grid, mlp_flat: torch.Tensor, s: Samples, target: torch.Ten
                use_shadow: bool = False, want_rgb: bool = True, active=None, mlp_adam=None):
     """Forward, photometric loss, adjoint and the grids' Adam step in one
     library call; accumulates (+=) the network gradient into grad_mlp.
-    ``active`` as in render_bwd_adam.  ``mlp_adam`` = (m, v, lr): the network
-    (``mlp_flat``) also takes its Adam step in the call, with the same t,
-    betas and eps, and grad_mlp is left zero.  Returns (loss [1], rgb [B,3]
+    ``active`` as in render_bwd_adam.  ``mlp_adam`` = (m, v, lr) or
+    (m, v, lr, t_net): the network (``mlp_flat``) also takes its Adam step in
+    the call, with the same betas and eps and step count t (or t_net), and
+    grad_mlp is left zero.  Returns (loss [1], rgb [B,3]
     or None)."""
     lib = load()
     dev = s.rays_o.device
@@ -351,9 +368,10 @@ def train_step(grid: Grid, mlp_flat: torch.Tensor, s: Samples, target: torch.Ten
     opt = _grid_adam(grid, density_m, density_v, feat_m, feat_v, lr, t, betas, eps, active)
     net = None
     if mlp_adam is not None:
-        m_, v_, lr_ = mlp_adam
+        m_, v_, lr_ = mlp_adam[:3]
+        t_net = mlp_adam[3] if len(mlp_adam) > 3 else t
         net = AdamState(_ptr(mlp_flat), _ptr(m_), _ptr(v_), float(lr_), float(betas[0]), float(betas[1]), float(eps),
-                        int(t))
+                        int(t_net))
     rgb = torch.empty((s.B, 3), dtype=torch.float32, device=dev) if want_rgb else None
     loss = torch.empty(1, dtype=torch.float32, device=dev)
     nws = lib.dvgo_render_workspace_bytes(s.B, s.capacity, CHANNELS, ctypes.byref(field.box))
@@ -454,7 +472,7 @@ def toy2d_loss_grad(V: torch.Tensor, target: torch.Tensor, mode: int, delta: flo
 
 def render_image(grid: Grid, mlp_flat: torch.Tensor, c2w, origin, H: int, W: int, focal: float, step: float,
                  max_samples: int, coarse=None, bg=(1.0, 1.0, 1.0), precision: int = DVGO_F32,
-                 use_shadow: bool = False, chunk: int = 1 << 16, want_rays: bool = False) -> dict:
+                 use_shadow: bool = False, chunk: int = 1 << 16, want_rays: bool = False, fine=None) -> dict:
     """``dvgo_render_image``: rgb [H*W, 3], depth and acc [H*W] of one
     pinhole view (c2w: 3x3 camera-to-world rotation); with ``want_rays``
     also the cast rays."""
@@ -479,10 +497,29 @@ def render_image(grid: Grid, mlp_flat: torch.Tensor, c2w, origin, H: int, W: int
     if coarse is not None:
         cbits = coarse[0]
         cbox = make_box(coarse[1], coarse[2], coarse[3])
+    ff = None
+    if fine is not None:
+        ff = _lib.FineFilter(fine[0].data_ptr(), make_box(grid.box_min, grid.box_max, tuple(fine[0].shape)),
+                             float(fine[1]))
     nws = lib.dvgo_render_image_workspace_bytes(int(chunk), int(max_samples), ctypes.byref(field.box))
     ws = workspace(nws, dev)
     check("dvgo_render_image", lib.dvgo_render_image(
         ctypes.byref(field), ctypes.byref(mlp), ctypes.byref(cam), float(step), int(max_samples), _ptr(cbits),
-        ctypes.byref(cbox) if cbox is not None else None, _bg(bg), int(chunk), _ptr(out["rgb"]), _ptr(out["depth"]),
+        ctypes.byref(cbox) if cbox is not None else None, ctypes.byref(ff) if ff is not None else None, _bg(bg),
+        int(chunk), _ptr(out["rgb"]), _ptr(out["depth"]),
         _ptr(out["acc"]), _ptr(out.get("rays_o")), _ptr(out.get("rays_d")), _ptr(ws), nws, _stream(dev)))
     return out
+
+
+def grid_resample(src: torch.Tensor, n_new, box_min, box_max) -> torch.Tensor:
+    """``dvgo_grid_resample``: src [n0,n1,n2(,C)] resized to n_new vertices per
+    axis over the same box."""
+    lib = load()
+    C = 1 if src.dim() == 3 else src.shape[3]
+    out_shape = tuple(n_new) + (() if src.dim() == 3 else (C,))
+    dst = torch.empty(out_shape, dtype=torch.float32, device=src.device)
+    sb = make_box(box_min, box_max, tuple(src.shape[:3]))
+    db = make_box(box_min, box_max, tuple(n_new))
+    check("dvgo_grid_resample", lib.dvgo_grid_resample(_ptr(src), ctypes.byref(sb), int(C), _ptr(dst),
+                                                       ctypes.byref(db), _stream(src.device)))
+    return dst

@@ -33,7 +33,7 @@ enum KernelId {
     K_RAY_SETUP = 0, K_MORTON_SORT, K_COUNT_KEPT, K_SCAN, K_FILL_KEPT, K_COARSE_MASK,
     K_PACK, K_RAY_BASE, K_GATHER, K_MLP_FWD, K_COMPOSE_FWD, K_COMPOSE_BWD, K_MLP_BWD, K_SCATTER,
     K_REDUCE, K_PHOTO_LOSS, K_ADAM, K_PROP_FWD, K_PROP_BWD, K_PROP_REDUCE, K_SCENE, K_BIN_COUNT,
-    K_CELL_SCAN, K_BIN_PLACE, K_GRID_ADAM, K_GRID_ACTIVE, K_TOY_PIXEL, K_TOY_VERTEX, K_TOY_REDUCE, K_NUM_KERNELS
+    K_CELL_SCAN, K_BIN_PLACE, K_GRID_ADAM, K_GRID_ACTIVE, K_TOY_PIXEL, K_TOY_VERTEX, K_TOY_REDUCE, K_GRID_RESAMPLE, K_NUM_KERNELS
 };
 // Bracket one launch with events when timing of `id` is enabled.
 void prof_begin(int id, hipStream_t s);
@@ -115,6 +115,37 @@ __device__ __forceinline__ int recipe_cell(const dvgo::GridArgs& g, const float 
         idx[i] = static_cast<int>(fl);
     }
     return (idx[0] * (g.n[1] - 1) + idx[1]) * (g.n[2] - 1) + idx[2];
+}
+
+// Trilinear interpolation of a float32 vertex grid for a discrete decision,
+// in a fixed float32 recipe: per axis u = (x-min)*scale, fl = clamp(floor(u),
+// 0, n-2), f = clamp(u-fl, 0, 1); corner c = (c>>2 &1, c>>1 &1, c &1) has
+// weight (gx*gy)*gz; the value adds w_c*V_c one product at a time in corner
+// order.
+__device__ __forceinline__ float recipe_trilerp(const dvgo::GridArgs& g, const float* __restrict__ v,
+                                                const float x[3]) {
+#pragma clang fp contract(off)
+    int i0[3];
+    float gw[3][2];
+    for (int i = 0; i < 3; ++i) {
+        const float u = (x[i] - g.mn[i]) * g.scale[i];
+        const float fl = fminf(fmaxf(floorf(u), 0.0f), static_cast<float>(g.n[i] - 2));
+        const float f = fminf(fmaxf(u - fl, 0.0f), 1.0f);
+        i0[i] = static_cast<int>(fl);
+        gw[i][0] = 1.0f - f;
+        gw[i][1] = f;
+    }
+    const int64_t sx = static_cast<int64_t>(g.n[1]) * g.n[2], sy = g.n[2];
+    const int64_t base = i0[0] * sx + i0[1] * sy + i0[2];
+    float c[8];
+    for (int k = 0; k < 8; ++k) c[k] = v[base + ((k >> 2) & 1) * sx + ((k >> 1) & 1) * sy + (k & 1)];
+    float val = 0.0f;
+    for (int k = 0; k < 8; ++k) {
+        const float w = (gw[0][(k >> 2) & 1] * gw[1][(k >> 1) & 1]) * gw[2][k & 1];
+        const float term = w * c[k];
+        val = k == 0 ? term : val + term;
+    }
+    return val;
 }
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {

@@ -36,4 +36,16 @@ int32_t dvgo_lr_at(double base_lr, int64_t it, int64_t decay_steps, double decay
     return DVGO_OK;
 }
 
+// Vertices per axis before checkpoint k of K: the voxel count starts at
+// 1/2^K of the final one and doubles at every checkpoint, so
+// floor((n_final^3 / 2^(K-k))^(1/3)) (a cube root within 1e-9 of an integer
+// counts as that integer).
+int32_t dvgo_pg_resolution(int32_t n_final, int32_t n_checkpoints, int32_t k, int32_t* n) {
+    if (!n || n_final < 2 || n_checkpoints < 0 || k < 0 || k > n_checkpoints) return DVGO_E_ARG;
+    const double x = std::cbrt(std::pow(static_cast<double>(n_final), 3.0) / std::ldexp(1.0, n_checkpoints - k));
+    const int32_t v = static_cast<int32_t>(std::floor(x + 1e-9));
+    *n = v < 2 ? 2 : v;
+    return DVGO_OK;
+}
+
 }  // extern "C"

@@ -1,7 +1,8 @@
 // Test-time rendering of a whole image (the paper renders 800 x 800 views
 // at test time with the same sampler and forward as training, minus the
-// jitter): per chunk of pixels, one kernel casts the pinhole rays, then the
-// plain sampler (coarse mask, no jitter, no proposal) and the forward
+// jitter, and skips free space in testing too): per chunk of pixels, one
+// kernel casts the pinhole rays, then the plain sampler (coarse mask and
+// optional fine-density skip, no jitter, no proposal) and the forward
 // render run on them through the library's own entry points.
 #include "common.hpp"
 
@@ -78,7 +79,7 @@ size_t dvgo_render_image_workspace_bytes(int32_t chunk, int32_t max_samples, con
 
 int32_t dvgo_render_image(const dvgo_field* field, const dvgo_mlp* mlp, const dvgo_camera* cam, float step,
                           int32_t max_samples, const uint32_t* coarse_bits, const dvgo_box* coarse_box,
-                          const float* bg, int32_t chunk, float* rgb, float* depth, float* acc, float* rays_o,
+                          const dvgo_fine_filter* fine, const float* bg, int32_t chunk, float* rgb, float* depth, float* acc, float* rays_o,
                           float* rays_d, void* workspace, size_t workspace_bytes, void* stream) {
     if (!field || !mlp || !cam || !bg || !rgb || chunk < 1 || max_samples < 1 || !(step > 0.0f)) return DVGO_E_ARG;
     if (cam->H < 1 || cam->W < 1 || !(cam->focal > 0.0f)) return DVGO_E_ARG;
@@ -106,7 +107,7 @@ int32_t dvgo_render_image(const dvgo_field* field, const dvgo_mlp* mlp, const dv
         hipLaunchKernelGGL(cast_rays_kernel, dim3((n + 255) / 256), dim3(256), 0, s, c, p0, n, ro, rd);
         if (int32_t st = dvgo::launch_status()) return st;
         if (int32_t st = dvgo_sample_rays(ro, rd, nullptr, n, &field->box, step, max_samples, coarse_bits,
-                                          coarse_box, nullptr, 0, F(L.t_near), F(L.t_far),
+                                          coarse_box, nullptr, fine, 0, F(L.t_near), F(L.t_far),
                                           reinterpret_cast<uint8_t*>(ws + L.valid), I(L.n_uniform), I(L.perm),
                                           I(L.ray_offset), I(L.sample_ray), I(L.sample_k), cap,
                                           reinterpret_cast<int64_t*>(ws + L.n_kept), ws + L.samp,

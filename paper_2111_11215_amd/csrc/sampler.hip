@@ -1,8 +1,8 @@
 // Fine-stage ray sampler: ray-box clip, uniform sample counts, coarse
-// alpha-mask skipping, optional Morton ray order, compaction into a per-ray
-// sample list (paper Sec. 4.2 "Fine-stage points sampling" and "Free space
-// skipping" rule one, Eq. coarse_sample, training jitter of the supplementary
-// implementation details).
+// alpha-mask skipping and the fine-density alpha skip, optional Morton ray
+// order, compaction into a per-ray sample list (paper Sec. 4.2 "Fine-stage
+// points sampling" and "Free space skipping", Eq. coarse_sample, training
+// jitter of the supplementary implementation details).
 #include <mutex>
 
 #include "common.hpp"
@@ -145,6 +145,9 @@ struct KeepArgs {
     const uint32_t* coarse_bits;
     const uint32_t* seg_mask;
     GridArgs cg;
+    const float* fine_density;   // second free-space rule (nullptr: off)
+    GridArgs fg;
+    float fine_thr;
     float step;
     int B;
 };
@@ -175,11 +178,17 @@ __device__ __forceinline__ bool keep_sample(const KeepArgs& a, const RayView& v,
         const int seg = static_cast<int>((32LL * k) / v.n);
         if (!((v.seg >> seg) & 1u)) return false;
     }
-    if (a.coarse_bits) {
+    if (a.coarse_bits || a.fine_density) {
         float x[3];
         recipe_x(v.o, v.d, recipe_tk(v.tn, v.p, k, a.step), x);
-        const int c = recipe_cell(a.cg, x);
-        if (!((a.coarse_bits[c >> 5] >> (c & 31)) & 1u)) return false;
+        if (a.coarse_bits) {
+            const int c = recipe_cell(a.cg, x);
+            if (!((a.coarse_bits[c >> 5] >> (c & 31)) & 1u)) return false;
+        }
+        // unknown space: skip a point whose fine post-activated alpha is
+        // below tau^(f), i.e. whose interpolated raw density is below the
+        // equivalent threshold
+        if (a.fine_density && !(recipe_trilerp(a.fg, a.fine_density, x) >= a.fine_thr)) return false;
     }
     return true;
 }
@@ -486,7 +495,8 @@ size_t dvgo_sample_workspace_bytes(int32_t B) {
 
 static int32_t sample_rays_impl(const float* rays_o, const float* rays_d, const float* jitter, int32_t B,
                          const dvgo_box* box, float step, int32_t max_samples, const uint32_t* coarse_bits,
-                         const dvgo_box* coarse_box, const uint32_t* seg_mask, int32_t morton, float* t_near,
+                         const dvgo_box* coarse_box, const uint32_t* seg_mask, const dvgo_fine_filter* fine,
+                         int32_t morton, float* t_near,
                          float* t_far, uint8_t* valid, int32_t* n_uniform, int32_t* perm, int32_t* ray_offset,
                          int32_t* sample_ray, int32_t* sample_k, int64_t capacity, int64_t* n_kept,
                          void* workspace, size_t workspace_bytes, void* stream) {
@@ -495,6 +505,9 @@ static int32_t sample_rays_impl(const float* rays_o, const float* rays_d, const 
     for (int i = 0; i < 3; ++i)
         if (!(box->xyz_max[i] > box->xyz_min[i])) return DVGO_E_ARG;
     if (coarse_bits && !dvgo::box_ok(coarse_box, 2)) return DVGO_E_ARG;
+    if (fine && (!fine->density || !dvgo::box_ok(&fine->box, 2))) return DVGO_E_ARG;
+    if (fine && static_cast<int64_t>(fine->box.n[0]) * fine->box.n[1] * fine->box.n[2] >= (1LL << 31))
+        return DVGO_E_UNSUPPORTED;
     // clip only: no sample list asked for (capacity 0, ray_offset and n_kept NULL)
     const bool clip_only = capacity == 0 && !ray_offset && !n_kept;
     if (!clip_only && (!n_kept || !ray_offset)) return DVGO_E_ARG;
@@ -533,6 +546,9 @@ static int32_t sample_rays_impl(const float* rays_o, const float* rays_d, const 
     ka.coarse_bits = coarse_bits;
     ka.seg_mask = seg_mask;
     ka.cg = coarse_bits ? dvgo::make_grid(*coarse_box) : GridArgs{};
+    ka.fine_density = fine ? fine->density : nullptr;
+    ka.fg = fine ? dvgo::make_grid(fine->box) : GridArgs{};
+    ka.fine_thr = fine ? fine->raw_threshold : 0.0f;
     ka.step = step;
     ka.B = B;
     const unsigned wblocks = static_cast<unsigned>((B + 3) / 4);
@@ -569,12 +585,13 @@ static int32_t sample_rays_impl(const float* rays_o, const float* rays_d, const 
 
 int32_t dvgo_sample_rays(const float* rays_o, const float* rays_d, const float* jitter, int32_t B,
                          const dvgo_box* box, float step, int32_t max_samples, const uint32_t* coarse_bits,
-                         const dvgo_box* coarse_box, const uint32_t* seg_mask, int32_t morton, float* t_near,
+                         const dvgo_box* coarse_box, const uint32_t* seg_mask, const dvgo_fine_filter* fine,
+                         int32_t morton, float* t_near,
                          float* t_far, uint8_t* valid, int32_t* n_uniform, int32_t* perm, int32_t* ray_offset,
                          int32_t* sample_ray, int32_t* sample_k, int64_t capacity, int64_t* n_kept,
                          void* workspace, size_t workspace_bytes, void* stream) {
     return sample_rays_impl(rays_o, rays_d, jitter, B, box, step, max_samples, coarse_bits, coarse_box, seg_mask,
-                            morton, t_near, t_far, valid, n_uniform, perm, ray_offset, sample_ray, sample_k, capacity,
+                            fine, morton, t_near, t_far, valid, n_uniform, perm, ray_offset, sample_ray, sample_k, capacity,
                             n_kept, workspace, workspace_bytes, stream);
 }
 
@@ -584,7 +601,8 @@ int32_t dvgo_sample_rays(const float* rays_o, const float* rays_d, const float* 
 // reading them, so nothing needs clearing between calls.
 int32_t dvgo_sample_rays_noalloc(const float* rays_o, const float* rays_d, const float* jitter, int32_t B,
                                  const dvgo_box* box, float step, int32_t max_samples, const uint32_t* coarse_bits,
-                                 const dvgo_box* coarse_box, const uint32_t* seg_mask, int32_t morton,
+                                 const dvgo_box* coarse_box, const uint32_t* seg_mask,
+                                 const dvgo_fine_filter* fine, int32_t morton,
                                  float* t_near, float* t_far, uint8_t* valid, int32_t* n_uniform, int32_t* perm,
                                  int32_t* ray_offset, int32_t* sample_ray, int32_t* sample_k, int64_t capacity,
                                  int64_t* n_kept, void* stream) {
@@ -595,7 +613,7 @@ int32_t dvgo_sample_rays_noalloc(const float* rays_o, const float* rays_d, const
     void* ws = nullptr;
     if (int32_t st = scratch_address(&ws)) return st;
     return sample_rays_impl(rays_o, rays_d, jitter, B, box, step, max_samples, coarse_bits, coarse_box, seg_mask,
-                            morton, t_near, t_far, valid, n_uniform, perm, ray_offset, sample_ray, sample_k, capacity,
+                            fine, morton, t_near, t_far, valid, n_uniform, perm, ray_offset, sample_ray, sample_k, capacity,
                             n_kept, ws, kNoAllocScratchBytes, stream);
 }
 

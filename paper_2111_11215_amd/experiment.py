@@ -115,9 +115,10 @@ def render_view(model: train.FineModel, view, chunk: int = 1 << 16) -> dict:
     """One held-out view through dvgo_render_image (rays cast on the GPU,
     plain sampler without jitter, forward in chunks)."""
     c = model.cfg
+    fine = (model.grid.density, model.fine_thr) if model.fine_thr is not None else None
     return api.render_image(model.grid, model.mlp, view.c2w, view.center, view.H, view.W, view.focal, c.step,
                             c.max_samples, coarse=model.coarse, bg=c.bg, precision=c.precision,
-                            use_shadow=c.bf16_feat, chunk=chunk)
+                            use_shadow=c.bf16_feat, chunk=chunk, fine=fine)
 
 
 def frame_ms(model: train.FineModel, view, reps: int = 3) -> float:

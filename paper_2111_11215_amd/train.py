@@ -8,6 +8,7 @@ exponentially to 0.1x at 20k iterations.
 
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass, field
 from typing import Optional
 
@@ -54,6 +55,9 @@ class FineConfig:
                                      # memory, the adjoint reuses the forward's gathers and colours
     skip_idle: bool = True           # the fused grid Adam skips vertices with zero moments that no sample
                                      # touches (their step changes no bit), tracked by an activity mask
+    fine_tau: Optional[float] = None  # second free-space rule: skip samples whose fine alpha is below this
+    pg_ckpt: tuple = ()              # progressive scaling: iterations at which the grids double their voxels
+    pg_final_n: int = 0              # vertices per axis after the last checkpoint (with pg_ckpt)
 
 
 class FineModel:
@@ -62,28 +66,52 @@ class FineModel:
 
     def __init__(self, density, feat, mlp_flat, box_min, box_max, act_shift, cfg: FineConfig, coarse=None):
         self.cfg = cfg
-        self.grid = api.Grid(density, feat, tuple(box_min), tuple(box_max), float(act_shift))
         self.mlp = mlp_flat
         self.coarse = coarse
+        self.st_mlp = AdamState.of(mlp_flat)
+        self.t = 0          # iterations (the network's Adam step count and the learning-rate schedule)
+        self._set_grids(density, feat, box_min, box_max, act_shift)
+
+    def _set_grids(self, density, feat, box_min, box_max, act_shift) -> None:
+        """New grid tensors with fresh Adam state (zero moments, own step
+        count) and a clear activity mask."""
+        cfg = self.cfg
+        self.grid = api.Grid(density, feat, tuple(box_min), tuple(box_max), float(act_shift))
         self.st_density = AdamState.of(density)
         self.st_feat = AdamState.of(feat, shadow=cfg.bf16_feat)
-        self.st_mlp = AdamState.of(mlp_flat)
         self.grid.feat_shadow = self.st_feat.shadow
+        self.t_grid = 0     # the grids' Adam step count (restarts when the grids are resized)
         # one bit per vertex: its moments may be non-zero (all clear with the zero moments above)
         self.active = None
         if cfg.fused_grid_adam and cfg.skip_idle:
             self.active = torch.zeros(api.grid_active_words(density.numel()), dtype=torch.int32,
                                       device=density.device)
-        self.t = 0
+        self.fine_thr = None
+        if cfg.fine_tau is not None:
+            self.fine_thr = api.coarse_raw_threshold(cfg.fine_tau, cfg.step, act_shift)
+
+    def rescale(self, n_new: int) -> None:
+        """Progressive scaling (Sec. 4.2): resize both grids to n_new vertices
+        per axis by trilinear interpolation; the sample step follows the
+        voxel size (half a voxel), the shift b stays, and the grids' Adam
+        state restarts (the network's does not)."""
+        g = self.grid
+        dens = api.grid_resample(g.density, (n_new,) * 3, g.box_min, g.box_max)
+        feat = api.grid_resample(g.feat, (n_new,) * 3, g.box_min, g.box_max)
+        span = max(hi - lo for lo, hi in zip(g.box_min, g.box_max))
+        self.cfg.step = 0.5 * span / (n_new - 1)
+        self.cfg.max_samples = int(math.ceil(math.sqrt(3.0) * span / self.cfg.step)) + 1
+        self._set_grids(dens, feat, g.box_min, g.box_max, g.act_shift)
 
     def lr(self, base: float) -> float:
         return api.lr_at(base, self.t, self.cfg.decay_steps)
 
     def sample(self, rays_o, rays_d, jitter, seg_mask=None, capacity=None, morton=None) -> api.Samples:
         c = self.cfg
+        fine = (self.grid.density, self.fine_thr) if self.fine_thr is not None else None
         return api.sample_rays(rays_o, rays_d, jitter, self.grid.box_min, self.grid.box_max, c.step, c.max_samples,
                                coarse=self.coarse, seg_mask=seg_mask, morton=c.morton if morton is None else morton,
-                               capacity=c.capacity if capacity is None else capacity)
+                               capacity=c.capacity if capacity is None else capacity, fine=fine)
 
     def render(self, s: api.Samples, **kw) -> dict:
         c = self.cfg
@@ -97,9 +125,11 @@ class FineModel:
     def adam(self) -> None:
         c = self.cfg
         self.t += 1
+        self.t_grid += 1
         lg, lm = self.lr(c.lr_grid), self.lr(c.lr_mlp)
-        for st, lr in ((self.st_density, lg), (self.st_feat, lg), (self.st_mlp, lm)):
-            api.adam_step(st.p, st.g, st.m, st.v, lr, self.t, c.betas, c.eps, shadow=st.shadow)
+        for st, lr, t in ((self.st_density, lg, self.t_grid), (self.st_feat, lg, self.t_grid),
+                          (self.st_mlp, lm, self.t)):
+            api.adam_step(st.p, st.g, st.m, st.v, lr, t, c.betas, c.eps, shadow=st.shadow)
         if self.active is not None:   # dense steps moved moments the mask does not know of
             d, f = self.st_density, self.st_feat
             api.grid_active_init(d.m, d.v, f.m, f.v, self.active)
@@ -109,26 +139,33 @@ class FineModel:
         Adam step (same result as ``backward`` followed by ``adam``)."""
         c = self.cfg
         self.t += 1
+        self.t_grid += 1
         lg, lm = self.lr(c.lr_grid), self.lr(c.lr_mlp)
         d, f = self.st_density, self.st_feat
         api.render_bwd_adam(self.grid, self.mlp, s, out["log_t_end"], grad_rgb, d.m, d.v, f.m, f.v, self.st_mlp.g,
-                            lg, self.t, c.betas, c.eps, c.bg, precision=c.precision, use_shadow=c.bf16_feat,
+                            lg, self.t_grid, c.betas, c.eps, c.bg, precision=c.precision, use_shadow=c.bf16_feat,
                             active=self.active)
         m = self.st_mlp
         api.adam_step(m.p, m.g, m.m, m.v, lm, self.t, c.betas, c.eps)
 
     def train_step(self, rays_o, rays_d, target, jitter=None, seg_mask=None) -> dict:
         """One full iteration: sample, render, photometric loss, adjoint,
-        Adam.  Returns the loss (device tensor) and the sample list."""
+        Adam.  Returns the loss (device tensor) and the sample list.  With
+        progressive scaling the grids are resized when the iteration count
+        reaches a checkpoint."""
+        c = self.cfg
+        if c.pg_ckpt and self.t in c.pg_ckpt:
+            k = list(c.pg_ckpt).index(self.t) + 1
+            self.rescale(api.pg_resolution(c.pg_final_n, len(c.pg_ckpt), k))
         s = self.sample(rays_o, rays_d, jitter, seg_mask)
         if self.cfg.fused_grid_adam:
-            c = self.cfg
             self.t += 1
+            self.t_grid += 1
             lg, lm = self.lr(c.lr_grid), self.lr(c.lr_mlp)
             d, f, m = self.st_density, self.st_feat, self.st_mlp
-            loss, rgb = api.train_step(self.grid, self.mlp, s, target, d.m, d.v, f.m, f.v, m.g, lg, self.t, c.betas,
-                                       c.eps, c.bg, precision=c.precision, use_shadow=c.bf16_feat,
-                                       active=self.active, mlp_adam=(m.m, m.v, lm))
+            loss, rgb = api.train_step(self.grid, self.mlp, s, target, d.m, d.v, f.m, f.v, m.g, lg, self.t_grid,
+                                       c.betas, c.eps, c.bg, precision=c.precision, use_shadow=c.bf16_feat,
+                                       active=self.active, mlp_adam=(m.m, m.v, lm, self.t))
             return {"loss": loss, "samples": s, "rgb": rgb}
         out = self.render(s, want_depth_acc=False)
         loss, grad = api.photo_loss(out["rgb"], target)

@@ -59,6 +59,6 @@ def test_noalloc_sampler_refuses_beyond_its_limit(gpu_lib):
     box = _lib.make_box((-1, -1, -1), (1, 1, 1))
     fake = ctypes.c_void_p(16)
     st = lib.dvgo_sample_rays_noalloc(fake, fake, None, (1 << 18) + 1, ctypes.byref(box), 0.1, 10, None, None, None,
-                                      0, fake, fake, fake, fake, fake, fake, fake, fake, 1, fake, None)
+                                      None, 0, fake, fake, fake, fake, fake, fake, fake, fake, 1, fake, None)
     assert st == -6
     assert b"static scratch" in lib.dvgo_last_error()
