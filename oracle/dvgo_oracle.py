@@ -465,15 +465,19 @@ def _padded(ray_offset, n):
 
 
 class Params:
-    """Fine-stage scene representation: density grid, feature grid, MLP
-    (Eq. fine_queries), the softplus shift b and the AABB."""
+    """Scene representation: the fine stage's density grid, feature grid and
+    MLP (Eq. fine_queries), or the coarse stage's density grid and
+    view-invariant colour grid (Eq. coarse_queries: feat holds V^(rgb), Ws
+    and bs are None, the colour is sigmoid(interp(x, V^(rgb))), the output
+    activation of Sec. 3), with the softplus shift b and the AABB."""
 
     def __init__(self, density, feat, Ws, bs, box_min, box_max, act_shift, mlp_bf16=False):
         self.mlp_bf16 = bool(mlp_bf16)
         self.density = np.asarray(density)
         self.feat = np.asarray(feat)
-        self.Ws = [np.asarray(w) for w in Ws]
-        self.bs = [np.asarray(b) for b in bs]
+        self.grid_colour = Ws is None
+        self.Ws = None if Ws is None else [np.asarray(w) for w in Ws]
+        self.bs = None if bs is None else [np.asarray(b) for b in bs]
         self.box_min = np.asarray(box_min, F32)
         self.box_max = np.asarray(box_max, F32)
         self.act_shift = float(act_shift)
@@ -520,15 +524,19 @@ def render_forward(P: Params, o, d, jitter, samp, step, bg, with_color=True):
     seg_w = np.zeros((B, NSEG))
     np.add.at(seg_w, (slot, seg), w)
     res = {}
-    if with_color:
+    if with_color and P.grid_colour:
+        c = sigmoid(interp(P.feat, x, P.box_min, P.box_max))
+        mcache = None
+    elif with_color:
         f = interp(P.feat, x, P.box_min, P.box_max)
         pe = positional_encoding(d.astype(np.float64))[sr]
         xin = np.concatenate([f, pe], axis=1)
         c, mcache = mlp_forward(P.Ws, P.bs, xin, bf16=P.mlp_bf16, n_feat=P.feat.shape[-1])
+    if with_color:
         rgb = np.zeros((B, 3))
         np.add.at(rgb, slot, w[:, None] * c)
         rgb += T_end_slot[:, None] * np.asarray(bg, np.float64)[None, :]
-        cache.update(f=f, c=c, mcache=mcache)
+        cache.update(c=c, mcache=mcache)
         res["rgb"] = np.empty((B, 3))
         res["rgb"][perm] = rgb
     for key in ("acc", "depth"):
@@ -547,7 +555,7 @@ def render_forward(P: Params, o, d, jitter, samp, step, bg, with_color=True):
 
 
 def render_backward(P: Params, o, d, jitter, samp, step, bg, fwd, grad_rgb,
-                    grad_depth=None, grad_acc=None):
+                    grad_depth=None, grad_acc=None, grad_c=None, grad_t_end=None):
     """Hand-written adjoint of ``render_forward`` walked from each ray's end.
 
     With per-sample channel vectors v_k = (c_k, t_k, 1), background
@@ -557,7 +565,13 @@ def render_backward(P: Params, o, d, jitter, samp, step, bg, fwd, grad_rgb,
       dL/draw_k   = dL/dsigma_k * sigmoid(raw_k + b),
       dL/dc_k     = w_k dL/dC, then back through the MLP to the features,
     followed by the transpose of the trilinear interpolation into both grids.
-    Returns dict(density, feat, Ws, bs) of float64 gradients.
+    Optional direct gradients: grad_c [n, 3] on every listed sample's colour
+    (added to w_k dL/dC) and grad_t_end [B] on each ray's final
+    transmittance, which reaches every sample of the ray through
+    dT_end/dsigma_k = -delta T_end.  In the coarse stage's grid-colour form
+    the colour gradient goes through the sigmoid into the colour grid.
+    Returns dict(density, feat, Ws, bs) of float64 gradients (Ws, bs absent
+    in the grid-colour form).
     """
     cache = fwd["cache"]
     B = np.asarray(o).shape[0]
@@ -587,14 +601,22 @@ def render_backward(P: Params, o, d, jitter, samp, step, bg, fwd, grad_rgb,
     T_next = cache["T_excl"][slot, col] * (1.0 - cache["alpha"])
     gs = g[slot]
     dsigma = step * np.sum(gs * (T_next[:, None] * v - S_after[slot, col]), axis=1)
+    if grad_t_end is not None:
+        dsigma = dsigma - step * t_end[slot] * np.asarray(grad_t_end, np.float64)[perm][slot]
     draw = dsigma * sigmoid(cache["raw"] + P.act_shift)
     grads = dict(density=interp_scatter(P.density.shape, cache["x"], P.box_min, P.box_max, draw))
     if "c" in cache:
         dc = cache["w"][:, None] * gs[:, :3]
-        dx, dWs, dbs = mlp_backward(P.Ws, cache["mcache"], dc)
-        df = dx[:, :P.feat.shape[-1]]
-        grads["feat"] = interp_scatter(P.feat.shape, cache["x"], P.box_min, P.box_max, df)
-        grads["Ws"], grads["bs"] = dWs, dbs
+        if grad_c is not None:
+            dc = dc + np.asarray(grad_c, np.float64)
+        if P.grid_colour:
+            c = cache["c"]
+            grads["feat"] = interp_scatter(P.feat.shape, cache["x"], P.box_min, P.box_max, dc * c * (1.0 - c))
+        else:
+            dx, dWs, dbs = mlp_backward(P.Ws, cache["mcache"], dc)
+            df = dx[:, :P.feat.shape[-1]]
+            grads["feat"] = interp_scatter(P.feat.shape, cache["x"], P.box_min, P.box_max, df)
+            grads["Ws"], grads["bs"] = dWs, dbs
     grads["sample_draw"] = draw
     return grads
 
@@ -634,6 +656,64 @@ def photo_loss(rgb, target):
     B = rgb.shape[0]
     diff = rgb - tgt
     return float(np.sum(diff * diff) / B), 2.0 * diff / B
+
+
+def view_counts(n, box_min, box_max, centers, c2ws, H, W, focal):
+    """Prior 2 of Sec. 4.1 (view-count-based learning rate): for each vertex
+    j of an n[0] x n[1] x n[2] grid spanning the box, n_j = the number of
+    training views it is visible to.  Reading: visible means inside the
+    view's pinhole frustum: with p = R^T (x_j - centre) in camera
+    coordinates (the camera looks down -z), p_z < 0 and the projection
+    (focal p_x / (-p_z) + W/2, -focal p_y / (-p_z) + H/2) lies in
+    [0, W) x [0, H) (no occlusion test).  Returns int64 counts [n]."""
+    axes = [float(box_min[i]) + np.arange(n[i]) * (float(box_max[i]) - float(box_min[i])) / (n[i] - 1)
+            for i in range(3)]
+    X = np.stack(np.meshgrid(*axes, indexing="ij"), axis=-1).reshape(-1, 3)
+    cnt = np.zeros(X.shape[0], np.int64)
+    for c, R in zip(np.asarray(centers, np.float64), np.asarray(c2ws, np.float64)):
+        pc = (X - c) @ R            # rows: R^T (x - c)
+        z = -pc[:, 2]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            u = focal * pc[:, 0] / z + W / 2.0
+            v = -focal * pc[:, 1] / z + H / 2.0
+        vis = (z > 0) & (u >= 0) & (u < W) & (v >= 0) & (v < H)
+        cnt += vis
+    return cnt.reshape(tuple(n))
+
+
+def view_count_lr_scale(counts):
+    """Per-vertex learning-rate factor n_j / n_max (Prior 2)."""
+    c = np.asarray(counts, np.float64)
+    return c / max(float(c.max()), 1.0)
+
+
+BG_CLAMP = 1e-6
+
+
+def aux_losses(fwd, target):
+    """The two auxiliary losses of the training objectives (Sec. 4.1 and 4.2
+    "Training objective", supplementary table of the auxiliary losses),
+    unweighted, with their gradients:
+    per-point rgb: (1/|R|) sum_r sum_k w_k ||c_k - C(r)||^2, which supervises
+      each sample's colour directly: the weights w_k are held fixed, so the
+      gradient reaches the colours only, 2 w_k (c_k - C(r))/|R|;
+    background entropy: (1/|R|) sum_r H(T_end(r)) with H(p) = -p log p -
+      (1-p) log(1-p), the background probability clamped to [1e-6, 1-1e-6];
+      dH/dT_end = log((1-p)/p), zero where the clamp is active.
+    Returns dict(pt, bg, grad_c [n,3] in list order, grad_t_end [B] by ray)."""
+    cache = fwd["cache"]
+    sr = np.asarray(fwd["_sample_ray"], np.int64)
+    tgt = np.asarray(target, np.float64)
+    B = tgt.shape[0]
+    diff = cache["c"] - tgt[sr]
+    pt = float(np.sum(cache["w"] * np.sum(diff * diff, axis=1)) / B)
+    grad_c = 2.0 * cache["w"][:, None] * diff / B
+    te = np.asarray(fwd["t_end"], np.float64)
+    p = np.clip(te, BG_CLAMP, 1.0 - BG_CLAMP)
+    bg = float(np.sum(-p * np.log(p) - (1.0 - p) * np.log(1.0 - p)) / B)
+    inside = (te > BG_CLAMP) & (te < 1.0 - BG_CLAMP)
+    grad_t = np.where(inside, np.log((1.0 - p) / p), 0.0) / B
+    return dict(pt=pt, bg=bg, grad_c=grad_c, grad_t_end=grad_t)
 
 
 def adam_step(p, g, m, v, lr, beta1, beta2, eps, t):
