@@ -76,6 +76,8 @@ def parse():
                          " the timed form continues from its trained state")
     ap.add_argument("--extra-configs", type=int, default=1, help="1: also time the precision and stress shapes")
     ap.add_argument("--toy", type=int, default=1, help="1: also run the image-fitting toy")
+    ap.add_argument("--coarse-iters", type=int, default=5000,
+                    help="train the coarse stage this long first and add a fine form on its learned mask")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -148,7 +150,47 @@ def make_views(ctx):
     return views
 
 
-def new_model(ctx, bf16, skip_pg=False):
+def coarse_stage(ctx, iters, alpha_init, rays=8192, pool=64):
+    """The coarse stage of Sec. 4.1 (100^3 grids, view-count learning rate,
+    loss weights 0.1 and 0.01, lr 0.1) from ``alpha_init``, on the sphere
+    scene, for ``iters`` iterations over a pool of batches; then its
+    free-space mask (tau^(c) = 1e-3 over the fine step) against the mask
+    rasterised from the analytic scene."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2111_11215_amd import api, experiment, train
+    cams = ctx["cams"]
+    R = [synth.look_at_c2w(c) for c in cams]
+    model = train.CoarseModel(100, ctx["bmin"], ctx["bmax"], train.cams_table(R, cams, "cuda:0"), 800, 800, 1000.0,
+                              alpha_init=alpha_init)
+    batches = make_batches(ctx, pool, rays, seed0=90000)
+    experiment.count_uniform_with(model.sample, batches)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = []
+    for it in range(iters):
+        b = batches[it % pool]
+        res = model.train_step(b.o, b.d, b.target, b.j)
+        if it % 500 == 0 or it == iters - 1:
+            losses.append((it, float(res["loss"].item())))
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    n_uni = sum(batches[it % pool].n_uniform for it in range(iters))
+    mask = model.free_space_mask(1e-3, ctx["step"])
+    thr = api.coarse_raw_threshold(1e-3, ctx["step"])
+    rast = api.coarse_mask_build(torch.as_tensor(ctx["raw"]).to("cuda:0"), ctx["bmin"], ctx["bmax"], thr)
+    bits = lambda w: np.unpackbits(w.cpu().numpy().view(np.uint8), bitorder="little").astype(bool)
+    lb, rb = bits(mask), bits(rast)
+    rep = {"iters": iters, "rays_per_iter": rays, "alpha_init": alpha_init, "ms_per_step": 1e3 * sec / iters,
+           "ray_samples_per_s": n_uni / sec, "loss_first_last": [losses[0][1], losses[-1][1]],
+           "loss_curve": losses, "mask_cells_kept": {"learned": int(lb.sum()), "rasterised": int(rb.sum())},
+           "mask_recall_of_rasterised": float((lb & rb).sum() / max(rb.sum(), 1))}
+    return rep, (mask, ctx["bmin"], ctx["bmax"], (100, 100, 100))
+
+
+def new_model(ctx, bf16, skip_pg=False, coarse=None):
     import numpy as np
     import torch
 
@@ -173,7 +215,8 @@ def new_model(ctx, bf16, skip_pg=False):
         cfg.step = 0.5 * 2.0 / (n - 1)
         cfg.max_samples = int(math.ceil(2.0 * math.sqrt(3.0) / cfg.step)) + 1
     return train.FineModel(torch.zeros((n, n, n), device=dev), torch.zeros((n, n, n, 12), device=dev), flat,
-                           ctx["bmin"], ctx["bmax"], ctx["b"], cfg, coarse=ctx["coarse"])
+                           ctx["bmin"], ctx["bmax"], ctx["b"], cfg,
+                           coarse=ctx["coarse"] if coarse is None else coarse)
 
 
 def new_proposal(ctx):
@@ -189,7 +232,8 @@ def new_proposal(ctx):
 FORMS = {"plain": ("plain_fp32", False, False), "bf16": ("bf16", True, False),
          "proposal": ("bf16_proposal", True, True)}
 # forms trained in the comparison only: bf16 with the fine-density skip and progressive scaling
-EXTRA_FORMS = {"skip_pg": ("bf16_fine_skip_progressive", True, False)}
+EXTRA_FORMS = {"skip_pg": ("bf16_fine_skip_progressive", True, False),
+               "learned_coarse": ("bf16_learned_coarse_mask", True, False)}
 
 
 def compare_forms(ctx, iters, rays, keep):
@@ -207,9 +251,11 @@ def compare_forms(ctx, iters, rays, keep):
     res = {"iters": iters, "rays_per_iter": rays, "views": len(views)}
     kept = None
     ctx = dict(ctx, compare_iters=iters)
-    for form in ("plain", "bf16", "proposal", "skip_pg"):
+    forms = ("plain", "bf16", "proposal", "skip_pg") + (("learned_coarse",) if "coarse_learned" in ctx else ())
+    for form in forms:
         name, bf16, use_prop = FORMS.get(form) or EXTRA_FORMS[form]
-        model = new_model(ctx, bf16, skip_pg=form == "skip_pg")
+        model = new_model(ctx, bf16, skip_pg=form == "skip_pg",
+                          coarse=ctx["coarse_learned"] if form == "learned_coarse" else None)
         if form == "plain":
             experiment.count_uniform(model, batches)
         prop = new_proposal(ctx) if use_prop else None
@@ -243,6 +289,11 @@ def compare_forms(ctx, iters, rays, keep):
     sp, b16 = res["bf16_fine_skip_progressive"], res["bf16"]
     res["fine_skip_progressive_vs_bf16"] = {"speedup": sp["ray_samples_per_s"] / b16["ray_samples_per_s"],
                                             "delta_psnr_db": sp["psnr_db"] - b16["psnr_db"]}
+    if "bf16_learned_coarse_mask" in res:
+        lc = res["bf16_learned_coarse_mask"]
+        res["learned_vs_rasterised_coarse_mask"] = {"delta_psnr_db": lc["psnr_db"] - b16["psnr_db"],
+                                                    "evaluated_ratio": lc["evaluated_per_step_end"] /
+                                                    b16["evaluated_per_step_end"]}
     return res, kept
 
 
@@ -492,6 +543,14 @@ def main():
     ctx = setup(args)
     name, bf16, use_prop = FORMS[args.form]
     out_cmp = None
+    coarse_rep = None
+    if args.coarse_iters > 0:
+        # the paper's alpha_init 1e-6, and 1e-4, whose mask the fine form below trains on: on this scene of
+        # low-density spheres 1e-6 leaves a quarter of the occupied cells out of the mask after 5-10k
+        # iterations (recall 0.69 / 0.75), 1e-4 keeps 97 % of them
+        log(f"bench: coarse stage, {args.coarse_iters} iterations, alpha_init 1e-6 and 1e-4")
+        coarse_rep = {"alpha_init_1e-6": coarse_stage(ctx, args.coarse_iters, 1e-6)[0]}
+        coarse_rep["alpha_init_1e-4"], ctx["coarse_learned"] = coarse_stage(ctx, args.coarse_iters, 1e-4)
     if args.compare_iters > 0:
         out_cmp, (model, prop) = compare_forms(ctx, args.compare_iters, args.rays, args.form)
         seed0 = 1000 + args.compare_iters
@@ -573,6 +632,8 @@ def main():
         out["kernels_ms_per_step"] = {k: v["ms_total"] / n_prof for k, v in per_kernel.items()}
     if out_cmp is not None:
         out["proposal_comparison"] = out_cmp
+    if coarse_rep is not None:
+        out["coarse_stage"] = coarse_rep
     if args.extra_configs:
         # the precision configuration's batch (16384 rays, bfloat16 form, no
         # proposal) on the trained model, and the stress shapes (256^3,

@@ -28,6 +28,10 @@ class FineFilter(ctypes.Structure):
     _fields_ = [("density", c_void_p), ("box", Box), ("raw_threshold", c_float)]
 
 
+class CoarseField(ctypes.Structure):
+    _fields_ = [("density", c_void_p), ("rgb", c_void_p), ("box", Box), ("act_shift", c_float)]
+
+
 class Field(ctypes.Structure):
     _fields_ = [("density", c_void_p), ("feat", c_void_p), ("feat_dtype", c_int32), ("channels", c_int32),
                 ("box", Box), ("act_shift", c_float)]
@@ -103,6 +107,12 @@ SIGNATURES = {
     "dvgo_render_image": (c_int32, [POINTER(Field), POINTER(Mlp), POINTER(Camera), c_float, c_int32, P, POINTER(Box),
                                     POINTER(FineFilter), POINTER(c_float), c_int32, P, P, P, P, P, P, c_size_t, P]),
     "dvgo_grid_resample": (c_int32, [P, POINTER(Box), c_int32, P, POINTER(Box), P]),
+    "dvgo_coarse_workspace_bytes": (c_size_t, [c_int32]),
+    "dvgo_coarse_step": (c_int32, [POINTER(CoarseField), P, P, P, P, P, P, P, P, c_int64, c_int32, c_int32, c_float,
+                                   POINTER(c_float), P, c_float, c_float, P, P, P, P, P, c_size_t, P]),
+    "dvgo_view_counts_workspace_bytes": (c_size_t, []),
+    "dvgo_view_counts": (c_int32, [POINTER(Box), P, c_int32, c_int32, c_int32, c_float, P, P, P, c_size_t, P]),
+    "dvgo_adam_step_scaled": (c_int32, [P, P, P, P, P, c_int64, c_float, c_float, c_float, c_float, c_int32, P]),
     "dvgo_toy2d_workspace_bytes": (c_size_t, [c_int32, c_int32]),
     "dvgo_toy2d_forward": (c_int32, [P, c_int32, c_int32, c_int32, c_int32, c_int32, c_float, P, P]),
     "dvgo_toy2d_loss_grad": (c_int32, [P, c_int32, c_int32, P, c_int32, c_int32, c_int32, c_float, P, P, P, c_size_t,
@@ -118,7 +128,7 @@ KERNEL_IDS = {name: i for i, name in enumerate([
     "ray_setup", "morton_sort", "count_kept", "scan", "fill_kept", "coarse_mask", "pack", "ray_base", "gather",
     "mlp_fwd", "compose_fwd", "compose_bwd", "mlp_bwd", "scatter", "reduce", "photo_loss", "adam", "prop_fwd",
     "prop_bwd", "prop_reduce", "scene", "bin_count", "cell_scan", "bin_place", "grid_adam", "grid_active",
-    "toy_pixel", "toy_vertex", "toy_reduce", "grid_resample"])}
+    "toy_pixel", "toy_vertex", "toy_reduce", "grid_resample", "coarse_step", "view_count"])}
 
 _lib = None
 

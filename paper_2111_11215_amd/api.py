@@ -523,3 +523,48 @@ def grid_resample(src: torch.Tensor, n_new, box_min, box_max) -> torch.Tensor:
     check("dvgo_grid_resample", lib.dvgo_grid_resample(_ptr(src), ctypes.byref(sb), int(C), _ptr(dst),
                                                        ctypes.byref(db), _stream(src.device)))
     return dst
+
+
+def coarse_step(density: torch.Tensor, rgb_grid: torch.Tensor, box_min, box_max, act_shift: float, s: Samples,
+                target: torch.Tensor, grad_density: torch.Tensor, grad_rgb: torch.Tensor, max_samples: int,
+                w_pt: float = 0.1, w_bg: float = 0.01, bg=(1.0, 1.0, 1.0), want_rgb: bool = False):
+    """``dvgo_coarse_step``: forward, the coarse objective and its gradient
+    accumulated (+=) into grad_density and grad_rgb.  Returns (loss [1],
+    rgb [B,3] or None)."""
+    lib = load()
+    dev = density.device
+    f = _lib.CoarseField(density.data_ptr(), rgb_grid.data_ptr(), make_box(box_min, box_max, tuple(density.shape)),
+                         float(act_shift))
+    rgb = torch.empty((s.B, 3), dtype=torch.float32, device=dev) if want_rgb else None
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    nws = lib.dvgo_coarse_workspace_bytes(s.B)
+    ws = workspace(nws, dev)
+    check("dvgo_coarse_step", lib.dvgo_coarse_step(
+        ctypes.byref(f), _ptr(s.rays_o), _ptr(s.rays_d), _ptr(s.jitter), _ptr(s.t_near), _ptr(s.perm),
+        _ptr(s.ray_offset), _ptr(s.sample_k), _ptr(s.n_kept), s.capacity, s.B, int(max_samples), s.step, _bg(bg),
+        _ptr(target), float(w_pt), float(w_bg), _ptr(rgb), _ptr(grad_density), _ptr(grad_rgb), _ptr(loss), _ptr(ws),
+        nws, _stream(dev)))
+    return loss, rgb
+
+
+def view_counts(n, box_min, box_max, cams: torch.Tensor, H: int, W: int, focal: float):
+    """``dvgo_view_counts``: (counts int32 [n], lr_scale float32 [n]); cams
+    [ncam, 12] device float32 (row-major R, centre)."""
+    lib = load()
+    dev = cams.device
+    counts = torch.empty(tuple(n), dtype=torch.int32, device=dev)
+    scale = torch.empty(tuple(n), dtype=torch.float32, device=dev)
+    box = make_box(box_min, box_max, tuple(n))
+    nws = lib.dvgo_view_counts_workspace_bytes()
+    ws = torch.empty(max(nws, 256), dtype=torch.uint8, device=dev)
+    check("dvgo_view_counts", lib.dvgo_view_counts(ctypes.byref(box), _ptr(cams), cams.shape[0], int(H), int(W),
+                                                   float(focal), _ptr(counts), _ptr(scale), _ptr(ws), nws,
+                                                   _stream(dev)))
+    return counts, scale
+
+
+def adam_step_scaled(p, g, m, v, lr_scale, lr, t, betas=(0.9, 0.999), eps=1e-8) -> None:
+    lib = load()
+    check("dvgo_adam_step_scaled", lib.dvgo_adam_step_scaled(_ptr(p), _ptr(g), _ptr(m), _ptr(v), _ptr(lr_scale),
+                                                             p.numel(), float(lr), float(betas[0]), float(betas[1]),
+                                                             float(eps), int(t), _stream(p.device)))

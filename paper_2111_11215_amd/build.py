@@ -21,7 +21,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libdvgo.so")
 
-SOURCES = ["abi.hip", "hyper.hip", "sampler.hip", "render.hip", "optim.hip", "proposal.hip", "scene.hip", "toy2d.hip", "image.hip", "scale.hip"]
+SOURCES = ["abi.hip", "hyper.hip", "sampler.hip", "render.hip", "optim.hip", "proposal.hip", "scene.hip", "toy2d.hip", "image.hip", "scale.hip", "coarse.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

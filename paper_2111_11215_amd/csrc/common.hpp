@@ -33,7 +33,7 @@ enum KernelId {
     K_RAY_SETUP = 0, K_MORTON_SORT, K_COUNT_KEPT, K_SCAN, K_FILL_KEPT, K_COARSE_MASK,
     K_PACK, K_RAY_BASE, K_GATHER, K_MLP_FWD, K_COMPOSE_FWD, K_COMPOSE_BWD, K_MLP_BWD, K_SCATTER,
     K_REDUCE, K_PHOTO_LOSS, K_ADAM, K_PROP_FWD, K_PROP_BWD, K_PROP_REDUCE, K_SCENE, K_BIN_COUNT,
-    K_CELL_SCAN, K_BIN_PLACE, K_GRID_ADAM, K_GRID_ACTIVE, K_TOY_PIXEL, K_TOY_VERTEX, K_TOY_REDUCE, K_GRID_RESAMPLE, K_NUM_KERNELS
+    K_CELL_SCAN, K_BIN_PLACE, K_GRID_ADAM, K_GRID_ACTIVE, K_TOY_PIXEL, K_TOY_VERTEX, K_TOY_REDUCE, K_GRID_RESAMPLE, K_COARSE_STEP, K_VIEW_COUNT, K_NUM_KERNELS
 };
 // Bracket one launch with events when timing of `id` is enabled.
 void prof_begin(int id, hipStream_t s);

@@ -51,6 +51,13 @@ class RunStats:
         return self.uniform_samples / self.seconds if self.seconds > 0 else 0.0
 
 
+def count_uniform_with(sample, batches) -> None:
+    """Fill each batch's count of uniform in-box samples (the metric's
+    numerator) from ``sample(o, d, j)``'s n_uniform."""
+    for b in batches:
+        b.n_uniform = int(sample(b.o, b.d, b.j).n_uniform.sum().item())
+
+
 def count_uniform(model: train.FineModel, batches) -> None:
     """Fill each batch's uniform-sample count (clip and count, no list)."""
     for b in batches:

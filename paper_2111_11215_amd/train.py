@@ -243,3 +243,63 @@ def render_rays(model: FineModel, rays_o, rays_d, chunk: int = 1 << 16) -> torch
         s = model.sample(rays_o[a:b].contiguous(), rays_d[a:b].contiguous(), None, morton=False)
         out[a:b] = model.render(s, want_depth_acc=False)["rgb"]
     return out
+
+
+class CoarseModel:
+    """Coarse stage (Sec. 4.1): a density grid with the low-density
+    initialisation (Prior 1: zero grid, shift from alpha_init at the coarse
+    voxel size) and a view-invariant colour grid, trained with the
+    photometric, per-point rgb and background entropy losses; the density's
+    Adam step takes the view-count learning-rate factor (Prior 2).  The
+    trained density gives the fine stage its free-space mask."""
+
+    def __init__(self, n: int, box_min, box_max, cams: torch.Tensor, H: int, W: int, focal: float,
+                 alpha_init: float = 1e-6, lr: float = 0.1, w_pt: float = 0.1, w_bg: float = 0.01,
+                 decay_steps: int = 20000, bg=(1.0, 1.0, 1.0), view_count_lr: bool = True):
+        dev = cams.device
+        self.box_min, self.box_max = tuple(box_min), tuple(box_max)
+        self.n = n
+        span = max(hi - lo for lo, hi in zip(self.box_min, self.box_max))
+        self.voxel = span / (n - 1)
+        self.step = 0.5 * self.voxel
+        self.max_samples = int(math.ceil(math.sqrt(3.0) * span / self.step)) + 1
+        self.act_shift = api.low_density_bias(alpha_init, self.voxel)
+        self.st_density = AdamState.of(torch.zeros((n, n, n), device=dev))
+        self.st_rgb = AdamState.of(torch.zeros((n, n, n, 3), device=dev))
+        self.counts, self.lr_scale = api.view_counts((n, n, n), self.box_min, self.box_max, cams, H, W, focal)
+        if not view_count_lr:
+            self.lr_scale = torch.ones_like(self.lr_scale)
+        self.lr, self.w_pt, self.w_bg, self.decay_steps, self.bg = lr, w_pt, w_bg, decay_steps, bg
+        self.t = 0
+
+    @property
+    def density(self) -> torch.Tensor:
+        return self.st_density.p
+
+    def sample(self, rays_o, rays_d, jitter) -> api.Samples:
+        return api.sample_rays(rays_o, rays_d, jitter, self.box_min, self.box_max, self.step, self.max_samples)
+
+    def train_step(self, rays_o, rays_d, target, jitter=None) -> dict:
+        s = self.sample(rays_o, rays_d, jitter)
+        d, c = self.st_density, self.st_rgb
+        loss, _ = api.coarse_step(d.p, c.p, self.box_min, self.box_max, self.act_shift, s, target, d.g, c.g,
+                                  self.max_samples, self.w_pt, self.w_bg, self.bg)
+        self.t += 1
+        lr = api.lr_at(self.lr, self.t, self.decay_steps)
+        api.adam_step_scaled(d.p, d.g, d.m, d.v, self.lr_scale, lr, self.t)
+        api.adam_step(c.p, c.g, c.m, c.v, lr, self.t)
+        return {"loss": loss, "samples": s}
+
+    def free_space_mask(self, tau: float, fine_step: float) -> torch.Tensor:
+        """Known free space for the fine stage (Sec. 4.2): the per-cell keep
+        bits of the trained density at threshold tau, with alpha taken over
+        the fine sample spacing."""
+        thr = api.coarse_raw_threshold(tau, fine_step, self.act_shift)
+        return api.coarse_mask_build(self.density, self.box_min, self.box_max, thr)
+
+
+def cams_table(c2ws, centers, device) -> torch.Tensor:
+    """[ncam, 12] float32 for dvgo_view_counts: each camera's row-major
+    camera-to-world rotation (columns right, up, back) and its centre."""
+    rows = [[float(x) for row in R for x in row] + [float(x) for x in c] for R, c in zip(c2ws, centers)]
+    return torch.tensor(rows, dtype=torch.float32, device=device)
