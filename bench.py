@@ -190,7 +190,7 @@ def coarse_stage(ctx, iters, alpha_init, rays=8192, pool=64):
     return rep, (mask, ctx["bmin"], ctx["bmax"], (100, 100, 100))
 
 
-def new_model(ctx, bf16, skip_pg=False, coarse=None):
+def new_model(ctx, bf16, skip_pg=False, coarse=None, aux=False):
     import numpy as np
     import torch
 
@@ -203,6 +203,9 @@ def new_model(ctx, bf16, skip_pg=False, coarse=None):
     flat = api.flat_from([Ws[0], bs[0], Ws[1], bs[1], Ws[2], bs[2]], api.MLP_SHAPES, dev)
     cfg = train.FineConfig(step=ctx["step"], max_samples=ctx["max_samples"],
                            precision=DVGO_BF16 if bf16 else DVGO_F32, bf16_feat=bf16, morton=ctx["morton"])
+    if aux:
+        # the paper's fine objective: photometric + 1e-2 per-point rgb + 1e-3 background entropy
+        cfg.w_pt_rgb, cfg.w_bg_entropy = 1e-2, 1e-3
     if skip_pg:
         # the paper's second free-space rule (tau^(f) = 1e-4) and progressive
         # scaling, its checkpoints at 1k, 2k, 3k of 20k iterations scaled to
@@ -233,6 +236,7 @@ FORMS = {"plain": ("plain_fp32", False, False), "bf16": ("bf16", True, False),
          "proposal": ("bf16_proposal", True, True)}
 # forms trained in the comparison only: bf16 with the fine-density skip and progressive scaling
 EXTRA_FORMS = {"skip_pg": ("bf16_fine_skip_progressive", True, False),
+               "aux": ("bf16_auxiliary_losses", True, False),
                "learned_coarse": ("bf16_learned_coarse_mask", True, False)}
 
 
@@ -251,10 +255,10 @@ def compare_forms(ctx, iters, rays, keep):
     res = {"iters": iters, "rays_per_iter": rays, "views": len(views)}
     kept = None
     ctx = dict(ctx, compare_iters=iters)
-    forms = ("plain", "bf16", "proposal", "skip_pg") + (("learned_coarse",) if "coarse_learned" in ctx else ())
+    forms = ("plain", "bf16", "proposal", "skip_pg", "aux") + (("learned_coarse",) if "coarse_learned" in ctx else ())
     for form in forms:
         name, bf16, use_prop = FORMS.get(form) or EXTRA_FORMS[form]
-        model = new_model(ctx, bf16, skip_pg=form == "skip_pg",
+        model = new_model(ctx, bf16, skip_pg=form == "skip_pg", aux=form == "aux",
                           coarse=ctx["coarse_learned"] if form == "learned_coarse" else None)
         if form == "plain":
             experiment.count_uniform(model, batches)
@@ -289,6 +293,9 @@ def compare_forms(ctx, iters, rays, keep):
     sp, b16 = res["bf16_fine_skip_progressive"], res["bf16"]
     res["fine_skip_progressive_vs_bf16"] = {"speedup": sp["ray_samples_per_s"] / b16["ray_samples_per_s"],
                                             "delta_psnr_db": sp["psnr_db"] - b16["psnr_db"]}
+    ax = res["bf16_auxiliary_losses"]
+    res["auxiliary_losses_vs_bf16"] = {"ms_per_step_ratio": ax["ms_per_step"] / b16["ms_per_step"],
+                                       "delta_psnr_db": ax["psnr_db"] - b16["psnr_db"]}
     if "bf16_learned_coarse_mask" in res:
         lc = res["bf16_learned_coarse_mask"]
         res["learned_vs_rasterised_coarse_mask"] = {"delta_psnr_db": lc["psnr_db"] - b16["psnr_db"],

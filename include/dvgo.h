@@ -368,6 +368,20 @@ typedef struct {
     int32_t t;
 } dvgo_adam_state;
 
+/* Weights of the auxiliary losses of the fine stage's training objective
+ * (paper Sec. 4.2 "Training objective for fine representation" and the
+ * supplementary implementation details: 1e-2 and 1e-3), added to the
+ * photometric loss by dvgo_train_step:
+ *   w_pt_rgb * (1/B) sum_r sum_k w_k ||c_k - C*_r||^2 (per-point rgb; the
+ *     weights w_k are held fixed: it supervises the colours only), and
+ *   w_bg_entropy * (1/B) sum_r H(clamp(T_end, 1e-6, 1 - 1e-6)) with
+ *     H(p) = -p log p - (1-p) log(1-p) (background entropy; its gradient is
+ *     zero where the clamp is active). */
+typedef struct dvgo_aux_loss {
+    float w_pt_rgb;
+    float w_bg_entropy;
+} dvgo_aux_loss;
+
 /* One whole training step of the fine stage in one call: dvgo_render_fwd
  * (colour and log T_end only), dvgo_photo_loss against target [B][3]
  * (Eq. photo_loss), and dvgo_render_bwd_adam, with the same result.  Inside
@@ -385,7 +399,10 @@ typedef struct {
  * mlp_opt->m, mlp_opt->v, NULL, n, ...) after the accumulation (grad_mlp is
  * left zero).  The network weights that mlp points at must be
  * mlp_opt->param's (every read of them ends before the update within the
- * call).  Same arguments, workspace and errors as the separate calls. */
+ * call).  With aux (host, or NULL for none) the loss and its gradient also
+ * carry the auxiliary losses (dvgo_aux_loss); when the call has no samples
+ * at all (capacity 0) they are left out.  Same arguments, workspace and
+ * errors as the separate calls; negative aux weights are DVGO_E_ARG. */
 int32_t dvgo_train_step(const dvgo_field* field /*host*/, const dvgo_mlp* mlp /*host*/,
                         const float* rays_o, const float* rays_d, const float* jitter,
                         const float* t_near, const int32_t* n_uniform, const int32_t* perm,
@@ -395,6 +412,7 @@ int32_t dvgo_train_step(const dvgo_field* field /*host*/, const dvgo_mlp* mlp /*
                         const float* target, float* rgb, float* loss,
                         const dvgo_grid_adam* opt /*host*/, float* grad_mlp,
                         const dvgo_adam_state* mlp_opt /*host or NULL*/,
+                        const dvgo_aux_loss* aux /*host or NULL*/,
                         void* workspace, size_t workspace_bytes, void* stream);
 
 /* Photometric loss of paper Eq. photo_loss: loss = (1/B) sum_r
@@ -446,6 +464,61 @@ int32_t dvgo_proposal_bwd(const float* rays_o, const float* rays_d, const float*
                           const float* log_t_end, float* grad_prop, float* loss,
                           void* workspace, size_t workspace_bytes, void* stream);
 size_t dvgo_proposal_workspace_bytes(int32_t B);
+
+/* ------------------------------------------------------------------------ */
+/* Coarse stage (paper Sec. 4.1, "Coarse geometry searching").
+ *
+ * dvgo_coarse_field: the coarse density grid (post-activated with shift
+ * act_shift, Eq. density_activation) and the view-invariant colour grid
+ * rgb [n0][n1][n2][3] (Eq. coarse_queries; the colour is the sigmoid of the
+ * interpolated 3 channels, the output activation of the paper's Sec. 3).
+ *
+ * dvgo_coarse_step: one training step's forward and gradient over the
+ * sample list of dvgo_sample_rays (the coarse stage samples every in-box
+ * point: no coarse mask), per ray in ascending k, with the quadrature of
+ * dvgo_render_fwd (bg host float[3]) and the loss
+ *   L = (1/B) sum_r [ ||C_r - C*_r||^2 + w_pt sum_k w_k ||c_k - C*_r||^2
+ *                     + w_bg H(clamp(T_end, 1e-6, 1 - 1e-6)) ],
+ * H(p) = -p log p - (1-p) log(1-p); in the per-point term the weights w_k
+ * are held fixed (it supervises the colours only); H's gradient is zero
+ * where the clamp is active.  target [B][3]; rgb [B][3] (or NULL) receives
+ * C_r; loss (device float) L; grad_density [n] and grad_rgb [n][3] are
+ * ACCUMULATED (+=) with float atomics (the summation order varies between
+ * runs).  The adjoint walks each ray from its end with the transmittance
+ * recomputed by prefix sums.  max_samples (the sampler's) at most 4096, else
+ * DVGO_E_UNSUPPORTED.  workspace: dvgo_coarse_workspace_bytes(B). */
+typedef struct dvgo_coarse_field {
+    const float* density;
+    const float* rgb;
+    dvgo_box box;
+    float act_shift;
+} dvgo_coarse_field;
+size_t dvgo_coarse_workspace_bytes(int32_t B);
+int32_t dvgo_coarse_step(const dvgo_coarse_field* field /*host*/, const float* rays_o, const float* rays_d,
+                         const float* jitter, const float* t_near, const int32_t* perm, const int32_t* ray_offset,
+                         const int32_t* sample_k, const int64_t* n_kept, int64_t capacity, int32_t B,
+                         int32_t max_samples, float step, const float* bg /*host[3]*/, const float* target,
+                         float w_pt, float w_bg, float* rgb, float* grad_density, float* grad_rgb, float* loss,
+                         void* workspace, size_t workspace_bytes, void* stream);
+
+/* Prior 2 of Sec. 4.1 (view-count-based learning rate): counts [n] = the
+ * number of the ncam training views each vertex of `box` (positions
+ * min + j*((max-min)/(n-1)), float32) is visible to, and lr_scale [n] =
+ * counts / max(counts).  Visible: inside the pinhole frustum, no occlusion
+ * test: with p = R^T (x - centre), p_z < 0 and (focal p_x/(-p_z) + W/2,
+ * -focal p_y/(-p_z) + H/2) in [0, W) x [0, H).  cams [ncam][12] device
+ * float32: R row-major (camera-to-world, columns right, up, back) then the
+ * centre.  workspace: dvgo_view_counts_workspace_bytes(). */
+size_t dvgo_view_counts_workspace_bytes(void);
+int32_t dvgo_view_counts(const dvgo_box* box /*host*/, const float* cams, int32_t ncam, int32_t H, int32_t W,
+                         float focal, int32_t* counts, float* lr_scale, void* workspace, size_t workspace_bytes,
+                         void* stream);
+
+/* dvgo_adam_step with a per-element learning-rate factor: element i takes
+ * the step with lr * lr_scale[i] (Prior 2's n_j / n_max on the coarse
+ * density); g is zeroed.  No bfloat16 copy. */
+int32_t dvgo_adam_step_scaled(float* p, float* g, float* m, float* v, const float* lr_scale, int64_t n,
+                              float lr, float beta1, float beta2, float eps, int32_t t, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Progressive scaling (paper Sec. 4.2, "Progressive scaling": at each
@@ -545,7 +618,8 @@ int32_t dvgo_version(void);
  *   23 record placement when there is no network,
  *   24 vertex gather with the grids' Adam step (dvgo_render_bwd_adam),
  *   25 activity mask from moments (dvgo_grid_active_init), 26 toy pixels,
- *   27 toy vertex gradients, 28 toy loss reduction, 29 grid resample. */
+ *   27 toy vertex gradients, 28 toy loss reduction, 29 grid resample,
+ *   30 coarse-stage step, 31 view counts. */
 int32_t dvgo_profile_enable(int32_t kernel_id);
 int32_t dvgo_profile_read(double* total_ms, int64_t* launches);
 

@@ -28,6 +28,10 @@ class FineFilter(ctypes.Structure):
     _fields_ = [("density", c_void_p), ("box", Box), ("raw_threshold", c_float)]
 
 
+class AuxLoss(ctypes.Structure):
+    _fields_ = [("w_pt_rgb", c_float), ("w_bg_entropy", c_float)]
+
+
 class CoarseField(ctypes.Structure):
     _fields_ = [("density", c_void_p), ("rgb", c_void_p), ("box", Box), ("act_shift", c_float)]
 
@@ -87,8 +91,8 @@ SIGNATURES = {
     "dvgo_render_bwd_adam": (c_int32, [POINTER(Field), POINTER(Mlp), P, P, P, P, P, P, P, P, P, P, c_int64, c_int32,
                                        c_float, POINTER(c_float), P, P, P, P, POINTER(GridAdam), P, P, c_size_t, P]),
     "dvgo_train_step": (c_int32, [POINTER(Field), POINTER(Mlp), P, P, P, P, P, P, P, P, P, P, c_int64, c_int32,
-                                  c_float, POINTER(c_float), P, P, P, POINTER(GridAdam), P, POINTER(AdamState), P,
-                                  c_size_t, P]),
+                                  c_float, POINTER(c_float), P, P, P, POINTER(GridAdam), P, POINTER(AdamState),
+                                  POINTER(AuxLoss), P, c_size_t, P]),
     "dvgo_photo_loss": (c_int32, [P, P, c_int32, P, P, P]),
     "dvgo_adam_step": (c_int32, [P, P, P, P, P, c_int64, c_float, c_float, c_float, c_float, c_int32, P]),
     "dvgo_grid_active_init": (c_int32, [P, P, P, P, c_int64, P, P]),

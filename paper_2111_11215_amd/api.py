@@ -353,14 +353,14 @@ def render_bwd_adam(grid: Grid, mlp_flat: torch.Tensor, s: Samples, log_t_end: t
 def train_step(grid: Grid, mlp_flat: torch.Tensor, s: Samples, target: torch.Tensor, density_m: torch.Tensor,
                density_v: torch.Tensor, feat_m: torch.Tensor, feat_v: torch.Tensor, grad_mlp: torch.Tensor,
                lr: float, t: int, betas=(0.9, 0.999), eps=1e-8, bg=(1.0, 1.0, 1.0), precision: int = DVGO_F32,
-               use_shadow: bool = False, want_rgb: bool = True, active=None, mlp_adam=None):
+               use_shadow: bool = False, want_rgb: bool = True, active=None, mlp_adam=None, aux=None):
     """Forward, photometric loss, adjoint and the grids' Adam step in one
     library call; accumulates (+=) the network gradient into grad_mlp.
     ``active`` as in render_bwd_adam.  ``mlp_adam`` = (m, v, lr) or
     (m, v, lr, t_net): the network (``mlp_flat``) also takes its Adam step in
     the call, with the same betas and eps and step count t (or t_net), and
-    grad_mlp is left zero.  Returns (loss [1], rgb [B,3]
-    or None)."""
+    grad_mlp is left zero.  ``aux`` = (w_pt_rgb, w_bg_entropy): the
+    auxiliary losses' weights.  Returns (loss [1], rgb [B,3] or None)."""
     lib = load()
     dev = s.rays_o.device
     field = grid.field(use_shadow)
@@ -380,7 +380,9 @@ def train_step(grid: Grid, mlp_flat: torch.Tensor, s: Samples, target: torch.Ten
         ctypes.byref(field), ctypes.byref(mlp), _ptr(s.rays_o), _ptr(s.rays_d), _ptr(s.jitter), _ptr(s.t_near),
         _ptr(s.n_uniform), _ptr(s.perm), _ptr(s.ray_offset), _ptr(s.sample_ray), _ptr(s.sample_k), _ptr(s.n_kept),
         s.capacity, s.B, s.step, _bg(bg), _ptr(target), _ptr(rgb), _ptr(loss), ctypes.byref(opt), _ptr(grad_mlp),
-        ctypes.byref(net) if net is not None else None, _ptr(ws), nws, _stream(dev)))
+        ctypes.byref(net) if net is not None else None,
+        ctypes.byref(_lib.AuxLoss(float(aux[0]), float(aux[1]))) if aux is not None else None, _ptr(ws), nws,
+        _stream(dev)))
     return loss, rgb
 
 

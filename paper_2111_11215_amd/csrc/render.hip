@@ -305,10 +305,13 @@ struct ComposeArgs {
     float* seg_w;
     float* sample_w;
     // forward, inside dvgo_train_step: the photometric loss's gradient and
-    // each ray's squared error (summed later in a fixed order)
+    // each ray's loss (summed later in a fixed order); with w_pt or w_bg also
+    // the per-point rgb and background entropy terms (the backward reads
+    // target for the per-point term)
     const float* target;
     float* grad_rgb_out;
     float* sq_err;
+    float w_pt, w_bg;
     // backward inputs
     const float* log_t_end_in;
     const float* grad_rgb;
@@ -370,7 +373,10 @@ __global__ __launch_bounds__(256) void compose_fwd_kernel(ComposeArgs a) {
     const float step = a.sa.step;
     if (lane < 32) segs[wave][lane] = 0.0f;
     __builtin_amdgcn_wave_barrier();
-    float logT = 0.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f, dep = 0.0f, accw = 0.0f;
+    float logT = 0.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f, dep = 0.0f, accw = 0.0f, ptl = 0.0f;
+    float tg[3] = {0.0f, 0.0f, 0.0f};
+    if (a.w_pt > 0.0f)
+        for (int c = 0; c < 3; ++c) tg[c] = a.target[3 * r + c];
     for (int64_t base = s0; base < s1; base += 64) {
         const int64_t s = base + lane;
         const bool ok = s < s1;
@@ -393,6 +399,10 @@ __global__ __launch_bounds__(256) void compose_fwd_kernel(ComposeArgs a) {
         cr += w * c0; cg += w * c1; cb += w * c2;
         dep += w * tk;
         accw += w;
+        if (a.w_pt > 0.0f) {   // per-point rgb: w_k ||c_k - C*||^2
+            const float e0 = c0 - tg[0], e1 = c1 - tg[1], e2 = c2 - tg[2];
+            ptl += w * (e0 * e0 + e1 * e1 + e2 * e2);
+        }
         if (ok && a.seg_w) atomicAdd(&segs[wave][(32LL * k) / nu], w);
         if (ok && a.sample_w) a.sample_w[s] = w;
         logT -= lane_value(incl, 63);
@@ -400,6 +410,7 @@ __global__ __launch_bounds__(256) void compose_fwd_kernel(ComposeArgs a) {
     cr = wave_sum(cr); cg = wave_sum(cg); cb = wave_sum(cb);
     dep = wave_sum(dep);
     accw = wave_sum(accw);
+    if (a.w_pt > 0.0f) ptl = wave_sum(ptl);
     __builtin_amdgcn_wave_barrier();
     if (lane == 0) {
         const float T = expf(logT);
@@ -415,6 +426,11 @@ __global__ __launch_bounds__(256) void compose_fwd_kernel(ComposeArgs a) {
                     const float d = c3[c] - a.target[3 * r + c];
                     a.grad_rgb_out[3 * r + c] = 2.0f * d * invB;
                     e2 += d * d;
+                }
+                if (a.w_pt > 0.0f) e2 += a.w_pt * ptl;
+                if (a.w_bg > 0.0f) {   // background entropy of T_end, clamped to [1e-6, 1 - 1e-6]
+                    const float pb = fminf(fmaxf(T, 1e-6f), 1.0f - 1e-6f);
+                    e2 += a.w_bg * (-pb * logf(pb) - (1.0f - pb) * log1pf(-pb));
                 }
                 a.sq_err[r] = e2;
             }
@@ -469,6 +485,17 @@ __global__ __launch_bounds__(256) void compose_bwd_kernel(ComposeArgs a) {
     }
     const float Tend = expf(a.log_t_end_in[r]);
     float S[5] = {Tend * a.bg[0], Tend * a.bg[1], Tend * a.bg[2], 0.0f, 0.0f};
+    // auxiliary losses: the background entropy's gradient on T_end reaches
+    // every sample through dT_end/dsigma_k = -delta T_end; the per-point rgb
+    // loss adds 2 w_pt w_k (c_k - C*)/B to each colour's gradient
+    const float invB = 1.0f / static_cast<float>(a.B);
+    float dsig_bg = 0.0f;
+    if (a.w_bg > 0.0f && Tend > 1e-6f && Tend < 1.0f - 1e-6f)
+        dsig_bg = -Tend * a.w_bg * (log1pf(-Tend) - logf(Tend)) * invB;
+    float tg[3] = {0.0f, 0.0f, 0.0f};
+    if (a.w_pt > 0.0f)
+        for (int c = 0; c < 3; ++c) tg[c] = a.target[3 * r + c];
+    const float ptk = 2.0f * a.w_pt * invB;
     const int64_t nsteps = (s1 - s0 + 63) / 64;
     const int64_t ngroups = (nsteps + 63) / 64;
     for (int64_t grp = ngroups - 1; grp >= 0; --grp) {
@@ -501,7 +528,7 @@ __global__ __launch_bounds__(256) void compose_bwd_kernel(ComposeArgs a) {
             const float excl = dpp_wave<0x138>(incl);   // wave_shr:1, lane 0 reads 0
             const float Tafter = expf(logT0 - incl);     // T_{k+1}
             const float w = ok ? expf(logT0 - excl) * -expm1f(-sd) : 0.0f;   // T_k alpha_k, as the forward
-            float dsig = 0.0f;
+            float dsig = dsig_bg;
             float tot[5];
             for (int ch = 0; ch < 5; ++ch) {
                 const float wv = w * v[ch];
@@ -514,7 +541,13 @@ __global__ __launch_bounds__(256) void compose_bwd_kernel(ComposeArgs a) {
             if (ok) {
                 a.raw[s] = draw;
                 if (a.with_color) {
-                    reinterpret_cast<float4*>(a.col)[s] = make_float4(w * g[0], w * g[1], w * g[2], 0.0f);
+                    float4 dc = make_float4(w * g[0], w * g[1], w * g[2], 0.0f);
+                    if (a.w_pt > 0.0f) {
+                        dc.x += ptk * w * (v[0] - tg[0]);
+                        dc.y += ptk * w * (v[1] - tg[1]);
+                        dc.z += ptk * w * (v[2] - tg[2]);
+                    }
+                    reinterpret_cast<float4*>(a.col)[s] = dc;
                 }
             }
             if (a.cell_count) {   // bin the sample by fine cell (wave-uniform branch)
@@ -1269,7 +1302,8 @@ int32_t render_bwd_impl(const dvgo_field* field, const dvgo_mlp* mlp, const floa
                         const float* grad_acc, float* grad_density, float* grad_feat, const GridAdamArgs* opt,
                         float* grad_mlp, void* workspace, size_t workspace_bytes, void* stream,
                         bool forward_done = false, const float* sq_err = nullptr, float* loss = nullptr,
-                        const NetAdam* net = nullptr) {
+                        const NetAdam* net = nullptr, const float* aux_target = nullptr, float w_pt = 0.0f,
+                        float w_bg = 0.0f) {
     if (int32_t st = validate(field, mlp, rays_o, rays_d, t_near, n_uniform, perm, ray_offset, sample_ray, sample_k,
                               n_kept, capacity, B, step, bg, workspace, workspace_bytes))
         return st;
@@ -1305,6 +1339,9 @@ int32_t render_bwd_impl(const dvgo_field* field, const dvgo_mlp* mlp, const floa
     // adjoint of the compositing; bins every sample by fine cell on the way
     ComposeArgs ca = make_compose(cm, perm, ray_offset, n_uniform, n_kept, field->act_shift, bg, mlp != nullptr);
     ca.log_t_end_in = log_t_end;
+    ca.target = aux_target;
+    ca.w_pt = w_pt;
+    ca.w_bg = w_bg;
     ca.grad_rgb = grad_rgb;
     ca.grad_depth = grad_depth;
     ca.grad_acc = grad_acc;
@@ -1442,11 +1479,14 @@ int32_t dvgo_train_step(const dvgo_field* field, const dvgo_mlp* mlp, const floa
                         const int32_t* ray_offset, const int32_t* sample_ray, const int32_t* sample_k,
                         const int64_t* n_kept, int64_t capacity, int32_t B, float step, const float* bg,
                         const float* target, float* rgb, float* loss, const dvgo_grid_adam* opt, float* grad_mlp,
-                        const dvgo_adam_state* mlp_opt, void* workspace, size_t workspace_bytes, void* stream) {
+                        const dvgo_adam_state* mlp_opt, const dvgo_aux_loss* aux, void* workspace,
+                        size_t workspace_bytes, void* stream) {
     if (int32_t st = validate(field, mlp, rays_o, rays_d, t_near, n_uniform, perm, ray_offset, sample_ray, sample_k,
                               n_kept, capacity, B, step, bg, workspace, workspace_bytes))
         return st;
     if (!mlp || !opt || !grad_mlp || (B > 0 && !target)) return DVGO_E_ARG;
+    const float w_pt = aux ? aux->w_pt_rgb : 0.0f, w_bg = aux ? aux->w_bg_entropy : 0.0f;
+    if (!(w_pt >= 0.0f) || !(w_bg >= 0.0f)) return DVGO_E_ARG;
     NetAdam net{};
     if (mlp_opt) {
         if (!mlp_opt->param || !mlp_opt->m || !mlp_opt->v ||
@@ -1497,13 +1537,15 @@ int32_t dvgo_train_step(const dvgo_field* field, const dvgo_mlp* mlp, const floa
     ca.target = target;          // the loss gradient comes out of the compositing
     ca.grad_rgb_out = grad_w;
     ca.sq_err = sq_w;
+    ca.w_pt = w_pt;
+    ca.w_bg = w_bg;
     DVGO_LAUNCH(K_COMPOSE_FWD, compose_fwd_kernel, dim3((B + 3) / 4), dim3(256), 0, s, ca);
     if (int32_t st = dvgo::launch_status()) return st;
     // adjoint and Adam, reusing the forward's gathered features, colours and prep
     return render_bwd_impl(field, mlp, rays_o, rays_d, jitter, t_near, n_uniform, perm, ray_offset, sample_ray,
                            sample_k, n_kept, capacity, B, step, bg, logt_w, grad_w, nullptr, nullptr, nullptr,
                            nullptr, &o, grad_mlp, workspace, workspace_bytes, stream, true, sq_w, loss,
-                           mlp_opt ? &net : nullptr);
+                           mlp_opt ? &net : nullptr, target, w_pt, w_bg);
 }
 
 }  // extern "C"

@@ -58,6 +58,8 @@ class FineConfig:
     fine_tau: Optional[float] = None  # second free-space rule: skip samples whose fine alpha is below this
     pg_ckpt: tuple = ()              # progressive scaling: iterations at which the grids double their voxels
     pg_final_n: int = 0              # vertices per axis after the last checkpoint (with pg_ckpt)
+    w_pt_rgb: float = 0.0            # auxiliary losses of the fine objective (the paper: 1e-2 and 1e-3)
+    w_bg_entropy: float = 0.0
 
 
 class FineModel:
@@ -165,7 +167,8 @@ class FineModel:
             d, f, m = self.st_density, self.st_feat, self.st_mlp
             loss, rgb = api.train_step(self.grid, self.mlp, s, target, d.m, d.v, f.m, f.v, m.g, lg, self.t_grid,
                                        c.betas, c.eps, c.bg, precision=c.precision, use_shadow=c.bf16_feat,
-                                       active=self.active, mlp_adam=(m.m, m.v, lm, self.t))
+                                       active=self.active, mlp_adam=(m.m, m.v, lm, self.t),
+                                       aux=(c.w_pt_rgb, c.w_bg_entropy) if (c.w_pt_rgb or c.w_bg_entropy) else None)
             return {"loss": loss, "samples": s, "rgb": rgb}
         out = self.render(s, want_depth_acc=False)
         loss, grad = api.photo_loss(out["rgb"], target)

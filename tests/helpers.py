@@ -51,7 +51,7 @@ def mlp_unflat(g, channels=12, hidden=128):
     return out
 
 
-def kink_budget(prm, ref, grad_rgb, zeta_rel, feat_shape, box_min, box_max):
+def kink_budget(prm, ref, grad_rgb, zeta_rel, feat_shape, box_min, box_max, dc_extra=None):
     """Error budget from ReLU decisions that the arithmetic cannot resolve.
 
     A hidden unit whose oracle pre-activation z satisfies |z| <= zeta_rel *
@@ -74,6 +74,8 @@ def kink_budget(prm, ref, grad_rgb, zeta_rel, feat_shape, box_min, box_max):
     amb = (np.abs(mc["z1"]) <= zeta_rel * s1).any(1) | (np.abs(mc["z2"]) <= zeta_rel * s2).any(1)
     g = np.asarray(grad_rgb, np.float64)[np.asarray(ref_perm_slots(ref))]
     dc = cache["w"][:, None] * g
+    if dc_extra is not None:     # direct colour gradients (the per-point rgb loss)
+        dc = np.abs(dc) + np.abs(dc_extra)
     c = mc["c"]
     dz3 = np.abs(dc * c * (1 - c))
     dh2 = dz3 @ np.abs(W3)
@@ -248,7 +250,7 @@ def density_grad_condition(ref, grad_rgb, step, act_shift, bg):
     return step * O.sigmoid(cache["raw"] + act_shift) * terms
 
 
-def feat_grad_condition(prm, ref, grad_rgb):
+def feat_grad_condition(prm, ref, grad_rgb, dc_extra=None):
     """Per-sample, per-channel scale of the feature adjoint's terms: with
     dz3 = dc c (1 - c) and absolute values throughout,
       U = ((|dz3| |W3|) |W2|) |W1f|,
@@ -262,7 +264,10 @@ def feat_grad_condition(prm, ref, grad_rgb):
     W1, W2, W3 = [np.abs(np.asarray(w, np.float64)) for w in prm.Ws]
     g = np.asarray(grad_rgb, np.float64)[np.asarray(ref["_sample_ray"], np.int64)]
     c = mc["c"]
-    dz3 = np.abs(cache["w"][:, None] * g * c * (1 - c))
+    dc = np.abs(cache["w"][:, None] * g)
+    if dc_extra is not None:
+        dc = dc + np.abs(dc_extra)
+    dz3 = dc * c * (1 - c)
     return ((dz3 @ W3) @ W2) @ W1[:, :prm.feat.shape[-1]]
 
 

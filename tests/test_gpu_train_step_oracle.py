@@ -58,7 +58,7 @@ def _seeded_moments(rng, shape, frac):
     return m, v
 
 
-def _run_case(P, coarse_gpu, coarse_ref, bf16, active, t, lr_grid, lr_mlp, moments, seed):
+def _run_case(P, coarse_gpu, coarse_ref, bf16, active, t, lr_grid, lr_mlp, moments, seed, aux=None):
     import torch
     from paper_2111_11215_amd import api
     from paper_2111_11215_amd._lib import DVGO_BF16, DVGO_F32
@@ -92,7 +92,7 @@ def _run_case(P, coarse_gpu, coarse_ref, bf16, active, t, lr_grid, lr_mlp, momen
                         coarse=coarse_gpu)
     gm = torch.zeros_like(flat)
     loss, rgb = api.train_step(grid, flat, s, to_dev(P.rays.target), mD, vD, mF, vF, gm, lr_grid, t, BETAS, EPS,
-                               P.bg, precision=prec, use_shadow=bf16, active=act, mlp_adam=(mM, vM, lr_mlp))
+                               P.bg, precision=prec, use_shadow=bf16, active=act, mlp_adam=(mM, vM, lr_mlp), aux=aux)
     torch.cuda.synchronize()
     assert float(gm.abs().max()) == 0.0
     got = dict(rgb=np_of(rgb), loss=float(np_of(loss)[0]), pD=np_of(grid.density), pF=np_of(grid.feat),
@@ -108,14 +108,21 @@ def _run_case(P, coarse_gpu, coarse_ref, bf16, active, t, lr_grid, lr_mlp, momen
     prm = O.Params(P.density, feat, P.Ws, P.bs, P.box_min, P.box_max, P.act_shift, mlp_bf16=bf16)
     ref = O.render_forward(prm, P.rays.o, P.rays.d, P.rays.jitter, samp, P.step, P.bg)
     L, g = O.photo_loss(ref["rgb"], P.rays.target)
-    gr = O.render_backward(prm, P.rays.o, P.rays.d, P.rays.jitter, samp, P.step, P.bg, ref, g)
+    dc_extra, gt = None, None
+    if aux is not None:   # the auxiliary losses of the fine objective
+        ax = O.aux_losses(ref, P.rays.target)
+        L = L + aux[0] * ax["pt"] + aux[1] * ax["bg"]
+        dc_extra, gt = aux[0] * ax["grad_c"], aux[1] * ax["grad_t_end"]
+    gr = O.render_backward(prm, P.rays.o, P.rays.d, P.rays.jitter, samp, P.step, P.bg, ref, g, grad_c=dc_extra,
+                           grad_t_end=gt)
     tol = TOLBF if bf16 else TOL32
     tol_max = ZETA_BF16 if bf16 else TOL32
     assert_close("rgb", got["rgb"], ref["rgb"], tol, tol_max)
     print(f"  loss {got['loss']:.7e} oracle {L:.7e}", flush=True)
     assert abs(got["loss"] - L) <= tol * L
 
-    budget, wb, frac = kink_budget(prm, ref, g, ZETA_BF16 if bf16 else ZETA, P.feat.shape, P.box_min, P.box_max)
+    budget, wb, frac = kink_budget(prm, ref, g, ZETA_BF16 if bf16 else ZETA, P.feat.shape, P.box_min, P.box_max,
+                                   dc_extra=dc_extra)
     print(f"  samples with an ambiguous ReLU unit: {frac:.2e}", flush=True)
     gD, gF = gr["density"], gr["feat"]
     gM = np.concatenate([gr["Ws"][0].ravel(), gr["bs"][0], gr["Ws"][1].ravel(), gr["bs"][1], gr["Ws"][2].ravel(),
@@ -125,12 +132,15 @@ def _run_case(P, coarse_gpu, coarse_ref, bf16, active, t, lr_grid, lr_mlp, momen
     # max_samples terms (cancellation in T_{k+1} v_k - S_{k+1} included) and
     # of the vertex's sum over its samples
     cond = density_grad_condition(ref, g, P.step, P.act_shift, P.bg)
+    if gt is not None:
+        cond = cond + P.step * O.sigmoid(ref["cache"]["raw"] + P.act_shift) * \
+            (np.abs(gt) * ref["t_end"])[ref["_sample_ray"]]
     nv = samples_per_vertex(ref["cache"]["x"], P.box_min, P.box_max, P.density.shape)
     eD = tol_max * np.abs(gD).max() + (P.max_samples + nv) * 2.0 ** -24 * \
         O.interp_scatter(P.density.shape, ref["cache"]["x"], P.box_min, P.box_max, cond)
     # feature entries: kink budget, plus the running-error bound of the
     # network adjoint's contractions (K <= 3 + 128 + 128) and the vertex sums
-    U = feat_grad_condition(prm, ref, g)
+    U = feat_grad_condition(prm, ref, g, dc_extra)
     eF = tol_max * np.abs(gF).max() + budget + (259 + nv[..., None]) * 2.0 ** -24 * \
         O.interp_scatter(P.feat.shape, ref["cache"]["x"], P.box_min, P.box_max, U)
     eM = np.concatenate([np.full(a.size, tol_max * np.abs(a).max() + wb[k])
@@ -141,7 +151,7 @@ def _run_case(P, coarse_gpu, coarse_ref, bf16, active, t, lr_grid, lr_mlp, momen
     check_adam_entries("features", got["pF"], got["mF"], got["vF"], P.feat, mF0, vF0, gF, eF, lr_grid, t,
                        untouched=idle[..., None])
     check_adam_entries("network", got["pM"], got["mM"], got["vM"], flat0, mM0, vM0, gM, eM, lr_mlp, t)
-    if not moments:   # m = (1 - beta1) g: the gradients themselves, normwise and max (R23)
+    if not moments and aux is None:   # m = (1 - beta1) g: the gradients themselves, normwise and max (R23)
         b1 = float(F32(BETAS[0]))
         assert_close("grad density (from m)", got["mD"] / (1 - b1), gD, tol, tol_max)
         check_grid_grad("grad feat (from m)", got["mF"] / (1 - b1), gF, budget, tol)
@@ -187,3 +197,15 @@ def test_train_step_full_batch_against_oracle(gpu_lib, bf16):
     lr = api.lr_at(0.1, 5)
     _run_case(P, (bits, P.box_min, P.box_max, raw.shape), (bits_ref, P.box_min, P.box_max, raw.shape), bf16, True,
               5, lr, api.lr_at(1e-3, 5), True, seed=41 + bf16)
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("bf16", [False, True])
+@pytest.mark.parametrize("aux", [(1e-2, 1e-3), (0.5, 0.3)])
+def test_train_step_with_auxiliary_losses(gpu_lib, bf16, aux):
+    """The fine objective with the per-point rgb and background entropy
+    losses (the paper's weights, and large weights under which a dropped or
+    mis-signed term shows): the tiny batch at t = 5 from seeded moments with
+    the activity mask, against the oracle's losses and adjoint."""
+    P = synth.tiny_config(1, jitter=True, n_rays=4096)
+    _run_case(P, None, None, bf16, True, 5, 0.1, 1e-3, True, seed=51 + bf16, aux=aux)
