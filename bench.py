@@ -10,8 +10,8 @@ network.  One step = the whole hot path over one batch, inputs resident in
 HBM: in the default form (bfloat16 features and network plus the learned
 proposal) clip and count, proposal forward and segment masks, sampling of
 the selected segments, forward, loss, adjoint with the grids' Adam step,
-the network's Adam step, and the proposal's own update from a density-only
-pass on 1/8 of the batch.  Forms: proposal (default), bf16, plain (float32,
+the network's Adam step, and, every 4th step, the proposal's own update
+from a density-only pass on half of the batch.  Forms: proposal (default), bf16, plain (float32,
 no proposal).
 
 Before timing, the comparison trains the plain float32, the bfloat16 and the

@@ -421,6 +421,17 @@ int32_t dvgo_train_step(const dvgo_field* field /*host*/, const dvgo_mlp* mlp /*
 int32_t dvgo_photo_loss(const float* rgb, const float* target, int32_t B, float* grad_rgb,
                         float* loss, void* stream);
 
+/* Float64 reduction for central finite differences of the rendering
+ * (checking the adjoint of Eq. volume_rendering against differences of
+ * forward passes): *out = sum over i < n of sum_c weight[r][c] * rgb[r][c]
+ * with r = rays[i] (rays [n] device int32), or r = i when rays is NULL
+ * (then n <= B).  rgb and weight are [B][3] float32 on the device; out is
+ * one device double, overwritten.  Every product is exact in float64 and
+ * the sum runs in one fixed order, so equal inputs give equal bits.  Ray
+ * indices outside [0, B) are skipped.  n = 0 writes 0. */
+int32_t dvgo_fd_reduce_f64(const float* rgb, const float* weight, const int32_t* rays, int32_t n,
+                           int32_t B, double* out, void* stream);
+
 /* One Adam step (the paper's optimiser, Sec. 5.2) over n float32 values:
  *   m = beta1*m + (1-beta1)*g;  v = beta2*v + (1-beta2)*g^2;
  *   p -= lr * (m/(1-beta1^t)) / (sqrt(v/(1-beta2^t)) + eps);  g = 0;

@@ -94,6 +94,7 @@ SIGNATURES = {
                                   c_float, POINTER(c_float), P, P, P, POINTER(GridAdam), P, POINTER(AdamState),
                                   POINTER(AuxLoss), P, c_size_t, P]),
     "dvgo_photo_loss": (c_int32, [P, P, c_int32, P, P, P]),
+    "dvgo_fd_reduce_f64": (c_int32, [P, P, P, c_int32, c_int32, P, P]),
     "dvgo_adam_step": (c_int32, [P, P, P, P, P, c_int64, c_float, c_float, c_float, c_float, c_int32, P]),
     "dvgo_grid_active_init": (c_int32, [P, P, P, P, c_int64, P, P]),
     "dvgo_proposal_fwd": (c_int32, [P, P, P, P, c_int32, POINTER(Box), POINTER(Prop), c_float, c_float, P, P, P,

@@ -395,6 +395,17 @@ def photo_loss(rgb: torch.Tensor, target: torch.Tensor):
     return loss, grad
 
 
+def fd_reduce_f64(rgb: torch.Tensor, weight: torch.Tensor, rays: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """sum over the listed rays (all when None) of weight . rgb, in float64
+    on the device (a one-element double tensor)."""
+    lib = load()
+    out = torch.empty(1, dtype=torch.float64, device=rgb.device)
+    n = rays.numel() if rays is not None else rgb.shape[0]
+    check("dvgo_fd_reduce_f64", lib.dvgo_fd_reduce_f64(_ptr(rgb), _ptr(weight), _ptr(rays), n, rgb.shape[0],
+                                                       _ptr(out), _stream(rgb.device)))
+    return out
+
+
 def adam_step(p, g, m, v, lr, t, betas=(0.9, 0.999), eps=1e-8, shadow=None) -> None:
     lib = load()
     check("dvgo_adam_step", lib.dvgo_adam_step(_ptr(p), _ptr(g), _ptr(m), _ptr(v), _ptr(shadow), p.numel(),

@@ -84,9 +84,45 @@ __global__ __launch_bounds__(1024) void photo_loss_kernel(const float* __restric
     }
 }
 
+// Single workgroup: thread t adds the listed rays t, t + 256, ... in float64
+// (each product of two float32 values is exact in float64; the three
+// channels in order), then a fixed-shape tree sums the 256 partials, so the
+// result does not depend on scheduling.  Ray indices outside [0, B) are
+// skipped.
+__global__ __launch_bounds__(256) void fd_reduce_kernel(const float* __restrict__ rgb,
+                                                       const float* __restrict__ weight,
+                                                       const int32_t* __restrict__ rays, int n, int B,
+                                                       double* __restrict__ out) {
+    __shared__ double part[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const int r = rays ? rays[i] : i;
+        if (r < 0 || r >= B) continue;
+        for (int c = 0; c < 3; ++c)
+            acc += static_cast<double>(weight[3 * r + c]) * static_cast<double>(rgb[3 * r + c]);
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (static_cast<int>(threadIdx.x) < h) part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = part[0];
+}
+
 }  // namespace
 
 extern "C" {
+
+int32_t dvgo_fd_reduce_f64(const float* rgb, const float* weight, const int32_t* rays, int32_t n, int32_t B,
+                           double* out, void* stream) {
+    if (n < 0 || B < 0 || !out) return DVGO_E_ARG;
+    if (!rays && n > B) return DVGO_E_SHAPE;
+    if (n > 0 && (!rgb || !weight)) return DVGO_E_ARG;
+    hipLaunchKernelGGL(fd_reduce_kernel, dim3(1), dim3(256), 0, dvgo::as_stream(stream), rgb, weight, rays, n, B,
+                       out);
+    return dvgo::launch_status();
+}
 
 int32_t dvgo_photo_loss(const float* rgb, const float* target, int32_t B, float* grad_rgb, float* loss,
                         void* stream) {

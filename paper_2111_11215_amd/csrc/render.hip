@@ -13,7 +13,9 @@
 // and the backward pass adds
 //   compose' walk each ray from its end (suffix scans from log_t_end)
 //   mlp'     network adjoint, per-block weight-gradient partials
-//   scatter  transpose of the trilinear interpolation, float atomics
+//   scatter  transpose of the trilinear interpolation: samples binned by
+//            grid cell, one thread per vertex gathers its gradient (no
+//            float atomics), the grids' Adam step fused in
 //   reduce   deterministic sum of the per-block weight-gradient partials
 #include "adam.hpp"
 #include "common.hpp"

@@ -141,6 +141,12 @@ def test_host_validation_rejects_before_launch(lib):
     assert lib.dvgo_grid_active_init(fake, fake, 20, fake, 10, fake, nul) == -1
     assert lib.dvgo_grid_active_init(fake, fake, fake, fake, 10, 18, nul) == -1
     assert lib.dvgo_grid_active_init(None, None, None, None, 0, None, nul) == 0
+    # finite-difference reduction: no output, negative counts, more rays than
+    # the batch without an index list, missing inputs
+    assert lib.dvgo_fd_reduce_f64(fake, fake, nul, 4, 4, nul, nul) == -1
+    assert lib.dvgo_fd_reduce_f64(fake, fake, nul, -1, 4, fake, nul) == -1
+    assert lib.dvgo_fd_reduce_f64(fake, fake, nul, 5, 4, fake, nul) == -2
+    assert lib.dvgo_fd_reduce_f64(nul, fake, fake, 5, 4, fake, nul) == -1
 
 
 def test_host_scalars_match_the_oracle(lib):

@@ -174,3 +174,153 @@ def test_stress_finite_differences_and_adjoint(gpu_lib):
     print(f"  samples with an ambiguous ReLU unit: {frac:.2e}", flush=True)
     check_grid_grad("grad_feat", gf, gr["feat"], budget, TOL_LONG)
     check_weight_grads(gm, gr["Ws"], gr["bs"], wb, TOL_LONG)
+
+
+FD_H = 2.0 ** -7     # perturbation of the stored value; the realised step is used
+
+
+def _perturbed(v, h, bf16):
+    """The stored values v + h and v - h as the grid holds them (float32, or
+    bfloat16 for the feature shadow), and whether both are exact."""
+    import torch
+    dt = torch.bfloat16 if bf16 else torch.float32
+    vp = float(torch.tensor(v + h, dtype=torch.float64).to(dt).double())
+    vm = float(torch.tensor(v - h, dtype=torch.float64).to(dt).double())
+    return vp, vm, vp == v + h and vm == v - h
+
+
+def _set_stored(grid, idx, val, bf16):
+    import torch
+    if bf16:
+        grid.feat_shadow[idx] = torch.tensor([val], dtype=torch.float32).to(torch.bfloat16).view(torch.int16)[0].item()
+    else:
+        grid.density[idx] = float(np.float32(val))
+
+
+@pytest.mark.timeout(600)
+def test_stress_fd_through_gpu_forwards(gpu_lib):
+    """Central differences of the GPU's own float32 forward (bfloat16 feature
+    storage, 256^3 grids) with the per-ray loss terms reduced in float64 on
+    the GPU (dvgo_fd_reduce_f64), against the GPU adjoint, on density and
+    feature entries touched by 64 rays of up to 800 samples.  The stored
+    value moves by 2^-7 either way (exact in float32 and in bfloat16 for
+    these values).  Per entry the allowed gap is the sum of: the central
+    difference's own truncation at that step (the float64 oracle's
+    difference minus its adjoint), the float32 forward's rounding (the
+    measured per-ray colour errors of both GPU forwards against the float64
+    oracle, weighted by |g| and divided by the step), and the adjoint's
+    asserted accuracy (3e-5 of the gradient's maximum).  Entries whose two
+    evaluations take different ReLU branches in the oracle are kinks and
+    skipped; density entries never meet a ReLU.  The float64 reduction is
+    also checked against the host's float64 sum of the same values."""
+    import torch
+    from paper_2111_11215_amd import api
+    from paper_2111_11215_amd._lib import DVGO_F32
+    P = synth.stress_config(0)
+    P.act_shift = O.low_density_bias(P.extra["alpha_init"], P.extra["voxel"])
+    n = P.density.shape[0]
+    rng = np.random.default_rng(19)
+    sel = np.sort(rng.choice(P.rays.o.shape[0], 64, replace=False))
+    o, d, j = P.rays.o[sel], P.rays.d[sel], P.rays.jitter[sel]
+    g = rng.normal(size=(64, 3)).astype(F32)
+
+    grid = api.Grid(to_dev(P.density), to_dev(P.feat), tuple(P.box_min), tuple(P.box_max), P.act_shift)
+    grid.feat_shadow = grid.feat.to(torch.bfloat16).view(torch.int16).contiguous()
+    flat = to_dev(mlp_flat_np(P.Ws, P.bs))
+    s = api.sample_rays(to_dev(o), to_dev(d), to_dev(j), P.box_min, P.box_max, P.step, P.max_samples)
+    g_dev = to_dev(g)
+
+    def fwd():
+        return api.render_fwd(grid, flat, s, P.bg, precision=DVGO_F32, use_shadow=True, want_depth_acc=False)
+
+    out = fwd()
+    gd, gf, gm = torch.zeros_like(grid.density), torch.zeros_like(grid.feat), torch.zeros_like(flat)
+    api.render_bwd(grid, flat, s, out["log_t_end"], g_dev, gd, gf, gm, P.bg, precision=DVGO_F32, use_shadow=True)
+    gd, gf = np_of(gd), np_of(gf)
+
+    # float64 reduction against the host's
+    rgb0 = np_of(out["rgb"])
+    rays_all = to_dev(np.arange(64, dtype=np.int32))
+    red = float(np_of(api.fd_reduce_f64(out["rgb"], g_dev, rays_all))[0])
+    terms = g.astype(np.float64) * rgb0.astype(np.float64)
+    assert abs(red - terms.sum()) <= 1e-14 * np.abs(terms).sum()
+    assert float(np_of(api.fd_reduce_f64(out["rgb"], g_dev))[0]) == red
+
+    dens64 = P.density.astype(np.float64)
+    feat64 = O.bf16_round(P.feat)
+    prm = O.Params(dens64, feat64, [w.astype(np.float64) for w in P.Ws], [b.astype(np.float64) for b in P.bs],
+                   P.box_min, P.box_max, P.act_shift)
+    samp = O.sample_rays(o, d, j, P.box_min, P.box_max, P.step, P.max_samples, morton=False)
+    ref = O.render_forward(prm, o, d, j, samp, P.step, P.bg)
+    gr = O.render_backward(prm, o, d, j, samp, P.step, P.bg, ref, g.astype(np.float64))
+    x = ref["cache"]["x"]
+    ray_of = np.asarray(ref["_sample_ray"])
+    i0, wts, offs = O.trilinear_corners(x, P.box_min, P.box_max, (n, n, n))
+    verts_all = i0[:, None, :] + offs[None, :, :]
+
+    def orc(rays):
+        sp = O.sample_rays(o[rays], d[rays], j[rays], P.box_min, P.box_max, P.step, P.max_samples, morton=False)
+        rf = O.render_forward(prm, o[rays], d[rays], j[rays], sp, P.step, P.bg)
+        mc = rf["cache"]["mcache"]
+        return rf["rgb"], (mc["z1"] > 0, mc["z2"] > 0)
+
+    n_entries = 48
+    picks = rng.choice(x.shape[0], 4 * n_entries, replace=False)
+    corners = rng.integers(0, 8, 4 * n_entries)
+    checked, kinks, inexact, worst, rels = 0, 0, 0, 0.0, []
+    max_gd, max_gf = np.abs(gr["density"]).max(), np.abs(gr["feat"]).max()
+    for e in range(4 * n_entries):
+        if checked + kinks >= n_entries:
+            break
+        v = i0[picks[e]] + offs[corners[e]]
+        is_feat = (checked + kinks) % 2 == 1
+        if is_feat:
+            ch = int(rng.integers(0, 12))
+            idx = (int(v[0]), int(v[1]), int(v[2]), ch)
+            arr, a_orc, a_gpu, amax = feat64, gr["feat"][idx], gf[idx], max_gf
+        else:
+            idx = tuple(int(t) for t in v)
+            arr, a_orc, a_gpu, amax = dens64, gr["density"][idx], gd[idx], max_gd
+        v0 = float(arr[idx])
+        vp, vm, exact = _perturbed(v0, FD_H, is_feat)
+        if not exact:
+            inexact += 1
+            continue
+        hit = np.any(np.all(verts_all == v, axis=2) & (wts > 0), axis=1)
+        rays = np.unique(ray_of[hit])
+        rays_dev = to_dev(rays.astype(np.int32))
+        # GPU: two forwards, float64 reduction over the touching rays
+        _set_stored(grid, idx, vp, is_feat)
+        out_p = fwd()
+        lp = api.fd_reduce_f64(out_p["rgb"], g_dev, rays_dev)
+        rgb_p = np_of(out_p["rgb"])[rays]
+        _set_stored(grid, idx, vm, is_feat)
+        out_m = fwd()
+        lm = api.fd_reduce_f64(out_m["rgb"], g_dev, rays_dev)
+        rgb_m = np_of(out_m["rgb"])[rays]
+        _set_stored(grid, idx, v0, is_feat)
+        fd_gpu = (float(np_of(lp)[0]) - float(np_of(lm)[0])) / (vp - vm)
+        # oracle at the same stored values
+        arr[idx] = vp
+        orc_p, mp = orc(rays)
+        arr[idx] = vm
+        orc_m, mm = orc(rays)
+        arr[idx] = v0
+        if not (np.array_equal(mp[0], mm[0]) and np.array_equal(mp[1], mm[1])):
+            kinks += 1
+            continue
+        gr_rays = np.abs(g[rays].astype(np.float64))
+        fd_orc = float(np.sum(g[rays] * orc_p) - np.sum(g[rays] * orc_m)) / (vp - vm)
+        noise = float(np.sum(gr_rays * (np.abs(rgb_p - orc_p) + np.abs(rgb_m - orc_m)))) / (vp - vm)
+        trunc = abs(fd_orc - a_orc)
+        allowed = trunc + noise + TOL_LONG * amax
+        gap = abs(fd_gpu - a_gpu)
+        worst = max(worst, gap / allowed)
+        rels.append(gap / max(abs(a_gpu), 1e-3 * amax))
+        assert gap <= allowed, (idx, fd_gpu, a_gpu, trunc, noise)
+        checked += 1
+    rels = np.array(rels)
+    print(f"  GPU-forward differences: {checked} entries checked, {kinks} kinks, {inexact} inexact steps skipped; "
+          f"gap / allowed max {worst:.3f}; relative gap median {np.median(rels):.2e} max {rels.max():.2e}",
+          flush=True)
+    assert checked >= 0.75 * n_entries
