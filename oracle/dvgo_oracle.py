@@ -373,6 +373,14 @@ def positional_encoding(d, n_freq=4):
     return np.concatenate(parts, axis=-1)
 
 
+def box_coordinates(x, box_min, box_max):
+    """Position in the box's own coordinates, [-1, 1] on each axis:
+    u = (x - centre) / half-extent (the input of the position encoding)."""
+    lo = np.asarray(box_min, np.float64)
+    hi = np.asarray(box_max, np.float64)
+    return (np.asarray(x, np.float64) - 0.5 * (lo + hi)) / (0.5 * (hi - lo))
+
+
 def bf16_round(x):
     """Round float32 values to bfloat16 (round to nearest, ties to even) and
     return them as float64: keep the top 16 bits of the float32 pattern after
@@ -469,10 +477,14 @@ class Params:
     MLP (Eq. fine_queries), or the coarse stage's density grid and
     view-invariant colour grid (Eq. coarse_queries: feat holds V^(rgb), Ws
     and bs are None, the colour is sigmoid(interp(x, V^(rgb))), the output
-    activation of Sec. 3), with the softplus shift b and the AABB."""
+    activation of Sec. 3), with the softplus shift b and the AABB.  With
+    pe_x = k_x > 0 the colour MLP also takes the encoded query position
+    (Eq. fine_queries with k_x frequencies): its input is [interp(x, V_feat),
+    PE_{k_x}(u), PE_4(d)], u the position in box coordinates."""
 
-    def __init__(self, density, feat, Ws, bs, box_min, box_max, act_shift, mlp_bf16=False):
+    def __init__(self, density, feat, Ws, bs, box_min, box_max, act_shift, mlp_bf16=False, pe_x=0):
         self.mlp_bf16 = bool(mlp_bf16)
+        self.pe_x = int(pe_x)       # frequencies of the position encoding in the MLP input (0: none)
         self.density = np.asarray(density)
         self.feat = np.asarray(feat)
         self.grid_colour = Ws is None
@@ -490,7 +502,8 @@ def render_forward(P: Params, o, d, jitter, samp, step, bg, with_color=True):
     For each ray, over its kept samples in ascending k:
       raw_k = interp(x_k, V_density), sigma_k = softplus(raw_k + b),
       alpha_k = 1 - exp(-sigma_k delta),  T_k = prod_{j<k} (1 - alpha_j),
-      c_k = MLP([interp(x_k, V_feat), PE(d)]),
+      c_k = MLP([interp(x_k, V_feat), PE(d)])  (with P.pe_x > 0:
+            MLP([interp(x_k, V_feat), PE_{k_x}(u_k), PE(d)])),
       C = sum_k T_k alpha_k c_k + T_{K+1} c_bg.
     Also depth = sum w_k t_k, acc = sum w_k, log T_{K+1} = -delta sum sigma_k
     (equal to log prod (1 - alpha_k)), per-segment weight sums and the
@@ -530,8 +543,12 @@ def render_forward(P: Params, o, d, jitter, samp, step, bg, with_color=True):
     elif with_color:
         f = interp(P.feat, x, P.box_min, P.box_max)
         pe = positional_encoding(d.astype(np.float64))[sr]
-        xin = np.concatenate([f, pe], axis=1)
-        c, mcache = mlp_forward(P.Ws, P.bs, xin, bf16=P.mlp_bf16, n_feat=P.feat.shape[-1])
+        if P.pe_x > 0:
+            pex = positional_encoding(box_coordinates(x, P.box_min, P.box_max), P.pe_x)
+            xin = np.concatenate([f, pex, pe], axis=1)
+        else:
+            xin = np.concatenate([f, pe], axis=1)
+        c, mcache = mlp_forward(P.Ws, P.bs, xin, bf16=P.mlp_bf16, n_feat=xin.shape[1] - pe.shape[1])
     if with_color:
         rgb = np.zeros((B, 3))
         np.add.at(rgb, slot, w[:, None] * c)

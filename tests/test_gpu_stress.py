@@ -176,17 +176,23 @@ def test_stress_finite_differences_and_adjoint(gpu_lib):
     check_weight_grads(gm, gr["Ws"], gr["bs"], wb, TOL_LONG)
 
 
-FD_H = 2.0 ** -7     # perturbation of the stored value; the realised step is used
+# Perturbations of the stored values.  Density never meets a ReLU, so its
+# step can be larger (the truncation error stays small and the float32
+# forward's rounding is divided by a larger step); feature steps are kept
+# smaller so that few evaluations cross a ReLU kink.
+FD_H_DENSITY = 2.0 ** -4
+FD_H_FEAT = 2.0 ** -6
 
 
 def _perturbed(v, h, bf16):
-    """The stored values v + h and v - h as the grid holds them (float32, or
-    bfloat16 for the feature shadow), and whether both are exact."""
+    """The stored values nearest v + h and v - h as the grid holds them
+    (float32, or bfloat16 for the feature shadow); both sides of the check
+    evaluate at exactly these values and divide by their difference."""
     import torch
     dt = torch.bfloat16 if bf16 else torch.float32
     vp = float(torch.tensor(v + h, dtype=torch.float64).to(dt).double())
     vm = float(torch.tensor(v - h, dtype=torch.float64).to(dt).double())
-    return vp, vm, vp == v + h and vm == v - h
+    return vp, vm
 
 
 def _set_stored(grid, idx, val, bf16):
@@ -203,8 +209,8 @@ def test_stress_fd_through_gpu_forwards(gpu_lib):
     storage, 256^3 grids) with the per-ray loss terms reduced in float64 on
     the GPU (dvgo_fd_reduce_f64), against the GPU adjoint, on density and
     feature entries touched by 64 rays of up to 800 samples.  The stored
-    value moves by 2^-7 either way (exact in float32 and in bfloat16 for
-    these values).  Per entry the allowed gap is the sum of: the central
+    value moves to the nearest stored values to v +- 2^-4 (density) or
+    v +- 2^-6 (features).  Per entry the allowed gap is the sum of: the central
     difference's own truncation at that step (the float64 oracle's
     difference minus its adjoint), the float32 forward's rounding (the
     measured per-ray colour errors of both GPU forwards against the float64
@@ -267,7 +273,9 @@ def test_stress_fd_through_gpu_forwards(gpu_lib):
     n_entries = 48
     picks = rng.choice(x.shape[0], 4 * n_entries, replace=False)
     corners = rng.integers(0, 8, 4 * n_entries)
-    checked, kinks, inexact, worst, rels = 0, 0, 0, 0.0, []
+    checked, kinks, worst = 0, 0, 0.0
+    rels = {False: [], True: []}
+    parts = {False: [], True: []}
     max_gd, max_gf = np.abs(gr["density"]).max(), np.abs(gr["feat"]).max()
     for e in range(4 * n_entries):
         if checked + kinks >= n_entries:
@@ -282,10 +290,7 @@ def test_stress_fd_through_gpu_forwards(gpu_lib):
             idx = tuple(int(t) for t in v)
             arr, a_orc, a_gpu, amax = dens64, gr["density"][idx], gd[idx], max_gd
         v0 = float(arr[idx])
-        vp, vm, exact = _perturbed(v0, FD_H, is_feat)
-        if not exact:
-            inexact += 1
-            continue
+        vp, vm = _perturbed(v0, FD_H_FEAT if is_feat else FD_H_DENSITY, is_feat)
         hit = np.any(np.all(verts_all == v, axis=2) & (wts > 0), axis=1)
         rays = np.unique(ray_of[hit])
         rays_dev = to_dev(rays.astype(np.int32))
@@ -316,11 +321,15 @@ def test_stress_fd_through_gpu_forwards(gpu_lib):
         allowed = trunc + noise + TOL_LONG * amax
         gap = abs(fd_gpu - a_gpu)
         worst = max(worst, gap / allowed)
-        rels.append(gap / max(abs(a_gpu), 1e-3 * amax))
+        scale = max(abs(a_gpu), 1e-3 * amax)
+        rels[is_feat].append(gap / scale)
+        parts[is_feat].append((trunc / scale, noise / scale))
         assert gap <= allowed, (idx, fd_gpu, a_gpu, trunc, noise)
         checked += 1
-    rels = np.array(rels)
-    print(f"  GPU-forward differences: {checked} entries checked, {kinks} kinks, {inexact} inexact steps skipped; "
-          f"gap / allowed max {worst:.3f}; relative gap median {np.median(rels):.2e} max {rels.max():.2e}",
-          flush=True)
+    for is_feat, name in ((False, "density"), (True, "feature")):
+        r, pt = np.array(rels[is_feat]), np.array(parts[is_feat])
+        print(f"  {name}: {r.size} entries; |FD(GPU) - adjoint(GPU)| / |adjoint| median {np.median(r):.2e} "
+              f"max {r.max():.2e}; of which truncation (median) {np.median(pt[:, 0]):.2e}, float32 forward "
+              f"rounding (median) {np.median(pt[:, 1]):.2e}", flush=True)
+    print(f"  {checked} entries checked, {kinks} kinks skipped; gap / allowed max {worst:.3f}", flush=True)
     assert checked >= 0.75 * n_entries

@@ -313,9 +313,11 @@ def test_softplus_sigmoid_textbook():
 # ---------------------------------------------------------------------------
 # the hand adjoint: torch autograd of an independent forward, and FD
 # ---------------------------------------------------------------------------
-def _torch_forward(dens, feat, Ws, bs, b, o, d, jit, samp, step, bg):
+def _torch_forward(dens, feat, Ws, bs, b, o, d, jit, samp, step, bg, pe_x=0):
     """Independent float64 torch forward of the same quadrature (written with
-    torch ops, product form of the transmittance, per-ray loop)."""
+    torch ops, product form of the transmittance, per-ray loop).  With
+    pe_x > 0 the network input is [features, encoded position (box [-1,1]^3,
+    so box coordinates are the position itself), encoded direction]."""
     t_near = samp["t_near"]
     outs = torch.zeros((o.shape[0], 3), dtype=torch.float64)
     n = np.array(dens.shape)
@@ -345,7 +347,15 @@ def _torch_forward(dens, feat, Ws, bs, b, o, d, jit, samp, step, bg):
                 fv = fv + wgt * feat[ii[0], ii[1], ii[2]]
             sig = torch.nn.functional.softplus(raw + b)
             a = 1 - torch.exp(-sig * step)
-            h = torch.relu(Ws[0] @ torch.cat([fv, pe]) + bs[0])
+            if pe_x:
+                xt = torch.tensor(x, dtype=torch.float64)
+                pex = [xt]
+                for fr in range(pe_x):
+                    pex += [torch.sin(xt * 2 ** fr), torch.cos(xt * 2 ** fr)]
+                inp = torch.cat([fv, torch.cat(pex), pe])
+            else:
+                inp = torch.cat([fv, pe])
+            h = torch.relu(Ws[0] @ inp + bs[0])
             h = torch.relu(Ws[1] @ h + bs[1])
             col = torch.sigmoid(Ws[2] @ h + bs[2])
             C = C + T * a * col
@@ -389,6 +399,59 @@ def test_adjoint_matches_torch_autograd():
     assert np.allclose(gr["feat"], tf.grad.numpy(), rtol=1e-9, atol=1e-13)
     for a, t in zip(gr["Ws"] + gr["bs"], tW + tb):
         assert np.allclose(a, t.grad.numpy(), rtol=1e-9, atol=1e-13)
+
+
+def test_adjoint_with_position_encoding_matches_torch_autograd():
+    """The variant whose network also takes PE_5 of the query position
+    (72 inputs): forward and every gradient by autograd of the independent
+    torch forward."""
+    dens, feat, _, bs, o, d, jit, tgt, step = _small_problem(3, n=5, rays=16)
+    rng = np.random.default_rng(31)
+    Ws, _ = synth.xavier_uniform_mlp(rng, (72, 128, 128, 3))
+    b, bg = 0.3, np.array([1.0, 0.9, 0.8])
+    samp = O.sample_rays(o, d, jit, [-1] * 3, [1] * 3, step, 64, morton=True)
+    prm = O.Params(dens, feat, Ws, bs, [-1] * 3, [1] * 3, b, pe_x=5)
+    fwd = O.render_forward(prm, o, d, jit, samp, step, bg)
+    loss, g = O.photo_loss(fwd["rgb"], tgt)
+    gr = O.render_backward(prm, o, d, jit, samp, step, bg, fwd, g)
+    T = lambda a: torch.tensor(np.asarray(a, np.float64), requires_grad=True)
+    td, tf = T(dens), T(feat)
+    tW = [T(w) for w in Ws]
+    tb = [T(x) for x in bs]
+    rgb = _torch_forward(td, tf, tW, tb, b, o, d, jit, samp, step, bg, pe_x=5)
+    assert np.allclose(rgb.detach().numpy(), fwd["rgb"], rtol=1e-12, atol=1e-13)
+    L = ((rgb - torch.tensor(tgt)) ** 2).sum() / rgb.shape[0]
+    L.backward()
+    assert np.allclose(gr["density"], td.grad.numpy(), rtol=1e-9, atol=1e-13)
+    assert np.allclose(gr["feat"], tf.grad.numpy(), rtol=1e-9, atol=1e-13)
+    for a, t in zip(gr["Ws"] + gr["bs"], tW + tb):
+        assert np.allclose(a, t.grad.numpy(), rtol=1e-9, atol=1e-13)
+
+
+def test_position_encoding_columns_sit_between_features_and_direction():
+    """With the 33 position columns of W1 zero, the 72-input network renders
+    what the 39-input network [W1_feat | W1_dir] renders, and its position
+    columns still receive a gradient; box coordinates put the box's centre
+    at 0 and its faces at -1 and 1."""
+    dens, feat, Ws39, bs, o, d, jit, tgt, step = _small_problem(4, n=5, rays=16)
+    rng = np.random.default_rng(32)
+    W1 = np.zeros((128, 72))
+    W1[:, :12] = Ws39[0][:, :12]
+    W1[:, 45:] = Ws39[0][:, 12:]
+    Ws72 = [W1, Ws39[1], Ws39[2]]
+    samp = O.sample_rays(o, d, jit, [-1] * 3, [1] * 3, step, 64)
+    p39 = O.Params(dens, feat, Ws39, bs, [-1] * 3, [1] * 3, 0.2)
+    p72 = O.Params(dens, feat, Ws72, bs, [-1] * 3, [1] * 3, 0.2, pe_x=5)
+    f39 = O.render_forward(p39, o, d, jit, samp, step, np.ones(3))
+    f72 = O.render_forward(p72, o, d, jit, samp, step, np.ones(3))
+    assert np.allclose(f39["rgb"], f72["rgb"], rtol=0, atol=1e-14)
+    _, g = O.photo_loss(f72["rgb"], tgt)
+    gr = O.render_backward(p72, o, d, jit, samp, step, np.ones(3), f72, g)
+    assert np.abs(gr["Ws"][0][:, 12:45]).max() > 0
+    u = O.box_coordinates(np.array([[3.0, -1.0, 0.5]]), [2, -3, 0], [4, 1, 1])
+    assert np.allclose(u, [[0.0, 0.0, 0.0]])
+    u = O.box_coordinates(np.array([[4.0, -3.0, 0.75]]), [2, -3, 0], [4, 1, 1])
+    assert np.allclose(u, [[1.0, -1.0, 0.5]])
 
 
 def test_adjoint_depth_acc_terms_match_fd():
