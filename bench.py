@@ -190,7 +190,7 @@ def coarse_stage(ctx, iters, alpha_init, rays=8192, pool=64):
     return rep, (mask, ctx["bmin"], ctx["bmax"], (100, 100, 100))
 
 
-def new_model(ctx, bf16, skip_pg=False, coarse=None, aux=False):
+def new_model(ctx, bf16, skip_pg=False, coarse=None, aux=False, pe_x=0):
     import numpy as np
     import torch
 
@@ -199,8 +199,9 @@ def new_model(ctx, bf16, skip_pg=False, coarse=None, aux=False):
     from paper_2111_11215_amd._lib import DVGO_BF16, DVGO_F32
     dev = torch.device("cuda:0")
     n = ctx["n"]
-    Ws, bs = synth.xavier_uniform_mlp(np.random.default_rng(7), (39, 128, 128, 3))
-    flat = api.flat_from([Ws[0], bs[0], Ws[1], bs[1], Ws[2], bs[2]], api.MLP_SHAPES, dev)
+    # pe_x = 5: the paper's network that also takes the encoded position (72 inputs)
+    Ws, bs = synth.xavier_uniform_mlp(np.random.default_rng(7), (72 if pe_x else 39, 128, 128, 3))
+    flat = api.flat_from([Ws[0], bs[0], Ws[1], bs[1], Ws[2], bs[2]], api.mlp_shapes(pe_x), dev)
     cfg = train.FineConfig(step=ctx["step"], max_samples=ctx["max_samples"],
                            precision=DVGO_BF16 if bf16 else DVGO_F32, bf16_feat=bf16, morton=ctx["morton"])
     if aux:
@@ -237,6 +238,7 @@ FORMS = {"plain": ("plain_fp32", False, False), "bf16": ("bf16", True, False),
 # forms trained in the comparison only: bf16 with the fine-density skip and progressive scaling
 EXTRA_FORMS = {"skip_pg": ("bf16_fine_skip_progressive", True, False),
                "aux": ("bf16_auxiliary_losses", True, False),
+               "paper": ("fp32_paper_network_and_objective", False, False),
                "learned_coarse": ("bf16_learned_coarse_mask", True, False)}
 
 
@@ -255,11 +257,13 @@ def compare_forms(ctx, iters, rays, keep):
     res = {"iters": iters, "rays_per_iter": rays, "views": len(views)}
     kept = None
     ctx = dict(ctx, compare_iters=iters)
-    forms = ("plain", "bf16", "proposal", "skip_pg", "aux") + (("learned_coarse",) if "coarse_learned" in ctx else ())
+    forms = ("plain", "bf16", "proposal", "skip_pg", "aux", "paper") + \
+        (("learned_coarse",) if "coarse_learned" in ctx else ())
     for form in forms:
         name, bf16, use_prop = FORMS.get(form) or EXTRA_FORMS[form]
-        model = new_model(ctx, bf16, skip_pg=form == "skip_pg", aux=form == "aux",
-                          coarse=ctx["coarse_learned"] if form == "learned_coarse" else None)
+        model = new_model(ctx, bf16, skip_pg=form == "skip_pg", aux=form in ("aux", "paper"),
+                          coarse=ctx["coarse_learned"] if form == "learned_coarse" else None,
+                          pe_x=5 if form == "paper" else 0)
         if form == "plain":
             experiment.count_uniform(model, batches)
         prop = new_proposal(ctx) if use_prop else None
@@ -293,6 +297,9 @@ def compare_forms(ctx, iters, rays, keep):
     sp, b16 = res["bf16_fine_skip_progressive"], res["bf16"]
     res["fine_skip_progressive_vs_bf16"] = {"speedup": sp["ray_samples_per_s"] / b16["ray_samples_per_s"],
                                             "delta_psnr_db": sp["psnr_db"] - b16["psnr_db"]}
+    pp, f32 = res["fp32_paper_network_and_objective"], res["plain_fp32"]
+    res["paper_network_and_objective_vs_plain_fp32"] = {"ms_per_step_ratio": pp["ms_per_step"] / f32["ms_per_step"],
+                                                         "delta_psnr_db": pp["psnr_db"] - f32["psnr_db"]}
     ax = res["bf16_auxiliary_losses"]
     res["auxiliary_losses_vs_bf16"] = {"ms_per_step_ratio": ax["ms_per_step"] / b16["ms_per_step"],
                                        "delta_psnr_db": ax["psnr_db"] - b16["psnr_db"]}

@@ -75,17 +75,27 @@ typedef struct dvgo_field {
  * two ReLU layers of `hidden` (must be 128) and a sigmoid RGB output.
  * Weights are float32 masters [out][in]; `precision` selects the arithmetic
  * of its matrix products: DVGO_F32 (float32 matrix cores) or DVGO_BF16
- * (bfloat16 inputs, float32 accumulation). */
+ * (bfloat16 inputs, float32 accumulation).
+ * pe_x = 5 selects the paper's network that also takes the encoded query
+ * position (Eq. fine_queries with k_x = 5 frequencies, supplementary
+ * implementation details): input [feat(C), PE_5(u)(33), PE(d)(27)] (72 for
+ * C = 12), where u = (x - centre) / half-extent is the sample's position in
+ * the field box's coordinates (centre and 2/(max - min) rounded once to
+ * float32) and PE_5(u) = [u, sin(2^j u), cos(2^j u)], j = 0..4, three
+ * components each; float32 precision only.  pe_x = 0 (zero-initialised
+ * structs) is the 39-input network; other values are DVGO_E_UNSUPPORTED,
+ * and so is pe_x = 5 with DVGO_BF16. */
 typedef struct dvgo_mlp {
-    const float* w1; const float* b1;   /* [hidden][C+27], [hidden] */
+    const float* w1; const float* b1;   /* [hidden][C+27] (pe_x 5: [hidden][C+60]), [hidden] */
     const float* w2; const float* b2;   /* [hidden][hidden], [hidden] */
     const float* w3; const float* b3;   /* [3][hidden], [3] */
     int32_t hidden;
     int32_t precision;
+    int32_t pe_x;
 } dvgo_mlp;
 
 /* Flat gradient layout of dvgo_mlp: w1, b1, w2, b2, w3, b3 concatenated. */
-int64_t dvgo_mlp_param_count(int32_t channels, int32_t hidden);
+int64_t dvgo_mlp_param_count(int32_t channels, int32_t hidden, int32_t pe_x);
 
 /* Proposal network (not in the paper: a learned predictor of which of 32
  * equal-count ray segments carry the compositing weight): input 54 values

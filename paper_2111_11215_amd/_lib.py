@@ -43,7 +43,7 @@ class Field(ctypes.Structure):
 
 class Mlp(ctypes.Structure):
     _fields_ = [("w1", c_void_p), ("b1", c_void_p), ("w2", c_void_p), ("b2", c_void_p), ("w3", c_void_p),
-                ("b3", c_void_p), ("hidden", c_int32), ("precision", c_int32)]
+                ("b3", c_void_p), ("hidden", c_int32), ("precision", c_int32), ("pe_x", c_int32)]
 
 
 class Prop(ctypes.Structure):
@@ -75,7 +75,7 @@ class DvgoError(RuntimeError):
 P = c_void_p
 # name -> (restype, argtypes)
 SIGNATURES = {
-    "dvgo_mlp_param_count": (c_int64, [c_int32, c_int32]),
+    "dvgo_mlp_param_count": (c_int64, [c_int32, c_int32, c_int32]),
     "dvgo_prop_param_count": (c_int64, []),
     "dvgo_coarse_mask_build": (c_int32, [P, POINTER(Box), c_float, P, P]),
     "dvgo_sample_workspace_bytes": (c_size_t, [c_int32]),

@@ -120,8 +120,16 @@ class Grid:
         return f
 
 
-MLP_SHAPES = [("w1", (HIDDEN, CHANNELS + 27)), ("b1", (HIDDEN,)), ("w2", (HIDDEN, HIDDEN)), ("b2", (HIDDEN,)),
-              ("w3", (3, HIDDEN)), ("b3", (3,))]
+def mlp_shapes(pe_x: int = 0):
+    """Flat layout of the colour network; pe_x = 5 adds the encoded query
+    position (33 inputs) between the features and the view encoding."""
+    n_in = CHANNELS + (3 + 6 * pe_x if pe_x else 0) + 27
+    return [("w1", (HIDDEN, n_in)), ("b1", (HIDDEN,)), ("w2", (HIDDEN, HIDDEN)), ("b2", (HIDDEN,)),
+            ("w3", (3, HIDDEN)), ("b3", (3,))]
+
+
+MLP_SHAPES = mlp_shapes(0)
+MLP_SHAPES_PE_X = mlp_shapes(5)
 PROP_SHAPES = [("w1", (64, 54)), ("b1", (64,)), ("w2", (64, 64)), ("b2", (64,)), ("w3", (NSEG, 64)),
                ("b3", (NSEG,))]
 
@@ -144,12 +152,16 @@ def flat_from(arrays, shapes, device) -> torch.Tensor:
 
 
 def mlp_struct(flat: torch.Tensor, precision: int = DVGO_F32) -> Mlp:
-    v = split_flat(flat, MLP_SHAPES)
+    """dvgo_mlp over a flat parameter tensor; its size tells the 39-input
+    network from the one with the encoded position (72 inputs)."""
+    pe_x = 5 if flat.numel() == sum(math.prod(s) for _, s in MLP_SHAPES_PE_X) else 0
+    v = split_flat(flat, mlp_shapes(pe_x))
     m = Mlp()
     for name in ("w1", "b1", "w2", "b2", "w3", "b3"):
         setattr(m, name, v[name].data_ptr())
     m.hidden = HIDDEN
     m.precision = precision
+    m.pe_x = pe_x
     return m
 
 

@@ -39,6 +39,35 @@ constexpr int kW3PackBF16 = 8 * 64 * 8;    // layer 3 as a 32-row tile (rows >= 
 constexpr int kW3TPackBF16 = 4 * 64 * 8;   // W3^T, one K step (k >= 3 zero)
 constexpr int kW1TPackBF16 = 8 * 64 * 8;   // W1[:, :12]^T as a 32-row tile (rows >= 12 zero)
 
+// Layout of the network whose input also carries the encoded query
+// position (Eq. fine_queries with k_x = KX frequencies): input [feat (12),
+// PE_KX(u) (3 + 6 KX), PE(d) (27)], u the position in box coordinates.  The
+// per-sample part of the first layer is [feat, PE_KX(u)] (kS values); the
+// view part is evaluated once per ray as before.  KX = 0 is the 39-input
+// network above.  Float32 matrix cores only.
+template <int KX>
+struct NetLayout {
+    static constexpr int kXPE = KX ? 3 + 6 * KX : 0;
+    static constexpr int kS = kC + kXPE;              // per-sample first-layer inputs
+    static constexpr int kIn = kS + kPE;              // first-layer inputs
+    static constexpr int kOffW1 = 0;
+    static constexpr int kOffB1 = kOffW1 + kH * kIn;
+    static constexpr int kOffW2 = kOffB1 + kH;
+    static constexpr int kOffB2 = kOffW2 + kH * kH;
+    static constexpr int kOffW3 = kOffB2 + kH;
+    static constexpr int kOffB3 = kOffW3 + 3 * kH;
+    static constexpr int kParams = kOffB3 + 3;
+    static constexpr int kPStride = (kParams + 63) / 64 * 64;
+    static constexpr int kQ1 = ((kS + 1) / 2 + 3) / 4;   // float4 groups of K = 2 layer-1 steps
+    static constexpr int kXT = (kIn + 1 + 31) / 32;      // 32-column tiles of x' = [input, 1]
+};
+static_assert(NetLayout<0>::kIn == kIn && NetLayout<0>::kParams == kMlpParams && NetLayout<0>::kQ1 == 2 &&
+                  NetLayout<0>::kXT == 2,
+              "the 39-input layout");
+constexpr int kMaxKX = 5;                                          // the paper's k_x
+constexpr int kW1PackF32Max = 4 * NetLayout<kMaxKX>::kQ1 * 64 * 4;   // packed W1 of either layout
+constexpr int kPStrideMax = NetLayout<kMaxKX>::kPStride;
+
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef short i16x8 __attribute__((ext_vector_type(8)));
@@ -96,6 +125,9 @@ struct PackArgs {
     uint16_t* w2pb;
     uint16_t* w2tpb;
     int bf16;
+    int w1_in;   // first-layer input width (row stride of W1)
+    int w1_ns;   // per-sample first-layer inputs (packed into w1p)
+    int w1_q;    // float4 groups of w1p per output tile
 };
 
 // Pack W1 (feature columns) and W2 / W2^T into matrix-core operand order.
@@ -120,12 +152,12 @@ __device__ __forceinline__ void pack_weights(const PackArgs& a, int gid) {
             a.w2tpb[gid] = f2bf(a.w2[k2 * kH + row2]);
         }
     }
-    if (gid < kW1PackF32) {
-        // float32 layer 1: index ((mt*2 + q)*64 + lane)*4 + u, st = 4q+u, k = 2st + h (< 12)
-        const int u = gid & 3, lane = (gid >> 2) & 63, q = (gid >> 8) & 1, mt = gid >> 9;
+    if (gid < 4 * a.w1_q * 64 * 4) {
+        // float32 layer 1: index ((mt*Q + q)*64 + lane)*4 + u, st = 4q+u, k = 2st + h (< w1_ns)
+        const int u = gid & 3, lane = (gid >> 2) & 63, q = (gid >> 8) % a.w1_q, mt = (gid >> 8) / a.w1_q;
         const int st = 4 * q + u, m = lane & 31, h = lane >> 5;
         const int kk = 2 * st + h;
-        a.w1p[gid] = kk < kC ? a.w1[(32 * mt + m) * kIn + kk] : 0.0f;
+        a.w1p[gid] = kk < a.w1_ns ? a.w1[(32 * mt + m) * a.w1_in + kk] : 0.0f;
     }
     if (a.bf16 && gid < kW3PackBF16) {
         // index (st*64 + lane)*8 + i; lane (m, h), element i
@@ -181,6 +213,21 @@ struct MlpArgs {
     const float4* rec_head;   // [cap] (fx, fy, fz, dL/draw)
     float4* rec;              // [cap][4] binned records
     int nrays;                // rows of base and pe
+};
+
+// The query position of each sample, for the networks with an encoded
+// position (a separate kernel argument, so that the other kernels' argument
+// block stays as it is): x = o + t_k d in the sampler's float32 recipe,
+// u = (x - pe_c) * pe_ih.
+struct PosArgs {
+    const float* rays_o;
+    const float* rays_d;
+    const float* jitter;
+    const float* t_near;
+    const int* sample_k;
+    float step;
+    float pe_c[3];
+    float pe_ih[3];
 };
 
 __device__ __forceinline__ float4* binned_record(const MlpArgs& a, int64_t s) {
@@ -245,22 +292,27 @@ __device__ __forceinline__ f32x16 chain_tile_f32(const P* w2op, int lane, int mt
     return acc;
 }
 
-template <typename P>
-__device__ __forceinline__ void forward_chain_f32(const MlpArgs& a, const P* w2op, int r, const float f[12], int lane,
-                                                  ChainF32& c) {
+// Layer 1 on the per-sample inputs xs (kS values: features, then the
+// encoded position), then layer 2.  Lane half h supplies input 2 st + h of
+// step st.
+template <int KX, typename P>
+__device__ __forceinline__ void forward_chain_f32(const MlpArgs& a, const P* w2op, int r,
+                                                  const float xs[NetLayout<KX>::kS], int lane, ChainF32& c) {
+    using L = NetLayout<KX>;
     const int h = lane >> 5;
     load_base(a.base, r, h, c.h1);
     const float4* w1p = reinterpret_cast<const float4*>(a.w1p);
     #pragma unroll
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < L::kQ1; ++q) {
         float4 a4[4];
         #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) a4[mt] = w1p[(mt * 2 + q) * 64 + lane];
+        for (int mt = 0; mt < 4; ++mt) a4[mt] = w1p[(mt * L::kQ1 + q) * 64 + lane];
         #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int st = 4 * q + u;
-            const int kk = 2 * st + h;
-            const float b = kk < 12 ? f[kk] : 0.0f;
+            const int k0 = 2 * (4 * q + u), k1 = k0 + 1;   // compile-time indices
+            const float v0 = k0 < L::kS ? xs[k0 < L::kS ? k0 : 0] : 0.0f;
+            const float v1 = k1 < L::kS ? xs[k1 < L::kS ? k1 : 0] : 0.0f;
+            const float b = h ? v1 : v0;
             #pragma unroll
             for (int mt = 0; mt < 4; ++mt) c.h1[mt] = mma_f32(a4[mt][u], b, c.h1[mt]);
         }
@@ -305,8 +357,40 @@ __device__ __forceinline__ void load_feat(const float* feat, int64_t s, float f[
     f[8] = q2.x; f[9] = q2.y; f[10] = q2.z; f[11] = q2.w;
 }
 
+// Per-sample first-layer inputs of sample s on ray r: its 12 features,
+// then (KX > 0) the encoded position [u, sin(2^j u), cos(2^j u)], j < KX,
+// with the library sine and cosine.
+template <int KX>
+__device__ __forceinline__ void sample_inputs(const PosArgs& a, const float* feat, int64_t s, int r,
+                                              float xs[NetLayout<KX>::kS]) {
+    load_feat(feat, s, xs);
+    if constexpr (KX > 0) {
+        float o[3], d[3], x[3];
+        #pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            o[i] = a.rays_o[3 * r + i];
+            d[i] = a.rays_d[3 * r + i];
+        }
+        const float p = a.jitter ? a.jitter[r] : 0.0f;
+        const float t = dvgo_dev::recipe_tk(a.t_near[r], p, a.sample_k[s], a.step);
+        dvgo_dev::recipe_x(o, d, t, x);
+        #pragma unroll
+        for (int i = 0; i < 3; ++i) xs[kC + i] = (x[i] - a.pe_c[i]) * a.pe_ih[i];
+        #pragma unroll
+        for (int j = 0; j < KX; ++j)
+            #pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                float sv, cv;
+                sincosf(xs[kC + i] * static_cast<float>(1 << j), &sv, &cv);
+                xs[kC + 3 + 6 * j + i] = sv;
+                xs[kC + 6 + 6 * j + i] = cv;
+            }
+    }
+}
+
 // Forward: colour of every listed sample.  LDS holds the packed W2.
-__global__ __launch_bounds__(256, 2) void mlp_fwd_f32_kernel(MlpArgs a0) {
+template <int KX>
+__global__ __launch_bounds__(256, 2) void mlp_fwd_f32_kernel(MlpArgs a0, PosArgs pa) {
     const MlpArgs& a = a0;
     __shared__ float4 sW2[kW2PackF32 / 4];
     for (int i = threadIdx.x; i < kW2PackF32 / 4; i += blockDim.x)
@@ -322,10 +406,10 @@ __global__ __launch_bounds__(256, 2) void mlp_fwd_f32_kernel(MlpArgs a0) {
         const bool ok = s < n;
         const int64_t sc = ok ? s : n - 1;
         const int r = a.sample_ray[sc];
-        float f[12];
-        load_feat(a.feat, sc, f);
+        float xs[NetLayout<KX>::kS];
+        sample_inputs<KX>(pa, a.feat, sc, r, xs);
         ChainF32 c;
-        forward_chain_f32(a, sW2, r, f, lane, c);
+        forward_chain_f32<KX>(a, sW2, r, xs, lane, c);
         float col[3];
         head(a, c.z2, h, col);
         if (ok && h == 0) reinterpret_cast<float4*>(a.col)[s] = make_float4(col[0], col[1], col[2], 0.0f);
@@ -337,19 +421,21 @@ __global__ __launch_bounds__(256, 2) void mlp_fwd_f32_kernel(MlpArgs a0) {
 // ---------------------------------------------------------------------------
 constexpr int kSRow = 132;      // LDS row pitch (floats) of a staged sample row
 
-__global__ __launch_bounds__(256, 1) void mlp_bwd_f32_kernel(MlpArgs a0) {
+template <int KX>
+__global__ __launch_bounds__(256, 1) void mlp_bwd_f32_kernel(MlpArgs a0, PosArgs pa) {
+    using L = NetLayout<KX>;
     __shared__ float sA[128 * kSRow];   // h1 rows, then dL/dz1 rows
     __shared__ float sB[128 * kSRow];   // h2 / dL/dz2 rows, then x' = [f, PE, 1, 0..] rows
     const int64_t n = *a0.n_kept < a0.cap ? *a0.n_kept : a0.cap;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m = lane & 31, h = lane >> 5;
-    f32x16 dW2[4], dW1[2];
+    f32x16 dW2[4], dW1[L::kXT];
     #pragma unroll
     for (int t = 0; t < 4; ++t)
         #pragma unroll
         for (int rr = 0; rr < 16; ++rr) dW2[t][rr] = 0.0f;
     #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < L::kXT; ++t)
         #pragma unroll
         for (int rr = 0; rr < 16; ++rr) dW1[t][rr] = 0.0f;
     float dW3a[3] = {0, 0, 0}, dW3b[3] = {0, 0, 0}, db2a = 0.0f, db2b = 0.0f, db3[3] = {0, 0, 0};
@@ -363,10 +449,10 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_f32_kernel(MlpArgs a0) {
         const bool ok = s < n;
         const int64_t sc = ok ? s : n - 1;
         const int r = a.sample_ray[sc];
-        float f[12];
-        load_feat(a.feat, sc, f);
+        float xs[L::kS];
+        sample_inputs<KX>(pa, a.feat, sc, r, xs);
         ChainF32 c;
-        forward_chain_f32(a, w2p, r, f, lane, c);
+        forward_chain_f32<KX>(a, w2p, r, xs, lane, c);
         float col[3];
         head(a, c.z2, h, col);
         float dz3[3] = {0, 0, 0};
@@ -457,7 +543,7 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_f32_kernel(MlpArgs a0) {
                 const int i = 32 * mt + acc_row(rr, h);
                 const float d = c.h1[mt][rr];
                 #pragma unroll
-                for (int cc = 0; cc < 12; ++cc) df[cc] += a.w1[i * kIn + cc] * d;
+                for (int cc = 0; cc < 12; ++cc) df[cc] += a.w1[i * L::kIn + cc] * d;
             }
         #pragma unroll
         for (int cc = 0; cc < 12; ++cc) df[cc] += __shfl_xor(df[cc], 32, 64);
@@ -470,18 +556,19 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_f32_kernel(MlpArgs a0) {
                 *reinterpret_cast<float4*>(myA + m * kSRow + 32 * mt + 8 * q + 4 * h) =
                     make_float4(c.h1[mt][4 * q], c.h1[mt][4 * q + 1], c.h1[mt][4 * q + 2], c.h1[mt][4 * q + 3]);
         {
+            // x' = [per-sample inputs, PE(d), 1, 0...]: lane half h stages
+            // columns kHalf h .. kHalf h + kHalf - 1 (both candidates of a
+            // column are compile-time indices)
+            constexpr int kHalf = 16 * L::kXT;
             const float* per = a.pe + static_cast<int64_t>(r) * 32;
-            float* row = myB + m * kSRow + 32 * h;
+            float* row = myB + m * kSRow + kHalf * h;
+            auto xval = [&](int j) -> float {
+                if (j < L::kS) return xs[j < L::kS ? j : 0];
+                if (j < L::kIn) return per[j - L::kS];
+                return j == L::kIn ? 1.0f : 0.0f;
+            };
             #pragma unroll
-            for (int cc = 0; cc < 32; ++cc) {
-                const int col = 32 * h + cc;
-                float v;
-                if (col < kC) v = f[col];
-                else if (col < kIn) v = per[col - kC];
-                else if (col == kIn) v = 1.0f;
-                else v = 0.0f;
-                row[cc] = v;
-            }
+            for (int cc = 0; cc < kHalf; ++cc) row[cc] = h ? xval(kHalf + cc) : xval(cc);
         }
         if (ok && h == 0) {
             float4* rec = binned_record(a, s);
@@ -498,28 +585,28 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_f32_kernel(MlpArgs a0) {
             for (int st = 0; st < 16; ++st) {
                 const int row = src * 32 + 2 * st + h;
                 const float av = sA[row * kSRow + 32 * wave + m];
-                dW1[0] = mma_f32(av, sB[row * kSRow + m], dW1[0]);
-                dW1[1] = mma_f32(av, sB[row * kSRow + 32 + m], dW1[1]);
+                #pragma unroll
+                for (int nt = 0; nt < L::kXT; ++nt) dW1[nt] = mma_f32(av, sB[row * kSRow + 32 * nt + m], dW1[nt]);
             }
         __syncthreads();
     }
     // ---- epilogue: this workgroup's partial of the flat gradient
-    float* out = a0.partial + static_cast<int64_t>(blockIdx.x) * kPStride;
+    float* out = a0.partial + static_cast<int64_t>(blockIdx.x) * L::kPStride;
     #pragma unroll
     for (int nt = 0; nt < 4; ++nt)
         #pragma unroll
         for (int rr = 0; rr < 16; ++rr) {
             const int j = 32 * wave + acc_row(rr, h);
-            out[kOffW2 + j * kH + 32 * nt + m] = dW2[nt][rr];
+            out[L::kOffW2 + j * kH + 32 * nt + m] = dW2[nt][rr];
         }
     #pragma unroll
-    for (int nt = 0; nt < 2; ++nt)
+    for (int nt = 0; nt < L::kXT; ++nt)
         #pragma unroll
         for (int rr = 0; rr < 16; ++rr) {
             const int i = 32 * wave + acc_row(rr, h);
             const int col = 32 * nt + m;
-            if (col < kIn) out[kOffW1 + i * kIn + col] = dW1[nt][rr];
-            else if (col == kIn) out[kOffB1 + i] = dW1[nt][rr];
+            if (col < L::kIn) out[L::kOffW1 + i * L::kIn + col] = dW1[nt][rr];
+            else if (col == L::kIn) out[L::kOffB1 + i] = dW1[nt][rr];
         }
     #pragma unroll
     for (int t = 0; t < 3; ++t) {
@@ -541,10 +628,10 @@ __global__ __launch_bounds__(256, 1) void mlp_bwd_f32_kernel(MlpArgs a0) {
     __syncthreads();
     for (int i = threadIdx.x; i < 512; i += blockDim.x) {
         const float v = red[i] + red[512 + i] + red[1024 + i] + red[1536 + i];
-        if (i < 384) out[kOffW3 + i] = v;
-        else out[kOffB2 + (i - 384)] = v;
+        if (i < 384) out[L::kOffW3 + i] = v;
+        else out[L::kOffB2 + (i - 384)] = v;
     }
-    if (threadIdx.x < 3) out[kOffB3 + threadIdx.x] = sB[threadIdx.x] + sB[4 + threadIdx.x] + sB[8 + threadIdx.x] +
+    if (threadIdx.x < 3) out[L::kOffB3 + threadIdx.x] = sB[threadIdx.x] + sB[4 + threadIdx.x] + sB[8 + threadIdx.x] +
                                                    sB[12 + threadIdx.x];
 }
 
@@ -1234,13 +1321,19 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
                                     sRed[12 + threadIdx.x];
 }
 
-inline void launch_mlp_fwd(const MlpArgs& a, int cus, hipStream_t s) {
+// kx: frequencies of the encoded position in the input (0 or kMaxKX; the
+// bfloat16 kernels take 0 only, which the entry points check).
+inline void launch_mlp_fwd(const MlpArgs& a, const PosArgs& pa, int kx, int cus, hipStream_t s) {
     if (a.bf16) DVGO_LAUNCH(K_MLP_FWD, mlp_fwd_bf16_kernel, dim3(cus * 2), dim3(256), 0, s, a);
-    else DVGO_LAUNCH(K_MLP_FWD, mlp_fwd_f32_kernel, dim3(cus * 2), dim3(256), 0, s, a);
+    else if (kx == kMaxKX)
+        DVGO_LAUNCH(K_MLP_FWD, mlp_fwd_f32_kernel<kMaxKX>, dim3(cus * 2), dim3(256), 0, s, a, pa);
+    else DVGO_LAUNCH(K_MLP_FWD, mlp_fwd_f32_kernel<0>, dim3(cus * 2), dim3(256), 0, s, a, pa);
 }
-inline void launch_mlp_bwd(const MlpArgs& a, int blocks, hipStream_t s) {
+inline void launch_mlp_bwd(const MlpArgs& a, const PosArgs& pa, int kx, int blocks, hipStream_t s) {
     if (a.bf16) DVGO_LAUNCH(K_MLP_BWD, mlp_bwd_bf16_kernel, dim3(blocks), dim3(512), 0, s, a);
-    else DVGO_LAUNCH(K_MLP_BWD, mlp_bwd_f32_kernel, dim3(blocks), dim3(256), 0, s, a);
+    else if (kx == kMaxKX)
+        DVGO_LAUNCH(K_MLP_BWD, mlp_bwd_f32_kernel<kMaxKX>, dim3(blocks), dim3(256), 0, s, a, pa);
+    else DVGO_LAUNCH(K_MLP_BWD, mlp_bwd_f32_kernel<0>, dim3(blocks), dim3(256), 0, s, a, pa);
 }
 
 }  // namespace

@@ -46,7 +46,7 @@ WsLayout ws_layout(int64_t B, int64_t cap, int64_t ncell) {
     };
     L.base = take(static_cast<size_t>(B) * kH * 4);
     L.pe = take(static_cast<size_t>(B) * 32 * 4);
-    L.w1p = take(kW1PackF32 * 4);
+    L.w1p = take(kW1PackF32Max * 4);
     L.w2p = take(kW2PackF32 * 4);
     L.w2tp = take(kW2PackF32 * 4);
     L.w1pb = take(kW1PackBF16 * 2);
@@ -58,7 +58,7 @@ WsLayout ws_layout(int64_t B, int64_t cap, int64_t ncell) {
     L.raw = take(static_cast<size_t>(cap) * 4);
     L.feat = take(static_cast<size_t>(cap) * kC * 4);
     L.col = take(static_cast<size_t>(cap) * 4 * 4);
-    L.partial = take(static_cast<size_t>(kMaxBwdBlocks) * kPStride * 4);
+    L.partial = take(static_cast<size_t>(kMaxBwdBlocks) * kPStrideMax * 4);
     L.cell_count = take(static_cast<size_t>(ncell + 1) * 4);
     L.cell_start = take(static_cast<size_t>(ncell + 1) * 4);
     L.scan_tmp = take(static_cast<size_t>((ncell + 1 + kScanPer - 1) / kScanPer + 1) * 8);
@@ -139,7 +139,9 @@ __device__ __forceinline__ int64_t live_count(const int64_t* n_kept, int64_t cap
 // ---------------------------------------------------------------------------
 // prep: per-ray encodings and first-layer per-ray part
 // ---------------------------------------------------------------------------
-// base[r][i] = b1[i] + sum_q W1[i][C+q] * PE(d_r)[q];  pe[r] = [PE(d_r) (27), 1, 0, 0, 0, 0]
+// base[r][i] = b1[i] + sum_q W1[i][view_col+q] * PE(d_r)[q];  pe[r] = [PE(d_r) (27), 1, 0, 0, 0, 0]
+// (view_col: the view part's first column, after the per-sample inputs;
+// w1_in: the row stride of W1)
 // Per-call preparation in one launch: the first kPackThreads/256 workgroups
 // pack the network's operands; each following workgroup takes kPrepRays
 // rays: 12 threads per ray evaluate its 24 sines and cosines once into LDS,
@@ -148,8 +150,9 @@ __device__ __forceinline__ int64_t live_count(const int64_t* n_kept, int64_t cap
 constexpr int kPrepRays = 16;   // rays per workgroup of prep_kernel
 __global__ __launch_bounds__(256) void prep_kernel(PackArgs pk, int pack, const float* __restrict__ rays_d, int B,
                                                    const float* __restrict__ w1, const float* __restrict__ b1,
-                                                   float* __restrict__ base, float* __restrict__ pe,
-                                                   int* __restrict__ zero, int64_t nzero, int zblocks) {
+                                                   int w1_in, int view_col, float* __restrict__ base,
+                                                   float* __restrict__ pe, int* __restrict__ zero, int64_t nzero,
+                                                   int zblocks) {
     constexpr int kPackBlocks = kPackThreads / 256;
     if (pack && static_cast<int>(blockIdx.x) < kPackBlocks) {
         pack_weights(pk, blockIdx.x * 256 + threadIdx.x);
@@ -194,7 +197,7 @@ __global__ __launch_bounds__(256) void prep_kernel(PackArgs pk, int pack, const 
     const float bi = w1 ? b1[i] : 0.0f;
     if (w1) {
         #pragma unroll
-        for (int q = 0; q < kPE; ++q) wv[q] = w1[i * kIn + kC + q];
+        for (int q = 0; q < kPE; ++q) wv[q] = w1[i * w1_in + view_col + q];
     }
     for (int rr = h; rr < kPrepRays; rr += 2) {
         const int r = r0 + rr;
@@ -976,26 +979,27 @@ struct NetAdam {
 };
 
 __global__ __launch_bounds__(1024) void reduce_partials_kernel(const float* __restrict__ partial, int nblk,
-                                                               float* __restrict__ out, const float* __restrict__ sq_err,
-                                                               int B, float* __restrict__ loss, NetAdam net) {
+                                                               int nparams, int pstride, float* __restrict__ out,
+                                                               const float* __restrict__ sq_err, int B,
+                                                               float* __restrict__ loss, NetAdam net) {
     __shared__ float sh[16][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int p = blockIdx.x * 64 + lane;
     static_assert(kMaxBwdBlocks <= 16 * 16, "a wavefront sums at most 16 partial rows");
     float s = 0.0f;
-    if (p < kMlpParams) {
+    if (p < nparams) {
         float v[16];
         #pragma unroll
         for (int u = 0; u < 16; ++u) {
             const int b = wave + 16 * u;
-            v[u] = b < nblk ? partial[static_cast<int64_t>(b) * kPStride + p] : 0.0f;
+            v[u] = b < nblk ? partial[static_cast<int64_t>(b) * pstride + p] : 0.0f;
         }
         #pragma unroll
         for (int u = 0; u < 16; ++u) s += v[u];
     }
     sh[wave][lane] = s;
     __syncthreads();
-    if (wave == 0 && p < kMlpParams) {
+    if (wave == 0 && p < nparams) {
         float t = 0.0f;
         for (int w = 0; w < 16; ++w) t += sh[w][lane];
         const float g = out[p] + t;
@@ -1041,6 +1045,7 @@ struct Common {
     char* ws;
     int64_t cap;
     int B;
+    float box_min[3], box_max[3];
 };
 
 int32_t validate(const dvgo_field* field, const dvgo_mlp* mlp, const float* rays_o, const float* rays_d,
@@ -1059,6 +1064,8 @@ int32_t validate(const dvgo_field* field, const dvgo_mlp* mlp, const float* rays
         if (field->feat_dtype != DVGO_F32 && field->feat_dtype != DVGO_BF16) return DVGO_E_DTYPE;
         if (mlp->hidden != kH) return DVGO_E_SHAPE;
         if (mlp->precision != DVGO_F32 && mlp->precision != DVGO_BF16) return DVGO_E_DTYPE;
+        if (mlp->pe_x != 0 && mlp->pe_x != kMaxKX) return DVGO_E_UNSUPPORTED;
+        if (mlp->pe_x != 0 && mlp->precision != DVGO_F32) return DVGO_E_UNSUPPORTED;
         if (!mlp->w1 || !mlp->b1 || !mlp->w2 || !mlp->b2 || !mlp->w3 || !mlp->b3) return DVGO_E_ARG;
     }
     if (B > 0 && (!rays_o || !rays_d || !t_near || !n_uniform || !perm || !ray_offset)) return DVGO_E_ARG;
@@ -1128,10 +1135,14 @@ int32_t run_prep(const Common& cm, const dvgo_mlp* mlp, hipStream_t s, int* zero
         pk.w3tpb = reinterpret_cast<uint16_t*>(cm.ws + cm.L.w3tpb);
         pk.w1tpb = reinterpret_cast<uint16_t*>(cm.ws + cm.L.w1tpb);
         pk.bf16 = mlp->precision == DVGO_BF16;
+        const bool xpe = mlp->pe_x == kMaxKX;
+        pk.w1_in = xpe ? NetLayout<kMaxKX>::kIn : kIn;
+        pk.w1_ns = xpe ? NetLayout<kMaxKX>::kS : kC;
+        pk.w1_q = xpe ? NetLayout<kMaxKX>::kQ1 : NetLayout<0>::kQ1;
         const int zblocks = zero ? grid_for(nzero, 256, dvgo::device_cu_count() * 4) : 0;
         const unsigned blocks = static_cast<unsigned>(kPackThreads / 256 + (cm.B + kPrepRays - 1) / kPrepRays + zblocks);
         DVGO_LAUNCH(K_RAY_BASE, prep_kernel, dim3(blocks), dim3(256), 0, s, pk, 1, cm.sa.rays_d, cm.B, mlp->w1,
-                    mlp->b1, base, pe, zero, nzero, zblocks);
+                    mlp->b1, pk.w1_in, pk.w1_ns, base, pe, zero, nzero, zblocks);
         if (int32_t st = dvgo::launch_status()) return st;
     } else if (zero) {
         DVGO_LAUNCH(K_CELL_SCAN, fill_int_kernel, dim3(grid_for(nzero, 256, dvgo::device_cu_count() * 8)), dim3(256),
@@ -1190,6 +1201,22 @@ MlpArgs make_mlp_args(const Common& cm, const dvgo_mlp* mlp, const int64_t* n_ke
     return ma;
 }
 
+PosArgs make_pos_args(const Common& cm) {
+    PosArgs pa;
+    pa.rays_o = cm.sa.rays_o;
+    pa.rays_d = cm.sa.rays_d;
+    pa.jitter = cm.sa.jitter;
+    pa.t_near = cm.sa.t_near;
+    pa.sample_k = cm.sa.sample_k;
+    pa.step = cm.sa.step;
+    for (int i = 0; i < 3; ++i) {
+        // box coordinates: centre and inverse half-extent, rounded once to float32
+        pa.pe_c[i] = 0.5f * (cm.box_min[i] + cm.box_max[i]);
+        pa.pe_ih[i] = 2.0f / (cm.box_max[i] - cm.box_min[i]);
+    }
+    return pa;
+}
+
 ComposeArgs make_compose(const Common& cm, const int32_t* perm, const int32_t* ray_offset, const int32_t* n_uniform,
                          const int64_t* n_kept, float act_shift, const float* bg, bool with_color) {
     ComposeArgs ca;
@@ -1225,6 +1252,10 @@ Common make_common(const dvgo_field* field, const float* rays_o, const float* ra
     cm.sa.sample_k = sample_k;
     cm.sa.step = step;
     cm.g = dvgo::make_grid(field->box);
+    for (int i = 0; i < 3; ++i) {
+        cm.box_min[i] = field->box.xyz_min[i];
+        cm.box_max[i] = field->box.xyz_max[i];
+    }
     cm.L = ws_layout(B, capacity, cell_count_of(field->box));
     cm.ws = static_cast<char*>(workspace);
     cm.cap = capacity;
@@ -1334,7 +1365,7 @@ int32_t render_bwd_impl(const dvgo_field* field, const dvgo_mlp* mlp, const floa
         if (int32_t st = run_prep(cm, mlp, s, bins.cell_count, bins.ncell + 1)) return st;
         if (int32_t st = run_gather(cm, field, mlp != nullptr, n_kept, s)) return st;
         if (mlp) {
-            launch_mlp_fwd(ma, dvgo::device_cu_count(), s);
+            launch_mlp_fwd(ma, make_pos_args(cm), mlp->pe_x, dvgo::device_cu_count(), s);
             if (int32_t st = dvgo::launch_status()) return st;
         }
     }
@@ -1362,7 +1393,7 @@ int32_t render_bwd_impl(const dvgo_field* field, const dvgo_mlp* mlp, const floa
         ma.rec = bins.rec;
         nblk = dvgo::device_cu_count();
         if (nblk > kMaxBwdBlocks) nblk = kMaxBwdBlocks;
-        launch_mlp_bwd(ma, nblk, s);
+        launch_mlp_bwd(ma, make_pos_args(cm), mlp->pe_x, nblk, s);
         if (int32_t st = dvgo::launch_status()) return st;
     }
     if (int32_t st = run_vertex(cm, field, bins, mlp != nullptr, mlp == nullptr, n_kept, grad_density, grad_feat, opt,
@@ -1371,8 +1402,12 @@ int32_t render_bwd_impl(const dvgo_field* field, const dvgo_mlp* mlp, const floa
     if (mlp) {
         NetAdam na{};
         if (net) na = *net;
-        DVGO_LAUNCH(K_REDUCE, reduce_partials_kernel, dim3((kMlpParams + 63) / 64), dim3(1024), 0, s,
-                    reinterpret_cast<const float*>(cm.ws + cm.L.partial), nblk, grad_mlp, sq_err, B, loss, na);
+        const bool xpe = mlp->pe_x == kMaxKX;
+        const int nparams = xpe ? NetLayout<kMaxKX>::kParams : kMlpParams;
+        const int pstride = xpe ? NetLayout<kMaxKX>::kPStride : kPStride;
+        DVGO_LAUNCH(K_REDUCE, reduce_partials_kernel, dim3((nparams + 63) / 64), dim3(1024), 0, s,
+                    reinterpret_cast<const float*>(cm.ws + cm.L.partial), nblk, nparams, pstride, grad_mlp, sq_err,
+                    B, loss, na);
         if (int32_t st = dvgo::launch_status()) return st;
     }
     return DVGO_OK;
@@ -1382,9 +1417,9 @@ int32_t render_bwd_impl(const dvgo_field* field, const dvgo_mlp* mlp, const floa
 
 extern "C" {
 
-int64_t dvgo_mlp_param_count(int32_t channels, int32_t hidden) {
-    if (channels < 0 || hidden < 0) return 0;
-    const int64_t in = channels + kPE;
+int64_t dvgo_mlp_param_count(int32_t channels, int32_t hidden, int32_t pe_x) {
+    if (channels < 0 || hidden < 0 || pe_x < 0) return 0;
+    const int64_t in = channels + (pe_x ? 3 + 6 * pe_x : 0) + kPE;
     return hidden * in + hidden + static_cast<int64_t>(hidden) * hidden + hidden + 3LL * hidden + 3;
 }
 
@@ -1419,7 +1454,7 @@ int32_t dvgo_render_fwd(const dvgo_field* field, const dvgo_mlp* mlp, const floa
     if (int32_t st = run_gather(cm, field, mlp != nullptr, n_kept, s)) return st;
     if (mlp && capacity > 0) {
         MlpArgs ma = make_mlp_args(cm, mlp, n_kept);
-        launch_mlp_fwd(ma, dvgo::device_cu_count(), s);
+        launch_mlp_fwd(ma, make_pos_args(cm), mlp->pe_x, dvgo::device_cu_count(), s);
         if (int32_t st = dvgo::launch_status()) return st;
     }
     ComposeArgs ca = make_compose(cm, perm, ray_offset, n_uniform, n_kept, field->act_shift, bg, mlp != nullptr);
@@ -1517,7 +1552,7 @@ int32_t dvgo_train_step(const dvgo_field* field, const dvgo_mlp* mlp, const floa
             return st;
         if (!mlp_opt) return DVGO_OK;
         return dvgo_adam_step(mlp_opt->param, grad_mlp, mlp_opt->m, mlp_opt->v, nullptr,
-                              dvgo_mlp_param_count(field->channels, mlp->hidden), mlp_opt->lr, mlp_opt->beta1,
+                              dvgo_mlp_param_count(field->channels, mlp->hidden, mlp->pe_x), mlp_opt->lr, mlp_opt->beta1,
                               mlp_opt->beta2, mlp_opt->eps, mlp_opt->t, stream);
     }
     GridAdamArgs o;
@@ -1530,7 +1565,7 @@ int32_t dvgo_train_step(const dvgo_field* field, const dvgo_mlp* mlp, const floa
     if (int32_t st = run_prep(cm, mlp, s, bins.cell_count, bins.ncell + 1)) return st;
     if (int32_t st = run_gather(cm, field, true, n_kept, s)) return st;
     MlpArgs ma = make_mlp_args(cm, mlp, n_kept);
-    launch_mlp_fwd(ma, dvgo::device_cu_count(), s);
+    launch_mlp_fwd(ma, make_pos_args(cm), mlp->pe_x, dvgo::device_cu_count(), s);
     if (int32_t st = dvgo::launch_status()) return st;
     float* sq_w = reinterpret_cast<float*>(ws + L.step_sqerr);
     ComposeArgs ca = make_compose(cm, perm, ray_offset, n_uniform, n_kept, field->act_shift, bg, true);

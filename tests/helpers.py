@@ -42,9 +42,13 @@ def mlp_flat_np(Ws, bs):
 
 
 def mlp_unflat(g, channels=12, hidden=128):
+    """Split a flat network vector; its size gives the first layer's input
+    width (39, or 72 with the encoded position)."""
+    n_in = (np.asarray(g).size - (hidden + hidden * hidden + hidden + 3 * hidden + 3)) // hidden
+    assert n_in in (channels + 27, channels + 33 + 27)
     i = 0
     out = []
-    for shp in [(hidden, channels + 27), (hidden,), (hidden, hidden), (hidden,), (3, hidden), (3,)]:
+    for shp in [(hidden, n_in), (hidden,), (hidden, hidden), (hidden,), (3, hidden), (3,)]:
         n = int(np.prod(shp))
         out.append(g[i:i + n].reshape(shp))
         i += n

@@ -42,7 +42,8 @@ def test_status_strings(lib):
 
 
 def test_param_counts(lib):
-    assert lib.dvgo_mlp_param_count(12, 128) == 128 * 39 + 128 + 128 * 128 + 128 + 3 * 128 + 3 == 22019
+    assert lib.dvgo_mlp_param_count(12, 128, 0) == 128 * 39 + 128 + 128 * 128 + 128 + 3 * 128 + 3 == 22019
+    assert lib.dvgo_mlp_param_count(12, 128, 5) == 128 * 72 + 128 + 128 * 128 + 128 + 3 * 128 + 3 == 26243
     assert lib.dvgo_prop_param_count() == 64 * 54 + 64 + 64 * 64 + 64 + 32 * 64 + 32
 
 
@@ -107,6 +108,14 @@ def test_host_validation_rejects_before_launch(lib):
     f.box = _lib.make_box((-1, -1, -1), (1, 1, 1), (4, 4, 4))
     m.precision = 7
     assert lib.dvgo_render_fwd(ctypes.byref(f), ctypes.byref(m), fake, fake, nul, *args[3:]) == -3
+    # the encoded-position network: k_x other than 5, or with bfloat16 products
+    m.precision = 0
+    m.pe_x = 3
+    assert lib.dvgo_render_fwd(ctypes.byref(f), ctypes.byref(m), fake, fake, nul, *args[3:]) == -6
+    m.pe_x = 5
+    m.precision = 1
+    assert lib.dvgo_render_fwd(ctypes.byref(f), ctypes.byref(m), fake, fake, nul, *args[3:]) == -6
+    m.pe_x = 0
     # scene: too many spheres
     assert lib.dvgo_scene_render(fake, fake, 1, ctypes.byref(box), fake, 100000, 0.01, 0.01, bg, fake, nul) == -1
     # proposal: bad selection fraction

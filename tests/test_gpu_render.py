@@ -64,14 +64,25 @@ def _gpu(P, coarse=None, morton=True, bf16=False):
 
 
 def _oracle(P, morton=True, coarse=None, bf16=False, rays=None):
+    """Oracle forward on the problem's rays (or the subset ``rays``); the
+    network's input width (39 or 72) selects the encoded-position variant."""
     o, d, j = P.rays.o, P.rays.d, P.rays.jitter
     if rays is not None:
         o, d, j = o[rays], d[rays], (j[rays] if j is not None else None)
     samp = O.sample_rays(o, d, j, P.box_min, P.box_max, P.step, P.max_samples, coarse=coarse, morton=morton)
     feat = O.bf16_round(P.feat) if bf16 else P.feat
-    prm = O.Params(P.density, feat, P.Ws, P.bs, P.box_min, P.box_max, P.act_shift, mlp_bf16=bf16)
+    prm = O.Params(P.density, feat, P.Ws, P.bs, P.box_min, P.box_max, P.act_shift, mlp_bf16=bf16,
+                   pe_x=5 if P.Ws[0].shape[1] == 72 else 0)
     ref = O.render_forward(prm, o, d, j, samp, P.step, P.bg)
     return samp, prm, ref, (o, d, j)
+
+
+def _with_position_encoding(P, seed):
+    """The paper's colour network that also takes PE_5 of the query position:
+    72 inputs [features, PE_5(u), PE_4(d)], Xavier weights from the seed."""
+    Ws, _ = synth.xavier_uniform_mlp(np.random.default_rng(seed), (72, 128, 128, 3))
+    P.Ws = [w.astype(F32) for w in Ws]
+    return P
 
 
 def _grads(api, grid, flat, s, out, g, P, bf16=False, gD=None, gA=None):
@@ -149,6 +160,28 @@ def test_render_backward_parity_tiny(gpu_lib, bf16, jitter):
     _, g = O.photo_loss(ref["rgb"], P.rays.target)
     gd, gf, gm = _grads(api, grid, flat, s, out, g, P, bf16)
     _check_backward(P, prm, ref, ro, gd, gf, gm, g, TOLBF if bf16 else TOL32)
+
+
+@pytest.mark.parametrize("jitter", [True, False])
+def test_render_position_encoding_parity_tiny(gpu_lib, jitter):
+    """The network with the encoded query position (Eq. fine_queries with
+    k_x = 5; float32 form): forward outputs and every gradient of the tiny
+    configuration against the oracle at the float32 bounds."""
+    from paper_2111_11215_amd import api
+    from paper_2111_11215_amd._lib import DVGO_F32
+    P = _with_position_encoding(_problem(2, jitter=jitter, bias=0.2), 61)
+    grid, flat, s = _gpu(P)
+    assert flat.numel() == 26243
+    out = api.render_fwd(grid, flat, s, P.bg, precision=DVGO_F32, want_seg_w=True, want_sample_w=True)
+    samp, prm, ref, ro = _oracle(P)
+    assert prm.pe_x == 5
+    n = int(samp["ray_offset"][-1])
+    _fwd_keys(out, ref, ("rgb", "depth", "acc", "log_t_end", "seg_w"), TOL32)
+    assert_close("sample_w", np_of(out["sample_w"])[:n], ref["sample_w"], TOL32)
+    ref["_samp"] = samp
+    _, g = O.photo_loss(ref["rgb"], P.rays.target)
+    gd, gf, gm = _grads(api, grid, flat, s, out, g, P)
+    _check_backward(P, prm, ref, ro, gd, gf, gm, g, TOL32)
 
 
 def test_render_backward_depth_acc_channels(gpu_lib):
@@ -229,13 +262,14 @@ def test_render_opaque_samples(gpu_lib):
     _check_backward(P, prm, ref, ro, gd, gf, gm, g, tol)
 
 
-@pytest.mark.parametrize("bf16", [False, True])
-def test_render_full_size_sampled_rays(gpu_lib, bf16):
+@pytest.mark.parametrize("bf16,pe_x", [(False, 0), (True, 0), (False, 5)])
+def test_render_full_size_sampled_rays(gpu_lib, bf16, pe_x):
     """Full configuration (160^3 grids with random values, 8192 rays, coarse
     mask of the sphere scene, launch configuration of the benchmark): the
     outputs of 256 sampled rays against the oracle on those rays, and the
     gradients with the loss gradient restricted to those rays, which the
-    oracle then computes exactly."""
+    oracle then computes exactly.  pe_x = 5: the network with the encoded
+    query position."""
     from paper_2111_11215_amd import api
     from paper_2111_11215_amd._lib import DVGO_BF16, DVGO_F32
     P = synth.full_config(0)
@@ -243,6 +277,8 @@ def test_render_full_size_sampled_rays(gpu_lib, bf16):
     P.density = rng.uniform(-1, 1, P.density.shape).astype(F32)
     P.feat = rng.uniform(-1, 1, P.feat.shape).astype(F32)
     P.act_shift = O.low_density_bias(synth.FULL_ALPHA_INIT, 2.0 / 159)
+    if pe_x:
+        P = _with_position_encoding(P, 62)
     raw = P.coarse_raw
     thr = O.coarse_raw_threshold(synth.FULL_TAU, P.step)
     bits = api.coarse_mask_build(to_dev(raw), P.box_min, P.box_max, float(thr))

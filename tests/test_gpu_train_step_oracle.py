@@ -105,7 +105,8 @@ def _run_case(P, coarse_gpu, coarse_ref, bf16, active, t, lr_grid, lr_mlp, momen
                          coarse=coarse_ref)
     assert got["n_kept"] == int(samp["ray_offset"][-1])
     feat = O.bf16_round(P.feat) if bf16 else P.feat
-    prm = O.Params(P.density, feat, P.Ws, P.bs, P.box_min, P.box_max, P.act_shift, mlp_bf16=bf16)
+    prm = O.Params(P.density, feat, P.Ws, P.bs, P.box_min, P.box_max, P.act_shift, mlp_bf16=bf16,
+                   pe_x=5 if P.Ws[0].shape[1] == 72 else 0)
     ref = O.render_forward(prm, P.rays.o, P.rays.d, P.rays.jitter, samp, P.step, P.bg)
     L, g = O.photo_loss(ref["rgb"], P.rays.target)
     dc_extra, gt = None, None
@@ -209,3 +210,16 @@ def test_train_step_with_auxiliary_losses(gpu_lib, bf16, aux):
     the activity mask, against the oracle's losses and adjoint."""
     P = synth.tiny_config(1, jitter=True, n_rays=4096)
     _run_case(P, None, None, bf16, True, 5, 0.1, 1e-3, True, seed=51 + bf16, aux=aux)
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("aux", [None, (1e-2, 1e-3)])
+def test_train_step_with_position_encoding(gpu_lib, aux):
+    """The paper's fine network with the encoded query position (72 inputs,
+    float32), alone and with the auxiliary losses at the paper's weights (the
+    paper's whole fine objective): the tiny batch at t = 5 from seeded
+    moments with the activity mask, against the oracle."""
+    P = synth.tiny_config(2, jitter=True, n_rays=4096)
+    Ws, _ = synth.xavier_uniform_mlp(np.random.default_rng(71), (72, 128, 128, 3))
+    P.Ws = [w.astype(F32) for w in Ws]
+    _run_case(P, None, None, False, True, 5, 0.1, 1e-3, True, seed=61, aux=aux)
