@@ -468,7 +468,10 @@ int32_t dvgo_adam_step(float* p, float* g, float* m, float* v, uint16_t* shadow_
  * term at a time in that order; the chosen q are added in the order chosen
  * until the sum reaches cum_frac*pred_mass (float32 product).
  * cum_frac in (0, 1], min_mass in [0, 1], else DVGO_E_ARG.
- * valid/t_near come from dvgo_sample_rays. */
+ * valid/t_near come from dvgo_sample_rays; with t_near (and valid) NULL the
+ * call clips each ray against box itself with the sampler's recipe, which
+ * gives the same t_near and validity bit for bit (one launch instead of a
+ * separate clip).  valid without t_near is DVGO_E_ARG. */
 int32_t dvgo_proposal_fwd(const float* rays_o, const float* rays_d, const float* t_near,
                           const uint8_t* valid, int32_t B, const dvgo_box* box /*host*/,
                           const dvgo_prop* prop /*host*/, float cum_frac, float min_mass,
@@ -478,7 +481,8 @@ int32_t dvgo_proposal_fwd(const float* rays_o, const float* rays_d, const float*
  * the batch size B (invalid rays contribute nothing), with target
  * p = (seg_w[r][0..31], exp(log_t_end[r])) from a density-only render;
  * dL/dz_s = (q_s - p_s)/B.  grad_prop (flat, dvgo_prop_param_count) is
- * ACCUMULATED; loss (device float or NULL) is overwritten. */
+ * ACCUMULATED; loss (device float or NULL) is overwritten.  t_near/valid
+ * as in dvgo_proposal_fwd (NULL: clipped here). */
 int32_t dvgo_proposal_bwd(const float* rays_o, const float* rays_d, const float* t_near,
                           const uint8_t* valid, int32_t B, const dvgo_box* box /*host*/,
                           const dvgo_prop* prop /*host*/, const float* seg_w,

@@ -444,6 +444,24 @@ def proposal_fwd(s: Samples, box_min, box_max, prop_flat: Optional[torch.Tensor]
     return logits, mass, mask
 
 
+def proposal_fwd_rays(rays_o: torch.Tensor, rays_d: torch.Tensor, box_min, box_max, prop_flat: torch.Tensor,
+                      cum_frac=0.99, min_mass=0.9):
+    """proposal_fwd on bare rays: the call clips them against the box itself
+    (the sampler's recipe), so no clip pass runs before it."""
+    lib = load()
+    dev = rays_o.device
+    B = rays_o.shape[0]
+    logits = torch.empty((B, NSEG), dtype=torch.float32, device=dev)
+    mass = torch.empty(B, dtype=torch.float32, device=dev)
+    mask = torch.empty(B, dtype=torch.int32, device=dev)
+    box = make_box(box_min, box_max)
+    prop = prop_struct(prop_flat)
+    check("dvgo_proposal_fwd", lib.dvgo_proposal_fwd(
+        _ptr(rays_o), _ptr(rays_d), None, None, B, ctypes.byref(box), ctypes.byref(prop), float(cum_frac),
+        float(min_mass), _ptr(logits), _ptr(mass), _ptr(mask), _stream(dev)))
+    return logits, mass, mask
+
+
 def proposal_bwd(s: Samples, box_min, box_max, prop_flat: torch.Tensor, seg_w: torch.Tensor,
                  log_t_end: torch.Tensor, grad_prop: torch.Tensor):
     lib = load()

@@ -104,6 +104,32 @@ __device__ __forceinline__ void recipe_x(const float o[3], const float d[3], flo
     }
 }
 
+// Slab clip of the ray o + t d against the box [mn, mx] (float32 recipe, no
+// contraction): per axis with d_i != 0, t0 = (mn_i - o_i) * (1/d_i) and
+// t1 = (mx_i - o_i) * (1/d_i); a zero component misses unless o_i lies in
+// the slab.  t_near = max(0, max_i min(t0, t1)), t_far = min_i max(t0, t1);
+// the ray is valid iff it does not miss and t_near < t_far.
+__device__ __forceinline__ bool recipe_slab(const float o[3], const float d[3], const float mn[3], const float mx[3],
+                                            float* t_near, float* t_far) {
+#pragma clang fp contract(off)
+    float te = -INFINITY, tx = INFINITY;
+    bool miss = false;
+    for (int i = 0; i < 3; ++i) {
+        if (d[i] == 0.0f) {
+            if (o[i] < mn[i] || o[i] > mx[i]) miss = true;
+        } else {
+            const float inv = 1.0f / d[i];
+            const float t0 = (mn[i] - o[i]) * inv;
+            const float t1 = (mx[i] - o[i]) * inv;
+            te = fmaxf(te, fminf(t0, t1));
+            tx = fminf(tx, fmaxf(t0, t1));
+        }
+    }
+    *t_near = fmaxf(te, 0.0f);
+    *t_far = tx;
+    return !miss && (*t_near < tx);
+}
+
 // Cell of the coarse grid holding x: clamp(floor((x-min)*scale), 0, n-2).
 __device__ __forceinline__ int recipe_cell(const dvgo::GridArgs& g, const float x[3]) {
 #pragma clang fp contract(off)

@@ -105,9 +105,8 @@ __device__ __forceinline__ bf16x8 frag_cols(const float* w, int st, int col, int
 // and every value is rounded to bfloat16 before the first layer, so the
 // hardware sine and cosine (absolute error below 1e-6 here) replace the
 // full-range library sincos and its range reduction.
-__device__ void encode(const PropArgs& a, int r, float e[kIn]) {
+__device__ void encode(const PropArgs& a, int r, float tn, float e[kIn]) {
     float d[3], u[3];
-    const float tn = a.t_near[r];
     for (int i = 0; i < 3; ++i) {
         d[i] = a.rays_d[3 * r + i];
         const float x0 = a.rays_o[3 * r + i] + tn * d[i];
@@ -135,11 +134,30 @@ struct PropFwd {
     f32x16 h1[2], h2[2], z;
 };
 
-// Forward of the 32 rays of a wave (ray = lane % 32).
-__device__ void prop_forward(const PropArgs& a, int r, bool ray_ok, int lane, PropFwd& f) {
+// Box entry t_near of ray r and whether the ray meets the box: the caller's
+// clip, or (no t_near given) the sampler's slab clip of the same box, which
+// gives the same bits (t_near 0 for a ray that misses, as the sampler
+// stores it).
+__device__ __forceinline__ bool ray_entry(const PropArgs& a, int r, float* tn) {
+    if (a.t_near) {
+        *tn = a.t_near[r];
+        return !a.valid || a.valid[r];
+    }
+    float o[3], d[3], tx;
+    for (int i = 0; i < 3; ++i) {
+        o[i] = a.rays_o[3 * r + i];
+        d[i] = a.rays_d[3 * r + i];
+    }
+    const bool v = dvgo_dev::recipe_slab(o, d, a.mn, a.mx, tn, &tx);
+    if (!v) *tn = 0.0f;
+    return v;
+}
+
+// Forward of the 32 rays of a wave (ray = lane % 32); tn: the ray's t_near.
+__device__ void prop_forward(const PropArgs& a, int r, bool ray_ok, float tn, int lane, PropFwd& f) {
     const int h = lane >> 5, m = lane & 31;
     float e[kIn];
-    if (ray_ok) encode(a, r, e);
+    if (ray_ok) encode(a, r, tn, e);
     #pragma unroll
     for (int st = 0; st < 4; ++st)
         #pragma unroll
@@ -280,10 +298,12 @@ __global__ __launch_bounds__(64) void proposal_fwd_kernel(PropArgs a, int run_ne
     const int m = lane & 31, h = lane >> 5;
     const int r = (blockIdx.x * kWaves + wave) * kRaysPerWave + m;
     const bool ray_ok = r < a.B;
+    float tn = 0.0f;
+    const bool meets = ray_ok && ray_entry(a, r, &tn);
     float z[16];
     if (run_net) {
         PropFwd f;
-        prop_forward(a, r, ray_ok, lane, f);
+        prop_forward(a, r, ray_ok, tn, lane, f);
         #pragma unroll
         for (int rr = 0; rr < 16; ++rr) {
             z[rr] = f.z[rr];
@@ -296,7 +316,7 @@ __global__ __launch_bounds__(64) void proposal_fwd_kernel(PropArgs a, int run_ne
     float pm;
     uint32_t mask = select_mask_pair(z, h, cum_frac, min_mass, &pm);
     if (ray_ok && h == 0) {
-        if (a.valid && !a.valid[r]) mask = 0xFFFFFFFFu;
+        if (!meets) mask = 0xFFFFFFFFu;
         if (pred_mass) pred_mass[r] = pm;
         if (seg_mask) seg_mask[r] = mask;
     }
@@ -318,9 +338,10 @@ __global__ __launch_bounds__(64) void proposal_bwd_kernel(PropArgs a, const floa
     const int wglob = blockIdx.x * kWaves + wave;
     const int r = wglob * kRaysPerWave + m;
     const bool in_batch = r < a.B;
-    const bool ok = in_batch && (!a.valid || a.valid[r]);
+    float tn = 0.0f;
+    const bool ok = in_batch && ray_entry(a, r, &tn);
     PropFwd f;
-    prop_forward(a, r, in_batch, lane, f);
+    prop_forward(a, r, in_batch, tn, lane, f);
     // softmax over the 32 logits and the implicit 0, split over the two halves
     float mx = 0.0f;
     #pragma unroll
@@ -470,12 +491,14 @@ __global__ __launch_bounds__(1024) void proposal_reduce_kernel(const float* __re
     }
 }
 
+// t_near NULL (then valid NULL too): the kernels clip each ray themselves.
 bool fill_args(PropArgs& a, const float* rays_o, const float* rays_d, const float* t_near, const uint8_t* valid,
                int32_t B, const dvgo_box* box, const dvgo_prop* prop) {
     if (B < 0 || !box) return false;
     for (int i = 0; i < 3; ++i)
         if (!(box->xyz_max[i] > box->xyz_min[i])) return false;
-    if (B > 0 && (!rays_o || !rays_d || !t_near)) return false;
+    if (B > 0 && (!rays_o || !rays_d)) return false;
+    if (!t_near && valid) return false;
     a.rays_o = rays_o;
     a.rays_d = rays_d;
     a.t_near = t_near;

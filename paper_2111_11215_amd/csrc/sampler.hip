@@ -34,23 +34,9 @@ struct Clip {
 __device__ __forceinline__ Clip clip_ray(const float o[3], const float d[3], float p, const BoxF& box, float step,
                                          int max_samples) {
 #pragma clang fp contract(off)
-    float te = -INFINITY, tx = INFINITY;
-    bool miss = false;
-    for (int i = 0; i < 3; ++i) {
-        if (d[i] == 0.0f) {
-            if (o[i] < box.mn[i] || o[i] > box.mx[i]) miss = true;
-        } else {
-            const float inv = 1.0f / d[i];
-            const float t0 = (box.mn[i] - o[i]) * inv;
-            const float t1 = (box.mx[i] - o[i]) * inv;
-            te = fmaxf(te, fminf(t0, t1));
-            tx = fminf(tx, fmaxf(t0, t1));
-        }
-    }
     Clip c;
-    c.tn = fmaxf(te, 0.0f);
-    c.tx = tx;
-    c.v = !miss && (c.tn < tx);
+    c.v = recipe_slab(o, d, box.mn, box.mx, &c.tn, &c.tx);
+    const float tx = c.tx;
     c.n = 0;
     if (c.v) {
         // estimate, then settle on the exact prefix length (t_k is monotone in k)

@@ -100,9 +100,7 @@ def evaluated_per_step(model: train.FineModel, batches, prop: train.ProposalMode
         if prop is None:
             s = model.sample(b.o, b.d, b.j)
         else:
-            s0 = api.sample_rays(b.o, b.d, b.j, model.grid.box_min, model.grid.box_max, model.cfg.step,
-                                 model.cfg.max_samples, clip_only=True)
-            _, _, mask = prop.masks(s0)
+            _, _, mask = prop.masks_rays(b.o, b.d)
             s = model.sample(b.o, b.d, b.j, seg_mask=mask)
         tot += int(s.n_kept.item())
     return tot / n
@@ -151,9 +149,7 @@ def proposal_render_psnr(model: train.FineModel, prop: train.ProposalModel, view
         for a in range(0, v.o.shape[0], 1 << 16):
             b = min(a + (1 << 16), v.o.shape[0])
             o, d = v.o[a:b].contiguous(), v.d[a:b].contiguous()
-            s0 = api.sample_rays(o, d, None, model.grid.box_min, model.grid.box_max, model.cfg.step,
-                                 model.cfg.max_samples, clip_only=True)
-            _, _, mask = prop.masks(s0)
+            _, _, mask = prop.masks_rays(o, d)
             s = model.sample(o, d, None, seg_mask=mask, morton=False)
             out[a:b] = model.render(s, want_depth_acc=False)["rgb"]
         mse = float(((out - ref) ** 2).mean().item())

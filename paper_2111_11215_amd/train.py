@@ -207,6 +207,11 @@ class ProposalModel:
     def masks(self, s: api.Samples):
         return api.proposal_fwd(s, self.box_min, self.box_max, self.flat, self.cum_frac, self.min_mass)
 
+    def masks_rays(self, rays_o, rays_d):
+        """Segment masks of bare rays (the call clips them itself)."""
+        return api.proposal_fwd_rays(rays_o, rays_d, self.box_min, self.box_max, self.flat, self.cum_frac,
+                                     self.min_mass)
+
     def learn(self, model: "FineModel", rays_o, rays_d, jitter) -> torch.Tensor:
         """One proposal update from a density-only pass on the given rays."""
         s = model.sample(rays_o, rays_d, jitter)
@@ -220,13 +225,12 @@ class ProposalModel:
 
 def proposal_train_step(model: FineModel, prop: ProposalModel, rays_o, rays_d, target, jitter=None,
                         learn: bool = True) -> dict:
-    """One iteration of the proposal form: clip (no list), predict
-    segment masks, sample only the selected segments (all of them where the
-    proposal falls back), render / adjoint / Adam, then (every learn_every-th
-    iteration) update the proposal on the first 1/sub of the batch."""
-    s0 = api.sample_rays(rays_o, rays_d, jitter, model.grid.box_min, model.grid.box_max, model.cfg.step,
-                         model.cfg.max_samples, clip_only=True)
-    _, mass, mask = prop.masks(s0)
+    """One iteration of the proposal form: predict segment masks (the
+    proposal call clips the rays itself), sample only the selected segments
+    (all of them where the proposal falls back), render / adjoint / Adam,
+    then (every learn_every-th iteration) update the proposal on the first
+    1/sub of the batch."""
+    _, mass, mask = prop.masks_rays(rays_o, rays_d)
     res = model.train_step(rays_o, rays_d, target, jitter, seg_mask=mask)
     prop.calls += 1
     if learn and (prop.calls - 1) % prop.learn_every == 0:

@@ -60,13 +60,20 @@ def kink_budget(prm, ref, grad_rgb, zeta_rel, feat_shape, box_min, box_max, dc_e
 
     A hidden unit whose oracle pre-activation z satisfies |z| <= zeta_rel *
     (sum of |terms| of its dot product + |bias|) may legitimately take the
-    other branch in a float32 (or bfloat16) evaluation.  For every sample
-    holding such a unit, any two choices of masks change that sample's
-    feature gradient by at most 2*U, U = |dz3| |W3| |W2| |W1f| (absolute
-    values bound every masked product), and its weight-gradient
-    contributions by at most 2x the norms bounded the same way.  Returns
-    (per-grid-entry feature budget, per-tensor weight budgets dict, fraction
-    of ambiguous samples)."""
+    other branch in a float32 (or bfloat16) evaluation; only such units can
+    flip.  With absolute adjoint magnitudes that hold for any masks,
+    a2 = |dz3| |W3| (layer-2 units) and a1 = a2 |W2| (layer-1 units), any
+    set of flips among a sample's ambiguous units changes
+      dz2 by at most a2 on the ambiguous layer-2 units J (zero elsewhere),
+      dz1 by at most D1 = (a2 . 1_J) |W2| + a1 . 1_I (I: ambiguous layer-1
+        units; the first term is the change of dh1 that J's flips cause),
+    hence that sample's contributions to dW1 and db1 by ||D1|| ||x|| and
+    ||D1||, to dW2 and db2 by ||a2 . 1_J|| ||h1|| and ||a2 . 1_J||, and its
+    feature gradient by D1 |W1f| per channel (the forward's change of a
+    flipped unit's output is |z| <= zeta_rel of its terms, below the other
+    bounds, and is not counted).  Budgets are twice these (either branch),
+    summed over samples.  Returns (per-grid-entry feature budget, per-tensor
+    weight budgets dict, fraction of samples with an ambiguous unit)."""
     import oracle as O
     cache = ref["cache"]
     mc = cache["mcache"]
@@ -75,28 +82,29 @@ def kink_budget(prm, ref, grad_rgb, zeta_rel, feat_shape, box_min, box_max, dc_e
     x, h1 = mc["x"], mc["h1"]
     s1 = np.abs(x) @ np.abs(W1).T + np.abs(b1)
     s2 = np.abs(h1) @ np.abs(W2).T + np.abs(b2)
-    amb = (np.abs(mc["z1"]) <= zeta_rel * s1).any(1) | (np.abs(mc["z2"]) <= zeta_rel * s2).any(1)
+    amb1 = np.abs(mc["z1"]) <= zeta_rel * s1
+    amb2 = np.abs(mc["z2"]) <= zeta_rel * s2
     g = np.asarray(grad_rgb, np.float64)[np.asarray(ref_perm_slots(ref))]
     dc = cache["w"][:, None] * g
     if dc_extra is not None:     # direct colour gradients (the per-point rgb loss)
         dc = np.abs(dc) + np.abs(dc_extra)
     c = mc["c"]
     dz3 = np.abs(dc * c * (1 - c))
-    dh2 = dz3 @ np.abs(W3)
-    dh1 = dh2 @ np.abs(W2)
-    U = dh1 @ np.abs(W1[:, :feat_shape[-1]])
-    Ua = np.where(amb[:, None], 2.0 * U, 0.0)
-    grid_budget = O.interp_scatter(feat_shape, cache["x"], box_min, box_max, Ua)
-    nx = np.linalg.norm(x, axis=1)
-    nh1 = np.linalg.norm(h1, axis=1)
+    a2 = dz3 @ np.abs(W3)
+    a1 = a2 @ np.abs(W2)
+    d2 = a2 * amb2
+    d1 = d2 @ np.abs(W2) + a1 * amb1
+    df = d1 @ np.abs(W1[:, :feat_shape[-1]])
+    grid_budget = O.interp_scatter(feat_shape, cache["x"], box_min, box_max, 2.0 * df)
+    n1, n2 = np.linalg.norm(d1, axis=1), np.linalg.norm(d2, axis=1)
     w_b = {
-        "W1": 2.0 * np.sum(np.linalg.norm(dh1, axis=1)[amb] * nx[amb]),
-        "b1": 2.0 * np.sum(np.linalg.norm(dh1, axis=1)[amb]),
-        "W2": 2.0 * np.sum(np.linalg.norm(dh2, axis=1)[amb] * nh1[amb]),
-        "b2": 2.0 * np.sum(np.linalg.norm(dh2, axis=1)[amb]),
+        "W1": 2.0 * np.sum(n1 * np.linalg.norm(x, axis=1)),
+        "b1": 2.0 * np.sum(n1),
+        "W2": 2.0 * np.sum(n2 * np.linalg.norm(h1, axis=1)),
+        "b2": 2.0 * np.sum(n2),
         "W3": 0.0, "b3": 0.0,
     }
-    return grid_budget, w_b, float(amb.mean())
+    return grid_budget, w_b, float((amb1.any(1) | amb2.any(1)).mean())
 
 
 def ref_perm_slots(ref):

@@ -121,6 +121,9 @@ def test_host_validation_rejects_before_launch(lib):
     # proposal: bad selection fraction
     assert lib.dvgo_proposal_fwd(fake, fake, fake, nul, 1, ctypes.byref(box), nul, 1.5, 0.9, fake, nul, nul,
                                  nul) == -1
+    # proposal: a validity mask without the t_near it belongs to
+    assert lib.dvgo_proposal_fwd(fake, fake, nul, fake, 1, ctypes.byref(box), nul, 0.99, 0.9, fake, nul, nul,
+                                 nul) == -1
     # fused backward + grid Adam: missing optimiser state, bad beta, misaligned
     # feature pointer, then a shape error from the shared validation
     ga = _lib.GridAdam(16, 16, 16, 16, 16, 16, None, 0.1, 0.9, 0.999, 1e-8, 1)

@@ -86,3 +86,33 @@ def test_proposal_forward_backward_bf16(gpu_lib):
         nw, _ = report(name, g[off:off + n].reshape(ref_t.shape), ref_t)
         assert nw <= 1e-3, name
         off += n
+
+
+def test_proposal_clips_rays_itself_bit_identically(gpu_lib):
+    """dvgo_proposal_fwd without t_near clips each ray itself: logits, mass
+    and masks equal those of the call fed by the sampler's clip, bit for bit,
+    on rays that miss the box, start inside it, graze it or run along an
+    axis; the backward without t_near equals the backward with it."""
+    import torch
+    from paper_2111_11215_amd import api
+    P = synth.tiny_config(2, n_rays=1000)
+    o, d = P.rays.o.copy(), P.rays.d.copy()
+    o[:8] = [[5, 5, 5], [0.2, 0.1, -0.3], [-3, 1.0, 0.2], [-3, 0.3, 0.2], [0.5, -3, 0.5], [0, 0, 3], [-3, 1, 1],
+             [0.99, -0.99, 0.0]]
+    d[:8] = [[1, 0, 0], [0, 0, 1], [1, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, -1], [1, 0, 0], [-0.6, 0.8, 0.0]]
+    s = api.sample_rays(to_dev(o), to_dev(d), None, P.box_min, P.box_max, P.step, P.max_samples, clip_only=True)
+    _, _, flat = _prop_weights(5)
+    ft = to_dev(flat)
+    z0, m0, k0 = api.proposal_fwd(s, P.box_min, P.box_max, ft, cum_frac=0.9, min_mass=0.2)
+    z1, m1, k1 = api.proposal_fwd_rays(s.rays_o, s.rays_d, P.box_min, P.box_max, ft, cum_frac=0.9, min_mass=0.2)
+    assert np.array_equal(np_of(z0), np_of(z1))
+    assert np.array_equal(np_of(m0), np_of(m1))
+    assert np.array_equal(np_of(k0), np_of(k1))
+    assert (np_of(k0).view(np.uint32) != 0xFFFFFFFF).any()
+    seg_w = to_dev(np.full((1000, 32), 1.0 / 64, F32))
+    lte = to_dev(np.full(1000, np.log(0.5), F32))
+    g0, g1 = torch.zeros_like(ft), torch.zeros_like(ft)
+    l0 = api.proposal_bwd(s, P.box_min, P.box_max, ft, seg_w, lte, g0)
+    s_bare = api.Samples(**{**s.__dict__, "t_near": None, "valid": None})
+    l1 = api.proposal_bwd(s_bare, P.box_min, P.box_max, ft, seg_w, lte, g1)
+    assert np.array_equal(np_of(g0), np_of(g1)) and np.array_equal(np_of(l0), np_of(l1))
