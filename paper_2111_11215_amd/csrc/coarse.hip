@@ -9,7 +9,11 @@
 //                       then the adjoint walked from the ray's end with the
 //                       transmittance recomputed by prefix sums as in the
 //                       forward, scattering the grid gradients with float
-//                       atomics (100^3 grids: few samples per vertex)
+//                       atomics aggregated over the wavefront: consecutive
+//                       samples of a ray in the same cell share its eight
+//                       corners, so their contributions are summed across
+//                       lanes first and the run's first lane adds them
+//                       (100^3 grids: few samples per vertex)
 //   loss_reduce         the per-ray losses summed in a fixed order
 //   view_count / scale  Prior 2: per-vertex view counts and n_j / n_max
 //   adam_scaled         Adam with a per-element learning-rate factor
@@ -55,10 +59,23 @@ __device__ __forceinline__ float sigmoid_c(float x) { return 1.0f / (1.0f + expf
 // One sample's interpolated raw density and colour pre-activation, with the
 // corner indices and weights for the scatter.
 struct CSample {
-    int64_t corner[8];
+    int64_t corner[8];   // corner[0] is the cell's base vertex
     float w[8];
     float raw, pre[3], t;
 };
+
+// Sum of v over the lanes from this one to the end of its run of equal
+// keys (runs are contiguous: a ray's samples in one cell are consecutive,
+// and a lane without a sample has a key of its own).
+__device__ __forceinline__ float run_suffix_sum(float v, int64_t key, int lane) {
+    #pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const float ov = __shfl_down(v, off, 64);
+        const int64_t ok = __shfl_down(key, off, 64);
+        if (lane + off < 64 && ok == key) v += ov;
+    }
+    return v;
+}
 
 __device__ __forceinline__ void coarse_sample(const CoarseArgs& a, const float o[3], const float d[3], float tn, float p,
                                               int k, CSample& cs) {
@@ -178,16 +195,29 @@ __global__ __launch_bounds__(256) void coarse_step_kernel(CoarseArgs a) {
             dsig += gC[ch] * (Tafter * c[ch] - (S[ch] + sfx_ex));
             tot[ch] = lane_value(sfx, 0);
         }
-        if (ok) {
-            const float draw = a.step * dsig * sigmoid_c(cs.raw + a.act_shift);
-            float dpre[3];
-            for (int ch = 0; ch < 3; ++ch) {
-                const float dc = w * gC[ch] + ptk * w * (c[ch] - tgt[ch]);
-                dpre[ch] = dc * c[ch] * (1.0f - c[ch]);
+        {
+            float draw = 0.0f, dpre[3] = {0.0f, 0.0f, 0.0f};
+            if (ok) {
+                draw = a.step * dsig * sigmoid_c(cs.raw + a.act_shift);
+                for (int ch = 0; ch < 3; ++ch) {
+                    const float dc = w * gC[ch] + ptk * w * (c[ch] - tgt[ch]);
+                    dpre[ch] = dc * c[ch] * (1.0f - c[ch]);
+                }
             }
+            // every lane takes part in the shuffles; a lane without a sample
+            // has a key of its own and contributes zeros
+            const int64_t key = ok ? cs.corner[0] : -1 - static_cast<int64_t>(lane);
+            const int64_t prev = __shfl_up(key, 1, 64);
+            const bool head = ok && (lane == 0 || prev != key);
             for (int k = 0; k < 8; ++k) {
-                atomicAdd(a.grad_density + cs.corner[k], cs.w[k] * draw);
-                for (int ch = 0; ch < 3; ++ch) atomicAdd(a.grad_rgb + 3 * cs.corner[k] + ch, cs.w[k] * dpre[ch]);
+                const float wk = ok ? cs.w[k] : 0.0f;
+                const float gd = run_suffix_sum(wk * draw, key, lane);
+                float gr[3];
+                for (int ch = 0; ch < 3; ++ch) gr[ch] = run_suffix_sum(wk * dpre[ch], key, lane);
+                if (head) {
+                    atomicAdd(a.grad_density + cs.corner[k], gd);
+                    for (int ch = 0; ch < 3; ++ch) atomicAdd(a.grad_rgb + 3 * cs.corner[k] + ch, gr[ch]);
+                }
             }
         }
         for (int ch = 0; ch < 3; ++ch) S[ch] += tot[ch];

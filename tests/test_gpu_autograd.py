@@ -7,7 +7,7 @@ loss does not use arrive as None and are skipped."""
 import numpy as np
 import pytest
 
-from tests.helpers import assert_close, np_of, report, to_dev
+from tests.helpers import assert_close, np_of, to_dev
 from tests.test_gpu_render import TOL32, _check_backward, _gpu, _oracle, _problem
 
 pytestmark = pytest.mark.gpu
@@ -59,5 +59,5 @@ def test_autograd_rgb_only_equals_direct_adjoint(gpu_lib):
     api.render_bwd(grid, flat, s, out["log_t_end"], torch.full_like(out["rgb"], 0.5), gd, gf, gm, P.bg)
     assert torch.equal(rgb.detach(), out["rgb"])
     assert torch.equal(m.grad, gm)
-    assert report("grad_density", np_of(d.grad), np_of(gd))[0] <= 1e-6
-    assert report("grad_feat", np_of(f.grad), np_of(gf))[0] <= 1e-6
+    assert_close("grad_density", np_of(d.grad), np_of(gd), 1e-6)
+    assert_close("grad_feat", np_of(f.grad), np_of(gf), 1e-6)

@@ -8,7 +8,7 @@ sample in the batch every vertex takes the zero-gradient step."""
 import numpy as np
 import pytest
 
-from tests.helpers import assert_close, np_of, report, to_dev
+from tests.helpers import assert_close, np_of, to_dev
 from tests.test_gpu_render import _gpu, _problem
 
 pytestmark = pytest.mark.gpu
@@ -61,7 +61,7 @@ def test_fused_backward_adam_equals_separate(gpu_lib, bf16):
     assert torch.equal(gm, gmb)
     for name, p0, pa, pb in (("density", grid.density, ga.density, gb.density), ("feat", grid.feat, ga.feat,
                                                                                    gb.feat)):
-        assert report(f"{name} update", np_of(pb - p0), np_of(pa - p0))[0] <= 1e-5, name
+        assert_close(f"{name} update", np_of(pb - p0), np_of(pa - p0), 1e-5)
     for name, a, b in (("m density", mDa, mDb), ("v density", vDa, vDb), ("m feat", mFa, mFb), ("v feat", vFa, vFb)):
         assert_close(name, np_of(b), np_of(a), 1e-5)
     if bf16:
@@ -132,7 +132,7 @@ def test_train_step_equals_separate_calls(gpu_lib, bf16):
     assert torch.equal(gma, gmb)
     for name, p0, pa, pb in (("density", grid.density, ga.density, gb.density),
                              ("feat", grid.feat, ga.feat, gb.feat)):
-        assert report(f"{name} update", np_of(pb - p0), np_of(pa - p0))[0] <= 1e-5, name
+        assert_close(f"{name} update", np_of(pb - p0), np_of(pa - p0), 1e-5)
     for name, a, b in (("m density", mDa, mDb), ("v density", vDa, vDb), ("m feat", mFa, mFb), ("v feat", vFa, vFb)):
         assert_close(name, np_of(b), np_of(a), 1e-5)
     if bf16:
@@ -198,14 +198,14 @@ def test_activity_mask_skips_idle_vertices_exactly(gpu_lib, bf16):
     for name, p0, pa, pb in pairs:
         a, b, z = np_of(pa).reshape(nv, -1), np_of(pb).reshape(nv, -1), np_of(p0).reshape(nv, -1)
         assert np.array_equal(a[idle], z[idle]) and np.array_equal(b[idle], z[idle]), name
-        assert report(f"{name} update", (b - z), (a - z))[0] <= 1e-6, name
+        assert_close(f"{name} update", (b - z), (a - z), 1e-6)
     for name, a, b in zip(("m density", "v density", "m feat", "v feat"), sa, sb):
-        assert report(name, np_of(b), np_of(a))[0] <= 1e-6, name
+        assert_close(name, np_of(b), np_of(a), 1e-6)
         assert np.all(np_of(b).reshape(nv, -1)[idle] == 0), name
     if bf16:
         assert np.array_equal(np_of(gb.feat_shadow).view(np.uint16), _bf16_bits(np_of(gb.feat)))
-        assert np.array_equal(np_of(gb.feat_shadow).view(np.uint16), np_of(ga.feat_shadow).view(np.uint16)) or \
-            report("shadow", np_of(gb.feat), np_of(ga.feat))[0] <= 1e-6
+        if not np.array_equal(np_of(gb.feat_shadow).view(np.uint16), np_of(ga.feat_shadow).view(np.uint16)):
+            assert_close("shadow", np_of(gb.feat), np_of(ga.feat), 1e-6)
 
 
 @pytest.mark.parametrize("bf16", [False, True])
@@ -246,7 +246,7 @@ def test_train_step_network_adam_equals_separate(gpu_lib, bf16):
     assert abs(float(la[0]) - float(lb[0])) <= 1e-6 * float(la[0])
     for name, p0, pa, pb in (("density", grid.density, ga.density, gb.density), ("feat", grid.feat, ga.feat,
                                                                                    gb.feat)):
-        assert report(f"{name} update", np_of(pb - p0), np_of(pa - p0))[0] <= 1e-5, name
+        assert_close(f"{name} update", np_of(pb - p0), np_of(pa - p0), 1e-5)
 
 
 def test_activity_mask_without_samples(gpu_lib):
@@ -352,7 +352,7 @@ def test_train_step_full_size_matches_separate(gpu_lib):
     assert abs(float(loss_a[0]) - float(loss_b[0])) <= 1e-6 * float(loss_a[0])
     assert torch.equal(fa, fb) and torch.equal(sa[4], sb[4]) and torch.equal(sa[5], sb[5])
     for name, p0, pa, pb in (("density", dens, ga.density, gb.density), ("feat", feat, ga.feat, gb.feat)):
-        assert report(f"{name} update", np_of(pb - p0), np_of(pa - p0))[0] <= 1e-5, name
+        assert_close(f"{name} update", np_of(pb - p0), np_of(pa - p0), 1e-5)
     for name, a, b in zip(("m density", "v density", "m feat", "v feat"), sa[:4], sb[:4]):
         assert_close(name, np_of(b), np_of(a), 1e-5)
     assert np.array_equal(np_of(gb.feat_shadow).view(np.uint16), _bf16_bits(np_of(gb.feat)))

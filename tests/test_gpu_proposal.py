@@ -1,14 +1,16 @@
 """GPU parity of the learned proposal: the segment selection and the
-predicted mass bit-exact from the same float32 logits (float32 recipe), the bfloat16 network forward and backward against
-the oracle's bfloat16 form (tolerance 1e-3 normwise: the float32 encoding
-may round to a neighbouring bfloat16 value; measured values printed)."""
+predicted mass bit-exact from the same float32 logits (float32 recipe), the
+bfloat16 network forward and backward against the oracle's bfloat16 form:
+1e-3 normwise and 4e-3 of the largest entry per entry (R23's two metrics; the
+float32 encoding may round to a neighbouring bfloat16 value, which moves one
+product term by 2^-8 of itself; measured values printed)."""
 
 import numpy as np
 import pytest
 
 import oracle as O
 import synth
-from tests.helpers import np_of, report, to_dev
+from tests.helpers import assert_close, np_of, to_dev
 
 pytestmark = pytest.mark.gpu
 F32 = np.float32
@@ -60,7 +62,7 @@ def test_proposal_forward_backward_bf16(gpu_lib):
     tn, tf, v = O.ray_box_clip(P.rays.o, P.rays.d, P.box_min, P.box_max)
     enc = O.proposal_encoding(P.rays.o, P.rays.d, tn, P.box_min, P.box_max)
     z, cache = O.proposal_forward(Ws, bs, enc, bf16=True)
-    assert report("logits", np_of(logits)[v], z[v])[0] <= 1e-3
+    assert_close("logits", np_of(logits)[v], z[v], 1e-3, 4e-3)
     # targets from the oracle's density-only render of a random grid
     prm = O.Params(P.density, P.feat, P.Ws, P.bs, P.box_min, P.box_max, 0.0)
     samp = O.sample_rays(P.rays.o, P.rays.d, None, P.box_min, P.box_max, P.step, P.max_samples)
@@ -83,8 +85,7 @@ def test_proposal_forward_backward_bf16(gpu_lib):
     off = 0
     for name, ref_t in zip(["W1", "b1", "W2", "b2", "W3", "b3"], [dWs[0], dbs[0], dWs[1], dbs[1], dWs[2], dbs[2]]):
         n = ref_t.size
-        nw, _ = report(name, g[off:off + n].reshape(ref_t.shape), ref_t)
-        assert nw <= 1e-3, name
+        assert_close(name, g[off:off + n].reshape(ref_t.shape), ref_t, 1e-3, 4e-3)
         off += n
 
 
