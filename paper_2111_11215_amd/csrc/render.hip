@@ -731,14 +731,16 @@ __global__ __launch_bounds__(256) void vertex_adam_kernel(BinArgs a, GridAdamArg
     f4* V = reinterpret_cast<f4*>(o.vf);
     u2* S = reinterpret_cast<u2*>(o.shadow);
     // Workgroups are dealt to the 8 XCDs round robin (block b on XCD b % 8).
-    // The vertices are cut into chunks of kChunk, dealt to the XCDs round
-    // robin as well: within a chunk neighbouring vertices share cell starts
-    // and sample records in one XCD's L2, and every XCD gets an even share of
-    // the grid's busy middle (its vertices with moments and samples) and of
-    // its idle rim.  The blocks of an XCD walk its chunks in 256-vertex
-    // steps.  gridDim.x is a multiple of 8; every wave's first vertex is a
-    // multiple of 64, so a wave owns two whole words of the activity mask.
-    constexpr int64_t kChunk = 4096;
+    // The vertices are cut into chunks of two x-planes (rounded up to a
+    // multiple of 256), dealt to the XCDs round robin as well: a cell's
+    // records and start are read by the vertices of two neighbouring
+    // x-planes, which then mostly sit in one chunk and so in one XCD's L2,
+    // and every XCD gets an even share of the grid's busy middle (its
+    // vertices with moments and samples) and of its idle rim.  The blocks of
+    // an XCD walk its chunks in 256-vertex steps.  gridDim.x is a multiple of
+    // 8; every wave's first vertex is a multiple of 64, so a wave owns two
+    // whole words of the activity mask.
+    const int64_t kChunk = (2 * static_cast<int64_t>(ny) * nz + 255) / 256 * 256;
     const int xcd = blockIdx.x & 7, nloc = gridDim.x >> 3, loc = blockIdx.x >> 3;
     const int64_t nchunk = (nv + kChunk - 1) / kChunk;
     const int64_t mine = nchunk > xcd ? (nchunk - xcd + 7) / 8 : 0;   // chunks of this XCD
