@@ -1272,16 +1272,19 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
                 *reinterpret_cast<uint2*>(chunk_at(tB, col_s, 8 * h + k)) = bits;
             }
             if (ok) {
+                // dft[0..3] hold channels 4h .. 4h + 3 of this half, dft[4..7]
+                // (half 0) channels 8..11: half h writes record word 1 + h,
+                // half 0 also words 0 and 3.  Written with fixed register
+                // indices and one float4 store per word (the two halves'
+                // stores merged into one with a lane-dependent register
+                // index had become 16-way selects and four dword stores).
                 float4* rec = a.rec + (static_cast<int64_t>(slot0) + cr.y) * 4;
+                const float4 oa = *reinterpret_cast<const float4*>(&sD[col_s][4 * h]);
+                rec[1 + h] = make_float4(dft[0] + oa.x, dft[1] + oa.y, dft[2] + oa.z, dft[3] + oa.w);
                 if (h == 0) {
-                    const float4 o0 = *reinterpret_cast<const float4*>(&sD[col_s][0]);
                     const float4 o8 = *reinterpret_cast<const float4*>(&sD[col_s][8]);
                     rec[0] = rh;
-                    rec[1] = make_float4(dft[0] + o0.x, dft[1] + o0.y, dft[2] + o0.z, dft[3] + o0.w);
                     rec[3] = make_float4(dft[4] + o8.x, dft[5] + o8.y, dft[6] + o8.z, dft[7] + o8.w);
-                } else {
-                    const float4 o4 = *reinterpret_cast<const float4*>(&sD[col_s][4]);
-                    rec[2] = make_float4(dft[0] + o4.x, dft[1] + o4.y, dft[2] + o4.z, dft[3] + o4.w);
                 }
             }
         }
