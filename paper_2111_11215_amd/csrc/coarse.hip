@@ -94,6 +94,7 @@ __device__ __forceinline__ void coarse_sample(const CoarseArgs& a, const float o
     const int64_t base = i0[0] * sx + i0[1] * sy + i0[2];
     cs.raw = 0.0f;
     cs.pre[0] = cs.pre[1] = cs.pre[2] = 0.0f;
+    #pragma unroll
     for (int c = 0; c < 8; ++c) {
         const int bx = (c >> 2) & 1, by = (c >> 1) & 1, bz = c & 1;
         cs.w[c] = (bx ? f[0] : 1.0f - f[0]) * (by ? f[1] : 1.0f - f[1]) * (bz ? f[2] : 1.0f - f[2]);
@@ -209,6 +210,7 @@ __global__ __launch_bounds__(256) void coarse_step_kernel(CoarseArgs a) {
             const int64_t key = ok ? cs.corner[0] : -1 - static_cast<int64_t>(lane);
             const int64_t prev = __shfl_up(key, 1, 64);
             const bool head = ok && (lane == 0 || prev != key);
+            #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 const float wk = ok ? cs.w[k] : 0.0f;
                 const float gd = run_suffix_sum(wk * draw, key, lane);
