@@ -8,16 +8,23 @@ threshold 1e-4, 8192 rays per iteration drawn with replacement from 100
 cameras of 800x800 pixels, step half a voxel, the 39-128-128-3 colour
 network.  One step = the whole hot path over one batch, inputs resident in
 HBM: in the default form (bfloat16 features and network plus the learned
-proposal) clip and count, proposal forward and segment masks, sampling of
-the selected segments, forward, loss, adjoint with the grids' Adam step,
-the network's Adam step, and, every 4th step, the proposal's own update
-from a density-only pass on half of the batch.  Forms: proposal (default), bf16, plain (float32,
-no proposal).
+proposal) proposal forward with its own clip and the segment masks,
+sampling of the selected segments, forward, loss, adjoint with the grids'
+Adam step, the network's Adam step, and, every 4th step, the proposal's own
+update from a density-only pass on half of the batch.  Forms: proposal
+(default), bf16, plain (float32, no proposal).
 
-Before timing, the comparison trains the plain float32, the bfloat16 and the
-bfloat16 + proposal forms for --compare-iters iterations each from identical
-states on identical batches (throughput and held-out PSNR of each); the
-timed steps continue training the selected form from its trained state.
+Before timing, the comparison trains, for --compare-iters iterations each
+from identical states on identical batches, the plain float32, the bfloat16
+and the bfloat16 + proposal forms, and beside them the paper's further
+parts: the fine-alpha skip with progressive scaling, the auxiliary losses,
+the network with the encoded position plus those losses (float32 and
+bfloat16), and the mask learned by the coarse stage (throughput and
+held-out PSNR of each); the timed steps continue training the selected
+form from its trained state.  The coarse stage runs first (its learned mask
+feeds one of the forms); the precision (16384 rays) and stress (256^3,
+32768 rays) configurations and the image-fitting toy are timed after the
+timed steps, and the oracle on the host last.
 
 Metric: ray-samples/s = (sum over the timed iterations of the uniform
 in-box samples of each batch, before coarse or proposal skipping) / wall
@@ -239,6 +246,7 @@ FORMS = {"plain": ("plain_fp32", False, False), "bf16": ("bf16", True, False),
 EXTRA_FORMS = {"skip_pg": ("bf16_fine_skip_progressive", True, False),
                "aux": ("bf16_auxiliary_losses", True, False),
                "paper": ("fp32_paper_network_and_objective", False, False),
+               "paper_bf16": ("bf16_paper_network_and_objective", True, False),
                "learned_coarse": ("bf16_learned_coarse_mask", True, False)}
 
 
@@ -257,13 +265,13 @@ def compare_forms(ctx, iters, rays, keep):
     res = {"iters": iters, "rays_per_iter": rays, "views": len(views)}
     kept = None
     ctx = dict(ctx, compare_iters=iters)
-    forms = ("plain", "bf16", "proposal", "skip_pg", "aux", "paper") + \
+    forms = ("plain", "bf16", "proposal", "skip_pg", "aux", "paper", "paper_bf16") + \
         (("learned_coarse",) if "coarse_learned" in ctx else ())
     for form in forms:
         name, bf16, use_prop = FORMS.get(form) or EXTRA_FORMS[form]
-        model = new_model(ctx, bf16, skip_pg=form == "skip_pg", aux=form in ("aux", "paper"),
+        model = new_model(ctx, bf16, skip_pg=form == "skip_pg", aux=form in ("aux", "paper", "paper_bf16"),
                           coarse=ctx["coarse_learned"] if form == "learned_coarse" else None,
-                          pe_x=5 if form == "paper" else 0)
+                          pe_x=5 if form in ("paper", "paper_bf16") else 0)
         if form == "plain":
             experiment.count_uniform(model, batches)
         prop = new_proposal(ctx) if use_prop else None
@@ -300,6 +308,9 @@ def compare_forms(ctx, iters, rays, keep):
     pp, f32 = res["fp32_paper_network_and_objective"], res["plain_fp32"]
     res["paper_network_and_objective_vs_plain_fp32"] = {"ms_per_step_ratio": pp["ms_per_step"] / f32["ms_per_step"],
                                                          "delta_psnr_db": pp["psnr_db"] - f32["psnr_db"]}
+    pb = res["bf16_paper_network_and_objective"]
+    res["paper_network_and_objective_vs_bf16"] = {"ms_per_step_ratio": pb["ms_per_step"] / res["bf16"]["ms_per_step"],
+                                                  "delta_psnr_db": pb["psnr_db"] - res["bf16"]["psnr_db"]}
     ax = res["bf16_auxiliary_losses"]
     res["auxiliary_losses_vs_bf16"] = {"ms_per_step_ratio": ax["ms_per_step"] / b16["ms_per_step"],
                                        "delta_psnr_db": ax["psnr_db"] - b16["psnr_db"]}

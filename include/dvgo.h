@@ -82,9 +82,10 @@ typedef struct dvgo_field {
  * C = 12), where u = (x - centre) / half-extent is the sample's position in
  * the field box's coordinates (centre and 2/(max - min) rounded once to
  * float32) and PE_5(u) = [u, sin(2^j u), cos(2^j u)], j = 0..4, three
- * components each; float32 precision only.  pe_x = 0 (zero-initialised
- * structs) is the 39-input network; other values are DVGO_E_UNSUPPORTED,
- * and so is pe_x = 5 with DVGO_BF16. */
+ * components each.  In DVGO_BF16 the per-sample part [feat, PE_5(u)] is
+ * rounded to bfloat16 as feat alone is otherwise.  pe_x = 0
+ * (zero-initialised structs) is the 39-input network; other values are
+ * DVGO_E_UNSUPPORTED. */
 typedef struct dvgo_mlp {
     const float* w1; const float* b1;   /* [hidden][C+27] (pe_x 5: [hidden][C+60]), [hidden] */
     const float* w2; const float* b2;   /* [hidden][hidden], [hidden] */

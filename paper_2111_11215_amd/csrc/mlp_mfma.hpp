@@ -59,6 +59,7 @@ struct NetLayout {
     static constexpr int kParams = kOffB3 + 3;
     static constexpr int kPStride = (kParams + 63) / 64 * 64;
     static constexpr int kQ1 = ((kS + 1) / 2 + 3) / 4;   // float4 groups of K = 2 layer-1 steps
+    static constexpr int kS1 = (kS + 15) / 16;            // K = 16 layer-1 steps (bfloat16)
     static constexpr int kXT = (kIn + 1 + 31) / 32;      // 32-column tiles of x' = [input, 1]
 };
 static_assert(NetLayout<0>::kIn == kIn && NetLayout<0>::kParams == kMlpParams && NetLayout<0>::kQ1 == 2 &&
@@ -66,6 +67,7 @@ static_assert(NetLayout<0>::kIn == kIn && NetLayout<0>::kParams == kMlpParams &&
               "the 39-input layout");
 constexpr int kMaxKX = 5;                                          // the paper's k_x
 constexpr int kW1PackF32Max = 4 * NetLayout<kMaxKX>::kQ1 * 64 * 4;   // packed W1 of either layout
+constexpr int kW1PackBF16Max = 4 * NetLayout<kMaxKX>::kS1 * 64 * 8;
 constexpr int kPStrideMax = NetLayout<kMaxKX>::kPStride;
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -128,6 +130,7 @@ struct PackArgs {
     int w1_in;   // first-layer input width (row stride of W1)
     int w1_ns;   // per-sample first-layer inputs (packed into w1p)
     int w1_q;    // float4 groups of w1p per output tile
+    int w1_s1;   // K = 16 steps of w1pb per output tile
 };
 
 // Pack W1 (feature columns) and W2 / W2^T into matrix-core operand order.
@@ -165,7 +168,7 @@ __device__ __forceinline__ void pack_weights(const PackArgs& a, int gid) {
         const int m = lane & 31, h = lane >> 5;
         const int k = phi16(st, i, h);
         a.w3pb[gid] = m < 3 ? f2bf(a.w3[m * kH + k]) : static_cast<uint16_t>(0);
-        a.w1tpb[gid] = m < kC ? f2bf(a.w1[k * kIn + m]) : static_cast<uint16_t>(0);
+        a.w1tpb[gid] = m < kC ? f2bf(a.w1[k * a.w1_in + m]) : static_cast<uint16_t>(0);
     }
     if (a.bf16 && gid < kW3TPackBF16) {
         // index (mt*64 + lane)*8 + i, k = 8h + i (< 3)
@@ -174,12 +177,12 @@ __device__ __forceinline__ void pack_weights(const PackArgs& a, int gid) {
         const int k = 8 * h + i;
         a.w3tpb[gid] = k < 3 ? f2bf(a.w3[k * kH + 32 * mt + m]) : static_cast<uint16_t>(0);
     }
-    if (a.bf16 && gid < kW1PackBF16) {
-        // bfloat16 layer 1: index (mt*64 + lane)*8 + i, k = 8h + i (< 12)
-        const int i = gid & 7, lane = (gid >> 3) & 63, mt = gid >> 9;
+    if (a.bf16 && gid < 4 * a.w1_s1 * 64 * 8) {
+        // bfloat16 layer 1: index ((mt*S1 + st)*64 + lane)*8 + i, k = 16st + 8h + i (< w1_ns)
+        const int i = gid & 7, lane = (gid >> 3) & 63, st = (gid >> 9) % a.w1_s1, mt = (gid >> 9) / a.w1_s1;
         const int m = lane & 31, h = lane >> 5;
-        const int kk = 8 * h + i;
-        a.w1pb[gid] = kk < kC ? f2bf(a.w1[(32 * mt + m) * kIn + kk]) : static_cast<uint16_t>(0);
+        const int kk = 16 * st + 8 * h + i;
+        a.w1pb[gid] = kk < a.w1_ns ? f2bf(a.w1[(32 * mt + m) * a.w1_in + kk]) : static_cast<uint16_t>(0);
     }
 }
 
@@ -789,17 +792,37 @@ struct ChainBF16 {
     bf16x8 hb[8];   // bf16(relu(layer 1)) in chained operand order
 };
 
+// Operand of layer-1 K step st for lane half h: per-sample inputs
+// 16st + 8h .. 16st + 8h + 7 (zero beyond kS), selected with constant
+// indices.
+template <int KX>
+__device__ __forceinline__ bf16x8 layer1_operand(const float xs[NetLayout<KX>::kS], int st, int h) {
+    constexpr int kS = NetLayout<KX>::kS;
+    bf16x8 fb;
+    #pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int k0 = 16 * st + e, k1 = k0 + 8;
+        const float v0 = k0 < kS ? xs[k0 < kS ? k0 : 0] : 0.0f;
+        const float v1 = k1 < kS ? xs[k1 < kS ? k1 : 0] : 0.0f;
+        fb[e] = static_cast<__bf16>(h ? v1 : v0);
+    }
+    return fb;
+}
+
+template <int KX>
 __device__ __forceinline__ void forward_chain_bf16(const MlpArgs& a, const bf16x8* sW1, const bf16x8* sW2,
-                                                   const float* sB2, int r, const float f[12], int lane,
-                                                   ChainBF16& c) {
+                                                   const float* sB2, int r, const float xs[NetLayout<KX>::kS],
+                                                   int lane, ChainBF16& c) {
+    constexpr int kS1 = NetLayout<KX>::kS1;
     const int h = lane >> 5;
     f32x16 h1[4];
     load_base(a.base, r, h, h1);
-    bf16x8 fb;   // features 8h .. 8h+7 (zero beyond 12), selected with constant indices
     #pragma unroll
-    for (int e = 0; e < 8; ++e) fb[e] = static_cast<__bf16>(h ? (e < kC - 8 ? f[8 + (e < kC - 8 ? e : 0)] : 0.0f) : f[e]);
-    #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) h1[mt] = mma_bf16(sW1[mt * 64 + lane], fb, h1[mt]);
+    for (int st = 0; st < kS1; ++st) {
+        const bf16x8 fb = layer1_operand<KX>(xs, st, h);
+        #pragma unroll
+        for (int mt = 0; mt < 4; ++mt) h1[mt] = mma_bf16(sW1[(mt * kS1 + st) * 64 + lane], fb, h1[mt]);
+    }
     #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
         #pragma unroll
@@ -861,11 +884,11 @@ struct Frags {
     }
 };
 
-// The forward's operands: packed W1, W2 and b2 (float32).
-template <int kThreads>
+// The forward's operands: packed W1 (kW1 fragments), W2 and b2 (float32).
+template <int kThreads, int kW1>
 __device__ __forceinline__ void load_packed_bf16(const MlpArgs& a, bf16x8* sW1, bf16x8* sW2, float* sB2) {
     Frags<kThreads, kW2PackBF16 / 8> f2;
-    Frags<kThreads, kW1PackBF16 / 8> f1;
+    Frags<kThreads, kW1> f1;
     f2.load(reinterpret_cast<const bf16x8*>(a.w2pb));
     f1.load(reinterpret_cast<const bf16x8*>(a.w1pb));
     const float b2 = threadIdx.x < kH ? a.b2[threadIdx.x] : 0.0f;
@@ -874,11 +897,13 @@ __device__ __forceinline__ void load_packed_bf16(const MlpArgs& a, bf16x8* sW1, 
     if (threadIdx.x < kH) sB2[threadIdx.x] = b2;
 }
 
-__global__ __launch_bounds__(256, 2) void mlp_fwd_bf16_kernel(MlpArgs a0) {
+template <int KX>
+__global__ __launch_bounds__(256, 2) void mlp_fwd_bf16_kernel(MlpArgs a0, PosArgs pa) {
+    constexpr int kW1 = 4 * NetLayout<KX>::kS1 * 64;   // layer-1 operand fragments
     __shared__ bf16x8 sW2[kW2PackBF16 / 8];
-    __shared__ bf16x8 sW1[kW1PackBF16 / 8];
+    __shared__ bf16x8 sW1[kW1];
     __shared__ __attribute__((aligned(16))) float sB2[kH];
-    load_packed_bf16<256>(a0, sW1, sW2, sB2);
+    load_packed_bf16<256, kW1>(a0, sW1, sW2, sB2);
     __syncthreads();
     const int64_t n = *a0.n_kept < a0.cap ? *a0.n_kept : a0.cap;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -890,10 +915,10 @@ __global__ __launch_bounds__(256, 2) void mlp_fwd_bf16_kernel(MlpArgs a0) {
         const bool ok = s < n;
         const int64_t sc = ok ? s : n - 1;
         const int r = a.sample_ray[sc];
-        float f[12];
-        load_feat(a.feat, sc, f);
+        float xs[NetLayout<KX>::kS];
+        sample_inputs<KX>(pa, a.feat, sc, r, xs);
         ChainBF16 c;
-        forward_chain_bf16(a, sW1, sW2, sB2, r, f, lane, c);
+        forward_chain_bf16<KX>(a, sW1, sW2, sB2, r, xs, lane, c);
         float col[3];
         bf16x8 h2b[8];
         head_bf16(a, c.z2, lane, col, h2b);
@@ -949,10 +974,19 @@ __device__ __forceinline__ void load_base2(const float* base, int r, int h, int 
 // of tiles 2q, 2q + 1; dW1 rows 32g, x' columns of tile q; dW3 (q = 0) or
 // db2 (q = 1) rows 32g.  The two halves of the head's logits and of
 // dL/dfeat are summed through LDS.
-__global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
+//
+// With the encoded position (KX > 0) the first layer takes kS1 K steps, the
+// x' rows hold [f, PE_KX(u), PE(d), 1] (three tiles: the q = 0 wavefronts
+// also accumulate tile 2), and the next block's inputs are not prefetched
+// (its LDS goes to the wider first-layer operand).
+template <int KX>
+__global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0, PosArgs pa) {
+    using L = NetLayout<KX>;
+    constexpr int kS1 = L::kS1;
+    constexpr bool kPre = KX == 0;   // the next block's layer-1 inputs prefetched into LDS
     __shared__ bf16x8 sW2[kW2PackBF16 / 8];
     __shared__ bf16x8 sW2T[kW2PackBF16 / 8];
-    __shared__ bf16x8 sW1[kW1PackBF16 / 8];
+    __shared__ bf16x8 sW1[4 * kS1 * 64];
     __shared__ __attribute__((aligned(16))) __bf16 tA[128 * kTP];   // h1 then dL/dz1, [sample][feature]
     __shared__ __attribute__((aligned(16))) __bf16 tB[128 * kTP];   // h2, then dL/dz2, then x'
     // dL/dz3 [channel][sample]: rows 0..2, row 3 zero (the B operand rows of
@@ -977,12 +1011,12 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
     // the rays r0 .. r0 + kPreRays - 1 (r0: the ray of the block's first
     // sample) and the features of the block's 128 samples.
     constexpr int kPreRays = 8;
-    __shared__ __attribute__((aligned(16))) float sPB[kPreRays * kH];
-    __shared__ __attribute__((aligned(16))) float sPF[128 * kC];
+    __shared__ __attribute__((aligned(16))) float sPB[kPre ? kPreRays * kH : 4];
+    __shared__ __attribute__((aligned(16))) float sPF[kPre ? 128 * kC : 4];
     __shared__ float sRed[4 * 4];
     {   // every operand this kernel keeps in LDS: all loads first, then the stores
         Frags<512, kW2PackBF16 / 8> f2, f2t;
-        Frags<512, kW1PackBF16 / 8> f1;
+        Frags<512, 4 * kS1 * 64> f1;
         f2.load(reinterpret_cast<const bf16x8*>(a0.w2pb));
         f2t.load(reinterpret_cast<const bf16x8*>(a0.w2tpb));
         f1.load(reinterpret_cast<const bf16x8*>(a0.w1pb));
@@ -1019,12 +1053,14 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
     const int m = lane & 31, h = lane >> 5;
     const int col_s = g * 32 + m;     // this lane's sample column in the staged block
     f32x16 dW2[2], dW1, dX;           // dX: dW3 (q = 0) or db2 (q = 1)
+    f32x16 dW1c;                      // KX > 0, q = 0: x' tile 2
     #pragma unroll
     for (int rr = 0; rr < 16; ++rr) {
         dW2[0][rr] = 0.0f;
         dW2[1][rr] = 0.0f;
         dW1[rr] = 0.0f;
         dX[rr] = 0.0f;
+        dW1c[rr] = 0.0f;
     }
     float db3[3] = {0, 0, 0};
     bf16x8 ones, zero8;
@@ -1041,6 +1077,7 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
     // the barrier before their use.
     typedef __attribute__((address_space(3))) void lds_void;
     auto prefetch = [&](const MlpArgs& a, int64_t b, int r0) {
+        if constexpr (!kPre) return;
         if (wave < 4) {
             const int row = 2 * wave + (lane >> 5);
             const int rr = r0 + row < a.nrays ? r0 + row : a.nrays - 1;
@@ -1088,23 +1125,30 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
         {
             // features and the ray's first-layer row from the copies in LDS
             // (a ray outside the copied rows reads global memory); a sample
-            // past the end takes zero features, its copy may be stale
-            float f[12];
-            load_feat(sPF, col_s, f);
+            // past the end takes zero inputs, its copy may be stale.  With
+            // the encoded position: features and row from global memory, the
+            // encoding evaluated here.
+            float xs[L::kS];
             f32x16 h1[2];
-            const unsigned d = static_cast<unsigned>(r - r0);
-            if (d < static_cast<unsigned>(kPreRays)) load_base2(sPB, static_cast<int>(d), h, 2 * q, h1);
-            else load_base2(a.base, r, h, 2 * q, h1);
-            bf16x8 fb;
+            if constexpr (kPre) {
+                load_feat(sPF, col_s, xs);
+                const unsigned d = static_cast<unsigned>(r - r0);
+                if (d < static_cast<unsigned>(kPreRays)) load_base2(sPB, static_cast<int>(d), h, 2 * q, h1);
+                else load_base2(a.base, r, h, 2 * q, h1);
+            } else {
+                sample_inputs<KX>(pa, a.feat, sc, r, xs);
+                load_base2(a.base, r, h, 2 * q, h1);
+            }
             #pragma unroll
-            for (int e = 0; e < 8; ++e)
-                fb[e] = static_cast<__bf16>(!ok ? 0.0f : h ? (e < kC - 8 ? f[8 + (e < kC - 8 ? e : 0)] : 0.0f) : f[e]);
+            for (int st = 0; st < kS1; ++st) {
+                const bf16x8 fb = ok ? layer1_operand<KX>(xs, st, h) : zero8;
+                #pragma unroll
+                for (int t = 0; t < 2; ++t) h1[t] = mma_bf16(sW1[((2 * q + t) * kS1 + st) * 64 + lane], fb, h1[t]);
+            }
             #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                h1[t] = mma_bf16(sW1[(2 * q + t) * 64 + lane], fb, h1[t]);
+            for (int t = 0; t < 2; ++t)
                 #pragma unroll
                 for (int gg = 0; gg < 2; ++gg) stage_row(tA, col_s, 4 * q + 2 * t + gg, h, relu_pack8(h1[t], gg));
-            }
         }
         __syncthreads();   // B1: h1 rows complete; sPB, sPF read
         // ---- layer 2 and the head on this half
@@ -1246,7 +1290,30 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
         asm volatile("" ::"v"(r_next));
         #pragma unroll
         for (int u = 0; u < 4; ++u) stage_row(tA, col_s, 4 * q + u, h, d1[u]);
+        if (q == 0 && KX > 0) {
+            // x' = [f, PE_KX(u), PE(d), 1, 0...] -> tB (96 columns, this
+            // lane's half of 24 four-column chunks), the per-sample inputs
+            // evaluated again (every lane, at its clamped sample)
+            float xs[L::kS];
+            sample_inputs<KX>(pa, a.feat, sc, r, xs);
+            const float* per = a.pe + static_cast<int64_t>(r) * 32;
+            auto xval = [&](int j) -> float {
+                if (j < L::kS) return xs[j < L::kS ? j : 0];
+                if (j < L::kIn) return per[j - L::kS];
+                return j == L::kIn ? 1.0f : 0.0f;
+            };
+            constexpr int kChunks = 4 * L::kXT;   // per lane half
+            #pragma unroll
+            for (int kk = 0; kk < kChunks; ++kk) {
+                bf16x4 bv;
+                #pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    bv[e] = static_cast<__bf16>(h ? xval(4 * (kChunks + kk) + e) : xval(4 * kk + e));
+                *reinterpret_cast<uint2*>(chunk_at(tB, col_s, kChunks * h + kk)) = __builtin_bit_cast(uint2, bv);
+            }
+        }
         if (q == 0) {
+            if constexpr (KX == 0) {
             // x' = [f, PE, 1, 0...] -> tB (64 columns, this lane's half of
             // 8 float4 chunks): half 0 takes f[0..11] and PE[0..19], half 1
             // PE[20..26] and the constant 1 (stored after the PE) and zeros.
@@ -1271,6 +1338,7 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
                 }
                 *reinterpret_cast<uint2*>(chunk_at(tB, col_s, 8 * h + k)) = bits;
             }
+            }
             if (ok) {
                 // dft[0..3] hold channels 4h .. 4h + 3 of this half, dft[4..7]
                 // (half 0) channels 8..11: half h writes record word 1 + h,
@@ -1290,24 +1358,32 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
         }
         __syncthreads();   // B7: dz1 and x' rows complete
         #pragma unroll
-        for (int st = 0; st < 8; ++st)
-            dW1 = mma_bf16(tr_operand(tA, 16 * st, 32 * g, lane), tr_operand(tB, 16 * st, 32 * q, lane), dW1);
+        for (int st = 0; st < 8; ++st) {
+            const bf16x8 av = tr_operand(tA, 16 * st, 32 * g, lane);
+            dW1 = mma_bf16(av, tr_operand(tB, 16 * st, 32 * q, lane), dW1);
+            if (KX > 0 && q == 0) dW1c = mma_bf16(av, tr_operand(tB, 16 * st, 64, lane), dW1c);
+        }
         __builtin_amdgcn_s_waitcnt(0);   // the next block's copies to sPB, sPF have landed
         __syncthreads();   // B8: rows read before the next block's staging
         r0 = __builtin_amdgcn_readfirstlane(r0_next);
     }
     // ---- epilogue: this workgroup's partial of the flat gradient
-    float* out = a0.partial + static_cast<int64_t>(blockIdx.x) * kPStride;
+    float* out = a0.partial + static_cast<int64_t>(blockIdx.x) * L::kPStride;
     #pragma unroll
     for (int rr = 0; rr < 16; ++rr) {
         const int row = 32 * g + acc_row(rr, h);
         #pragma unroll
-        for (int t = 0; t < 2; ++t) out[kOffW2 + row * kH + 32 * (2 * q + t) + m] = dW2[t][rr];
+        for (int t = 0; t < 2; ++t) out[L::kOffW2 + row * kH + 32 * (2 * q + t) + m] = dW2[t][rr];
         const int cidx = 32 * q + m;
-        if (cidx < kIn) out[kOffW1 + row * kIn + cidx] = dW1[rr];
-        else if (cidx == kIn) out[kOffB1 + row] = dW1[rr];
-        if (q == 0 && m < 3) out[kOffW3 + m * kH + row] = dX[rr];
-        if (q == 1 && m == 0) out[kOffB2 + row] = dX[rr];
+        if (cidx < L::kIn) out[L::kOffW1 + row * L::kIn + cidx] = dW1[rr];
+        else if (cidx == L::kIn) out[L::kOffB1 + row] = dW1[rr];
+        if (KX > 0 && q == 0) {
+            const int c2 = 64 + m;
+            if (c2 < L::kIn) out[L::kOffW1 + row * L::kIn + c2] = dW1c[rr];
+            else if (c2 == L::kIn) out[L::kOffB1 + row] = dW1c[rr];
+        }
+        if (q == 0 && m < 3) out[L::kOffW3 + m * kH + row] = dX[rr];
+        if (q == 1 && m == 0) out[L::kOffB2 + row] = dX[rr];
     }
     if (q == 0) {
         #pragma unroll
@@ -1320,20 +1396,23 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0) {
     }
     __syncthreads();
     if (threadIdx.x < 3)
-        out[kOffB3 + threadIdx.x] = sRed[threadIdx.x] + sRed[4 + threadIdx.x] + sRed[8 + threadIdx.x] +
+        out[L::kOffB3 + threadIdx.x] = sRed[threadIdx.x] + sRed[4 + threadIdx.x] + sRed[8 + threadIdx.x] +
                                     sRed[12 + threadIdx.x];
 }
 
-// kx: frequencies of the encoded position in the input (0 or kMaxKX; the
-// bfloat16 kernels take 0 only, which the entry points check).
+// kx: frequencies of the encoded position in the input (0 or kMaxKX).
 inline void launch_mlp_fwd(const MlpArgs& a, const PosArgs& pa, int kx, int cus, hipStream_t s) {
-    if (a.bf16) DVGO_LAUNCH(K_MLP_FWD, mlp_fwd_bf16_kernel, dim3(cus * 2), dim3(256), 0, s, a);
+    if (a.bf16 && kx == kMaxKX)
+        DVGO_LAUNCH(K_MLP_FWD, mlp_fwd_bf16_kernel<kMaxKX>, dim3(cus * 2), dim3(256), 0, s, a, pa);
+    else if (a.bf16) DVGO_LAUNCH(K_MLP_FWD, mlp_fwd_bf16_kernel<0>, dim3(cus * 2), dim3(256), 0, s, a, pa);
     else if (kx == kMaxKX)
         DVGO_LAUNCH(K_MLP_FWD, mlp_fwd_f32_kernel<kMaxKX>, dim3(cus * 2), dim3(256), 0, s, a, pa);
     else DVGO_LAUNCH(K_MLP_FWD, mlp_fwd_f32_kernel<0>, dim3(cus * 2), dim3(256), 0, s, a, pa);
 }
 inline void launch_mlp_bwd(const MlpArgs& a, const PosArgs& pa, int kx, int blocks, hipStream_t s) {
-    if (a.bf16) DVGO_LAUNCH(K_MLP_BWD, mlp_bwd_bf16_kernel, dim3(blocks), dim3(512), 0, s, a);
+    if (a.bf16 && kx == kMaxKX)
+        DVGO_LAUNCH(K_MLP_BWD, mlp_bwd_bf16_kernel<kMaxKX>, dim3(blocks), dim3(512), 0, s, a, pa);
+    else if (a.bf16) DVGO_LAUNCH(K_MLP_BWD, mlp_bwd_bf16_kernel<0>, dim3(blocks), dim3(512), 0, s, a, pa);
     else if (kx == kMaxKX)
         DVGO_LAUNCH(K_MLP_BWD, mlp_bwd_f32_kernel<kMaxKX>, dim3(blocks), dim3(256), 0, s, a, pa);
     else DVGO_LAUNCH(K_MLP_BWD, mlp_bwd_f32_kernel<0>, dim3(blocks), dim3(256), 0, s, a, pa);

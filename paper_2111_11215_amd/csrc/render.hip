@@ -49,7 +49,7 @@ WsLayout ws_layout(int64_t B, int64_t cap, int64_t ncell) {
     L.w1p = take(kW1PackF32Max * 4);
     L.w2p = take(kW2PackF32 * 4);
     L.w2tp = take(kW2PackF32 * 4);
-    L.w1pb = take(kW1PackBF16 * 2);
+    L.w1pb = take(kW1PackBF16Max * 2);
     L.w2pb = take(kW2PackBF16 * 2);
     L.w2tpb = take(kW2PackBF16 * 2);
     L.w3pb = take(kW3PackBF16 * 2);
@@ -1067,7 +1067,6 @@ int32_t validate(const dvgo_field* field, const dvgo_mlp* mlp, const float* rays
         if (mlp->hidden != kH) return DVGO_E_SHAPE;
         if (mlp->precision != DVGO_F32 && mlp->precision != DVGO_BF16) return DVGO_E_DTYPE;
         if (mlp->pe_x != 0 && mlp->pe_x != kMaxKX) return DVGO_E_UNSUPPORTED;
-        if (mlp->pe_x != 0 && mlp->precision != DVGO_F32) return DVGO_E_UNSUPPORTED;
         if (!mlp->w1 || !mlp->b1 || !mlp->w2 || !mlp->b2 || !mlp->w3 || !mlp->b3) return DVGO_E_ARG;
     }
     if (B > 0 && (!rays_o || !rays_d || !t_near || !n_uniform || !perm || !ray_offset)) return DVGO_E_ARG;
@@ -1141,6 +1140,7 @@ int32_t run_prep(const Common& cm, const dvgo_mlp* mlp, hipStream_t s, int* zero
         pk.w1_in = xpe ? NetLayout<kMaxKX>::kIn : kIn;
         pk.w1_ns = xpe ? NetLayout<kMaxKX>::kS : kC;
         pk.w1_q = xpe ? NetLayout<kMaxKX>::kQ1 : NetLayout<0>::kQ1;
+        pk.w1_s1 = xpe ? NetLayout<kMaxKX>::kS1 : NetLayout<0>::kS1;
         const int zblocks = zero ? grid_for(nzero, 256, dvgo::device_cu_count() * 4) : 0;
         const unsigned blocks = static_cast<unsigned>(kPackThreads / 256 + (cm.B + kPrepRays - 1) / kPrepRays + zblocks);
         DVGO_LAUNCH(K_RAY_BASE, prep_kernel, dim3(blocks), dim3(256), 0, s, pk, 1, cm.sa.rays_d, cm.B, mlp->w1,

@@ -108,12 +108,9 @@ def test_host_validation_rejects_before_launch(lib):
     f.box = _lib.make_box((-1, -1, -1), (1, 1, 1), (4, 4, 4))
     m.precision = 7
     assert lib.dvgo_render_fwd(ctypes.byref(f), ctypes.byref(m), fake, fake, nul, *args[3:]) == -3
-    # the encoded-position network: k_x other than 5, or with bfloat16 products
+    # the encoded-position network: k_x other than 5
     m.precision = 0
     m.pe_x = 3
-    assert lib.dvgo_render_fwd(ctypes.byref(f), ctypes.byref(m), fake, fake, nul, *args[3:]) == -6
-    m.pe_x = 5
-    m.precision = 1
     assert lib.dvgo_render_fwd(ctypes.byref(f), ctypes.byref(m), fake, fake, nul, *args[3:]) == -6
     m.pe_x = 0
     # scene: too many spheres

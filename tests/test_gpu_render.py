@@ -163,25 +163,29 @@ def test_render_backward_parity_tiny(gpu_lib, bf16, jitter):
 
 
 @pytest.mark.parametrize("jitter", [True, False])
-def test_render_position_encoding_parity_tiny(gpu_lib, jitter):
+@pytest.mark.parametrize("bf16", [False, True])
+def test_render_position_encoding_parity_tiny(gpu_lib, bf16, jitter):
     """The network with the encoded query position (Eq. fine_queries with
-    k_x = 5; float32 form): forward outputs and every gradient of the tiny
-    configuration against the oracle at the float32 bounds."""
+    k_x = 5): forward outputs and every gradient of the tiny configuration
+    against the oracle at the bounds of each form (the bfloat16 form rounds
+    the per-sample inputs [f, PE_5(u)] as it rounds f alone)."""
     from paper_2111_11215_amd import api
-    from paper_2111_11215_amd._lib import DVGO_F32
+    from paper_2111_11215_amd._lib import DVGO_BF16, DVGO_F32
     P = _with_position_encoding(_problem(2, jitter=jitter, bias=0.2), 61)
-    grid, flat, s = _gpu(P)
+    grid, flat, s = _gpu(P, bf16=bf16)
     assert flat.numel() == 26243
-    out = api.render_fwd(grid, flat, s, P.bg, precision=DVGO_F32, want_seg_w=True, want_sample_w=True)
-    samp, prm, ref, ro = _oracle(P)
+    out = api.render_fwd(grid, flat, s, P.bg, precision=DVGO_BF16 if bf16 else DVGO_F32, use_shadow=bf16,
+                         want_seg_w=True, want_sample_w=True)
+    samp, prm, ref, ro = _oracle(P, bf16=bf16)
     assert prm.pe_x == 5
     n = int(samp["ray_offset"][-1])
-    _fwd_keys(out, ref, ("rgb", "depth", "acc", "log_t_end", "seg_w"), TOL32)
-    assert_close("sample_w", np_of(out["sample_w"])[:n], ref["sample_w"], TOL32)
+    tol = TOLBF if bf16 else TOL32
+    _fwd_keys(out, ref, ("rgb", "depth", "acc", "log_t_end", "seg_w"), tol, tol_max=_tol_max(bf16, tol))
+    assert_close("sample_w", np_of(out["sample_w"])[:n], ref["sample_w"], tol, _tol_max(bf16, tol))
     ref["_samp"] = samp
     _, g = O.photo_loss(ref["rgb"], P.rays.target)
-    gd, gf, gm = _grads(api, grid, flat, s, out, g, P)
-    _check_backward(P, prm, ref, ro, gd, gf, gm, g, TOL32)
+    gd, gf, gm = _grads(api, grid, flat, s, out, g, P, bf16)
+    _check_backward(P, prm, ref, ro, gd, gf, gm, g, tol)
 
 
 def test_render_backward_depth_acc_channels(gpu_lib):
@@ -262,7 +266,7 @@ def test_render_opaque_samples(gpu_lib):
     _check_backward(P, prm, ref, ro, gd, gf, gm, g, tol)
 
 
-@pytest.mark.parametrize("bf16,pe_x", [(False, 0), (True, 0), (False, 5)])
+@pytest.mark.parametrize("bf16,pe_x", [(False, 0), (True, 0), (False, 5), (True, 5)])
 def test_render_full_size_sampled_rays(gpu_lib, bf16, pe_x):
     """Full configuration (160^3 grids with random values, 8192 rays, coarse
     mask of the sphere scene, launch configuration of the benchmark): the

@@ -213,13 +213,14 @@ def test_train_step_with_auxiliary_losses(gpu_lib, bf16, aux):
 
 
 @pytest.mark.timeout(300)
+@pytest.mark.parametrize("bf16", [False, True])
 @pytest.mark.parametrize("aux", [None, (1e-2, 1e-3)])
-def test_train_step_with_position_encoding(gpu_lib, aux):
-    """The paper's fine network with the encoded query position (72 inputs,
-    float32), alone and with the auxiliary losses at the paper's weights (the
-    paper's whole fine objective): the tiny batch at t = 5 from seeded
+def test_train_step_with_position_encoding(gpu_lib, aux, bf16):
+    """The paper's fine network with the encoded query position (72 inputs),
+    both forms, alone and with the auxiliary losses at the paper's weights
+    (the paper's whole fine objective): the tiny batch at t = 5 from seeded
     moments with the activity mask, against the oracle."""
     P = synth.tiny_config(2, jitter=True, n_rays=4096)
     Ws, _ = synth.xavier_uniform_mlp(np.random.default_rng(71), (72, 128, 128, 3))
     P.Ws = [w.astype(F32) for w in Ws]
-    _run_case(P, None, None, False, True, 5, 0.1, 1e-3, True, seed=61, aux=aux)
+    _run_case(P, None, None, bf16, True, 5, 0.1, 1e-3, True, seed=61 + bf16, aux=aux)

@@ -6,7 +6,9 @@ The contract (the "bfloat16 form" of both networks) names exactly which
 operands of which products are rounded.  bf(v) is v's float32 value rounded
 to bfloat16, round to nearest, ties to even.  Products and sums are exact.
 
-Colour network (input x = [f (12), PE(d) (27)], W1 = [W1f | W1d]):
+Colour network (input x = [f (12), PE(d) (27)], W1 = [W1f | W1d]; with the
+encoded position, x = [f, PE_5(u) (33), PE(d)] and f below stands for the
+45 per-sample inputs [f, PE_5(u)], W1f for their 45 columns):
   z1 = bf(f) bf(W1f)^T + (PE(d) W1d^T + b1)     h1 = relu(z1)
   z2 = bf(h1) bf(W2)^T + b2                     h2 = relu(z2)
   z3 = bf(h2) bf(W3)^T + b3                     c  = sigmoid(z3)
@@ -54,24 +56,28 @@ def _rel(a, b):
     return float(np.abs(a - b).max() / den)
 
 
-def _colour_problem(seed, S=300):
+def _colour_problem(seed, S=300, pe_x=False):
     rng = np.random.default_rng(seed)
-    Ws, bs = synth.xavier_uniform_mlp(rng, (39, 128, 128, 3))
+    Ws, bs = synth.xavier_uniform_mlp(rng, (72 if pe_x else 39, 128, 128, 3))
     bs = [(rng.normal(size=b.shape) * 0.1).astype(np.float32) for b in bs]
     f = rng.uniform(-1, 1, (S, 12)).astype(np.float32)
     d = rng.normal(size=(S, 3))
     d /= np.linalg.norm(d, axis=1, keepdims=True)
-    x = np.concatenate([f.astype(np.float64), O.positional_encoding(d)], axis=1)
+    parts = [f.astype(np.float64)]
+    if pe_x:
+        parts.append(O.positional_encoding(rng.uniform(-1, 1, (S, 3)), 5))
+    x = np.concatenate(parts + [O.positional_encoding(d)], axis=1)
     dc = rng.normal(size=(S, 3)) * 1e-2
     return Ws, bs, x, dc
 
 
-def _torch_colour_bf16(Ws, bs, x, dc):
+def _torch_colour_bf16(Ws, bs, x, dc, ns=12):
+    """ns: the per-sample inputs (12, or 45 with the encoded position)."""
     W1, W2, W3 = [_t(w) for w in Ws]
     b1, b2, b3 = [_t(b) for b in bs]
     X = _t(x)
-    f, pe = X[:, :12], X[:, 12:]
-    W1f, W1d = W1[:, :12], W1[:, 12:]
+    f, pe = X[:, :ns], X[:, ns:]
+    W1f, W1d = W1[:, :ns], W1[:, ns:]
     z1 = torch.matmul(bf(f), bf(W1f).T) + (torch.matmul(pe, W1d.T) + b1)
     h1 = torch.clamp(z1, min=0.0)
     z2 = torch.matmul(bf(h1), bf(W2).T) + b2
@@ -91,14 +97,15 @@ def _torch_colour_bf16(Ws, bs, x, dc):
     return c, df, [dW1, dW2, dW3], [db1, db2, db3]
 
 
-@pytest.mark.parametrize("seed", [0, 1])
-def test_colour_bf16_form_matches_torch_emulation(seed):
-    Ws, bs, x, dc = _colour_problem(seed)
-    c_ref, df_ref, dW_ref, db_ref = _torch_colour_bf16(Ws, bs, x, dc)
-    c, cache = O.mlp_forward(Ws, bs, x, bf16=True)
+@pytest.mark.parametrize("seed,pe_x", [(0, False), (1, False), (2, True)])
+def test_colour_bf16_form_matches_torch_emulation(seed, pe_x):
+    Ws, bs, x, dc = _colour_problem(seed, pe_x=pe_x)
+    ns = 45 if pe_x else 12
+    c_ref, df_ref, dW_ref, db_ref = _torch_colour_bf16(Ws, bs, x, dc, ns)
+    c, cache = O.mlp_forward(Ws, bs, x, bf16=True, n_feat=ns)
     dx, dWs, dbs = O.mlp_backward(Ws, cache, dc)
     assert _rel(c, c_ref.numpy()) < TOL
-    assert _rel(dx[:, :12], df_ref.numpy()) < TOL
+    assert _rel(dx[:, :ns], df_ref.numpy()) < TOL
     for name, a, b in zip(["dW1", "dW2", "dW3", "db1", "db2", "db3"], dWs + dbs, dW_ref + db_ref):
         assert _rel(a, b.numpy()) < TOL, name
 
