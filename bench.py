@@ -368,6 +368,50 @@ def cpu_baseline(ctx, rays, B):
                        f"{dens.size + feat.size + 22019} parameters ({t_adam:.2f} s); 1 thread")}
 
 
+def unique_footprint(ctx, B, gather_ms):
+    """The unique-footprint lower bound of the fine pass's gather, counted
+    by the oracle (part of the CPU-baseline leg): the distinct grid vertices
+    that the samples of the first B-ray batch touch (trilinear corners, plain
+    coarse-mask sampler, no proposal), times the bytes a vertex holds for the
+    gather (float32 density + 12 bfloat16 features), over the measured
+    average gather launch; and the distinct 128-byte lines those vertices
+    occupy, the least that a cache can fetch for them."""
+    import numpy as np
+
+    import oracle as O
+    import synth
+
+    rng = np.random.default_rng(1000)
+    flat = rng.integers(0, len(ctx["cams"]) * 800 * 800, size=B)
+    o, d, *_ = synth.scenes._rays_for_flat_pixels(ctx["cams"], 800, 800, 1000.0, flat)
+    j = rng.random(B).astype(np.float32)
+    n = ctx["n"]
+    thr = O.coarse_raw_threshold(synth.FULL_TAU, ctx["step"])
+    bits = O.coarse_cell_bits(ctx["raw"], thr)
+    t0 = time.perf_counter()
+    samp = O.sample_rays(o, d, j, ctx["bmin"], ctx["bmax"], ctx["step"], ctx["max_samples"],
+                         coarse=(bits, ctx["bmin"], ctx["bmax"], ctx["raw"].shape))
+    r = samp["sample_ray"].astype(np.int64)
+    x = O.sample_x(o[r], d[r], O.sample_t(samp["t_near"][r], j[r], samp["sample_k"].astype(np.int64), ctx["step"]))
+    i0, _, offs = O.trilinear_corners(x, ctx["bmin"], ctx["bmax"], (n, n, n))
+    ids = np.concatenate([((i0[:, 0] + dx) * n + (i0[:, 1] + dy)) * n + (i0[:, 2] + dz) for dx, dy, dz in offs])
+    uniq = np.unique(ids)
+    verts = int(uniq.size)
+    # the same vertices at the 128-byte line granularity of the caches: the
+    # density array (4 B per vertex) and the bfloat16 feature copy (24 B)
+    lines = int(np.unique(uniq * 4 // 128).size + np.unique(uniq * 24 // 128).size)
+    secs = time.perf_counter() - t0
+    per_vertex = 4 + 12 * 2
+    out = {"distinct_vertices": verts, "samples": int(samp["sample_k"].size), "bytes_per_vertex": per_vertex,
+           "bytes": verts * per_vertex, "distinct_128B_lines": lines, "line_bytes": lines * 128,
+           "sample": (f"first {B}-ray batch, plain coarse-mask sampler (no proposal), trilinear corners "
+                      f"counted by the oracle ({secs:.1f} s)")}
+    if gather_ms:
+        out["gather_GBps_lower_bound"] = verts * per_vertex / (gather_ms * 1e-3) / 1e9
+        out["gather_launch_ms"] = gather_ms
+    return out
+
+
 def calibrate_copy(mib):
     """A plain device-to-device copy of known size, to scale the HBM
     traffic counters (FETCH_SIZE, WRITE_SIZE) of a profiled run; also
@@ -685,6 +729,8 @@ def main():
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(ctx, args.cpu_rays, args.rays)
+        g = out.get("kernels_roofline", {}).get("gather", {})
+        out["unique_footprint"] = unique_footprint(ctx, args.rays, g.get("launch_ms"))
     print(json.dumps(out), flush=True)
 
 
