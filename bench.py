@@ -322,6 +322,18 @@ def compare_forms(ctx, iters, rays, keep):
     return res, kept
 
 
+def host_cpu_model():
+    """The host CPU's model name, as the kernel reports it."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(ctx, rays, B):
     """The oracle as it stands, one thread, on a bounded sample: the plain
     float64 step (sample, forward, loss, adjoint) for ``rays`` rays drawn as
@@ -363,6 +375,7 @@ def cpu_baseline(ctx, rays, B):
     per_iter = t_rays * scale + t_adam
     n_uni = float(np.sum(samp["n_uniform"])) * scale
     return {"value": n_uni / per_iter, "unit": "ray-samples/s", "cores": 1, "kind": "oracle",
+            "host_cpu": host_cpu_model(), "host_cpus_available": len(os.sched_getaffinity(0)),
             "sample": (f"plain float64 step of the first {rays} of the {B} rays of the first batch (sample, "
                        f"forward, loss, adjoint: {t_rays:.2f} s, scaled x{scale:.0f}) + one Adam step over all "
                        f"{dens.size + feat.size + 22019} parameters ({t_adam:.2f} s); 1 thread")}
