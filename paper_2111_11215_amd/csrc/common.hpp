@@ -174,6 +174,42 @@ __device__ __forceinline__ float recipe_trilerp(const dvgo::GridArgs& g, const f
     return val;
 }
 
+// Sine and cosine of x for |x| <= 1024, for the encoded query position
+// (whose arguments 2^j u stay within 16 in magnitude): Cody and Waite's
+// reduction x = k pi/2 + r with pi/2 split into three parts (the first two
+// with 12 significant bits, so that k times each is exact for |k| < 2^12),
+// then the Taylor series of sin and cos on |r| <= pi/4 to the terms in r^11
+// and r^12 (the first omitted terms are below 1e-11) in Horner form, and
+// the quadrant k mod 4 picks and signs the pair.  About one unit in the last
+// place, and free of the large-argument path that the library's sincosf
+// carries in registers.
+__device__ __forceinline__ void pe_sincos(float x, float* s, float* c) {
+    constexpr float kTwoOverPi = 0x1.45f306p-1f;
+    constexpr float kP1 = 0x1.922p+0f, kP2 = -0x1.2aep-18f, kP3 = -0x1.de974p-31f;
+    const float k = rintf(x * kTwoOverPi);
+    float r = fmaf(-k, kP1, x);
+    r = fmaf(-k, kP2, r);
+    r = fmaf(-k, kP3, r);
+    const float r2 = r * r;
+    float ps = -1.0f / 39916800.0f;
+    ps = fmaf(ps, r2, 1.0f / 362880.0f);
+    ps = fmaf(ps, r2, -1.0f / 5040.0f);
+    ps = fmaf(ps, r2, 1.0f / 120.0f);
+    ps = fmaf(ps, r2, -1.0f / 6.0f);
+    const float sr = fmaf(ps * r2, r, r);
+    float pc = 1.0f / 479001600.0f;
+    pc = fmaf(pc, r2, -1.0f / 3628800.0f);
+    pc = fmaf(pc, r2, 1.0f / 40320.0f);
+    pc = fmaf(pc, r2, -1.0f / 720.0f);
+    pc = fmaf(pc, r2, 1.0f / 24.0f);
+    pc = fmaf(pc, r2, -0.5f);
+    const float cr = fmaf(pc, r2, 1.0f);
+    const int q = static_cast<int>(k) & 3;
+    const float a = (q & 1) ? cr : sr, b = (q & 1) ? sr : cr;
+    *s = (q & 2) ? -a : a;
+    *c = ((q + 1) & 2) ? -b : b;
+}
+
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
                                      __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));

@@ -361,22 +361,40 @@ __device__ __forceinline__ void load_feat(const float* feat, int64_t s, float f[
 }
 
 // Per-sample first-layer inputs of sample s on ray r: its 12 features,
-// then (KX > 0) the encoded position [u, sin(2^j u), cos(2^j u)], j < KX,
-// with the library sine and cosine.
+// then (KX > 0) the encoded position [u, sin(2^j u), cos(2^j u)], j < KX
+// (sine and cosine by pe_sincos: |2^j u| <= 16 for a sample in the box).
+// (in two parts: the loads, then the arithmetic, so that a caller can place
+// other work between them)
+struct SampleIn {
+    float f[kC];
+    float o[3], d[3];
+    float p, tn;
+    int k;
+};
+
 template <int KX>
-__device__ __forceinline__ void sample_inputs(const PosArgs& a, const float* feat, int64_t s, int r,
-                                              float xs[NetLayout<KX>::kS]) {
-    load_feat(feat, s, xs);
+__device__ __forceinline__ void sample_loads(const PosArgs& a, const float* feat, int64_t s, int r, SampleIn& in) {
+    load_feat(feat, s, in.f);
     if constexpr (KX > 0) {
-        float o[3], d[3], x[3];
         #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            o[i] = a.rays_o[3 * r + i];
-            d[i] = a.rays_d[3 * r + i];
+            in.o[i] = a.rays_o[3 * r + i];
+            in.d[i] = a.rays_d[3 * r + i];
         }
-        const float p = a.jitter ? a.jitter[r] : 0.0f;
-        const float t = dvgo_dev::recipe_tk(a.t_near[r], p, a.sample_k[s], a.step);
-        dvgo_dev::recipe_x(o, d, t, x);
+        in.p = a.jitter ? a.jitter[r] : 0.0f;
+        in.tn = a.t_near[r];
+        in.k = a.sample_k[s];
+    }
+}
+
+template <int KX>
+__device__ __forceinline__ void sample_encode(const PosArgs& a, const SampleIn& in, float xs[NetLayout<KX>::kS]) {
+    #pragma unroll
+    for (int i = 0; i < kC; ++i) xs[i] = in.f[i];
+    if constexpr (KX > 0) {
+        float x[3];
+        const float t = dvgo_dev::recipe_tk(in.tn, in.p, in.k, a.step);
+        dvgo_dev::recipe_x(in.o, in.d, t, x);
         #pragma unroll
         for (int i = 0; i < 3; ++i) xs[kC + i] = (x[i] - a.pe_c[i]) * a.pe_ih[i];
         #pragma unroll
@@ -384,11 +402,19 @@ __device__ __forceinline__ void sample_inputs(const PosArgs& a, const float* fea
             #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 float sv, cv;
-                sincosf(xs[kC + i] * static_cast<float>(1 << j), &sv, &cv);
+                dvgo_dev::pe_sincos(xs[kC + i] * static_cast<float>(1 << j), &sv, &cv);
                 xs[kC + 3 + 6 * j + i] = sv;
                 xs[kC + 6 + 6 * j + i] = cv;
             }
     }
+}
+
+template <int KX>
+__device__ __forceinline__ void sample_inputs(const PosArgs& a, const float* feat, int64_t s, int r,
+                                              float xs[NetLayout<KX>::kS]) {
+    SampleIn in;
+    sample_loads<KX>(a, feat, s, r, in);
+    sample_encode<KX>(a, in, xs);
 }
 
 // Forward: colour of every listed sample.  LDS holds the packed W2.
@@ -1290,70 +1316,78 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0, PosArg
         asm volatile("" ::"v"(r_next));
         #pragma unroll
         for (int u = 0; u < 4; ++u) stage_row(tA, col_s, 4 * q + u, h, d1[u]);
-        if (q == 0 && KX > 0) {
-            // x' = [f, PE_KX(u), PE(d), 1, 0...] -> tB (96 columns, this
-            // lane's half of 24 four-column chunks), the per-sample inputs
-            // evaluated again (every lane, at its clamped sample)
-            float xs[L::kS];
-            sample_inputs<KX>(pa, a.feat, sc, r, xs);
-            const float* per = a.pe + static_cast<int64_t>(r) * 32;
-            auto xval = [&](int j) -> float {
-                if (j < L::kS) return xs[j < L::kS ? j : 0];
-                if (j < L::kIn) return per[j - L::kS];
-                return j == L::kIn ? 1.0f : 0.0f;
-            };
-            constexpr int kChunks = 4 * L::kXT;   // per lane half
-            #pragma unroll
-            for (int kk = 0; kk < kChunks; ++kk) {
-                bf16x4 bv;
-                #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    bv[e] = static_cast<__bf16>(h ? xval(4 * (kChunks + kk) + e) : xval(4 * kk + e));
-                *reinterpret_cast<uint2*>(chunk_at(tB, col_s, kChunks * h + kk)) = __builtin_bit_cast(uint2, bv);
+        // The sample's record: dft[0..3] hold channels 4h .. 4h + 3 of this
+        // half, dft[4..7] (half 0) channels 8..11: half h writes record word
+        // 1 + h, half 0 also words 0 and 3.  Written with fixed register
+        // indices and one float4 store per word (the two halves' stores
+        // merged into one with a lane-dependent register index had become
+        // 16-way selects and four dword stores).
+        auto write_record = [&]() {
+            if (!ok) return;
+            float4* rec = a.rec + (static_cast<int64_t>(slot0) + cr.y) * 4;
+            const float4 oa = *reinterpret_cast<const float4*>(&sD[col_s][4 * h]);
+            rec[1 + h] = make_float4(dft[0] + oa.x, dft[1] + oa.y, dft[2] + oa.z, dft[3] + oa.w);
+            if (h == 0) {
+                const float4 o8 = *reinterpret_cast<const float4*>(&sD[col_s][8]);
+                rec[0] = rh;
+                rec[3] = make_float4(dft[4] + o8.x, dft[5] + o8.y, dft[6] + o8.z, dft[7] + o8.w);
             }
-        }
+        };
         if (q == 0) {
-            if constexpr (KX == 0) {
-            // x' = [f, PE, 1, 0...] -> tB (64 columns, this lane's half of
-            // 8 float4 chunks): half 0 takes f[0..11] and PE[0..19], half 1
-            // PE[20..26] and the constant 1 (stored after the PE) and zeros.
-            // Every lane issues the same unconditional loads; half 1 then
-            // zeroes chunks 2..7.
-            const float4* f4 = reinterpret_cast<const float4*>(a.feat + sc * kC);
-            const float4* p4 = reinterpret_cast<const float4*>(a.pe + static_cast<int64_t>(r) * 32);
-            const float4* c01 = h ? p4 + 5 : f4;
-            float4 v[8] = {c01[0], c01[1], f4[2], p4[0], p4[1], p4[2], p4[3], p4[4]};
-            const uint32_t keep = static_cast<uint32_t>(h) - 1u;   // all ones in half 0, zero in half 1
-            #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                bf16x4 b;
-                b[0] = static_cast<__bf16>(v[k].x);
-                b[1] = static_cast<__bf16>(v[k].y);
-                b[2] = static_cast<__bf16>(v[k].z);
-                b[3] = static_cast<__bf16>(v[k].w);
-                uint2 bits = __builtin_bit_cast(uint2, b);
-                if (k >= 2) {   // a mask, not a branch: both halves run the same code
-                    bits.x &= keep;
-                    bits.y &= keep;
+            if constexpr (KX > 0) {
+                // x' = [f, PE_KX(u), PE(d), 1, 0...] -> tB (96 columns, this
+                // lane's half of 24 four-column chunks), the per-sample
+                // inputs evaluated again (every lane, at its clamped
+                // sample).  Their loads go first, then the record (whose
+                // operands then die before the encoding), then the
+                // arithmetic: a wait on those loads does not include the
+                // record stores.
+                SampleIn in;
+                sample_loads<KX>(pa, a.feat, sc, r, in);
+                write_record();
+                float xs[L::kS];
+                sample_encode<KX>(pa, in, xs);
+                const float* per = a.pe + static_cast<int64_t>(r) * 32;
+                auto xval = [&](int j) -> float {
+                    if (j < L::kS) return xs[j < L::kS ? j : 0];
+                    if (j < L::kIn) return per[j - L::kS];
+                    return j == L::kIn ? 1.0f : 0.0f;
+                };
+                constexpr int kChunks = 4 * L::kXT;   // per lane half
+                #pragma unroll
+                for (int kk = 0; kk < kChunks; ++kk) {
+                    bf16x4 bv;
+                    #pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        bv[e] = static_cast<__bf16>(h ? xval(4 * (kChunks + kk) + e) : xval(4 * kk + e));
+                    *reinterpret_cast<uint2*>(chunk_at(tB, col_s, kChunks * h + kk)) = __builtin_bit_cast(uint2, bv);
                 }
-                *reinterpret_cast<uint2*>(chunk_at(tB, col_s, 8 * h + k)) = bits;
-            }
-            }
-            if (ok) {
-                // dft[0..3] hold channels 4h .. 4h + 3 of this half, dft[4..7]
-                // (half 0) channels 8..11: half h writes record word 1 + h,
-                // half 0 also words 0 and 3.  Written with fixed register
-                // indices and one float4 store per word (the two halves'
-                // stores merged into one with a lane-dependent register
-                // index had become 16-way selects and four dword stores).
-                float4* rec = a.rec + (static_cast<int64_t>(slot0) + cr.y) * 4;
-                const float4 oa = *reinterpret_cast<const float4*>(&sD[col_s][4 * h]);
-                rec[1 + h] = make_float4(dft[0] + oa.x, dft[1] + oa.y, dft[2] + oa.z, dft[3] + oa.w);
-                if (h == 0) {
-                    const float4 o8 = *reinterpret_cast<const float4*>(&sD[col_s][8]);
-                    rec[0] = rh;
-                    rec[3] = make_float4(dft[4] + o8.x, dft[5] + o8.y, dft[6] + o8.z, dft[7] + o8.w);
+            } else {
+                // x' = [f, PE, 1, 0...] -> tB (64 columns, this lane's half of
+                // 8 float4 chunks): half 0 takes f[0..11] and PE[0..19], half 1
+                // PE[20..26] and the constant 1 (stored after the PE) and zeros.
+                // Every lane issues the same unconditional loads; half 1 then
+                // zeroes chunks 2..7.
+                const float4* f4 = reinterpret_cast<const float4*>(a.feat + sc * kC);
+                const float4* p4 = reinterpret_cast<const float4*>(a.pe + static_cast<int64_t>(r) * 32);
+                const float4* c01 = h ? p4 + 5 : f4;
+                float4 v[8] = {c01[0], c01[1], f4[2], p4[0], p4[1], p4[2], p4[3], p4[4]};
+                const uint32_t keep = static_cast<uint32_t>(h) - 1u;   // all ones in half 0, zero in half 1
+                #pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    bf16x4 b;
+                    b[0] = static_cast<__bf16>(v[k].x);
+                    b[1] = static_cast<__bf16>(v[k].y);
+                    b[2] = static_cast<__bf16>(v[k].z);
+                    b[3] = static_cast<__bf16>(v[k].w);
+                    uint2 bits = __builtin_bit_cast(uint2, b);
+                    if (k >= 2) {   // a mask, not a branch: both halves run the same code
+                        bits.x &= keep;
+                        bits.y &= keep;
+                    }
+                    *reinterpret_cast<uint2*>(chunk_at(tB, col_s, 8 * h + k)) = bits;
                 }
+                write_record();
             }
         }
         __syncthreads();   // B7: dz1 and x' rows complete
