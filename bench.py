@@ -267,14 +267,24 @@ def compare_forms(ctx, iters, rays, keep):
     ctx = dict(ctx, compare_iters=iters)
     forms = ("plain", "bf16", "proposal", "skip_pg", "aux", "paper", "paper_bf16") + \
         (("learned_coarse",) if "coarse_learned" in ctx else ())
-    for form in forms:
+
+    def build(form):
         name, bf16, use_prop = FORMS.get(form) or EXTRA_FORMS[form]
         model = new_model(ctx, bf16, skip_pg=form == "skip_pg", aux=form in ("aux", "paper", "paper_bf16"),
                           coarse=ctx["coarse_learned"] if form == "learned_coarse" else None,
                           pe_x=5 if form in ("paper", "paper_bf16") else 0)
+        return name, model, new_proposal(ctx) if use_prop else None
+
+    # every form's code path once on a throwaway state, so that no timed run
+    # pays for first use (code loading, allocator growth) on another's behalf
+    for form in forms:
+        _, model, prop = build(form)
+        experiment.run(model, batches, min(8, iters), prop=prop, record_every=0)
+        del model, prop
+    for form in forms:
+        name, model, prop = build(form)
         if form == "plain":
             experiment.count_uniform(model, batches)
-        prop = new_proposal(ctx) if use_prop else None
         st = experiment.run(model, batches, iters, prop=prop, record_every=100)
         entry = {"seconds": st.seconds, "ms_per_step": 1e3 * st.seconds / iters,
                  "ray_samples_per_s": st.samples_per_s, "psnr_db": experiment.psnr_views(model, views),

@@ -1003,13 +1003,18 @@ __device__ __forceinline__ void load_base2(const float* base, int r, int h, int 
 //
 // With the encoded position (KX > 0) the first layer takes kS1 K steps, the
 // x' rows hold [f, PE_KX(u), PE(d), 1] (three tiles: the q = 0 wavefronts
-// also accumulate tile 2), and the next block's inputs are not prefetched
+// also accumulate tile 2, whose nine non-zero columns share dX with dW3,
+// moved to columns 29..31), and the next block's inputs are not prefetched
 // (its LDS goes to the wider first-layer operand).
 template <int KX>
 __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0, PosArgs pa) {
     using L = NetLayout<KX>;
     constexpr int kS1 = L::kS1;
     constexpr bool kPre = KX == 0;   // the next block's layer-1 inputs prefetched into LDS
+    // dX columns of dW3 (q = 0): 0..2, or 29..31 when x' tile 2 takes
+    // columns 0..8 (x' columns 64..72; its columns 73..95 are zero)
+    constexpr int kW3Col = KX > 0 ? 29 : 0;
+    static_assert(KX == 0 || NetLayout<KX>::kIn + 1 - 64 <= kW3Col, "x' tile 2 and dW3 share dX");
     __shared__ bf16x8 sW2[kW2PackBF16 / 8];
     __shared__ bf16x8 sW2T[kW2PackBF16 / 8];
     __shared__ bf16x8 sW1[4 * kS1 * 64];
@@ -1078,15 +1083,13 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0, PosArg
     const int g = wave & 3, q = wave >> 2;
     const int m = lane & 31, h = lane >> 5;
     const int col_s = g * 32 + m;     // this lane's sample column in the staged block
-    f32x16 dW2[2], dW1, dX;           // dX: dW3 (q = 0) or db2 (q = 1)
-    f32x16 dW1c;                      // KX > 0, q = 0: x' tile 2
+    f32x16 dW2[2], dW1, dX;           // dX: dW3 and (KX > 0) x' tile 2 (q = 0), or db2 (q = 1)
     #pragma unroll
     for (int rr = 0; rr < 16; ++rr) {
         dW2[0][rr] = 0.0f;
         dW2[1][rr] = 0.0f;
         dW1[rr] = 0.0f;
         dX[rr] = 0.0f;
-        dW1c[rr] = 0.0f;
     }
     float db3[3] = {0, 0, 0};
     bf16x8 ones, zero8;
@@ -1259,7 +1262,8 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0, PosArg
             #pragma unroll
             for (int st = 0; st < 8; ++st) {
                 const bf16x8 av = tr_operand(tB, 16 * st, 32 * g, lane);
-                const bf16x8 bv = *reinterpret_cast<const bf16x8*>(sC + (m < 3 ? m : 3) * kBP + 16 * st + 8 * h);
+                const int cm = m - kW3Col;   // dz3 channel of this lane's column (row 3 of sC is zero)
+                const bf16x8 bv = *reinterpret_cast<const bf16x8*>(sC + (cm >= 0 && cm < 3 ? cm : 3) * kBP + 16 * st + 8 * h);
                 dX = mma_bf16(av, bv, dX);
             }
         }
@@ -1395,7 +1399,7 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0, PosArg
         for (int st = 0; st < 8; ++st) {
             const bf16x8 av = tr_operand(tA, 16 * st, 32 * g, lane);
             dW1 = mma_bf16(av, tr_operand(tB, 16 * st, 32 * q, lane), dW1);
-            if (KX > 0 && q == 0) dW1c = mma_bf16(av, tr_operand(tB, 16 * st, 64, lane), dW1c);
+            if (KX > 0 && q == 0) dX = mma_bf16(av, tr_operand(tB, 16 * st, 64, lane), dX);
         }
         __builtin_amdgcn_s_waitcnt(0);   // the next block's copies to sPB, sPF have landed
         __syncthreads();   // B8: rows read before the next block's staging
@@ -1413,10 +1417,10 @@ __global__ __launch_bounds__(512, 2) void mlp_bwd_bf16_kernel(MlpArgs a0, PosArg
         else if (cidx == L::kIn) out[L::kOffB1 + row] = dW1[rr];
         if (KX > 0 && q == 0) {
             const int c2 = 64 + m;
-            if (c2 < L::kIn) out[L::kOffW1 + row * L::kIn + c2] = dW1c[rr];
-            else if (c2 == L::kIn) out[L::kOffB1 + row] = dW1c[rr];
+            if (c2 < L::kIn) out[L::kOffW1 + row * L::kIn + c2] = dX[rr];
+            else if (c2 == L::kIn) out[L::kOffB1 + row] = dX[rr];
         }
-        if (q == 0 && m < 3) out[L::kOffW3 + m * kH + row] = dX[rr];
+        if (q == 0 && m >= kW3Col && m < kW3Col + 3) out[L::kOffW3 + (m - kW3Col) * kH + row] = dX[rr];
         if (q == 1 && m == 0) out[L::kOffB2 + row] = dX[rr];
     }
     if (q == 0) {
