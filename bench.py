@@ -723,7 +723,7 @@ def main():
         out["kernels_roofline"] = {
             k: {f: v for f, v in roofline(per_kernel, k, n_prof, kept, nv, model.st_mlp.p.numel(), bf16,
                                           n_active).items()
-                if f in ("bound", "achieved", "unit", "frac", "launch_ms", "launches_per_step")}
+                if f in ("bound", "achieved", "unit", "frac", "launch_ms", "launches_per_step", "traffic")}
             for k in ROOFLINE_MODELS if k in per_kernel and k != "adam"}
         out["kernels_ms_per_step"] = {k: v["ms_total"] / n_prof for k, v in per_kernel.items()}
     if out_cmp is not None:
