@@ -275,11 +275,11 @@ def compare_forms(ctx, iters, rays, keep):
                           pe_x=5 if form in ("paper", "paper_bf16") else 0)
         return name, model, new_proposal(ctx) if use_prop else None
 
-    # every form's code path once on a throwaway state, so that no timed run
+    # every form's code path on a throwaway state first, so that no timed run
     # pays for first use (code loading, allocator growth) on another's behalf
     for form in forms:
         _, model, prop = build(form)
-        experiment.run(model, batches, min(8, iters), prop=prop, record_every=0)
+        experiment.run(model, batches, min(50, iters), prop=prop, record_every=0)
         del model, prop
     for form in forms:
         name, model, prop = build(form)
