@@ -142,24 +142,45 @@ __device__ __forceinline__ int64_t live_count(const int64_t* n_kept, int64_t cap
 // base[r][i] = b1[i] + sum_q W1[i][view_col+q] * PE(d_r)[q];  pe[r] = [PE(d_r) (27), 1, 0, 0, 0, 0]
 // (view_col: the view part's first column, after the per-sample inputs;
 // w1_in: the row stride of W1)
-// Per-call preparation in one launch: the first kPackThreads/256 workgroups
-// pack the network's operands; each following workgroup takes kPrepRays
-// rays: 12 threads per ray evaluate its 24 sines and cosines once into LDS,
-// then each thread forms one output of the first layer's view part for half
-// of the rays.
-constexpr int kPrepRays = 16;   // rays per workgroup of prep_kernel
-__global__ __launch_bounds__(256) void prep_kernel(PackArgs pk, int pack, const float* __restrict__ rays_d, int B,
-                                                   const float* __restrict__ w1, const float* __restrict__ b1,
-                                                   int w1_in, int view_col, float* __restrict__ base,
-                                                   float* __restrict__ pe, int* __restrict__ zero, int64_t nzero,
-                                                   int zblocks) {
+// Per-call preparation, one workgroup role per block: the first
+// kPackThreads/256 workgroups pack the network's operands; each following
+// workgroup takes kPrepRays rays: 12 threads per ray evaluate its 24 sines
+// and cosines once into LDS, then each thread forms one output of the first
+// layer's view part for half of the rays; the last zblocks workgroups clear
+// the backward's cell counts.
+constexpr int kPrepRays = 16;   // rays per workgroup of the preparation
+struct PrepArgs {
+    PackArgs pk;
+    const float* rays_d;
+    int B;
+    const float* w1;
+    const float* b1;
+    int w1_in;      // row stride of W1
+    int view_col;   // first column of W1's view part
+    float* base;
+    float* pe;
+    int* zero;      // cleared (NULL: none)
+    int64_t nzero;
+    int zblocks;
+    int blocks;     // workgroups of the preparation
+};
+
+__device__ __forceinline__ void prep_body(const PrepArgs& P, int blk) {
     constexpr int kPackBlocks = kPackThreads / 256;
-    if (pack && static_cast<int>(blockIdx.x) < kPackBlocks) {
-        pack_weights(pk, blockIdx.x * 256 + threadIdx.x);
+    if (blk < kPackBlocks) {
+        pack_weights(P.pk, blk * 256 + threadIdx.x);
         return;
     }
+    const int B = P.B, w1_in = P.w1_in, view_col = P.view_col, zblocks = P.zblocks;
+    const float* __restrict__ rays_d = P.rays_d;
+    const float* __restrict__ w1 = P.w1;
+    const float* __restrict__ b1 = P.b1;
+    float* __restrict__ base = P.base;
+    float* __restrict__ pe = P.pe;
+    int* __restrict__ zero = P.zero;
+    const int64_t nzero = P.nzero;
     const int ray_blocks = (B + kPrepRays - 1) / kPrepRays;
-    const int zb = static_cast<int>(blockIdx.x) - (pack ? kPackBlocks : 0) - ray_blocks;
+    const int zb = blk - kPackBlocks - ray_blocks;
     if (zb >= 0) {   // the last zblocks workgroups clear `zero` (the backward's cell counts)
         const int64_t stride = static_cast<int64_t>(zblocks) * 256, first = static_cast<int64_t>(zb) * 256 + threadIdx.x;
         int64_t done = 0;
@@ -174,7 +195,7 @@ __global__ __launch_bounds__(256) void prep_kernel(PackArgs pk, int pack, const 
     }
     __shared__ float se[kPrepRays][32];
     const int t = threadIdx.x;
-    const int r0 = kPrepRays * (static_cast<int>(blockIdx.x) - (pack ? kPackBlocks : 0));
+    const int r0 = kPrepRays * (blk - kPackBlocks);
     if (t < 12 * kPrepRays) {
         const int rr = t / 12, q = t % 12, fq = q / 3, c = q % 3;
         const int r = r0 + rr;
@@ -212,6 +233,8 @@ __global__ __launch_bounds__(256) void prep_kernel(PackArgs pk, int pack, const 
     }
 }
 
+__global__ __launch_bounds__(256) void prep_kernel(PrepArgs P) { prep_body(P, blockIdx.x); }
+
 // ---------------------------------------------------------------------------
 // gather: raw density and interpolated features per sample
 // ---------------------------------------------------------------------------
@@ -230,12 +253,13 @@ struct GatherArgs {
 
 // kFeat: 0 density only, 1 float32 features, 2 bfloat16 features.  One
 // instantiation per case, so that every corner load of a sample (density and
-// features) is issued before any of them is consumed.
+// features) is issued before any of them is consumed.  Workgroup blk of nblk
+// takes samples blk*256 + thread, then every nblk*256-th.
 template <int kFeat>
-__global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
+__device__ __forceinline__ void gather_body(const GatherArgs& a, int blk, int nblk) {
     const int64_t n = live_count(a.n_kept, a.cap);
-    for (int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; s < n;
-         s += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    for (int64_t s = static_cast<int64_t>(blk) * blockDim.x + threadIdx.x; s < n;
+         s += static_cast<int64_t>(nblk) * blockDim.x) {
         const int r = a.sa.sample_ray[s];
         const int k = a.sa.sample_k[s];
         float x[3];
@@ -284,6 +308,20 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
         out[1] = f[1];
         out[2] = f[2];
     }
+}
+
+template <int kFeat>
+__global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) { gather_body<kFeat>(a, blockIdx.x, gridDim.x); }
+
+// The gather and the per-call preparation in one launch (the two are
+// independent: the preparation's workgroups fill the gather's latency-bound
+// schedule, 6-9 us per training step at the full configuration): the first
+// gather_blocks workgroups gather, the others prepare.
+template <int kFeat>
+__global__ __launch_bounds__(256) void prep_gather_kernel(PrepArgs P, GatherArgs a, int gather_blocks) {
+    const int blk = static_cast<int>(blockIdx.x);
+    if (blk < gather_blocks) gather_body<kFeat>(a, blk, gather_blocks);
+    else prep_body(P, blk - gather_blocks);
 }
 
 // ---------------------------------------------------------------------------
@@ -1118,10 +1156,12 @@ int grid_adam_blocks(int64_t nv) {
     return static_cast<int>(8 * b);
 }
 
-int32_t run_prep(const Common& cm, const dvgo_mlp* mlp, hipStream_t s, int* zero = nullptr, int64_t nzero = 0) {
-    float* base = reinterpret_cast<float*>(cm.ws + cm.L.base);
-    float* pe = reinterpret_cast<float*>(cm.ws + cm.L.pe);
-    if (mlp) {
+// The preparation's arguments (mlp != NULL).
+PrepArgs prep_args(const Common& cm, const dvgo_mlp* mlp, int* zero, int64_t nzero) {
+    PrepArgs P;
+    P.base = reinterpret_cast<float*>(cm.ws + cm.L.base);
+    P.pe = reinterpret_cast<float*>(cm.ws + cm.L.pe);
+    {
         PackArgs pk;
         pk.w1 = mlp->w1;
         pk.w2 = mlp->w2;
@@ -1142,9 +1182,25 @@ int32_t run_prep(const Common& cm, const dvgo_mlp* mlp, hipStream_t s, int* zero
         pk.w1_q = xpe ? NetLayout<kMaxKX>::kQ1 : NetLayout<0>::kQ1;
         pk.w1_s1 = xpe ? NetLayout<kMaxKX>::kS1 : NetLayout<0>::kS1;
         const int zblocks = zero ? grid_for(nzero, 256, dvgo::device_cu_count() * 4) : 0;
-        const unsigned blocks = static_cast<unsigned>(kPackThreads / 256 + (cm.B + kPrepRays - 1) / kPrepRays + zblocks);
-        DVGO_LAUNCH(K_RAY_BASE, prep_kernel, dim3(blocks), dim3(256), 0, s, pk, 1, cm.sa.rays_d, cm.B, mlp->w1,
-                    mlp->b1, pk.w1_in, pk.w1_ns, base, pe, zero, nzero, zblocks);
+        P.pk = pk;
+        P.rays_d = cm.sa.rays_d;
+        P.B = cm.B;
+        P.w1 = mlp->w1;
+        P.b1 = mlp->b1;
+        P.w1_in = pk.w1_in;
+        P.view_col = pk.w1_ns;
+        P.zero = zero;
+        P.nzero = nzero;
+        P.zblocks = zblocks;
+        P.blocks = kPackThreads / 256 + (cm.B + kPrepRays - 1) / kPrepRays + zblocks;
+    }
+    return P;
+}
+
+int32_t run_prep(const Common& cm, const dvgo_mlp* mlp, hipStream_t s, int* zero = nullptr, int64_t nzero = 0) {
+    if (mlp) {
+        const PrepArgs P = prep_args(cm, mlp, zero, nzero);
+        DVGO_LAUNCH(K_RAY_BASE, prep_kernel, dim3(P.blocks), dim3(256), 0, s, P);
         if (int32_t st = dvgo::launch_status()) return st;
     } else if (zero) {
         DVGO_LAUNCH(K_CELL_SCAN, fill_int_kernel, dim3(grid_for(nzero, 256, dvgo::device_cu_count() * 8)), dim3(256),
@@ -1154,9 +1210,7 @@ int32_t run_prep(const Common& cm, const dvgo_mlp* mlp, hipStream_t s, int* zero
     return DVGO_OK;
 }
 
-int32_t run_gather(const Common& cm, const dvgo_field* field, bool with_feat, const int64_t* n_kept,
-                   hipStream_t s) {
-    if (cm.cap == 0) return DVGO_OK;
+GatherArgs gather_args(const Common& cm, const dvgo_field* field, bool with_feat, const int64_t* n_kept) {
     GatherArgs ga;
     ga.sa = cm.sa;
     ga.g = cm.g;
@@ -1168,10 +1222,36 @@ int32_t run_gather(const Common& cm, const dvgo_field* field, bool with_feat, co
     ga.cap = cm.cap;
     ga.raw_out = reinterpret_cast<float*>(cm.ws + cm.L.raw);
     ga.feat_out = reinterpret_cast<float*>(cm.ws + cm.L.feat);
-    const int blocks = grid_for(cm.cap, 256, dvgo::device_cu_count() * 16);
+    return ga;
+}
+
+int gather_blocks(const Common& cm) { return grid_for(cm.cap, 256, dvgo::device_cu_count() * 16); }
+
+int32_t run_gather(const Common& cm, const dvgo_field* field, bool with_feat, const int64_t* n_kept,
+                   hipStream_t s) {
+    if (cm.cap == 0) return DVGO_OK;
+    const GatherArgs ga = gather_args(cm, field, with_feat, n_kept);
+    const int blocks = gather_blocks(cm);
     if (!with_feat) DVGO_LAUNCH(K_GATHER, gather_kernel<0>, dim3(blocks), dim3(256), 0, s, ga);
     else if (!ga.feat_bf16) DVGO_LAUNCH(K_GATHER, gather_kernel<1>, dim3(blocks), dim3(256), 0, s, ga);
     else DVGO_LAUNCH(K_GATHER, gather_kernel<2>, dim3(blocks), dim3(256), 0, s, ga);
+    return dvgo::launch_status();
+}
+
+// The preparation and the gather of a render with a network, in one launch
+// (the gather's workgroups first); without a network or samples, each alone.
+int32_t run_prep_gather(const Common& cm, const dvgo_mlp* mlp, const dvgo_field* field, const int64_t* n_kept,
+                        hipStream_t s, int* zero = nullptr, int64_t nzero = 0) {
+    if (!mlp || cm.cap == 0) {
+        if (int32_t st = run_prep(cm, mlp, s, zero, nzero)) return st;
+        return run_gather(cm, field, mlp != nullptr, n_kept, s);
+    }
+    const PrepArgs P = prep_args(cm, mlp, zero, nzero);
+    const GatherArgs ga = gather_args(cm, field, true, n_kept);
+    const int gb = gather_blocks(cm);
+    const dim3 grid(static_cast<unsigned>(gb + P.blocks));
+    if (ga.feat_bf16) DVGO_LAUNCH(K_GATHER, prep_gather_kernel<2>, grid, dim3(256), 0, s, P, ga, gb);
+    else DVGO_LAUNCH(K_GATHER, prep_gather_kernel<1>, grid, dim3(256), 0, s, P, ga, gb);
     return dvgo::launch_status();
 }
 
@@ -1364,8 +1444,7 @@ int32_t render_bwd_impl(const dvgo_field* field, const dvgo_mlp* mlp, const floa
     if (mlp) ma = make_mlp_args(cm, mlp, n_kept);
     if (!forward_done) {
         // prep (packing, per-ray encoding) also clears the cell counts
-        if (int32_t st = run_prep(cm, mlp, s, bins.cell_count, bins.ncell + 1)) return st;
-        if (int32_t st = run_gather(cm, field, mlp != nullptr, n_kept, s)) return st;
+        if (int32_t st = run_prep_gather(cm, mlp, field, n_kept, s, bins.cell_count, bins.ncell + 1)) return st;
         if (mlp) {
             launch_mlp_fwd(ma, make_pos_args(cm), mlp->pe_x, dvgo::device_cu_count(), s);
             if (int32_t st = dvgo::launch_status()) return st;
@@ -1452,8 +1531,7 @@ int32_t dvgo_render_fwd(const dvgo_field* field, const dvgo_mlp* mlp, const floa
     if (B == 0) return DVGO_OK;
     Common cm = make_common(field, rays_o, rays_d, jitter, t_near, sample_ray, sample_k, capacity, B, step,
                             workspace);
-    if (int32_t st = run_prep(cm, mlp, s)) return st;
-    if (int32_t st = run_gather(cm, field, mlp != nullptr, n_kept, s)) return st;
+    if (int32_t st = run_prep_gather(cm, mlp, field, n_kept, s)) return st;
     if (mlp && capacity > 0) {
         MlpArgs ma = make_mlp_args(cm, mlp, n_kept);
         launch_mlp_fwd(ma, make_pos_args(cm), mlp->pe_x, dvgo::device_cu_count(), s);
@@ -1564,8 +1642,7 @@ int32_t dvgo_train_step(const dvgo_field* field, const dvgo_mlp* mlp, const floa
     Common cm = make_common(field, rays_o, rays_d, jitter, t_near, sample_ray, sample_k, capacity, B, step,
                             workspace);
     const Bins bins = bins_of(cm, field);
-    if (int32_t st = run_prep(cm, mlp, s, bins.cell_count, bins.ncell + 1)) return st;
-    if (int32_t st = run_gather(cm, field, true, n_kept, s)) return st;
+    if (int32_t st = run_prep_gather(cm, mlp, field, n_kept, s, bins.cell_count, bins.ncell + 1)) return st;
     MlpArgs ma = make_mlp_args(cm, mlp, n_kept);
     launch_mlp_fwd(ma, make_pos_args(cm), mlp->pe_x, dvgo::device_cu_count(), s);
     if (int32_t st = dvgo::launch_status()) return st;
