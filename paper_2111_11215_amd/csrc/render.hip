@@ -757,7 +757,7 @@ struct GridAdamArgs {
 // and p - lr * 0 / (0 + eps) = p, so skipping it changes no bit, and its
 // parameters and moments are neither read nor written.  A vertex that takes
 // a step with any non-zero gradient gets its bit set.
-__global__ __launch_bounds__(256) void vertex_adam_kernel(BinArgs a, GridAdamArgs o) {
+__device__ __forceinline__ void vertex_adam_body(const BinArgs& a, const GridAdamArgs& o, int blk, int nblk) {
     __shared__ float4 sg[4][64 * 3];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int ny = a.g.n[1], nz = a.g.n[2];
@@ -779,7 +779,7 @@ __global__ __launch_bounds__(256) void vertex_adam_kernel(BinArgs a, GridAdamArg
     // 8; every wave's first vertex is a multiple of 64, so a wave owns two
     // whole words of the activity mask.
     const int64_t kChunk = (2 * static_cast<int64_t>(ny) * nz + 255) / 256 * 256;
-    const int xcd = blockIdx.x & 7, nloc = gridDim.x >> 3, loc = blockIdx.x >> 3;
+    const int xcd = blk & 7, nloc = nblk >> 3, loc = blk >> 3;
     const int64_t nchunk = (nv + kChunk - 1) / kChunk;
     const int64_t mine = nchunk > xcd ? (nchunk - xcd + 7) / 8 : 0;   // chunks of this XCD
     const int64_t hi = nv;
@@ -891,6 +891,10 @@ __global__ __launch_bounds__(256) void vertex_adam_kernel(BinArgs a, GridAdamArg
         }
         __syncthreads();
     }
+}
+
+__global__ __launch_bounds__(256) void vertex_adam_kernel(BinArgs a, GridAdamArgs o) {
+    vertex_adam_body(a, o, blockIdx.x, gridDim.x);
 }
 
 // Activity mask from given moments: bit v set iff any of vertex v's 26
@@ -1018,30 +1022,50 @@ struct NetAdam {
     dvgo::AdamCoef c;
 };
 
-__global__ __launch_bounds__(1024) void reduce_partials_kernel(const float* __restrict__ partial, int nblk,
-                                                               int nparams, int pstride, float* __restrict__ out,
-                                                               const float* __restrict__ sq_err, int B,
-                                                               float* __restrict__ loss, NetAdam net) {
-    __shared__ float sh[16][64];
+struct ReduceArgs {
+    const float* partial;   // [nblk][pstride]
+    int nblk, nparams, pstride;
+    float* out;             // the flat gradient (accumulated), or zeroed after the Adam step
+    const float* sq_err;    // per-ray squared errors (NULL: no loss)
+    int B;
+    float* loss;
+    NetAdam net;
+};
+
+// Workgroup blk (256 threads) sums the partials of parameters blk*64 ..
+// blk*64 + 63 in a fixed order: wavefront w takes rows w, w + 4, ...
+// (sixteen loads in flight at a time), then wavefront 0 adds the four sums
+// in order; with net.param it then takes the Adam step.  Workgroup 0 also
+// sums the squared errors into the loss.
+__device__ __forceinline__ void reduce_body(const ReduceArgs& R, int blk) {
+    __shared__ float sh[4][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int p = blockIdx.x * 64 + lane;
-    static_assert(kMaxBwdBlocks <= 16 * 16, "a wavefront sums at most 16 partial rows");
+    const int p = blk * 64 + lane;
+    const int nblk = R.nblk, nparams = R.nparams, pstride = R.pstride, B = R.B;
+    const float* __restrict__ partial = R.partial;
+    float* __restrict__ out = R.out;
+    const float* __restrict__ sq_err = R.sq_err;
+    const NetAdam& net = R.net;
+    static_assert(kMaxBwdBlocks <= 4 * 64, "a wavefront sums at most 64 partial rows");
     float s = 0.0f;
     if (p < nparams) {
-        float v[16];
         #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int b = wave + 16 * u;
-            v[u] = b < nblk ? partial[static_cast<int64_t>(b) * pstride + p] : 0.0f;
+        for (int u0 = 0; u0 < 64; u0 += 16) {
+            float v[16];
+            #pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int b = wave + 4 * (u0 + u);
+                v[u] = b < nblk ? partial[static_cast<int64_t>(b) * pstride + p] : 0.0f;
+            }
+            #pragma unroll
+            for (int u = 0; u < 16; ++u) s += v[u];
         }
-        #pragma unroll
-        for (int u = 0; u < 16; ++u) s += v[u];
     }
     sh[wave][lane] = s;
     __syncthreads();
     if (wave == 0 && p < nparams) {
         float t = 0.0f;
-        for (int w = 0; w < 16; ++w) t += sh[w][lane];
+        for (int w = 0; w < 4; ++w) t += sh[w][lane];
         const float g = out[p] + t;
         if (net.param) {
             float pp = net.param[p], mm = net.m[p], vv = net.v[p];
@@ -1054,13 +1078,13 @@ __global__ __launch_bounds__(1024) void reduce_partials_kernel(const float* __re
             out[p] = g;
         }
     }
-    if (blockIdx.x == 0 && sq_err) {
+    if (blk == 0 && sq_err) {
         __syncthreads();
         float e = 0.0f;
-        for (int i0 = threadIdx.x; i0 < B; i0 += 1024 * 8) {   // eight loads in flight, summed in order
+        for (int i0 = threadIdx.x; i0 < B; i0 += 256 * 8) {   // eight loads in flight, summed in order
             float v[8];
             #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = i0 + 1024 * u < B ? sq_err[i0 + 1024 * u] : 0.0f;
+            for (int u = 0; u < 8; ++u) v[u] = i0 + 256 * u < B ? sq_err[i0 + 256 * u] : 0.0f;
             #pragma unroll
             for (int u = 0; u < 8; ++u) e += v[u];
         }
@@ -1069,10 +1093,22 @@ __global__ __launch_bounds__(1024) void reduce_partials_kernel(const float* __re
         __syncthreads();
         if (threadIdx.x == 0) {
             float t = 0.0f;
-            for (int w = 0; w < 16; ++w) t += sh[0][w];
-            if (loss) *loss = t * (1.0f / static_cast<float>(B));
+            for (int w = 0; w < 4; ++w) t += sh[0][w];
+            if (R.loss) *R.loss = t * (1.0f / static_cast<float>(B));
         }
     }
+}
+
+__global__ __launch_bounds__(256) void reduce_partials_kernel(ReduceArgs R) { reduce_body(R, blockIdx.x); }
+
+// The fused grid Adam and the reduction of the network's gradient partials
+// in one launch (independent of each other): the first vblocks workgroups
+// step the grids, the rest reduce, filling the grid step's tail.
+__global__ __launch_bounds__(256) void vertex_adam_reduce_kernel(BinArgs a, GridAdamArgs o, int vblocks,
+                                                                 ReduceArgs R) {
+    const int blk = static_cast<int>(blockIdx.x);
+    if (blk < vblocks) vertex_adam_body(a, o, blk, vblocks);
+    else reduce_body(R, blk - vblocks);
 }
 
 // ---------------------------------------------------------------------------
@@ -1381,7 +1417,7 @@ int32_t run_cell_scan(const Common& cm, const Bins& b, hipStream_t s) {
 // the grids' fused Adam step.
 int32_t run_vertex(const Common& cm, const dvgo_field* field, const Bins& b, bool with_feat, bool place,
                    const int64_t* n_kept, float* grad_density, float* grad_feat, const GridAdamArgs* opt,
-                   hipStream_t s) {
+                   hipStream_t s, const ReduceArgs* red = nullptr) {
     BinArgs ba;
     ba.sa = cm.sa;
     ba.g = cm.g;
@@ -1402,7 +1438,11 @@ int32_t run_vertex(const Common& cm, const dvgo_field* field, const Bins& b, boo
         if (int32_t st = dvgo::launch_status()) return st;
     }
     const int64_t nv = static_cast<int64_t>(field->box.n[0]) * field->box.n[1] * field->box.n[2];
-    if (opt)
+    if (opt && red) {
+        const int vb = grid_adam_blocks(nv);
+        DVGO_LAUNCH(K_GRID_ADAM, vertex_adam_reduce_kernel, dim3(vb + (red->nparams + 63) / 64), dim3(256), 0, s, ba,
+                    *opt, vb, *red);
+    } else if (opt)
         DVGO_LAUNCH(K_GRID_ADAM, vertex_adam_kernel, dim3(grid_adam_blocks(nv)), dim3(256), 0, s, ba, *opt);
     else
         DVGO_LAUNCH(K_SCATTER, vertex_gather_kernel, dim3(grid_for(nv, 256, cus * 16)), dim3(256), 0, s, ba);
@@ -1477,18 +1517,27 @@ int32_t render_bwd_impl(const dvgo_field* field, const dvgo_mlp* mlp, const floa
         launch_mlp_bwd(ma, make_pos_args(cm), mlp->pe_x, nblk, s);
         if (int32_t st = dvgo::launch_status()) return st;
     }
-    if (int32_t st = run_vertex(cm, field, bins, mlp != nullptr, mlp == nullptr, n_kept, grad_density, grad_feat, opt,
-                                s))
-        return st;
+    ReduceArgs red{};
     if (mlp) {
-        NetAdam na{};
-        if (net) na = *net;
+        red.net = NetAdam{};
+        if (net) red.net = *net;
         const bool xpe = mlp->pe_x == kMaxKX;
-        const int nparams = xpe ? NetLayout<kMaxKX>::kParams : kMlpParams;
-        const int pstride = xpe ? NetLayout<kMaxKX>::kPStride : kPStride;
-        DVGO_LAUNCH(K_REDUCE, reduce_partials_kernel, dim3((nparams + 63) / 64), dim3(1024), 0, s,
-                    reinterpret_cast<const float*>(cm.ws + cm.L.partial), nblk, nparams, pstride, grad_mlp, sq_err,
-                    B, loss, na);
+        red.partial = reinterpret_cast<const float*>(cm.ws + cm.L.partial);
+        red.nblk = nblk;
+        red.nparams = xpe ? NetLayout<kMaxKX>::kParams : kMlpParams;
+        red.pstride = xpe ? NetLayout<kMaxKX>::kPStride : kPStride;
+        red.out = grad_mlp;
+        red.sq_err = sq_err;
+        red.B = B;
+        red.loss = loss;
+    }
+    // with the fused grid Adam, the network's reduction rides in its launch
+    const bool merged = mlp && opt;
+    if (int32_t st = run_vertex(cm, field, bins, mlp != nullptr, mlp == nullptr, n_kept, grad_density, grad_feat, opt,
+                                s, merged ? &red : nullptr))
+        return st;
+    if (mlp && !merged) {
+        DVGO_LAUNCH(K_REDUCE, reduce_partials_kernel, dim3((red.nparams + 63) / 64), dim3(256), 0, s, red);
         if (int32_t st = dvgo::launch_status()) return st;
     }
     return DVGO_OK;
