@@ -56,6 +56,15 @@ BYTES_GATHER_BF16 = 8 * 4 + 8 * 24 + (4 + 48) + 8
 # written (24 B); bfloat16 copy 2 B per feature; binned sample records 64 B
 BYTES_GRID_ADAM_VERTEX = 24 * 13
 BYTES_REC = 64
+# launched with the grid Adam: the network's gradient reduction, per
+# parameter one float per partial row read, the flat gradient read and
+# cleared, p, m, v read and written
+BYTES_REDUCE_PARAM_FIXED = 4 + 4 + 24
+# launched with the fine pass's gather: the preparation, per ray the
+# direction read and the first layer's view part (128 floats) and encoding
+# (32 floats) written; the cleared cell counts; the packed operands
+BYTES_PREP_RAY = 12 + 128 * 4 + 32 * 4
+BYTES_PREP_PACK = 2 * 16384 * 4 + 2 * 16384 * 2 + 4 * 2 * 64 * 4 + 4 * 64 * 8 * 2
 PEAK = {"hbm": 8000.0, "f32": 157.3, "bf16": 2500.0}
 
 
@@ -493,12 +502,23 @@ def measured_traffic(kname):
     return rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
-def roofline(per_kernel, kname, n_prof, kept, nv, n_mlp, bf16, n_step=None):
+def partial_rows():
+    """Per-workgroup rows of the network adjoint's gradient partials: one
+    workgroup per compute unit, at most 256."""
+    import torch
+    return min(torch.cuda.get_device_properties(0).multi_processor_count, 256)
+
+
+def roofline(per_kernel, kname, n_prof, kept, nv, n_mlp, bf16, n_step=None, rays=0, rows=256):
     """Achieved rate of the named kernel: algorithmic work per launch over
     its event-timed average launch duration.  ``kept`` = evaluated samples
     per step, ``nv`` = grid vertices, ``n_step`` = vertices that take the
     grid Adam step (those with non-zero moments or samples; the others'
-    step changes nothing and moves no byte), all of them when None."""
+    step changes nothing and moves no byte), all of them when None.  Where
+    the library launches the network's gradient reduction with the grid
+    Adam (no launch of its own) or the preparation with the gather, their
+    bytes count with that launch (``rays`` rays per step, ``rows``
+    per-workgroup partial rows)."""
     k = per_kernel[kname]
     lps = k["launches"] / n_prof            # launches per step
     if kname in ("mlp_bwd", "mlp_fwd"):
@@ -512,11 +532,16 @@ def roofline(per_kernel, kname, n_prof, kept, nv, n_mlp, bf16, n_step=None):
             work = BYTES_GRID_ADAM_VERTEX * ns + (2 * 12 * ns if bf16 else 0) + BYTES_REC * kept
             if n_step is not None:
                 work += 2 * ((nv + 31) // 32) * 4      # activity mask read and written
+            if "reduce" not in per_kernel or per_kernel["reduce"]["launches"] == 0:
+                work += (4 * rows + BYTES_REDUCE_PARAM_FIXED) * n_mlp + 4 * rays
         elif kname == "adam":
             work = 32 * n_mlp + ((32 * 13 * nv + (2 * 12 * nv if bf16 else 0)) if "grid_adam" not in per_kernel
                                  or per_kernel["grid_adam"]["launches"] == 0 else 0)
         elif kname == "gather":
             work = (BYTES_GATHER_BF16 if bf16 else BYTES_GATHER_F32) * kept
+            if "ray_base" not in per_kernel or per_kernel["ray_base"]["launches"] == 0:
+                n1 = round(nv ** (1.0 / 3.0)) - 1
+                work += BYTES_PREP_RAY * rays + 4 * (n1 ** 3 + 1) + BYTES_PREP_PACK + 4 * n_mlp
         else:
             work = BYTES_SCATTER * kept
         work /= lps
@@ -569,7 +594,8 @@ def measure_config(ctx, model, batches, warmup, steps, bf16, n_prof=2):
             "ms_per_step": 1e3 * st.seconds / steps, "ray_samples_per_s": st.samples_per_s,
             "evaluated_samples_per_step": kept, "grid_vertices_stepped": n_active, "grid_vertices": nv,
             "kernels_roofline": {k: {f: v for f, v in roofline(per_kernel, k, n_prof, kept, nv,
-                                                                model.st_mlp.p.numel(), bf16, n_active).items()
+                                                                model.st_mlp.p.numel(), bf16, n_active,
+                                                                int(batches[0].o.shape[0]), partial_rows()).items()
                                      if f in ("bound", "achieved", "peak", "unit", "frac", "launch_ms")}
                                  for k in per_kernel}}
 
@@ -719,10 +745,11 @@ def main():
         if kname == "auto":
             kname = max((k for k in ROOFLINE_MODELS if k in per_kernel), key=lambda k: per_kernel[k]["ms_total"])
         nv = ctx["n"] ** 3
-        out["roofline"] = roofline(per_kernel, kname, n_prof, kept, nv, model.st_mlp.p.numel(), bf16, n_active)
+        out["roofline"] = roofline(per_kernel, kname, n_prof, kept, nv, model.st_mlp.p.numel(), bf16, n_active,
+                                   args.rays, partial_rows())
         out["kernels_roofline"] = {
             k: {f: v for f, v in roofline(per_kernel, k, n_prof, kept, nv, model.st_mlp.p.numel(), bf16,
-                                          n_active).items()
+                                          n_active, args.rays, partial_rows()).items()
                 if f in ("bound", "achieved", "unit", "frac", "launch_ms", "launches_per_step", "traffic")}
             for k in ROOFLINE_MODELS if k in per_kernel and k != "adam"}
         out["kernels_ms_per_step"] = {k: v["ms_total"] / n_prof for k, v in per_kernel.items()}
