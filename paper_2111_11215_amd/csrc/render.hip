@@ -400,11 +400,12 @@ __device__ __forceinline__ int run_rank(int cell, bool ok, int lane, int* __rest
     return rbase + lane - leader;
 }
 
-__global__ __launch_bounds__(256) void compose_fwd_kernel(ComposeArgs a) {
-    __shared__ float segs[4][32];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int slot = blockIdx.x * 4 + wave;
-    if (slot >= a.B) return;
+// Forward compositing of ray slot `slot` by one wavefront (segs: its 32
+// segment sums in LDS).  With a.target it also forms the photometric
+// gradient dL/dC; every lane returns that gradient in g and log T_end in
+// *log_t_end (what a fused adjoint needs).
+__device__ __forceinline__ void compose_fwd_ray(const ComposeArgs& a, int slot, int lane, float* segs, float g[3],
+                                                float* log_t_end) {
     const int64_t n = live_count(a.n_kept, a.cap);
     const int r = a.perm[slot];
     int64_t s0 = a.ray_offset[slot], s1 = a.ray_offset[slot + 1];
@@ -414,7 +415,7 @@ __global__ __launch_bounds__(256) void compose_fwd_kernel(ComposeArgs a) {
     const float tn = a.sa.t_near[r];
     const float p = a.sa.jitter ? a.sa.jitter[r] : 0.0f;
     const float step = a.sa.step;
-    if (lane < 32) segs[wave][lane] = 0.0f;
+    if (lane < 32) segs[lane] = 0.0f;
     __builtin_amdgcn_wave_barrier();
     float logT = 0.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f, dep = 0.0f, accw = 0.0f, ptl = 0.0f;
     float tg[3] = {0.0f, 0.0f, 0.0f};
@@ -446,7 +447,7 @@ __global__ __launch_bounds__(256) void compose_fwd_kernel(ComposeArgs a) {
             const float e0 = c0 - tg[0], e1 = c1 - tg[1], e2 = c2 - tg[2];
             ptl += w * (e0 * e0 + e1 * e1 + e2 * e2);
         }
-        if (ok && a.seg_w) atomicAdd(&segs[wave][(32LL * k) / nu], w);
+        if (ok && a.seg_w) atomicAdd(&segs[(32LL * k) / nu], w);
         if (ok && a.sample_w) a.sample_w[s] = w;
         logT -= lane_value(incl, 63);
     }
@@ -455,34 +456,51 @@ __global__ __launch_bounds__(256) void compose_fwd_kernel(ComposeArgs a) {
     accw = wave_sum(accw);
     if (a.w_pt > 0.0f) ptl = wave_sum(ptl);
     __builtin_amdgcn_wave_barrier();
-    if (lane == 0) {
-        const float T = expf(logT);
-        if (a.rgb) {
-            const float c3[3] = {cr + T * a.bg[0], cg + T * a.bg[1], cb + T * a.bg[2]};
+    // the ray's colour and loss terms, in every lane (the stores from lane 0)
+    const float T = expf(logT);
+    g[0] = g[1] = g[2] = 0.0f;
+    *log_t_end = logT;
+    if (a.rgb) {
+        const float c3[3] = {cr + T * a.bg[0], cg + T * a.bg[1], cb + T * a.bg[2]};
+        if (lane == 0) {
             a.rgb[3 * r + 0] = c3[0];
             a.rgb[3 * r + 1] = c3[1];
             a.rgb[3 * r + 2] = c3[2];
-            if (a.target) {   // Eq. photo_loss: gradient 2 (C - C*)/B, as dvgo_photo_loss forms it
-                const float invB = 1.0f / static_cast<float>(a.B);
-                float e2 = 0.0f;
-                for (int c = 0; c < 3; ++c) {
-                    const float d = c3[c] - a.target[3 * r + c];
-                    a.grad_rgb_out[3 * r + c] = 2.0f * d * invB;
-                    e2 += d * d;
-                }
-                if (a.w_pt > 0.0f) e2 += a.w_pt * ptl;
-                if (a.w_bg > 0.0f) {   // background entropy of T_end, clamped to [1e-6, 1 - 1e-6]
-                    const float pb = fminf(fmaxf(T, 1e-6f), 1.0f - 1e-6f);
-                    e2 += a.w_bg * (-pb * logf(pb) - (1.0f - pb) * log1pf(-pb));
-                }
+        }
+        if (a.target) {   // Eq. photo_loss: gradient 2 (C - C*)/B, as dvgo_photo_loss forms it
+            const float invB = 1.0f / static_cast<float>(a.B);
+            float e2 = 0.0f;
+            for (int c = 0; c < 3; ++c) {
+                const float d = c3[c] - a.target[3 * r + c];
+                g[c] = 2.0f * d * invB;
+                e2 += d * d;
+            }
+            if (a.w_pt > 0.0f) e2 += a.w_pt * ptl;
+            if (a.w_bg > 0.0f) {   // background entropy of T_end, clamped to [1e-6, 1 - 1e-6]
+                const float pb = fminf(fmaxf(T, 1e-6f), 1.0f - 1e-6f);
+                e2 += a.w_bg * (-pb * logf(pb) - (1.0f - pb) * log1pf(-pb));
+            }
+            if (lane == 0) {
+                for (int c = 0; c < 3; ++c) a.grad_rgb_out[3 * r + c] = g[c];
                 a.sq_err[r] = e2;
             }
         }
+    }
+    if (lane == 0) {
         if (a.depth) a.depth[r] = dep;
         if (a.acc) a.acc[r] = accw;
         a.log_t_end[r] = logT;
     }
-    if (a.seg_w && lane < 32) a.seg_w[static_cast<int64_t>(r) * 32 + lane] = segs[wave][lane];
+    if (a.seg_w && lane < 32) a.seg_w[static_cast<int64_t>(r) * 32 + lane] = segs[lane];
+}
+
+__global__ __launch_bounds__(256) void compose_fwd_kernel(ComposeArgs a) {
+    __shared__ float segs[4][32];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int slot = blockIdx.x * 4 + wave;
+    if (slot >= a.B) return;
+    float g[3], lt;
+    compose_fwd_ray(a, slot, lane, segs[wave], g, &lt);
 }
 
 // Backward of compose: walk each ray from its end in 64-sample steps,
@@ -498,10 +516,11 @@ __device__ __forceinline__ float sd_of(const ComposeArgs& a, int64_t s, int64_t 
     return s < s1 ? softplus_f(a.raw[s] + a.act_shift) * a.sa.step : 0.0f;
 }
 
-__global__ __launch_bounds__(256) void compose_bwd_kernel(ComposeArgs a) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int slot = blockIdx.x * 4 + wave;
-    if (slot >= a.B) return;
+// The adjoint of ray slot `slot` by one wavefront.  gin (dL/dC) and
+// log_t_end come from the fused forward's registers, or (gin NULL) from
+// a.grad_rgb and a.log_t_end_in.
+__device__ __forceinline__ void compose_bwd_ray(const ComposeArgs& a, int slot, int lane, const float* gin,
+                                                float log_t_end) {
     const int64_t n = live_count(a.n_kept, a.cap);
     const int r = a.perm[slot];
     int64_t s0 = a.ray_offset[slot], s1 = a.ray_offset[slot + 1];
@@ -514,9 +533,9 @@ __global__ __launch_bounds__(256) void compose_bwd_kernel(ComposeArgs a) {
     const float p = a.sa.jitter ? a.sa.jitter[r] : 0.0f;
     const float step = a.sa.step;
     float g[5];
-    g[0] = a.grad_rgb ? a.grad_rgb[3 * r + 0] : 0.0f;
-    g[1] = a.grad_rgb ? a.grad_rgb[3 * r + 1] : 0.0f;
-    g[2] = a.grad_rgb ? a.grad_rgb[3 * r + 2] : 0.0f;
+    g[0] = gin ? gin[0] : a.grad_rgb ? a.grad_rgb[3 * r + 0] : 0.0f;
+    g[1] = gin ? gin[1] : a.grad_rgb ? a.grad_rgb[3 * r + 1] : 0.0f;
+    g[2] = gin ? gin[2] : a.grad_rgb ? a.grad_rgb[3 * r + 2] : 0.0f;
     g[3] = a.grad_depth ? a.grad_depth[r] : 0.0f;
     g[4] = a.grad_acc ? a.grad_acc[r] : 0.0f;
     float ro[3] = {0.0f, 0.0f, 0.0f}, rd[3] = {0.0f, 0.0f, 0.0f};   // the ray, for the binning
@@ -526,7 +545,7 @@ __global__ __launch_bounds__(256) void compose_bwd_kernel(ComposeArgs a) {
             rd[i] = a.sa.rays_d[3 * r + i];
         }
     }
-    const float Tend = expf(a.log_t_end_in[r]);
+    const float Tend = expf(gin ? log_t_end : a.log_t_end_in[r]);
     float S[5] = {Tend * a.bg[0], Tend * a.bg[1], Tend * a.bg[2], 0.0f, 0.0f};
     // auxiliary losses: the background entropy's gradient on T_end reaches
     // every sample through dT_end/dsigma_k = -delta T_end; the per-point rgb
@@ -607,6 +626,27 @@ __global__ __launch_bounds__(256) void compose_bwd_kernel(ComposeArgs a) {
             for (int ch = 0; ch < 5; ++ch) S[ch] += tot[ch];
         }
     }
+}
+
+__global__ __launch_bounds__(256) void compose_bwd_kernel(ComposeArgs a) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int slot = blockIdx.x * 4 + wave;
+    if (slot >= a.B) return;
+    compose_bwd_ray(a, slot, lane, nullptr, 0.0f);
+}
+
+// The training step's compositing and its adjoint in one launch: each
+// wavefront composites its ray (forward outputs, loss terms, dL/dC), then
+// walks it back with dL/dC and log T_end from its registers.  The adjoint
+// of a ray depends only on that ray's forward, so no other wavefront waits.
+__global__ __launch_bounds__(256) void compose_step_kernel(ComposeArgs fa, ComposeArgs ba) {
+    __shared__ float segs[4][32];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int slot = blockIdx.x * 4 + wave;
+    if (slot >= fa.B) return;
+    float g[3], lt;
+    compose_fwd_ray(fa, slot, lane, segs[wave], g, &lt);
+    compose_bwd_ray(ba, slot, lane, g, lt);
 }
 
 // ---------------------------------------------------------------------------
@@ -1458,7 +1498,7 @@ int32_t render_bwd_impl(const dvgo_field* field, const dvgo_mlp* mlp, const floa
                         float* grad_mlp, void* workspace, size_t workspace_bytes, void* stream,
                         bool forward_done = false, const float* sq_err = nullptr, float* loss = nullptr,
                         const NetAdam* net = nullptr, const float* aux_target = nullptr, float w_pt = 0.0f,
-                        float w_bg = 0.0f) {
+                        float w_bg = 0.0f, const ComposeArgs* fwd_compose = nullptr) {
     if (int32_t st = validate(field, mlp, rays_o, rays_d, t_near, n_uniform, perm, ray_offset, sample_ray, sample_k,
                               n_kept, capacity, B, step, bg, workspace, workspace_bytes))
         return st;
@@ -1503,7 +1543,10 @@ int32_t render_bwd_impl(const dvgo_field* field, const dvgo_mlp* mlp, const floa
     ca.cell_count = bins.cell_count;
     ca.cell_rank = bins.cell_rank;
     ca.rec_head = bins.rec_head;
-    DVGO_LAUNCH(K_COMPOSE_BWD, compose_bwd_kernel, dim3((B + 3) / 4), dim3(256), 0, s, ca);
+    if (fwd_compose)   // the forward compositing not yet run: both in one launch
+        DVGO_LAUNCH(K_COMPOSE_BWD, compose_step_kernel, dim3((B + 3) / 4), dim3(256), 0, s, *fwd_compose, ca);
+    else
+        DVGO_LAUNCH(K_COMPOSE_BWD, compose_bwd_kernel, dim3((B + 3) / 4), dim3(256), 0, s, ca);
     if (int32_t st = dvgo::launch_status()) return st;
     if (int32_t st = run_cell_scan(cm, bins, s)) return st;
     int nblk = 0;
@@ -1704,13 +1747,12 @@ int32_t dvgo_train_step(const dvgo_field* field, const dvgo_mlp* mlp, const floa
     ca.sq_err = sq_w;
     ca.w_pt = w_pt;
     ca.w_bg = w_bg;
-    DVGO_LAUNCH(K_COMPOSE_FWD, compose_fwd_kernel, dim3((B + 3) / 4), dim3(256), 0, s, ca);
-    if (int32_t st = dvgo::launch_status()) return st;
-    // adjoint and Adam, reusing the forward's gathered features, colours and prep
+    // adjoint and Adam, reusing the forward's gathered features, colours and
+    // prep; the compositing (ca) runs in the adjoint's first launch
     return render_bwd_impl(field, mlp, rays_o, rays_d, jitter, t_near, n_uniform, perm, ray_offset, sample_ray,
                            sample_k, n_kept, capacity, B, step, bg, logt_w, grad_w, nullptr, nullptr, nullptr,
                            nullptr, &o, grad_mlp, workspace, workspace_bytes, stream, true, sq_w, loss,
-                           mlp_opt ? &net : nullptr, target, w_pt, w_bg);
+                           mlp_opt ? &net : nullptr, target, w_pt, w_bg, &ca);
 }
 
 }  // extern "C"
