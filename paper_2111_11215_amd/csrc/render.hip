@@ -365,6 +365,9 @@ struct ComposeArgs {
     int* cell_count;       // [ncell + 1], zero on entry
     int2* cell_rank;       // [cap] (cell, rank within cell)
     float4* rec_head;      // [cap] (fx, fy, fz, dL/draw)
+    // forward without a network: each sample's raw density interpolated
+    // here from this grid (on g) instead of read from raw
+    const float* density_in;
 };
 
 // Fine cell of a point (its vertex (0,0,0)) and the fractional position f
@@ -404,6 +407,7 @@ __device__ __forceinline__ int run_rank(int cell, bool ok, int lane, int* __rest
 // segment sums in LDS).  With a.target it also forms the photometric
 // gradient dL/dC; every lane returns that gradient in g and log T_end in
 // *log_t_end (what a fused adjoint needs).
+template <bool kInline>   // kInline: the raw densities interpolated here (a.density_in)
 __device__ __forceinline__ void compose_fwd_ray(const ComposeArgs& a, int slot, int lane, float* segs, float g[3],
                                                 float* log_t_end) {
     const int64_t n = live_count(a.n_kept, a.cap);
@@ -415,6 +419,12 @@ __device__ __forceinline__ void compose_fwd_ray(const ComposeArgs& a, int slot, 
     const float tn = a.sa.t_near[r];
     const float p = a.sa.jitter ? a.sa.jitter[r] : 0.0f;
     const float step = a.sa.step;
+    float ro[3] = {0.0f, 0.0f, 0.0f}, rd[3] = {0.0f, 0.0f, 0.0f};   // the ray, for the inline density
+    if (kInline)
+        for (int i = 0; i < 3; ++i) {
+            ro[i] = a.sa.rays_o[3 * r + i];
+            rd[i] = a.sa.rays_d[3 * r + i];
+        }
     if (lane < 32) segs[lane] = 0.0f;
     __builtin_amdgcn_wave_barrier();
     float logT = 0.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f, dep = 0.0f, accw = 0.0f, ptl = 0.0f;
@@ -427,11 +437,25 @@ __device__ __forceinline__ void compose_fwd_ray(const ComposeArgs& a, int slot, 
         float sd = 0.0f, alpha = 0.0f, tk = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
         int k = 0;
         if (ok) {
-            const float sig = softplus_f(a.raw[s] + a.act_shift);
-            sd = sig * step;
-            alpha = -expm1f(-sd);
             k = a.sa.sample_k[s];
             tk = recipe_tk(tn, p, k, step);
+            float raw;
+            if (kInline) {   // the gather's interpolation, in its order
+                float x[3];
+                recipe_x(ro, rd, tk, x);
+                const Tri t = trilinear(a.g, x);
+                float dv[8];
+                #pragma unroll
+                for (int c = 0; c < 8; ++c) dv[c] = a.density_in[corner(t, c)];
+                raw = 0.0f;
+                #pragma unroll
+                for (int c = 0; c < 8; ++c) raw += t.w[c] * dv[c];
+            } else {
+                raw = a.raw[s];
+            }
+            const float sig = softplus_f(raw + a.act_shift);
+            sd = sig * step;
+            alpha = -expm1f(-sd);
             if (a.with_color) {
                 const float4 c = reinterpret_cast<const float4*>(a.col)[s];
                 c0 = c.x; c1 = c.y; c2 = c.z;
@@ -494,13 +518,14 @@ __device__ __forceinline__ void compose_fwd_ray(const ComposeArgs& a, int slot, 
     if (a.seg_w && lane < 32) a.seg_w[static_cast<int64_t>(r) * 32 + lane] = segs[lane];
 }
 
+template <bool kInline>
 __global__ __launch_bounds__(256) void compose_fwd_kernel(ComposeArgs a) {
     __shared__ float segs[4][32];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int slot = blockIdx.x * 4 + wave;
     if (slot >= a.B) return;
     float g[3], lt;
-    compose_fwd_ray(a, slot, lane, segs[wave], g, &lt);
+    compose_fwd_ray<kInline>(a, slot, lane, segs[wave], g, &lt);
 }
 
 // Backward of compose: walk each ray from its end in 64-sample steps,
@@ -645,7 +670,7 @@ __global__ __launch_bounds__(256) void compose_step_kernel(ComposeArgs fa, Compo
     const int slot = blockIdx.x * 4 + wave;
     if (slot >= fa.B) return;
     float g[3], lt;
-    compose_fwd_ray(fa, slot, lane, segs[wave], g, &lt);
+    compose_fwd_ray<false>(fa, slot, lane, segs[wave], g, &lt);
     compose_bwd_ray(ba, slot, lane, g, lt);
 }
 
@@ -1623,7 +1648,11 @@ int32_t dvgo_render_fwd(const dvgo_field* field, const dvgo_mlp* mlp, const floa
     if (B == 0) return DVGO_OK;
     Common cm = make_common(field, rays_o, rays_d, jitter, t_near, sample_ray, sample_k, capacity, B, step,
                             workspace);
-    if (int32_t st = run_prep_gather(cm, mlp, field, n_kept, s)) return st;
+    // with a network, the preparation and the gather first; without one
+    // the compositing interpolates each sample's density itself
+    if (mlp) {
+        if (int32_t st = run_prep_gather(cm, mlp, field, n_kept, s)) return st;
+    }
     if (mlp && capacity > 0) {
         MlpArgs ma = make_mlp_args(cm, mlp, n_kept);
         launch_mlp_fwd(ma, make_pos_args(cm), mlp->pe_x, dvgo::device_cu_count(), s);
@@ -1636,7 +1665,13 @@ int32_t dvgo_render_fwd(const dvgo_field* field, const dvgo_mlp* mlp, const floa
     ca.log_t_end = log_t_end;
     ca.seg_w = seg_w;
     ca.sample_w = sample_w;
-    DVGO_LAUNCH(K_COMPOSE_FWD, compose_fwd_kernel, dim3((B + 3) / 4), dim3(256), 0, s, ca);
+    if (!mlp) {
+        ca.density_in = field->density;
+        ca.g = cm.g;
+        DVGO_LAUNCH(K_COMPOSE_FWD, compose_fwd_kernel<true>, dim3((B + 3) / 4), dim3(256), 0, s, ca);
+    } else {
+        DVGO_LAUNCH(K_COMPOSE_FWD, compose_fwd_kernel<false>, dim3((B + 3) / 4), dim3(256), 0, s, ca);
+    }
     return dvgo::launch_status();
 }
 
