@@ -367,10 +367,11 @@ int32_t dvgo_render_bwd_adam(const dvgo_field* field /*host*/, const dvgo_mlp* m
                              const dvgo_grid_adam* opt /*host*/, float* grad_mlp,
                              void* workspace, size_t workspace_bytes, void* stream);
 
-/* Adam state of a flat float32 parameter array for dvgo_train_step's fused
- * network step: param, m, v [n] device pointers (n = dvgo_mlp_param_count),
- * param in the flat layout of the network gradient; lr, beta1, beta2, eps
- * and t >= 1 as in dvgo_adam_step. */
+/* Adam state of a flat float32 parameter array for a fused optimiser step:
+ * param, m, v [n] device pointers, param in the flat layout of the gradient
+ * it is stepped with (n = dvgo_mlp_param_count for dvgo_train_step's network
+ * step, dvgo_prop_param_count for dvgo_proposal_bwd_adam); lr, beta1,
+ * beta2, eps and t >= 1 as in dvgo_adam_step. */
 typedef struct {
     float* param;
     float* m;
@@ -490,6 +491,24 @@ int32_t dvgo_proposal_bwd(const float* rays_o, const float* rays_d, const float*
                           const float* log_t_end, float* grad_prop, float* loss,
                           void* workspace, size_t workspace_bytes, void* stream);
 size_t dvgo_proposal_workspace_bytes(int32_t B);
+
+/* dvgo_proposal_bwd followed by the proposal's Adam step, the step taken in
+ * the launch that sums the gradient (Adam with bias correction, the
+ * optimiser of Sec. 5.2, on a network that is not in the paper): the same
+ * result bit for bit as dvgo_proposal_bwd(..., grad_prop, loss, ...) then
+ * dvgo_adam_step(opt->param, grad_prop, opt->m, opt->v, NULL,
+ * dvgo_prop_param_count(), opt->lr, opt->beta1, opt->beta2, opt->eps,
+ * opt->t).  grad_prop (device, may hold gradient from earlier calls) is
+ * consumed and left zero; opt->param is normally the flat array that prop
+ * points into (the weights are read before the step).  B == 0 still takes
+ * the step.  opt NULL, a NULL pointer in it or bad hyper-parameters:
+ * DVGO_E_ARG; workspace as for dvgo_proposal_bwd. */
+int32_t dvgo_proposal_bwd_adam(const float* rays_o, const float* rays_d, const float* t_near,
+                               const uint8_t* valid, int32_t B, const dvgo_box* box /*host*/,
+                               const dvgo_prop* prop /*host*/, const float* seg_w,
+                               const float* log_t_end, float* grad_prop,
+                               const dvgo_adam_state* opt /*host*/, float* loss,
+                               void* workspace, size_t workspace_bytes, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Coarse stage (paper Sec. 4.1, "Coarse geometry searching").

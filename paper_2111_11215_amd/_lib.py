@@ -100,6 +100,8 @@ SIGNATURES = {
     "dvgo_proposal_fwd": (c_int32, [P, P, P, P, c_int32, POINTER(Box), POINTER(Prop), c_float, c_float, P, P, P,
                                     P]),
     "dvgo_proposal_bwd": (c_int32, [P, P, P, P, c_int32, POINTER(Box), POINTER(Prop), P, P, P, P, P, c_size_t, P]),
+    "dvgo_proposal_bwd_adam": (c_int32, [P, P, P, P, c_int32, POINTER(Box), POINTER(Prop), P, P, P,
+                                         POINTER(AdamState), P, P, c_size_t, P]),
     "dvgo_proposal_workspace_bytes": (c_size_t, [c_int32]),
     "dvgo_scene_render": (c_int32, [P, P, c_int32, POINTER(Box), P, c_int32, c_float, c_float, POINTER(c_float), P,
                                     P]),

@@ -477,6 +477,26 @@ def proposal_bwd(s: Samples, box_min, box_max, prop_flat: torch.Tensor, seg_w: t
     return loss
 
 
+def proposal_bwd_adam(s: Samples, box_min, box_max, prop_flat: torch.Tensor, seg_w: torch.Tensor,
+                      log_t_end: torch.Tensor, grad_prop: torch.Tensor, m: torch.Tensor, v: torch.Tensor, lr, t,
+                      betas=(0.9, 0.999), eps=1e-8):
+    """proposal_bwd then the Adam step of prop_flat, in one call (the step is
+    taken where the gradient is summed; grad_prop is left zero)."""
+    lib = load()
+    dev = s.rays_o.device
+    box = make_box(box_min, box_max)
+    prop = prop_struct(prop_flat)
+    opt = AdamState(_ptr(prop_flat), _ptr(m), _ptr(v), float(lr), float(betas[0]), float(betas[1]), float(eps),
+                    int(t))
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    nws = lib.dvgo_proposal_workspace_bytes(s.B)
+    ws = torch.empty(max(nws, 256), dtype=torch.uint8, device=dev)
+    check("dvgo_proposal_bwd_adam", lib.dvgo_proposal_bwd_adam(
+        _ptr(s.rays_o), _ptr(s.rays_d), _ptr(s.t_near), _ptr(s.valid), s.B, ctypes.byref(box), ctypes.byref(prop),
+        _ptr(seg_w), _ptr(log_t_end), _ptr(grad_prop), ctypes.byref(opt), _ptr(loss), _ptr(ws), nws, _stream(dev)))
+    return loss
+
+
 def scene_render(rays_o, rays_d, spheres_f32: torch.Tensor, box_min, box_max, step, bg=(1.0, 1.0, 1.0),
                  edge=0.01) -> torch.Tensor:
     lib = load()

@@ -5,6 +5,7 @@
 // activations and weights rounded to bfloat16, float32 accumulation), one
 // wavefront per 32 rays; the selection follows an explicit float32 recipe so
 // that it is reproducible bit for bit from the float32 logits.
+#include "adam.hpp"
 #include "common.hpp"
 
 namespace {
@@ -448,12 +449,25 @@ __global__ __launch_bounds__(64) void proposal_bwd_kernel(PropArgs a, const floa
     if (lane == 0) loss_part[wglob] = kl;
 }
 
+// Optional Adam step taken on each parameter right after its gradient is
+// summed (param NULL: none).
+struct PropAdam {
+    float* param;
+    float* m;
+    float* v;
+    dvgo::AdamCoef c;
+};
+
 // 64 parameters per workgroup, 16 wavefronts each summing every 16th
 // partial row, then a fixed-order sum of the 16 (deterministic); the
-// first workgroup also sums the loss partials.
+// first workgroup also sums the loss partials.  With an Adam step the
+// accumulated gradient is consumed at once: the parameter and its moments
+// are updated and the gradient is cleared, the same bits as the streaming
+// Adam kernel on the stored gradient.
 __global__ __launch_bounds__(1024) void proposal_reduce_kernel(const float* __restrict__ partial,
                                                                const float* __restrict__ loss_part, int nwaves,
-                                                               float* __restrict__ grad, float* __restrict__ loss) {
+                                                               float* __restrict__ grad, float* __restrict__ loss,
+                                                               PropAdam opt) {
     __shared__ float sh[16][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int p = blockIdx.x * 64 + lane;
@@ -476,7 +490,17 @@ __global__ __launch_bounds__(1024) void proposal_reduce_kernel(const float* __re
     if (wave == 0 && p < kParams) {
         float t = 0.0f;
         for (int w = 0; w < 16; ++w) t += sh[w][lane];
-        grad[p] += t;
+        const float g = grad[p] + t;
+        if (opt.param) {
+            float q = opt.param[p], m = opt.m[p], v = opt.v[p];
+            dvgo::adam_update(opt.c, q, g, m, v);
+            opt.param[p] = q;
+            opt.m[p] = m;
+            opt.v[p] = v;
+            grad[p] = 0.0f;
+        } else {
+            grad[p] = g;
+        }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0 && loss) {
         float l = 0.0f;
@@ -522,6 +546,45 @@ bool fill_args(PropArgs& a, const float* rays_o, const float* rays_d, const floa
     return true;
 }
 
+// The backward launch and the reduction; opt non-NULL adds the Adam step to
+// the reduction.  B == 0 with an Adam step still takes the step (on the
+// gradient as it stands), as the separate Adam call would.
+int32_t proposal_bwd_impl(const float* rays_o, const float* rays_d, const float* t_near, const uint8_t* valid,
+                          int32_t B, const dvgo_box* box, const dvgo_prop* prop, const float* seg_w,
+                          const float* log_t_end, float* grad_prop, float* loss, const dvgo_adam_state* opt,
+                          void* workspace, size_t workspace_bytes, void* stream) {
+    PropArgs a;
+    if (!prop || !fill_args(a, rays_o, rays_d, t_near, valid, B, box, prop)) return DVGO_E_ARG;
+    if (B > 0 && (!seg_w || !log_t_end || !grad_prop)) return DVGO_E_ARG;
+    if (opt && !grad_prop) return DVGO_E_ARG;
+    PropAdam pa{};
+    if (opt) {
+        if (!opt->param || !opt->m || !opt->v) return DVGO_E_ARG;
+        if (!dvgo::adam_hyper_ok(opt->beta1, opt->beta2, opt->eps, opt->t)) return DVGO_E_ARG;
+        pa.param = opt->param;
+        pa.m = opt->m;
+        pa.v = opt->v;
+        pa.c = dvgo::adam_coef(opt->lr, opt->beta1, opt->beta2, opt->eps, opt->t);
+    }
+    if (workspace_bytes < dvgo_proposal_workspace_bytes(B) || (B > 0 && !workspace)) return DVGO_E_CAPACITY;
+    if (B == 0 && !opt) return DVGO_OK;
+    const int nblk = (B + kRaysPerWave * kWaves - 1) / (kRaysPerWave * kWaves);
+    const int nw = nblk * kWaves;
+    float* partial = static_cast<float*>(workspace);
+    float* loss_part = B > 0 ? reinterpret_cast<float*>(static_cast<char*>(workspace) +
+                                                         dvgo::align_up(static_cast<size_t>(nw) * kPStride * 4, 256))
+                             : nullptr;
+    hipStream_t s = dvgo::as_stream(stream);
+    if (B > 0) {
+        DVGO_LAUNCH(K_PROP_BWD, proposal_bwd_kernel, dim3(nblk), dim3(64 * kWaves), 0, s, a, seg_w, log_t_end,
+                    partial, loss_part);
+        if (int32_t st = dvgo::launch_status()) return st;
+    }
+    DVGO_LAUNCH(K_PROP_REDUCE, proposal_reduce_kernel, dim3((kParams + 63) / 64), dim3(1024), 0, s, partial, loss_part,
+                nw, grad_prop, B > 0 ? loss : nullptr, pa);
+    return dvgo::launch_status();
+}
+
 }  // namespace
 
 extern "C" {
@@ -552,23 +615,17 @@ int32_t dvgo_proposal_bwd(const float* rays_o, const float* rays_d, const float*
                           int32_t B, const dvgo_box* box, const dvgo_prop* prop, const float* seg_w,
                           const float* log_t_end, float* grad_prop, float* loss, void* workspace,
                           size_t workspace_bytes, void* stream) {
-    PropArgs a;
-    if (!prop || !fill_args(a, rays_o, rays_d, t_near, valid, B, box, prop)) return DVGO_E_ARG;
-    if (B > 0 && (!seg_w || !log_t_end || !grad_prop)) return DVGO_E_ARG;
-    if (workspace_bytes < dvgo_proposal_workspace_bytes(B) || (B > 0 && !workspace)) return DVGO_E_CAPACITY;
-    if (B == 0) return DVGO_OK;
-    const int nblk = (B + kRaysPerWave * kWaves - 1) / (kRaysPerWave * kWaves);
-    const int nw = nblk * kWaves;
-    float* partial = static_cast<float*>(workspace);
-    float* loss_part = reinterpret_cast<float*>(static_cast<char*>(workspace) +
-                                                dvgo::align_up(static_cast<size_t>(nw) * kPStride * 4, 256));
-    hipStream_t s = dvgo::as_stream(stream);
-    DVGO_LAUNCH(K_PROP_BWD, proposal_bwd_kernel, dim3(nblk), dim3(64 * kWaves), 0, s, a, seg_w, log_t_end, partial,
-                loss_part);
-    if (int32_t st = dvgo::launch_status()) return st;
-    DVGO_LAUNCH(K_PROP_REDUCE, proposal_reduce_kernel, dim3((kParams + 63) / 64), dim3(1024), 0, s, partial, loss_part,
-                nw, grad_prop, loss);
-    return dvgo::launch_status();
+    return proposal_bwd_impl(rays_o, rays_d, t_near, valid, B, box, prop, seg_w, log_t_end, grad_prop, loss, nullptr,
+                             workspace, workspace_bytes, stream);
+}
+
+int32_t dvgo_proposal_bwd_adam(const float* rays_o, const float* rays_d, const float* t_near, const uint8_t* valid,
+                               int32_t B, const dvgo_box* box, const dvgo_prop* prop, const float* seg_w,
+                               const float* log_t_end, float* grad_prop, const dvgo_adam_state* opt, float* loss,
+                               void* workspace, size_t workspace_bytes, void* stream) {
+    if (!opt) return DVGO_E_ARG;
+    return proposal_bwd_impl(rays_o, rays_d, t_near, valid, B, box, prop, seg_w, log_t_end, grad_prop, loss, opt,
+                             workspace, workspace_bytes, stream);
 }
 
 }  // extern "C"

@@ -216,11 +216,9 @@ class ProposalModel:
         """One proposal update from a density-only pass on the given rays."""
         s = model.sample(rays_o, rays_d, jitter)
         tgt = api.render_fwd(model.grid, None, s, model.cfg.bg, want_seg_w=True, want_depth_acc=False)
-        loss = api.proposal_bwd(s, self.box_min, self.box_max, self.flat, tgt["seg_w"], tgt["log_t_end"],
-                                self.st.g)
         self.t += 1
-        api.adam_step(self.st.p, self.st.g, self.st.m, self.st.v, self.lr, self.t)
-        return loss
+        return api.proposal_bwd_adam(s, self.box_min, self.box_max, self.flat, tgt["seg_w"], tgt["log_t_end"],
+                                     self.st.g, self.st.m, self.st.v, self.lr, self.t)
 
 
 def proposal_train_step(model: FineModel, prop: ProposalModel, rays_o, rays_d, target, jitter=None,

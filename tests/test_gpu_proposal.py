@@ -117,3 +117,48 @@ def test_proposal_clips_rays_itself_bit_identically(gpu_lib):
     s_bare = api.Samples(**{**s.__dict__, "t_near": None, "valid": None})
     l1 = api.proposal_bwd(s_bare, P.box_min, P.box_max, ft, seg_w, lte, g1)
     assert np.array_equal(np_of(g0), np_of(g1)) and np.array_equal(np_of(l0), np_of(l1))
+
+
+def _first_rays(s, n):
+    """The per-ray inputs the proposal calls read, cut to the first n rays."""
+    from paper_2111_11215_amd import api
+    cut = {k: getattr(s, k)[:n].contiguous() for k in ("rays_o", "rays_d", "t_near", "valid")}
+    return api.Samples(**{**s.__dict__, **cut})
+
+
+def test_proposal_bwd_adam_equals_separate_calls(gpu_lib):
+    """dvgo_proposal_bwd_adam (the Adam step taken where the gradient is
+    summed) equals dvgo_proposal_bwd then dvgo_adam_step bit for bit:
+    parameters, both moments and the loss over three steps in a row (the
+    first on a gradient that already holds a value, the last on fewer rays),
+    the gradient left zero, and a call on no rays that still takes the step."""
+    import torch
+    from paper_2111_11215_amd import api
+    P = synth.tiny_config(3, n_rays=1500)
+    s_full = _samples(P)
+    _, _, flat = _prop_weights(6)
+    rng = np.random.default_rng(7)
+    seg_w = rng.uniform(0, 1, (1500, 32)).astype(F32)
+    seg_w /= seg_w.sum(1, keepdims=True) * 1.25
+    lte = np.log(rng.uniform(0.05, 0.3, 1500)).astype(F32)
+    pa, pb = to_dev(flat), to_dev(flat)
+    ma, va = torch.zeros_like(pa), torch.zeros_like(pa)
+    mb, vb = torch.zeros_like(pa), torch.zeros_like(pa)
+    ga = to_dev(rng.normal(size=flat.shape).astype(F32) * 1e-3)
+    gb = ga.clone()
+    for t, n in ((1, 1500), (2, 1500), (3, 777)):
+        s = _first_rays(s_full, n)
+        sw, lt = to_dev(seg_w[:n]), to_dev(lte[:n])
+        la = api.proposal_bwd(s, P.box_min, P.box_max, pa, sw, lt, ga)
+        api.adam_step(pa, ga, ma, va, 3e-3, t)
+        lb = api.proposal_bwd_adam(s, P.box_min, P.box_max, pb, sw, lt, gb, mb, vb, 3e-3, t)
+        for x, y in ((pa, pb), (ma, mb), (va, vb), (la, lb), (ga, gb)):
+            assert np.array_equal(np_of(x), np_of(y)), t
+        assert not np_of(gb).any()
+    s0 = _first_rays(s_full, 0)
+    ga.copy_(to_dev(rng.normal(size=flat.shape).astype(F32) * 1e-3))
+    gb.copy_(ga)
+    api.adam_step(pa, ga, ma, va, 3e-3, 4)
+    api.proposal_bwd_adam(s0, P.box_min, P.box_max, pb, to_dev(seg_w[:0]), to_dev(lte[:0]), gb, mb, vb, 3e-3, 4)
+    for x, y in ((pa, pb), (ma, mb), (va, vb), (ga, gb)):
+        assert np.array_equal(np_of(x), np_of(y))
