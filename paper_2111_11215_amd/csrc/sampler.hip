@@ -136,7 +136,14 @@ struct KeepArgs {
     float fine_thr;
     float step;
     int B;
+    // the counting pass's keep ballots, kKeepWords per ray slot, read back by
+    // the fill (nullptr: the fill evaluates the keep rule again)
+    uint64_t* words;
 };
+
+// Ballot words kept per ray slot: rays of up to 64 * kKeepWords uniform
+// samples reuse the counting pass's keep decisions in the fill.
+constexpr int kKeepWords = 16;
 
 struct RayView {
     float o[3], d[3], tn, p;
@@ -207,7 +214,11 @@ __global__ __launch_bounds__(256) void setup_count_kernel(KeepArgs a, BoxF box, 
         perm[r] = r;
     }
     int cnt = 0;
-    for (int base = 0; base < v.n; base += 64) cnt += __popcll(__ballot(keep_sample(a, v, base + lane)));
+    for (int base = 0; base < v.n; base += 64) {
+        const uint64_t m = __ballot(keep_sample(a, v, base + lane));
+        cnt += __popcll(m);
+        if (a.words && lane == 0) a.words[static_cast<int64_t>(r) * kKeepWords + (base >> 6)] = m;
+    }
     if (lane == 0) counts[r] = cnt;
 }
 
@@ -219,8 +230,9 @@ __global__ __launch_bounds__(256) void count_kept_kernel(KeepArgs a, int* __rest
     const RayView v = load_ray(a, slot);
     int cnt = 0;
     for (int base = 0; base < v.n; base += 64) {
-        const bool keep = keep_sample(a, v, base + lane);
-        cnt += __popcll(__ballot(keep));
+        const uint64_t m = __ballot(keep_sample(a, v, base + lane));
+        cnt += __popcll(m);
+        if (a.words && lane == 0) a.words[static_cast<int64_t>(slot) * kKeepWords + (base >> 6)] = m;
     }
     if (lane == 0) counts[slot] = cnt;
 }
@@ -310,6 +322,30 @@ __device__ __forceinline__ void fill_ray(const KeepArgs& a, const RayView& v, in
     }
 }
 
+// The same from the counting pass's ballot words of ray slot `slot`: lane w
+// loads word w, each 64-sample step takes its word from that lane.
+__device__ __forceinline__ void fill_ray_words(const KeepArgs& a, int slot, int64_t pos0, int64_t capacity,
+                                               int* __restrict__ sample_ray, int* __restrict__ sample_k,
+                                               int lane) {
+    const int r = a.perm[slot];
+    const int n = a.n_uniform[r];
+    const int nw = (n + 63) >> 6;
+    const uint64_t own = lane < nw ? a.words[static_cast<int64_t>(slot) * kKeepWords + lane] : 0;
+    const uint32_t lo = static_cast<uint32_t>(own), hi = static_cast<uint32_t>(own >> 32);
+    for (int w = 0; w < nw; ++w) {
+        // (readlane returns a signed int: the halves widen as unsigned)
+        const uint32_t wl = __builtin_amdgcn_readlane(lo, w), wh = __builtin_amdgcn_readlane(hi, w);
+        const uint64_t mask = (static_cast<uint64_t>(wh) << 32) | wl;
+        const bool keep = (mask >> lane) & 1u;
+        const int64_t pos = pos0 + lanes_below(mask);
+        if (keep && pos < capacity) {
+            sample_ray[pos] = r;
+            sample_k[pos] = 64 * w + lane;
+        }
+        pos0 += __popcll(mask);
+    }
+}
+
 // One wavefront per ray slot: write the kept (ray, k) pairs in ascending k.
 __global__ __launch_bounds__(256) void fill_kept_kernel(KeepArgs a, const int* __restrict__ ray_offset,
                                                         int64_t capacity, int* __restrict__ sample_ray,
@@ -317,6 +353,10 @@ __global__ __launch_bounds__(256) void fill_kept_kernel(KeepArgs a, const int* _
     const int slot = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (slot >= a.B) return;
+    if (a.words) {
+        fill_ray_words(a, slot, ray_offset[slot], capacity, sample_ray, sample_k, lane);
+        return;
+    }
     const RayView v = load_ray(a, slot);
     fill_ray(a, v, ray_offset[slot], capacity, sample_ray, sample_k, lane);
 }
@@ -387,6 +427,10 @@ __global__ __launch_bounds__(1024) void offsets_fill_kernel(KeepArgs a, const in
             *n_kept = total;
         }
     }
+    if (a.words) {
+        fill_ray_words(a, slot, pos0, capacity, sample_ray, sample_k, lane);
+        return;
+    }
     const RayView v = load_ray(a, slot);
     fill_ray(a, v, pos0, capacity, sample_ray, sample_k, lane);
 }
@@ -415,19 +459,26 @@ __global__ void coarse_mask_kernel(const float* __restrict__ raw, int nx, int ny
     bits[w] = word;
 }
 
+// Per-ray counts and Morton keys, each rounded up to 256 bytes, plus 256;
+// the public workspace adds the keep ballot words.
+constexpr size_t base_workspace_bytes(int32_t B) {
+    return (static_cast<size_t>(B) * 4 + 255) / 256 * 256 * 2 + 256;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // Static scratch of dvgo_sample_rays_noalloc: the workspace of up to
-// kNoAllocMaxRays rays (per-ray counts and Morton keys, each rounded up to
-// 256 bytes, plus 256), held by every GPU the library runs on until the
+// kNoAllocMaxRays rays without the keep ballot words (per-ray counts and
+// Morton keys; the fill evaluates the keep rule again), held by every GPU
+// the library runs on until the
 // process ends.  Host code never passes the array's name to a kernel: it is
 // a host-side stand-in, not a device address.  Each device's own address of
 // its copy comes from hipGetSymbolAddress, taken once per device with that
 // device current, and is what the call hands its kernels.
 // ---------------------------------------------------------------------------
 constexpr int32_t kNoAllocMaxRays = 1 << 18;
-constexpr size_t kNoAllocScratchBytes = ((static_cast<size_t>(kNoAllocMaxRays) * 4 + 255) / 256 * 256) * 2 + 256;
+constexpr size_t kNoAllocScratchBytes = base_workspace_bytes(kNoAllocMaxRays);
 
 static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
@@ -476,7 +527,7 @@ int32_t dvgo_coarse_mask_build(const float* raw, const dvgo_box* cbox, float raw
 
 size_t dvgo_sample_workspace_bytes(int32_t B) {
     if (B < 0) return 0;
-    return dvgo::align_up(static_cast<size_t>(B) * 4, 256) * 2 + 256;
+    return base_workspace_bytes(B) + dvgo::align_up(static_cast<size_t>(B) * kKeepWords * 8, 256);
 }
 
 static int32_t sample_rays_impl(const float* rays_o, const float* rays_d, const float* jitter, int32_t B,
@@ -485,7 +536,7 @@ static int32_t sample_rays_impl(const float* rays_o, const float* rays_d, const 
                          int32_t morton, float* t_near,
                          float* t_far, uint8_t* valid, int32_t* n_uniform, int32_t* perm, int32_t* ray_offset,
                          int32_t* sample_ray, int32_t* sample_k, int64_t capacity, int64_t* n_kept,
-                         void* workspace, size_t workspace_bytes, void* stream) {
+                         void* workspace, size_t workspace_bytes, bool keep_words, void* stream) {
     if (B < 0 || !box) return DVGO_E_ARG;
     if (!(step > 0.0f) || max_samples < 0 || capacity < 0) return DVGO_E_ARG;
     for (int i = 0; i < 3; ++i)
@@ -501,7 +552,9 @@ static int32_t sample_rays_impl(const float* rays_o, const float* rays_d, const 
     if (capacity > 0 && (!sample_ray || !sample_k)) return DVGO_E_ARG;
     if (morton && B > kMaxMortonRays) return DVGO_E_UNSUPPORTED;
     if (static_cast<int64_t>(B) * max_samples >= (1LL << 31)) return DVGO_E_UNSUPPORTED;
-    if (workspace_bytes < dvgo_sample_workspace_bytes(B) || (B > 0 && !workspace)) return DVGO_E_CAPACITY;
+    if (workspace_bytes < (keep_words ? dvgo_sample_workspace_bytes(B) : base_workspace_bytes(B)) ||
+        (B > 0 && !workspace))
+        return DVGO_E_CAPACITY;
 
     hipStream_t s = dvgo::as_stream(stream);
     if (B == 0) {
@@ -537,6 +590,9 @@ static int32_t sample_rays_impl(const float* rays_o, const float* rays_d, const 
     ka.fine_thr = fine ? fine->raw_threshold : 0.0f;
     ka.step = step;
     ka.B = B;
+    ka.words = keep_words && max_samples <= 64 * kKeepWords
+                   ? reinterpret_cast<uint64_t*>(ws + base_workspace_bytes(B))
+                   : nullptr;
     const unsigned wblocks = static_cast<unsigned>((B + 3) / 4);
     if (!morton && !clip_only) {
         DVGO_LAUNCH(K_RAY_SETUP, setup_count_kernel, dim3(wblocks), dim3(256), 0, s, ka, bf, max_samples, t_near,
@@ -578,7 +634,7 @@ int32_t dvgo_sample_rays(const float* rays_o, const float* rays_d, const float* 
                          void* workspace, size_t workspace_bytes, void* stream) {
     return sample_rays_impl(rays_o, rays_d, jitter, B, box, step, max_samples, coarse_bits, coarse_box, seg_mask,
                             fine, morton, t_near, t_far, valid, n_uniform, perm, ray_offset, sample_ray, sample_k, capacity,
-                            n_kept, workspace, workspace_bytes, stream);
+                            n_kept, workspace, workspace_bytes, true, stream);
 }
 
 // The same call with its workspace in the library's static device array
@@ -600,7 +656,7 @@ int32_t dvgo_sample_rays_noalloc(const float* rays_o, const float* rays_d, const
     if (int32_t st = scratch_address(&ws)) return st;
     return sample_rays_impl(rays_o, rays_d, jitter, B, box, step, max_samples, coarse_bits, coarse_box, seg_mask,
                             fine, morton, t_near, t_far, valid, n_uniform, perm, ray_offset, sample_ray, sample_k, capacity,
-                            n_kept, ws, kNoAllocScratchBytes, stream);
+                            n_kept, ws, kNoAllocScratchBytes, false, stream);
 }
 
 }  // extern "C"

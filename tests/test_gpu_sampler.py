@@ -174,3 +174,26 @@ def test_sampler_offsets_span_several_scan_passes(gpu_lib, n_rays):
     assert int(np_of(s.n_kept)[0]) == int(want[-1])
     sr = np_of(s.sample_ray)[:int(want[-1])]
     assert np.array_equal(sr, np.repeat(np.arange(n_rays), nu))
+
+
+@pytest.mark.parametrize("max_samples", [1024, 1100])
+def test_sampler_long_rays_both_fill_paths(gpu_lib, max_samples):
+    """Rays of up to 1024 uniform samples are filled from the counting pass's
+    keep ballots, longer ones by evaluating the keep rule again: both
+    bit-exact against the oracle, with a coarse and a segment mask, on rays
+    that reach the sample cap, so every ballot word (lanes 31/32 included) is
+    used."""
+    from paper_2111_11215_amd import api
+    P = synth.tiny_config(4, jitter=True, n_rays=300)
+    step = 0.0025
+    raw = np.random.default_rng(8).normal(-4, 3, (17, 19, 15)).astype(F32)
+    bits, bits_ref, _ = _coarse(raw, P.box_min, P.box_max, 1e-3, step)
+    segm = np.random.default_rng(9).integers(0, 2 ** 32, 300, dtype=np.uint64).astype(np.uint32)
+    segm[:100] = 0xFFFFFFFF
+    s = api.sample_rays(to_dev(P.rays.o), to_dev(P.rays.d), to_dev(P.rays.jitter), P.box_min, P.box_max, step,
+                        max_samples, coarse=(bits, P.box_min, P.box_max, raw.shape),
+                        seg_mask=to_dev(segm.view(np.int32)))
+    ref = O.sample_rays(P.rays.o, P.rays.d, P.rays.jitter, P.box_min, P.box_max, step, max_samples,
+                        coarse=(bits_ref, P.box_min, P.box_max, raw.shape), seg_mask=segm)
+    assert ref["n_uniform"].max() == max_samples
+    _check_samples(s, ref, 300)
