@@ -121,6 +121,12 @@ def test_host_validation_rejects_before_launch(lib):
     # proposal: a validity mask without the t_near it belongs to
     assert lib.dvgo_proposal_fwd(fake, fake, nul, fake, 1, ctypes.byref(box), nul, 0.99, 0.9, fake, nul, nul,
                                  nul) == -1
+    # proposal backward with its Adam step: no optimiser state, then a bad beta
+    pr = _lib.Prop(16, 16, 16, 16, 16, 16)
+    pargs = [fake, fake, nul, nul, 1, ctypes.byref(box), ctypes.byref(pr), fake, fake, fake]
+    assert lib.dvgo_proposal_bwd_adam(*pargs, None, fake, fake, 1 << 30, nul) == -1
+    st = _lib.AdamState(16, 16, 16, 1e-3, 1.0, 0.999, 1e-8, 1)
+    assert lib.dvgo_proposal_bwd_adam(*pargs, ctypes.byref(st), fake, fake, 1 << 30, nul) == -1
     # fused backward + grid Adam: missing optimiser state, bad beta, misaligned
     # feature pointer, then a shape error from the shared validation
     ga = _lib.GridAdam(16, 16, 16, 16, 16, 16, None, 0.1, 0.9, 0.999, 1e-8, 1)
