@@ -469,7 +469,7 @@ def calibrate_copy(mib):
 TRAFFIC_SOURCES = {"grid_adam": ("paper_2111_11215_amd/csrc/render.hip", "paper_2111_11215_amd/csrc/adam.hpp",
                                  "paper_2111_11215_amd/csrc/common.hpp"),
                    # the fine pass's launch (density and features); the
-                   # proposal's density-only launch is not in the figure
+                   # proposal's density-only pass has no gather launch
                    "gather": ("paper_2111_11215_amd/csrc/render.hip", "paper_2111_11215_amd/csrc/adam.hpp",
                               "paper_2111_11215_amd/csrc/common.hpp"),
                    "mlp_bwd": ("paper_2111_11215_amd/csrc/render.hip", "paper_2111_11215_amd/csrc/mlp_mfma.hpp",
