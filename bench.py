@@ -84,7 +84,8 @@ def parse():
     ap.add_argument("--rays", type=int, default=8192)
     ap.add_argument("--profile-kernel", default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rays", type=int, default=256)
+    ap.add_argument("--cpu-rays", type=int, default=0, help="oracle sample: rays of the first batch (0: all)")
+    ap.add_argument("--cpu-reps", type=int, default=4, help="oracle steps timed (their mean is reported)")
     ap.add_argument("--profile-steps", type=int, default=10,
                     help="steps per kernel of the event-timed pass (0: skip it)")
     ap.add_argument("--compare-iters", type=int, default=1000,
@@ -353,11 +354,12 @@ def host_cpu_model():
     return "unknown"
 
 
-def cpu_baseline(ctx, rays, B):
+def cpu_baseline(ctx, rays, B, reps=1):
     """The oracle as it stands, one thread, on a bounded sample: the plain
     float64 step (sample, forward, loss, adjoint) for ``rays`` rays drawn as
     the first batch is drawn, scaled to the B-ray batch, plus one oracle Adam
-    step over every parameter of the configuration."""
+    step over every parameter of the configuration; the mean over ``reps``
+    such steps."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -375,29 +377,32 @@ def cpu_baseline(ctx, rays, B):
     bits = O.coarse_cell_bits(ctx["raw"], thr)
     dens = np.zeros((n, n, n), np.float32)
     feat = np.zeros((n, n, n, 12), np.float32)
+    t_rays = t_adam = 0.0
     with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        samp = O.sample_rays(o, d, j, ctx["bmin"], ctx["bmax"], ctx["step"], ctx["max_samples"],
-                             coarse=(bits, ctx["bmin"], ctx["bmax"], ctx["raw"].shape))
-        prm = O.Params(dens, feat, Ws, bs, ctx["bmin"], ctx["bmax"], ctx["b"])
-        fwd = O.render_forward(prm, o, d, j, samp, ctx["step"], (1.0, 1.0, 1.0))
-        _, g = O.photo_loss(fwd["rgb"], tgt)
-        gr = O.render_backward(prm, o, d, j, samp, ctx["step"], (1.0, 1.0, 1.0), fwd, g)
-        t_rays = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        for p_, g_ in ((dens, gr["density"]), (feat, gr["feat"])):
-            O.adam_step(p_, g_, np.zeros(p_.shape), np.zeros(p_.shape), 0.1, 0.9, 0.999, 1e-8, 1)
-        for w_, gw in zip(Ws + bs, gr["Ws"] + gr["bs"]):
-            O.adam_step(w_, gw, np.zeros(w_.shape), np.zeros(w_.shape), 1e-3, 0.9, 0.999, 1e-8, 1)
-        t_adam = time.perf_counter() - t0
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            samp = O.sample_rays(o, d, j, ctx["bmin"], ctx["bmax"], ctx["step"], ctx["max_samples"],
+                                 coarse=(bits, ctx["bmin"], ctx["bmax"], ctx["raw"].shape))
+            prm = O.Params(dens, feat, Ws, bs, ctx["bmin"], ctx["bmax"], ctx["b"])
+            fwd = O.render_forward(prm, o, d, j, samp, ctx["step"], (1.0, 1.0, 1.0))
+            _, g = O.photo_loss(fwd["rgb"], tgt)
+            gr = O.render_backward(prm, o, d, j, samp, ctx["step"], (1.0, 1.0, 1.0), fwd, g)
+            t_rays += (time.perf_counter() - t0) / reps
+            t0 = time.perf_counter()
+            for p_, g_ in ((dens, gr["density"]), (feat, gr["feat"])):
+                O.adam_step(p_, g_, np.zeros(p_.shape), np.zeros(p_.shape), 0.1, 0.9, 0.999, 1e-8, 1)
+            for w_, gw in zip(Ws + bs, gr["Ws"] + gr["bs"]):
+                O.adam_step(w_, gw, np.zeros(w_.shape), np.zeros(w_.shape), 1e-3, 0.9, 0.999, 1e-8, 1)
+            t_adam += (time.perf_counter() - t0) / reps
     scale = B / rays
     per_iter = t_rays * scale + t_adam
     n_uni = float(np.sum(samp["n_uniform"])) * scale
     return {"value": n_uni / per_iter, "unit": "ray-samples/s", "cores": 1, "kind": "oracle",
             "host_cpu": host_cpu_model(), "host_cpus_available": len(os.sched_getaffinity(0)),
             "sample": (f"plain float64 step of the first {rays} of the {B} rays of the first batch (sample, "
-                       f"forward, loss, adjoint: {t_rays:.2f} s, scaled x{scale:.0f}) + one Adam step over all "
-                       f"{dens.size + feat.size + 22019} parameters ({t_adam:.2f} s); 1 thread")}
+                       f"forward, loss, adjoint: {t_rays:.2f} s" + (f", scaled x{scale:.0f}" if rays < B else "")
+                       + f") + one Adam step over all {dens.size + feat.size + 22019} parameters "
+                       f"({t_adam:.2f} s); mean of {reps} steps, {reps * (t_rays + t_adam):.1f} s in all; 1 thread")}
 
 
 def unique_footprint(ctx, B, gather_ms):
@@ -778,7 +783,7 @@ def main():
         out["toy2d"] = toy2d_report()
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(ctx, args.cpu_rays, args.rays)
+        out["cpu_baseline"] = cpu_baseline(ctx, args.cpu_rays or args.rays, args.rays, args.cpu_reps)
         g = out.get("kernels_roofline", {}).get("gather", {})
         out["unique_footprint"] = unique_footprint(ctx, args.rays, g.get("launch_ms"))
     print(json.dumps(out), flush=True)
