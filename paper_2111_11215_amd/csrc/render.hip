@@ -518,11 +518,19 @@ __device__ __forceinline__ void compose_fwd_ray(const ComposeArgs& a, int slot, 
     if (a.seg_w && lane < 32) a.seg_w[static_cast<int64_t>(r) * 32 + lane] = segs[lane];
 }
 
+// Wavefronts (rays) per workgroup of the compositing kernels: one, so that a
+// long ray holds only its own slot (with four, a workgroup's resources stayed
+// held until its longest ray was done: the training step's compositing took
+// 1 us longer).
+constexpr int kComposeWaves = 1;
+constexpr int kComposeThreads = 64 * kComposeWaves;
+inline dim3 compose_grid(int B) { return dim3((B + kComposeWaves - 1) / kComposeWaves); }
+
 template <bool kInline>
-__global__ __launch_bounds__(256) void compose_fwd_kernel(ComposeArgs a) {
-    __shared__ float segs[4][32];
+__global__ __launch_bounds__(kComposeThreads) void compose_fwd_kernel(ComposeArgs a) {
+    __shared__ float segs[kComposeWaves][32];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int slot = blockIdx.x * 4 + wave;
+    const int slot = blockIdx.x * kComposeWaves + wave;
     if (slot >= a.B) return;
     float g[3], lt;
     compose_fwd_ray<kInline>(a, slot, lane, segs[wave], g, &lt);
@@ -653,9 +661,9 @@ __device__ __forceinline__ void compose_bwd_ray(const ComposeArgs& a, int slot, 
     }
 }
 
-__global__ __launch_bounds__(256) void compose_bwd_kernel(ComposeArgs a) {
+__global__ __launch_bounds__(kComposeThreads) void compose_bwd_kernel(ComposeArgs a) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int slot = blockIdx.x * 4 + wave;
+    const int slot = blockIdx.x * kComposeWaves + wave;
     if (slot >= a.B) return;
     compose_bwd_ray(a, slot, lane, nullptr, 0.0f);
 }
@@ -664,10 +672,10 @@ __global__ __launch_bounds__(256) void compose_bwd_kernel(ComposeArgs a) {
 // wavefront composites its ray (forward outputs, loss terms, dL/dC), then
 // walks it back with dL/dC and log T_end from its registers.  The adjoint
 // of a ray depends only on that ray's forward, so no other wavefront waits.
-__global__ __launch_bounds__(256) void compose_step_kernel(ComposeArgs fa, ComposeArgs ba) {
-    __shared__ float segs[4][32];
+__global__ __launch_bounds__(kComposeThreads) void compose_step_kernel(ComposeArgs fa, ComposeArgs ba) {
+    __shared__ float segs[kComposeWaves][32];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int slot = blockIdx.x * 4 + wave;
+    const int slot = blockIdx.x * kComposeWaves + wave;
     if (slot >= fa.B) return;
     float g[3], lt;
     compose_fwd_ray<false>(fa, slot, lane, segs[wave], g, &lt);
@@ -1569,9 +1577,9 @@ int32_t render_bwd_impl(const dvgo_field* field, const dvgo_mlp* mlp, const floa
     ca.cell_rank = bins.cell_rank;
     ca.rec_head = bins.rec_head;
     if (fwd_compose)   // the forward compositing not yet run: both in one launch
-        DVGO_LAUNCH(K_COMPOSE_BWD, compose_step_kernel, dim3((B + 3) / 4), dim3(256), 0, s, *fwd_compose, ca);
+        DVGO_LAUNCH(K_COMPOSE_BWD, compose_step_kernel, compose_grid(B), dim3(kComposeThreads), 0, s, *fwd_compose, ca);
     else
-        DVGO_LAUNCH(K_COMPOSE_BWD, compose_bwd_kernel, dim3((B + 3) / 4), dim3(256), 0, s, ca);
+        DVGO_LAUNCH(K_COMPOSE_BWD, compose_bwd_kernel, compose_grid(B), dim3(kComposeThreads), 0, s, ca);
     if (int32_t st = dvgo::launch_status()) return st;
     if (int32_t st = run_cell_scan(cm, bins, s)) return st;
     int nblk = 0;
@@ -1668,9 +1676,9 @@ int32_t dvgo_render_fwd(const dvgo_field* field, const dvgo_mlp* mlp, const floa
     if (!mlp) {
         ca.density_in = field->density;
         ca.g = cm.g;
-        DVGO_LAUNCH(K_COMPOSE_FWD, compose_fwd_kernel<true>, dim3((B + 3) / 4), dim3(256), 0, s, ca);
+        DVGO_LAUNCH(K_COMPOSE_FWD, compose_fwd_kernel<true>, compose_grid(B), dim3(kComposeThreads), 0, s, ca);
     } else {
-        DVGO_LAUNCH(K_COMPOSE_FWD, compose_fwd_kernel<false>, dim3((B + 3) / 4), dim3(256), 0, s, ca);
+        DVGO_LAUNCH(K_COMPOSE_FWD, compose_fwd_kernel<false>, compose_grid(B), dim3(kComposeThreads), 0, s, ca);
     }
     return dvgo::launch_status();
 }
