@@ -188,11 +188,12 @@ __device__ __forceinline__ bool keep_sample(const KeepArgs& a, const RayView& v,
 
 // Identity order: one wavefront per ray clips it (every lane the same
 // float32 recipe; lane 0 writes) and counts its kept samples, in one pass.
-__global__ __launch_bounds__(256) void setup_count_kernel(KeepArgs a, BoxF box, int max_samples,
+// One ray per workgroup, so that a long ray holds only its own slot.
+__global__ __launch_bounds__(64) void setup_count_kernel(KeepArgs a, BoxF box, int max_samples,
                                                           float* __restrict__ t_near, float* __restrict__ t_far,
                                                           uint8_t* __restrict__ valid, int* __restrict__ n_uniform,
                                                           int* __restrict__ perm, int* __restrict__ counts) {
-    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int r = blockIdx.x;
     const int lane = threadIdx.x & 63;
     if (r >= a.B) return;
     RayView v;
@@ -595,7 +596,7 @@ static int32_t sample_rays_impl(const float* rays_o, const float* rays_d, const 
                    : nullptr;
     const unsigned wblocks = static_cast<unsigned>((B + 3) / 4);
     if (!morton && !clip_only) {
-        DVGO_LAUNCH(K_RAY_SETUP, setup_count_kernel, dim3(wblocks), dim3(256), 0, s, ka, bf, max_samples, t_near,
+        DVGO_LAUNCH(K_RAY_SETUP, setup_count_kernel, dim3(B), dim3(64), 0, s, ka, bf, max_samples, t_near,
                     t_far, valid, n_uniform, perm, counts);
         if (int32_t st = dvgo::launch_status()) return st;
     } else {
